@@ -466,6 +466,16 @@ def rank_from_colors(color: np.ndarray) -> np.ndarray:
     return rank
 
 
+def tile_colors(nx: int, ny: int, tile_x: int = 32, tile_y: int = 32) -> np.ndarray:
+    """Red-black colouring of tile_x x tile_y tiles of the grid (cell c = x + nx y):
+    colour ((x // tile_x) + (y // tile_y)) mod 2.  With rank_from_colors this
+    orders all red tiles before all black tiles and keeps the natural order
+    inside every tile; a single tile covering the grid is the natural order."""
+    x = np.arange(nx)[None, :] // tile_x
+    y = np.arange(ny)[:, None] // tile_y
+    return ((x + y) % 2).astype(np.int32).reshape(-1)
+
+
 class BlockILU0:
     def __init__(self, A: BSR, rank: np.ndarray):
         self.A, self.rank = A, _i32(rank)
