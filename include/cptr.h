@@ -1,0 +1,185 @@
+/*
+ * cptr.h -- C ABI of the MI355X multi-stage preconditioned GMRES solver.
+ *
+ * The solver takes the reduced (primary) system A x = b of a fully implicit
+ * thermal-compositional(-reactive) Newton step (Cremon, Castelletto & White,
+ * Sec. "Static-Condensation Strategy", Eq. reduced) in cell-interleaved block
+ * form, left-scales it once (Eq. splitPrec1), and runs right-preconditioned
+ * restarted GMRES or flexible GMRES with a multi-stage preconditioner
+ * (Eq. multistageprec): the three-stage CPTR3 scheme (Eqs. CPTR31, CPTR32,
+ * CPTR3M1, CPTRM2, CPTR3M3; Algorithm 2), the two-stage CPR scheme
+ * (Eqs. CPR, CPRM1; Algorithm 1) or a block-ILU(0) / block-Jacobi stage alone.
+ * Every stage runs as HIP kernels on the caller's stream.
+ *
+ * Data layout (all device memory unless stated otherwise)
+ *   BSR matrix with n_cells block rows, block size b (2 <= b <= 8):
+ *     row_ptr  int32[n_cells + 1]
+ *     col_idx  int32[nnzb]    ascending within a row, the diagonal block
+ *                             present, pattern structurally symmetric
+ *     vals     double[nnzb * b * b]  row-major b x b blocks
+ *   vectors: double[n_cells * b], cell-interleaved (unknown k of cell i at i*b + k).
+ *   Inside a cell, p_index is pressure and T_index temperature; every other
+ *   unknown belongs to the group "s" (saturations, mole fractions).
+ *
+ * Ownership: pointers passed in stay owned by the caller; a call never frees
+ * or keeps them past its return (setup copies what it needs).  The context
+ * owns the scaled matrix, the AMG hierarchies, the ILU factors and the Krylov
+ * workspace, and releases them in cptr_destroy.
+ *
+ * Errors: every entry point returns a cptr_status.  Negative values are hard
+ * errors (outputs not valid); positive values are soft (outputs written).
+ * cptr_last_error() returns a thread-local message for the last failure
+ * (e.g. the failing cell).  Nothing aborts or exits.
+ */
+#ifndef CPTR_H
+#define CPTR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cptr_ctx cptr_ctx;
+
+typedef enum {
+    CPTR_OK = 0,
+    CPTR_NOT_CONVERGED = 1,      /* max_iters reached; x holds the last iterate */
+    CPTR_E_ARG = -1,             /* invalid argument / unsupported pattern      */
+    CPTR_E_HIP = -2,             /* HIP runtime error                           */
+    CPTR_E_SINGULAR_BLOCK = -3,  /* singular D_ss, zero Ahat_PP, singular pivot */
+    CPTR_E_NONFINITE = -4,       /* NaN / Inf in the input or during the solve  */
+    CPTR_E_OOM = -5,             /* device allocation failed                    */
+    CPTR_E_STATE = -6            /* call out of order (e.g. solve before setup) */
+} cptr_status;
+
+/* preconditioner variants (Sec. "Multi-Stage Preconditioning") */
+enum { CPTR_VARIANT_CPTR3 = 0, CPTR_VARIANT_CPR = 1, CPTR_VARIANT_LAST_ONLY = 3 };
+/* order of the two scalar AMG stages of CPTR3: temperature first as in
+ * Eqs. CPTR3M1 / CPTRM2, or pressure first */
+enum { CPTR_T_THEN_P = 0, CPTR_P_THEN_T = 1 };
+/* last (global) stage: block ILU(0) in the tile order, or block Jacobi */
+enum { CPTR_LAST_BILU0 = 0, CPTR_LAST_BJACOBI = 1 };
+enum { CPTR_GMRES = 0, CPTR_FGMRES = 1 };
+enum { CPTR_FP64 = 0, CPTR_FP32 = 1 };
+enum { CPTR_SMOOTH_JACOBI = 0, CPTR_SMOOTH_L1JACOBI = 1 };
+enum { CPTR_INTERP_CLASSICAL = 0, CPTR_INTERP_LEARNED = 1 };
+
+typedef struct {
+    int32_t variant;            /* CPTR_VARIANT_*                                 */
+    int32_t stage_order;        /* CPTR_T_THEN_P (default) | CPTR_P_THEN_T         */
+    int32_t last_stage;         /* CPTR_LAST_*                                    */
+    int32_t krylov;             /* CPTR_GMRES | CPTR_FGMRES                        */
+    int32_t restart;            /* Krylov restart length m (1..200)                */
+    int32_t max_iters;          /* total Arnoldi steps                            */
+    double  rtol;               /* |bbar - Abar x| <= rtol |bbar| (scaled system)  */
+    int32_t precond_precision;  /* CPTR_FP64 | CPTR_FP32 (needs CPTR_FGMRES)       */
+    int32_t reorth;             /* 1: second Gram-Schmidt pass                    */
+    double  amg_theta;          /* strength threshold (0.25)                      */
+    int32_t amg_max_coarse;     /* direct solve at or below this size (1000)      */
+    int32_t amg_max_levels;     /* (25)                                           */
+    int32_t amg_pmax;           /* interpolation truncation, 0 = none (4)         */
+    int32_t smoother;           /* CPTR_SMOOTH_*                                  */
+    int32_t pre_sweeps, post_sweeps;
+    double  jacobi_omega;       /* (2/3)                                          */
+    uint64_t pmis_seed;         /* seed of the coarsening's random measure        */
+    int32_t ilu_tile_x, ilu_tile_y;  /* tile shape of the BILU(0) order (32, 32)  */
+    int32_t t_interp;           /* CPTR_INTERP_CLASSICAL | CPTR_INTERP_LEARNED     */
+    double  reuse_rho_max;      /* hierarchy reuse threshold for update_values    */
+} cptr_options;
+
+typedef struct {
+    int32_t iterations;         /* Arnoldi steps over all restarts                */
+    int32_t restarts;
+    int32_t converged;
+    int32_t used_learned;
+    double  rel_res_scaled;     /* |bbar - Abar x| / |bbar|, recomputed in FP64   */
+    double  rel_res_unscaled;   /* |b - A x| / |b|                                */
+    double  rho_T, rho_P;       /* V-cycle convergence factors (if measured)      */
+    double  setup_ms, solve_ms;
+    int32_t levels_T, levels_P;
+    int32_t reused;             /* update_values kept the hierarchy               */
+} cptr_result;
+
+/* Fill *opt with the defaults noted above (CPTR3, T then P, BILU(0) in 32x32
+ * tiles, GMRES(30), rtol 1e-8, classical AMG with the paper's max coarse size
+ * 1000 (Sec. "Thermal-Compositional Homogeneous Cases")). */
+cptr_status cptr_default_options(cptr_options *opt);
+
+/* Create a context on HIP device `hip_device`; all work goes to `hip_stream`
+ * (a hipStream_t, NULL = the default stream).  *opt is copied. */
+cptr_status cptr_create(cptr_ctx **ctx, int32_t hip_device, void *hip_stream, const cptr_options *opt);
+
+/* Set up the solver for a system (Eqs. splitPrec1, CPTR31, CPTR32 and the
+ * sub-solver setups): left scaling, extraction of B_PP and C_TT, two AMG
+ * hierarchies, the ILU(0) factors.  nx * ny must equal n_cells when the
+ * cells form an nx x ny grid (cell c = x + nx*y), which the BILU(0) tile
+ * order needs; pass nx = ny = 0 for an unstructured pattern (then only block
+ * Jacobi is accepted as last stage).  Device pointers; copied. */
+cptr_status cptr_setup(cptr_ctx *ctx, int32_t n_cells, int32_t b, int32_t nnzb,
+                       const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_vals,
+                       int32_t p_index, int32_t T_index, int32_t nx, int32_t ny);
+
+/* New values on the same pattern (a Newton sequence): rescale and refactor;
+ * the AMG hierarchies are kept (numeric Galerkin products redone) while the
+ * measured V-cycle convergence factor stays below reuse_rho_max, else they
+ * are rebuilt. */
+cptr_status cptr_update_values(cptr_ctx *ctx, const double *d_vals);
+
+/* Solve A x = b: d_rhs (device, n_cells*b) in, d_x (device) out.  Returns
+ * after the work on the stream has finished; *out (host) may be NULL. */
+cptr_status cptr_solve(cptr_ctx *ctx, const double *d_rhs, double *d_x, cptr_result *out);
+
+/* Relative Givens residual estimates of the last solve, one per iteration
+ * (host buffer of capacity cap; *len receives the count). */
+cptr_status cptr_residual_history(const cptr_ctx *ctx, double *host_buf, int32_t cap, int32_t *len);
+
+/* Thread-local message describing the last error. */
+const char *cptr_last_error(void);
+
+cptr_status cptr_destroy(cptr_ctx *ctx);
+
+/* ---------------------------------------------------------------------- */
+/* Stage-level entry points on the same kernels, for inspection and tests.  */
+/* All pointers are device memory unless stated otherwise.                  */
+/* ---------------------------------------------------------------------- */
+
+/* The left scaling of Eqs. CPTR31/CPTR32 (variant CPTR3) or Eq. CPR (variant
+ * CPR) on a BSR matrix and rhs: writes d_abar (nnzb*b*b) and d_rhsbar. */
+cptr_status cptr_decouple(int32_t variant, int32_t n_cells, int32_t b, const int32_t *d_row_ptr,
+                          const int32_t *d_col_idx, const double *d_vals, const double *d_rhs,
+                          int32_t p_index, int32_t T_index, double *d_abar, double *d_rhsbar,
+                          void *hip_stream);
+
+/* y = A x for a BSR matrix (the outer operator apply of every Arnoldi step). */
+cptr_status cptr_bsr_spmv(int32_t n_cells, int32_t b, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                          const double *d_vals, const double *d_x, double *d_y, void *hip_stream);
+
+/* Number of AMG levels of hierarchy `which` (0 = temperature C_TT, 1 = pressure B_PP). */
+cptr_status cptr_amg_levels(const cptr_ctx *ctx, int32_t which, int32_t *levels);
+
+/* Sizes of level `level`: rows and nnz of the operator, nnz of P (0 on the coarsest). */
+cptr_status cptr_amg_level_info(const cptr_ctx *ctx, int32_t which, int32_t level,
+                                int32_t *nrows, int32_t *nnz, int32_t *p_nnz);
+
+/* Copy level `level` of a hierarchy to host buffers sized by cptr_amg_level_info:
+ * operator CSR (rp, ci, v), C/F split (cf, 1 = C; NULL allowed) and P CSR
+ * (NULL allowed, and on the coarsest level). */
+cptr_status cptr_amg_level_copy(const cptr_ctx *ctx, int32_t which, int32_t level,
+                                int32_t *h_rp, int32_t *h_ci, double *h_v, int32_t *h_cf,
+                                int32_t *h_prp, int32_t *h_pci, double *h_pv);
+
+/* One V-cycle of hierarchy `which` with zero initial guess: d_x = V(d_b) (length = fine rows). */
+cptr_status cptr_amg_vcycle(cptr_ctx *ctx, int32_t which, const double *d_b, double *d_x);
+
+/* One application of the multi-stage preconditioner: d_y = M^{-1} d_r. */
+cptr_status cptr_precond_apply(cptr_ctx *ctx, const double *d_r, double *d_y);
+
+/* The scaled right-hand side and matrix held by the context (device copies). */
+cptr_status cptr_get_scaled(const cptr_ctx *ctx, double *d_abar, double *d_rhsbar_or_null, const double *d_rhs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPTR_H */

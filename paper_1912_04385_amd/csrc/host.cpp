@@ -1,0 +1,891 @@
+// Host orchestration of the MI355X multi-stage preconditioned GMRES solver
+// and the C ABI declared in cptr.h.  Everything numerical runs in the
+// kernels of k_*.hip on the context's stream; the host sequences launches,
+// sizes allocations from a few device->host scalars during setup, and reads
+// one small status record per Arnoldi step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using namespace cptr;
+
+static thread_local std::string g_last_error;
+
+static void set_error(const std::string &m) { g_last_error = m; }
+
+constexpr int MAX_COARSE_DENSE = 8192;
+
+struct cptr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    cptr_options opt{};
+    // problem
+    int n = 0, b = 0, nnzb = 0, ip = 0, it = 1, nx = 0, ny = 0;
+    bool ready = false;
+    DBuf<int> rp, ci, tpos;
+    DBuf<double> abar, wp, wt, beta, slabT, slabP;
+    DBuf<float> abar32, slabT32, slabP32;
+    // last stage
+    bool use_tiles = false;
+    TileSched ts;
+    DBuf<int> cell_list;
+    DBuf<double> dinv;
+    DBuf<float> dinv32;
+    // scalar stages: 0 = temperature (C_TT), 1 = pressure (B_PP)
+    Hierarchy H[2];
+    DBuf<double> tw;
+    DBuf<float> tw32;
+    // Krylov workspace
+    int m_alloc = 0;
+    DBuf<double> V, Z, w, x, rhsbar, r, part, part2, hcol, hcol2, Hm, cs, sn, g, y, scal, hinfo, tmpv;
+    double *hinfo_host = nullptr;
+    std::vector<double> history;
+    DBuf<int> flag;
+    // setup scratch
+    DBuf<int> s_i1, s_i2, s_i3, s_i4;
+    DBuf<double> s_d1, s_d2;
+    DBuf<uint64_t> s_u1;
+    DBuf<unsigned char> s_c1;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_setup_ms = 0.0;
+
+    ~cptr_ctx() {
+        if (hinfo_host) (void)hipHostFree(hinfo_host);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <class T>
+static T read_scalar(const T *d, hipStream_t s) {
+    T v;
+    CPTR_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, s));
+    CPTR_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+static int read_flag_and_clear(cptr_ctx *c) {
+    int f = read_scalar(c->flag.p, c->stream);
+    fill_int(c->flag.p, 0, 1, c->stream);
+    return f;
+}
+
+static int scan_total(const int *in, int *out, int n, hipStream_t s) {
+    scan_exclusive(in, out, n, nullptr, s);
+    return read_scalar(out + n, s);
+}
+
+// ---------------------------------------------------------------------------
+// AMG hierarchy (setup)
+// ---------------------------------------------------------------------------
+static void csr_spgemm(cptr_ctx *c, const CsrD &A, const CsrD &B, CsrD &C) {
+    hipStream_t s = c->stream;
+    const int m = A.n;
+    c->s_i1.alloc((size_t)m + 1);
+    c->s_i2.alloc((size_t)m + 1);
+    c->s_i3.alloc((size_t)m + 1);
+    amg_spgemm_bound(m, A.rp, A.ci, B.rp, c->s_i1.p, s);
+    const int cap = scan_total(c->s_i1.p, c->s_i2.p, m, s);   // hash offsets
+    DBuf<int> hk;
+    DBuf<double> hv;
+    hk.alloc((size_t)cap);
+    hv.alloc((size_t)cap);
+    amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
+    C.n = m;
+    C.ncols = B.ncols;
+    C.rp_own.alloc((size_t)m + 1);
+    const int nnz = scan_total(c->s_i3.p, C.rp_own.p, m, s);
+    C.nnz = nnz;
+    C.ci_own.alloc((size_t)nnz);
+    C.v.alloc((size_t)nnz);
+    amg_compact(m, c->s_i2.p, hk.p, hv.p, C.rp_own.p, C.ci_own.p, C.v.p, s);
+    C.rp = C.rp_own.p;
+    C.ci = C.ci_own.p;
+    CPTR_HIP(hipStreamSynchronize(s));
+}
+
+static void csr_transpose(cptr_ctx *c, const CsrD &P, CsrD &R) {
+    hipStream_t s = c->stream;
+    R.n = P.ncols;
+    R.ncols = P.n;
+    R.nnz = P.nnz;
+    R.rp_own.alloc((size_t)R.n + 1);
+    R.ci_own.alloc((size_t)R.nnz);
+    R.v.alloc((size_t)R.nnz);
+    c->s_i4.alloc((size_t)R.n + 1);
+    amg_transpose(P.n, P.ncols, P.rp, P.ci, P.v.p, R.rp_own.p, R.ci_own.p, R.v.p, c->s_i4.p, s);
+    R.rp = R.rp_own.p;
+    R.ci = R.ci_own.p;
+}
+
+static void level_vectors(Level &L, int n, bool fp32) {
+    L.x.alloc(n);
+    L.b.alloc(n);
+    L.r.alloc(2 * (size_t)n);   // r and the ping-pong buffer of the smoother
+    if (fp32) {
+        L.x32.alloc(n);
+        L.b32.alloc(n);
+        L.r32.alloc(2 * (size_t)n);
+    }
+}
+
+// Build the hierarchy of a scalar operator whose level-0 pattern is the BSR
+// pattern (rp, ci owned by the context) and whose values are `vals` (copied).
+static void build_hierarchy(cptr_ctx *c, Hierarchy &h, const double *vals) {
+    hipStream_t s = c->stream;
+    const cptr_options &o = c->opt;
+    const bool fp32 = (o.precond_precision == CPTR_FP32);
+    h.L.clear();
+    h.L.emplace_back();
+    {
+        Level &L0 = h.L.back();
+        L0.A.n = c->n;
+        L0.A.ncols = c->n;
+        L0.A.nnz = c->nnzb;
+        L0.A.rp = c->rp.p;
+        L0.A.ci = c->ci.p;
+        L0.A.v.alloc(c->nnzb);
+        CPTR_HIP(hipMemcpyAsync(L0.A.v.p, vals, sizeof(double) * c->nnzb, hipMemcpyDeviceToDevice, s));
+    }
+    while (true) {
+        Level &L = h.L.back();
+        const int m = L.A.n;
+        L.dinv.alloc(m);
+        c->s_d1.alloc(m);   // diagonal of this level
+        amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
+        level_vectors(L, m, fp32);
+        if (m <= o.amg_max_coarse || (int)h.L.size() >= o.amg_max_levels) break;
+        // strength and PMIS
+        c->s_i1.alloc((size_t)L.A.nnz + 1);    // transpose positions
+        transpose_index(m, L.A.rp, L.A.ci, c->s_i1.p, c->flag.p, s);
+        if (read_flag_and_clear(c) & 8) throw Error(CPTR_E_ARG, "AMG level pattern is not structurally symmetric");
+        L.strong.alloc((size_t)L.A.nnz + 1);
+        amg_strength(m, L.A.rp, L.A.ci, L.A.v.p, o.amg_theta, L.strong.p, s);
+        c->s_i2.alloc((size_t)m + 1);          // |S^T|
+        c->s_u1.alloc((size_t)m);              // random measure
+        L.cf.alloc((size_t)m + 1);             // state -> C/F
+        c->s_c1.alloc((size_t)m);              // new C flags
+        c->s_i3.alloc(4);                      // undecided counter
+        fill_int(c->s_i3.p, 0, 1, s);
+        amg_pmis_init(m, L.A.rp, L.A.ci, L.strong.p, c->s_i1.p, o.pmis_seed, c->s_i2.p, c->s_u1.p, L.cf.p,
+                      c->s_i3.p, s);
+        int und = read_scalar(c->s_i3.p, s);
+        int rounds = 0;
+        while (und > 0) {
+            fill_int(c->s_i3.p, 0, 1, s);
+            amg_pmis_round(m, L.A.rp, L.A.ci, L.strong.p, c->s_i1.p, c->s_i2.p, c->s_u1.p, L.cf.p, c->s_c1.p,
+                           c->s_i3.p, s);
+            und = read_scalar(c->s_i3.p, s);
+            if (++rounds > 10000) throw Error(CPTR_E_STATE, "PMIS did not terminate");
+        }
+        // coarse numbering
+        DBuf<int> cidx;
+        cidx.alloc((size_t)m + 1);
+        const int nc = scan_total(L.cf.p, cidx.p, m, s);
+        if (nc == 0 || nc == m) break;
+        // extended+i interpolation
+        DBuf<int> ub, off, cnt, tcol;
+        DBuf<double> twt, td;
+        ub.alloc(m + 1);
+        off.alloc(m + 1);
+        cnt.alloc(m + 1);
+        amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, s);
+        const int cap = scan_total(ub.p, off.p, m, s);
+        tcol.alloc(cap);
+        twt.alloc(cap);
+        td.alloc((size_t)L.A.nnz + 1);
+        amg_exti_compute2(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
+                          tcol.p, twt.p, td.p, cnt.p, s);
+        CsrD &P = L.P;
+        P.n = m;
+        P.ncols = nc;
+        P.rp_own.alloc((size_t)m + 1);
+        P.nnz = scan_total(cnt.p, P.rp_own.p, m, s);
+        P.ci_own.alloc((size_t)P.nnz + 1);
+        P.v.alloc((size_t)P.nnz + 1);
+        amg_compact(m, off.p, tcol.p, twt.p, P.rp_own.p, P.ci_own.p, P.v.p, s);
+        P.rp = P.rp_own.p;
+        P.ci = P.ci_own.p;
+        L.nc = nc;
+        csr_transpose(c, P, L.R);
+        CsrD AP;
+        csr_spgemm(c, L.A, P, AP);
+        Level nxt;
+        csr_spgemm(c, L.R, AP, nxt.A);
+        h.L.push_back(std::move(nxt));
+    }
+    // coarsest level: dense inverse
+    Level &Lc = h.L.back();
+    const int nc = Lc.A.n;
+    if (nc > MAX_COARSE_DENSE)
+        throw Error(CPTR_E_ARG, "coarsest AMG level has " + std::to_string(nc) +
+                                    " rows (more than the dense limit); raise amg_max_levels or lower amg_max_coarse");
+    h.ncoarse = nc;
+    h.cinv.alloc((size_t)nc * nc);
+    if (fp32) h.cinv32.alloc((size_t)nc * nc);
+    DBuf<double> aug;
+    DBuf<int> used, piv;
+    aug.alloc((size_t)nc * 2 * nc);
+    used.alloc(nc);
+    piv.alloc(nc);
+    amg_dense_inverse(nc, Lc.A.rp, Lc.A.ci, Lc.A.v.p, aug.p, used.p, piv.p, c->flag.p, h.cinv.p,
+                      fp32 ? h.cinv32.p : nullptr, s);
+    int f = read_flag_and_clear(c);
+    if (f & 64) throw Error(CPTR_E_SINGULAR_BLOCK, "singular coarsest AMG operator");
+    if (f & 32) throw Error(CPTR_E_SINGULAR_BLOCK, "zero diagonal in an AMG level");
+    if (fp32) {
+        for (auto &L : h.L) {
+            L.A.v32.alloc((size_t)L.A.nnz + 1);
+            to_float(L.A.v.p, L.A.v32.p, L.A.nnz, s);
+            L.dinv32.alloc(L.A.n);
+            to_float(L.dinv.p, L.dinv32.p, L.A.n, s);
+            if (L.P.nnz) {
+                L.P.v32.alloc(L.P.nnz);
+                to_float(L.P.v.p, L.P.v32.p, L.P.nnz, s);
+                L.R.v32.alloc(L.R.nnz);
+                to_float(L.R.v.p, L.R.v32.p, L.R.nnz, s);
+            }
+        }
+    }
+    CPTR_HIP(hipStreamSynchronize(s));
+    h.built = true;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle (zero initial guess); input h.L[lvl].b, returns the buffer holding x
+// ---------------------------------------------------------------------------
+template <class T> struct Prec;
+template <> struct Prec<double> {
+    static const double *v(const CsrD &A) { return A.v.p; }
+    static double *x(Level &L) { return L.x.p; }
+    static double *b(Level &L) { return L.b.p; }
+    static double *r(Level &L) { return L.r.p; }
+    static const double *dinv(const Level &L) { return L.dinv.p; }
+};
+template <> struct Prec<float> {
+    static const float *v(const CsrD &A) { return A.v32.p; }
+    static float *x(Level &L) { return L.x32.p; }
+    static float *b(Level &L) { return L.b32.p; }
+    static float *r(Level &L) { return L.r32.p; }
+    static const float *dinv(const Level &L) { return L.dinv32.p; }
+};
+
+template <class T>
+static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl) {
+    hipStream_t s = c->stream;
+    Level &L = h.L[lvl];
+    const int n = L.A.n;
+    T *x = Prec<T>::x(L);
+    T *b = Prec<T>::b(L);
+    if (lvl == (int)h.L.size() - 1) {
+        if constexpr (std::is_same<T, double>::value)
+            vc_dense_apply<double>(n, h.cinv.p, b, x, s);
+        else
+            vc_dense_apply_mixed(n, h.cinv.p, b, x, s);
+        return x;
+    }
+    const cptr_options &o = c->opt;
+    const T omega = (T)((o.smoother == CPTR_SMOOTH_JACOBI) ? o.jacobi_omega : 1.0);
+    T *r = Prec<T>::r(L);
+    T *tmp = r + n;
+    const T *v = Prec<T>::v(L.A);
+    const T *dinv = Prec<T>::dinv(L);
+    if (o.pre_sweeps >= 1) {
+        vc_presmooth_residual<T>(n, L.A.rp, L.A.ci, v, dinv, omega, b, 1, 0, x, r, s);
+        if (o.pre_sweeps > 1) {
+            for (int k = 1; k < o.pre_sweeps; ++k) {
+                vc_smooth<T>(n, L.A.rp, L.A.ci, v, dinv, omega, b, 1, 0, x, tmp, s);
+                CPTR_HIP(hipMemcpyAsync(x, tmp, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+            }
+            vc_residual<T>(n, L.A.rp, L.A.ci, v, b, x, r, s);
+        }
+    } else {
+        CPTR_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, s));
+        CPTR_HIP(hipMemcpyAsync(r, b, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+    }
+    Level &Ln = h.L[lvl + 1];
+    vc_spmv<T>(L.R.n, L.R.rp, L.R.ci, Prec<T>::v(L.R), r, Prec<T>::b(Ln), s);
+    T *xc = vcycle<T>(c, h, lvl + 1);
+    vc_prolong_add<T>(n, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, s);
+    for (int k = 0; k < o.post_sweeps; ++k) {
+        vc_smooth<T>(n, L.A.rp, L.A.ci, v, dinv, omega, b, 1, 0, x, tmp, s);
+        std::swap(x, tmp);
+    }
+    if (x != Prec<T>::x(L)) {
+        CPTR_HIP(hipMemcpyAsync(Prec<T>::x(L), x, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+        x = Prec<T>::x(L);
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// multi-stage preconditioner: y = M^{-1} r (Eq. multistageprec; Algorithm 2
+// for CPTR3, Algorithm 1 for CPR), r and y double, internals in T
+// ---------------------------------------------------------------------------
+template <class T>
+static void precond_apply(cptr_ctx *c, const double *r, double *y) {
+    hipStream_t s = c->stream;
+    const int n = c->n, b = c->b;
+    const bool f32 = std::is_same<T, float>::value;
+    const T *abar = f32 ? (const T *)c->abar32.p : (const T *)c->abar.p;
+    const T *dinv = f32 ? (const T *)c->dinv32.p : (const T *)c->dinv.p;
+    const T *slabT = f32 ? (const T *)c->slabT32.p : (const T *)c->slabT.p;
+    const T *slabP = f32 ? (const T *)c->slabP32.p : (const T *)c->slabP.p;
+    T *tw = f32 ? (T *)c->tw32.p : (T *)c->tw.p;
+    const T *xT = nullptr, *vP = nullptr;
+    const int variant = c->opt.variant;
+    if (variant == CPTR_VARIANT_CPTR3) {
+        const bool t_first = (c->opt.stage_order == CPTR_T_THEN_P);
+        Hierarchy &h1 = c->H[t_first ? 0 : 1];
+        Hierarchy &h2 = c->H[t_first ? 1 : 0];
+        const int comp1 = t_first ? c->it : c->ip, comp2 = t_first ? c->ip : c->it;
+        // M1: gather, V-cycle
+        ms_stage_input<T>(n, b, c->rp.p, c->ci.p, (const T *)nullptr, comp1, r, (const T *)nullptr,
+                          Prec<T>::b(h1.L[0]), s);
+        const T *x1 = vcycle<T>(c, h1, 0);
+        // M2 on z = r - Abar x (only its comp2 entries are needed)
+        ms_stage_input<T>(n, b, c->rp.p, c->ci.p, t_first ? slabT : slabP, comp2, r, x1, Prec<T>::b(h2.L[0]), s);
+        const T *x2 = vcycle<T>(c, h2, 0);
+        xT = t_first ? x1 : x2;
+        vP = t_first ? x2 : x1;
+    } else if (variant == CPTR_VARIANT_CPR) {
+        Hierarchy &hp = c->H[1];
+        ms_stage_input<T>(n, b, c->rp.p, c->ci.p, (const T *)nullptr, c->ip, r, (const T *)nullptr,
+                          Prec<T>::b(hp.L[0]), s);
+        vP = vcycle<T>(c, hp, 0);
+    }
+    // last stage on u = r - Abar (x + v), combined output y = x + v + ilu^{-1} u
+    if (c->use_tiles)
+        bilu_apply_tiles<T>(c->ts, b, c->rp.p, c->ci.p, abar, dinv, slabT, slabP, c->ip, c->it, r, xT, vP, tw, y, s);
+    else
+        bj_apply_cells<T>(n, b, c->rp.p, c->ci.p, dinv, slabT, slabP, c->ip, c->it, r, xT, vP, y, s);
+}
+
+static void precond(cptr_ctx *c, const double *r, double *y) {
+    if (c->opt.precond_precision == CPTR_FP32)
+        precond_apply<float>(c, r, y);
+    else
+        precond_apply<double>(c, r, y);
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+static void validate_options(const cptr_options &o) {
+    if (o.variant != CPTR_VARIANT_CPTR3 && o.variant != CPTR_VARIANT_CPR && o.variant != CPTR_VARIANT_LAST_ONLY)
+        throw Error(CPTR_E_ARG, "unknown variant");
+    if (o.restart < 1 || o.restart > 200) throw Error(CPTR_E_ARG, "restart must be 1..200");
+    if (o.max_iters < 1) throw Error(CPTR_E_ARG, "max_iters must be positive");
+    if (!(o.rtol > 0.0)) throw Error(CPTR_E_ARG, "rtol must be positive");
+    if (o.precond_precision == CPTR_FP32 && o.krylov != CPTR_FGMRES)
+        throw Error(CPTR_E_ARG, "the FP32 preconditioner needs flexible GMRES");
+    if (o.amg_max_coarse < 1 || o.amg_max_levels < 1) throw Error(CPTR_E_ARG, "AMG size limits must be positive");
+    if (o.ilu_tile_x < 1 || o.ilu_tile_y < 1) throw Error(CPTR_E_ARG, "ILU tile must be at least 1 x 1");
+    if (o.pre_sweeps < 0 || o.post_sweeps < 0) throw Error(CPTR_E_ARG, "negative smoothing sweeps");
+}
+
+static void do_setup_values(cptr_ctx *c, const double *vals) {
+    hipStream_t s = c->stream;
+    const int n = c->n, b = c->b, nnzb = c->nnzb;
+    const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
+    c->abar.alloc((size_t)nnzb * b * b);
+    c->wp.alloc((size_t)n * b);
+    c->wt.alloc((size_t)n * b);
+    c->beta.alloc(n);
+    count_nonfinite(vals, (size_t)nnzb * b * b, c->flag.p, s);
+    if (read_flag_and_clear(c) & 16) throw Error(CPTR_E_NONFINITE, "non-finite matrix entry");
+    c->s_i4.alloc(2);
+    fill_int(c->s_i4.p, 0x7fffffff, 1, s);
+    if (c->opt.variant == CPTR_VARIANT_LAST_ONLY) {
+        CPTR_HIP(hipMemcpyAsync(c->abar.p, vals, sizeof(double) * nnzb * b * b, hipMemcpyDeviceToDevice, s));
+    } else {
+        launch_decouple(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->abar.p, c->wp.p, c->wt.p,
+                        c->beta.p, c->s_i4.p, s);
+    }
+    int bad = read_scalar(c->s_i4.p, s);
+    if (bad != 0x7fffffff)
+        throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block (D_ss or Ahat_PP) in cell " + std::to_string(bad));
+    c->slabT.alloc((size_t)nnzb * b);
+    c->slabP.alloc((size_t)nnzb * b);
+    DBuf<double> ctt, bpp;
+    ctt.alloc(nnzb);
+    bpp.alloc(nnzb);
+    if (fp32) {
+        c->abar32.alloc((size_t)nnzb * b * b);
+        c->slabT32.alloc((size_t)nnzb * b);
+        c->slabP32.alloc((size_t)nnzb * b);
+    }
+    launch_extract(n, b, nnzb, c->abar.p, c->ip, c->it, ctt.p, bpp.p, c->slabT.p, c->slabP.p,
+                   fp32 ? c->abar32.p : nullptr, fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
+    // scalar stages
+    if (c->opt.variant == CPTR_VARIANT_CPTR3) build_hierarchy(c, c->H[0], ctt.p);
+    if (c->opt.variant == CPTR_VARIANT_CPTR3 || c->opt.variant == CPTR_VARIANT_CPR) build_hierarchy(c, c->H[1], bpp.p);
+    // last stage
+    c->dinv.alloc((size_t)n * b * b);
+    fill_int(c->s_i4.p, 0x7fffffff, 1, s);
+    if (c->use_tiles) {
+        bilu_factor_tiles(c->ts, n, b, c->rp.p, c->ci.p, c->tpos.p, c->abar.p, c->dinv.p, c->s_i4.p, 0, 0, s);
+        bilu_factor_tiles(c->ts, n, b, c->rp.p, c->ci.p, c->tpos.p, c->abar.p, c->dinv.p, c->s_i4.p, 1, 0, s);
+    } else {
+        bj_factor_cells(n, b, c->rp.p, c->ci.p, c->abar.p, c->dinv.p, c->s_i4.p, nullptr, s);
+    }
+    bad = read_scalar(c->s_i4.p, s);
+    if (bad != 0x7fffffff)
+        throw Error(CPTR_E_SINGULAR_BLOCK, "singular ILU pivot block in cell " + std::to_string(bad));
+    if (fp32) {
+        c->dinv32.alloc((size_t)n * b * b);
+        to_float(c->dinv.p, c->dinv32.p, (size_t)n * b * b, s);
+        c->tw32.alloc((size_t)n * b);
+    } else {
+        c->tw.alloc((size_t)n * b);
+    }
+    CPTR_HIP(hipStreamSynchronize(s));
+}
+
+static void alloc_krylov(cptr_ctx *c) {
+    const size_t N = (size_t)c->n * c->b;
+    const int m = c->opt.restart;
+    c->V.alloc((m + 1) * N);
+    c->Z.alloc(m * N);
+    c->w.alloc(N);
+    c->x.alloc(N);
+    c->rhsbar.alloc(N);
+    c->r.alloc(N);
+    c->tmpv.alloc(N);
+    const int nblk = kr_nblk((int)N);
+    c->part.alloc((size_t)nblk * (m + 2));
+    c->part2.alloc((size_t)nblk * (m + 2));
+    c->hcol.alloc(m + 2);
+    c->hcol2.alloc(m + 2);
+    c->Hm.alloc((size_t)(m + 1) * m);
+    c->cs.alloc(m);
+    c->sn.alloc(m);
+    c->g.alloc(m + 1);
+    c->y.alloc(m);
+    c->scal.alloc(2);
+    c->hinfo.alloc(4);
+    if (!c->hinfo_host) CPTR_HIP(hipHostMalloc((void **)&c->hinfo_host, 8 * sizeof(double), hipHostMallocDefault));
+    c->m_alloc = m;
+}
+
+// ---------------------------------------------------------------------------
+// restarted right-preconditioned GMRES / FGMRES on Abar x = bbar
+// ---------------------------------------------------------------------------
+static double device_norm(cptr_ctx *c, const double *v, int N) {
+    const int nblk = kr_nblk(N);
+    kr_norm2_partial(N, v, c->part.p, nblk, c->stream);
+    kr_reduce(c->part.p, nblk, 1, c->hcol.p, c->stream);
+    return std::sqrt(read_scalar(c->hcol.p, c->stream));
+}
+
+static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
+    hipStream_t s = c->stream;
+    const int N = c->n * c->b;
+    const int m = c->opt.restart;
+    const size_t ld = (size_t)N;
+    const int nblk = kr_nblk(N);
+    c->history.clear();
+    const double bnorm = device_norm(c, c->rhsbar.p, N);
+    fill_double(c->x.p, 0.0, N, s);
+    if (bnorm == 0.0) {
+        res->iterations = 0;
+        res->converged = 1;
+        res->rel_res_scaled = 0.0;
+        return CPTR_OK;
+    }
+    CPTR_HIP(hipMemcpyAsync(c->r.p, c->rhsbar.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    int its = 0, restarts = 0;
+    double true_rel = 1.0;
+    bool converged = false;
+    while (true) {
+        kr_norm2_partial(N, c->r.p, c->part.p, nblk, s);
+        kr_cycle_prep(c->part.p, nblk, m, c->g.p, c->scal.p, c->hinfo.p, s);
+        kr_scale(N, c->r.p, c->scal.p, c->V.p, s);
+        int k = 0;
+        bool breakdown = false;
+        for (int j = 0; j < m; ++j) {
+            double *vj = c->V.p + (size_t)j * ld;
+            double *zj = c->Z.p + (size_t)j * ld;
+            precond(c, vj, zj);
+            launch_bsr_spmv(c->n, c->b, c->rp.p, c->ci.p, c->abar.p, zj, c->w.p, s);
+            kr_mdot(N, j + 1, c->V.p, ld, c->w.p, c->part.p, nblk, s);
+            kr_reduce(c->part.p, nblk, j + 2, c->hcol.p, s);
+            kr_update(N, j + 1, c->V.p, ld, c->hcol.p, c->w.p, c->part2.p, nblk, s);
+            const double *h2 = nullptr;
+            if (c->opt.reorth) {
+                kr_mdot(N, j + 1, c->V.p, ld, c->w.p, c->part.p, nblk, s);
+                kr_reduce(c->part.p, nblk, j + 2, c->hcol2.p, s);
+                kr_update(N, j + 1, c->V.p, ld, c->hcol2.p, c->w.p, c->part2.p, nblk, s);
+                h2 = c->hcol2.p;
+            }
+            kr_arnoldi_finish2(j, m, c->Hm.p, c->cs.p, c->sn.p, c->g.p, c->hcol.p, h2, c->part2.p, nblk, c->scal.p,
+                               c->hinfo.p, s);
+            kr_scale(N, c->w.p, c->scal.p, c->V.p + (size_t)(j + 1) * ld, s);
+            CPTR_HIP(hipMemcpyAsync(c->hinfo_host, c->hinfo.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+            CPTR_HIP(hipStreamSynchronize(s));
+            ++its;
+            k = j + 1;
+            const double gres = c->hinfo_host[0], hj1 = c->hinfo_host[1], wn0 = c->hinfo_host[2];
+            if (!std::isfinite(gres) || !std::isfinite(hj1)) {
+                set_error("non-finite value in the Arnoldi process");
+                return CPTR_E_NONFINITE;
+            }
+            c->history.push_back(gres / bnorm);
+            if (hj1 <= 1e-14 * wn0) { breakdown = true; break; }
+            if (gres <= c->opt.rtol * bnorm || its >= c->opt.max_iters) break;
+        }
+        kr_solve_upper(k, m, c->Hm.p, c->g.p, c->y.p, s);
+        kr_combine<double>(N, k, c->Z.p, ld, c->y.p, c->x.p, s);
+        launch_bsr_residual(c->n, c->b, c->rp.p, c->ci.p, c->abar.p, c->x.p, c->rhsbar.p, c->r.p, s);
+        const double rn = device_norm(c, c->r.p, N);
+        if (!std::isfinite(rn)) {
+            set_error("non-finite residual");
+            return CPTR_E_NONFINITE;
+        }
+        true_rel = rn / bnorm;
+        if (true_rel <= c->opt.rtol) { converged = true; break; }
+        if (its >= c->opt.max_iters) break;
+        if (breakdown && rn == 0.0) break;
+        ++restarts;
+    }
+    res->iterations = its;
+    res->restarts = restarts;
+    res->converged = converged ? 1 : 0;
+    res->rel_res_scaled = true_rel;
+    return converged ? CPTR_OK : CPTR_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#define CPTR_API_BEGIN try {
+#define CPTR_API_END                                                   \
+    }                                                                  \
+    catch (const Error &e) {                                           \
+        set_error(e.what());                                           \
+        return e.status;                                               \
+    }                                                                  \
+    catch (const std::exception &e) {                                  \
+        set_error(e.what());                                           \
+        return CPTR_E_HIP;                                             \
+    }
+
+extern "C" {
+
+const char *cptr_last_error(void) { return g_last_error.c_str(); }
+
+cptr_status cptr_default_options(cptr_options *o) {
+    if (!o) { set_error("null options"); return CPTR_E_ARG; }
+    std::memset(o, 0, sizeof(*o));
+    o->variant = CPTR_VARIANT_CPTR3;
+    o->stage_order = CPTR_T_THEN_P;
+    o->last_stage = CPTR_LAST_BILU0;
+    o->krylov = CPTR_GMRES;
+    o->restart = 30;
+    o->max_iters = 1000;
+    o->rtol = 1e-8;
+    o->precond_precision = CPTR_FP64;
+    o->reorth = 0;
+    o->amg_theta = 0.25;
+    o->amg_max_coarse = 1000;
+    o->amg_max_levels = 25;
+    o->amg_pmax = 4;
+    o->smoother = CPTR_SMOOTH_JACOBI;
+    o->pre_sweeps = 1;
+    o->post_sweeps = 1;
+    o->jacobi_omega = 2.0 / 3.0;
+    o->pmis_seed = 0;
+    o->ilu_tile_x = 32;
+    o->ilu_tile_y = 32;
+    o->t_interp = CPTR_INTERP_CLASSICAL;
+    o->reuse_rho_max = 0.3;
+    return CPTR_OK;
+}
+
+cptr_status cptr_create(cptr_ctx **out, int32_t dev, void *stream, const cptr_options *opt) {
+    CPTR_API_BEGIN
+    if (!out) throw Error(CPTR_E_ARG, "null context pointer");
+    *out = nullptr;
+    int ndev = 0;
+    CPTR_HIP(hipGetDeviceCount(&ndev));
+    if (dev < 0 || dev >= ndev) throw Error(CPTR_E_ARG, "invalid HIP device");
+    CPTR_HIP(hipSetDevice(dev));
+    auto c = std::make_unique<cptr_ctx>();
+    c->device = dev;
+    c->stream = (hipStream_t)stream;
+    if (opt) c->opt = *opt;
+    else cptr_default_options(&c->opt);
+    validate_options(c->opt);
+    c->flag.alloc(4);
+    fill_int(c->flag.p, 0, 1, c->stream);
+    CPTR_HIP(hipEventCreate(&c->ev0));
+    CPTR_HIP(hipEventCreate(&c->ev1));
+    CPTR_HIP(hipStreamSynchronize(c->stream));
+    *out = c.release();
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_destroy(cptr_ctx *c) {
+    CPTR_API_BEGIN
+    if (!c) return CPTR_OK;
+    CPTR_HIP(hipSetDevice(c->device));
+    CPTR_HIP(hipStreamSynchronize(c->stream));
+    delete c;
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_setup(cptr_ctx *c, int32_t n, int32_t b, int32_t nnzb, const int32_t *d_rp, const int32_t *d_ci,
+                       const double *d_vals, int32_t p_index, int32_t T_index, int32_t nx, int32_t ny) {
+    CPTR_API_BEGIN
+    if (!c) throw Error(CPTR_E_ARG, "null context");
+    CPTR_HIP(hipSetDevice(c->device));
+    if (n <= 0 || nnzb < n || b < 2 || b > 8) throw Error(CPTR_E_ARG, "need n > 0, nnzb >= n, 2 <= b <= 8");
+    if (!d_rp || !d_ci || !d_vals) throw Error(CPTR_E_ARG, "null matrix pointer");
+    if (p_index < 0 || p_index >= b || T_index < 0 || T_index >= b || p_index == T_index)
+        throw Error(CPTR_E_ARG, "invalid pressure / temperature index");
+    const bool grid = (nx > 0 && ny > 0);
+    if (grid && (long)nx * ny != n) throw Error(CPTR_E_ARG, "nx * ny must equal n_cells");
+    if (c->opt.last_stage == CPTR_LAST_BILU0 && !grid)
+        throw Error(CPTR_E_ARG, "BILU(0) needs the grid shape (nx, ny); use block Jacobi otherwise");
+    hipStream_t s = c->stream;
+    c->ready = false;
+    CPTR_HIP(hipEventRecord(c->ev0, s));
+    c->n = n; c->b = b; c->nnzb = nnzb; c->ip = p_index; c->it = T_index; c->nx = nx; c->ny = ny;
+    c->rp.alloc((size_t)n + 1);
+    c->ci.alloc(nnzb);
+    CPTR_HIP(hipMemcpyAsync(c->rp.p, d_rp, sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
+    CPTR_HIP(hipMemcpyAsync(c->ci.p, d_ci, sizeof(int) * nnzb, hipMemcpyDeviceToDevice, s));
+    int last = read_scalar(c->rp.p + n, s);
+    int first = read_scalar(c->rp.p, s);
+    if (first != 0 || last != nnzb) throw Error(CPTR_E_ARG, "row_ptr[0] must be 0 and row_ptr[n] = nnzb");
+    check_pattern(n, c->rp.p, c->ci.p, c->flag.p, s);
+    c->tpos.alloc(nnzb);
+    transpose_index(n, c->rp.p, c->ci.p, c->tpos.p, c->flag.p, s);
+    int f = read_flag_and_clear(c);
+    if (f & 1) throw Error(CPTR_E_ARG, "block column index out of range");
+    if (f & 2) throw Error(CPTR_E_ARG, "block columns must ascend within each row");
+    if (f & 4) throw Error(CPTR_E_ARG, "missing diagonal block");
+    if (f & 8) throw Error(CPTR_E_ARG, "block pattern is not structurally symmetric");
+    c->use_tiles = (c->opt.last_stage == CPTR_LAST_BILU0);
+    if (c->use_tiles) {
+        tiles_build(c->ts, n, nx, ny, c->opt.ilu_tile_x, c->opt.ilu_tile_y, c->rp.p, c->ci.p, c->flag.p, s);
+        if (read_flag_and_clear(c) & 128)
+            throw Error(CPTR_E_ARG, "BILU(0) tile order needs a 5-point grid pattern; use block Jacobi");
+    }
+    do_setup_values(c, d_vals);
+    alloc_krylov(c);
+    CPTR_HIP(hipEventRecord(c->ev1, s));
+    CPTR_HIP(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    CPTR_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_setup_ms = ms;
+    c->ready = true;
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_update_values(cptr_ctx *c, const double *d_vals) {
+    CPTR_API_BEGIN
+    if (!c || !c->ready) throw Error(CPTR_E_STATE, "update_values before setup");
+    CPTR_HIP(hipSetDevice(c->device));
+    CPTR_HIP(hipEventRecord(c->ev0, c->stream));
+    do_setup_values(c, d_vals);
+    CPTR_HIP(hipEventRecord(c->ev1, c->stream));
+    CPTR_HIP(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    CPTR_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_setup_ms = ms;
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_solve(cptr_ctx *c, const double *d_rhs, double *d_x, cptr_result *out) {
+    CPTR_API_BEGIN
+    if (!c || !c->ready) throw Error(CPTR_E_STATE, "solve before setup");
+    if (!d_rhs || !d_x) throw Error(CPTR_E_ARG, "null vector");
+    CPTR_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    cptr_result res{};
+    CPTR_HIP(hipEventRecord(c->ev0, s));
+    const int N = c->n * c->b;
+    count_nonfinite(d_rhs, (size_t)N, c->flag.p, s);
+    if (read_flag_and_clear(c) & 16) throw Error(CPTR_E_NONFINITE, "non-finite right-hand side");
+    if (c->opt.variant == CPTR_VARIANT_LAST_ONLY)
+        CPTR_HIP(hipMemcpyAsync(c->rhsbar.p, d_rhs, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    else
+        launch_scale_rhs(c->opt.variant, c->n, c->b, d_rhs, c->ip, c->it, c->wp.p, c->wt.p, c->beta.p, c->rhsbar.p, s);
+    cptr_status st = run_gmres(c, &res);
+    if (st < 0) return st;
+    CPTR_HIP(hipMemcpyAsync(d_x, c->x.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    // unscaled residual |b - A x| = |N (bbar - Abar x)|
+    if (c->opt.variant == CPTR_VARIANT_LAST_ONLY)
+        CPTR_HIP(hipMemcpyAsync(c->tmpv.p, c->r.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    else
+        launch_unscale(c->opt.variant, c->n, c->b, c->r.p, c->ip, c->it, c->wp.p, c->wt.p, c->beta.p, c->tmpv.p, s);
+    const double rn = device_norm(c, c->tmpv.p, N);
+    const double bn = device_norm(c, d_rhs, N);
+    res.rel_res_unscaled = (bn > 0) ? rn / bn : 0.0;
+    CPTR_HIP(hipEventRecord(c->ev1, s));
+    CPTR_HIP(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    CPTR_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    res.solve_ms = ms;
+    res.setup_ms = c->last_setup_ms;
+    res.levels_T = (int)c->H[0].L.size();
+    res.levels_P = (int)c->H[1].L.size();
+    if (out) *out = res;
+    return st;
+    CPTR_API_END
+}
+
+cptr_status cptr_residual_history(const cptr_ctx *c, double *buf, int32_t cap, int32_t *len) {
+    CPTR_API_BEGIN
+    if (!c || !len) throw Error(CPTR_E_ARG, "null argument");
+    int k = (int)c->history.size();
+    *len = k;
+    if (buf)
+        for (int i = 0; i < k && i < cap; ++i) buf[i] = c->history[i];
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_decouple(int32_t variant, int32_t n, int32_t b, const int32_t *d_rp, const int32_t *d_ci,
+                          const double *d_vals, const double *d_rhs, int32_t ip, int32_t it, double *d_abar,
+                          double *d_rhsbar, void *stream) {
+    CPTR_API_BEGIN
+    if (variant != CPTR_VARIANT_CPTR3 && variant != CPTR_VARIANT_CPR) throw Error(CPTR_E_ARG, "variant");
+    if (n <= 0 || b < 2 || b > 8) throw Error(CPTR_E_ARG, "sizes");
+    hipStream_t s = (hipStream_t)stream;
+    DBuf<double> wp, wt, beta;
+    DBuf<int> err;
+    wp.alloc((size_t)n * b);
+    wt.alloc((size_t)n * b);
+    beta.alloc(n);
+    err.alloc(1);
+    fill_int(err.p, 0x7fffffff, 1, s);
+    launch_decouple(variant, n, b, d_rp, d_ci, d_vals, ip, it, d_abar, wp.p, wt.p, beta.p, err.p, s);
+    if (d_rhs && d_rhsbar) launch_scale_rhs(variant, n, b, d_rhs, ip, it, wp.p, wt.p, beta.p, d_rhsbar, s);
+    int bad = read_scalar(err.p, s);
+    if (bad != 0x7fffffff) throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block in cell " + std::to_string(bad));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_bsr_spmv(int32_t n, int32_t b, const int32_t *d_rp, const int32_t *d_ci, const double *d_vals,
+                          const double *d_x, double *d_y, void *stream) {
+    CPTR_API_BEGIN
+    if (n < 0 || b < 1 || b > 8) throw Error(CPTR_E_ARG, "sizes");
+    launch_bsr_spmv(n, b, d_rp, d_ci, d_vals, d_x, d_y, (hipStream_t)stream);
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+static Hierarchy &pick(const cptr_ctx *c, int which) {
+    if (!c || !c->ready) throw Error(CPTR_E_STATE, "context not set up");
+    if (which < 0 || which > 1) throw Error(CPTR_E_ARG, "which must be 0 (T) or 1 (P)");
+    Hierarchy &h = const_cast<cptr_ctx *>(c)->H[which];
+    if (!h.built) throw Error(CPTR_E_STATE, "hierarchy not built for this variant");
+    return h;
+}
+
+cptr_status cptr_amg_levels(const cptr_ctx *c, int32_t which, int32_t *levels) {
+    CPTR_API_BEGIN
+    *levels = (int)pick(c, which).L.size();
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_amg_level_info(const cptr_ctx *c, int32_t which, int32_t level, int32_t *nrows, int32_t *nnz,
+                                int32_t *p_nnz) {
+    CPTR_API_BEGIN
+    Hierarchy &h = pick(c, which);
+    if (level < 0 || level >= (int)h.L.size()) throw Error(CPTR_E_ARG, "level out of range");
+    const Level &L = h.L[level];
+    if (nrows) *nrows = L.A.n;
+    if (nnz) *nnz = L.A.nnz;
+    if (p_nnz) *p_nnz = (level + 1 < (int)h.L.size()) ? L.P.nnz : 0;
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_amg_level_copy(const cptr_ctx *c, int32_t which, int32_t level, int32_t *h_rp, int32_t *h_ci,
+                                double *h_v, int32_t *h_cf, int32_t *h_prp, int32_t *h_pci, double *h_pv) {
+    CPTR_API_BEGIN
+    Hierarchy &h = pick(c, which);
+    if (level < 0 || level >= (int)h.L.size()) throw Error(CPTR_E_ARG, "level out of range");
+    CPTR_HIP(hipSetDevice(c->device));
+    const Level &L = h.L[level];
+    hipStream_t s = c->stream;
+    if (h_rp) CPTR_HIP(hipMemcpyAsync(h_rp, L.A.rp, sizeof(int) * (L.A.n + 1), hipMemcpyDeviceToHost, s));
+    if (h_ci) CPTR_HIP(hipMemcpyAsync(h_ci, L.A.ci, sizeof(int) * L.A.nnz, hipMemcpyDeviceToHost, s));
+    if (h_v) CPTR_HIP(hipMemcpyAsync(h_v, L.A.v.p, sizeof(double) * L.A.nnz, hipMemcpyDeviceToHost, s));
+    const bool has_p = level + 1 < (int)h.L.size();
+    if (h_cf && has_p) CPTR_HIP(hipMemcpyAsync(h_cf, L.cf.p, sizeof(int) * L.A.n, hipMemcpyDeviceToHost, s));
+    if (has_p) {
+        if (h_prp) CPTR_HIP(hipMemcpyAsync(h_prp, L.P.rp, sizeof(int) * (L.P.n + 1), hipMemcpyDeviceToHost, s));
+        if (h_pci) CPTR_HIP(hipMemcpyAsync(h_pci, L.P.ci, sizeof(int) * L.P.nnz, hipMemcpyDeviceToHost, s));
+        if (h_pv) CPTR_HIP(hipMemcpyAsync(h_pv, L.P.v.p, sizeof(double) * L.P.nnz, hipMemcpyDeviceToHost, s));
+    }
+    CPTR_HIP(hipStreamSynchronize(s));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_amg_vcycle(cptr_ctx *c, int32_t which, const double *d_b, double *d_x) {
+    CPTR_API_BEGIN
+    Hierarchy &h = pick(c, which);
+    CPTR_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int n = h.L[0].A.n;
+    CPTR_HIP(hipMemcpyAsync(h.L[0].b.p, d_b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    double *x = vcycle<double>(c, h, 0);
+    CPTR_HIP(hipMemcpyAsync(d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    CPTR_HIP(hipStreamSynchronize(s));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_precond_apply(cptr_ctx *c, const double *d_r, double *d_y) {
+    CPTR_API_BEGIN
+    if (!c || !c->ready) throw Error(CPTR_E_STATE, "context not set up");
+    CPTR_HIP(hipSetDevice(c->device));
+    precond(c, d_r, d_y);
+    CPTR_HIP(hipStreamSynchronize(c->stream));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_get_scaled(const cptr_ctx *c, double *d_abar, double *d_rhsbar, const double *d_rhs) {
+    CPTR_API_BEGIN
+    if (!c || !c->ready) throw Error(CPTR_E_STATE, "context not set up");
+    CPTR_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    if (d_abar)
+        CPTR_HIP(hipMemcpyAsync(d_abar, c->abar.p, sizeof(double) * c->nnzb * c->b * c->b, hipMemcpyDeviceToDevice, s));
+    if (d_rhsbar && d_rhs) {
+        if (c->opt.variant == CPTR_VARIANT_LAST_ONLY)
+            CPTR_HIP(hipMemcpyAsync(d_rhsbar, d_rhs, sizeof(double) * c->n * c->b, hipMemcpyDeviceToDevice, s));
+        else
+            launch_scale_rhs(c->opt.variant, c->n, c->b, d_rhs, c->ip, c->it, c->wp.p, c->wt.p, c->beta.p, d_rhsbar, s);
+    }
+    CPTR_HIP(hipStreamSynchronize(s));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+}  // extern "C"

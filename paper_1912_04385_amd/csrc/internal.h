@@ -1,0 +1,211 @@
+// Internal declarations of the MI355X multi-stage GMRES library.
+// Host orchestration lives in host.cpp; kernels in k_*.hip; this header holds
+// the device-buffer helper, the error type and the kernel launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "cptr.h"
+
+namespace cptr {
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws, the C ABI converts to a status
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    cptr_status status;
+    Error(cptr_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+#define CPTR_HIP(x)                                                                        \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            throw ::cptr::Error(e_ == hipErrorOutOfMemory ? CPTR_E_OOM : CPTR_E_HIP,        \
+                                std::string(#x) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+#define CPTR_CHECK_LAUNCH() CPTR_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// device buffer (owned; freed in the destructor)
+// ---------------------------------------------------------------------------
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // (re)allocate to at least m elements; contents undefined
+    void alloc(size_t m) {
+        if (m <= n && p) return;
+        release();
+        size_t bytes = (m ? m : 1) * sizeof(T);
+        CPTR_HIP(hipMalloc((void **)&p, bytes));
+        n = m;
+    }
+    T *get() const { return p; }
+};
+
+// scalar CSR operator on the device
+struct CsrD {
+    int n = 0, ncols = 0, nnz = 0;
+    const int *rp = nullptr, *ci = nullptr;   // may alias storage owned elsewhere
+    DBuf<int> rp_own, ci_own;
+    DBuf<double> v;
+    DBuf<float> v32;
+};
+
+struct Level {
+    CsrD A;
+    DBuf<double> dinv;      // 1 / smoothing diagonal
+    DBuf<float> dinv32;
+    DBuf<int> cf;           // 1 = C, 0 = F (not on the coarsest level)
+    CsrD P, R;
+    int nc = 0;
+    // V-cycle work vectors
+    DBuf<double> x, b, r;
+    DBuf<float> x32, b32, r32;
+    // PMIS / interpolation scratch kept for inspection
+    DBuf<unsigned char> strong;
+};
+
+struct Hierarchy {
+    std::vector<Level> L;
+    int ncoarse = 0;
+    DBuf<double> cinv;      // dense inverse of the coarsest operator, row-major
+    DBuf<float> cinv32;
+    bool built = false;
+};
+
+// ---------------------------------------------------------------------------
+// kernel wrappers (defined in k_*.hip)
+// ---------------------------------------------------------------------------
+// k_common.hip
+void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t s);   // out[n] = total
+void fill_int(int *p, int v, size_t n, hipStream_t s);
+void fill_double(double *p, double v, size_t n, hipStream_t s);
+void check_pattern(int n, const int *rp, const int *ci, int *flag_dev, hipStream_t s);
+void transpose_index(int n, const int *rp, const int *ci, int *tpos, int *flag_dev, hipStream_t s);
+void count_nonfinite(const double *x, size_t n, int *flag_dev, hipStream_t s);
+void to_float(const double *x, float *y, size_t n, hipStream_t s);
+
+// k_decouple.hip
+void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
+                     double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s);
+void launch_scale_rhs(int variant, int n, int b, const double *rhs, int ip, int it, const double *wp,
+                      const double *wt, const double *beta, double *out, hipStream_t s);
+void launch_unscale(int variant, int n, int b, const double *v, int ip, int it, const double *wp,
+                    const double *wt, const double *beta, double *out, hipStream_t s);
+void launch_extract(int n, int b, int nnzb, const double *abar, int ip, int it, double *ctt, double *bpp,
+                    double *slabT, double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s);
+
+// k_amg_setup.hip
+void amg_strength(int n, const int *rp, const int *ci, const double *v, double theta, unsigned char *s,
+                  hipStream_t st);
+void amg_pmis_init(int n, const int *rp, const int *ci, const unsigned char *s, const int *tpos, uint64_t seed,
+                   int *cntT, uint64_t *h, int *state, int *und, hipStream_t st);
+void amg_pmis_round(int n, const int *rp, const int *ci, const unsigned char *s, const int *tpos, const int *cntT,
+                    const uint64_t *h, int *state, unsigned char *newc, int *und, hipStream_t st);
+void amg_exti_bound(int n, const int *rp, const int *ci, const unsigned char *s, const int *cf, int *ub,
+                    hipStream_t st);
+void amg_exti_compute2(int n, const int *rp, const int *ci, const double *v, const unsigned char *s, const int *cf,
+                       const int *cidx, const double *dg, int pmax, const int *off, int *tcol, double *tw,
+                       double *td, int *cnt, hipStream_t st);
+void amg_compact(int n, const int *off, const int *tcol, const double *tw, const int *prp, int *pci, double *pv,
+                 hipStream_t st);
+void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v, int *rpT, int *ciT, double *vT,
+                   int *work, hipStream_t st);
+void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, hipStream_t st);
+void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
+                        const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
+void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
+                   int *flag, hipStream_t st);
+void amg_dense_inverse(int n, const int *rp, const int *ci, const double *v, double *aug, int *used, int *pivrow,
+                       int *flag, double *inv, float *inv32, hipStream_t st);
+
+// k_vcycle.hip (double and float instantiations)
+template <class T>
+void vc_presmooth_residual(int n, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b,
+                           int bstride, int boff, T *x, T *r, hipStream_t st);
+template <class T>
+void vc_spmv(int n, const int *rp, const int *ci, const T *v, const T *x, T *y, hipStream_t st);
+template <class T>
+void vc_prolong_add(int n, const int *rp, const int *ci, const T *v, const T *xc, T *x, hipStream_t st);
+template <class T>
+void vc_smooth(int n, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b, int bstride,
+               int boff, const T *xin, T *xout, hipStream_t st);
+template <class T>
+void vc_residual(int n, const int *rp, const int *ci, const T *v, const T *b, const T *x, T *r, hipStream_t st);
+template <class T>
+void vc_dense_apply(int n, const T *Minv, const T *b, T *x, hipStream_t st);
+void vc_dense_apply_mixed(int n, const double *Minv, const float *b, float *x, hipStream_t st);
+template <class T>
+void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *slab, int comp, const double *r,
+                    const T *xs, T *out, hipStream_t st);
+
+// k_bilu.hip: BILU(0) in tile order / block Jacobi
+struct TileSched {
+    int nx = 0, ny = 0, tx = 0, ty = 0, ntx = 0, nty = 0;
+    int ntiles[2] = {0, 0};
+    DBuf<int> tiles[2];     // tile ids per colour
+    DBuf<int> color;        // per cell
+};
+void tiles_build(TileSched &ts, int n, int nx, int ny, int tx, int ty, const int *rp, const int *ci, int *flag,
+                 hipStream_t st);
+void bilu_factor_tiles(const TileSched &ts, int n, int b, const int *rp, const int *ci, const int *tpos,
+                       const double *abar, double *dinv, int *flag, int color, int diag_only, hipStream_t st);
+void bj_factor_cells(int n, int b, const int *rp, const int *ci, const double *abar, double *dinv, int *flag,
+                     const int *all_cells_tiles, hipStream_t st);
+// last stage apply, fused with Algorithm 2's residual updates:
+//   u = r - Abar[:,T] xT - Abar[:,P] vP  (terms dropped when xT / vP are null)
+//   w = ilu(Abar)^{-1} u,  y = w + xT e_T + vP e_P
+template <class T>
+void bilu_apply_tiles(const TileSched &ts, int b, const int *rp, const int *ci, const T *abar, const T *dinv,
+                      const T *slabT, const T *slabP, int ip, int it, const double *r, const T *xT, const T *vP,
+                      T *tw, double *y, hipStream_t st);
+template <class T>
+void bj_apply_cells(int n, int b, const int *rp, const int *ci, const T *dinv, const T *slabT, const T *slabP,
+                    int ip, int it, const double *r, const T *xT, const T *vP, double *y, hipStream_t st);
+
+// k_krylov.hip: outer operator and Arnoldi
+void launch_bsr_spmv(int n, int b, const int *rp, const int *ci, const double *A, const double *x, double *y,
+                     hipStream_t s);
+void launch_bsr_residual(int n, int b, const int *rp, const int *ci, const double *A, const double *x,
+                         const double *rhs, double *r, hipStream_t s);
+int kr_nblk(int N);
+void kr_mdot(int N, int k, const double *V, size_t ldv, const double *w, double *partial, int nblk,
+             hipStream_t st);
+void kr_reduce(const double *partial, int nblk, int k, double *out, hipStream_t st);
+void kr_update(int N, int k, const double *V, size_t ldv, const double *h, double *w, double *partial, int nblk,
+               hipStream_t st);
+void kr_norm2_partial(int N, const double *x, double *partial, int nblk, hipStream_t st);
+void kr_arnoldi_finish2(int j, int m, double *H, double *cs, double *sn, double *g, const double *hcol,
+                        const double *hcol2, const double *nrm_partial, int nblk, double *scal, double *hostinfo,
+                        hipStream_t st);
+void kr_cycle_prep(const double *nrm_partial, int nblk, int m, double *g, double *scal, double *hostinfo,
+                   hipStream_t st);
+void kr_scale(int N, const double *w, const double *scal, double *v, hipStream_t st);
+void kr_solve_upper(int k, int m, const double *H, const double *g, double *y, hipStream_t st);
+template <class TZ>
+void kr_combine(int N, int k, const TZ *Z, size_t ldz, const double *y, double *x, hipStream_t st);
+
+}  // namespace cptr

@@ -1,0 +1,591 @@
+// AMG setup on the GPU for the scalar subsystems C_TT and B_PP (the amg(.)
+// sub-solver of Eqs. CPTR3M1 and CPTRM2; the paper uses classical
+// Ruge-Stueben AMG, this library uses its parallel counterparts):
+//   strength of connection -> PMIS coarsening (De Sterck, Yang & Heys 2006)
+//   -> extended+i interpolation with truncation (De Sterck, Falgout, Nolting
+//   & Yang 2008) -> R = P^T -> Galerkin A_c = R (A P) by SpGEMM -> dense
+//   inverse of the coarsest operator.
+// Built with floating-point contraction off and with every sum taken in a
+// fixed, stated order, so a hierarchy is a deterministic function of its input
+// (one thread owns each row; no floating-point atomics anywhere).
+#include "internal.h"
+
+namespace cptr {
+
+static inline int blocks_for(long n, int t) { return (int)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+
+// --------------------------------------------------------------------------
+// strength: sigma_i = -1 if a_ii < 0 else +1, m_i = max_{k!=i} (-sigma_i a_ik);
+// j != i strong iff m_i > 0 and -sigma_i a_ij >= theta * m_i
+// --------------------------------------------------------------------------
+__global__ void k_strength(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                           const double *__restrict__ v, double theta, unsigned char *__restrict__ s) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = rp[i], b = rp[i + 1];
+    double aii = 0.0;
+    for (int e = a; e < b; ++e) if (ci[e] == i) aii = v[e];
+    const double sg = (aii < 0.0) ? -1.0 : 1.0;
+    double m = 0.0;
+    bool any = false;
+    for (int e = a; e < b; ++e) {
+        if (ci[e] == i) continue;
+        double t = -sg * v[e];
+        if (!any || t > m) { m = t; any = true; }
+    }
+    const double thr = theta * m;
+    for (int e = a; e < b; ++e) {
+        unsigned char st = 0;
+        if (ci[e] != i && any && m > 0.0 && -sg * v[e] >= thr) st = 1;
+        s[e] = st;
+    }
+}
+
+void amg_strength(int n, const int *rp, const int *ci, const double *v, double theta, unsigned char *s,
+                  hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_strength, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, rp, ci, v, theta, s);
+    CPTR_CHECK_LAUNCH();
+}
+
+// --------------------------------------------------------------------------
+// PMIS
+// --------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood 2014): output function on seed + (i+1) * gamma
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// measure lambda = |S^T| + random in [0,1): lexicographic (|S^T|, random), then lower index
+__device__ inline bool beats(int i, int j, const int *cntT, const uint64_t *h) {
+    int ci_ = cntT[i], cj = cntT[j];
+    if (ci_ != cj) return ci_ > cj;
+    uint64_t hi = h[i], hj = h[j];
+    if (hi != hj) return hi > hj;
+    return i < j;
+}
+
+constexpr int ST_UND = -1, ST_F = 0, ST_C = 1;
+
+__global__ void k_pmis_init(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                            const unsigned char *__restrict__ s, const int *__restrict__ tpos, uint64_t seed,
+                            int *__restrict__ cntT, uint64_t *__restrict__ h, int *__restrict__ state, int *und) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (ci[e] != i && tpos[e] >= 0 && s[tpos[e]]) c++;   // entry (j, i) strong: i in S_j
+    cntT[i] = c;
+    h[i] = splitmix64(seed, (uint64_t)i);
+    state[i] = (c == 0) ? ST_F : ST_UND;
+    if (c != 0) atomicAdd(und, 1);
+}
+
+void amg_pmis_init(int n, const int *rp, const int *ci, const unsigned char *s, const int *tpos, uint64_t seed,
+                   int *cntT, uint64_t *h, int *state, int *und, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_pmis_init, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, rp, ci, s, tpos, seed, cntT, h,
+                       state, und);
+    CPTR_CHECK_LAUNCH();
+}
+
+// an undecided point becomes C when it beats every undecided point of its
+// symmetrised strong neighbourhood S_i u S^T_i
+__global__ void k_pmis_select(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                              const unsigned char *__restrict__ s, const int *__restrict__ tpos,
+                              const int *__restrict__ cntT, const uint64_t *__restrict__ h,
+                              const int *__restrict__ state, unsigned char *__restrict__ newc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned char win = 0;
+    if (state[i] == ST_UND) {
+        win = 1;
+        for (int e = rp[i]; e < rp[i + 1] && win; ++e) {
+            int j = ci[e];
+            if (j == i) continue;
+            bool sym = s[e] || (tpos[e] >= 0 && s[tpos[e]]);
+            if (sym && state[j] == ST_UND && !beats(i, j, cntT, h)) win = 0;
+        }
+    }
+    newc[i] = win;
+}
+
+// new C points are fixed; undecided points that strongly depend on one become F
+__global__ void k_pmis_apply(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const unsigned char *__restrict__ s, const unsigned char *__restrict__ newc,
+                             int *__restrict__ state, int *und) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (state[i] != ST_UND) return;
+    if (newc[i]) { state[i] = ST_C; return; }
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (s[e] && newc[ci[e]]) { state[i] = ST_F; return; }
+    atomicAdd(und, 1);
+}
+
+void amg_pmis_round(int n, const int *rp, const int *ci, const unsigned char *s, const int *tpos, const int *cntT,
+                    const uint64_t *h, int *state, unsigned char *newc, int *und, hipStream_t st) {
+    hipLaunchKernelGGL(k_pmis_select, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, rp, ci, s, tpos, cntT, h,
+                       state, newc);
+    hipLaunchKernelGGL(k_pmis_apply, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, rp, ci, s, newc, state, und);
+    CPTR_CHECK_LAUNCH();
+}
+
+// --------------------------------------------------------------------------
+// extended+i interpolation
+// --------------------------------------------------------------------------
+// upper bound of |Chat_i| (with repeats): C rows 1; F rows: strong C
+// neighbours + strong C neighbours of strong F neighbours
+__global__ void k_exti_bound(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const unsigned char *__restrict__ s, const int *__restrict__ cf, int *__restrict__ ub) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == ST_C) { ub[i] = 1; return; }
+    int c = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        if (!s[e]) continue;
+        int j = ci[e];
+        if (cf[j] == ST_C) { c++; continue; }
+        for (int f = rp[j]; f < rp[j + 1]; ++f)
+            if (s[f] && cf[ci[f]] == ST_C) c++;
+    }
+    ub[i] = c > 0 ? c : 1;
+}
+
+void amg_exti_bound(int n, const int *rp, const int *ci, const unsigned char *s, const int *cf, int *ub,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_exti_bound, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, rp, ci, s, cf, ub);
+    CPTR_CHECK_LAUNCH();
+}
+
+__device__ inline double abar_of(double akk, double akl) {
+    return ((akk > 0.0 && akl < 0.0) || (akk < 0.0 && akl > 0.0)) ? akl : 0.0;
+}
+
+// value of entry (row, col) of a CSR matrix with ascending columns (0 if absent)
+__device__ inline double csr_value(const int *rp, const int *ci, const double *v, int row, int col) {
+    int lo = rp[row], hi = rp[row + 1] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int c = ci[mid];
+        if (c == col) return v[mid];
+        if (c < col) lo = mid + 1; else hi = mid - 1;
+    }
+    return 0.0;
+}
+
+__device__ inline bool in_sorted(const int *a, int len, int key) {
+    int lo = 0, hi = len - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int c = a[mid];
+        if (c == key) return true;
+        if (c < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return false;
+}
+
+// One thread per row.  Writes the row of P (coarse columns, weights) into the
+// scratch segment [off[i], off[i] + cnt[i]).  Evaluation order:
+//   d_k      = sum over row k ascending of abar_kl, l in Chat_i u {i} (zero terms skipped)
+//   atilde   = a_ii, then over row i ascending: + a_in (weak, not in Chat) or
+//              + (a_ik abar_ki) / d_k (strong F with d_k != 0) or + a_ik (strong F, d_k = 0)
+//   num_j    = a_ij, then over strong F k ascending: + (a_ik abar_kj) / d_k
+//   w_ij     = -num_j / atilde
+//   truncation to the pmax largest |w| (ties: lower column), kept weights times
+//   (sum of all w) / (sum of kept w), both sums in ascending column order.
+__global__ void k_exti_compute(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                               const double *__restrict__ v, const unsigned char *__restrict__ s,
+                               const int *__restrict__ cf, const int *__restrict__ cidx, const double *__restrict__ dg,
+                               int pmax, const int *__restrict__ off, int *__restrict__ tcol,
+                               double *__restrict__ tw, double *__restrict__ td, int *__restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int *hat = tcol + off[i];
+    double *w = tw + off[i];
+    if (cf[i] == ST_C) {
+        hat[0] = cidx[i];
+        w[0] = 1.0;
+        cnt[i] = 1;
+        return;
+    }
+    const int a = rp[i], b = rp[i + 1];
+    // gather Chat_i (fine indices), sort, unique
+    int nh = 0;
+    for (int e = a; e < b; ++e) {
+        if (!s[e]) continue;
+        int j = ci[e];
+        if (cf[j] == ST_C) { hat[nh++] = j; continue; }
+        for (int f = rp[j]; f < rp[j + 1]; ++f)
+            if (s[f] && cf[ci[f]] == ST_C) hat[nh++] = ci[f];
+    }
+    if (nh == 0) { cnt[i] = 0; return; }
+    for (int p = 1; p < nh; ++p) {
+        int t = hat[p], q = p - 1;
+        while (q >= 0 && hat[q] > t) { hat[q + 1] = hat[q]; --q; }
+        hat[q + 1] = t;
+    }
+    int u = 1;
+    for (int p = 1; p < nh; ++p)
+        if (hat[p] != hat[u - 1]) hat[u++] = hat[p];
+    nh = u;
+    // d_k of every strong F neighbour, stored at the neighbour's entry position
+    for (int e = a; e < b; ++e) {
+        int k = ci[e];
+        if (!s[e] || cf[k] == ST_C) continue;
+        const double akk = dg[k];
+        double d = 0.0;
+        for (int f = rp[k]; f < rp[k + 1]; ++f) {
+            int l = ci[f];
+            if (l == i || (l != k && cf[l] == ST_C && in_sorted(hat, nh, l))) {
+                double ab = abar_of(akk, v[f]);
+                if (ab != 0.0) d = d + ab;
+            }
+        }
+        td[e] = d;
+    }
+    const double aii = dg[i];
+    double at = aii;
+    for (int e = a; e < b; ++e) {
+        int nn = ci[e];
+        if (nn == i) continue;
+        if (s[e] && cf[nn] == ST_F) {
+            double d = td[e];
+            if (d != 0.0) {
+                double ab = abar_of(dg[nn], csr_value(rp, ci, v, nn, i));
+                if (ab != 0.0) at = at + (v[e] * ab) / d;
+            } else {
+                at = at + v[e];
+            }
+        } else if (!s[e] && !(cf[nn] == ST_C && in_sorted(hat, nh, nn))) {
+            at = at + v[e];
+        }
+    }
+    if (at == 0.0) { cnt[i] = 0; return; }
+    for (int p = 0; p < nh; ++p) {
+        const int j = hat[p];
+        double num = csr_value(rp, ci, v, i, j);
+        for (int e = a; e < b; ++e) {
+            int k = ci[e];
+            if (k == i || !s[e] || cf[k] == ST_C) continue;
+            double d = td[e];
+            if (d == 0.0) continue;
+            double ab = abar_of(dg[k], csr_value(rp, ci, v, k, j));
+            if (ab == 0.0) continue;
+            num = num + (v[e] * ab) / d;
+        }
+        w[p] = -num / at;
+    }
+    int keep = nh;
+    if (pmax > 0 && nh > pmax) {
+        // mark kept entries by encoding the column as -1 - col
+        for (int q = 0; q < pmax; ++q) {
+            int best = -1;
+            double bv = 0.0;
+            for (int p = 0; p < nh; ++p) {
+                if (hat[p] < 0) continue;
+                double av = fabs(w[p]);
+                if (best < 0 || av > bv) { best = p; bv = av; }
+            }
+            hat[best] = -1 - hat[best];
+        }
+        double sall = 0.0, skept = 0.0;
+        for (int p = 0; p < nh; ++p) sall = sall + w[p];
+        for (int p = 0; p < nh; ++p) if (hat[p] < 0) skept = skept + w[p];
+        const double scale = (skept != 0.0) ? sall / skept : 1.0;
+        int q = 0;
+        for (int p = 0; p < nh; ++p) {
+            if (hat[p] >= 0) continue;
+            int col = -1 - hat[p];
+            double wv = (skept != 0.0) ? w[p] * scale : w[p];
+            hat[q] = col;
+            w[q] = wv;
+            q++;
+        }
+        keep = pmax;
+    }
+    for (int p = 0; p < keep; ++p) hat[p] = cidx[hat[p]];
+    cnt[i] = keep;
+}
+
+void amg_exti_compute2(int n, const int *rp, const int *ci, const double *v, const unsigned char *s, const int *cf,
+                       const int *cidx, const double *dg, int pmax, const int *off, int *tcol, double *tw,
+                       double *td, int *cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_exti_compute, dim3(blocks_for(n, 128)), dim3(128), 0, st, n, rp, ci, v, s, cf, cidx, dg,
+                       pmax, off, tcol, tw, td, cnt);
+    CPTR_CHECK_LAUNCH();
+}
+
+// copy segments [off[i], off[i] + (prp[i+1]-prp[i])) to the compact CSR
+__global__ void k_compact(int n, const int *__restrict__ off, const int *__restrict__ tcol,
+                          const double *__restrict__ tw, const int *__restrict__ prp, int *__restrict__ pci,
+                          double *__restrict__ pv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int o = off[i], d = prp[i], c = prp[i + 1] - prp[i];
+    for (int p = 0; p < c; ++p) { pci[d + p] = tcol[o + p]; pv[d + p] = tw[o + p]; }
+}
+
+void amg_compact(int n, const int *off, const int *tcol, const double *tw, const int *prp, int *pci, double *pv,
+                 hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, off, tcol, tw, prp, pci, pv);
+    CPTR_CHECK_LAUNCH();
+}
+
+// --------------------------------------------------------------------------
+// transpose (R = P^T): count, scan, scatter, then sort each row by column
+// --------------------------------------------------------------------------
+__global__ void k_tr_count(int nr, const int *__restrict__ rp, const int *__restrict__ ci, int *__restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) atomicAdd(&cnt[ci[e]], 1);
+}
+
+__global__ void k_tr_scatter(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const double *__restrict__ v, int *__restrict__ cursor, int *__restrict__ ciT,
+                             double *__restrict__ vT) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int p = atomicAdd(&cursor[ci[e]], 1);
+        ciT[p] = i;
+        vT[p] = v[e];
+    }
+}
+
+__global__ void k_sort_rows(int n, const int *__restrict__ rp, int *__restrict__ ci, double *__restrict__ v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int a = rp[i], b = rp[i + 1];
+    for (int p = a + 1; p < b; ++p) {
+        int c = ci[p];
+        double x = v[p];
+        int q = p - 1;
+        while (q >= a && ci[q] > c) { ci[q + 1] = ci[q]; v[q + 1] = v[q]; --q; }
+        ci[q + 1] = c;
+        v[q + 1] = x;
+    }
+}
+
+void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v, int *rpT, int *ciT, double *vT,
+                   int *work, hipStream_t st) {
+    fill_int(work, 0, (size_t)nc + 1, st);
+    hipLaunchKernelGGL(k_tr_count, dim3(blocks_for(nr, 256)), dim3(256), 0, st, nr, rp, ci, work);
+    scan_exclusive(work, rpT, nc, nullptr, st);
+    CPTR_HIP(hipMemcpyAsync(work, rpT, sizeof(int) * nc, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_tr_scatter, dim3(blocks_for(nr, 256)), dim3(256), 0, st, nr, rp, ci, v, work, ciT, vT);
+    hipLaunchKernelGGL(k_sort_rows, dim3(blocks_for(nc, 128)), dim3(128), 0, st, nc, rpT, ciT, vT);
+    CPTR_CHECK_LAUNCH();
+}
+
+// --------------------------------------------------------------------------
+// SpGEMM C = A B (Gustavson, one thread per row, open-addressing hash
+// accumulator processed in A's row order, so every output entry sums its terms
+// in ascending k starting from the first term)
+// --------------------------------------------------------------------------
+__global__ void k_spgemm_bound(int m, const int *__restrict__ arp, const int *__restrict__ aci,
+                               const int *__restrict__ brp, int *__restrict__ ub) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int c = 0;
+    for (int e = arp[i]; e < arp[i + 1]; ++e) {
+        int k = aci[e];
+        c += brp[k + 1] - brp[k];
+    }
+    ub[i] = 2 * c + 1;      // hash capacity
+}
+
+void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, hipStream_t st) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_spgemm_bound, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, arp, aci, brp, ub);
+    CPTR_CHECK_LAUNCH();
+}
+
+__global__ void k_spgemm_compute(int m, const int *__restrict__ arp, const int *__restrict__ aci,
+                                 const double *__restrict__ av, const int *__restrict__ brp,
+                                 const int *__restrict__ bci, const double *__restrict__ bv,
+                                 const int *__restrict__ off, int *__restrict__ tcol, double *__restrict__ tval,
+                                 int *__restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int cap = off[i + 1] - off[i];
+    int *hk = tcol + off[i];
+    double *hv = tval + off[i];
+    for (int p = 0; p < cap; ++p) hk[p] = -1;
+    for (int e = arp[i]; e < arp[i + 1]; ++e) {
+        const int k = aci[e];
+        const double a = av[e];
+        for (int f = brp[k]; f < brp[k + 1]; ++f) {
+            const int j = bci[f];
+            const double t = a * bv[f];
+            unsigned hsh = ((unsigned)j * 2654435761u) % (unsigned)cap;
+            while (true) {
+                int key = hk[hsh];
+                if (key == -1) { hk[hsh] = j; hv[hsh] = t; break; }
+                if (key == j) { hv[hsh] = hv[hsh] + t; break; }
+                hsh = (hsh + 1 == (unsigned)cap) ? 0u : hsh + 1;
+            }
+        }
+    }
+    // compact the occupied slots to the front, then sort by column
+    int u = 0;
+    for (int p = 0; p < cap; ++p) {
+        if (hk[p] < 0) continue;
+        int c = hk[p];
+        double x = hv[p];
+        hk[u] = c;
+        hv[u] = x;
+        u++;
+    }
+    for (int p = 1; p < u; ++p) {
+        int c = hk[p];
+        double x = hv[p];
+        int q = p - 1;
+        while (q >= 0 && hk[q] > c) { hk[q + 1] = hk[q]; hv[q + 1] = hv[q]; --q; }
+        hk[q + 1] = c;
+        hv[q + 1] = x;
+    }
+    cnt[i] = u;
+}
+
+void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
+                        const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_spgemm_compute, dim3(blocks_for(m, 64)), dim3(64), 0, st, m, arp, aci, av, brp, bci, bv,
+                       off, tcol, tval, cnt);
+    CPTR_CHECK_LAUNCH();
+}
+
+// --------------------------------------------------------------------------
+// smoother diagonal and the coarsest level
+// --------------------------------------------------------------------------
+// dinv = 1 / a_ii (Jacobi) or 1 / (a_ii + sign(a_ii) sum_{j!=i} |a_ij|) (l1-Jacobi);
+// diag = a_ii; flag bit 32 on a zero diagonal
+__global__ void k_diag_inv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                           const double *__restrict__ v, int smoother, double *__restrict__ dinv,
+                           double *__restrict__ diag, int *flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double aii = 0.0, l1 = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        if (ci[e] == i) aii = v[e];
+        else l1 += fabs(v[e]);
+    }
+    if (diag) diag[i] = aii;
+    double d = aii;
+    if (smoother == CPTR_SMOOTH_L1JACOBI) d = aii + ((aii < 0.0) ? -l1 : l1);
+    if (d == 0.0) { atomicOr(flag, 32); dinv[i] = 0.0; return; }
+    dinv[i] = 1.0 / d;
+}
+
+void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
+                   int *flag, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_diag_inv, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, rp, ci, v, smoother, dinv, diag,
+                       flag);
+    CPTR_CHECK_LAUNCH();
+}
+
+// aug = [A | I], n x 2n row-major
+__global__ void k_dense_aug(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                            const double *__restrict__ v, double *__restrict__ aug) {
+    int r = blockIdx.x;
+    if (r >= n) return;
+    for (int c = threadIdx.x; c < 2 * n; c += blockDim.x) aug[(size_t)r * 2 * n + c] = (c == n + r) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int e = rp[r] + threadIdx.x; e < rp[r + 1]; e += blockDim.x) aug[(size_t)r * 2 * n + ci[e]] = v[e];
+}
+
+// Gauss-Jordan elimination with partial pivoting, without row normalisation,
+// one launch per column k.  Every block first finds the pivot of column k
+// redundantly (the first unused row with the largest |aug[r][k]|; rows used by
+// earlier steps are excluded through used[] (steps < k-1, written by earlier
+// launches) and pivrow[k-1]), so all blocks agree without a grid barrier; block
+// (0,0) records pivrow[k] and marks the previous pivot used.  Then every row
+// r != p of the block's row range gets aug[r][c] -= (aug[r][k]/aug[p][k]) aug[p][c]
+// for the block's columns c > k.
+constexpr int GJ_ROWS = 16;
+
+__global__ void __launch_bounds__(256) k_gj_step(int n, int k, double *aug, int *used, int *pivrow, int *flag) {
+    __shared__ double bv[256];
+    __shared__ int bi[256];
+    const size_t ld = 2 * (size_t)n;
+    const int pprev = (k > 0) ? pivrow[k - 1] : -1;
+    double best = -1.0;
+    int arg = -1;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        if (r == pprev || used[r]) continue;
+        double a = fabs(aug[(size_t)r * ld + k]);
+        if (a > best) { best = a; arg = r; }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = arg;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            double ov = bv[threadIdx.x + s];
+            int oi = bi[threadIdx.x + s];
+            if (oi >= 0 && (bi[threadIdx.x] < 0 || ov > bv[threadIdx.x] ||
+                            (ov == bv[threadIdx.x] && oi < bi[threadIdx.x]))) {
+                bv[threadIdx.x] = ov;
+                bi[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    int p = bi[0];
+    const bool bad = (p < 0) || (bv[0] == 0.0);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        pivrow[k] = (p < 0) ? 0 : p;
+        if (pprev >= 0) used[pprev] = 1;
+        if (bad) atomicOr(flag, 64);
+    }
+    if (bad) return;
+    const double piv = aug[(size_t)p * ld + k];
+    const int c = k + 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= 2 * n) return;
+    const double pc = aug[(size_t)p * ld + c];
+    const int r0 = blockIdx.y * GJ_ROWS;
+    const int r1 = min(n, r0 + GJ_ROWS);
+    for (int r = r0; r < r1; ++r) {
+        if (r == p) continue;
+        const double f = aug[(size_t)r * ld + k] / piv;
+        aug[(size_t)r * ld + c] -= f * pc;
+    }
+}
+
+// inv[k][c] = aug[p_k][n + c] / aug[p_k][k]
+__global__ void k_gj_extract(int n, const double *aug, const int *pivrow, double *inv, float *inv32) {
+    int k = blockIdx.x;
+    if (k >= n) return;
+    int p = pivrow[k];
+    const size_t ld = 2 * (size_t)n;
+    double d = aug[(size_t)p * ld + k];
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        double x = aug[(size_t)p * ld + n + c] / d;
+        inv[(size_t)k * n + c] = x;
+        if (inv32) inv32[(size_t)k * n + c] = (float)x;
+    }
+}
+
+void amg_dense_inverse(int n, const int *rp, const int *ci, const double *v, double *aug, int *used, int *pivrow,
+                       int *flag, double *inv, float *inv32, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_dense_aug, dim3(n), dim3(256), 0, st, n, rp, ci, v, aug);
+    fill_int(used, 0, n, st);
+    const int nby = (n + GJ_ROWS - 1) / GJ_ROWS;
+    for (int k = 0; k < n; ++k) {
+        int width = 2 * n - (k + 1);
+        int nbx = (width + 255) / 256;
+        if (nbx < 1) nbx = 1;
+        hipLaunchKernelGGL(k_gj_step, dim3(nbx, nby), dim3(256), 0, st, n, k, aug, used, pivrow, flag);
+    }
+    hipLaunchKernelGGL(k_gj_extract, dim3(n), dim3(256), 0, st, n, aug, pivrow, inv, inv32);
+    CPTR_CHECK_LAUNCH();
+}
+
+}  // namespace cptr

@@ -1,0 +1,393 @@
+// Last stage of the multi-stage preconditioner: block ILU(0) of the scaled
+// matrix (ilu(Abar), Eqs. CPRM1 ff. and CPTR3M3; block variant per the remark
+// on cell-wise interleaving) and block Jacobi.
+//
+// Elimination order: the nx x ny grid is cut into tiles; tiles are coloured
+// red/black like a checkerboard; all red tiles come before all black tiles and
+// each tile keeps the natural (x fastest) order inside.  ILU(0) in this order
+// is a global ILU(0) of Abar.  Red tiles are mutually independent (no 5-point
+// coupling between two red tiles), likewise black tiles, so one workgroup per
+// tile runs the tile's anti-diagonal wavefront in parallel with all other
+// tiles of its colour.  On the 5-point pattern zero fill changes only the
+// diagonal blocks:  D_i = Abar_ii - sum_{k lower, (k,i) stored} Abar_ik D_k^{-1} Abar_ki,
+// and M = (D + L) D^{-1} (D + U) with L, U the off-diagonal blocks of Abar.
+#include "internal.h"
+
+namespace cptr {
+
+constexpr int BL_THREADS = 256;
+
+struct TileGeom {
+    int nx, ny, tx, ty, ntx;
+};
+
+// cells of tile `tile` at anti-diagonal `lev`: lx in [lo, hi], ly = lev - lx
+__device__ inline void tile_dims(const TileGeom &g, int tile, int &x0, int &y0, int &tw, int &th) {
+    int tix = tile % g.ntx, tiy = tile / g.ntx;
+    x0 = tix * g.tx;
+    y0 = tiy * g.ty;
+    tw = min(g.tx, g.nx - x0);
+    th = min(g.ty, g.ny - y0);
+}
+
+template <class T>
+__device__ inline T shfl(T v, int src) { return __shfl(v, src, 64); }
+
+// ---------------------------------------------------------------------------
+// factorisation: lanes of a group own the rows of one cell's block
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ void __launch_bounds__(BL_THREADS) k_bilu_factor(TileGeom g, const int *__restrict__ tiles,
+                                                             const int *__restrict__ color,
+                                                             const int *__restrict__ rp, const int *__restrict__ ci,
+                                                             const int *__restrict__ tpos,
+                                                             const double *__restrict__ abar,
+                                                             double *__restrict__ dinv, int *flag,
+                                                             int diag_only) {
+    constexpr int GPW = 64 / B;               // cell groups per wavefront
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = lane / B, r = lane % B;
+    const bool active_lane = grp < GPW;
+    const int slot = wave * GPW + grp;        // cell slot inside the block
+    const int slots = (BL_THREADS / 64) * GPW;
+    const int gbase = grp * B;
+    int x0, y0, tw, th;
+    tile_dims(g, tiles ? tiles[blockIdx.x] : (int)blockIdx.x, x0, y0, tw, th);
+    const int nlev = tw + th - 1;
+    for (int lev = 0; lev < nlev; ++lev) {
+        const int lo = max(0, lev - th + 1), hi = min(lev, tw - 1);
+        for (int base = lo; base <= hi; base += slots) {
+            const int lx = base + slot;
+            const bool act = active_lane && lx <= hi;
+            const int i = act ? (x0 + lx) + g.nx * (y0 + (lev - lx)) : 0;
+            double row[B], inv[B];
+            int myk = -1;
+            bool bad = false;
+            if (act) {
+                int d = -1;
+                for (int e = rp[i]; e < rp[i + 1]; ++e) if (ci[e] == i) d = e;
+                for (int c = 0; c < B; ++c) row[c] = abar[(size_t)d * B * B + r * B + c];
+                if (!diag_only) {
+                    const int ci_ = color[i];
+                    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                        const int k = ci[e];
+                        if (k == i) continue;
+                        const int ck = color[k];
+                        if (!(ck < ci_ || (ck == ci_ && k < i))) continue;
+                        const int et = tpos[e];               // block (k, i)
+                        const double *Aik = abar + (size_t)e * B * B + r * B;
+                        const double *Dk = dinv + (size_t)k * B * B;
+                        const double *Aki = abar + (size_t)et * B * B;
+                        double y[B];
+                        for (int c = 0; c < B; ++c) {
+                            double t = 0.0;
+                            for (int m = 0; m < B; ++m) t += Aik[m] * Dk[m * B + c];
+                            y[c] = t;
+                        }
+                        for (int c = 0; c < B; ++c) {
+                            double t = 0.0;
+                            for (int m = 0; m < B; ++m) t += y[m] * Aki[m * B + c];
+                            row[c] -= t;
+                        }
+                    }
+                }
+                for (int c = 0; c < B; ++c) inv[c] = (c == r) ? 1.0 : 0.0;
+            }
+            // Gauss-Jordan with partial pivoting across the B lanes of the group
+            bool used = false;
+            for (int k = 0; k < B; ++k) {
+                const double mine = (act && !used) ? fabs(row[k]) : -1.0;
+                double cand = -2.0;
+                int who = 0;
+                for (int q = 0; q < B; ++q) {     // first lane with the largest |pivot|
+                    const double oc = shfl(mine, gbase + q);
+                    if (oc > cand) { cand = oc; who = q; }
+                }
+                const int p = who;
+                if (act && cand <= 0.0) bad = true;
+                double prow[B], pinv[B];
+                for (int c = 0; c < B; ++c) {
+                    prow[c] = shfl(row[c], gbase + p);
+                    pinv[c] = shfl(inv[c], gbase + p);
+                }
+                if (act) {
+                    if (r == p) {
+                        used = true;
+                        myk = k;
+                    } else if (!bad) {
+                        const double f = row[k] / prow[k];
+                        for (int c = 0; c < B; ++c) {
+                            row[c] -= f * prow[c];
+                            inv[c] -= f * pinv[c];
+                        }
+                    }
+                }
+            }
+            if (act) {
+                if (bad) {
+                    atomicMin(flag, i);
+                } else {
+                    const double dk = row[myk];
+                    for (int c = 0; c < B; ++c) dinv[(size_t)i * B * B + myk * B + c] = inv[c] / dk;
+                }
+            }
+            __syncthreads();   // the next level reads this level's D^{-1}
+        }
+    }
+}
+
+void bilu_factor_tiles(const TileSched &ts, int n, int b, const int *rp, const int *ci, const int *tpos,
+                       const double *abar, double *dinv, int *flag, int color, int diag_only, hipStream_t st) {
+    (void)n;
+    const int nt = ts.ntiles[color];
+    if (nt == 0) return;
+    TileGeom g{ts.nx, ts.ny, ts.tx, ts.ty, ts.ntx};
+#define CASE(BB) case BB: hipLaunchKernelGGL(k_bilu_factor<BB>, dim3(nt), dim3(BL_THREADS), 0, st, g, ts.tiles[color].p, ts.color.p, rp, ci, tpos, abar, dinv, flag, diag_only); break;
+    switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// apply: u computed on the fly (Algorithm 2's residual updates), then the
+// triangular sweeps.  Modes: 0 forward, 1 forward then backward (the last
+// colour), 2 backward.  tw holds t after the forward sweep, w after the
+// backward one.  y = w + xT e_T + vP e_P.
+// ---------------------------------------------------------------------------
+template <class T, int B>
+__device__ inline T u_entry(int i, int r, const int *rp, const int *ci, const T *slabT, const T *slabP,
+                            const double *rv, const T *xT, const T *vP) {
+    T u = (T)rv[(size_t)i * B + r];
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        if (xT) u -= slabT[(size_t)e * B + r] * xT[j];
+        if (vP) u -= slabP[(size_t)e * B + r] * vP[j];
+    }
+    return u;
+}
+
+template <class T, int B>
+__global__ void __launch_bounds__(BL_THREADS) k_bilu_apply(TileGeom g, int mode, const int *__restrict__ tiles,
+                                                            const int *__restrict__ color,
+                                                            const int *__restrict__ rp, const int *__restrict__ ci,
+                                                            const T *__restrict__ abar, const T *__restrict__ dinv,
+                                                            const T *__restrict__ slabT, const T *__restrict__ slabP,
+                                                            int ip, int it, const double *__restrict__ rv,
+                                                            const T *__restrict__ xT, const T *__restrict__ vP,
+                                                            T *__restrict__ tw, double *__restrict__ y) {
+    constexpr int GPW = 64 / B;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = lane / B, r = lane % B;
+    const bool active_lane = grp < GPW;
+    const int slot = wave * GPW + grp;
+    const int slots = (BL_THREADS / 64) * GPW;
+    const int gbase = grp * B;
+    int x0, y0, twd, th;
+    tile_dims(g, tiles[blockIdx.x], x0, y0, twd, th);
+    const int nlev = twd + th - 1;
+    if (mode == 0 || mode == 1) {
+        for (int lev = 0; lev < nlev; ++lev) {
+            const int lo = max(0, lev - th + 1), hi = min(lev, twd - 1);
+            for (int base = lo; base <= hi; base += slots) {
+                const int lx = base + slot;
+                const bool act = active_lane && lx <= hi;
+                const int i = act ? (x0 + lx) + g.nx * (y0 + (lev - lx)) : 0;
+                T s = 0;
+                if (act) {
+                    s = u_entry<T, B>(i, r, rp, ci, slabT, slabP, rv, xT, vP);
+                    const int ci_ = color[i];
+                    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                        const int k = ci[e];
+                        if (k == i) continue;
+                        const int ck = color[k];
+                        if (!(ck < ci_ || (ck == ci_ && k < i))) continue;
+                        const T *Aik = abar + (size_t)e * B * B + r * B;
+                        const T *tk = tw + (size_t)k * B;
+                        for (int m = 0; m < B; ++m) s -= Aik[m] * tk[m];
+                    }
+                }
+                T tval = 0;
+                const T *Di = dinv + (size_t)i * B * B + r * B;
+                for (int c = 0; c < B; ++c) {
+                    T sc = shfl(s, gbase + c);
+                    if (act) tval += Di[c] * sc;
+                }
+                if (act) tw[(size_t)i * B + r] = tval;
+            }
+            __syncthreads();
+        }
+    }
+    if (mode == 1 || mode == 2) {
+        for (int lev = nlev - 1; lev >= 0; --lev) {
+            const int lo = max(0, lev - th + 1), hi = min(lev, twd - 1);
+            for (int base = lo; base <= hi; base += slots) {
+                const int lx = base + slot;
+                const bool act = active_lane && lx <= hi;
+                const int i = act ? (x0 + lx) + g.nx * (y0 + (lev - lx)) : 0;
+                T q = 0;
+                if (act) {
+                    const int ci_ = color[i];
+                    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                        const int j = ci[e];
+                        if (j == i) continue;
+                        const int cj = color[j];
+                        if (!(cj > ci_ || (cj == ci_ && j > i))) continue;
+                        const T *Aij = abar + (size_t)e * B * B + r * B;
+                        const T *wj = tw + (size_t)j * B;
+                        for (int m = 0; m < B; ++m) q += Aij[m] * wj[m];
+                    }
+                }
+                T corr = 0;
+                const T *Di = dinv + (size_t)i * B * B + r * B;
+                for (int c = 0; c < B; ++c) {
+                    T qc = shfl(q, gbase + c);
+                    if (act) corr += Di[c] * qc;
+                }
+                if (act) {
+                    const T w = tw[(size_t)i * B + r] - corr;
+                    tw[(size_t)i * B + r] = w;
+                    double yv = (double)w;
+                    if (r == it && xT) yv += (double)xT[i];
+                    if (r == ip && vP) yv += (double)vP[i];
+                    y[(size_t)i * B + r] = yv;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <class T>
+void bilu_apply_tiles(const TileSched &ts, int b, const int *rp, const int *ci, const T *abar, const T *dinv,
+                      const T *slabT, const T *slabP, int ip, int it, const double *r, const T *xT, const T *vP,
+                      T *tw, double *y, hipStream_t st) {
+    TileGeom g{ts.nx, ts.ny, ts.tx, ts.ty, ts.ntx};
+    auto launch = [&](int color, int mode) {
+        const int nt = ts.ntiles[color];
+        if (nt == 0) return;
+#define CASE(BB) case BB: hipLaunchKernelGGL((k_bilu_apply<T, BB>), dim3(nt), dim3(BL_THREADS), 0, st, g, mode, ts.tiles[color].p, ts.color.p, rp, ci, abar, dinv, slabT, slabP, ip, it, r, xT, vP, tw, y); break;
+        switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
+        CPTR_CHECK_LAUNCH();
+    };
+    if (ts.ntiles[1] == 0) {
+        launch(0, 1);
+    } else {
+        launch(0, 0);
+        launch(1, 1);
+        launch(0, 2);
+    }
+}
+template void bilu_apply_tiles<double>(const TileSched &, int, const int *, const int *, const double *,
+                                       const double *, const double *, const double *, int, int, const double *,
+                                       const double *, const double *, double *, double *, hipStream_t);
+template void bilu_apply_tiles<float>(const TileSched &, int, const int *, const int *, const float *,
+                                      const float *, const float *, const float *, int, int, const double *,
+                                      const float *, const float *, float *, double *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// block Jacobi: y_i = D_i^{-1} u_i + xT e_T + vP e_P   (D_i^{-1} = inv(Abar_ii))
+// ---------------------------------------------------------------------------
+template <class T, int B>
+__global__ void __launch_bounds__(BL_THREADS) k_bj_apply(int n, const int *__restrict__ rp,
+                                                          const int *__restrict__ ci, const T *__restrict__ dinv,
+                                                          const T *__restrict__ slabT, const T *__restrict__ slabP,
+                                                          int ip, int it, const double *__restrict__ rv,
+                                                          const T *__restrict__ xT, const T *__restrict__ vP,
+                                                          double *__restrict__ y) {
+    constexpr int GPW = 64 / B;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = lane / B, r = lane % B;
+    const int i = (blockIdx.x * (BL_THREADS / 64) + wave) * GPW + grp;
+    const bool act = grp < GPW && i < n;
+    const int gbase = grp * B;
+    T s = act ? u_entry<T, B>(i, r, rp, ci, slabT, slabP, rv, xT, vP) : (T)0;
+    T w = 0;
+    const T *Di = dinv + (size_t)(act ? i : 0) * B * B + r * B;
+    for (int c = 0; c < B; ++c) {
+        T sc = shfl(s, gbase + c);
+        if (act) w += Di[c] * sc;
+    }
+    if (act) {
+        double yv = (double)w;
+        if (r == it && xT) yv += (double)xT[i];
+        if (r == ip && vP) yv += (double)vP[i];
+        y[(size_t)i * B + r] = yv;
+    }
+}
+
+template <class T>
+void bj_apply_cells(int n, int b, const int *rp, const int *ci, const T *dinv, const T *slabT, const T *slabP,
+                    int ip, int it, const double *r, const T *xT, const T *vP, double *y, hipStream_t st) {
+    if (n == 0) return;
+    const int cells_per_block = (BL_THREADS / 64) * (64 / b);
+    const int nb = (n + cells_per_block - 1) / cells_per_block;
+#define CASE(BB) case BB: hipLaunchKernelGGL((k_bj_apply<T, BB>), dim3(nb), dim3(BL_THREADS), 0, st, n, rp, ci, dinv, slabT, slabP, ip, it, r, xT, vP, y); break;
+    switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+template void bj_apply_cells<double>(int, int, const int *, const int *, const double *, const double *,
+                                     const double *, int, int, const double *, const double *, const double *,
+                                     double *, hipStream_t);
+template void bj_apply_cells<float>(int, int, const int *, const int *, const float *, const float *,
+                                    const float *, int, int, const double *, const float *, const float *,
+                                    double *, hipStream_t);
+
+// block Jacobi factors: the same group Gauss-Jordan on every diagonal block
+// (the tile kernel with diag_only over a single "tile" per cell is not needed:
+// reuse it with a 1 x 1 tile geometry)
+void bj_factor_cells(int n, int b, const int *rp, const int *ci, const double *abar, double *dinv, int *flag,
+                     const int *all_cells_tiles, hipStream_t st) {
+    if (n == 0) return;
+    TileGeom g{n, 1, 1, 1, n};
+#define CASE(BB) case BB: hipLaunchKernelGGL(k_bilu_factor<BB>, dim3(n), dim3(BL_THREADS), 0, st, g, all_cells_tiles, nullptr, rp, ci, nullptr, abar, dinv, flag, 1); break;
+    switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+// the BSR pattern must be a subset of the 5-point grid stencil for the tile
+// order (flag bit 128 otherwise)
+__global__ void k_check_5pt(int n, int nx, const int *__restrict__ rp, const int *__restrict__ ci, int *flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int xi = i % nx, yi = i / nx;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int j = ci[e];
+        if (j == i) continue;
+        int xj = j % nx, yj = j / nx;
+        if (abs(xi - xj) + abs(yi - yj) != 1) { atomicOr(flag, 128); return; }
+    }
+}
+
+// colour of every cell and the tile lists per colour
+__global__ void k_tile_colors(int nx, int ny, int tx, int ty, int *color) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx * ny) return;
+    int x = i % nx, y = i / nx;
+    color[i] = ((x / tx) + (y / ty)) & 1;
+}
+
+void tiles_build(TileSched &ts, int n, int nx, int ny, int tx, int ty, const int *rp, const int *ci, int *flag,
+                 hipStream_t st) {
+    ts.nx = nx; ts.ny = ny; ts.tx = tx; ts.ty = ty;
+    ts.ntx = (nx + tx - 1) / tx;
+    ts.nty = (ny + ty - 1) / ty;
+    std::vector<int> lists[2];
+    for (int t = 0; t < ts.ntx * ts.nty; ++t) lists[((t % ts.ntx) + (t / ts.ntx)) & 1].push_back(t);
+    for (int c = 0; c < 2; ++c) {
+        ts.ntiles[c] = (int)lists[c].size();
+        ts.tiles[c].alloc(lists[c].size() + 1);
+        if (!lists[c].empty())
+            CPTR_HIP(hipMemcpyAsync(ts.tiles[c].p, lists[c].data(), sizeof(int) * lists[c].size(),
+                                    hipMemcpyHostToDevice, st));
+    }
+    ts.color.alloc(n);
+    hipLaunchKernelGGL(k_tile_colors, dim3((n + 255) / 256), dim3(256), 0, st, nx, ny, tx, ty, ts.color.p);
+    hipLaunchKernelGGL(k_check_5pt, dim3((n + 255) / 256), dim3(256), 0, st, n, nx, rp, ci, flag);
+    CPTR_HIP(hipStreamSynchronize(st));   // host lists must outlive the copies
+    CPTR_CHECK_LAUNCH();
+}
+
+}  // namespace cptr

@@ -1,0 +1,210 @@
+// Shared device utilities: prefix scan, fills, pattern checks, conversions.
+#include "internal.h"
+
+namespace cptr {
+
+constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+// exclusive scan of one value per thread across a 1024-thread block
+__device__ inline int block_scan_excl(int v, int *lds_waves, int *total) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds_waves[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+        int w = (lane < (int)(blockDim.x >> 6)) ? lds_waves[lane] : 0;
+        int s = w;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            int y = __shfl_up(s, d, 64);
+            if (lane >= d) s += y;
+        }
+        if (lane < (int)(blockDim.x >> 6)) lds_waves[lane] = s - w;
+        if (lane == (int)(blockDim.x >> 6) - 1) lds_waves[32] = s;
+    }
+    __syncthreads();
+    int r = x - v + lds_waves[wave];
+    if (total) *total = lds_waves[32];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_blocksum(const int *in, int n, int *bsum) {
+    __shared__ int lds[33];
+    long base = (long)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) s += in[base + k];
+    int tot;
+    block_scan_excl(s, lds, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_offsets(int *bsum, int nb, int *out_total) {
+    __shared__ int lds[33];
+    int carry = 0;
+    for (int base = 0; base < nb; base += SCAN_THREADS) {
+        int i = base + threadIdx.x;
+        int v = (i < nb) ? bsum[i] : 0;
+        int tot;
+        int e = block_scan_excl(v, lds, &tot);
+        if (i < nb) bsum[i] = e + carry;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *out_total = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_final(const int *in, int n, const int *boff, int *out) {
+    __shared__ int lds[33];
+    long base = (long)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int e = block_scan_excl(s, lds, nullptr) + boff[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = e;
+        e += v[k];
+    }
+}
+
+// scratch for the block sums: grown on demand and kept for the life of the
+// process (one small allocation per device; never freed so that no HIP call
+// runs during static destruction)
+static int *g_scan_scratch[64];
+static size_t g_scan_cap[64];
+
+void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t s) {
+    int nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb < 1) nb = 1;
+    int dev = 0;
+    CPTR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) throw Error(CPTR_E_ARG, "device index out of range");
+    if ((size_t)nb > g_scan_cap[dev]) {
+        CPTR_HIP(hipStreamSynchronize(s));
+        if (g_scan_scratch[dev]) CPTR_HIP(hipFree(g_scan_scratch[dev]));
+        g_scan_scratch[dev] = nullptr;
+        g_scan_cap[dev] = 0;
+        size_t cap = (size_t)nb * 2 + 64;
+        CPTR_HIP(hipMalloc((void **)&g_scan_scratch[dev], cap * sizeof(int)));
+        g_scan_cap[dev] = cap;
+    }
+    int *bsum = g_scan_scratch[dev];
+    hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, bsum);
+    int *tot = total_dev ? total_dev : out + n;
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(SCAN_THREADS), 0, s, bsum, nb, tot);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, bsum, out);
+    if (total_dev && total_dev != out + n)
+        CPTR_HIP(hipMemcpyAsync(out + n, total_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
+    CPTR_CHECK_LAUNCH();
+}
+
+template <class T>
+__global__ void k_fill(T *p, T v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t st = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st) p[i] = v;
+}
+
+static int grid_for(size_t n, int threads, int cap = 65536) {
+    size_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > (size_t)cap) g = cap;
+    return (int)g;
+}
+
+void fill_int(int *p, int v, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<int>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    CPTR_CHECK_LAUNCH();
+}
+
+void fill_double(double *p, double v, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    CPTR_CHECK_LAUNCH();
+}
+
+// flag bits: 1 column out of range, 2 columns not ascending, 4 diagonal missing
+__global__ void k_check_pattern(int n, const int *rp, const int *ci, int *flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int f = 0, diag = 0, prev = -1;
+    int a = rp[i], b = rp[i + 1];
+    if (b < a) f |= 2;
+    for (int e = a; e < b; ++e) {
+        int j = ci[e];
+        if (j < 0 || j >= n) f |= 1;
+        if (j <= prev) f |= 2;
+        if (j == i) diag = 1;
+        prev = j;
+    }
+    if (!diag) f |= 4;
+    if (f) atomicOr(flag, f);
+}
+
+void check_pattern(int n, const int *rp, const int *ci, int *flag_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_pattern, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, ci, flag_dev);
+    CPTR_CHECK_LAUNCH();
+}
+
+// tpos[e] = position of entry (j, i) for e = (i, j); flag bit 8 when missing
+__global__ void k_transpose_index(int n, const int *rp, const int *ci, int *tpos, int *flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int j = ci[e];
+        int lo = rp[j], hi = rp[j + 1] - 1, pos = -1;
+        while (lo <= hi) {
+            int mid = (lo + hi) >> 1;
+            int c = ci[mid];
+            if (c == i) { pos = mid; break; }
+            if (c < i) lo = mid + 1; else hi = mid - 1;
+        }
+        tpos[e] = pos;
+        if (pos < 0) atomicOr(flag, 8);
+    }
+}
+
+void transpose_index(int n, const int *rp, const int *ci, int *tpos, int *flag_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose_index, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, ci, tpos, flag_dev);
+    CPTR_CHECK_LAUNCH();
+}
+
+__global__ void k_nonfinite(const double *x, size_t n, int *flag) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t st = (size_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (; i < n; i += st)
+        if (!isfinite(x[i])) bad = 1;
+    if (bad) atomicOr(flag, 16);
+}
+
+void count_nonfinite(const double *x, size_t n, int *flag_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, x, n, flag_dev);
+    CPTR_CHECK_LAUNCH();
+}
+
+__global__ void k_to_float(const double *x, float *y, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t st = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st) y[i] = (float)x[i];
+}
+
+void to_float(const double *x, float *y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_float, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+    CPTR_CHECK_LAUNCH();
+}
+
+}  // namespace cptr

@@ -1,0 +1,235 @@
+// Left decoupling N^{-1} (Eq. splitPrec1) of the CPTR3 scheme (Eqs. CPTR31,
+// CPTR32) and of CPR (Eq. CPR), and extraction of the scalar subsystems
+// B_PP, C_TT and of the P / T column slabs used by Algorithm 2's residual
+// updates.  Built with floating-point contraction off: the scaled matrix, and
+// through it the AMG hierarchies, are reproducible bit for bit from the
+// definition's evaluation order (stated at each formula).
+#include "internal.h"
+
+namespace cptr {
+
+// One wavefront per cell.  Every lane redundantly solves the small system
+// D_gg^T [w_P w_T] = [D_Pg^T D_Tg^T] (g = the eliminated group: s for CPTR3,
+// s u {T} for CPR) by Gaussian elimination with partial pivoting -- first
+// largest |pivot|, kij order, back substitution in descending rows -- then
+// handles block entry (r, c) = (lane / b, lane % b) of every block of the row:
+//   Ahat[P][c] = A[P][c] - sum_{k ascending} w_P[k] A[g_k][c]
+//   Ahat[T][c] = A[T][c] - sum_{k ascending} w_T[k] A[g_k][c]
+//   CPTR3: beta = Ahat_ii[T][P] / Ahat_ii[P][P];  Abar[T][c] = Ahat[T][c] - beta Ahat[P][c]
+template <int B>
+__global__ void __launch_bounds__(64) k_decouple(int variant, int n, const int *__restrict__ rp,
+                                                 const int *__restrict__ ci, const double *__restrict__ A, int ip,
+                                                 int it, double *__restrict__ abar, double *__restrict__ wp,
+                                                 double *__restrict__ wt, double *__restrict__ beta, int *err) {
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (i >= n) return;
+    int grp[B];
+    int ng = 0;
+    for (int r = 0; r < B; ++r) {
+        if (r == ip) continue;
+        if (r == it && variant != CPTR_VARIANT_CPR) continue;
+        grp[ng++] = r;
+    }
+    int d = -1;
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (ci[e] == i) d = e;
+    if (d < 0) {
+        if (lane == 0) atomicMin(err, i);
+        return;
+    }
+    const double *D = A + (size_t)d * B * B;
+    const int nrhs = (variant == CPTR_VARIANT_CPR) ? 1 : 2;
+    double M[B * B];
+    double F[B * 2];
+    for (int r = 0; r < ng; ++r) {
+        for (int c = 0; c < ng; ++c) M[r * ng + c] = D[grp[c] * B + grp[r]];
+        F[r * nrhs + 0] = D[ip * B + grp[r]];
+        if (nrhs == 2) F[r * nrhs + 1] = D[it * B + grp[r]];
+    }
+    bool singular = false;
+    for (int k = 0; k < ng; ++k) {
+        int p = k;
+        double best = fabs(M[k * ng + k]);
+        for (int r = k + 1; r < ng; ++r) {
+            double a = fabs(M[r * ng + k]);
+            if (a > best) { best = a; p = r; }
+        }
+        if (best == 0.0) { singular = true; break; }
+        if (p != k) {
+            for (int c = 0; c < ng; ++c) { double t = M[k * ng + c]; M[k * ng + c] = M[p * ng + c]; M[p * ng + c] = t; }
+            for (int j = 0; j < nrhs; ++j) { double t = F[k * nrhs + j]; F[k * nrhs + j] = F[p * nrhs + j]; F[p * nrhs + j] = t; }
+        }
+        for (int r = k + 1; r < ng; ++r) {
+            double l = M[r * ng + k] / M[k * ng + k];
+            for (int c = k + 1; c < ng; ++c) M[r * ng + c] = M[r * ng + c] - l * M[k * ng + c];
+            for (int j = 0; j < nrhs; ++j) F[r * nrhs + j] = F[r * nrhs + j] - l * F[k * nrhs + j];
+        }
+    }
+    if (!singular) {
+        for (int k = ng - 1; k >= 0; --k)
+            for (int j = 0; j < nrhs; ++j) {
+                double t = F[k * nrhs + j];
+                for (int c = k + 1; c < ng; ++c) t = t - M[k * ng + c] * F[c * nrhs + j];
+                F[k * nrhs + j] = t / M[k * ng + k];
+            }
+    }
+    double bt = 0.0;
+    if (!singular && variant == CPTR_VARIANT_CPTR3) {
+        double hp = D[ip * B + ip], ht = D[it * B + ip];
+        for (int k = 0; k < ng; ++k) hp = hp - F[k * nrhs + 0] * D[grp[k] * B + ip];
+        for (int k = 0; k < ng; ++k) ht = ht - F[k * nrhs + 1] * D[grp[k] * B + ip];
+        if (hp == 0.0) singular = true;
+        else bt = ht / hp;
+    }
+    if (singular) {
+        if (lane == 0) atomicMin(err, i);
+        return;
+    }
+    if (lane < B) {
+        double vp = 0.0, vt = 0.0;
+        for (int k = 0; k < ng; ++k)
+            if (grp[k] == lane) { vp = F[k * nrhs + 0]; if (nrhs == 2) vt = F[k * nrhs + 1]; }
+        wp[(size_t)i * B + lane] = vp;
+        wt[(size_t)i * B + lane] = vt;
+    }
+    if (lane == 0) beta[i] = bt;
+    if (lane >= B * B) return;
+    const int r = lane / B, c = lane % B;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const double *Bk = A + (size_t)e * B * B;
+        double out = Bk[r * B + c];
+        if (r == ip || (r == it && variant != CPTR_VARIANT_CPR)) {
+            double hp = Bk[ip * B + c];
+            for (int k = 0; k < ng; ++k) hp = hp - F[k * nrhs + 0] * Bk[grp[k] * B + c];
+            if (r == ip) {
+                out = hp;
+            } else {
+                double ht = Bk[it * B + c];
+                for (int k = 0; k < ng; ++k) ht = ht - F[k * nrhs + 1] * Bk[grp[k] * B + c];
+                out = (variant == CPTR_VARIANT_CPTR3) ? ht - bt * hp : ht;
+            }
+        }
+        abar[(size_t)e * B * B + lane] = out;
+    }
+}
+
+void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
+                     double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s) {
+    if (n == 0) return;
+#define CASE(BB) case BB: hipLaunchKernelGGL(k_decouple<BB>, dim3(n), dim3(64), 0, s, variant, n, rp, ci, A, ip, it, abar, wp, wt, beta, err); break;
+    switch (b) {
+        CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        default: throw Error(CPTR_E_ARG, "block size must be 2..8");
+    }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+// bbar = N^{-1} b for one right-hand side, same order as the rows:
+//   hp = b[P] - sum_{g ascending} w_P[g] b[g];  ht likewise;  T: ht - beta hp
+// The stored w vectors are zero outside the group, and the sum skips the
+// P and T positions (and T for CPR's P row) exactly like the group loop.
+template <int B>
+__global__ void k_scale_rhs(int variant, int n, const double *__restrict__ rhs, int ip, int it,
+                            const double *__restrict__ wp, const double *__restrict__ wt,
+                            const double *__restrict__ beta, double *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *bi = rhs + (size_t)i * B;
+    double v[B];
+    for (int r = 0; r < B; ++r) v[r] = bi[r];
+    double hp = v[ip];
+    for (int g = 0; g < B; ++g) {
+        if (g == ip || (g == it && variant != CPTR_VARIANT_CPR)) continue;
+        hp = hp - wp[(size_t)i * B + g] * v[g];
+    }
+    double o[B];
+    for (int r = 0; r < B; ++r) o[r] = v[r];
+    o[ip] = hp;
+    if (variant != CPTR_VARIANT_CPR) {
+        double ht = v[it];
+        for (int g = 0; g < B; ++g) {
+            if (g == ip || g == it) continue;
+            ht = ht - wt[(size_t)i * B + g] * v[g];
+        }
+        o[it] = (variant == CPTR_VARIANT_CPTR3) ? ht - beta[i] * hp : ht;
+    }
+    for (int r = 0; r < B; ++r) out[(size_t)i * B + r] = o[r];
+}
+
+// v = N r: undo the scaling (second scaling first, then the first)
+template <int B>
+__global__ void k_unscale(int variant, int n, const double *__restrict__ rv, int ip, int it,
+                          const double *__restrict__ wp, const double *__restrict__ wt,
+                          const double *__restrict__ beta, double *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v[B];
+    for (int r = 0; r < B; ++r) v[r] = rv[(size_t)i * B + r];
+    if (variant == CPTR_VARIANT_CPTR3) v[it] = v[it] + beta[i] * v[ip];
+    double sp = 0.0, st = 0.0;
+    for (int g = 0; g < B; ++g) {
+        if (g == ip || (g == it && variant != CPTR_VARIANT_CPR)) continue;
+        sp += wp[(size_t)i * B + g] * v[g];
+        if (variant != CPTR_VARIANT_CPR && g != it) st += wt[(size_t)i * B + g] * v[g];
+    }
+    double o[B];
+    for (int r = 0; r < B; ++r) o[r] = v[r];
+    o[ip] = v[ip] + sp;
+    if (variant != CPTR_VARIANT_CPR) o[it] = v[it] + st;
+    for (int r = 0; r < B; ++r) out[(size_t)i * B + r] = o[r];
+}
+
+void launch_scale_rhs(int variant, int n, int b, const double *rhs, int ip, int it, const double *wp,
+                      const double *wt, const double *beta, double *out, hipStream_t s) {
+    if (n == 0) return;
+    dim3 g((n + 127) / 128), t(128);
+#define CASE(BB) case BB: hipLaunchKernelGGL(k_scale_rhs<BB>, g, t, 0, s, variant, n, rhs, ip, it, wp, wt, beta, out); break;
+    switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+void launch_unscale(int variant, int n, int b, const double *v, int ip, int it, const double *wp,
+                    const double *wt, const double *beta, double *out, hipStream_t s) {
+    if (n == 0) return;
+    dim3 g((n + 127) / 128), t(128);
+#define CASE(BB) case BB: hipLaunchKernelGGL(k_unscale<BB>, g, t, 0, s, variant, n, v, ip, it, wp, wt, beta, out); break;
+    switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+// Scalar subsystems on the BSR pattern: C_TT = Abar[T,T] (Eq. CPTR32),
+// B_PP = Abar[P,P] (Eq. CPTR31); column slabs slab_T[e*b + r] = Abar_e[r][T],
+// slab_P[e*b + r] = Abar_e[r][P]; optional FP32 copies.
+__global__ void k_extract(int nnzb, int b, const double *__restrict__ abar, int ip, int it, double *ctt,
+                          double *bpp, double *slabT, double *slabP, float *abar32, float *slabT32,
+                          float *slabP32) {
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)nnzb) return;
+    const double *Bk = abar + e * b * b;
+    if (ctt) ctt[e] = Bk[it * b + it];
+    if (bpp) bpp[e] = Bk[ip * b + ip];
+    for (int r = 0; r < b; ++r) {
+        double vt = Bk[r * b + it], vp = Bk[r * b + ip];
+        if (slabT) slabT[e * b + r] = vt;
+        if (slabP) slabP[e * b + r] = vp;
+        if (slabT32) slabT32[e * b + r] = (float)vt;
+        if (slabP32) slabP32[e * b + r] = (float)vp;
+    }
+    if (abar32)
+        for (int k = 0; k < b * b; ++k) abar32[e * b * b + k] = (float)Bk[k];
+}
+
+void launch_extract(int n, int b, int nnzb, const double *abar, int ip, int it, double *ctt, double *bpp,
+                    double *slabT, double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s) {
+    (void)n;
+    if (nnzb == 0) return;
+    hipLaunchKernelGGL(k_extract, dim3((nnzb + 255) / 256), dim3(256), 0, s, nnzb, b, abar, ip, it, ctt, bpp, slabT,
+                       slabP, abar32, slabT32, slabP32);
+    CPTR_CHECK_LAUNCH();
+}
+
+}  // namespace cptr

@@ -1,0 +1,339 @@
+// Outer operator apply (BSR SpMV) and the Arnoldi / Givens kernels of
+// right-preconditioned restarted GMRES and flexible GMRES (the Krylov solver
+// the paper applies to the left-scaled system, Eq. splitPrec2).
+#include "internal.h"
+
+namespace cptr {
+
+// ---------------------------------------------------------------------------
+// BSR SpMV
+// ---------------------------------------------------------------------------
+
+// b = 8: one wavefront per block row; lane l owns block entry (l/8, l%8), so
+// the row's value stream (contiguous, 512 B per block) is read fully
+// coalesced; the 8 partial products of a row are summed with xor shuffles.
+template <bool RESID>
+__global__ void __launch_bounds__(256) k_bsr8(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                              const double *__restrict__ A, const double *__restrict__ x,
+                                              const double *__restrict__ rhs, double *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const int c = lane & 7;
+    const int a = rp[row], e1 = rp[row + 1];
+    double acc = 0.0;
+    for (int e = a; e < e1; ++e) {
+        const int j = ci[e];
+        acc += A[(size_t)e * 64 + lane] * x[(size_t)j * 8 + c];
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    if (c == 0) {
+        const size_t o = (size_t)row * 8 + (lane >> 3);
+        y[o] = RESID ? rhs[o] - acc : acc;
+    }
+}
+
+// generic b: one thread per scalar row (i, r)
+template <bool RESID>
+__global__ void k_bsr_gen(int n, int b, const int *__restrict__ rp, const int *__restrict__ ci,
+                          const double *__restrict__ A, const double *__restrict__ x,
+                          const double *__restrict__ rhs, double *__restrict__ y) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n * b) return;
+    const int i = (int)(t / b), r = (int)(t % b);
+    double acc = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const double *Bk = A + (size_t)e * b * b + r * b;
+        const double *xc = x + (size_t)ci[e] * b;
+        for (int c = 0; c < b; ++c) acc += Bk[c] * xc[c];
+    }
+    y[t] = RESID ? rhs[t] - acc : acc;
+}
+
+void launch_bsr_spmv(int n, int b, const int *rp, const int *ci, const double *A, const double *x, double *y,
+                     hipStream_t s) {
+    if (n == 0) return;
+    if (b == 8)
+        hipLaunchKernelGGL(k_bsr8<false>, dim3((n + 3) / 4), dim3(256), 0, s, n, rp, ci, A, x, nullptr, y);
+    else
+        hipLaunchKernelGGL(k_bsr_gen<false>, dim3(((long)n * b + 255) / 256), dim3(256), 0, s, n, b, rp, ci, A, x,
+                           nullptr, y);
+    CPTR_CHECK_LAUNCH();
+}
+
+void launch_bsr_residual(int n, int b, const int *rp, const int *ci, const double *A, const double *x,
+                         const double *rhs, double *r, hipStream_t s) {
+    if (n == 0) return;
+    if (b == 8)
+        hipLaunchKernelGGL(k_bsr8<true>, dim3((n + 3) / 4), dim3(256), 0, s, n, rp, ci, A, x, rhs, r);
+    else
+        hipLaunchKernelGGL(k_bsr_gen<true>, dim3(((long)n * b + 255) / 256), dim3(256), 0, s, n, b, rp, ci, A, x,
+                           rhs, r);
+    CPTR_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// reductions: per-block partials in a fixed order, then one block sums them
+// in a fixed order -> deterministic results (no floating-point atomics)
+// ---------------------------------------------------------------------------
+constexpr int KR_THREADS = 256;
+constexpr int KR_GROUP = 8;   // vectors handled per pass of the multi-dot
+
+int kr_nblk(int N) {
+    long b = ((long)N + KR_THREADS * 8 - 1) / (KR_THREADS * 8);
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+__device__ inline double block_sum(double v, double *lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w];
+    return s;   // valid in thread 0
+}
+
+// partial[blk*(k+1) + j] = sum over the block's rows of V_j . w (j < k), and
+// partial[blk*(k+1) + k] = w . w
+__global__ void __launch_bounds__(KR_THREADS) k_mdot(int N, int k, const double *__restrict__ V, size_t ldv,
+                                                     const double *__restrict__ w, double *__restrict__ partial) {
+    __shared__ double lds[KR_THREADS / 64];
+    const long chunk = ((long)N + gridDim.x - 1) / gridDim.x;
+    const long r0 = (long)blockIdx.x * chunk;
+    const long r1 = min((long)N, r0 + chunk);
+    for (int j0 = 0; j0 <= k; j0 += KR_GROUP) {
+        double acc[KR_GROUP];
+#pragma unroll
+        for (int q = 0; q < KR_GROUP; ++q) acc[q] = 0.0;
+        for (long r = r0 + threadIdx.x; r < r1; r += KR_THREADS) {
+            const double wr = w[r];
+#pragma unroll
+            for (int q = 0; q < KR_GROUP; ++q) {
+                const int j = j0 + q;
+                if (j < k) acc[q] += V[(size_t)j * ldv + r] * wr;
+                else if (j == k) acc[q] += wr * wr;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KR_GROUP; ++q) {
+            const int j = j0 + q;
+            if (j > k) break;
+            double s = block_sum(acc[q], lds);
+            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (k + 1) + j] = s;
+        }
+    }
+}
+
+void kr_mdot(int N, int k, const double *V, size_t ldv, const double *w, double *partial, int nblk,
+             hipStream_t st) {
+    hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(KR_THREADS), 0, st, N, k, V, ldv, w, partial);
+    CPTR_CHECK_LAUNCH();
+}
+
+// out[j] = sum_{blk ascending} partial[blk*k + j]
+__global__ void k_reduce(const double *__restrict__ partial, int nblk, int k, double *__restrict__ out) {
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * k + j];
+        out[j] = s;
+    }
+}
+
+void kr_reduce(const double *partial, int nblk, int k, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, nblk, k, out);
+    CPTR_CHECK_LAUNCH();
+}
+
+// w -= sum_j h_j V_j (classical Gram-Schmidt projection), partial[blk] = |w|^2
+__global__ void __launch_bounds__(KR_THREADS) k_update(int N, int k, const double *__restrict__ V, size_t ldv,
+                                                       const double *__restrict__ h, double *__restrict__ w,
+                                                       double *__restrict__ partial) {
+    __shared__ double hs[256];
+    __shared__ double lds[KR_THREADS / 64];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = h[j];
+    __syncthreads();
+    const long chunk = ((long)N + gridDim.x - 1) / gridDim.x;
+    const long r0 = (long)blockIdx.x * chunk;
+    const long r1 = min((long)N, r0 + chunk);
+    double nrm = 0.0;
+    for (long r = r0 + threadIdx.x; r < r1; r += KR_THREADS) {
+        double acc = w[r];
+        for (int j = 0; j < k; ++j) acc -= hs[j] * V[(size_t)j * ldv + r];
+        w[r] = acc;
+        nrm += acc * acc;
+    }
+    double s = block_sum(nrm, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+void kr_update(int N, int k, const double *V, size_t ldv, const double *h, double *w, double *partial, int nblk,
+               hipStream_t st) {
+    if (k > 256) throw Error(CPTR_E_ARG, "restart too long");
+    hipLaunchKernelGGL(k_update, dim3(nblk), dim3(KR_THREADS), 0, st, N, k, V, ldv, h, w, partial);
+    CPTR_CHECK_LAUNCH();
+}
+
+__global__ void __launch_bounds__(KR_THREADS) k_norm2(int N, const double *__restrict__ x,
+                                                      double *__restrict__ partial) {
+    __shared__ double lds[KR_THREADS / 64];
+    const long chunk = ((long)N + gridDim.x - 1) / gridDim.x;
+    const long r0 = (long)blockIdx.x * chunk;
+    const long r1 = min((long)N, r0 + chunk);
+    double nrm = 0.0;
+    for (long r = r0 + threadIdx.x; r < r1; r += KR_THREADS) nrm += x[r] * x[r];
+    double s = block_sum(nrm, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+void kr_norm2_partial(int N, const double *x, double *partial, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(KR_THREADS), 0, st, N, x, partial);
+    CPTR_CHECK_LAUNCH();
+}
+
+// Arnoldi step j finishes on one block: sum the |w|^2 partials (fixed order),
+// store column j of H (h_{i,j} from hcol, plus a second-pass correction when
+// re-orthogonalised), h_{j+1,j} = |w|; apply the previous Givens rotations,
+// form the new one, update g.  scal[0] = 1 / h_{j+1,j} for the normalisation.
+// hostinfo (host-visible): [ |g_{j+1}|, h_{j+1,j}, |A z_j| ].
+// H is column-major with leading dimension m+1.
+__global__ void k_arnoldi_finish(int j, int m, double *H, double *cs, double *sn, double *g,
+                                 const double *hcol, const double *hcol2, const double *nrm_partial, int nblk,
+                                 double *scal, double *hostinfo) {
+    double p = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) p += nrm_partial[b];
+    // fixed-shape tree over the block
+    __shared__ double red[256];
+    red[threadIdx.x] = p;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const int ld = m + 1;
+    double *Hc = H + (size_t)j * ld;
+    for (int i = 0; i <= j; ++i) Hc[i] = hcol[i] + (hcol2 ? hcol2[i] : 0.0);
+    const double wn = sqrt(red[0]);
+    const double wnorm0 = sqrt(hcol[j + 1]);   // |A z_j| from the first multi-dot
+    Hc[j + 1] = wn;
+    for (int i = 0; i < j; ++i) {
+        double t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];
+        Hc[i + 1] = -sn[i] * Hc[i] + cs[i] * Hc[i + 1];
+        Hc[i] = t;
+    }
+    const double den = hypot(Hc[j], Hc[j + 1]);
+    cs[j] = Hc[j] / den;
+    sn[j] = Hc[j + 1] / den;
+    const double hj1 = Hc[j + 1];
+    Hc[j] = den;
+    Hc[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    scal[0] = (hj1 != 0.0) ? 1.0 / hj1 : 0.0;
+    hostinfo[0] = fabs(g[j + 1]);
+    hostinfo[1] = hj1;
+    hostinfo[2] = wnorm0;
+}
+
+void kr_arnoldi_finish2(int j, int m, double *H, double *cs, double *sn, double *g, const double *hcol,
+                        const double *hcol2, const double *nrm_partial, int nblk, double *scal, double *hostinfo,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(256), 0, st, j, m, H, cs, sn, g, hcol, hcol2, nrm_partial,
+                       nblk, scal, hostinfo);
+    CPTR_CHECK_LAUNCH();
+}
+
+__global__ void k_scale(int N, const double *__restrict__ w, const double *__restrict__ scal,
+                        double *__restrict__ v) {
+    const double s = scal[0];
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long st = (long)gridDim.x * blockDim.x;
+    for (; i < N; i += st) v[i] = w[i] * s;
+}
+
+void kr_scale(int N, const double *w, const double *scal, double *v, hipStream_t st) {
+    long g = ((long)N + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_scale, dim3((int)g), dim3(256), 0, st, N, w, scal, v);
+    CPTR_CHECK_LAUNCH();
+}
+
+// start of a restart cycle from the residual r: beta = |r| (partials summed in
+// a fixed order), v0 = r / beta, g = beta e_1.  hostinfo[0] = beta.
+__global__ void k_cycle_prep(const double *nrm_partial, int nblk, int m, double *g, double *scal,
+                             double *hostinfo) {
+    __shared__ double red[256];
+    double p = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) p += nrm_partial[b];
+    red[threadIdx.x] = p;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double beta = sqrt(red[0]);
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        scal[0] = (beta != 0.0) ? 1.0 / beta : 0.0;
+        hostinfo[0] = beta;
+    }
+}
+
+void kr_cycle_prep(const double *nrm_partial, int nblk, int m, double *g, double *scal, double *hostinfo,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_cycle_prep, dim3(1), dim3(256), 0, st, nrm_partial, nblk, m, g, scal, hostinfo);
+    CPTR_CHECK_LAUNCH();
+}
+
+// y = R^{-1} g for the k x k upper triangle of the rotated H (back substitution)
+__global__ void k_solve_upper(int k, int m, const double *H, const double *g, double *y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int ld = m + 1;
+    for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int c = i + 1; c < k; ++c) t -= H[(size_t)c * ld + i] * y[c];
+        y[i] = t / H[(size_t)i * ld + i];
+    }
+}
+
+void kr_solve_upper(int k, int m, const double *H, const double *g, double *y, hipStream_t st) {
+    hipLaunchKernelGGL(k_solve_upper, dim3(1), dim3(64), 0, st, k, m, H, g, y);
+    CPTR_CHECK_LAUNCH();
+}
+
+// x += sum_j y_j Z_j
+template <class TZ>
+__global__ void k_combine(int N, int k, const TZ *__restrict__ Z, size_t ldz, const double *__restrict__ y,
+                          double *__restrict__ x) {
+    __shared__ double ys[256];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) ys[j] = y[j];
+    __syncthreads();
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long st = (long)gridDim.x * blockDim.x;
+    for (; i < N; i += st) {
+        double acc = x[i];
+        for (int j = 0; j < k; ++j) acc += ys[j] * (double)Z[(size_t)j * ldz + i];
+        x[i] = acc;
+    }
+}
+
+template <class TZ>
+void kr_combine(int N, int k, const TZ *Z, size_t ldz, const double *y, double *x, hipStream_t st) {
+    if (k > 256) throw Error(CPTR_E_ARG, "restart too long");
+    long g = ((long)N + 255) / 256;
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(k_combine<TZ>, dim3((int)g), dim3(256), 0, st, N, k, Z, ldz, y, x);
+    CPTR_CHECK_LAUNCH();
+}
+template void kr_combine<double>(int, int, const double *, size_t, const double *, double *, hipStream_t);
+template void kr_combine<float>(int, int, const float *, size_t, const double *, double *, hipStream_t);
+
+}  // namespace cptr

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle on
+the same seeded inputs.
+
+Bars: setup arithmetic (decoupling, AMG hierarchy: C/F split, P, coarse
+operators) bit for bit; solve-phase kernels to 1e-12 relative; end-to-end
+plain FP64 solves to 1e-10 relative in the solution with iteration counts
+within +-1 (the agreement asked of the plain GPU path)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import config1, config2, tiny
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():   # collected on CPU-only machines but never run there
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1912_04385_amd import cptr  # noqa: E402
+
+
+def _t(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.cuda() if dtype is None else t.to(dtype).cuda()
+
+
+def _oracle_opts(s, tile=(32, 32), **kw):
+    amg = O.AMGOptions(**{k[4:]: v for k, v in kw.items() if k.startswith("amg_")})
+    rest = {k: v for k, v in kw.items() if not k.startswith("amg_")}
+    color = O.tile_colors(s.nx, s.ny, *tile)
+    return O.Options(color=color, amg=amg, **rest)
+
+
+def _gpu_opts(**kw):
+    m = {"amg_max_coarse": "amg_max_coarse", "amg_pmax": "amg_pmax", "amg_theta": "amg_theta"}
+    out = {}
+    for k, v in kw.items():
+        out[m.get(k, k)] = v
+    return out
+
+
+# --------------------------------------------------------------------------
+# setup arithmetic, bit for bit
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("b,variant", [(2, 0), (3, 0), (6, 0), (8, 0), (6, 1), (8, 1)])
+def test_decouple_bitwise(b, variant):
+    print(f"case decouple b={b} variant={variant}", flush=True)
+    s = tiny(9, 7, b, peclet=3.0, seed=b + 10 * variant)
+    A = O.bsr_of(s)
+    ref = O.decouple(A, s.rhs, variant=variant)
+    abar, rb = cptr.decouple(variant, s.row_ptr, s.col_idx, s.vals.reshape(-1), s.rhs)
+    assert np.array_equal(abar.cpu().numpy(), ref.Abar.vals.reshape(-1))
+    assert np.array_equal(rb.cpu().numpy(), ref.rhsbar)
+
+
+@pytest.mark.parametrize("b,nx,ny", [(3, 20, 20), (6, 33, 17), (8, 41, 23), (5, 7, 1)])
+def test_bsr_spmv(b, nx, ny):
+    print(f"case spmv b={b} {nx}x{ny}", flush=True)
+    s = tiny(nx, ny, b, seed=2)
+    x = np.random.default_rng(1).standard_normal(s.n * b)
+    y = cptr.bsr_spmv(s.row_ptr, s.col_idx, s.vals.reshape(-1), x, b).cpu().numpy()
+    ref = O.bsr_of(s).matvec(x)
+    assert np.allclose(y, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def _compare_hierarchy(solver, h, which):
+    nl = solver.amg_levels(which)
+    assert nl == len(h.levels), (nl, h.sizes)
+    for lvl in range(nl):
+        g = solver.amg_level(which, lvl)
+        L = h.levels[lvl]
+        assert g["n"] == L.A.nrows
+        assert np.array_equal(g["rp"], L.A.rp)
+        assert np.array_equal(g["ci"], L.A.ci)
+        assert np.array_equal(g["v"], L.A.v), f"level {lvl} operator values differ"
+        if lvl + 1 < nl:
+            assert np.array_equal(g["cf"], L.cf), f"level {lvl} C/F split differs"
+            assert np.array_equal(g["prp"], L.P.rp)
+            assert np.array_equal(g["pci"], L.P.ci)
+            assert np.array_equal(g["pv"], L.P.v), f"level {lvl} interpolation weights differ"
+
+
+@pytest.mark.parametrize("name,max_coarse,pmax", [("c1", 40, 4), ("tiny48x40b6", 30, 4), ("tiny48x40b6", 30, 0),
+                                                  ("tiny64x20b8", 50, 2)])
+def test_amg_hierarchy_bitwise(name, max_coarse, pmax):
+    print(f"case hierarchy {name} max_coarse={max_coarse} pmax={pmax}", flush=True)
+    if name == "c1":
+        s = config1()
+    elif name == "tiny48x40b6":
+        s = tiny(48, 40, 6, peclet=0.5, seed=3)
+    else:
+        s = tiny(64, 20, 8, peclet=20.0, seed=4)
+    ref = O.solve(s, _oracle_opts(s, amg_max_coarse=max_coarse, amg_pmax=pmax, max_iters=1))
+    solver = cptr.solver_for(s, amg_max_coarse=max_coarse, amg_pmax=pmax)
+    _compare_hierarchy(solver, ref.hierarchies["T"], 0)
+    _compare_hierarchy(solver, ref.hierarchies["P"], 1)
+    solver.close()
+
+
+# --------------------------------------------------------------------------
+# solve-phase kernels
+# --------------------------------------------------------------------------
+def test_vcycle_parity():
+    print("case vcycle", flush=True)
+    s = tiny(48, 40, 6, peclet=0.5, seed=3)
+    ref = O.solve(s, _oracle_opts(s, amg_max_coarse=30, max_iters=1))
+    solver = cptr.solver_for(s, amg_max_coarse=30)
+    rng = np.random.default_rng(5)
+    for which, key in ((0, "T"), (1, "P")):
+        bvec = rng.standard_normal(s.n)
+        x = solver.vcycle(which, _t(bvec)).cpu().numpy()
+        xr = O.vcycle(ref.hierarchies[key], bvec)
+        assert np.allclose(x, xr, rtol=1e-12, atol=1e-12 * np.abs(xr).max())
+    solver.close()
+
+
+@pytest.mark.parametrize("variant,order,last,tile", [(0, 0, 0, (32, 32)), (0, 1, 0, (8, 4)), (1, 0, 0, (16, 16)),
+                                                     (0, 0, 1, (32, 32)), (3, 0, 0, (5, 3))])
+def test_precond_apply_parity(variant, order, last, tile):
+    print(f"case precond variant={variant} order={order} last={last} tile={tile}", flush=True)
+    s = tiny(37, 21, 6, peclet=2.0, seed=6)
+    ov = {0: O.CPTR3, 1: O.CPR, 3: O.BJ_ONLY}[variant]
+    opts = _oracle_opts(s, tile=tile, amg_max_coarse=25, variant=ov, stage_order=order,
+                        last_stage=O.LAST_BJACOBI if last else O.LAST_BILU0, max_iters=1)
+    ref = O.solve(s, opts)
+    apply, _, _ = O.build_preconditioner(ref.dec, opts)
+    solver = cptr.solver_for(s, amg_max_coarse=25, variant=variant, stage_order=order, last_stage=last,
+                             ilu_tile_x=tile[0], ilu_tile_y=tile[1])
+    r = np.random.default_rng(7).standard_normal(s.n * 6)
+    y = solver.precond_apply(_t(r)).cpu().numpy()
+    yr = apply(r)
+    assert np.allclose(y, yr, rtol=1e-11, atol=1e-11 * np.abs(yr).max())
+    solver.close()
+
+
+# --------------------------------------------------------------------------
+# end-to-end plain FP64 solves
+# --------------------------------------------------------------------------
+def _solve_both(s, tile=(32, 32), **kw):
+    ref = O.solve(s, _oracle_opts(s, tile=tile, **kw))
+    gkw = dict(kw)
+    if "variant" in gkw:
+        gkw["variant"] = {O.CPTR3: 0, O.CPR: 1, O.BJ_ONLY: 3}[gkw["variant"]]
+    solver = cptr.solver_for(s, ilu_tile_x=tile[0], ilu_tile_y=tile[1], **gkw)
+    x, res = solver.solve(_t(s.rhs))
+    hist = solver.residual_history()
+    solver.close()
+    return ref, x.cpu().numpy(), res, hist
+
+
+def _assert_parity(ref, x, res):
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    print(f"  gpu its={res['iterations']} oracle its={ref.iterations} rel_res={res['rel_res_scaled']:.2e} "
+          f"err={err:.2e}", flush=True)
+    assert res["converged"] == 1 and res["rel_res_scaled"] <= 1e-8
+    assert abs(res["iterations"] - ref.iterations) <= 1
+    assert err <= 1e-10
+    assert abs(res["rel_res_unscaled"] - ref.rel_res_unscaled) <= 1e-9
+
+
+@pytest.mark.parametrize("max_coarse", [1000, 40])
+def test_solve_config1(max_coarse):
+    print(f"case solve c1 max_coarse={max_coarse}", flush=True)
+    s = config1()
+    ref, x, res, hist = _solve_both(s, amg_max_coarse=max_coarse)
+    _assert_parity(ref, x, res)
+    assert np.allclose(hist, ref.history, rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("index", [0, 1, 2, 3])
+def test_solve_config2(index):
+    print(f"case solve c2-{index}", flush=True)
+    s = config2(index)
+    ref, x, res, _ = _solve_both(s)
+    _assert_parity(ref, x, res)
+
+
+@pytest.mark.parametrize("case", ["b2", "ragged_tiles", "single_level", "bjacobi", "cpr", "p_then_t", "restart5",
+                                  "l1jacobi", "sweeps2"])
+def test_solve_variants(case):
+    print(f"case solve variant {case}", flush=True)
+    kw, tile = {}, (32, 32)
+    s = tiny(45, 29, 6, peclet=1.0, seed=12)
+    if case == "b2":
+        s = tiny(40, 30, 2, peclet=1.0, seed=13)
+    elif case == "ragged_tiles":
+        tile = (7, 5)
+    elif case == "single_level":
+        kw["amg_max_coarse"] = 5000
+    elif case == "bjacobi":
+        kw["last_stage"] = O.LAST_BJACOBI
+    elif case == "cpr":
+        kw["variant"] = O.CPR
+    elif case == "p_then_t":
+        kw["stage_order"] = O.P_THEN_T
+    elif case == "restart5":
+        kw["restart"] = 5
+    elif case == "l1jacobi":
+        kw["amg_smoother"] = O.SMOOTH_L1JACOBI
+    elif case == "sweeps2":
+        kw["amg_pre"] = 2
+        kw["amg_post"] = 2
+    okw = dict(kw)
+    gkw = {k: v for k, v in kw.items() if not k.startswith("amg_")}
+    if "amg_max_coarse" in kw:
+        gkw["amg_max_coarse"] = kw["amg_max_coarse"]
+    if "amg_smoother" in kw:
+        gkw["smoother"] = kw["amg_smoother"]
+    if "amg_pre" in kw:
+        gkw["pre_sweeps"], gkw["post_sweeps"] = kw["amg_pre"], kw["amg_post"]
+    ref = O.solve(s, _oracle_opts(s, tile=tile, **okw))
+    if "variant" in gkw:
+        gkw["variant"] = {O.CPTR3: 0, O.CPR: 1}[gkw["variant"]]
+    solver = cptr.solver_for(s, ilu_tile_x=tile[0], ilu_tile_y=tile[1], **gkw)
+    x, res = solver.solve(_t(s.rhs))
+    solver.close()
+    _assert_parity(ref, x.cpu().numpy(), res)
+
+
+# --------------------------------------------------------------------------
+# error paths (forced from the host with crafted inputs)
+# --------------------------------------------------------------------------
+def test_nonfinite_rhs_is_rejected():
+    s = config1()
+    solver = cptr.solver_for(s)
+    rhs = s.rhs.copy()
+    rhs[17] = np.nan
+    with pytest.raises(cptr.CptrError) as e:
+        solver.solve(_t(rhs))
+    assert e.value.status == -4
+    solver.close()
+
+
+def test_singular_block_names_the_cell():
+    s = tiny(6, 5, 4, seed=1)
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    e = np.nonzero((rows == 13) & (s.col_idx == 13))[0][0]
+    s.vals[e, 2:, 2:] = 0.0
+    with pytest.raises(cptr.CptrError) as err:
+        cptr.solver_for(s)
+    assert err.value.status == -3 and "cell 13" in str(err.value)
+
+
+def test_max_iters_reports_not_converged():
+    s = config1()
+    solver = cptr.solver_for(s, max_iters=2)
+    x, res = solver.solve(_t(s.rhs))
+    assert res["status"] == "NOT_CONVERGED" and res["iterations"] == 2 and res["converged"] == 0
+    solver.close()
+
+
+def test_bad_pattern_is_rejected():
+    s = tiny(5, 4, 3, seed=0)
+    ci = s.col_idx.copy()
+    ci[[0, 1]] = ci[[1, 0]]          # columns out of order in row 0
+    solver = cptr.Solver()
+    with pytest.raises(cptr.CptrError) as e:
+        solver.setup(_t(s.row_ptr), _t(ci), _t(s.vals.reshape(-1)), 0, 1, s.nx, s.ny)
+    assert e.value.status == -1
+    solver.close()
+
+
+def test_zero_rhs_returns_zero():
+    s = config1()
+    solver = cptr.solver_for(s)
+    x, res = solver.solve(torch.zeros(s.n * s.b, dtype=torch.float64, device="cuda"))
+    assert res["iterations"] == 0 and float(x.abs().max()) == 0.0
+    solver.close()
