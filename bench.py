@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-stage preconditioned GMRES path on one MI355X.
+
+A step is one complete pass of the hot path over one linear system: the left
+decoupling and extraction, both AMG setups, the BILU(0) factorisation, and the
+preconditioned Krylov solve to an FP64 true relative residual of 1e-8 on the
+scaled system.  The workload is the 1000 x 500-cell, block-8 (4M unknowns)
+channelised-permeability recipe at Pe 0.1 and Pe 100 (steps alternate between
+the two systems), solved with the FP32 preconditioner inside FP64 flexible
+GMRES(50); the plain FP64 path (GMRES(50), FP64 preconditioner) is timed the
+same way for comparison.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (rank 0; one GPU only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def spmv_algorithmic_bytes(n: int, nnzb: int, b: int, s: int = 8) -> int:
+    """Compulsory traffic of one BSR SpMV: every value, column index and row
+    pointer once, x once, y once."""
+    return nnzb * b * b * s + nnzb * 4 + (n + 1) * 4 + 2 * n * b * s
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1912_04385_amd", "csrc", "k_krylov.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(nbytes_alg: int):
+    """HBM bytes per SpMV launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "spmv_bsr8_c3_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(seconds_hint: float = 20.0) -> dict:
+    """The CPU FP64 oracle (as it stands) on a bounded sample of the same
+    recipe: a 250 x 125-cell grid with the config-3 generator, plain FP64
+    CPTR3 GMRES(50); solves/s scaled to the full 1000 x 500 grid by the cell
+    ratio (the oracle's cost is linear in the cells at fixed iterations)."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:   # pragma: no cover
+        threadpool_limits = None
+    import oracle as O
+    from synthetic import config3
+
+    nx, ny = 250, 125
+    s = config3(0, nx, ny)
+    opts = O.Options(color=O.tile_colors(nx, ny), restart=50)
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    t0 = time.perf_counter()
+    reps = 0
+    its = []
+    while True:
+        r = O.solve(s, opts)
+        its.append(r.iterations)
+        reps += 1
+        if time.perf_counter() - t0 > seconds_hint or reps >= 20:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    if ctx is not None:
+        ctx.__exit__(None, None, None)
+    scale = (1000 * 500) / (nx * ny)
+    return {"value": 1.0 / (dt * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"config-3 recipe on {nx}x{ny} cells (b=8, Pe 0.1, seed 0), plain FP64 CPTR3 GMRES(50), "
+                      f"{reps} solve(s) of {dt:.2f} s each ({int(np.mean(its))} iterations), "
+                      f"scaled x{scale:.0f} by cell count"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nx", type=int, default=1000)
+    ap.add_argument("--ny", type=int, default=500)
+    ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this solver build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1912_04385_amd import cptr
+    from synthetic import config3
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    systems = []
+    for idx in (0, 1):
+        s = config3(idx, args.nx, args.ny)
+        systems.append(dict(
+            rp=torch.from_numpy(s.row_ptr).to(dev), ci=torch.from_numpy(s.col_idx).to(dev),
+            vals=torch.from_numpy(s.vals.reshape(-1)).to(dev), rhs=torch.from_numpy(s.rhs).to(dev),
+            n=s.n, nnzb=s.nnzb, b=s.b, nx=s.nx, ny=s.ny, pe=s.meta["peclet"]))
+        del s
+    torch.cuda.synchronize()
+    print(f"# generated {len(systems)} systems in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    def run(solver, k):
+        sy = systems[k % len(systems)]
+        solver.setup(sy["rp"], sy["ci"], sy["vals"], 0, 1, sy["nx"], sy["ny"])
+        x, res = solver.solve(sy["rhs"])
+        if not res["converged"] or res["rel_res_scaled"] > 1e-8:
+            raise RuntimeError(f"step {k} did not reach 1e-8: {res}")
+        return res
+
+    def timed(solver, label):
+        for k in range(args.warmup):
+            run(solver, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        results = [run(solver, k) for k in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for k, r in enumerate(results):
+            print(f"# {label} step {k}: its={r['iterations']} setup={r['setup_ms']:.1f} ms "
+                  f"solve={r['solve_ms']:.1f} ms rel_res={r['rel_res_scaled']:.2e} "
+                  f"unscaled={r['rel_res_unscaled']:.2e}", file=sys.stderr, flush=True)
+        return dt * 1000.0 / args.steps, results
+
+    fp32 = cptr.Solver(krylov=cptr.FGMRES, restart=50, precond_precision=cptr.FP32, timing=1)
+    ms32, res32 = timed(fp32, "fp32-precond")
+    fp32.close()
+    ms64, res64 = None, None
+    if not args.no_fp64:
+        fp64 = cptr.Solver(krylov=cptr.GMRES, restart=50, timing=1)
+        ms64, res64 = timed(fp64, "fp64")
+        fp64.close()
+
+    # roofline of the outer BSR SpMV, timed live with HIP events inside the solves
+    sy = systems[0]
+    nbytes = spmv_algorithmic_bytes(sy["n"], sy["nnzb"], sy["b"])
+    tot_ms = sum(r["t_spmv_ms"] for r in res32)
+    launches = sum(r["timed_steps"] for r in res32)
+    avg_s = tot_ms / launches / 1000.0
+    achieved = nbytes / avg_s / 1e9
+    traffic = load_traffic(nbytes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_bsr8 (BSR SpMV, b=8, FP64)", "bytes_per_launch": nbytes,
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches}
+
+    its32 = [r["iterations"] for r in res32]
+    out = {
+        "metric": "solves/s to an FP64 true relative residual of 1e-8 (setup + solve), FP32-preconditioned "
+                  "CPTR3 FGMRES(50) vs plain FP64",
+        "value": round(1000.0 / ms32, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 Krylov / f32 preconditioner",
+        "data": "synthetic (seeded generator, config-3 recipe)",
+        "config": {"workload": f"config3: {args.nx}x{args.ny} cells, b=8 ({args.nx * args.ny * 8} unknowns), "
+                               f"channelised ln-sigma 2, Pe 0.1 and 100 alternating",
+                   "krylov": "FGMRES(50)", "preconditioner": "CPTR3 (T-AMG, P-AMG, BILU(0) 32x32 tiles), FP32",
+                   "tol": 1e-8},
+        "iterations": its32,
+        "setup_ms": [round(r["setup_ms"], 2) for r in res32],
+        "solve_ms": [round(r["solve_ms"], 2) for r in res32],
+        "final_rel_res_fp64": [r["rel_res_scaled"] for r in res32],
+        "stage_ms_per_step": {k: round(sum(r[k] for r in res32) / max(1, launches), 4)
+                              for k in ("t_stage1_ms", "t_stage2_ms", "t_last_ms", "t_spmv_ms", "t_arnoldi_ms")},
+        "roofline": roofline,
+    }
+    if ms64 is not None:
+        out["fp64_plain"] = {"ms_per_step": round(ms64, 2), "solves_per_s": round(1000.0 / ms64, 4),
+                             "iterations": [r["iterations"] for r in res64],
+                             "setup_ms": [round(r["setup_ms"], 2) for r in res64],
+                             "solve_ms": [round(r["solve_ms"], 2) for r in res64]}
+        out["speedup_vs_fp64"] = round(ms64 / ms32, 4)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

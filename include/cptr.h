@@ -87,6 +87,8 @@ typedef struct {
     int32_t ilu_tile_x, ilu_tile_y;  /* tile shape of the BILU(0) order (32, 32)  */
     int32_t t_interp;           /* CPTR_INTERP_CLASSICAL | CPTR_INTERP_LEARNED     */
     double  reuse_rho_max;      /* hierarchy reuse threshold for update_values    */
+    int32_t timing;             /* 1: time every stage of every Arnoldi step with */
+                                /*    HIP events on the solve stream              */
 } cptr_options;
 
 typedef struct {
@@ -100,6 +102,13 @@ typedef struct {
     double  setup_ms, solve_ms;
     int32_t levels_T, levels_P;
     int32_t reused;             /* update_values kept the hierarchy               */
+    /* with options.timing = 1: summed HIP-event times over all Arnoldi steps  */
+    int32_t timed_steps;
+    double  t_stage1_ms;        /* first scalar stage (gather + V-cycle)          */
+    double  t_stage2_ms;        /* second scalar stage (residual update + V-cycle) */
+    double  t_last_ms;          /* last stage (fused residual update + BILU/BJ)   */
+    double  t_spmv_ms;          /* outer operator apply w = Abar z                */
+    double  t_arnoldi_ms;       /* Gram-Schmidt, Givens, normalisation            */
 } cptr_result;
 
 /* Fill *opt with the defaults noted above (CPTR3, T then P, BILU(0) in 32x32

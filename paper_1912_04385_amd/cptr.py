@@ -40,7 +40,7 @@ class Options(ctypes.Structure):
         ("amg_pmax", ctypes.c_int32), ("smoother", ctypes.c_int32), ("pre_sweeps", ctypes.c_int32),
         ("post_sweeps", ctypes.c_int32), ("jacobi_omega", ctypes.c_double), ("pmis_seed", ctypes.c_uint64),
         ("ilu_tile_x", ctypes.c_int32), ("ilu_tile_y", ctypes.c_int32), ("t_interp", ctypes.c_int32),
-        ("reuse_rho_max", ctypes.c_double),
+        ("reuse_rho_max", ctypes.c_double), ("timing", ctypes.c_int32),
     ]
 
 
@@ -50,7 +50,9 @@ class Result(ctypes.Structure):
         ("used_learned", ctypes.c_int32), ("rel_res_scaled", ctypes.c_double),
         ("rel_res_unscaled", ctypes.c_double), ("rho_T", ctypes.c_double), ("rho_P", ctypes.c_double),
         ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("levels_T", ctypes.c_int32),
-        ("levels_P", ctypes.c_int32), ("reused", ctypes.c_int32),
+        ("levels_P", ctypes.c_int32), ("reused", ctypes.c_int32), ("timed_steps", ctypes.c_int32),
+        ("t_stage1_ms", ctypes.c_double), ("t_stage2_ms", ctypes.c_double), ("t_last_ms", ctypes.c_double),
+        ("t_spmv_ms", ctypes.c_double), ("t_arnoldi_ms", ctypes.c_double),
     ]
 
     def to_dict(self) -> dict:

@@ -58,8 +58,18 @@ struct cptr_ctx {
     DBuf<unsigned char> s_c1;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_setup_ms = 0.0;
+    // per-step stage timing (options.timing)
+    hipEvent_t tev[6] = {};
+    double tacc[5] = {};
+    int tsteps = 0;
+
+    void mark(int k) {
+        if (opt.timing) CPTR_HIP(hipEventRecord(tev[k], stream));
+    }
 
     ~cptr_ctx() {
+        for (auto &e : tev)
+            if (e) (void)hipEventDestroy(e);
         if (hinfo_host) (void)hipHostFree(hinfo_host);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -356,9 +366,11 @@ static void precond_apply(cptr_ctx *c, const double *r, double *y) {
         ms_stage_input<T>(n, b, c->rp.p, c->ci.p, (const T *)nullptr, comp1, r, (const T *)nullptr,
                           Prec<T>::b(h1.L[0]), s);
         const T *x1 = vcycle<T>(c, h1, 0);
+        c->mark(1);
         // M2 on z = r - Abar x (only its comp2 entries are needed)
         ms_stage_input<T>(n, b, c->rp.p, c->ci.p, t_first ? slabT : slabP, comp2, r, x1, Prec<T>::b(h2.L[0]), s);
         const T *x2 = vcycle<T>(c, h2, 0);
+        c->mark(2);
         xT = t_first ? x1 : x2;
         vP = t_first ? x2 : x1;
     } else if (variant == CPTR_VARIANT_CPR) {
@@ -366,6 +378,11 @@ static void precond_apply(cptr_ctx *c, const double *r, double *y) {
         ms_stage_input<T>(n, b, c->rp.p, c->ci.p, (const T *)nullptr, c->ip, r, (const T *)nullptr,
                           Prec<T>::b(hp.L[0]), s);
         vP = vcycle<T>(c, hp, 0);
+        c->mark(1);
+        c->mark(2);
+    } else {
+        c->mark(1);
+        c->mark(2);
     }
     // last stage on u = r - Abar (x + v), combined output y = x + v + ilu^{-1} u
     if (c->use_tiles)
@@ -498,6 +515,8 @@ static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
     const size_t ld = (size_t)N;
     const int nblk = kr_nblk(N);
     c->history.clear();
+    for (double &t : c->tacc) t = 0.0;
+    c->tsteps = 0;
     const double bnorm = device_norm(c, c->rhsbar.p, N);
     fill_double(c->x.p, 0.0, N, s);
     if (bnorm == 0.0) {
@@ -519,8 +538,11 @@ static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
         for (int j = 0; j < m; ++j) {
             double *vj = c->V.p + (size_t)j * ld;
             double *zj = c->Z.p + (size_t)j * ld;
+            c->mark(0);
             precond(c, vj, zj);
+            c->mark(3);
             launch_bsr_spmv(c->n, c->b, c->rp.p, c->ci.p, c->abar.p, zj, c->w.p, s);
+            c->mark(4);
             kr_mdot(N, j + 1, c->V.p, ld, c->w.p, c->part.p, nblk, s);
             kr_reduce(c->part.p, nblk, j + 2, c->hcol.p, s);
             kr_update(N, j + 1, c->V.p, ld, c->hcol.p, c->w.p, c->part2.p, nblk, s);
@@ -534,8 +556,17 @@ static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
             kr_arnoldi_finish2(j, m, c->Hm.p, c->cs.p, c->sn.p, c->g.p, c->hcol.p, h2, c->part2.p, nblk, c->scal.p,
                                c->hinfo.p, s);
             kr_scale(N, c->w.p, c->scal.p, c->V.p + (size_t)(j + 1) * ld, s);
+            c->mark(5);
             CPTR_HIP(hipMemcpyAsync(c->hinfo_host, c->hinfo.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
             CPTR_HIP(hipStreamSynchronize(s));
+            if (c->opt.timing) {
+                for (int q = 0; q < 5; ++q) {
+                    float ms = 0.f;
+                    CPTR_HIP(hipEventElapsedTime(&ms, c->tev[q], c->tev[q + 1]));
+                    c->tacc[q] += ms;
+                }
+                c->tsteps++;
+            }
             ++its;
             k = j + 1;
             const double gres = c->hinfo_host[0], hj1 = c->hinfo_host[1], wn0 = c->hinfo_host[2];
@@ -565,6 +596,12 @@ static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
     res->restarts = restarts;
     res->converged = converged ? 1 : 0;
     res->rel_res_scaled = true_rel;
+    res->timed_steps = c->tsteps;
+    res->t_stage1_ms = c->tacc[0];
+    res->t_stage2_ms = c->tacc[1];
+    res->t_last_ms = c->tacc[2];
+    res->t_spmv_ms = c->tacc[3];
+    res->t_arnoldi_ms = c->tacc[4];
     return converged ? CPTR_OK : CPTR_NOT_CONVERGED;
 }
 
@@ -612,6 +649,7 @@ cptr_status cptr_default_options(cptr_options *o) {
     o->ilu_tile_y = 32;
     o->t_interp = CPTR_INTERP_CLASSICAL;
     o->reuse_rho_max = 0.3;
+    o->timing = 0;
     return CPTR_OK;
 }
 
@@ -633,6 +671,7 @@ cptr_status cptr_create(cptr_ctx **out, int32_t dev, void *stream, const cptr_op
     fill_int(c->flag.p, 0, 1, c->stream);
     CPTR_HIP(hipEventCreate(&c->ev0));
     CPTR_HIP(hipEventCreate(&c->ev1));
+    for (auto &e : c->tev) CPTR_HIP(hipEventCreate(&e));
     CPTR_HIP(hipStreamSynchronize(c->stream));
     *out = c.release();
     return CPTR_OK;

@@ -124,7 +124,7 @@ def assemble(nx: int, ny: int, b: int, perm: np.ndarray, *, peclet: float,
              coupling: float = 0.1, seed: int = 0,
              field_seed: int | None = None, band: tuple[int, int, float] | None = None,
              zero_coupling: bool = False, flow: bool = True,
-             transmissibility: bool = True, coupling_ref: str = "row",
+             transmissibility: bool = True, coupling_ref: str = "flux",
              heat_capacity: float = 1.0) -> BSRSystem:
     """Assemble the BSR system on an nx x ny grid of unit cells (index c = x + nx*y).
 
@@ -146,9 +146,12 @@ def assemble(nx: int, ny: int, b: int, perm: np.ndarray, *, peclet: float,
       pressure row    diag acc + sum_f T_f,                  off-diag -T_f
       temperature row diag acc_T + sum_f K_T + rcp sum_out F, off-diag -K_T - rcp F_f [J upwind of I]
       composition row diag acc + sum_out F,                  off-diag -F_f [J upwind of I]
-    Cross-unknown entries: for every stored block and r != c,
-      A_IJ[r, c] = xi * A_IJ[r, r] (``coupling_ref="row"``; "col" uses A_IJ[c, c]),
-      xi ~ U(-coupling, coupling) independent per entry.
+    Cross-unknown entries (``coupling_ref="flux"``, the default): conservative
+      face couplings, see ``_flux_couplings``.  Alternative readings kept for
+      comparison: "row" sets A_IJ[r, c] = xi * A_IJ[r, r] and "col" sets
+      A_IJ[r, c] = xi * A_IJ[c, c] on every stored block independently; both
+      break conservation, and with the near-incompressible pressure
+      accumulation the decoupled pressure block then turns indefinite.
     ``band = (x0, x1, factor)`` multiplies A_II[T, T] by ``factor`` for x0 <= x < x1
     (the moving combustion front of the Newton sequence).
 
@@ -243,14 +246,20 @@ def assemble(nx: int, ny: int, b: int, perm: np.ndarray, *, peclet: float,
 
     # cross-unknown couplings ------------------------------------------------
     rng_c = np.random.default_rng([seed, 2])
-    xi = rng_c.uniform(-coupling, coupling, size=(nnzb, b, b))
-    if zero_coupling:
-        xi[:] = 0.0
-    d = np.diagonal(vals, axis1=1, axis2=2).copy()   # (nnzb, b)
-    off = ~np.eye(b, dtype=bool)
-    ref = d[:, None, :] if coupling_ref == "col" else d[:, :, None]
-    vals += np.where(off[None], xi * ref, 0.0)
-    del xi
+    if coupling_ref == "flux":
+        if not zero_coupling:
+            acc_col = np.full(b, acc)
+            acc_col[T_INDEX] = acc_t
+            _flux_couplings(vals, b, nx, ny, slot, tx, ty, fx, fy, acc_col, coupling, rng_c)
+    else:
+        xi = rng_c.uniform(-coupling, coupling, size=(nnzb, b, b))
+        if zero_coupling:
+            xi[:] = 0.0
+        d = np.diagonal(vals, axis1=1, axis2=2).copy()   # (nnzb, b)
+        off = ~np.eye(b, dtype=bool)
+        ref = d[:, None, :] if coupling_ref == "col" else d[:, :, None]
+        vals += np.where(off[None], xi * ref, 0.0)
+        del xi
 
     if band is not None:
         x0, x1, factor = band
@@ -265,6 +274,45 @@ def assemble(nx: int, ny: int, b: int, perm: np.ndarray, *, peclet: float,
     meta = dict(nx=nx, ny=ny, b=b, peclet=peclet, k_thermal=kt, rho_cp=rcp,
                 dt=dt, acc=acc, seed=seed, field_seed=field_seed, band=band)
     return BSRSystem(nx, ny, b, row_ptr.astype(np.int32), col_idx, vals, rhs, meta)
+
+
+def _flux_couplings(vals, b, nx, ny, slot, tx, ty, fx, fy, acc_col, coupling, rng):
+    """Conservative cross-unknown couplings (reading of "coupling entries
+    uniform(-0.1, 0.1) times the diagonal").  For every interior face f from
+    an upwind cell I to a downwind cell J and every pair r != c, the flux of
+    quantity r across f depends on unknown c with a coefficient xi times the
+    face's own (diagonal) flux coefficient of c: the transmissibility T_f for
+    pressure (flux_r += xi T_f (p_I - p_J)), the Darcy flux F_f for every other
+    unknown, taken upwind (flux_r += xi F_f c_I).  The flux leaves row I and
+    enters row J, so every face term has zero column sum like the principal
+    terms (conservation).  Each cell's accumulation of r also depends on its
+    own unknown c with xi times c's accumulation coefficient.
+    xi ~ U(-coupling, coupling), independent per face (or cell), r and c;
+    drawn in the order: x-faces, y-faces, cells."""
+    off = ~np.eye(b, dtype=bool)
+    s_dn, s_w, s_i, s_e, s_n = slot      # (ny, nx) block positions S, W, I, E, N
+    faces = (
+        # (T_f, F_f, block II, block IJ (I's entry for J), block JI, block JJ)
+        (tx, fx, s_i[:, :-1], s_e[:, :-1], s_w[:, 1:], s_i[:, 1:]),
+        (ty, fy, s_i[:-1, :], s_n[:-1, :], s_dn[1:, :], s_i[1:, :]),
+    )
+    for tf, ff, ii, ij, ji, jj in faces:
+        if tf.size == 0:
+            continue
+        xi = rng.uniform(-coupling, coupling, size=tf.shape + (b, b)) * off
+        scale = np.empty(tf.shape + (1, b))
+        scale[..., :] = ff[..., None, None]
+        scale[..., P_INDEX] = tf[..., None]
+        coef = xi * scale                         # (.., r, c)
+        pcol = np.zeros(b, bool); pcol[P_INDEX] = True
+        cp = np.where(pcol, coef, 0.0)            # pressure derivatives: central
+        cu = np.where(pcol, 0.0, coef)            # other unknowns: upwind (cell I)
+        np.add.at(vals, ii.reshape(-1), (cp + cu).reshape(-1, b, b))
+        np.add.at(vals, ij.reshape(-1), (-cp).reshape(-1, b, b))
+        np.add.at(vals, ji.reshape(-1), (-cp - cu).reshape(-1, b, b))
+        np.add.at(vals, jj.reshape(-1), cp.reshape(-1, b, b))
+    xi = rng.uniform(-coupling, coupling, size=(ny, nx, b, b)) * off
+    np.add.at(vals, s_i.reshape(-1), (xi * acc_col[None, None, None, :]).reshape(-1, b, b))
 
 
 # ---------------------------------------------------------------------------
