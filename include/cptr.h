@@ -84,7 +84,7 @@ typedef struct {
     int32_t pre_sweeps, post_sweeps;
     double  jacobi_omega;       /* (2/3)                                          */
     uint64_t pmis_seed;         /* seed of the coarsening's random measure        */
-    int32_t ilu_tile_x, ilu_tile_y;  /* tile shape of the BILU(0) order (32, 32)  */
+    int32_t ilu_tile_x, ilu_tile_y;  /* tile shape of the BILU(0) order (32, 8)   */
     int32_t t_interp;           /* CPTR_INTERP_CLASSICAL | CPTR_INTERP_LEARNED     */
     double  reuse_rho_max;      /* hierarchy reuse threshold for update_values    */
     int32_t timing;             /* 1: time every stage of every Arnoldi step with */
@@ -111,7 +111,7 @@ typedef struct {
     double  t_arnoldi_ms;       /* Gram-Schmidt, Givens, normalisation            */
 } cptr_result;
 
-/* Fill *opt with the defaults noted above (CPTR3, T then P, BILU(0) in 32x32
+/* Fill *opt with the defaults noted above (CPTR3, T then P, BILU(0) in 32x8
  * tiles, GMRES(30), rtol 1e-8, classical AMG with the paper's max coarse size
  * 1000 (Sec. "Thermal-Compositional Homogeneous Cases")). */
 cptr_status cptr_default_options(cptr_options *opt);

@@ -466,7 +466,7 @@ def rank_from_colors(color: np.ndarray) -> np.ndarray:
     return rank
 
 
-def tile_colors(nx: int, ny: int, tile_x: int = 32, tile_y: int = 32) -> np.ndarray:
+def tile_colors(nx: int, ny: int, tile_x: int = 32, tile_y: int = 8) -> np.ndarray:
     """Red-black colouring of tile_x x tile_y tiles of the grid (cell c = x + nx y):
     colour ((x // tile_x) + (y // tile_y)) mod 2.  With rank_from_colors this
     orders all red tiles before all black tiles and keeps the natural order

@@ -426,15 +426,6 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
     if (read_flag_and_clear(c) & 16) throw Error(CPTR_E_NONFINITE, "non-finite matrix entry");
     c->s_i4.alloc(2);
     fill_int(c->s_i4.p, 0x7fffffff, 1, s);
-    if (c->opt.variant == CPTR_VARIANT_LAST_ONLY) {
-        CPTR_HIP(hipMemcpyAsync(c->abar.p, vals, sizeof(double) * nnzb * b * b, hipMemcpyDeviceToDevice, s));
-    } else {
-        launch_decouple(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->abar.p, c->wp.p, c->wt.p,
-                        c->beta.p, c->s_i4.p, s);
-    }
-    int bad = read_scalar(c->s_i4.p, s);
-    if (bad != 0x7fffffff)
-        throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block (D_ss or Ahat_PP) in cell " + std::to_string(bad));
     c->slabT.alloc((size_t)nnzb * b);
     c->slabP.alloc((size_t)nnzb * b);
     DBuf<double> ctt, bpp;
@@ -445,8 +436,19 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
         c->slabT32.alloc((size_t)nnzb * b);
         c->slabP32.alloc((size_t)nnzb * b);
     }
-    launch_extract(n, b, nnzb, c->abar.p, c->ip, c->it, ctt.p, bpp.p, c->slabT.p, c->slabP.p,
-                   fp32 ? c->abar32.p : nullptr, fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
+    if (c->opt.variant == CPTR_VARIANT_LAST_ONLY) {
+        CPTR_HIP(hipMemcpyAsync(c->abar.p, vals, sizeof(double) * nnzb * b * b, hipMemcpyDeviceToDevice, s));
+        launch_extract(n, b, nnzb, c->abar.p, c->ip, c->it, ctt.p, bpp.p, c->slabT.p, c->slabP.p,
+                       fp32 ? c->abar32.p : nullptr, fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
+    } else {
+        launch_decouple_extract(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->abar.p, c->wp.p,
+                                c->wt.p, c->beta.p, c->s_i4.p, ctt.p, bpp.p, c->slabT.p, c->slabP.p,
+                                fp32 ? c->abar32.p : nullptr, fp32 ? c->slabT32.p : nullptr,
+                                fp32 ? c->slabP32.p : nullptr, s);
+    }
+    int bad = read_scalar(c->s_i4.p, s);
+    if (bad != 0x7fffffff)
+        throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block (D_ss or Ahat_PP) in cell " + std::to_string(bad));
     // scalar stages
     if (c->opt.variant == CPTR_VARIANT_CPTR3) build_hierarchy(c, c->H[0], ctt.p);
     if (c->opt.variant == CPTR_VARIANT_CPTR3 || c->opt.variant == CPTR_VARIANT_CPR) build_hierarchy(c, c->H[1], bpp.p);
@@ -465,9 +467,9 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
     if (fp32) {
         c->dinv32.alloc((size_t)n * b * b);
         to_float(c->dinv.p, c->dinv32.p, (size_t)n * b * b, s);
-        c->tw32.alloc((size_t)n * b);
+        c->tw32.alloc(2 * (size_t)n * b);
     } else {
-        c->tw.alloc((size_t)n * b);
+        c->tw.alloc(2 * (size_t)n * b);
     }
     CPTR_HIP(hipStreamSynchronize(s));
 }
@@ -646,7 +648,7 @@ cptr_status cptr_default_options(cptr_options *o) {
     o->jacobi_omega = 2.0 / 3.0;
     o->pmis_seed = 0;
     o->ilu_tile_x = 32;
-    o->ilu_tile_y = 32;
+    o->ilu_tile_y = 8;
     o->t_interp = CPTR_INTERP_CLASSICAL;
     o->reuse_rho_max = 0.3;
     o->timing = 0;
@@ -661,6 +663,7 @@ cptr_status cptr_create(cptr_ctx **out, int32_t dev, void *stream, const cptr_op
     CPTR_HIP(hipGetDeviceCount(&ndev));
     if (dev < 0 || dev >= ndev) throw Error(CPTR_E_ARG, "invalid HIP device");
     CPTR_HIP(hipSetDevice(dev));
+    StreamScope scope((hipStream_t)stream);
     auto c = std::make_unique<cptr_ctx>();
     c->device = dev;
     c->stream = (hipStream_t)stream;
@@ -682,8 +685,11 @@ cptr_status cptr_destroy(cptr_ctx *c) {
     CPTR_API_BEGIN
     if (!c) return CPTR_OK;
     CPTR_HIP(hipSetDevice(c->device));
+    StreamScope scope(c->stream);
     CPTR_HIP(hipStreamSynchronize(c->stream));
+    hipStream_t s = c->stream;
     delete c;
+    pool_trim(s);
     return CPTR_OK;
     CPTR_API_END
 }
@@ -691,6 +697,7 @@ cptr_status cptr_destroy(cptr_ctx *c) {
 cptr_status cptr_setup(cptr_ctx *c, int32_t n, int32_t b, int32_t nnzb, const int32_t *d_rp, const int32_t *d_ci,
                        const double *d_vals, int32_t p_index, int32_t T_index, int32_t nx, int32_t ny) {
     CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
     if (!c) throw Error(CPTR_E_ARG, "null context");
     CPTR_HIP(hipSetDevice(c->device));
     if (n <= 0 || nnzb < n || b < 2 || b > 8) throw Error(CPTR_E_ARG, "need n > 0, nnzb >= n, 2 <= b <= 8");
@@ -740,6 +747,7 @@ cptr_status cptr_setup(cptr_ctx *c, int32_t n, int32_t b, int32_t nnzb, const in
 
 cptr_status cptr_update_values(cptr_ctx *c, const double *d_vals) {
     CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
     if (!c || !c->ready) throw Error(CPTR_E_STATE, "update_values before setup");
     CPTR_HIP(hipSetDevice(c->device));
     CPTR_HIP(hipEventRecord(c->ev0, c->stream));
@@ -755,6 +763,7 @@ cptr_status cptr_update_values(cptr_ctx *c, const double *d_vals) {
 
 cptr_status cptr_solve(cptr_ctx *c, const double *d_rhs, double *d_x, cptr_result *out) {
     CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
     if (!c || !c->ready) throw Error(CPTR_E_STATE, "solve before setup");
     if (!d_rhs || !d_x) throw Error(CPTR_E_ARG, "null vector");
     CPTR_HIP(hipSetDevice(c->device));
@@ -807,6 +816,7 @@ cptr_status cptr_decouple(int32_t variant, int32_t n, int32_t b, const int32_t *
                           const double *d_vals, const double *d_rhs, int32_t ip, int32_t it, double *d_abar,
                           double *d_rhsbar, void *stream) {
     CPTR_API_BEGIN
+    StreamScope scope((hipStream_t)stream);
     if (variant != CPTR_VARIANT_CPTR3 && variant != CPTR_VARIANT_CPR) throw Error(CPTR_E_ARG, "variant");
     if (n <= 0 || b < 2 || b > 8) throw Error(CPTR_E_ARG, "sizes");
     hipStream_t s = (hipStream_t)stream;
@@ -865,6 +875,7 @@ cptr_status cptr_amg_level_info(const cptr_ctx *c, int32_t which, int32_t level,
 cptr_status cptr_amg_level_copy(const cptr_ctx *c, int32_t which, int32_t level, int32_t *h_rp, int32_t *h_ci,
                                 double *h_v, int32_t *h_cf, int32_t *h_prp, int32_t *h_pci, double *h_pv) {
     CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
     Hierarchy &h = pick(c, which);
     if (level < 0 || level >= (int)h.L.size()) throw Error(CPTR_E_ARG, "level out of range");
     CPTR_HIP(hipSetDevice(c->device));
@@ -887,6 +898,7 @@ cptr_status cptr_amg_level_copy(const cptr_ctx *c, int32_t which, int32_t level,
 
 cptr_status cptr_amg_vcycle(cptr_ctx *c, int32_t which, const double *d_b, double *d_x) {
     CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
     Hierarchy &h = pick(c, which);
     CPTR_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;
@@ -901,6 +913,7 @@ cptr_status cptr_amg_vcycle(cptr_ctx *c, int32_t which, const double *d_b, doubl
 
 cptr_status cptr_precond_apply(cptr_ctx *c, const double *d_r, double *d_y) {
     CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
     if (!c || !c->ready) throw Error(CPTR_E_STATE, "context not set up");
     CPTR_HIP(hipSetDevice(c->device));
     precond(c, d_r, d_y);
@@ -911,6 +924,7 @@ cptr_status cptr_precond_apply(cptr_ctx *c, const double *d_r, double *d_y) {
 
 cptr_status cptr_get_scaled(const cptr_ctx *c, double *d_abar, double *d_rhsbar, const double *d_rhs) {
     CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
     if (!c || !c->ready) throw Error(CPTR_E_STATE, "context not set up");
     CPTR_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;

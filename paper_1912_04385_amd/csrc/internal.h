@@ -34,33 +34,57 @@ struct Error : std::runtime_error {
 #define CPTR_CHECK_LAUNCH() CPTR_HIP(hipGetLastError())
 
 // ---------------------------------------------------------------------------
-// device buffer (owned; freed in the destructor)
+// device memory: a caching pool per (device, stream).  Blocks released by a
+// buffer go back to the pool of the stream they were allocated for and are
+// reused by later allocations on that stream (stream order makes the reuse
+// safe); cptr_destroy returns the idle blocks of its stream to the driver.
+// Every API entry point names its stream with StreamScope.
 // ---------------------------------------------------------------------------
+hipStream_t current_stream();
+void *pool_alloc(size_t bytes, size_t *cap, hipStream_t *owner, int *dev);
+void pool_free(void *p, size_t cap, hipStream_t owner, int dev);
+void pool_trim(hipStream_t s);
+
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s);
+    ~StreamScope();
+};
+
 template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    size_t cap = 0;              // bytes of the pooled block
+    hipStream_t owner = nullptr;
+    int dev = 0;
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), cap(o.cap), owner(o.owner), dev(o.dev) {
+        o.p = nullptr; o.n = 0; o.cap = 0;
+    }
     DBuf &operator=(DBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; cap = o.cap; owner = o.owner; dev = o.dev;
+            o.p = nullptr; o.n = 0; o.cap = 0;
+        }
         return *this;
     }
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) pool_free(p, cap, owner, dev);
         p = nullptr;
         n = 0;
+        cap = 0;
     }
     // (re)allocate to at least m elements; contents undefined
     void alloc(size_t m) {
         if (m <= n && p) return;
         release();
-        size_t bytes = (m ? m : 1) * sizeof(T);
-        CPTR_HIP(hipMalloc((void **)&p, bytes));
-        n = m;
+        p = (T *)pool_alloc((m ? m : 1) * sizeof(T), &cap, &owner, &dev);
+        n = cap / sizeof(T);
     }
     T *get() const { return p; }
 };
@@ -111,6 +135,10 @@ void to_float(const double *x, float *y, size_t n, hipStream_t s);
 // k_decouple.hip
 void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                      double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s);
+void launch_decouple_extract(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
+                             int it, double *abar, double *wp, double *wt, double *beta, int *err, double *ctt,
+                             double *bpp, double *slabT, double *slabP, float *abar32, float *slabT32,
+                             float *slabP32, hipStream_t s);
 void launch_scale_rhs(int variant, int n, int b, const double *rhs, int ip, int it, const double *wp,
                       const double *wt, const double *beta, double *out, hipStream_t s);
 void launch_unscale(int variant, int n, int b, const double *v, int ip, int it, const double *wp,

@@ -13,6 +13,8 @@
 // and M = (D + L) D^{-1} (D + U) with L, U the off-diagonal blocks of Abar.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace cptr {
 
 constexpr int BL_THREADS = 256;
@@ -257,10 +259,286 @@ __global__ void __launch_bounds__(BL_THREADS) k_bilu_apply(TileGeom g, int mode,
     }
 }
 
+// ---------------------------------------------------------------------------
+// one-wavefront-per-tile apply (tiles with at most 64/b cells per
+// anti-diagonal and at most WT_MAX_CELLS cells).  The tile's wavefront values
+// live in LDS; couplings to other tiles (all of another colour, final from an
+// earlier launch) are folded in by a parallel pre-pass; the level loop then
+// only touches in-tile neighbours, with the next level's matrix rows loaded
+// into registers while the current level computes.
+// ---------------------------------------------------------------------------
+constexpr int WT_MAX_CELLS = 512;   // 64 KB of LDS at b = 8 in FP64
+
+// u = r - Abar[:,T] xT - Abar[:,P] vP, one thread per scalar row
+template <class T>
+__global__ void k_stage_residual(int n, int b, const int *__restrict__ rp, const int *__restrict__ ci,
+                                 const T *__restrict__ slabT, const T *__restrict__ slabP,
+                                 const double *__restrict__ rv, const T *__restrict__ xT, const T *__restrict__ vP,
+                                 T *__restrict__ u) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n * b) return;
+    const int i = (int)(t / b), r = (int)(t % b);
+    T acc = (T)rv[t];
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        if (xT) acc -= slabT[(size_t)e * b + r] * xT[j];
+        if (vP) acc -= slabP[(size_t)e * b + r] * vP[j];
+    }
+    u[t] = acc;
+}
+
+template <class T, int B>
+__global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const int *__restrict__ tiles,
+                                                  const int *__restrict__ color, const int *__restrict__ rp,
+                                                  const int *__restrict__ ci, const T *__restrict__ abar,
+                                                  const T *__restrict__ dinv, const T *__restrict__ u,
+                                                  T *__restrict__ tw, double *__restrict__ y, int ip, int it,
+                                                  const T *__restrict__ xT, const T *__restrict__ vP) {
+    constexpr int GPW = 64 / B;
+    extern __shared__ unsigned char lds_raw[];
+    T *S = reinterpret_cast<T *>(lds_raw);                  // pre-pass sums
+    T *W = S + (size_t)g.tx * g.ty * B;                      // t (forward), then w (backward)
+    const int lane = threadIdx.x;
+    const int grp = lane / B, r = lane % B;
+    const bool glane = grp < GPW;
+    const int gbase = grp * B;
+    const int tile = tiles[blockIdx.x];
+    int x0, y0, tw_, th;
+    tile_dims(g, tile, x0, y0, tw_, th);
+    const int ncell = tw_ * th;
+    const int nlev = tw_ + th - 1;
+    const int mycolor = color[x0 + g.nx * y0];
+    auto cell_of = [&](int loc) { return (x0 + loc % tw_) + g.nx * (y0 + loc / tw_); };
+    auto in_tile = [&](int j, int &loc) {
+        const int xj = j % g.nx - x0, yj = j / g.nx - y0;
+        loc = xj + tw_ * yj;
+        return xj >= 0 && xj < tw_ && yj >= 0 && yj < th;
+    };
+
+    if (mode == 0 || mode == 1) {
+        // pre-pass: S = u - (couplings to lower-colour tiles) . t
+        for (int base = 0; base < ncell; base += GPW) {
+            const int loc = base + grp;
+            if (glane && loc < ncell) {
+                const int i = cell_of(loc);
+                T acc = u[(size_t)i * B + r];
+                for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                    const int j = ci[e];
+                    if (j == i || color[j] >= mycolor) continue;
+                    const T *Aij = abar + (size_t)e * B * B + r * B;
+                    const T *tj = tw + (size_t)j * B;
+#pragma unroll
+                    for (int m = 0; m < B; ++m) acc -= Aij[m] * tj[m];
+                }
+                S[loc * B + r] = acc;
+            }
+        }
+        __syncthreads();
+        // level loop (forward): in-tile lower neighbours are W (x-1) and S (y-1)
+        T na0[B], na1[B], nd[B];
+        int nl0 = -1, nl1 = -1, nloc = -1, ni = 0;
+        auto load_fwd = [&](int lev, int slot) {
+            const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
+            const int lx = lo + slot + grp;      // this lane group's cell of the level
+            nloc = -1; nl0 = -1; nl1 = -1;
+            if (!glane || lev >= nlev || lx > hi) return;
+            const int ly = lev - lx;
+            nloc = lx + tw_ * ly;
+            ni = (x0 + lx) + g.nx * (y0 + ly);
+            for (int e = rp[ni]; e < rp[ni + 1]; ++e) {
+                const int j = ci[e];
+                int lj;
+                if (j == ni || !in_tile(j, lj) || j > ni) continue;
+                const T *Aij = abar + (size_t)e * B * B + r * B;
+                if (nl0 < 0) {
+                    nl0 = lj;
+#pragma unroll
+                    for (int m = 0; m < B; ++m) na0[m] = Aij[m];
+                } else {
+                    nl1 = lj;
+#pragma unroll
+                    for (int m = 0; m < B; ++m) na1[m] = Aij[m];
+                }
+            }
+            const T *Di = dinv + (size_t)ni * B * B + r * B;
+#pragma unroll
+            for (int c = 0; c < B; ++c) nd[c] = Di[c];
+        };
+        int lev = 0, slot = 0;
+        load_fwd(0, 0);
+        while (lev < nlev) {
+            T a0[B], a1[B], d[B];
+#pragma unroll
+            for (int m = 0; m < B; ++m) { a0[m] = na0[m]; a1[m] = na1[m]; d[m] = nd[m]; }
+            const int l0 = nl0, l1 = nl1, loc = nloc, i = ni;
+            // advance to the next (level, slot) and prefetch it
+            const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
+            int nlev_ = lev, nslot = slot + GPW;
+            if (lo + nslot > hi) { nlev_ = lev + 1; nslot = 0; }
+            load_fwd(nlev_, nslot);
+            T s = 0;
+            if (loc >= 0) {
+                s = S[loc * B + r];
+                if (l0 >= 0) {
+#pragma unroll
+                    for (int m = 0; m < B; ++m) s -= a0[m] * W[l0 * B + m];
+                }
+                if (l1 >= 0) {
+#pragma unroll
+                    for (int m = 0; m < B; ++m) s -= a1[m] * W[l1 * B + m];
+                }
+            }
+            T tv = 0;
+#pragma unroll
+            for (int c = 0; c < B; ++c) tv += d[c] * shfl(s, gbase + c);
+            if (loc >= 0) {
+                W[loc * B + r] = tv;
+                if (mode == 0) tw[(size_t)i * B + r] = tv;
+            }
+            __syncthreads();
+            lev = nlev_;
+            slot = nslot;
+        }
+    }
+    if (mode == 1 || mode == 2) {
+        if (mode == 2) {
+            // pre-pass: S = (couplings to higher-colour tiles) . w, W = t from the forward launch
+            for (int base = 0; base < ncell; base += GPW) {
+                const int loc = base + grp;
+                if (glane && loc < ncell) {
+                    const int i = cell_of(loc);
+                    T acc = 0;
+                    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                        const int j = ci[e];
+                        if (j == i || color[j] <= mycolor) continue;
+                        const T *Aij = abar + (size_t)e * B * B + r * B;
+                        const T *wj = tw + (size_t)j * B;
+#pragma unroll
+                        for (int m = 0; m < B; ++m) acc += Aij[m] * wj[m];
+                    }
+                    S[loc * B + r] = acc;
+                    W[loc * B + r] = tw[(size_t)i * B + r];
+                }
+            }
+        } else {
+            for (int k = lane; k < ncell * B; k += 64) S[k] = 0;
+        }
+        __syncthreads();
+        T na0[B], na1[B], nd[B];
+        int nl0 = -1, nl1 = -1, nloc = -1, ni = 0;
+        auto load_bwd = [&](int lev, int slot) {
+            nloc = -1; nl0 = -1; nl1 = -1;
+            if (!glane || lev < 0) return;
+            const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
+            const int lx = lo + slot + grp;      // this lane group's cell of the level
+            if (lx > hi) return;
+            const int ly = lev - lx;
+            nloc = lx + tw_ * ly;
+            ni = (x0 + lx) + g.nx * (y0 + ly);
+            for (int e = rp[ni]; e < rp[ni + 1]; ++e) {
+                const int j = ci[e];
+                int lj;
+                if (j == ni || !in_tile(j, lj) || j < ni) continue;
+                const T *Aij = abar + (size_t)e * B * B + r * B;
+                if (nl0 < 0) {
+                    nl0 = lj;
+#pragma unroll
+                    for (int m = 0; m < B; ++m) na0[m] = Aij[m];
+                } else {
+                    nl1 = lj;
+#pragma unroll
+                    for (int m = 0; m < B; ++m) na1[m] = Aij[m];
+                }
+            }
+            const T *Di = dinv + (size_t)ni * B * B + r * B;
+#pragma unroll
+            for (int c = 0; c < B; ++c) nd[c] = Di[c];
+        };
+        int lev = nlev - 1, slot = 0;
+        load_bwd(lev, 0);
+        while (lev >= 0) {
+            T a0[B], a1[B], d[B];
+#pragma unroll
+            for (int m = 0; m < B; ++m) { a0[m] = na0[m]; a1[m] = na1[m]; d[m] = nd[m]; }
+            const int l0 = nl0, l1 = nl1, loc = nloc, i = ni;
+            const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
+            int nlev_ = lev, nslot = slot + GPW;
+            if (lo + nslot > hi) { nlev_ = lev - 1; nslot = 0; }
+            load_bwd(nlev_, nslot);
+            T q = 0, tval = 0;
+            if (loc >= 0) {
+                q = S[loc * B + r];
+                tval = W[loc * B + r];
+                if (l0 >= 0) {
+#pragma unroll
+                    for (int m = 0; m < B; ++m) q += a0[m] * W[l0 * B + m];
+                }
+                if (l1 >= 0) {
+#pragma unroll
+                    for (int m = 0; m < B; ++m) q += a1[m] * W[l1 * B + m];
+                }
+            }
+            T corr = 0;
+#pragma unroll
+            for (int c = 0; c < B; ++c) corr += d[c] * shfl(q, gbase + c);
+            __syncthreads();   // every lane has read its W entries before they are overwritten
+            if (loc >= 0) {
+                const T w = tval - corr;
+                W[loc * B + r] = w;
+                if (mode == 1) tw[(size_t)i * B + r] = w;
+                double yv = (double)w;
+                if (r == it && xT) yv += (double)xT[i];
+                if (r == ip && vP) yv += (double)vP[i];
+                y[(size_t)i * B + r] = yv;
+            }
+            __syncthreads();
+            lev = nlev_;
+            slot = nslot;
+        }
+    }
+}
+
+template <class T>
+static void bilu_apply_wave(const TileSched &ts, int n, int b, const int *rp, const int *ci, const T *abar,
+                            const T *dinv, const T *slabT, const T *slabP, int ip, int it, const double *r,
+                            const T *xT, const T *vP, T *u, T *tw, double *y, hipStream_t st) {
+    const long nr = (long)n * b;
+    hipLaunchKernelGGL(k_stage_residual<T>, dim3((int)((nr + 255) / 256)), dim3(256), 0, st, n, b, rp, ci, slabT,
+                       slabP, r, xT, vP, u);
+    TileGeom g{ts.nx, ts.ny, ts.tx, ts.ty, ts.ntx};
+    const size_t lds = 2 * (size_t)ts.tx * ts.ty * b * sizeof(T);
+    auto launch = [&](int color, int mode) {
+        const int nt = ts.ntiles[color];
+        if (nt == 0) return;
+#define CASE(BB) case BB: hipLaunchKernelGGL((k_bilu_wave<T, BB>), dim3(nt), dim3(64), lds, st, g, mode, ts.tiles[color].p, ts.color.p, rp, ci, abar, dinv, u, tw, y, ip, it, xT, vP); break;
+        switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
+        CPTR_CHECK_LAUNCH();
+    };
+    if (ts.ntiles[1] == 0) {
+        launch(0, 1);
+    } else {
+        launch(0, 0);
+        launch(1, 1);
+        launch(0, 2);
+    }
+}
+
+bool bilu_wave_ok(const TileSched &ts, int b) {
+    return ts.tx * ts.ty <= WT_MAX_CELLS && std::min(ts.tx, ts.ty) <= 64 / b;
+}
+
 template <class T>
 void bilu_apply_tiles(const TileSched &ts, int b, const int *rp, const int *ci, const T *abar, const T *dinv,
                       const T *slabT, const T *slabP, int ip, int it, const double *r, const T *xT, const T *vP,
                       T *tw, double *y, hipStream_t st) {
+    if (bilu_wave_ok(ts, b)) {
+        // tw holds 2 n b values: the stage residual u, then t / w
+        const int n = ts.nx * ts.ny;
+        bilu_apply_wave<T>(ts, n, b, rp, ci, abar, dinv, slabT, slabP, ip, it, r, xT, vP, tw + (size_t)n * b, tw,
+                           y, st);
+        return;
+    }
     TileGeom g{ts.nx, ts.ny, ts.tx, ts.ty, ts.ntx};
     auto launch = [&](int color, int mode) {
         const int nt = ts.ntiles[color];

@@ -1,7 +1,86 @@
 // Shared device utilities: prefix scan, fills, pattern checks, conversions.
 #include "internal.h"
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 namespace cptr {
+
+// ---------------------------------------------------------------------------
+// caching device allocator
+// ---------------------------------------------------------------------------
+static thread_local hipStream_t t_stream = nullptr;
+static std::mutex g_pool_mu;
+static std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> *g_pool;
+
+hipStream_t current_stream() { return t_stream; }
+
+StreamScope::StreamScope(hipStream_t s) : prev(t_stream) { t_stream = s; }
+StreamScope::~StreamScope() { t_stream = prev; }
+
+static size_t round_cap(size_t bytes) {
+    // 256-byte granules, then at most 1/8 slack per power of two
+    size_t b = (bytes + 255) & ~(size_t)255;
+    if (b <= 4096) return b;
+    size_t p2 = 1;
+    while (p2 < b) p2 <<= 1;
+    size_t step = p2 / 16;
+    return ((b + step - 1) / step) * step;
+}
+
+void *pool_alloc(size_t bytes, size_t *cap, hipStream_t *owner, int *devp) {
+    int dev = 0;
+    CPTR_HIP(hipGetDevice(&dev));
+    *devp = dev;
+    const size_t want = round_cap(bytes);
+    const hipStream_t s = t_stream;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (!g_pool) g_pool = new std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>>();
+        auto &fl = (*g_pool)[{dev, s}];
+        auto it = fl.lower_bound(want);
+        if (it != fl.end() && it->first <= want + want / 4) {
+            void *p = it->second;
+            *cap = it->first;
+            fl.erase(it);
+            *owner = s;
+            return p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        // give idle blocks of this stream back and retry once
+        (void)hipGetLastError();
+        pool_trim(s);
+        CPTR_HIP(hipMalloc(&p, want));
+    }
+    *cap = want;
+    *owner = s;
+    return p;
+}
+
+void pool_free(void *p, size_t cap, hipStream_t owner, int dev) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pool) g_pool = new std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>>();
+    (*g_pool)[{dev, owner}].insert({cap, p});
+}
+
+void pool_trim(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::multimap<size_t, void *> victims;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (!g_pool) return;
+        auto it = g_pool->find({dev, s});
+        if (it == g_pool->end()) return;
+        victims.swap(it->second);
+    }
+    (void)hipStreamSynchronize(s);
+    for (auto &kv : victims) (void)hipFree(kv.second);
+}
 
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 4;

@@ -8,29 +8,43 @@
 
 namespace cptr {
 
+// index of the k-th unknown of the eliminated group: the unknowns other than
+// P (and T unless the group contains it), in ascending order
+__device__ inline int group_index(int k, int ip, int it, bool with_t) {
+    int lo = with_t ? ip : min(ip, it), hi = with_t ? -1 : max(ip, it);
+    int g = k;
+    if (g >= lo) ++g;
+    if (hi >= 0 && g >= hi) ++g;
+    return g;
+}
+
 // One wavefront per cell.  Every lane redundantly solves the small system
 // D_gg^T [w_P w_T] = [D_Pg^T D_Tg^T] (g = the eliminated group: s for CPTR3,
 // s u {T} for CPR) by Gaussian elimination with partial pivoting -- first
-// largest |pivot|, kij order, back substitution in descending rows -- then
-// handles block entry (r, c) = (lane / b, lane % b) of every block of the row:
+// largest |pivot|, kij order, back substitution in descending rows -- in
+// registers, then handles block entry (r, c) = (lane / b, lane % b) of every
+// block of the row:
 //   Ahat[P][c] = A[P][c] - sum_{k ascending} w_P[k] A[g_k][c]
 //   Ahat[T][c] = A[T][c] - sum_{k ascending} w_T[k] A[g_k][c]
 //   CPTR3: beta = Ahat_ii[T][P] / Ahat_ii[P][P];  Abar[T][c] = Ahat[T][c] - beta Ahat[P][c]
-template <int B>
-__global__ void __launch_bounds__(64) k_decouple(int variant, int n, const int *__restrict__ rp,
-                                                 const int *__restrict__ ci, const double *__restrict__ A, int ip,
-                                                 int it, double *__restrict__ abar, double *__restrict__ wp,
-                                                 double *__restrict__ wt, double *__restrict__ beta, int *err) {
+// The same lanes extract C_TT = Abar[T,T], B_PP = Abar[P,P], the T and P
+// column slabs and the FP32 copies.
+template <int B, int VAR>
+__global__ void __launch_bounds__(64) k_decouple(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                 const double *__restrict__ A, int ip, int it,
+                                                 double *__restrict__ abar, double *__restrict__ wp,
+                                                 double *__restrict__ wt, double *__restrict__ beta, int *err,
+                                                 double *__restrict__ ctt, double *__restrict__ bpp,
+                                                 double *__restrict__ slabT, double *__restrict__ slabP,
+                                                 float *__restrict__ abar32, float *__restrict__ slabT32,
+                                                 float *__restrict__ slabP32) {
+    constexpr bool CPR = (VAR == CPTR_VARIANT_CPR);
+    constexpr int NG = CPR ? B - 1 : B - 2;
+    constexpr int NR = CPR ? 1 : 2;
+    constexpr int NGX = NG > 0 ? NG : 1;
     const int i = blockIdx.x;
     const int lane = threadIdx.x;
     if (i >= n) return;
-    int grp[B];
-    int ng = 0;
-    for (int r = 0; r < B; ++r) {
-        if (r == ip) continue;
-        if (r == it && variant != CPTR_VARIANT_CPR) continue;
-        grp[ng++] = r;
-    }
     int d = -1;
     for (int e = rp[i]; e < rp[i + 1]; ++e)
         if (ci[e] == i) d = e;
@@ -39,91 +53,143 @@ __global__ void __launch_bounds__(64) k_decouple(int variant, int n, const int *
         return;
     }
     const double *D = A + (size_t)d * B * B;
-    const int nrhs = (variant == CPTR_VARIANT_CPR) ? 1 : 2;
-    double M[B * B];
-    double F[B * 2];
-    for (int r = 0; r < ng; ++r) {
-        for (int c = 0; c < ng; ++c) M[r * ng + c] = D[grp[c] * B + grp[r]];
-        F[r * nrhs + 0] = D[ip * B + grp[r]];
-        if (nrhs == 2) F[r * nrhs + 1] = D[it * B + grp[r]];
+    double M[NGX][NGX];
+    double F[NGX][NR];
+#pragma unroll
+    for (int r = 0; r < NG; ++r) {
+        const int gr = group_index(r, ip, it, CPR);
+#pragma unroll
+        for (int c = 0; c < NG; ++c) M[r][c] = D[group_index(c, ip, it, CPR) * B + gr];
+        F[r][0] = D[ip * B + gr];
+        if (NR == 2) F[r][NR - 1] = D[it * B + gr];
     }
     bool singular = false;
-    for (int k = 0; k < ng; ++k) {
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
         int p = k;
-        double best = fabs(M[k * ng + k]);
-        for (int r = k + 1; r < ng; ++r) {
-            double a = fabs(M[r * ng + k]);
+        double best = fabs(M[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < NG; ++r) {
+            const double a = fabs(M[r][k]);
             if (a > best) { best = a; p = r; }
         }
-        if (best == 0.0) { singular = true; break; }
-        if (p != k) {
-            for (int c = 0; c < ng; ++c) { double t = M[k * ng + c]; M[k * ng + c] = M[p * ng + c]; M[p * ng + c] = t; }
-            for (int j = 0; j < nrhs; ++j) { double t = F[k * nrhs + j]; F[k * nrhs + j] = F[p * nrhs + j]; F[p * nrhs + j] = t; }
-        }
-        for (int r = k + 1; r < ng; ++r) {
-            double l = M[r * ng + k] / M[k * ng + k];
-            for (int c = k + 1; c < ng; ++c) M[r * ng + c] = M[r * ng + c] - l * M[k * ng + c];
-            for (int j = 0; j < nrhs; ++j) F[r * nrhs + j] = F[r * nrhs + j] - l * F[k * nrhs + j];
-        }
-    }
-    if (!singular) {
-        for (int k = ng - 1; k >= 0; --k)
-            for (int j = 0; j < nrhs; ++j) {
-                double t = F[k * nrhs + j];
-                for (int c = k + 1; c < ng; ++c) t = t - M[k * ng + c] * F[c * nrhs + j];
-                F[k * nrhs + j] = t / M[k * ng + k];
+        if (best == 0.0) singular = true;
+#pragma unroll
+        for (int r = k + 1; r < NG; ++r) {
+            if (r == p) {
+#pragma unroll
+                for (int c = 0; c < NG; ++c) { double t = M[k][c]; M[k][c] = M[r][c]; M[r][c] = t; }
+#pragma unroll
+                for (int j = 0; j < NR; ++j) { double t = F[k][j]; F[k][j] = F[r][j]; F[r][j] = t; }
             }
-    }
-    double bt = 0.0;
-    if (!singular && variant == CPTR_VARIANT_CPTR3) {
-        double hp = D[ip * B + ip], ht = D[it * B + ip];
-        for (int k = 0; k < ng; ++k) hp = hp - F[k * nrhs + 0] * D[grp[k] * B + ip];
-        for (int k = 0; k < ng; ++k) ht = ht - F[k * nrhs + 1] * D[grp[k] * B + ip];
-        if (hp == 0.0) singular = true;
-        else bt = ht / hp;
+        }
+#pragma unroll
+        for (int r = k + 1; r < NG; ++r) {
+            const double l = M[r][k] / M[k][k];
+#pragma unroll
+            for (int c = k + 1; c < NG; ++c) M[r][c] = M[r][c] - l * M[k][c];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) F[r][j] = F[r][j] - l * F[k][j];
+        }
     }
     if (singular) {
         if (lane == 0) atomicMin(err, i);
         return;
     }
+#pragma unroll
+    for (int k = NG - 1; k >= 0; --k) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            double t = F[k][j];
+#pragma unroll
+            for (int c = k + 1; c < NG; ++c) t = t - M[k][c] * F[c][j];
+            F[k][j] = t / M[k][k];
+        }
+    }
+    double bt = 0.0;
+    if (!CPR) {
+        double hp = D[ip * B + ip], ht = D[it * B + ip];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) hp = hp - F[k][0] * D[group_index(k, ip, it, CPR) * B + ip];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) ht = ht - F[k][NR - 1] * D[group_index(k, ip, it, CPR) * B + ip];
+        if (hp == 0.0) {
+            if (lane == 0) atomicMin(err, i);
+            return;
+        }
+        bt = ht / hp;
+    }
     if (lane < B) {
         double vp = 0.0, vt = 0.0;
-        for (int k = 0; k < ng; ++k)
-            if (grp[k] == lane) { vp = F[k * nrhs + 0]; if (nrhs == 2) vt = F[k * nrhs + 1]; }
+#pragma unroll
+        for (int k = 0; k < NG; ++k)
+            if (group_index(k, ip, it, CPR) == lane) { vp = F[k][0]; vt = (NR == 2) ? F[k][NR - 1] : 0.0; }
         wp[(size_t)i * B + lane] = vp;
         wt[(size_t)i * B + lane] = vt;
     }
     if (lane == 0) beta[i] = bt;
     if (lane >= B * B) return;
     const int r = lane / B, c = lane % B;
+    const bool rowP = (r == ip), rowT = (!CPR && r == it);
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const double *Bk = A + (size_t)e * B * B;
-        double out = Bk[r * B + c];
-        if (r == ip || (r == it && variant != CPTR_VARIANT_CPR)) {
+        double out;
+        if (rowP || rowT) {
             double hp = Bk[ip * B + c];
-            for (int k = 0; k < ng; ++k) hp = hp - F[k * nrhs + 0] * Bk[grp[k] * B + c];
-            if (r == ip) {
+#pragma unroll
+            for (int k = 0; k < NG; ++k) hp = hp - F[k][0] * Bk[group_index(k, ip, it, CPR) * B + c];
+            if (rowP) {
                 out = hp;
             } else {
                 double ht = Bk[it * B + c];
-                for (int k = 0; k < ng; ++k) ht = ht - F[k * nrhs + 1] * Bk[grp[k] * B + c];
-                out = (variant == CPTR_VARIANT_CPTR3) ? ht - bt * hp : ht;
+#pragma unroll
+                for (int k = 0; k < NG; ++k) ht = ht - F[k][NR - 1] * Bk[group_index(k, ip, it, CPR) * B + c];
+                out = (VAR == CPTR_VARIANT_CPTR3) ? ht - bt * hp : ht;
             }
+        } else {
+            out = Bk[r * B + c];
         }
         abar[(size_t)e * B * B + lane] = out;
+        if (abar32) abar32[(size_t)e * B * B + lane] = (float)out;
+        if (c == it) {
+            if (slabT) slabT[(size_t)e * B + r] = out;
+            if (slabT32) slabT32[(size_t)e * B + r] = (float)out;
+            if (r == it && ctt) ctt[e] = out;
+        }
+        if (c == ip) {
+            if (slabP) slabP[(size_t)e * B + r] = out;
+            if (slabP32) slabP32[(size_t)e * B + r] = (float)out;
+            if (r == ip && bpp) bpp[e] = out;
+        }
     }
 }
 
-void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
-                     double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s) {
+void launch_decouple_extract(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
+                             int it, double *abar, double *wp, double *wt, double *beta, int *err, double *ctt,
+                             double *bpp, double *slabT, double *slabP, float *abar32, float *slabT32,
+                             float *slabP32, hipStream_t s) {
     if (n == 0) return;
-#define CASE(BB) case BB: hipLaunchKernelGGL(k_decouple<BB>, dim3(n), dim3(64), 0, s, variant, n, rp, ci, A, ip, it, abar, wp, wt, beta, err); break;
+#define CASE(BB)                                                                                                  \
+    case BB:                                                                                                      \
+        if (variant == CPTR_VARIANT_CPR)                                                                          \
+            hipLaunchKernelGGL((k_decouple<BB, CPTR_VARIANT_CPR>), dim3(n), dim3(64), 0, s, n, rp, ci, A, ip, it,  \
+                               abar, wp, wt, beta, err, ctt, bpp, slabT, slabP, abar32, slabT32, slabP32);       \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_decouple<BB, CPTR_VARIANT_CPTR3>), dim3(n), dim3(64), 0, s, n, rp, ci, A, ip,    \
+                               it, abar, wp, wt, beta, err, ctt, bpp, slabT, slabP, abar32, slabT32, slabP32);   \
+        break;
     switch (b) {
         CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         default: throw Error(CPTR_E_ARG, "block size must be 2..8");
     }
 #undef CASE
     CPTR_CHECK_LAUNCH();
+}
+
+void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
+                     double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s) {
+    launch_decouple_extract(variant, n, b, rp, ci, A, ip, it, abar, wp, wt, beta, err, nullptr, nullptr, nullptr,
+                            nullptr, nullptr, nullptr, nullptr, s);
 }
 
 // bbar = N^{-1} b for one right-hand side, same order as the rows:

@@ -137,17 +137,25 @@ void kr_mdot(int N, int k, const double *V, size_t ldv, const double *w, double 
     CPTR_CHECK_LAUNCH();
 }
 
-// out[j] = sum_{blk ascending} partial[blk*k + j]
-__global__ void k_reduce(const double *__restrict__ partial, int nblk, int k, double *__restrict__ out) {
-    for (int j = threadIdx.x; j < k; j += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * k + j];
-        out[j] = s;
+// out[j] = sum over blocks of partial[blk*k + j]: one block per output, each
+// thread sums a fixed strided subset, then a fixed-shape tree (deterministic)
+__global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ partial, int nblk, int k,
+                                                double *__restrict__ out) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[(size_t)b * k + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[j] = red[0];
 }
 
 void kr_reduce(const double *partial, int nblk, int k, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, nblk, k, out);
+    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(256), 0, st, partial, nblk, k, out);
     CPTR_CHECK_LAUNCH();
 }
 

@@ -25,7 +25,7 @@ def _t(a, dtype=None):
     return t.cuda() if dtype is None else t.to(dtype).cuda()
 
 
-def _oracle_opts(s, tile=(32, 32), **kw):
+def _oracle_opts(s, tile=(32, 8), **kw):
     amg = O.AMGOptions(**{k[4:]: v for k, v in kw.items() if k.startswith("amg_")})
     rest = {k: v for k, v in kw.items() if not k.startswith("amg_")}
     color = O.tile_colors(s.nx, s.ny, *tile)
@@ -115,8 +115,9 @@ def test_vcycle_parity():
     solver.close()
 
 
-@pytest.mark.parametrize("variant,order,last,tile", [(0, 0, 0, (32, 32)), (0, 1, 0, (8, 4)), (1, 0, 0, (16, 16)),
-                                                     (0, 0, 1, (32, 32)), (3, 0, 0, (5, 3))])
+@pytest.mark.parametrize("variant,order,last,tile", [(0, 0, 0, (32, 8)), (0, 0, 0, (32, 32)), (0, 1, 0, (8, 4)),
+                                                     (1, 0, 0, (16, 16)), (0, 0, 1, (32, 8)), (3, 0, 0, (5, 3)),
+                                                     (0, 0, 0, (37, 21))])
 def test_precond_apply_parity(variant, order, last, tile):
     print(f"case precond variant={variant} order={order} last={last} tile={tile}", flush=True)
     s = tiny(37, 21, 6, peclet=2.0, seed=6)
@@ -137,7 +138,7 @@ def test_precond_apply_parity(variant, order, last, tile):
 # --------------------------------------------------------------------------
 # end-to-end plain FP64 solves
 # --------------------------------------------------------------------------
-def _solve_both(s, tile=(32, 32), **kw):
+def _solve_both(s, tile=(32, 8), **kw):
     ref = O.solve(s, _oracle_opts(s, tile=tile, **kw))
     gkw = dict(kw)
     if "variant" in gkw:
@@ -176,16 +177,18 @@ def test_solve_config2(index):
     _assert_parity(ref, x, res)
 
 
-@pytest.mark.parametrize("case", ["b2", "ragged_tiles", "single_level", "bjacobi", "cpr", "p_then_t", "restart5",
+@pytest.mark.parametrize("case", ["b2", "ragged_tiles", "big_tiles", "single_level", "bjacobi", "cpr", "p_then_t", "restart5",
                                   "l1jacobi", "sweeps2"])
 def test_solve_variants(case):
     print(f"case solve variant {case}", flush=True)
-    kw, tile = {}, (32, 32)
+    kw, tile = {}, (32, 8)
     s = tiny(45, 29, 6, peclet=1.0, seed=12)
     if case == "b2":
         s = tiny(40, 30, 2, peclet=1.0, seed=13)
     elif case == "ragged_tiles":
         tile = (7, 5)
+    elif case == "big_tiles":
+        tile = (32, 32)
     elif case == "single_level":
         kw["amg_max_coarse"] = 5000
     elif case == "bjacobi":
