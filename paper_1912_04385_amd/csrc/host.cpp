@@ -9,7 +9,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <exception>
 #include <memory>
+#include <thread>
 #include <string>
 #include <type_traits>
 #include <utility>
@@ -24,6 +26,19 @@ static thread_local std::string g_last_error;
 static void set_error(const std::string &m) { g_last_error = m; }
 
 constexpr int MAX_COARSE_DENSE = 8192;
+
+// per-hierarchy setup state: each AMG hierarchy is built on its own stream
+// (and host thread) with its own scratch and flag word
+struct Builder {
+    hipStream_t stream = nullptr;
+    cptr_options opt{};
+    int n = 0, nnzb = 0;
+    struct { const int *p = nullptr; } rp, ci;
+    DBuf<int> s_i1, s_i2, s_i3, s_i4, flag;
+    DBuf<double> s_d1;
+    DBuf<uint64_t> s_u1;
+    DBuf<unsigned char> s_c1;
+};
 
 struct cptr_ctx {
     int device = 0;
@@ -60,6 +75,10 @@ struct cptr_ctx {
     double last_setup_ms = 0.0;
     // per-step stage timing (options.timing)
     hipEvent_t tev[6] = {};
+    // concurrent hierarchy builds
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t ev_dec = nullptr, ev_side[2] = {nullptr, nullptr};
+    Builder bld[2];
     double tacc[5] = {};
     int tsteps = 0;
 
@@ -70,6 +89,18 @@ struct cptr_ctx {
     ~cptr_ctx() {
         for (auto &e : tev)
             if (e) (void)hipEventDestroy(e);
+        for (int k = 0; k < 2; ++k) {
+            if (side[k]) {
+                (void)hipStreamSynchronize(side[k]);
+                for (auto *h : {&H[k]}) h->L.clear();
+                bld[k].~Builder();
+                new (&bld[k]) Builder();
+                pool_trim(side[k]);
+                (void)hipStreamDestroy(side[k]);
+            }
+            if (ev_side[k]) (void)hipEventDestroy(ev_side[k]);
+        }
+        if (ev_dec) (void)hipEventDestroy(ev_dec);
         if (hinfo_host) (void)hipHostFree(hinfo_host);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -93,6 +124,12 @@ static int read_flag_and_clear(cptr_ctx *c) {
     return f;
 }
 
+static int read_flag_and_clear(Builder *c) {
+    int f = read_scalar(c->flag.p, c->stream);
+    fill_int(c->flag.p, 0, 1, c->stream);
+    return f;
+}
+
 static int scan_total(const int *in, int *out, int n, hipStream_t s) {
     scan_exclusive(in, out, n, nullptr, s);
     return read_scalar(out + n, s);
@@ -101,7 +138,7 @@ static int scan_total(const int *in, int *out, int n, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // AMG hierarchy (setup)
 // ---------------------------------------------------------------------------
-static void csr_spgemm(cptr_ctx *c, const CsrD &A, const CsrD &B, CsrD &C) {
+static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
     hipStream_t s = c->stream;
     const int m = A.n;
     c->s_i1.alloc((size_t)m + 1);
@@ -127,7 +164,7 @@ static void csr_spgemm(cptr_ctx *c, const CsrD &A, const CsrD &B, CsrD &C) {
     CPTR_HIP(hipStreamSynchronize(s));
 }
 
-static void csr_transpose(cptr_ctx *c, const CsrD &P, CsrD &R) {
+static void csr_transpose(Builder *c, const CsrD &P, CsrD &R) {
     hipStream_t s = c->stream;
     R.n = P.ncols;
     R.ncols = P.n;
@@ -154,7 +191,7 @@ static void level_vectors(Level &L, int n, bool fp32) {
 
 // Build the hierarchy of a scalar operator whose level-0 pattern is the BSR
 // pattern (rp, ci owned by the context) and whose values are `vals` (copied).
-static void build_hierarchy(cptr_ctx *c, Hierarchy &h, const double *vals) {
+static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     const bool fp32 = (o.precond_precision == CPTR_FP32);
@@ -329,10 +366,17 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl) {
     Level &Ln = h.L[lvl + 1];
     vc_spmv<T>(L.R.n, L.R.rp, L.R.ci, Prec<T>::v(L.R), r, Prec<T>::b(Ln), s);
     T *xc = vcycle<T>(c, h, lvl + 1);
-    vc_prolong_add<T>(n, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, s);
-    for (int k = 0; k < o.post_sweeps; ++k) {
-        vc_smooth<T>(n, L.A.rp, L.A.ci, v, dinv, omega, b, 1, 0, x, tmp, s);
+    if (o.post_sweeps == 0) {
+        vc_prolong_add<T>(n, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, s);
+    } else {
+        // prolong into the spare buffer so that an odd number of Jacobi sweeps
+        // ends in x without a copy
+        vc_prolong_to<T>(n, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, tmp, s);
         std::swap(x, tmp);
+        for (int k = 0; k < o.post_sweeps; ++k) {
+            vc_smooth<T>(n, L.A.rp, L.A.ci, v, dinv, omega, b, 1, 0, x, tmp, s);
+            std::swap(x, tmp);
+        }
     }
     if (x != Prec<T>::x(L)) {
         CPTR_HIP(hipMemcpyAsync(Prec<T>::x(L), x, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
@@ -449,9 +493,43 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
     int bad = read_scalar(c->s_i4.p, s);
     if (bad != 0x7fffffff)
         throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block (D_ss or Ahat_PP) in cell " + std::to_string(bad));
-    // scalar stages
-    if (c->opt.variant == CPTR_VARIANT_CPTR3) build_hierarchy(c, c->H[0], ctt.p);
-    if (c->opt.variant == CPTR_VARIANT_CPTR3 || c->opt.variant == CPTR_VARIANT_CPR) build_hierarchy(c, c->H[1], bpp.p);
+    // scalar stages: the two hierarchies are built concurrently, each on its
+    // own stream and host thread, while this stream factors the last stage
+    const bool need[2] = {c->opt.variant == CPTR_VARIANT_CPTR3,
+                          c->opt.variant == CPTR_VARIANT_CPTR3 || c->opt.variant == CPTR_VARIANT_CPR};
+    const double *svals[2] = {ctt.p, bpp.p};
+    CPTR_HIP(hipEventRecord(c->ev_dec, s));
+    std::exception_ptr err[2];
+    std::thread th[2];
+    for (int k = 0; k < 2; ++k) {
+        if (!need[k]) continue;
+        Builder &B = c->bld[k];
+        B.stream = c->side[k];
+        B.opt = c->opt;
+        B.n = n;
+        B.nnzb = nnzb;
+        B.rp.p = c->rp.p;
+        B.ci.p = c->ci.p;
+        th[k] = std::thread([c, k, &B, &svals, &err]() {
+            try {
+                CPTR_HIP(hipSetDevice(c->device));
+                StreamScope scope(B.stream);
+                if (!B.flag.p) {
+                    B.flag.alloc(4);
+                    fill_int(B.flag.p, 0, 1, B.stream);
+                }
+                CPTR_HIP(hipStreamWaitEvent(B.stream, c->ev_dec, 0));
+                build_hierarchy(&B, c->H[k], svals[k]);
+                CPTR_HIP(hipEventRecord(c->ev_side[k], B.stream));
+            } catch (...) {
+                err[k] = std::current_exception();
+            }
+        });
+    }
+    struct Joiner {
+        std::thread *t;
+        ~Joiner() { for (int k = 0; k < 2; ++k) if (t[k].joinable()) t[k].join(); }
+    } joiner{th};
     // last stage
     c->dinv.alloc((size_t)n * b * b);
     fill_int(c->s_i4.p, 0x7fffffff, 1, s);
@@ -462,6 +540,12 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
         bj_factor_cells(n, b, c->rp.p, c->ci.p, c->abar.p, c->dinv.p, c->s_i4.p, nullptr, s);
     }
     bad = read_scalar(c->s_i4.p, s);
+    for (int k = 0; k < 2; ++k)
+        if (th[k].joinable()) th[k].join();
+    for (int k = 0; k < 2; ++k)
+        if (err[k]) std::rethrow_exception(err[k]);
+    for (int k = 0; k < 2; ++k)
+        if (need[k]) CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[k], 0));
     if (bad != 0x7fffffff)
         throw Error(CPTR_E_SINGULAR_BLOCK, "singular ILU pivot block in cell " + std::to_string(bad));
     if (fp32) {
@@ -675,6 +759,11 @@ cptr_status cptr_create(cptr_ctx **out, int32_t dev, void *stream, const cptr_op
     CPTR_HIP(hipEventCreate(&c->ev0));
     CPTR_HIP(hipEventCreate(&c->ev1));
     for (auto &e : c->tev) CPTR_HIP(hipEventCreate(&e));
+    CPTR_HIP(hipEventCreateWithFlags(&c->ev_dec, hipEventDisableTiming));
+    for (int k = 0; k < 2; ++k) {
+        CPTR_HIP(hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));   // default priority
+        CPTR_HIP(hipEventCreateWithFlags(&c->ev_side[k], hipEventDisableTiming));
+    }
     CPTR_HIP(hipStreamSynchronize(c->stream));
     *out = c.release();
     return CPTR_OK;

@@ -179,6 +179,9 @@ void vc_spmv(int n, const int *rp, const int *ci, const T *v, const T *x, T *y, 
 template <class T>
 void vc_prolong_add(int n, const int *rp, const int *ci, const T *v, const T *xc, T *x, hipStream_t st);
 template <class T>
+void vc_prolong_to(int n, const int *rp, const int *ci, const T *v, const T *xc, const T *xin, T *xout,
+                   hipStream_t st);
+template <class T>
 void vc_smooth(int n, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b, int bstride,
                int boff, const T *xin, T *xout, hipStream_t st);
 template <class T>

@@ -177,11 +177,11 @@ __device__ inline double csr_value(const int *rp, const int *ci, const double *v
     return 0.0;
 }
 
-__device__ inline bool in_sorted(const int *a, int len, int key) {
+__device__ inline bool in_sorted(const int *a, int stride, int len, int key) {
     int lo = 0, hi = len - 1;
     while (lo <= hi) {
         int mid = (lo + hi) >> 1;
-        int c = a[mid];
+        int c = a[mid * stride];
         if (c == key) return true;
         if (c < key) lo = mid + 1; else hi = mid - 1;
     }
@@ -197,40 +197,35 @@ __device__ inline bool in_sorted(const int *a, int len, int key) {
 //   w_ij     = -num_j / atilde
 //   truncation to the pmax largest |w| (ties: lower column), kept weights times
 //   (sum of all w) / (sum of kept w), both sums in ascending column order.
-__global__ void k_exti_compute(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                               const double *__restrict__ v, const unsigned char *__restrict__ s,
-                               const int *__restrict__ cf, const int *__restrict__ cidx, const double *__restrict__ dg,
-                               int pmax, const int *__restrict__ off, int *__restrict__ tcol,
-                               double *__restrict__ tw, double *__restrict__ td, int *__restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int *hat = tcol + off[i];
-    double *w = tw + off[i];
-    if (cf[i] == ST_C) {
-        hat[0] = cidx[i];
-        w[0] = 1.0;
-        cnt[i] = 1;
-        return;
-    }
+// The interpolatory set lives in LDS (interleaved across the block) when its
+// bound fits EXT_CAP entries, else in the row's global scratch segment.
+constexpr int EXT_T = 128;
+constexpr int EXT_CAP = 32;
+
+__device__ inline void exti_row(int i, const int *__restrict__ rp, const int *__restrict__ ci,
+                                const double *__restrict__ v, const unsigned char *__restrict__ s,
+                                const int *__restrict__ cf, const int *__restrict__ cidx,
+                                const double *__restrict__ dg, int pmax, int *hat, int hs, double *w,
+                                double *__restrict__ td, int *ocol, int *cnt) {
     const int a = rp[i], b = rp[i + 1];
     // gather Chat_i (fine indices), sort, unique
     int nh = 0;
     for (int e = a; e < b; ++e) {
         if (!s[e]) continue;
         int j = ci[e];
-        if (cf[j] == ST_C) { hat[nh++] = j; continue; }
+        if (cf[j] == ST_C) { hat[(nh++) * hs] = j; continue; }
         for (int f = rp[j]; f < rp[j + 1]; ++f)
-            if (s[f] && cf[ci[f]] == ST_C) hat[nh++] = ci[f];
+            if (s[f] && cf[ci[f]] == ST_C) hat[(nh++) * hs] = ci[f];
     }
     if (nh == 0) { cnt[i] = 0; return; }
     for (int p = 1; p < nh; ++p) {
-        int t = hat[p], q = p - 1;
-        while (q >= 0 && hat[q] > t) { hat[q + 1] = hat[q]; --q; }
-        hat[q + 1] = t;
+        int t = hat[p * hs], q = p - 1;
+        while (q >= 0 && hat[q * hs] > t) { hat[(q + 1) * hs] = hat[q * hs]; --q; }
+        hat[(q + 1) * hs] = t;
     }
     int u = 1;
     for (int p = 1; p < nh; ++p)
-        if (hat[p] != hat[u - 1]) hat[u++] = hat[p];
+        if (hat[p * hs] != hat[(u - 1) * hs]) hat[(u++) * hs] = hat[p * hs];
     nh = u;
     // d_k of every strong F neighbour, stored at the neighbour's entry position
     for (int e = a; e < b; ++e) {
@@ -240,7 +235,7 @@ __global__ void k_exti_compute(int n, const int *__restrict__ rp, const int *__r
         double d = 0.0;
         for (int f = rp[k]; f < rp[k + 1]; ++f) {
             int l = ci[f];
-            if (l == i || (l != k && cf[l] == ST_C && in_sorted(hat, nh, l))) {
+            if (l == i || (l != k && cf[l] == ST_C && in_sorted(hat, hs, nh, l))) {
                 double ab = abar_of(akk, v[f]);
                 if (ab != 0.0) d = d + ab;
             }
@@ -260,13 +255,13 @@ __global__ void k_exti_compute(int n, const int *__restrict__ rp, const int *__r
             } else {
                 at = at + v[e];
             }
-        } else if (!s[e] && !(cf[nn] == ST_C && in_sorted(hat, nh, nn))) {
+        } else if (!s[e] && !(cf[nn] == ST_C && in_sorted(hat, hs, nh, nn))) {
             at = at + v[e];
         }
     }
     if (at == 0.0) { cnt[i] = 0; return; }
     for (int p = 0; p < nh; ++p) {
-        const int j = hat[p];
+        const int j = hat[p * hs];
         double num = csr_value(rp, ci, v, i, j);
         for (int e = a; e < b; ++e) {
             int k = ci[e];
@@ -286,35 +281,61 @@ __global__ void k_exti_compute(int n, const int *__restrict__ rp, const int *__r
             int best = -1;
             double bv = 0.0;
             for (int p = 0; p < nh; ++p) {
-                if (hat[p] < 0) continue;
+                if (hat[p * hs] < 0) continue;
                 double av = fabs(w[p]);
                 if (best < 0 || av > bv) { best = p; bv = av; }
             }
-            hat[best] = -1 - hat[best];
+            hat[best * hs] = -1 - hat[best * hs];
         }
         double sall = 0.0, skept = 0.0;
         for (int p = 0; p < nh; ++p) sall = sall + w[p];
-        for (int p = 0; p < nh; ++p) if (hat[p] < 0) skept = skept + w[p];
+        for (int p = 0; p < nh; ++p) if (hat[p * hs] < 0) skept = skept + w[p];
         const double scale = (skept != 0.0) ? sall / skept : 1.0;
         int q = 0;
         for (int p = 0; p < nh; ++p) {
-            if (hat[p] >= 0) continue;
-            int col = -1 - hat[p];
+            if (hat[p * hs] >= 0) continue;
+            int col = -1 - hat[p * hs];
             double wv = (skept != 0.0) ? w[p] * scale : w[p];
-            hat[q] = col;
+            hat[q * hs] = col;
             w[q] = wv;
             q++;
         }
         keep = pmax;
     }
-    for (int p = 0; p < keep; ++p) hat[p] = cidx[hat[p]];
+    for (int p = 0; p < keep; ++p) ocol[p] = cidx[hat[p * hs]];
     cnt[i] = keep;
+}
+
+__global__ void __launch_bounds__(EXT_T) k_exti_compute(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                        const double *__restrict__ v,
+                                                        const unsigned char *__restrict__ s,
+                                                        const int *__restrict__ cf, const int *__restrict__ cidx,
+                                                        const double *__restrict__ dg, int pmax,
+                                                        const int *__restrict__ off, int *__restrict__ tcol,
+                                                        double *__restrict__ tw, double *__restrict__ td,
+                                                        int *__restrict__ cnt) {
+    __shared__ int shat[EXT_CAP * EXT_T];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int *ocol = tcol + off[i];
+    double *w = tw + off[i];
+    if (cf[i] == ST_C) {
+        ocol[0] = cidx[i];
+        w[0] = 1.0;
+        cnt[i] = 1;
+        return;
+    }
+    const int ub = off[i + 1] - off[i];
+    if (ub <= EXT_CAP)
+        exti_row(i, rp, ci, v, s, cf, cidx, dg, pmax, shat + threadIdx.x, EXT_T, w, td, ocol, cnt);
+    else
+        exti_row(i, rp, ci, v, s, cf, cidx, dg, pmax, ocol, 1, w, td, ocol, cnt);
 }
 
 void amg_exti_compute2(int n, const int *rp, const int *ci, const double *v, const unsigned char *s, const int *cf,
                        const int *cidx, const double *dg, int pmax, const int *off, int *tcol, double *tw,
                        double *td, int *cnt, hipStream_t st) {
-    hipLaunchKernelGGL(k_exti_compute, dim3(blocks_for(n, 128)), dim3(128), 0, st, n, rp, ci, v, s, cf, cidx, dg,
+    hipLaunchKernelGGL(k_exti_compute, dim3(blocks_for(n, EXT_T)), dim3(EXT_T), 0, st, n, rp, ci, v, s, cf, cidx, dg,
                        pmax, off, tcol, tw, td, cnt);
     CPTR_CHECK_LAUNCH();
 }
@@ -405,17 +426,19 @@ void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int
     CPTR_CHECK_LAUNCH();
 }
 
-__global__ void k_spgemm_compute(int m, const int *__restrict__ arp, const int *__restrict__ aci,
-                                 const double *__restrict__ av, const int *__restrict__ brp,
-                                 const int *__restrict__ bci, const double *__restrict__ bv,
-                                 const int *__restrict__ off, int *__restrict__ tcol, double *__restrict__ tval,
-                                 int *__restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const int cap = off[i + 1] - off[i];
-    int *hk = tcol + off[i];
-    double *hv = tval + off[i];
-    for (int p = 0; p < cap; ++p) hk[p] = -1;
+// One thread per output row.  The accumulator is an open-addressing hash
+// table filled strictly in A's row order, so every output entry sums its
+// terms in ascending k starting from the first term.  Rows whose table fits
+// (capacity <= SPG_CAP) keep it in LDS, interleaved across the block's
+// threads; longer rows use their segment of the global scratch.
+constexpr int SPG_T = 64;
+constexpr int SPG_CAP = 48;
+
+__device__ inline void spgemm_row(int i, const int *__restrict__ arp, const int *__restrict__ aci,
+                                  const double *__restrict__ av, const int *__restrict__ brp,
+                                  const int *__restrict__ bci, const double *__restrict__ bv, int *hk, double *hv,
+                                  int stride, int cap, int *ok, double *ov, int *cnt) {
+    for (int p = 0; p < cap; ++p) hk[p * stride] = -1;
     for (int e = arp[i]; e < arp[i + 1]; ++e) {
         const int k = aci[e];
         const double a = av[e];
@@ -424,39 +447,64 @@ __global__ void k_spgemm_compute(int m, const int *__restrict__ arp, const int *
             const double t = a * bv[f];
             unsigned hsh = ((unsigned)j * 2654435761u) % (unsigned)cap;
             while (true) {
-                int key = hk[hsh];
-                if (key == -1) { hk[hsh] = j; hv[hsh] = t; break; }
-                if (key == j) { hv[hsh] = hv[hsh] + t; break; }
+                const int key = hk[hsh * stride];
+                if (key == -1) { hk[hsh * stride] = j; hv[hsh * stride] = t; break; }
+                if (key == j) { hv[hsh * stride] = hv[hsh * stride] + t; break; }
                 hsh = (hsh + 1 == (unsigned)cap) ? 0u : hsh + 1;
             }
         }
     }
-    // compact the occupied slots to the front, then sort by column
+    // compact the occupied slots to the front, sort by column, write out
     int u = 0;
     for (int p = 0; p < cap; ++p) {
-        if (hk[p] < 0) continue;
-        int c = hk[p];
-        double x = hv[p];
-        hk[u] = c;
-        hv[u] = x;
+        const int c = hk[p * stride];
+        if (c < 0) continue;
+        const double x = hv[p * stride];
+        hk[u * stride] = c;
+        hv[u * stride] = x;
         u++;
     }
     for (int p = 1; p < u; ++p) {
-        int c = hk[p];
-        double x = hv[p];
+        const int c = hk[p * stride];
+        const double x = hv[p * stride];
         int q = p - 1;
-        while (q >= 0 && hk[q] > c) { hk[q + 1] = hk[q]; hv[q + 1] = hv[q]; --q; }
-        hk[q + 1] = c;
-        hv[q + 1] = x;
+        while (q >= 0 && hk[q * stride] > c) {
+            hk[(q + 1) * stride] = hk[q * stride];
+            hv[(q + 1) * stride] = hv[q * stride];
+            --q;
+        }
+        hk[(q + 1) * stride] = c;
+        hv[(q + 1) * stride] = x;
     }
+    if (ok != hk)
+        for (int p = 0; p < u; ++p) { ok[p] = hk[p * stride]; ov[p] = hv[p * stride]; }
     cnt[i] = u;
+}
+
+__global__ void __launch_bounds__(SPG_T) k_spgemm_compute(int m, const int *__restrict__ arp,
+                                                          const int *__restrict__ aci, const double *__restrict__ av,
+                                                          const int *__restrict__ brp, const int *__restrict__ bci,
+                                                          const double *__restrict__ bv, const int *__restrict__ off,
+                                                          int *__restrict__ tcol, double *__restrict__ tval,
+                                                          int *__restrict__ cnt) {
+    __shared__ int sk[SPG_CAP * SPG_T];
+    __shared__ double sv[SPG_CAP * SPG_T];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int cap = off[i + 1] - off[i];
+    int *ok = tcol + off[i];
+    double *ov = tval + off[i];
+    if (cap <= SPG_CAP)
+        spgemm_row(i, arp, aci, av, brp, bci, bv, sk + threadIdx.x, sv + threadIdx.x, SPG_T, cap, ok, ov, cnt);
+    else
+        spgemm_row(i, arp, aci, av, brp, bci, bv, ok, ov, 1, cap, ok, ov, cnt);
 }
 
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
                         const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_spgemm_compute, dim3(blocks_for(m, 64)), dim3(64), 0, st, m, arp, aci, av, brp, bci, bv,
-                       off, tcol, tval, cnt);
+    hipLaunchKernelGGL(k_spgemm_compute, dim3(blocks_for(m, SPG_T)), dim3(SPG_T), 0, st, m, arp, aci, av, brp, bci,
+                       bv, off, tcol, tval, cnt);
     CPTR_CHECK_LAUNCH();
 }
 

@@ -160,28 +160,13 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_final(const int *in, int 
     }
 }
 
-// scratch for the block sums: grown on demand and kept for the life of the
-// process (one small allocation per device; never freed so that no HIP call
-// runs during static destruction)
-static int *g_scan_scratch[64];
-static size_t g_scan_cap[64];
-
+// the block sums live in a pooled buffer of the calling stream
 void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t s) {
     int nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb < 1) nb = 1;
-    int dev = 0;
-    CPTR_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) throw Error(CPTR_E_ARG, "device index out of range");
-    if ((size_t)nb > g_scan_cap[dev]) {
-        CPTR_HIP(hipStreamSynchronize(s));
-        if (g_scan_scratch[dev]) CPTR_HIP(hipFree(g_scan_scratch[dev]));
-        g_scan_scratch[dev] = nullptr;
-        g_scan_cap[dev] = 0;
-        size_t cap = (size_t)nb * 2 + 64;
-        CPTR_HIP(hipMalloc((void **)&g_scan_scratch[dev], cap * sizeof(int)));
-        g_scan_cap[dev] = cap;
-    }
-    int *bsum = g_scan_scratch[dev];
+    DBuf<int> scratch;
+    scratch.alloc((size_t)nb + 1);
+    int *bsum = scratch.p;
     hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, bsum);
     int *tot = total_dev ? total_dev : out + n;
     hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(SCAN_THREADS), 0, s, bsum, nb, tot);

@@ -55,21 +55,29 @@ void vc_spmv(int n, const int *rp, const int *ci, const T *v, const T *x, T *y, 
     CPTR_CHECK_LAUNCH();
 }
 
-// x += P xc
+// xout = xin + P xc (xout may alias xin)
 template <class T>
 __global__ void k_prolong_add(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                              const T *__restrict__ v, const T *__restrict__ xc, T *__restrict__ x) {
+                              const T *__restrict__ v, const T *__restrict__ xc, const T *xin, T *xout) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    T acc = x[i];
+    T acc = xin[i];
     for (int e = rp[i]; e < rp[i + 1]; ++e) acc += v[e] * xc[ci[e]];
-    x[i] = acc;
+    xout[i] = acc;
 }
 
 template <class T>
 void vc_prolong_add(int n, const int *rp, const int *ci, const T *v, const T *xc, T *x, hipStream_t st) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, xc, x);
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, xc, x, x);
+    CPTR_CHECK_LAUNCH();
+}
+
+template <class T>
+void vc_prolong_to(int n, const int *rp, const int *ci, const T *v, const T *xc, const T *xin, T *xout,
+                   hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, xc, xin, xout);
     CPTR_CHECK_LAUNCH();
 }
 
@@ -180,6 +188,8 @@ void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *slab, i
                                            int, T *, T *, hipStream_t);                                          \
     template void vc_spmv<T>(int, const int *, const int *, const T *, const T *, T *, hipStream_t);             \
     template void vc_prolong_add<T>(int, const int *, const int *, const T *, const T *, T *, hipStream_t);      \
+    template void vc_prolong_to<T>(int, const int *, const int *, const T *, const T *, const T *, T *,          \
+                                   hipStream_t);                                                                 \
     template void vc_smooth<T>(int, const int *, const int *, const T *, const T *, T, const T *, int, int,        \
                                const T *, T *, hipStream_t);                                                     \
     template void vc_residual<T>(int, const int *, const int *, const T *, const T *, const T *, T *,            \

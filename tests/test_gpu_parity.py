@@ -270,3 +270,34 @@ def test_zero_rhs_returns_zero():
     x, res = solver.solve(torch.zeros(s.n * s.b, dtype=torch.float64, device="cuda"))
     assert res["iterations"] == 0 and float(x.abs().max()) == 0.0
     solver.close()
+
+
+# --------------------------------------------------------------------------
+# precision-split preconditioner (FP32 inside FP64 flexible GMRES)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("index", [0, 3])
+def test_fp32_preconditioner_fgmres(index):
+    """The FP32 preconditioner must still reach the FP64 true residual 1e-8;
+    the solution agrees with the FP64 oracle to the accuracy the tolerance
+    allows (bounded by cond(Abar) * 1e-8; asserted at 1e-6 here)."""
+    print(f"case fp32 fgmres c2-{index}", flush=True)
+    s = config2(index)
+    ref = O.solve(s, _oracle_opts(s, krylov=O.FGMRES, restart=50))
+    solver = cptr.solver_for(s, krylov=cptr.FGMRES, restart=50, precond_precision=cptr.FP32)
+    x, res = solver.solve(_t(s.rhs))
+    solver.close()
+    x = x.cpu().numpy()
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    print(f"  fp32 its={res['iterations']} fp64 oracle its={ref.iterations} rel_res={res['rel_res_scaled']:.2e} "
+          f"err={err:.2e}", flush=True)
+    assert res["converged"] == 1 and res["rel_res_scaled"] <= 1e-8
+    assert res["iterations"] <= ref.iterations + 3
+    assert err <= 1e-6
+    # the true residual is recomputed in FP64 from x
+    r = s.rhs - O.bsr_of(s).matvec(x)
+    assert np.linalg.norm(r) / np.linalg.norm(s.rhs) <= 2e-8
+
+
+def test_fp32_needs_fgmres():
+    with pytest.raises(cptr.CptrError):
+        cptr.Solver(precond_precision=cptr.FP32, krylov=cptr.GMRES)
