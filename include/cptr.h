@@ -89,6 +89,9 @@ typedef struct {
     double  reuse_rho_max;      /* hierarchy reuse threshold for update_values    */
     int32_t timing;             /* 1: time every stage of every Arnoldi step with */
                                 /*    HIP events on the solve stream              */
+    int32_t setup_kernels;      /* AMG setup row kernels: 0 by row length, 1 one  */
+                                /* wavefront per row, 2 one thread per row (the   */
+                                /* hierarchy is bit-identical either way)         */
 } cptr_options;
 
 typedef struct {

@@ -7,8 +7,10 @@ using a Solver does, and fails loudly when the library is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcptr.so")
@@ -40,7 +42,7 @@ class Options(ctypes.Structure):
         ("amg_pmax", ctypes.c_int32), ("smoother", ctypes.c_int32), ("pre_sweeps", ctypes.c_int32),
         ("post_sweeps", ctypes.c_int32), ("jacobi_omega", ctypes.c_double), ("pmis_seed", ctypes.c_uint64),
         ("ilu_tile_x", ctypes.c_int32), ("ilu_tile_y", ctypes.c_int32), ("t_interp", ctypes.c_int32),
-        ("reuse_rho_max", ctypes.c_double), ("timing", ctypes.c_int32),
+        ("reuse_rho_max", ctypes.c_double), ("timing", ctypes.c_int32), ("setup_kernels", ctypes.c_int32),
     ]
 
 
@@ -129,15 +131,29 @@ def _dev(t, dtype):
     return t.to(device="cuda", dtype=dtype).contiguous()
 
 
+_live_solvers = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Destroy every live context while the HIP runtime is certainly up."""
+    for s in list(_live_solvers):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One context of the C library: setup() once per matrix, solve() per rhs."""
 
     def __init__(self, device: int = 0, **opts):
         import torch
-        self.opts = default_options(**opts)
         self.ctx = ctypes.c_void_p()
+        self.opts = default_options(**opts)
         torch.cuda.set_device(device)
         _check(lib().cptr_create(ctypes.byref(self.ctx), device, _stream(), ctypes.byref(self.opts)))
+        _live_solvers.add(self)
         self.n = self.b = 0
 
     def setup(self, row_ptr, col_idx, vals, p_index: int = 0, T_index: int = 1, nx: int = 0, ny: int = 0):
@@ -266,6 +282,10 @@ def solver_for(system, **opts) -> Solver:
     """Solver set up on a generated system (cell c = x + nx*y on an nx x ny grid)."""
     import torch
     s = Solver(**opts)
-    s.setup(torch.from_numpy(system.row_ptr), torch.from_numpy(system.col_idx),
-            torch.from_numpy(system.vals.reshape(-1)), 0, 1, system.nx, system.ny)
+    try:
+        s.setup(torch.from_numpy(system.row_ptr), torch.from_numpy(system.col_idx),
+                torch.from_numpy(system.vals.reshape(-1)), 0, 1, system.nx, system.ny)
+    except Exception:
+        s.close()
+        raise
     return s

@@ -150,7 +150,13 @@ static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
     DBuf<double> hv;
     hk.alloc((size_t)cap);
     hv.alloc((size_t)cap);
-    amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
+    // short rows: one thread per row; long rows (coarse levels): one wavefront per row
+    const double avg_products = (double)(cap - m) / (2.0 * (m > 0 ? m : 1));
+    const int sk = c->opt.setup_kernels;
+    if (sk == 2 || (sk == 0 && avg_products <= 24.0))
+        amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
+    else
+        amg_spgemm_compute_wave(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
     C.n = m;
     C.ncols = B.ncols;
     C.rp_own.alloc((size_t)m + 1);
@@ -254,8 +260,13 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
         tcol.alloc(cap);
         twt.alloc(cap);
         td.alloc((size_t)L.A.nnz + 1);
-        amg_exti_compute2(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
-                          tcol.p, twt.p, td.p, cnt.p, s);
+        // short rows: one thread per row; long rows (coarse levels): one wavefront per row
+        if (o.setup_kernels == 2 || (o.setup_kernels == 0 && (double)cap / m <= 12.0))
+            amg_exti_compute2(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
+                              tcol.p, twt.p, td.p, cnt.p, s);
+        else
+            amg_exti_compute_wave(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax,
+                                  off.p, tcol.p, twt.p, td.p, cnt.p, s);
         CsrD &P = L.P;
         P.n = m;
         P.ncols = nc;
@@ -736,6 +747,7 @@ cptr_status cptr_default_options(cptr_options *o) {
     o->t_interp = CPTR_INTERP_CLASSICAL;
     o->reuse_rho_max = 0.3;
     o->timing = 0;
+    o->setup_kernels = 0;
     return CPTR_OK;
 }
 

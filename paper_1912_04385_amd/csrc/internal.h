@@ -158,6 +158,9 @@ void amg_exti_bound(int n, const int *rp, const int *ci, const unsigned char *s,
 void amg_exti_compute2(int n, const int *rp, const int *ci, const double *v, const unsigned char *s, const int *cf,
                        const int *cidx, const double *dg, int pmax, const int *off, int *tcol, double *tw,
                        double *td, int *cnt, hipStream_t st);
+void amg_exti_compute_wave(int n, const int *rp, const int *ci, const double *v, const unsigned char *s,
+                           const int *cf, const int *cidx, const double *dg, int pmax, const int *off, int *tcol,
+                           double *tw, double *td, int *cnt, hipStream_t st);
 void amg_compact(int n, const int *off, const int *tcol, const double *tw, const int *prp, int *pci, double *pv,
                  hipStream_t st);
 void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v, int *rpT, int *ciT, double *vT,
@@ -165,6 +168,8 @@ void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v
 void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, hipStream_t st);
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
                         const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
+void amg_spgemm_compute_wave(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
+                             const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
 void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
                    int *flag, hipStream_t st);
 void amg_dense_inverse(int n, const int *rp, const int *ci, const double *v, double *aug, int *used, int *pivrow,

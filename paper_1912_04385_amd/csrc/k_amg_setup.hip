@@ -10,6 +10,8 @@
 // (one thread owns each row; no floating-point atomics anywhere).
 #include "internal.h"
 
+#include <algorithm>
+
 namespace cptr {
 
 static inline int blocks_for(long n, int t) { return (int)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
@@ -332,6 +334,222 @@ __global__ void __launch_bounds__(EXT_T) k_exti_compute(int n, const int *__rest
         exti_row(i, rp, ci, v, s, cf, cidx, dg, pmax, ocol, 1, w, td, ocol, cnt);
 }
 
+// One wavefront per row for coarse levels (long rows).  Same definition and
+// evaluation order as exti_row: the candidate set is expanded and stably
+// ranked in LDS, d_k is computed per strong F neighbour by one lane each (row
+// k in ascending order), atilde is summed by one lane over row i in ascending
+// order, each numerator by one lane over the strong F neighbours in row order,
+// and the truncation picks the largest |w| (ties: lower column) round by
+// round.  Rows beyond the LDS capacities fall back to exti_row on lane 0.
+constexpr int EXW_CAP = 1024;
+constexpr int EXW_ROW = 256;
+
+__global__ void __launch_bounds__(64) k_exti_wave(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                  const double *__restrict__ v, const unsigned char *__restrict__ s,
+                                                  const int *__restrict__ cf, const int *__restrict__ cidx,
+                                                  const double *__restrict__ dg, int pmax,
+                                                  const int *__restrict__ off, int *__restrict__ tcol,
+                                                  double *__restrict__ tw, double *__restrict__ td,
+                                                  int *__restrict__ cnt) {
+    __shared__ int cand[EXW_CAP];
+    __shared__ int hat[EXW_CAP];
+    __shared__ double w[EXW_CAP];
+    __shared__ double dk[EXW_ROW];
+    __shared__ double term[EXW_ROW];
+    __shared__ unsigned char use[EXW_ROW];
+    __shared__ unsigned char kept[EXW_CAP];
+    __shared__ double at_s;
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (i >= n) return;
+    int *ocol = tcol + off[i];
+    double *ow = tw + off[i];
+    if (cf[i] == ST_C) {
+        if (lane == 0) { ocol[0] = cidx[i]; ow[0] = 1.0; cnt[i] = 1; }
+        return;
+    }
+    const int a = rp[i], b = rp[i + 1];
+    const int ub = off[i + 1] - off[i];
+    if (ub > EXW_CAP || b - a > EXW_ROW) {
+        if (lane == 0) exti_row(i, rp, ci, v, s, cf, cidx, dg, pmax, ocol, 1, ow, td, ocol, cnt);
+        return;
+    }
+    // 1. candidates with repeats, in row order
+    int nc = 0;
+    for (int e = a; e < b; ++e) {
+        if (!s[e]) continue;
+        const int j = ci[e];
+        if (cf[j] == ST_C) {
+            if (lane == 0) cand[nc] = j;
+            nc += 1;
+            continue;
+        }
+        const int f0 = rp[j], len = rp[j + 1] - f0;
+        for (int q0 = 0; q0 < len; q0 += 64) {
+            const int f = f0 + q0 + lane;
+            const bool take = (q0 + lane < len) && s[f] && cf[ci[f]] == ST_C;
+            const unsigned long long mask = __ballot(take);
+            if (take) cand[nc + __popcll(mask & ((1ull << lane) - 1ull))] = ci[f];
+            nc += __popcll(mask);
+        }
+    }
+    __syncthreads();
+    if (nc == 0) {
+        if (lane == 0) cnt[i] = 0;
+        return;
+    }
+    // 2. sort + unique: flag first occurrences, then rank them among each other
+    for (int p = lane; p < nc; p += 64) {
+        const int kp = cand[p];
+        bool first = true;
+        for (int r = 0; r < p && first; ++r) first = (cand[r] != kp);
+        kept[p] = first ? 1 : 0;      // kept[] doubles as the first-occurrence flag here
+    }
+    __syncthreads();
+    int nh = 0;
+    for (int c0 = 0; c0 < nc; c0 += 64) {
+        const int p = c0 + lane;
+        nh += __popcll(__ballot(p < nc && kept[p]));
+    }
+    for (int p = lane; p < nc; p += 64) {
+        if (!kept[p]) continue;
+        const int kp = cand[p];
+        int rank = 0;
+        for (int q = 0; q < nc; ++q) rank += (kept[q] && cand[q] < kp);
+        hat[rank] = kp;
+    }
+    __syncthreads();
+    auto inhat = [&](int key) {
+        int lo = 0, hi = nh - 1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const int c = hat[mid];
+            if (c == key) return true;
+            if (c < key) lo = mid + 1; else hi = mid - 1;
+        }
+        return false;
+    };
+    // 3. d_k per strong F neighbour (one lane per entry, row k ascending)
+    for (int e = a + lane; e < b; e += 64) {
+        const int k = ci[e];
+        double d = 0.0;
+        if (s[e] && cf[k] != ST_C) {
+            const double akk = dg[k];
+            for (int f = rp[k]; f < rp[k + 1]; ++f) {
+                const int l = ci[f];
+                if (l == i || (l != k && cf[l] == ST_C && inhat(l))) {
+                    const double ab = abar_of(akk, v[f]);
+                    if (ab != 0.0) d = d + ab;
+                }
+            }
+        }
+        dk[e - a] = d;
+        td[e] = d;
+    }
+    __syncthreads();
+    // 4. terms of atilde, summed in row order by lane 0
+    for (int e = a + lane; e < b; e += 64) {
+        const int nn = ci[e];
+        unsigned char u = 0;
+        double t = 0.0;
+        if (nn != i) {
+            if (s[e] && cf[nn] == ST_F) {
+                const double d = dk[e - a];
+                if (d != 0.0) {
+                    const double ab = abar_of(dg[nn], csr_value(rp, ci, v, nn, i));
+                    if (ab != 0.0) { t = (v[e] * ab) / d; u = 1; }
+                } else {
+                    t = v[e];
+                    u = 1;
+                }
+            } else if (!s[e] && !(cf[nn] == ST_C && inhat(nn))) {
+                t = v[e];
+                u = 1;
+            }
+        }
+        term[e - a] = t;
+        use[e - a] = u;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        double at = dg[i];
+        for (int e = 0; e < b - a; ++e)
+            if (use[e]) at = at + term[e];
+        at_s = at;
+    }
+    __syncthreads();
+    const double at = at_s;
+    if (at == 0.0) {
+        if (lane == 0) cnt[i] = 0;
+        return;
+    }
+    // 5. weights: one lane per interpolatory point
+    for (int p = lane; p < nh; p += 64) {
+        const int j = hat[p];
+        double num = csr_value(rp, ci, v, i, j);
+        for (int e = a; e < b; ++e) {
+            const int k = ci[e];
+            if (k == i || !s[e] || cf[k] == ST_C) continue;
+            const double d = dk[e - a];
+            if (d == 0.0) continue;
+            const double ab = abar_of(dg[k], csr_value(rp, ci, v, k, j));
+            if (ab == 0.0) continue;
+            num = num + (v[e] * ab) / d;
+        }
+        w[p] = -num / at;
+        kept[p] = 0;
+    }
+    __syncthreads();
+    int keep = nh;
+    if (pmax > 0 && nh > pmax) {
+        for (int round = 0; round < pmax; ++round) {
+            double bv = -1.0;
+            int bp = 0x7fffffff;
+            for (int p = lane; p < nh; p += 64) {
+                if (kept[p]) continue;
+                const double av = fabs(w[p]);
+                if (av > bv || (av == bv && p < bp)) { bv = av; bp = p; }
+            }
+            for (int d = 32; d >= 1; d >>= 1) {
+                const double ov = __shfl_xor(bv, d, 64);
+                const int op = __shfl_xor(bp, d, 64);
+                if (ov > bv || (ov == bv && op < bp)) { bv = ov; bp = op; }
+            }
+            if (lane == 0) kept[bp] = 1;
+            __syncthreads();
+        }
+        if (lane == 0) {
+            double sall = 0.0, skept = 0.0;
+            for (int p = 0; p < nh; ++p) sall = sall + w[p];
+            for (int p = 0; p < nh; ++p) if (kept[p]) skept = skept + w[p];
+            const double scale = (skept != 0.0) ? sall / skept : 1.0;
+            int q = 0;
+            for (int p = 0; p < nh; ++p) {
+                if (!kept[p]) continue;
+                ocol[q] = cidx[hat[p]];
+                ow[q] = (skept != 0.0) ? w[p] * scale : w[p];
+                q++;
+            }
+            cnt[i] = pmax;
+        }
+        return;
+    }
+    for (int p = lane; p < keep; p += 64) {
+        ocol[p] = cidx[hat[p]];
+        ow[p] = w[p];
+    }
+    if (lane == 0) cnt[i] = keep;
+}
+
+void amg_exti_compute_wave(int n, const int *rp, const int *ci, const double *v, const unsigned char *s,
+                           const int *cf, const int *cidx, const double *dg, int pmax, const int *off, int *tcol,
+                           double *tw, double *td, int *cnt, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_exti_wave, dim3(n), dim3(64), 0, st, n, rp, ci, v, s, cf, cidx, dg, pmax, off, tcol, tw, td,
+                       cnt);
+    CPTR_CHECK_LAUNCH();
+}
+
 void amg_exti_compute2(int n, const int *rp, const int *ci, const double *v, const unsigned char *s, const int *cf,
                        const int *cidx, const double *dg, int pmax, const int *off, int *tcol, double *tw,
                        double *td, int *cnt, hipStream_t st) {
@@ -498,6 +716,92 @@ __global__ void __launch_bounds__(SPG_T) k_spgemm_compute(int m, const int *__re
         spgemm_row(i, arp, aci, av, brp, bci, bv, sk + threadIdx.x, sv + threadIdx.x, SPG_T, cap, ok, ov, cnt);
     else
         spgemm_row(i, arp, aci, av, brp, bci, bv, ok, ov, 1, cap, ok, ov, cnt);
+}
+
+// One wavefront per output row, for products with long rows (coarse levels).
+// The row's products are expanded into LDS in A's row order (position p),
+// stably ranked by column (rank = #smaller columns + #equal columns at smaller
+// p), and each distinct column is summed sequentially over its terms in p
+// order starting from the first term -- the same sum, bit for bit, as the
+// sequential accumulation.  Rows with more than SPW_CAP products are handled
+// by lane 0 with the global-memory hash.
+constexpr int SPW_CAP = 1024;
+
+__global__ void __launch_bounds__(64) k_spgemm_wave(int m, const int *__restrict__ arp, const int *__restrict__ aci,
+                                                    const double *__restrict__ av, const int *__restrict__ brp,
+                                                    const int *__restrict__ bci, const double *__restrict__ bv,
+                                                    const int *__restrict__ off, int *__restrict__ tcol,
+                                                    double *__restrict__ tval, int *__restrict__ cnt) {
+    __shared__ int key[SPW_CAP];
+    __shared__ double val[SPW_CAP];
+    __shared__ int skey[SPW_CAP];
+    __shared__ double sval[SPW_CAP];
+    __shared__ int head_pos[SPW_CAP];
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (i >= m) return;
+    const int cap = off[i + 1] - off[i];
+    const int nprod = (cap - 1) / 2;           // the bound kernel stored 2 * products + 1
+    int *ok = tcol + off[i];
+    double *ov = tval + off[i];
+    if (nprod > SPW_CAP) {
+        if (lane == 0) spgemm_row(i, arp, aci, av, brp, bci, bv, ok, ov, 1, cap, ok, ov, cnt);
+        return;
+    }
+    // expansion in A's row order
+    int base = 0;
+    for (int e = arp[i]; e < arp[i + 1]; ++e) {
+        const int k = aci[e];
+        const double a = av[e];
+        const int f0 = brp[k], len = brp[k + 1] - f0;
+        for (int q = lane; q < len; q += 64) {
+            key[base + q] = bci[f0 + q];
+            val[base + q] = a * bv[f0 + q];
+        }
+        base += len;
+    }
+    __syncthreads();
+    const int P = base;
+    // stable rank by column
+    for (int p = lane; p < P; p += 64) {
+        const int kp = key[p];
+        int rank = 0;
+        for (int q = 0; q < P; ++q) {
+            const int kq = key[q];
+            rank += (kq < kp) || (kq == kp && q < p);
+        }
+        skey[rank] = kp;
+        sval[rank] = val[p];
+    }
+    __syncthreads();
+    // segment heads and their output slots
+    int nheads_before = 0;
+    for (int c0 = 0; c0 < P; c0 += 64) {
+        const int pos = c0 + lane;
+        const bool head = pos < P && (pos == 0 || skey[pos] != skey[pos - 1]);
+        const unsigned long long mask = __ballot(head);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (head) head_pos[nheads_before + before] = pos;
+        nheads_before += __popcll(mask);
+    }
+    __syncthreads();
+    const int u = nheads_before;
+    for (int h = lane; h < u; h += 64) {
+        const int pos = head_pos[h];
+        const int j = skey[pos];
+        double acc = sval[pos];
+        for (int q = pos + 1; q < P && skey[q] == j; ++q) acc = acc + sval[q];
+        ok[h] = j;
+        ov[h] = acc;
+    }
+    if (lane == 0) cnt[i] = u;
+}
+
+void amg_spgemm_compute_wave(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
+                             const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_spgemm_wave, dim3(m), dim3(64), 0, st, m, arp, aci, av, brp, bci, bv, off, tcol, tval, cnt);
+    CPTR_CHECK_LAUNCH();
 }
 
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,

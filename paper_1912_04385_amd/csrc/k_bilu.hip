@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(BL_THREADS) k_bilu_factor(TileGeom g, const in
     const int grp = lane / B, r = lane % B;
     const bool active_lane = grp < GPW;
     const int slot = wave * GPW + grp;        // cell slot inside the block
-    const int slots = (BL_THREADS / 64) * GPW;
+    const int slots = (int)(blockDim.x / 64) * GPW;
     const int gbase = grp * B;
     int x0, y0, tw, th;
     tile_dims(g, tiles ? tiles[blockIdx.x] : (int)blockIdx.x, x0, y0, tw, th);
@@ -144,7 +144,9 @@ void bilu_factor_tiles(const TileSched &ts, int n, int b, const int *rp, const i
     const int nt = ts.ntiles[color];
     if (nt == 0) return;
     TileGeom g{ts.nx, ts.ny, ts.tx, ts.ty, ts.ntx};
-#define CASE(BB) case BB: hipLaunchKernelGGL(k_bilu_factor<BB>, dim3(nt), dim3(BL_THREADS), 0, st, g, ts.tiles[color].p, ts.color.p, rp, ci, tpos, abar, dinv, flag, diag_only); break;
+    // one wavefront per tile when a tile's anti-diagonals fit in it
+    const int threads = (std::min(ts.tx, ts.ty) <= 64 / b) ? 64 : BL_THREADS;
+#define CASE(BB) case BB: hipLaunchKernelGGL(k_bilu_factor<BB>, dim3(nt), dim3(threads), 0, st, g, ts.tiles[color].p, ts.color.p, rp, ci, tpos, abar, dinv, flag, diag_only); break;
     switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
 #undef CASE
     CPTR_CHECK_LAUNCH();

@@ -81,18 +81,21 @@ def _compare_hierarchy(solver, h, which):
             assert np.array_equal(g["pv"], L.P.v), f"level {lvl} interpolation weights differ"
 
 
+@pytest.mark.parametrize("kernels", [1, 2])
 @pytest.mark.parametrize("name,max_coarse,pmax", [("c1", 40, 4), ("tiny48x40b6", 30, 4), ("tiny48x40b6", 30, 0),
-                                                  ("tiny64x20b8", 50, 2)])
-def test_amg_hierarchy_bitwise(name, max_coarse, pmax):
-    print(f"case hierarchy {name} max_coarse={max_coarse} pmax={pmax}", flush=True)
+                                                  ("tiny64x20b8", 50, 2), ("c2-0", 100, 4)])
+def test_amg_hierarchy_bitwise(name, max_coarse, pmax, kernels):
+    print(f"case hierarchy {name} max_coarse={max_coarse} pmax={pmax} kernels={kernels}", flush=True)
     if name == "c1":
         s = config1()
+    elif name == "c2-0":
+        s = config2(0)
     elif name == "tiny48x40b6":
         s = tiny(48, 40, 6, peclet=0.5, seed=3)
     else:
         s = tiny(64, 20, 8, peclet=20.0, seed=4)
     ref = O.solve(s, _oracle_opts(s, amg_max_coarse=max_coarse, amg_pmax=pmax, max_iters=1))
-    solver = cptr.solver_for(s, amg_max_coarse=max_coarse, amg_pmax=pmax)
+    solver = cptr.solver_for(s, amg_max_coarse=max_coarse, amg_pmax=pmax, setup_kernels=kernels)
     _compare_hierarchy(solver, ref.hierarchies["T"], 0)
     _compare_hierarchy(solver, ref.hierarchies["P"], 1)
     solver.close()
