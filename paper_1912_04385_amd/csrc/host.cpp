@@ -151,9 +151,10 @@ static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
     hk.alloc((size_t)cap);
     hv.alloc((size_t)cap);
     // short rows: one thread per row; long rows (coarse levels): one wavefront per row
-    const double avg_products = (double)(cap - m) / (2.0 * (m > 0 ? m : 1));
+    // many rows: one thread per row keeps the machine busy; few (long) rows:
+    // one wavefront per row avoids a sequential tail
     const int sk = c->opt.setup_kernels;
-    if (sk == 2 || (sk == 0 && avg_products <= 24.0))
+    if (sk == 2 || (sk == 0 && m > 50000))
         amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
     else
         amg_spgemm_compute_wave(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
@@ -261,7 +262,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
         twt.alloc(cap);
         td.alloc((size_t)L.A.nnz + 1);
         // short rows: one thread per row; long rows (coarse levels): one wavefront per row
-        if (o.setup_kernels == 2 || (o.setup_kernels == 0 && (double)cap / m <= 12.0))
+        if (o.setup_kernels == 2 || (o.setup_kernels == 0 && m > 100000))
             amg_exti_compute2(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
                               tcol.p, twt.p, td.p, cnt.p, s);
         else

@@ -754,15 +754,15 @@ __global__ void __launch_bounds__(64) k_spgemm_wave(int m, const int *__restrict
         const int k = aci[e];
         const double a = av[e];
         const int f0 = brp[k], len = brp[k + 1] - f0;
-        for (int q = lane; q < len; q += 64) {
-            key[base + q] = bci[f0 + q];
-            val[base + q] = a * bv[f0 + q];
+        for (int t = lane; t < len; t += 64) {
+            key[base + t] = bci[f0 + t];
+            val[base + t] = a * bv[f0 + t];
         }
         base += len;
     }
     __syncthreads();
     const int P = base;
-    // stable rank by column
+    // stable rank by column: smaller columns anywhere, equal columns earlier
     for (int p = lane; p < P; p += 64) {
         const int kp = key[p];
         int rank = 0;
@@ -790,7 +790,7 @@ __global__ void __launch_bounds__(64) k_spgemm_wave(int m, const int *__restrict
         const int pos = head_pos[h];
         const int j = skey[pos];
         double acc = sval[pos];
-        for (int q = pos + 1; q < P && skey[q] == j; ++q) acc = acc + sval[q];
+        for (int t = pos + 1; t < P && skey[t] == j; ++t) acc = acc + sval[t];
         ok[h] = j;
         ov[h] = acc;
     }

@@ -289,17 +289,50 @@ __global__ void k_stage_residual(int n, int b, const int *__restrict__ rp, const
     u[t] = acc;
 }
 
+// Couplings between tiles of different colours, fully parallel (one thread
+// per scalar row), in place on u:
+//   mode 0 (before the black sweep): black rows  u_i -= sum_{red j} Abar_ij t_j
+//   mode 1 (before the red backward sweep): red rows  u_i = sum_{black j} Abar_ij w_j
+template <class T>
+__global__ void k_cross_tile(int n, int b, int mode, const int *__restrict__ color, const int *__restrict__ rp,
+                             const int *__restrict__ ci, const T *__restrict__ abar, const T *__restrict__ tw,
+                             T *__restrict__ u) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n * b) return;
+    const int i = (int)(t / b), r = (int)(t % b);
+    const int ci_ = color[i];
+    if ((mode == 0 && ci_ == 0) || (mode == 1 && ci_ != 0)) return;
+    T acc = (mode == 0) ? u[t] : (T)0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        if (j == i || color[j] == ci_) continue;
+        const T *Aij = abar + (size_t)e * b * b + (size_t)r * b;
+        const T *vj = tw + (size_t)j * b;
+        T d = 0;
+        for (int m = 0; m < b; ++m) d += Aij[m] * vj[m];
+        if (mode == 0) acc -= d; else acc += d;
+    }
+    u[t] = acc;
+}
+
+// Level chain of one tile per wavefront.  s0 (forward right-hand side, with
+// the couplings to lower-colour tiles already folded in) and q0 (backward:
+// couplings to higher-colour tiles) come from u; in-tile neighbour values come
+// from LDS; the next level's matrix rows, D^{-1} row and s0/q0/t are loaded
+// into registers while the current level computes.
+//   mode 0: forward only (t to LDS and global)
+//   mode 1: forward then backward (the last colour); w to global, y written
+//   mode 2: backward only (t read from global); y written
 template <class T, int B>
 __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const int *__restrict__ tiles,
-                                                  const int *__restrict__ color, const int *__restrict__ rp,
-                                                  const int *__restrict__ ci, const T *__restrict__ abar,
-                                                  const T *__restrict__ dinv, const T *__restrict__ u,
-                                                  T *__restrict__ tw, double *__restrict__ y, int ip, int it,
-                                                  const T *__restrict__ xT, const T *__restrict__ vP) {
+                                                  const int *__restrict__ rp, const int *__restrict__ ci,
+                                                  const T *__restrict__ abar, const T *__restrict__ dinv,
+                                                  const T *__restrict__ u, T *__restrict__ tw,
+                                                  double *__restrict__ y, int ip, int it, const T *__restrict__ xT,
+                                                  const T *__restrict__ vP) {
     constexpr int GPW = 64 / B;
     extern __shared__ unsigned char lds_raw[];
-    T *S = reinterpret_cast<T *>(lds_raw);                  // pre-pass sums
-    T *W = S + (size_t)g.tx * g.ty * B;                      // t (forward), then w (backward)
+    T *W = reinterpret_cast<T *>(lds_raw);   // t (forward), then w (backward)
     const int lane = threadIdx.x;
     const int grp = lane / B, r = lane % B;
     const bool glane = grp < GPW;
@@ -307,80 +340,61 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
     const int tile = tiles[blockIdx.x];
     int x0, y0, tw_, th;
     tile_dims(g, tile, x0, y0, tw_, th);
-    const int ncell = tw_ * th;
     const int nlev = tw_ + th - 1;
-    const int mycolor = color[x0 + g.nx * y0];
-    auto cell_of = [&](int loc) { return (x0 + loc % tw_) + g.nx * (y0 + loc / tw_); };
     auto in_tile = [&](int j, int &loc) {
         const int xj = j % g.nx - x0, yj = j / g.nx - y0;
         loc = xj + tw_ * yj;
         return xj >= 0 && xj < tw_ && yj >= 0 && yj < th;
     };
-
-    if (mode == 0 || mode == 1) {
-        // pre-pass: S = u - (couplings to lower-colour tiles) . t
-        for (int base = 0; base < ncell; base += GPW) {
-            const int loc = base + grp;
-            if (glane && loc < ncell) {
-                const int i = cell_of(loc);
-                T acc = u[(size_t)i * B + r];
-                for (int e = rp[i]; e < rp[i + 1]; ++e) {
-                    const int j = ci[e];
-                    if (j == i || color[j] >= mycolor) continue;
-                    const T *Aij = abar + (size_t)e * B * B + r * B;
-                    const T *tj = tw + (size_t)j * B;
+    // prefetch registers
+    T na0[B], na1[B], nd[B];
+    T ns = 0, ntv = 0;
+    int nl0 = -1, nl1 = -1, nloc = -1, ni = 0;
+    auto load = [&](int lev, int slot, bool fwd) {
+        nloc = -1; nl0 = -1; nl1 = -1;
+        if (!glane || lev < 0 || lev >= nlev) return;
+        const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
+        const int lx = lo + slot + grp;      // this lane group's cell of the level
+        if (lx > hi) return;
+        const int ly = lev - lx;
+        nloc = lx + tw_ * ly;
+        ni = (x0 + lx) + g.nx * (y0 + ly);
+        for (int e = rp[ni]; e < rp[ni + 1]; ++e) {
+            const int j = ci[e];
+            int lj;
+            if (j == ni || !in_tile(j, lj) || (fwd ? (j > ni) : (j < ni))) continue;
+            const T *Aij = abar + (size_t)e * B * B + r * B;
+            if (nl0 < 0) {
+                nl0 = lj;
 #pragma unroll
-                    for (int m = 0; m < B; ++m) acc -= Aij[m] * tj[m];
-                }
-                S[loc * B + r] = acc;
+                for (int m = 0; m < B; ++m) na0[m] = Aij[m];
+            } else {
+                nl1 = lj;
+#pragma unroll
+                for (int m = 0; m < B; ++m) na1[m] = Aij[m];
             }
         }
-        __syncthreads();
-        // level loop (forward): in-tile lower neighbours are W (x-1) and S (y-1)
-        T na0[B], na1[B], nd[B];
-        int nl0 = -1, nl1 = -1, nloc = -1, ni = 0;
-        auto load_fwd = [&](int lev, int slot) {
-            const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
-            const int lx = lo + slot + grp;      // this lane group's cell of the level
-            nloc = -1; nl0 = -1; nl1 = -1;
-            if (!glane || lev >= nlev || lx > hi) return;
-            const int ly = lev - lx;
-            nloc = lx + tw_ * ly;
-            ni = (x0 + lx) + g.nx * (y0 + ly);
-            for (int e = rp[ni]; e < rp[ni + 1]; ++e) {
-                const int j = ci[e];
-                int lj;
-                if (j == ni || !in_tile(j, lj) || j > ni) continue;
-                const T *Aij = abar + (size_t)e * B * B + r * B;
-                if (nl0 < 0) {
-                    nl0 = lj;
+        const T *Di = dinv + (size_t)ni * B * B + r * B;
 #pragma unroll
-                    for (int m = 0; m < B; ++m) na0[m] = Aij[m];
-                } else {
-                    nl1 = lj;
-#pragma unroll
-                    for (int m = 0; m < B; ++m) na1[m] = Aij[m];
-                }
-            }
-            const T *Di = dinv + (size_t)ni * B * B + r * B;
-#pragma unroll
-            for (int c = 0; c < B; ++c) nd[c] = Di[c];
-        };
+        for (int c = 0; c < B; ++c) nd[c] = Di[c];
+        ns = u[(size_t)ni * B + r];
+        if (!fwd && mode == 2) ntv = tw[(size_t)ni * B + r];
+    };
+
+    if (mode == 0 || mode == 1) {
         int lev = 0, slot = 0;
-        load_fwd(0, 0);
+        load(0, 0, true);
         while (lev < nlev) {
             T a0[B], a1[B], d[B];
 #pragma unroll
             for (int m = 0; m < B; ++m) { a0[m] = na0[m]; a1[m] = na1[m]; d[m] = nd[m]; }
             const int l0 = nl0, l1 = nl1, loc = nloc, i = ni;
-            // advance to the next (level, slot) and prefetch it
+            T s = ns;
             const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
             int nlev_ = lev, nslot = slot + GPW;
             if (lo + nslot > hi) { nlev_ = lev + 1; nslot = 0; }
-            load_fwd(nlev_, nslot);
-            T s = 0;
+            load(nlev_, nslot, true);
             if (loc >= 0) {
-                s = S[loc * B + r];
                 if (l0 >= 0) {
 #pragma unroll
                     for (int m = 0; m < B; ++m) s -= a0[m] * W[l0 * B + m];
@@ -389,6 +403,8 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
 #pragma unroll
                     for (int m = 0; m < B; ++m) s -= a1[m] * W[l1 * B + m];
                 }
+            } else {
+                s = 0;
             }
             T tv = 0;
 #pragma unroll
@@ -403,74 +419,22 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
         }
     }
     if (mode == 1 || mode == 2) {
-        if (mode == 2) {
-            // pre-pass: S = (couplings to higher-colour tiles) . w, W = t from the forward launch
-            for (int base = 0; base < ncell; base += GPW) {
-                const int loc = base + grp;
-                if (glane && loc < ncell) {
-                    const int i = cell_of(loc);
-                    T acc = 0;
-                    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-                        const int j = ci[e];
-                        if (j == i || color[j] <= mycolor) continue;
-                        const T *Aij = abar + (size_t)e * B * B + r * B;
-                        const T *wj = tw + (size_t)j * B;
-#pragma unroll
-                        for (int m = 0; m < B; ++m) acc += Aij[m] * wj[m];
-                    }
-                    S[loc * B + r] = acc;
-                    W[loc * B + r] = tw[(size_t)i * B + r];
-                }
-            }
-        } else {
-            for (int k = lane; k < ncell * B; k += 64) S[k] = 0;
-        }
-        __syncthreads();
-        T na0[B], na1[B], nd[B];
-        int nl0 = -1, nl1 = -1, nloc = -1, ni = 0;
-        auto load_bwd = [&](int lev, int slot) {
-            nloc = -1; nl0 = -1; nl1 = -1;
-            if (!glane || lev < 0) return;
-            const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
-            const int lx = lo + slot + grp;      // this lane group's cell of the level
-            if (lx > hi) return;
-            const int ly = lev - lx;
-            nloc = lx + tw_ * ly;
-            ni = (x0 + lx) + g.nx * (y0 + ly);
-            for (int e = rp[ni]; e < rp[ni + 1]; ++e) {
-                const int j = ci[e];
-                int lj;
-                if (j == ni || !in_tile(j, lj) || j < ni) continue;
-                const T *Aij = abar + (size_t)e * B * B + r * B;
-                if (nl0 < 0) {
-                    nl0 = lj;
-#pragma unroll
-                    for (int m = 0; m < B; ++m) na0[m] = Aij[m];
-                } else {
-                    nl1 = lj;
-#pragma unroll
-                    for (int m = 0; m < B; ++m) na1[m] = Aij[m];
-                }
-            }
-            const T *Di = dinv + (size_t)ni * B * B + r * B;
-#pragma unroll
-            for (int c = 0; c < B; ++c) nd[c] = Di[c];
-        };
         int lev = nlev - 1, slot = 0;
-        load_bwd(lev, 0);
+        load(lev, 0, false);
         while (lev >= 0) {
             T a0[B], a1[B], d[B];
 #pragma unroll
             for (int m = 0; m < B; ++m) { a0[m] = na0[m]; a1[m] = na1[m]; d[m] = nd[m]; }
             const int l0 = nl0, l1 = nl1, loc = nloc, i = ni;
+            T q = (mode == 2) ? ns : (T)0;
+            const T tglob = ntv;
             const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
             int nlev_ = lev, nslot = slot + GPW;
             if (lo + nslot > hi) { nlev_ = lev - 1; nslot = 0; }
-            load_bwd(nlev_, nslot);
-            T q = 0, tval = 0;
+            load(nlev_, nslot, false);
+            T tval = 0;
             if (loc >= 0) {
-                q = S[loc * B + r];
-                tval = W[loc * B + r];
+                tval = (mode == 2) ? tglob : W[loc * B + r];
                 if (l0 >= 0) {
 #pragma unroll
                     for (int m = 0; m < B; ++m) q += a0[m] * W[l0 * B + m];
@@ -479,6 +443,8 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
 #pragma unroll
                     for (int m = 0; m < B; ++m) q += a1[m] * W[l1 * B + m];
                 }
+            } else {
+                q = 0;
             }
             T corr = 0;
 #pragma unroll
@@ -505,14 +471,14 @@ static void bilu_apply_wave(const TileSched &ts, int n, int b, const int *rp, co
                             const T *dinv, const T *slabT, const T *slabP, int ip, int it, const double *r,
                             const T *xT, const T *vP, T *u, T *tw, double *y, hipStream_t st) {
     const long nr = (long)n * b;
-    hipLaunchKernelGGL(k_stage_residual<T>, dim3((int)((nr + 255) / 256)), dim3(256), 0, st, n, b, rp, ci, slabT,
-                       slabP, r, xT, vP, u);
+    const int gr = (int)((nr + 255) / 256);
+    hipLaunchKernelGGL(k_stage_residual<T>, dim3(gr), dim3(256), 0, st, n, b, rp, ci, slabT, slabP, r, xT, vP, u);
     TileGeom g{ts.nx, ts.ny, ts.tx, ts.ty, ts.ntx};
-    const size_t lds = 2 * (size_t)ts.tx * ts.ty * b * sizeof(T);
+    const size_t lds = (size_t)ts.tx * ts.ty * b * sizeof(T);
     auto launch = [&](int color, int mode) {
         const int nt = ts.ntiles[color];
         if (nt == 0) return;
-#define CASE(BB) case BB: hipLaunchKernelGGL((k_bilu_wave<T, BB>), dim3(nt), dim3(64), lds, st, g, mode, ts.tiles[color].p, ts.color.p, rp, ci, abar, dinv, u, tw, y, ip, it, xT, vP); break;
+#define CASE(BB) case BB: hipLaunchKernelGGL((k_bilu_wave<T, BB>), dim3(nt), dim3(64), lds, st, g, mode, ts.tiles[color].p, rp, ci, abar, dinv, u, tw, y, ip, it, xT, vP); break;
         switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
 #undef CASE
         CPTR_CHECK_LAUNCH();
@@ -521,9 +487,12 @@ static void bilu_apply_wave(const TileSched &ts, int n, int b, const int *rp, co
         launch(0, 1);
     } else {
         launch(0, 0);
+        hipLaunchKernelGGL(k_cross_tile<T>, dim3(gr), dim3(256), 0, st, n, b, 0, ts.color.p, rp, ci, abar, tw, u);
         launch(1, 1);
+        hipLaunchKernelGGL(k_cross_tile<T>, dim3(gr), dim3(256), 0, st, n, b, 1, ts.color.p, rp, ci, abar, tw, u);
         launch(0, 2);
     }
+    CPTR_CHECK_LAUNCH();
 }
 
 bool bilu_wave_ok(const TileSched &ts, int b) {
