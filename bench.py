@@ -87,6 +87,36 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
                       f"scaled x{scale:.0f} by cell count"}
 
 
+def traffic_probe(args, dev) -> int:
+    """Five launches of the b = 8 SpMV on the config-3 matrix, then five
+    device-to-device copies of 1 GiB: the copy's counter reading per byte
+    calibrates the SpMV's."""
+    import torch
+    from paper_1912_04385_amd import cptr
+    from synthetic import config3
+
+    s = config3(0, args.nx, args.ny)
+    rp = torch.from_numpy(s.row_ptr).to(dev)
+    ci = torch.from_numpy(s.col_idx).to(dev)
+    vals = torch.from_numpy(s.vals.reshape(-1)).to(dev)
+    x = torch.from_numpy(s.rhs).to(dev)
+    nbytes = spmv_algorithmic_bytes(s.n, s.nnzb, s.b)
+    del s
+    for _ in range(5):
+        y = cptr.bsr_spmv(rp, ci, vals, x, 8)
+    torch.cuda.synchronize()
+    copy_bytes = 1 << 30
+    src = torch.ones(copy_bytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"spmv_algorithmic_bytes": nbytes, "copy_bytes_read": copy_bytes,
+                      "copy_bytes_written": copy_bytes, "spmv_checksum": float(y.sum()),
+                      "kernel_source_hash": kernel_source_hash()}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +127,9 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only launch the outer SpMV and a plain device copy of known size, 5 times each "
+                         "(the run that the HBM byte counters are read on)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -111,6 +144,8 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.traffic_probe:
+        return traffic_probe(args, dev)
     t_gen = time.perf_counter()
     systems = []
     for idx in (0, 1):
@@ -184,7 +219,7 @@ def main() -> int:
         "data": "synthetic (seeded generator, config-3 recipe)",
         "config": {"workload": f"config3: {args.nx}x{args.ny} cells, b=8 ({args.nx * args.ny * 8} unknowns), "
                                f"channelised ln-sigma 2, Pe 0.1 and 100 alternating",
-                   "krylov": "FGMRES(50)", "preconditioner": "CPTR3 (T-AMG, P-AMG, BILU(0) 32x32 tiles), FP32",
+                   "krylov": "FGMRES(50)", "preconditioner": "CPTR3 (T-AMG, P-AMG, BILU(0) 32x8 tiles), FP32",
                    "tol": 1e-8},
         "iterations": its32,
         "setup_ms": [round(r["setup_ms"], 2) for r in res32],

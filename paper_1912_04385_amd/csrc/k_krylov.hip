@@ -12,19 +12,44 @@ namespace cptr {
 // b = 8: one wavefront per block row; lane l owns block entry (l/8, l%8), so
 // the row's value stream (contiguous, 512 B per block) is read fully
 // coalesced; the 8 partial products of a row are summed with xor shuffles.
+// The row index is made wave-uniform so that the row pointers and block
+// columns come through scalar loads, and all value and x loads of a row are
+// issued before the first product (up to SPMV_UNROLL blocks in flight per
+// wave).  The value stream is read once: non-temporal loads keep it from
+// evicting x from the caches.
+constexpr int SPMV_UNROLL = 5;
+
 template <bool RESID>
 __global__ void __launch_bounds__(256) k_bsr8(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                               const double *__restrict__ A, const double *__restrict__ x,
                                               const double *__restrict__ rhs, double *__restrict__ y) {
     const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (row >= n) return;
     const int c = lane & 7;
     const int a = rp[row], e1 = rp[row + 1];
     double acc = 0.0;
-    for (int e = a; e < e1; ++e) {
-        const int j = ci[e];
-        acc += A[(size_t)e * 64 + lane] * x[(size_t)j * 8 + c];
+    const int last = e1 - 1;   // the diagonal block is always present: e1 > a
+    for (int e0 = a; e0 < e1; e0 += SPMV_UNROLL) {
+        // clamped entry indices: every load is in bounds and the batch has no
+        // branches; entries past the row end are loaded again and not summed
+        // (one vector load fetches the block columns; readlane makes them scalar)
+        int ek[SPMV_UNROLL], jk[SPMV_UNROLL];
+        const int jl = ci[min(e0 + (lane & 7), last)];
+#pragma unroll
+        for (int u = 0; u < SPMV_UNROLL; ++u) {
+            ek[u] = min(e0 + u, last);
+            jk[u] = __builtin_amdgcn_readlane(jl, u);
+        }
+        double av[SPMV_UNROLL], xv[SPMV_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SPMV_UNROLL; ++u) {
+            av[u] = __builtin_nontemporal_load(A + (size_t)ek[u] * 64 + lane);
+            xv[u] = x[(size_t)jk[u] * 8 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < SPMV_UNROLL; ++u)
+            if (e0 + u < e1) acc += av[u] * xv[u];
     }
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
