@@ -101,10 +101,12 @@ typedef struct {
     int32_t used_learned;
     double  rel_res_scaled;     /* |bbar - Abar x| / |bbar|, recomputed in FP64   */
     double  rel_res_unscaled;   /* |b - A x| / |b|                                */
-    double  rho_T, rho_P;       /* V-cycle convergence factors (if measured)      */
+    double  rho_T, rho_P;       /* convergence factors measured by the last       */
+                                /* update_values (-1: not measured)               */
     double  setup_ms, solve_ms;
     int32_t levels_T, levels_P;
-    int32_t reused;             /* update_values kept the hierarchy               */
+    int32_t reused;             /* bit 0: T hierarchy kept, bit 1: P hierarchy    */
+                                /* kept by the last update_values                 */
     /* with options.timing = 1: summed HIP-event times over all Arnoldi steps  */
     int32_t timed_steps;
     double  t_stage1_ms;        /* first scalar stage (gather + V-cycle)          */
@@ -133,10 +135,17 @@ cptr_status cptr_setup(cptr_ctx *ctx, int32_t n_cells, int32_t b, int32_t nnzb,
                        const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_vals,
                        int32_t p_index, int32_t T_index, int32_t nx, int32_t ny);
 
-/* New values on the same pattern (a Newton sequence): rescale and refactor;
- * the AMG hierarchies are kept (numeric Galerkin products redone) while the
- * measured V-cycle convergence factor stays below reuse_rho_max, else they
- * are rebuilt. */
+/* New values on the same pattern (a Newton sequence of systems, each with
+ * its own left scaling, Eqs. splitPrec1, CPTR31, CPTR32): the matrix is
+ * rescaled and the last stage refactored.  Each AMG hierarchy is first
+ * reused: its C/F splits and its P and R = P^T on every level are kept, and
+ * the Galerkin products, smoother diagonals and coarsest inverse are redone
+ * from the new values.  Its V-cycle convergence factor rho (as in
+ * cptr_amg_conv_factor, 10 cycles, seed 0) is then measured; the hierarchy
+ * is kept if rho < options.reuse_rho_max and rebuilt from scratch otherwise.
+ * reuse_rho_max <= 0 rebuilds always.  The next cptr_solve reports rho_T,
+ * rho_P and the kept hierarchies in cptr_result.reused.  d_vals: device,
+ * nnzb*b*b, same layout as in cptr_setup; copied. */
 cptr_status cptr_update_values(cptr_ctx *ctx, const double *d_vals);
 
 /* Solve A x = b: d_rhs (device, n_cells*b) in, d_x (device) out.  Returns
@@ -184,6 +193,14 @@ cptr_status cptr_amg_level_copy(const cptr_ctx *ctx, int32_t which, int32_t leve
 
 /* One V-cycle of hierarchy `which` with zero initial guess: d_x = V(d_b) (length = fine rows). */
 cptr_status cptr_amg_vcycle(cptr_ctx *ctx, int32_t which, const double *d_b, double *d_x);
+
+/* Asymptotic V-cycle convergence factor of hierarchy `which` (the measure
+ * that judges hierarchy reuse and the learned interpolation): from the start
+ * vector e_0[i] = u(seed, i) in [-1, 1), where u maps SplitMix64 of (seed, i)
+ * to its top 53 bits scaled to [0, 1) then to 2 u - 1, iterate
+ * e <- e - V(A e) `cycles` times (FP64) and return
+ * rho = (|e_K|_2 / |e_0|_2)^(1/K) in *rho (host). */
+cptr_status cptr_amg_conv_factor(cptr_ctx *ctx, int32_t which, int32_t cycles, uint64_t seed, double *rho);
 
 /* One application of the multi-stage preconditioner: d_y = M^{-1} d_r. */
 cptr_status cptr_precond_apply(cptr_ctx *ctx, const double *d_r, double *d_y);

@@ -28,6 +28,7 @@ T_THEN_P, P_THEN_T = 0, 1
 LAST_BILU0, LAST_BJACOBI = 0, 1
 GMRES, FGMRES = 0, 1
 SMOOTH_JACOBI, SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1, 2
+MAX_REUSE_BACKOFF = 8
 
 
 def build(force: bool = True) -> str:
@@ -342,6 +343,11 @@ def amg_setup(A: CSR, opts: AMGOptions | None = None, interp_fn=None) -> Hierarc
         R = P.transpose()
         L.P, L.R, L.strong, L.cf = P, R, s, cf
         cur = galerkin(cur, P, R)
+    return _finish_hierarchy(levels, opts)
+
+
+def _finish_hierarchy(levels: list, opts: AMGOptions) -> Hierarchy:
+    """Smoother data of every level but the last; dense LU of the last."""
     for L in levels[:-1]:
         _smoother_setup(L, opts)
     Ac = levels[-1].A.to_dense()
@@ -350,6 +356,23 @@ def amg_setup(A: CSR, opts: AMGOptions | None = None, interp_fn=None) -> Hierarc
     if lib().orc_dense_lu_factor(Ac.shape[0], _p(lu), _p(piv)) != 0:
         raise OracleError("singular coarsest AMG level")
     return Hierarchy(levels, lu, piv, opts)
+
+
+def amg_refresh(h: Hierarchy, A: CSR) -> Hierarchy:
+    """Reuse of hierarchy ``h`` for new level-0 values ``A`` on the same
+    pattern (the next system of a Newton sequence): the C/F splits and the
+    transfer operators P, R = P^T of every level are kept; the Galerkin
+    products A_{l+1} = R A_l P, the smoother data and the coarsest LU are
+    recomputed from the new values."""
+    levels = []
+    cur = A
+    for old in h.levels:
+        L = Level(cur, cur.diagonal(), old.P, old.R, old.strong, old.cf)
+        levels.append(L)
+        if old.P is None:
+            break
+        cur = galerkin(cur, old.P, old.R)
+    return _finish_hierarchy(levels, h.opts)
 
 
 def _smoother_setup(L: Level, opts: AMGOptions) -> None:
@@ -665,6 +688,8 @@ class Options:
     amg: AMGOptions = dataclasses.field(default_factory=AMGOptions)
     exact_subsolves: bool = False        # replace amg(.) by direct solves (the paper's exact study)
     exact_last_stage: bool = False       # replace ilu(Abar) by an exact solve (tests only)
+    reuse_rho_max: float = 0.3           # keep a reused AMG hierarchy while rho < this
+    rho_cycles: int = 10
 
 
 @dataclasses.dataclass
@@ -678,6 +703,9 @@ class SolveResult:
     history: list
     hierarchies: dict
     dec: Decoupled
+    rho: dict = dataclasses.field(default_factory=dict)      # measured for reused hierarchies
+    reused: dict = dataclasses.field(default_factory=dict)   # name -> kept?
+    reuse_state: dict = dataclasses.field(default_factory=dict)  # name -> (skip, backoff)
 
 
 class _Direct:
@@ -695,11 +723,22 @@ class _Direct:
         return f
 
 
-def build_preconditioner(dec: Decoupled, opts: Options):
+def build_preconditioner(dec: Decoupled, opts: Options, previous: dict | None = None,
+                         info: dict | None = None):
     """The stages of the chosen variant on Abar, in the paper's order:
     CPTR3: M1 = amg(C_TT), M2 = amg(B_PP), M3 = ilu(Abar) (Eqs. CPTR3M1,
     CPTRM2, CPTR3M3); CPR: M1 = amg(B_PP), M2 = ilu(Abar) (Eqs. CPRM1 ff.);
-    BJ_ONLY: the last stage alone.  Returns (apply, stages, hierarchies)."""
+    BJ_ONLY: the last stage alone.  Returns (apply, stages, hierarchies).
+
+    ``previous`` (name -> Hierarchy of the previous system of a sequence)
+    switches on reuse: each scalar stage first refreshes the previous
+    hierarchy with the new values and measures its V-cycle convergence
+    factor; it is kept if rho < opts.reuse_rho_max, else rebuilt.  The
+    factors and decisions are written into ``info["rho"]``, ``info["reused"]``.
+    After a rejected trial the next ``skip`` systems rebuild without a trial,
+    ``skip`` doubling (up to MAX_REUSE_BACKOFF) with each rejection in a row
+    and resetting to 1 on acceptance; ``info["state"]`` carries (skip,
+    backoff) per stage in and out."""
     Abar = dec.Abar
     n, b, ip, it = Abar.n, Abar.b, dec.ip, dec.it
     hier = {}
@@ -708,7 +747,29 @@ def build_preconditioner(dec: Decoupled, opts: Options):
         A = Abar.scalar_block(comp, comp)
         if opts.exact_subsolves:
             return _Direct(A)
-        h = amg_setup(A, opts.amg)
+        h = None
+        skip, backoff = (info or {}).get("state", {}).get(name, (0, 1))
+        if previous and name in previous and opts.reuse_rho_max > 0:
+            if skip > 0:
+                skip -= 1                   # rebuild without a trial
+            else:
+                hr = amg_refresh(previous[name], A)
+                rho = conv_factor(hr, opts.rho_cycles, 0)
+                keep = rho < opts.reuse_rho_max
+                if info is not None:
+                    info.setdefault("rho", {})[name] = rho
+                    info.setdefault("reused", {})[name] = keep
+                if keep:
+                    h = hr
+                    backoff = 1
+                else:
+                    skip, backoff = backoff, min(2 * backoff, MAX_REUSE_BACKOFF)
+        else:
+            skip, backoff = 0, 1
+        if info is not None:
+            info.setdefault("state", {})[name] = (skip, backoff)
+        if h is None:
+            h = amg_setup(A, opts.amg)
         hier[name] = h
         return lambda rr, h=h: vcycle(h, rr)
 
@@ -741,16 +802,20 @@ def build_preconditioner(dec: Decoupled, opts: Options):
     return (lambda r: multistage_apply(Abar, stages, r)), stages, hier
 
 
-def solve(system, opts: Options | None = None, ip: int = 0, it: int = 1) -> SolveResult:
+def solve(system, opts: Options | None = None, ip: int = 0, it: int = 1,
+          previous: "SolveResult | None" = None) -> SolveResult:
     """Left-scale (Eq. splitPrec1), build the right preconditioner, run
-    right-preconditioned GMRES/FGMRES on Abar x = bbar (Eq. splitPrec2)."""
+    right-preconditioned GMRES/FGMRES on Abar x = bbar (Eq. splitPrec2).
+    ``previous``: the result for the previous system of a sequence on the same
+    pattern, whose AMG hierarchies are offered for reuse."""
     opts = opts or Options()
     A = bsr_of(system)
     dec = decouple(A, system.rhs, ip, it, opts.variant)
-    apply, _, hier = build_preconditioner(dec, opts)
+    info = {"state": dict(previous.reuse_state) if previous else {}}
+    apply, _, hier = build_preconditioner(dec, opts, previous.hierarchies if previous else None, info)
     res = gmres(dec.Abar.matvec, dec.rhsbar, apply, opts.restart, opts.rtol, opts.max_iters,
                 flexible=(opts.krylov == FGMRES))
     r = system.rhs - A.matvec(res.x)
     unscaled = float(np.linalg.norm(r) / np.linalg.norm(system.rhs))
     return SolveResult(res.x, res.iterations, res.restarts, res.converged, res.true_rel_res, unscaled,
-                       res.history, hier, dec)
+                       res.history, hier, dec, info.get("rho", {}), info.get("reused", {}), info.get("state", {}))

@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
             "cptr_amg_level_info": [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)],
             "cptr_amg_level_copy": [P, I32, I32, P, P, P, P, P, P, P],
             "cptr_amg_vcycle": [P, I32, P, P],
+            "cptr_amg_conv_factor": [P, I32, I32, ctypes.c_uint64, ctypes.POINTER(D)],
             "cptr_precond_apply": [P, P, P],
             "cptr_get_scaled": [P, P, P, P],
         }
@@ -222,6 +223,11 @@ class Solver:
         x = torch.empty_like(bb)
         _check(lib().cptr_amg_vcycle(self.ctx, which, _ptr(bb), _ptr(x)))
         return x
+
+    def conv_factor(self, which: int, cycles: int = 10, seed: int = 0) -> float:
+        rho = ctypes.c_double(0.0)
+        _check(lib().cptr_amg_conv_factor(self.ctx, which, cycles, ctypes.c_uint64(seed), ctypes.byref(rho)))
+        return rho.value
 
     def precond_apply(self, r):
         import torch

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -58,6 +59,12 @@ struct cptr_ctx {
     DBuf<float> dinv32;
     // scalar stages: 0 = temperature (C_TT), 1 = pressure (B_PP)
     Hierarchy H[2];
+    DBuf<double> ctt, bpp;          // level-0 values of the two scalar operators
+    double rho[2] = {-1.0, -1.0};   // V-cycle convergence factors measured by update_values
+    int reused = 0;                 // bit k: hierarchy k was kept by the last update_values
+    // reuse trials after a rejection: the next skip[k] updates rebuild
+    // hierarchy k without a trial; skip doubles with every rejection in a row
+    int skip_left[2] = {0, 0}, backoff[2] = {1, 1};
     DBuf<double> tw;
     DBuf<float> tw32;
     // Krylov workspace
@@ -196,6 +203,48 @@ static void level_vectors(Level &L, int n, bool fp32) {
     }
 }
 
+// coarsest level: dense inverse (FP64, plus an FP32 copy for the precision split)
+static void coarse_inverse(Builder *c, Hierarchy &h) {
+    hipStream_t s = c->stream;
+    const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
+    Level &Lc = h.L.back();
+    const int nc = Lc.A.n;
+    if (nc > MAX_COARSE_DENSE)
+        throw Error(CPTR_E_ARG, "coarsest AMG level has " + std::to_string(nc) +
+                                    " rows (more than the dense limit); raise amg_max_levels or lower amg_max_coarse");
+    h.ncoarse = nc;
+    h.cinv.alloc((size_t)nc * nc);
+    if (fp32) h.cinv32.alloc((size_t)nc * nc);
+    DBuf<double> aug;
+    DBuf<int> used, piv;
+    aug.alloc((size_t)nc * 2 * nc);
+    used.alloc(nc);
+    piv.alloc(nc);
+    amg_dense_inverse(nc, Lc.A.rp, Lc.A.ci, Lc.A.v.p, aug.p, used.p, piv.p, c->flag.p, h.cinv.p,
+                      fp32 ? h.cinv32.p : nullptr, s);
+    int f = read_flag_and_clear(c);
+    if (f & 64) throw Error(CPTR_E_SINGULAR_BLOCK, "singular coarsest AMG operator");
+    if (f & 32) throw Error(CPTR_E_SINGULAR_BLOCK, "zero diagonal in an AMG level");
+}
+
+// FP32 copies of every level's operator, smoother diagonal and transfer operators
+static void hierarchy_fp32(Builder *c, Hierarchy &h) {
+    if (c->opt.precond_precision != CPTR_FP32) return;
+    hipStream_t s = c->stream;
+    for (auto &L : h.L) {
+        L.A.v32.alloc((size_t)L.A.nnz + 1);
+        to_float(L.A.v.p, L.A.v32.p, L.A.nnz, s);
+        L.dinv32.alloc(L.A.n);
+        to_float(L.dinv.p, L.dinv32.p, L.A.n, s);
+        if (L.P.nnz) {
+            L.P.v32.alloc(L.P.nnz);
+            to_float(L.P.v.p, L.P.v32.p, L.P.nnz, s);
+            L.R.v32.alloc(L.R.nnz);
+            to_float(L.R.v.p, L.R.v32.p, L.R.nnz, s);
+        }
+    }
+}
+
 // Build the hierarchy of a scalar operator whose level-0 pattern is the BSR
 // pattern (rp, ci owned by the context) and whose values are `vals` (copied).
 static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
@@ -286,41 +335,37 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
         csr_spgemm(c, L.R, AP, nxt.A);
         h.L.push_back(std::move(nxt));
     }
-    // coarsest level: dense inverse
-    Level &Lc = h.L.back();
-    const int nc = Lc.A.n;
-    if (nc > MAX_COARSE_DENSE)
-        throw Error(CPTR_E_ARG, "coarsest AMG level has " + std::to_string(nc) +
-                                    " rows (more than the dense limit); raise amg_max_levels or lower amg_max_coarse");
-    h.ncoarse = nc;
-    h.cinv.alloc((size_t)nc * nc);
-    if (fp32) h.cinv32.alloc((size_t)nc * nc);
-    DBuf<double> aug;
-    DBuf<int> used, piv;
-    aug.alloc((size_t)nc * 2 * nc);
-    used.alloc(nc);
-    piv.alloc(nc);
-    amg_dense_inverse(nc, Lc.A.rp, Lc.A.ci, Lc.A.v.p, aug.p, used.p, piv.p, c->flag.p, h.cinv.p,
-                      fp32 ? h.cinv32.p : nullptr, s);
-    int f = read_flag_and_clear(c);
-    if (f & 64) throw Error(CPTR_E_SINGULAR_BLOCK, "singular coarsest AMG operator");
-    if (f & 32) throw Error(CPTR_E_SINGULAR_BLOCK, "zero diagonal in an AMG level");
-    if (fp32) {
-        for (auto &L : h.L) {
-            L.A.v32.alloc((size_t)L.A.nnz + 1);
-            to_float(L.A.v.p, L.A.v32.p, L.A.nnz, s);
-            L.dinv32.alloc(L.A.n);
-            to_float(L.dinv.p, L.dinv32.p, L.A.n, s);
-            if (L.P.nnz) {
-                L.P.v32.alloc(L.P.nnz);
-                to_float(L.P.v.p, L.P.v32.p, L.P.nnz, s);
-                L.R.v32.alloc(L.R.nnz);
-                to_float(L.R.v.p, L.R.v32.p, L.R.nnz, s);
-            }
-        }
-    }
+    coarse_inverse(c, h);
+    hierarchy_fp32(c, h);
     CPTR_HIP(hipStreamSynchronize(s));
     h.built = true;
+}
+
+// Reuse of a hierarchy for new level-0 values on the same pattern (a Newton
+// sequence): the C/F splits and the interpolation / restriction operators of
+// every level are kept; the Galerkin products A_{l+1} = R_l A_l P_l, the
+// smoother diagonals and the coarsest inverse are recomputed from the new
+// values with the same kernels as a full setup.
+static void refresh_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
+    hipStream_t s = c->stream;
+    const cptr_options &o = c->opt;
+    if (!h.built || h.L.empty()) throw Error(CPTR_E_STATE, "no hierarchy to reuse");
+    Level &L0 = h.L[0];
+    CPTR_HIP(hipMemcpyAsync(L0.A.v.p, vals, sizeof(double) * c->nnzb, hipMemcpyDeviceToDevice, s));
+    for (size_t l = 0; l < h.L.size(); ++l) {
+        Level &L = h.L[l];
+        const int m = L.A.n;
+        c->s_d1.alloc(m);
+        amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
+        if (l + 1 == h.L.size()) break;
+        CsrD AP, Ac;
+        csr_spgemm(c, L.A, L.P, AP);
+        csr_spgemm(c, L.R, AP, Ac);
+        h.L[l + 1].A = std::move(Ac);
+    }
+    coarse_inverse(c, h);
+    hierarchy_fp32(c, h);
+    CPTR_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------------------
@@ -343,8 +388,7 @@ template <> struct Prec<float> {
 };
 
 template <class T>
-static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl) {
-    hipStream_t s = c->stream;
+static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     Level &L = h.L[lvl];
     const int n = L.A.n;
     T *x = Prec<T>::x(L);
@@ -377,7 +421,7 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl) {
     }
     Level &Ln = h.L[lvl + 1];
     vc_spmv<T>(L.R.n, L.R.rp, L.R.ci, Prec<T>::v(L.R), r, Prec<T>::b(Ln), s);
-    T *xc = vcycle<T>(c, h, lvl + 1);
+    T *xc = vcycle<T>(c, h, lvl + 1, s);
     if (o.post_sweeps == 0) {
         vc_prolong_add<T>(n, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, s);
     } else {
@@ -421,11 +465,11 @@ static void precond_apply(cptr_ctx *c, const double *r, double *y) {
         // M1: gather, V-cycle
         ms_stage_input<T>(n, b, c->rp.p, c->ci.p, (const T *)nullptr, comp1, r, (const T *)nullptr,
                           Prec<T>::b(h1.L[0]), s);
-        const T *x1 = vcycle<T>(c, h1, 0);
+        const T *x1 = vcycle<T>(c, h1, 0, s);
         c->mark(1);
         // M2 on z = r - Abar x (only its comp2 entries are needed)
         ms_stage_input<T>(n, b, c->rp.p, c->ci.p, t_first ? slabT : slabP, comp2, r, x1, Prec<T>::b(h2.L[0]), s);
-        const T *x2 = vcycle<T>(c, h2, 0);
+        const T *x2 = vcycle<T>(c, h2, 0, s);
         c->mark(2);
         xT = t_first ? x1 : x2;
         vP = t_first ? x2 : x1;
@@ -433,7 +477,7 @@ static void precond_apply(cptr_ctx *c, const double *r, double *y) {
         Hierarchy &hp = c->H[1];
         ms_stage_input<T>(n, b, c->rp.p, c->ci.p, (const T *)nullptr, c->ip, r, (const T *)nullptr,
                           Prec<T>::b(hp.L[0]), s);
-        vP = vcycle<T>(c, hp, 0);
+        vP = vcycle<T>(c, hp, 0, s);
         c->mark(1);
         c->mark(2);
     } else {
@@ -454,6 +498,38 @@ static void precond(cptr_ctx *c, const double *r, double *y) {
         precond_apply<double>(c, r, y);
 }
 
+// Asymptotic V-cycle convergence factor of a hierarchy on A e = 0:
+// e <- e - V(A e) from a SplitMix64-uniform start in [-1, 1), K cycles,
+// rho = (|e_K| / |e_0|)^(1/K).  FP64 V-cycles on stream s.
+static double conv_factor(cptr_ctx *c, Hierarchy &h, int cycles, uint64_t seed, hipStream_t s) {
+    Level &L0 = h.L[0];
+    const int n = L0.A.n;
+    DBuf<double> e, part, nrm;
+    e.alloc(n);
+    const int nblk = kr_nblk(n);
+    part.alloc(nblk);
+    nrm.alloc(2);
+    vc_hash_uniform(n, seed, e.p, s);
+    kr_norm2_partial(n, e.p, part.p, nblk, s);
+    kr_reduce(part.p, nblk, 1, nrm.p, s);
+    for (int k = 0; k < cycles; ++k) {
+        vc_spmv<double>(n, L0.A.rp, L0.A.ci, L0.A.v.p, e.p, L0.b.p, s);
+        const double *x = vcycle<double>(c, h, 0, s);
+        vc_sub(n, x, e.p, s);
+    }
+    kr_norm2_partial(n, e.p, part.p, nblk, s);
+    kr_reduce(part.p, nblk, 1, nrm.p + 1, s);
+    double v[2];
+    CPTR_HIP(hipMemcpyAsync(v, nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CPTR_HIP(hipStreamSynchronize(s));
+    if (!(v[0] > 0.0)) return 0.0;
+    return std::pow(std::sqrt(v[1]) / std::sqrt(v[0]), 1.0 / cycles);
+}
+
+constexpr int RHO_CYCLES = 10;
+constexpr int MAX_REUSE_BACKOFF = 8;
+constexpr uint64_t RHO_SEED = 0;
+
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
@@ -470,7 +546,7 @@ static void validate_options(const cptr_options &o) {
     if (o.pre_sweeps < 0 || o.post_sweeps < 0) throw Error(CPTR_E_ARG, "negative smoothing sweeps");
 }
 
-static void do_setup_values(cptr_ctx *c, const double *vals) {
+static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     hipStream_t s = c->stream;
     const int n = c->n, b = c->b, nnzb = c->nnzb;
     const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
@@ -484,7 +560,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
     fill_int(c->s_i4.p, 0x7fffffff, 1, s);
     c->slabT.alloc((size_t)nnzb * b);
     c->slabP.alloc((size_t)nnzb * b);
-    DBuf<double> ctt, bpp;
+    DBuf<double> &ctt = c->ctt, &bpp = c->bpp;
     ctt.alloc(nnzb);
     bpp.alloc(nnzb);
     if (fp32) {
@@ -510,6 +586,20 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
     const bool need[2] = {c->opt.variant == CPTR_VARIANT_CPTR3,
                           c->opt.variant == CPTR_VARIANT_CPTR3 || c->opt.variant == CPTR_VARIANT_CPR};
     const double *svals[2] = {ctt.p, bpp.p};
+    bool refresh[2] = {false, false};
+    for (int k = 0; k < 2; ++k) {
+        refresh[k] = need[k] && reuse && c->H[k].built;
+        if (!reuse) {
+            c->skip_left[k] = 0;
+            c->backoff[k] = 1;
+        } else if (refresh[k] && c->skip_left[k] > 0) {
+            --c->skip_left[k];
+            refresh[k] = false;
+        }
+    }
+    std::atomic<int> kept{0};
+    c->reused = 0;
+    c->rho[0] = c->rho[1] = -1.0;
     CPTR_HIP(hipEventRecord(c->ev_dec, s));
     std::exception_ptr err[2];
     std::thread th[2];
@@ -522,7 +612,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
         B.nnzb = nnzb;
         B.rp.p = c->rp.p;
         B.ci.p = c->ci.p;
-        th[k] = std::thread([c, k, &B, &svals, &err]() {
+        th[k] = std::thread([c, k, &B, &svals, &err, &refresh, &kept]() {
             try {
                 CPTR_HIP(hipSetDevice(c->device));
                 StreamScope scope(B.stream);
@@ -531,7 +621,23 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
                     fill_int(B.flag.p, 0, 1, B.stream);
                 }
                 CPTR_HIP(hipStreamWaitEvent(B.stream, c->ev_dec, 0));
-                build_hierarchy(&B, c->H[k], svals[k]);
+                if (refresh[k]) {
+                    // reuse decision: keep the refreshed hierarchy while its
+                    // measured V-cycle convergence factor stays below the
+                    // threshold, else build it anew
+                    refresh_hierarchy(&B, c->H[k], svals[k]);
+                    c->rho[k] = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
+                    if (c->rho[k] < c->opt.reuse_rho_max) {
+                        kept.fetch_or(1 << k);
+                        c->backoff[k] = 1;
+                    } else {
+                        c->skip_left[k] = c->backoff[k];
+                        c->backoff[k] = std::min(2 * c->backoff[k], MAX_REUSE_BACKOFF);
+                        build_hierarchy(&B, c->H[k], svals[k]);
+                    }
+                } else {
+                    build_hierarchy(&B, c->H[k], svals[k]);
+                }
                 CPTR_HIP(hipEventRecord(c->ev_side[k], B.stream));
             } catch (...) {
                 err[k] = std::current_exception();
@@ -556,6 +662,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals) {
         if (th[k].joinable()) th[k].join();
     for (int k = 0; k < 2; ++k)
         if (err[k]) std::rethrow_exception(err[k]);
+    c->reused = kept.load();
     for (int k = 0; k < 2; ++k)
         if (need[k]) CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[k], 0));
     if (bad != 0x7fffffff)
@@ -835,7 +942,12 @@ cptr_status cptr_setup(cptr_ctx *c, int32_t n, int32_t b, int32_t nnzb, const in
         if (read_flag_and_clear(c) & 128)
             throw Error(CPTR_E_ARG, "BILU(0) tile order needs a 5-point grid pattern; use block Jacobi");
     }
-    do_setup_values(c, d_vals);
+    for (auto &h : c->H) h.built = false;
+    c->rho[0] = c->rho[1] = -1.0;
+    c->reused = 0;
+    c->skip_left[0] = c->skip_left[1] = 0;
+    c->backoff[0] = c->backoff[1] = 1;
+    do_setup_values(c, d_vals, false);
     alloc_krylov(c);
     CPTR_HIP(hipEventRecord(c->ev1, s));
     CPTR_HIP(hipEventSynchronize(c->ev1));
@@ -852,8 +964,11 @@ cptr_status cptr_update_values(cptr_ctx *c, const double *d_vals) {
     StreamScope scope(c ? c->stream : nullptr);
     if (!c || !c->ready) throw Error(CPTR_E_STATE, "update_values before setup");
     CPTR_HIP(hipSetDevice(c->device));
+    if (!d_vals) throw Error(CPTR_E_ARG, "null matrix pointer");
     CPTR_HIP(hipEventRecord(c->ev0, c->stream));
-    do_setup_values(c, d_vals);
+    c->ready = false;
+    do_setup_values(c, d_vals, c->opt.reuse_rho_max > 0.0);
+    c->ready = true;
     CPTR_HIP(hipEventRecord(c->ev1, c->stream));
     CPTR_HIP(hipEventSynchronize(c->ev1));
     float ms = 0.f;
@@ -898,6 +1013,9 @@ cptr_status cptr_solve(cptr_ctx *c, const double *d_rhs, double *d_x, cptr_resul
     res.setup_ms = c->last_setup_ms;
     res.levels_T = (int)c->H[0].L.size();
     res.levels_P = (int)c->H[1].L.size();
+    res.rho_T = c->rho[0];
+    res.rho_P = c->rho[1];
+    res.reused = c->reused;
     if (out) *out = res;
     return st;
     CPTR_API_END
@@ -1006,9 +1124,21 @@ cptr_status cptr_amg_vcycle(cptr_ctx *c, int32_t which, const double *d_b, doubl
     hipStream_t s = c->stream;
     const int n = h.L[0].A.n;
     CPTR_HIP(hipMemcpyAsync(h.L[0].b.p, d_b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    double *x = vcycle<double>(c, h, 0);
+    double *x = vcycle<double>(c, h, 0, s);
     CPTR_HIP(hipMemcpyAsync(d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     CPTR_HIP(hipStreamSynchronize(s));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_amg_conv_factor(cptr_ctx *c, int32_t which, int32_t cycles, uint64_t seed, double *rho) {
+    CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
+    Hierarchy &h = pick(c, which);
+    if (cycles < 1 || cycles > 1000) throw Error(CPTR_E_ARG, "cycles must be 1..1000");
+    if (!rho) throw Error(CPTR_E_ARG, "null output");
+    CPTR_HIP(hipSetDevice(c->device));
+    *rho = conv_factor(c, h, cycles, seed, c->stream);
     return CPTR_OK;
     CPTR_API_END
 }

@@ -198,6 +198,9 @@ template <class T>
 void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *slab, int comp, const double *r,
                     const T *xs, T *out, hipStream_t st);
 
+void vc_hash_uniform(int n, uint64_t seed, double *e, hipStream_t st);
+void vc_sub(int n, const double *x, double *e, hipStream_t st);
+
 // k_bilu.hip: BILU(0) in tile order / block Jacobi
 struct TileSched {
     int nx = 0, ny = 0, tx = 0, ty = 0, ntx = 0, nty = 0;

@@ -183,6 +183,40 @@ void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *slab, i
     CPTR_CHECK_LAUNCH();
 }
 
+// start vector of the convergence-factor measurement: SplitMix64 of
+// (seed, i) mapped to a uniform double in [-1, 1) (53 random bits, exact)
+__device__ inline uint64_t vc_splitmix64(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_hash_uniform(int n, uint64_t seed, double *__restrict__ e) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t u = vc_splitmix64(seed, (uint64_t)i);
+    e[i] = (double)(u >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+
+void vc_hash_uniform(int n, uint64_t seed, double *e, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_hash_uniform, dim3(nblocks(n, 256)), dim3(256), 0, st, n, seed, e);
+    CPTR_CHECK_LAUNCH();
+}
+
+// e -= x
+__global__ void k_sub(int n, const double *__restrict__ x, double *__restrict__ e) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) e[i] -= x[i];
+}
+
+void vc_sub(int n, const double *x, double *e, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_sub, dim3(nblocks(n, 256)), dim3(256), 0, st, n, x, e);
+    CPTR_CHECK_LAUNCH();
+}
+
 #define INST(T)                                                                                                   \
     template void vc_presmooth_residual<T>(int, const int *, const int *, const T *, const T *, T, const T *, int, \
                                            int, T *, T *, hipStream_t);                                          \

@@ -307,12 +307,14 @@ def _flux_couplings(vals, b, nx, ny, slot, tx, ty, fx, fy, acc_col, coupling, rn
         pcol = np.zeros(b, bool); pcol[P_INDEX] = True
         cp = np.where(pcol, coef, 0.0)            # pressure derivatives: central
         cu = np.where(pcol, 0.0, coef)            # other unknowns: upwind (cell I)
-        np.add.at(vals, ii.reshape(-1), (cp + cu).reshape(-1, b, b))
-        np.add.at(vals, ij.reshape(-1), (-cp).reshape(-1, b, b))
-        np.add.at(vals, ji.reshape(-1), (-cp - cu).reshape(-1, b, b))
-        np.add.at(vals, jj.reshape(-1), cp.reshape(-1, b, b))
+        # each position occurs once per index array, so plain indexed adds
+        # equal unbuffered accumulation
+        vals[ii.reshape(-1)] += (cp + cu).reshape(-1, b, b)
+        vals[ij.reshape(-1)] += (-cp).reshape(-1, b, b)
+        vals[ji.reshape(-1)] += (-cp - cu).reshape(-1, b, b)
+        vals[jj.reshape(-1)] += cp.reshape(-1, b, b)
     xi = rng.uniform(-coupling, coupling, size=(ny, nx, b, b)) * off
-    np.add.at(vals, s_i.reshape(-1), (xi * acc_col[None, None, None, :]).reshape(-1, b, b))
+    vals[s_i.reshape(-1)] += (xi * acc_col[None, None, None, :]).reshape(-1, b, b)
 
 
 # ---------------------------------------------------------------------------
