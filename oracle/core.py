@@ -690,6 +690,7 @@ class Options:
     exact_last_stage: bool = False       # replace ilu(Abar) by an exact solve (tests only)
     reuse_rho_max: float = 0.3           # keep a reused AMG hierarchy while rho < this
     rho_cycles: int = 10
+    mlp_params: np.ndarray | None = None # learned T-interpolation weights (None = classical only)
 
 
 @dataclasses.dataclass
@@ -706,6 +707,7 @@ class SolveResult:
     rho: dict = dataclasses.field(default_factory=dict)      # measured for reused hierarchies
     reused: dict = dataclasses.field(default_factory=dict)   # name -> kept?
     reuse_state: dict = dataclasses.field(default_factory=dict)  # name -> (skip, backoff)
+    learned: dict = dataclasses.field(default_factory=dict)  # judge of the learned interpolation
 
 
 class _Direct:
@@ -770,6 +772,18 @@ def build_preconditioner(dec: Decoupled, opts: Options, previous: dict | None = 
             info.setdefault("state", {})[name] = (skip, backoff)
         if h is None:
             h = amg_setup(A, opts.amg)
+            if name == "T" and opts.mlp_params is not None and len(h.levels) > 1:
+                # the learned fine-level interpolation, judged by the V-cycle
+                # convergence factor against the classical one
+                from .learned import learned_interp
+                hl = amg_setup(A, opts.amg, learned_interp(opts.mlp_params))
+                rc = conv_factor(h, opts.rho_cycles, 0)
+                rl = conv_factor(hl, opts.rho_cycles, 0)
+                use = rl < rc
+                if info is not None:
+                    info["learned"] = dict(used=use, rho_classical=rc, rho_learned=rl)
+                if use:
+                    h = hl
         hier[name] = h
         return lambda rr, h=h: vcycle(h, rr)
 
@@ -818,4 +832,5 @@ def solve(system, opts: Options | None = None, ip: int = 0, it: int = 1,
     r = system.rhs - A.matvec(res.x)
     unscaled = float(np.linalg.norm(r) / np.linalg.norm(system.rhs))
     return SolveResult(res.x, res.iterations, res.restarts, res.converged, res.true_rel_res, unscaled,
-                       res.history, hier, dec, info.get("rho", {}), info.get("reused", {}), info.get("state", {}))
+                       res.history, hier, dec, info.get("rho", {}), info.get("reused", {}), info.get("state", {}),
+                       info.get("learned", {}))

@@ -5,3 +5,4 @@ solver consumes (see ``generator``)."""
 from .generator import (BSRSystem, P_INDEX, T_INDEX, assemble, tiny, config1, config2,
                         config3, config4_train, config5, config5_field, named,
                         CONFIG2_PECLET, CONFIG3_PECLET)
+from .mlp_init import mlp_init

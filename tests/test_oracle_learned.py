@@ -1,0 +1,157 @@
+"""Pins of the learned-interpolation oracle (features, network, loss gradient,
+Adam step, judge).  Its definitions are this build's, so the pins are
+closed forms, special cases and finite differences."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import learned as L
+from synthetic import mlp_init, tiny
+
+torch = pytest.importorskip("torch")
+
+
+def _poisson_1d(n):
+    rp = [0]
+    ci, v = [], []
+    for i in range(n):
+        for j, a in ((i - 1, -1.0), (i, 2.0), (i + 1, -1.0)):
+            if 0 <= j < n:
+                ci.append(j)
+                v.append(a)
+        rp.append(len(ci))
+    return O.CSR(n, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v))
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-6, 6, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.0e38, -1e-40]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(L.bf16(x), ref)
+
+
+def test_features_on_a_1d_poisson_row():
+    A = _poisson_1d(9)
+    s = O.strength(A, 0.25)
+    cf = np.array([1, 0, 1, 0, 1, 0, 1, 0, 1], np.int32)
+    P = O.interp_exti(A, s, cf, 4)
+    e = L.edge_features(A, s, cf, P)
+    assert list(e.frows) == [1, 3, 5, 7]
+    # row 3 (interior F point between C points 2 and 4): weights 1/2, 1/2
+    q = list(e.frows).index(3)
+    a, b = e.start[q], e.start[q + 1]
+    assert list(e.fine[a:b]) == [2, 4]
+    for x in e.X[a:b]:
+        expect = [-0.5, -0.5, 1.0, 0.0, 0.5, 0.0, 0.0, 0.5, 0.0, 1.0, 1.0, 0.5, 0.0, 1.0, 1.0, 0.0]
+        assert np.allclose(x, expect, rtol=0, atol=1e-15)
+    # row 1: its C neighbour 0 is a boundary point (row sum 1, so f12 = 1/2)
+    q = list(e.frows).index(1)
+    x0 = e.X[e.start[q]]
+    assert e.fine[e.start[q]] == 0 and x0[12] == 0.5
+
+
+def test_distance_two_edge_path_term():
+    """A 2-D 5-point Laplacian with C points on a diagonal pattern: the
+    path term of an edge sums a_ik a_kj / (a_ii a_kk) over common neighbours."""
+    s = tiny(6, 6, 2, peclet=1.0, seed=1)
+    Abar = O.decouple(O.bsr_of(s), s.rhs).Abar.scalar_block(1, 1)
+    st = O.strength(Abar, 0.25)
+    cf, _ = O.pmis(Abar, st, 0)
+    P = O.interp_exti(Abar, st, cf, 0)
+    e = L.edge_features(Abar, st, cf, P)
+    D = Abar.to_dense()
+    for k in range(len(e.row)):
+        i, j = e.row[k], e.fine[k]
+        path = sum(D[i, m] * D[m, j] / (D[i, i] * D[m, m]) for m in range(Abar.nrows)
+                   if m not in (i, j) and D[i, m] != 0 and D[m, j] != 0)
+        assert e.X[k, 5] == pytest.approx(path, rel=1e-12, abs=1e-15)
+        assert e.X[k, 3] == (0.0 if D[i, j] != 0 else 1.0)
+
+
+def _setup(seed=3, nx=20, ny=14, b=4):
+    s = tiny(nx, ny, b, peclet=5.0, seed=seed)
+    A = O.decouple(O.bsr_of(s), s.rhs).Abar.scalar_block(1, 1)
+    st = O.strength(A, 0.25)
+    cf, _ = O.pmis(A, st, 0)
+    P = O.interp_exti(A, st, cf, 4)
+    return A, st, cf, P, L.edge_features(A, st, cf, P)
+
+
+def test_zero_last_layer_reproduces_the_classical_weights():
+    A, st, cf, P, e = _setup()
+    p = L.unpack(mlp_init(0).astype(np.float64))
+    p["W3"][:] = 0.0
+    p["b3"][:] = 0.0
+    o, _ = L.forward(L.pack(p), e.X)
+    assert np.all(o == 0.0)
+    Pl = L.learned_weights(P, e, L.delta_of(o))
+    assert np.array_equal(Pl.v, P.v)
+
+
+def test_learned_row_sums_equal_the_classical_ones():
+    A, st, cf, P, e = _setup()
+    p = L.unpack(mlp_init(1).astype(np.float64))
+    p["W3"] *= 100.0            # a sizeable correction
+    o, _ = L.forward(L.pack(p), e.X)
+    d = L.delta_of(o)
+    assert np.max(np.abs(d)) > 0.05
+    Pl = L.learned_weights(P, e, d)
+    for q, i in enumerate(e.frows):
+        a, b = P.rp[i], P.rp[i + 1]
+        assert Pl.v[a:b].sum() == pytest.approx(P.v[a:b].sum(), rel=1e-12)
+
+
+def test_gradient_against_finite_differences():
+    A, st, cf, P, e = _setup(seed=4, nx=12, ny=10)
+    E = L.smooth_vectors(A, K=4, seed=2)
+    p = mlp_init(5).astype(np.float64)
+    q = L.unpack(p)
+    q["W3"] *= 50.0
+    q["b1"][:] = 0.05
+    p = L.pack(q)
+    loss, g = L.loss_and_grad(p, P, e, E, exact=True)
+    rng = np.random.default_rng(9)
+    idx = np.concatenate([rng.choice(L.NPARAMS, 40, replace=False), [L.NPARAMS - 1]])
+    for k in idx:
+        h = 1e-6 * max(1.0, abs(p[k]))
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (L.loss_and_grad(pp, P, e, E, exact=True)[0] - L.loss_and_grad(pm, P, e, E, exact=True)[0]) / (2 * h)
+        # central differences of an O(1) loss at h = 1e-6 carry ~1e-10 of rounding
+        assert abs(fd - g[k]) <= 1e-4 * abs(fd) + 2e-9, (k, fd, g[k])
+
+
+def test_loss_is_zero_for_exactly_interpolated_vectors():
+    """If every smooth vector is interpolated exactly by the weights, the
+    loss vanishes: vectors built as e_F = P e_C."""
+    A, st, cf, P, e = _setup()
+    p = L.unpack(mlp_init(0).astype(np.float64))
+    p["W3"][:] = 0.0
+    p["b3"][:] = 0.0
+    rng = np.random.default_rng(1)
+    ec = rng.standard_normal((3, P.ncols))
+    E = np.array([P.matvec(v) for v in ec])
+    loss, _ = L.loss_and_grad(L.pack(p), P, e, E)
+    assert loss < 1e-28
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    opt = L.Adam(lr=1e-3)
+    p = np.zeros(5)
+    g = np.array([2.0, -3.0, 1e-3, -1e-5, 0.0])
+    p1 = opt.step(p, g)
+    expect = -1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.allclose(p1, expect, rtol=1e-12, atol=0)
+
+
+def test_judge_keeps_classical_when_the_correction_is_zero():
+    s = tiny(32, 24, 4, peclet=5.0, seed=2)
+    p = L.unpack(mlp_init(0).astype(np.float64))
+    p["W3"][:] = 0.0
+    p["b3"][:] = 0.0
+    opts = O.Options(color=O.tile_colors(32, 24), amg=O.AMGOptions(max_coarse=30), mlp_params=L.pack(p))
+    r = O.solve(s, opts)
+    assert r.learned["rho_learned"] == r.learned["rho_classical"]
+    assert r.learned["used"] is False
