@@ -64,7 +64,10 @@ enum { CPTR_LAST_BILU0 = 0, CPTR_LAST_BJACOBI = 1 };
 enum { CPTR_GMRES = 0, CPTR_FGMRES = 1 };
 enum { CPTR_FP64 = 0, CPTR_FP32 = 1 };
 enum { CPTR_SMOOTH_JACOBI = 0, CPTR_SMOOTH_L1JACOBI = 1 };
-enum { CPTR_INTERP_CLASSICAL = 0, CPTR_INTERP_LEARNED = 1 };
+/* fine-level interpolation of the temperature AMG stage: classical
+ * extended+i, the learned correction judged against it by the V-cycle
+ * convergence factor, or the learned correction without the judge */
+enum { CPTR_INTERP_CLASSICAL = 0, CPTR_INTERP_LEARNED = 1, CPTR_INTERP_LEARNED_FORCED = 2 };
 
 typedef struct {
     int32_t variant;            /* CPTR_VARIANT_*                                 */
@@ -98,7 +101,8 @@ typedef struct {
     int32_t iterations;         /* Arnoldi steps over all restarts                */
     int32_t restarts;
     int32_t converged;
-    int32_t used_learned;
+    int32_t used_learned;       /* the temperature hierarchy uses the learned     */
+                                /* fine-level interpolation                       */
     double  rel_res_scaled;     /* |bbar - Abar x| / |bbar|, recomputed in FP64   */
     double  rel_res_unscaled;   /* |b - A x| / |b|                                */
     double  rho_T, rho_P;       /* convergence factors measured by the last       */
@@ -114,6 +118,9 @@ typedef struct {
     double  t_last_ms;          /* last stage (fused residual update + BILU/BJ)   */
     double  t_spmv_ms;          /* outer operator apply w = Abar z                */
     double  t_arnoldi_ms;       /* Gram-Schmidt, Givens, normalisation            */
+    /* learned interpolation judge of the last full temperature build        */
+    /* (-1: not measured)                                                    */
+    double  rho_T_classical, rho_T_learned;
 } cptr_result;
 
 /* Fill *opt with the defaults noted above (CPTR3, T then P, BILU(0) in 32x8
@@ -207,6 +214,64 @@ cptr_status cptr_precond_apply(cptr_ctx *ctx, const double *d_r, double *d_y);
 
 /* The scaled right-hand side and matrix held by the context (device copies). */
 cptr_status cptr_get_scaled(const cptr_ctx *ctx, double *d_abar, double *d_rhsbar_or_null, const double *d_rhs);
+
+/* ---------------------------------------------------------------------- */
+/* Learned fine-level interpolation of the temperature AMG stage (an        */
+/* extension of amg(C_TT), Eq. CPTR3M1).                                    */
+/*                                                                          */
+/* Edges are the F-row entries (i, J) of the classical extended+i           */
+/* interpolation of C_TT's fine level, in storage order.  Each edge has 16   */
+/* features (FP64 formulas, stored FP32):                                   */
+/*   0 a_ij/a_ii, 1 a_ji/a_jj, 2 (-s a_ij)/max_k(-s a_ik) with s = sign a_ii  */
+/*   (0 if that max <= 0), 3 1 if j is not a neighbour of i, 4 the classical  */
+/*   weight, 5 sum over neighbours k of i (k != j) coupled to j of            */
+/*   a_ik a_kj/(a_ii a_kk), 6 row sum of i / a_ii, 7 1/(edges of row i),     */
+/*   8 (a_ij - a_ji)/(|a_ij| + |a_ji|) (0 if both 0), 9 classical row sum,   */
+/*   10 weight / max |weight| of the row, 11 |a_jj|/(|a_ii| + |a_jj|),       */
+/*   12 row sum of j / a_jj, 13 strong couplings of i / (row length - 1),    */
+/*   14 1, 15 0.                                                            */
+/* The network 16 -> 64 -> 64 -> 1 (ReLU) has BF16 weights and runs on the  */
+/* matrix cores with FP32 accumulation; its input and first hidden layer are */
+/* rounded to BF16.  delta = tanh(o)/2 and w = w0 (1 + delta), rescaled to   */
+/* the classical row sum when the rescale factor lies in [1/4, 4].           */
+/* Parameters: float[CPTR_MLP_NPARAMS] host blob, W1[64][16], b1[64],        */
+/* W2[64][64], b2[64], W3[64], b3[1].                                       */
+/* ---------------------------------------------------------------------- */
+#define CPTR_MLP_NPARAMS 5313
+
+/* Parameters used by the next setups of ctx when options.t_interp is
+ * CPTR_INTERP_LEARNED (judged) or CPTR_INTERP_LEARNED_FORCED.  Host blob,
+ * copied; NULL removes them (classical interpolation only). */
+cptr_status cptr_load_mlp(cptr_ctx *ctx, const float *host_params);
+
+typedef struct cptr_mlp cptr_mlp;   /* trainable network: FP32 master weights, Adam moments */
+
+/* Create a trainable network on device `hip_device` from a host blob. */
+cptr_status cptr_mlp_create(cptr_mlp **mlp, int32_t hip_device, const float *host_params);
+
+/* Copy the current parameters and/or the last gradient to host (NULL skips). */
+cptr_status cptr_mlp_get(const cptr_mlp *mlp, float *host_params, float *host_grad);
+
+/* One training step on the temperature operator of a context set up with
+ * classical interpolation: K = n_vectors (1..16) smooth error vectors
+ * (20 damped-Jacobi sweeps, omega 2/3, on C_TT e = 0 from SplitMix64-uniform
+ * starts u(seed, k n + i)), loss = mean over F rows of
+ * sum_k (e_i - sum_J w_iJ e_j)^2 / sum_k e_i^2 with the corrected weights,
+ * gradient through the network (BF16 matrix-core products, FP32
+ * accumulation), then one Adam step (beta 0.9, 0.999, eps 1e-8) with
+ * learning rate lr.  *loss (host) receives the loss before the step.
+ * Runs on the context's stream. */
+cptr_status cptr_mlp_train_step(cptr_mlp *mlp, cptr_ctx *ctx, int32_t n_vectors, uint64_t seed, double lr,
+                                double *loss);
+
+/* Features and network outputs of the context's temperature edges (classical
+ * interpolation): host buffers of capacity cap edges (X: 16 floats per edge,
+ * o: one float per edge; either may be NULL); *n_edges receives the count.
+ * The outputs use mlp's parameters (o is skipped when mlp is NULL). */
+cptr_status cptr_mlp_edges(const cptr_mlp *mlp, cptr_ctx *ctx, float *host_X, float *host_o, int32_t cap,
+                           int32_t *n_edges);
+
+cptr_status cptr_mlp_destroy(cptr_mlp *mlp);
 
 #ifdef __cplusplus
 }

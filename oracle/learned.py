@@ -91,6 +91,14 @@ class Edges:
     start: np.ndarray    # edges of frows[q] are start[q]:start[q+1]
 
 
+def _seqsum(a) -> float:
+    """Left-to-right sum (the order the features are defined in)."""
+    s = 0.0
+    for x in a:
+        s += float(x)
+    return s
+
+
 def _entry(A: CSR, i: int, j: int):
     lo, hi = A.rp[i], A.rp[i + 1]
     k = lo + np.searchsorted(A.ci[lo:hi], j)
@@ -113,11 +121,11 @@ def edge_features(A: CSR, strong: np.ndarray, cf: np.ndarray, P: CSR) -> Edges:
         si = -1.0 if aii < 0 else 1.0
         offd = [(A.ci[e], A.v[e]) for e in range(lo, hi) if A.ci[e] != i]
         smax = max([-si * v for _, v in offd], default=0.0)
-        rowsum_i = float(np.sum(A.v[lo:hi]))
+        rowsum_i = _seqsum(A.v[lo:hi])
         nstrong = int(np.sum(strong[lo:hi]))
         plo, phi = P.rp[i], P.rp[i + 1]
         w0 = P.v[plo:phi]
-        S = float(np.sum(w0))
+        S = _seqsum(w0)
         wmax = float(np.max(np.abs(w0)))
         for e in range(plo, phi):
             j = int(fine_of[P.ci[e]])
@@ -146,7 +154,7 @@ def edge_features(A: CSR, strong: np.ndarray, cf: np.ndarray, P: CSR) -> Edges:
             x[9] = S
             x[10] = P.v[e] / wmax if wmax > 0 else 0.0
             x[11] = abs(ajj) / (abs(aii) + abs(ajj))
-            x[12] = float(np.sum(A.v[jlo:jhi])) / ajj
+            x[12] = _seqsum(A.v[jlo:jhi]) / ajj
             x[13] = nstrong / (hi - lo - 1) if hi - lo > 1 else 0.0
             x[14] = 1.0
             rows.append(i)

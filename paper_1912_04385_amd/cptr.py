@@ -21,7 +21,8 @@ LAST_BILU0, LAST_BJACOBI = 0, 1
 GMRES, FGMRES = 0, 1
 FP64, FP32 = 0, 1
 SMOOTH_JACOBI, SMOOTH_L1JACOBI = 0, 1
-INTERP_CLASSICAL, INTERP_LEARNED = 0, 1
+INTERP_CLASSICAL, INTERP_LEARNED, INTERP_LEARNED_FORCED = 0, 1, 2
+MLP_NPARAMS = 5313
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_HIP", -3: "E_SINGULAR_BLOCK",
           -4: "E_NONFINITE", -5: "E_OOM", -6: "E_STATE"}
@@ -55,6 +56,7 @@ class Result(ctypes.Structure):
         ("levels_P", ctypes.c_int32), ("reused", ctypes.c_int32), ("timed_steps", ctypes.c_int32),
         ("t_stage1_ms", ctypes.c_double), ("t_stage2_ms", ctypes.c_double), ("t_last_ms", ctypes.c_double),
         ("t_spmv_ms", ctypes.c_double), ("t_arnoldi_ms", ctypes.c_double),
+        ("rho_T_classical", ctypes.c_double), ("rho_T_learned", ctypes.c_double),
     ]
 
     def to_dict(self) -> dict:
@@ -89,6 +91,12 @@ def lib() -> ctypes.CDLL:
             "cptr_amg_conv_factor": [P, I32, I32, ctypes.c_uint64, ctypes.POINTER(D)],
             "cptr_precond_apply": [P, P, P],
             "cptr_get_scaled": [P, P, P, P],
+            "cptr_load_mlp": [P, P],
+            "cptr_mlp_create": [ctypes.POINTER(P), I32, P],
+            "cptr_mlp_get": [P, P, P],
+            "cptr_mlp_train_step": [P, P, I32, ctypes.c_uint64, D, ctypes.POINTER(D)],
+            "cptr_mlp_edges": [P, P, P, P, I32, ctypes.POINTER(I32)],
+            "cptr_mlp_destroy": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -168,6 +176,18 @@ class Solver:
         _check(lib().cptr_setup(self.ctx, self.n, self.b, nnzb, _ptr(self._rp), _ptr(self._ci), _ptr(v),
                                 p_index, T_index, nx, ny))
         return self
+
+    def load_mlp(self, params):
+        """Parameters of the learned temperature interpolation (float32 blob
+        of MLP_NPARAMS values; None removes them)."""
+        import numpy as np
+        if params is None:
+            _check(lib().cptr_load_mlp(self.ctx, None))
+            return
+        blob = np.ascontiguousarray(params, dtype=np.float32)
+        if blob.size != MLP_NPARAMS:
+            raise ValueError(f"need {MLP_NPARAMS} parameters, got {blob.size}")
+        _check(lib().cptr_load_mlp(self.ctx, blob.ctypes.data_as(ctypes.c_void_p)))
 
     def update_values(self, vals):
         import torch
@@ -295,3 +315,60 @@ def solver_for(system, **opts) -> Solver:
         s.close()
         raise
     return s
+
+
+class MLP:
+    """Trainable edge-MLP of the learned temperature interpolation (device
+    FP32 master weights and Adam moments)."""
+
+    def __init__(self, params, device: int = 0):
+        import numpy as np
+        import torch
+        torch.cuda.set_device(device)
+        blob = np.ascontiguousarray(params, dtype=np.float32)
+        if blob.size != MLP_NPARAMS:
+            raise ValueError(f"need {MLP_NPARAMS} parameters, got {blob.size}")
+        self.h = ctypes.c_void_p()
+        _check(lib().cptr_mlp_create(ctypes.byref(self.h), device, blob.ctypes.data_as(ctypes.c_void_p)))
+        _live_solvers.add(self)
+
+    def params(self):
+        import numpy as np
+        out = np.empty(MLP_NPARAMS, np.float32)
+        _check(lib().cptr_mlp_get(self.h, out.ctypes.data_as(ctypes.c_void_p), None))
+        return out
+
+    def grad(self):
+        import numpy as np
+        out = np.empty(MLP_NPARAMS, np.float32)
+        _check(lib().cptr_mlp_get(self.h, None, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def train_step(self, solver: "Solver", n_vectors: int = 8, seed: int = 0, lr: float = 1e-3) -> float:
+        loss = ctypes.c_double(0.0)
+        _check(lib().cptr_mlp_train_step(self.h, solver.ctx, n_vectors, ctypes.c_uint64(seed), lr,
+                                         ctypes.byref(loss)))
+        return loss.value
+
+    def edges(self, solver: "Solver", with_outputs: bool = True):
+        """(features [E, 16], outputs [E] or None) on the solver's temperature edges."""
+        import numpy as np
+        n = ctypes.c_int32()
+        _check(lib().cptr_mlp_edges(self.h, solver.ctx, None, None, 0, ctypes.byref(n)))
+        X = np.empty((max(n.value, 1), 16), np.float32)
+        o = np.empty(max(n.value, 1), np.float32)
+        _check(lib().cptr_mlp_edges(self.h, solver.ctx, X.ctypes.data_as(ctypes.c_void_p),
+                                    o.ctypes.data_as(ctypes.c_void_p) if with_outputs else None, n.value,
+                                    ctypes.byref(n)))
+        return X[: n.value], (o[: n.value] if with_outputs else None)
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            _check(lib().cptr_mlp_destroy(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -65,6 +65,11 @@ struct cptr_ctx {
     // reuse trials after a rejection: the next skip[k] updates rebuild
     // hierarchy k without a trial; skip doubles with every rejection in a row
     int skip_left[2] = {0, 0}, backoff[2] = {1, 1};
+    // learned temperature interpolation: parameters and the judge's measurements
+    DBuf<float> mlp;
+    bool have_mlp = false;
+    int used_learned = 0;
+    double rho_cls = -1.0, rho_lrn = -1.0;
     DBuf<double> tw;
     DBuf<float> tw32;
     // Krylov workspace
@@ -247,7 +252,52 @@ static void hierarchy_fp32(Builder *c, Hierarchy &h) {
 
 // Build the hierarchy of a scalar operator whose level-0 pattern is the BSR
 // pattern (rp, ci owned by the context) and whose values are `vals` (copied).
-static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
+// ---------------------------------------------------------------------------
+// learned fine-level interpolation (T stage): edges, features, MLP, weights
+// ---------------------------------------------------------------------------
+struct EdgeSet {
+    int nf = 0, E = 0;
+    DBuf<int> frows, estart, fine_of, cidx;
+    DBuf<float> X;
+};
+
+// the F-row edges of a level's (classical) interpolation and their features
+static void edges_build(hipStream_t s, const Level &L, EdgeSet &es) {
+    const int n = L.A.n;
+    DBuf<int> cnt, isf, erow, fpos;
+    cnt.alloc(n + 1);
+    isf.alloc(n + 1);
+    erow.alloc(n + 1);
+    fpos.alloc(n + 1);
+    es.cidx.alloc(n + 1);
+    es.fine_of.alloc(L.nc + 1);
+    scan_exclusive(L.cf.p, es.cidx.p, n, nullptr, s);
+    ln_edge_count(n, L.cf.p, es.cidx.p, L.P.rp, cnt.p, isf.p, es.fine_of.p, s);
+    scan_exclusive(cnt.p, erow.p, n, nullptr, s);
+    scan_exclusive(isf.p, fpos.p, n, nullptr, s);
+    es.E = read_scalar(erow.p + n, s);
+    es.nf = read_scalar(fpos.p + n, s);
+    es.frows.alloc(es.nf + 1);
+    es.estart.alloc(es.nf + 1);
+    ln_edge_rows(n, isf.p, fpos.p, erow.p, es.frows.p, es.estart.p, s);
+    es.X.alloc((size_t)es.E * MLP_NF + 1);
+    ln_edge_features(es.nf, es.frows.p, es.estart.p, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.P.rp, L.P.ci, L.P.v.p,
+                     es.fine_of.p, es.X.p, s);
+}
+
+// replace the F-row weights of level L's interpolation by the learned ones
+static void apply_learned(hipStream_t s, Level &L, const float *mlp) {
+    EdgeSet es;
+    edges_build(s, L, es);
+    if (es.E == 0) return;
+    DBuf<float> o;
+    o.alloc(es.E);
+    ln_mlp_forward(es.E, es.X.p, mlp, o.p, s);
+    ln_learned_weights(es.nf, es.frows.p, es.estart.p, L.P.rp, L.P.v.p, o.p, L.P.v.p, s);
+    CPTR_HIP(hipStreamSynchronize(s));
+}
+
+static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const float *mlp = nullptr) {
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     const bool fp32 = (o.precond_precision == CPTR_FP32);
@@ -328,6 +378,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
         P.rp = P.rp_own.p;
         P.ci = P.ci_own.p;
         L.nc = nc;
+        if (mlp && h.L.size() == 1) apply_learned(s, L, mlp);
         csr_transpose(c, P, L.R);
         CsrD AP;
         csr_spgemm(c, L.A, P, AP);
@@ -544,6 +595,37 @@ static void validate_options(const cptr_options &o) {
     if (o.amg_max_coarse < 1 || o.amg_max_levels < 1) throw Error(CPTR_E_ARG, "AMG size limits must be positive");
     if (o.ilu_tile_x < 1 || o.ilu_tile_y < 1) throw Error(CPTR_E_ARG, "ILU tile must be at least 1 x 1");
     if (o.pre_sweeps < 0 || o.post_sweeps < 0) throw Error(CPTR_E_ARG, "negative smoothing sweeps");
+    if (o.t_interp < CPTR_INTERP_CLASSICAL || o.t_interp > CPTR_INTERP_LEARNED_FORCED)
+        throw Error(CPTR_E_ARG, "unknown t_interp");
+    if (o.t_interp != CPTR_INTERP_CLASSICAL && (o.amg_pmax < 1 || o.amg_pmax > 16))
+        throw Error(CPTR_E_ARG, "learned interpolation needs amg_pmax in 1..16");
+}
+
+// A full build of hierarchy k.  For the temperature stage with learned
+// interpolation requested, the classical and the learned hierarchies are both
+// built and the learned one is kept only if its measured V-cycle convergence
+// factor is lower (CPTR_INTERP_LEARNED_FORCED keeps it without the judge).
+static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals) {
+    const bool learned = (k == 0) && c->have_mlp && c->opt.t_interp != CPTR_INTERP_CLASSICAL;
+    if (k == 0) {
+        c->used_learned = 0;
+        c->rho_cls = c->rho_lrn = -1.0;
+    }
+    build_hierarchy(&B, c->H[k], vals);
+    if (!learned || c->H[k].L.size() < 2) return;
+    Hierarchy hl;
+    build_hierarchy(&B, hl, vals, c->mlp.p);
+    if (c->opt.t_interp == CPTR_INTERP_LEARNED_FORCED) {
+        c->H[k] = std::move(hl);
+        c->used_learned = 1;
+        return;
+    }
+    c->rho_cls = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
+    c->rho_lrn = conv_factor(c, hl, RHO_CYCLES, RHO_SEED, B.stream);
+    if (c->rho_lrn < c->rho_cls) {
+        c->H[k] = std::move(hl);
+        c->used_learned = 1;
+    }
 }
 
 static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
@@ -633,10 +715,10 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                     } else {
                         c->skip_left[k] = c->backoff[k];
                         c->backoff[k] = std::min(2 * c->backoff[k], MAX_REUSE_BACKOFF);
-                        build_hierarchy(&B, c->H[k], svals[k]);
+                        full_build(c, B, k, svals[k]);
                     }
                 } else {
-                    build_hierarchy(&B, c->H[k], svals[k]);
+                    full_build(c, B, k, svals[k]);
                 }
                 CPTR_HIP(hipEventRecord(c->ev_side[k], B.stream));
             } catch (...) {
@@ -1016,6 +1098,9 @@ cptr_status cptr_solve(cptr_ctx *c, const double *d_rhs, double *d_x, cptr_resul
     res.rho_T = c->rho[0];
     res.rho_P = c->rho[1];
     res.reused = c->reused;
+    res.used_learned = c->used_learned;
+    res.rho_T_classical = c->rho_cls;
+    res.rho_T_learned = c->rho_lrn;
     if (out) *out = res;
     return st;
     CPTR_API_END
@@ -1167,6 +1252,161 @@ cptr_status cptr_get_scaled(const cptr_ctx *c, double *d_abar, double *d_rhsbar,
             CPTR_HIP(hipMemcpyAsync(d_rhsbar, d_rhs, sizeof(double) * c->n * c->b, hipMemcpyDeviceToDevice, s));
         else
             launch_scale_rhs(c->opt.variant, c->n, c->b, d_rhs, c->ip, c->it, c->wp.p, c->wt.p, c->beta.p, d_rhsbar, s);
+    }
+    CPTR_HIP(hipStreamSynchronize(s));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+struct cptr_mlp {
+    int device = 0;
+    DBuf<float> p, m, v, g;
+    int t = 0;
+};
+
+static Level &train_level(cptr_ctx *c) {
+    if (!c || !c->ready) throw Error(CPTR_E_STATE, "context not set up");
+    if (!c->H[0].built || c->H[0].L.size() < 2)
+        throw Error(CPTR_E_STATE, "the temperature hierarchy has a single level (no interpolation)");
+    if (c->used_learned) throw Error(CPTR_E_STATE, "the temperature interpolation is the learned one, not classical");
+    if (c->opt.amg_pmax < 1 || c->opt.amg_pmax > 16)
+        throw Error(CPTR_E_ARG, "the learned interpolation needs amg_pmax in 1..16 (edges per row)");
+    return c->H[0].L[0];
+}
+
+cptr_status cptr_load_mlp(cptr_ctx *c, const float *host_params) {
+    CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
+    if (!c) throw Error(CPTR_E_ARG, "null context");
+    CPTR_HIP(hipSetDevice(c->device));
+    if (!host_params) {
+        c->have_mlp = false;
+        return CPTR_OK;
+    }
+    c->mlp.alloc(MLP_NPARAMS);
+    CPTR_HIP(hipMemcpyAsync(c->mlp.p, host_params, sizeof(float) * MLP_NPARAMS, hipMemcpyHostToDevice, c->stream));
+    CPTR_HIP(hipStreamSynchronize(c->stream));
+    c->have_mlp = true;
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_mlp_create(cptr_mlp **out, int32_t dev, const float *host_params) {
+    CPTR_API_BEGIN
+    if (!out || !host_params) throw Error(CPTR_E_ARG, "null argument");
+    *out = nullptr;
+    int ndev = 0;
+    CPTR_HIP(hipGetDeviceCount(&ndev));
+    if (dev < 0 || dev >= ndev) throw Error(CPTR_E_ARG, "invalid HIP device");
+    CPTR_HIP(hipSetDevice(dev));
+    StreamScope scope(nullptr);
+    auto m = std::make_unique<cptr_mlp>();
+    m->device = dev;
+    m->p.alloc(MLP_NPARAMS);
+    m->m.alloc(MLP_NPARAMS);
+    m->v.alloc(MLP_NPARAMS);
+    m->g.alloc(MLP_NPARAMS);
+    CPTR_HIP(hipMemcpy(m->p.p, host_params, sizeof(float) * MLP_NPARAMS, hipMemcpyHostToDevice));
+    CPTR_HIP(hipMemset(m->m.p, 0, sizeof(float) * MLP_NPARAMS));
+    CPTR_HIP(hipMemset(m->v.p, 0, sizeof(float) * MLP_NPARAMS));
+    CPTR_HIP(hipMemset(m->g.p, 0, sizeof(float) * MLP_NPARAMS));
+    *out = m.release();
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_mlp_get(const cptr_mlp *m, float *host_params, float *host_grad) {
+    CPTR_API_BEGIN
+    if (!m) throw Error(CPTR_E_ARG, "null network");
+    CPTR_HIP(hipSetDevice(m->device));
+    CPTR_HIP(hipDeviceSynchronize());
+    if (host_params)
+        CPTR_HIP(hipMemcpy(host_params, m->p.p, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToHost));
+    if (host_grad) CPTR_HIP(hipMemcpy(host_grad, m->g.p, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToHost));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_mlp_destroy(cptr_mlp *m) {
+    CPTR_API_BEGIN
+    if (!m) return CPTR_OK;
+    CPTR_HIP(hipSetDevice(m->device));
+    CPTR_HIP(hipDeviceSynchronize());
+    StreamScope scope(nullptr);
+    delete m;
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_mlp_train_step(cptr_mlp *m, cptr_ctx *c, int32_t K, uint64_t seed, double lr, double *loss) {
+    CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
+    if (!m) throw Error(CPTR_E_ARG, "null network");
+    if (K < 1 || K > 16) throw Error(CPTR_E_ARG, "n_vectors must be 1..16");
+    if (!(lr > 0.0)) throw Error(CPTR_E_ARG, "learning rate must be positive");
+    Level &L = train_level(c);
+    if (m->device != c->device) throw Error(CPTR_E_ARG, "network and context on different devices");
+    CPTR_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int n = L.A.n;
+    EdgeSet es;
+    edges_build(s, L, es);
+    if (es.E == 0 || es.nf == 0) throw Error(CPTR_E_STATE, "no F-row edges to train on");
+    // smooth vectors
+    DBuf<double> Ev, tmp;
+    Ev.alloc((size_t)K * n);
+    tmp.alloc(n);
+    vc_hash_uniform(K * n, seed, Ev.p, s);
+    for (int k = 0; k < K; ++k) {
+        double *e = Ev.p + (size_t)k * n;
+        for (int sw = 0; sw < 20; sw += 2) {
+            ln_jacobi_zero(n, L.A.rp, L.A.ci, L.A.v.p, 2.0 / 3.0, e, tmp.p, s);
+            ln_jacobi_zero(n, L.A.rp, L.A.ci, L.A.v.p, 2.0 / 3.0, tmp.p, e, s);
+        }
+    }
+    // forward, loss and dL/do, backward, reduction, Adam
+    DBuf<float> o, dout, part;
+    DBuf<double> lrow, lsum;
+    o.alloc(es.E);
+    dout.alloc(es.E);
+    lrow.alloc(es.nf);
+    lsum.alloc(1);
+    ln_mlp_forward(es.E, es.X.p, m->p.p, o.p, s);
+    ln_interp_loss(es.nf, n, K, es.frows.p, es.estart.p, L.P.rp, L.P.ci, L.P.v.p, es.fine_of.p, Ev.p, o.p, lrow.p,
+                   dout.p, s);
+    kr_reduce(lrow.p, es.nf, 1, lsum.p, s);
+    const int nw = ln_mlp_waves(es.E);
+    part.alloc((size_t)nw * MLP_NPARAMS);
+    ln_mlp_backward(es.E, es.X.p, m->p.p, dout.p, part.p, s);
+    ln_grad_reduce(nw, part.p, m->g.p, s);
+    m->t += 1;
+    ln_adam(m->p.p, m->m.p, m->v.p, m->g.p, lr, 0.9, 0.999, 1e-8, m->t, s);
+    const double tot = read_scalar(lsum.p, s);
+    if (loss) *loss = tot / es.nf;
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_mlp_edges(const cptr_mlp *m, cptr_ctx *c, float *host_X, float *host_o, int32_t cap,
+                           int32_t *n_edges) {
+    CPTR_API_BEGIN
+    StreamScope scope(c ? c->stream : nullptr);
+    if (!n_edges) throw Error(CPTR_E_ARG, "null count");
+    Level &L = train_level(c);
+    CPTR_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    EdgeSet es;
+    edges_build(s, L, es);
+    *n_edges = es.E;
+    const int k = std::min(es.E, (int)std::max(cap, 0));
+    if (host_X && k > 0)
+        CPTR_HIP(hipMemcpyAsync(host_X, es.X.p, sizeof(float) * MLP_NF * k, hipMemcpyDeviceToHost, s));
+    if (host_o && m && k > 0) {
+        DBuf<float> o;
+        o.alloc(es.E);
+        ln_mlp_forward(es.E, es.X.p, m->p.p, o.p, s);
+        CPTR_HIP(hipMemcpyAsync(host_o, o.p, sizeof(float) * k, hipMemcpyDeviceToHost, s));
+        CPTR_HIP(hipStreamSynchronize(s));
     }
     CPTR_HIP(hipStreamSynchronize(s));
     return CPTR_OK;

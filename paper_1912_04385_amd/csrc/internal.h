@@ -201,6 +201,32 @@ void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *slab, i
 void vc_hash_uniform(int n, uint64_t seed, double *e, hipStream_t st);
 void vc_sub(int n, const double *x, double *e, hipStream_t st);
 
+// k_learned.hip: edge-MLP correction of the fine-level temperature interpolation
+constexpr int MLP_NF = 16, MLP_NH = 64;
+constexpr int MLP_NPARAMS = MLP_NH * MLP_NF + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NH + 1;
+constexpr int MLP_MAX_BLOCKS = 512;
+static_assert(MLP_NPARAMS == CPTR_MLP_NPARAMS, "parameter blob size");
+void ln_edge_count(int n, const int *cf, const int *cidx, const int *prp, int *cnt, int *isf, int *fine_of,
+                   hipStream_t s);
+void ln_edge_rows(int n, const int *isf, const int *fpos, const int *estart_row, int *frows, int *estart,
+                  hipStream_t s);
+void ln_edge_features(int nf, const int *frows, const int *estart, const int *rp, const int *ci, const double *v,
+                      const unsigned char *strong, const int *prp, const int *pci, const double *pv,
+                      const int *fine_of, float *X, hipStream_t s);
+int ln_mlp_waves(int E);
+void ln_mlp_forward(int E, const float *X, const float *params, float *o, hipStream_t s);
+void ln_learned_weights(int nf, const int *frows, const int *estart, const int *prp, const double *pv,
+                        const float *o, double *pv_out, hipStream_t s);
+void ln_interp_loss(int nf, int n, int K, const int *frows, const int *estart, const int *prp, const int *pci,
+                    const double *pv, const int *fine_of, const double *Ev, const float *o, double *lossrow,
+                    float *dout, hipStream_t s);
+void ln_jacobi_zero(int n, const int *rp, const int *ci, const double *v, double omega, const double *ein,
+                    double *eout, hipStream_t s);
+void ln_mlp_backward(int E, const float *X, const float *params, const float *dout, float *part, hipStream_t s);
+void ln_grad_reduce(int nw, const float *part, float *grad, hipStream_t s);
+void ln_adam(float *p, float *m, float *v, const float *g, double lr, double b1, double b2, double eps, int t,
+             hipStream_t s);
+
 // k_bilu.hip: BILU(0) in tile order / block Jacobi
 struct TileSched {
     int nx = 0, ny = 0, tx = 0, ty = 0, ntx = 0, nty = 0;
