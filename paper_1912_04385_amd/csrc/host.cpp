@@ -88,9 +88,11 @@ struct cptr_ctx {
     // per-step stage timing (options.timing)
     hipEvent_t tev[6] = {};
     // concurrent hierarchy builds
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t ev_dec = nullptr, ev_side[2] = {nullptr, nullptr};
-    Builder bld[2];
+    // side streams: 0 temperature hierarchy, 1 pressure hierarchy, 2 the
+    // learned temperature hierarchy built beside the classical one
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_dec = nullptr, ev_side[3] = {nullptr, nullptr, nullptr};
+    Builder bld[3];
     double tacc[5] = {};
     int tsteps = 0;
 
@@ -101,10 +103,10 @@ struct cptr_ctx {
     ~cptr_ctx() {
         for (auto &e : tev)
             if (e) (void)hipEventDestroy(e);
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 3; ++k) {
             if (side[k]) {
                 (void)hipStreamSynchronize(side[k]);
-                for (auto *h : {&H[k]}) h->L.clear();
+                if (k < 2) H[k].L.clear();
                 bld[k].~Builder();
                 new (&bld[k]) Builder();
                 pool_trim(side[k]);
@@ -611,21 +613,57 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals) {
         c->used_learned = 0;
         c->rho_cls = c->rho_lrn = -1.0;
     }
-    build_hierarchy(&B, c->H[k], vals);
-    if (!learned || c->H[k].L.size() < 2) return;
-    Hierarchy hl;
-    build_hierarchy(&B, hl, vals, c->mlp.p);
-    if (c->opt.t_interp == CPTR_INTERP_LEARNED_FORCED) {
-        c->H[k] = std::move(hl);
-        c->used_learned = 1;
+    if (!learned) {
+        build_hierarchy(&B, c->H[k], vals);
         return;
     }
-    c->rho_cls = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
-    c->rho_lrn = conv_factor(c, hl, RHO_CYCLES, RHO_SEED, B.stream);
-    if (c->rho_lrn < c->rho_cls) {
+    // the learned hierarchy (and its convergence factor) on its own stream
+    // and host thread, concurrently with the classical one
+    const bool judge = (c->opt.t_interp == CPTR_INTERP_LEARNED);
+    Hierarchy hl;
+    double rl = -1.0;
+    std::exception_ptr err;
+    Builder &B2 = c->bld[2];
+    B2.stream = c->side[2];
+    B2.opt = B.opt;
+    B2.n = B.n;
+    B2.nnzb = B.nnzb;
+    B2.rp.p = B.rp.p;
+    B2.ci.p = B.ci.p;
+    CPTR_HIP(hipEventRecord(c->ev_side[2], B.stream));   // vals are ready on B's stream
+    std::thread t2([c, &B2, &hl, &rl, &err, vals, judge]() {
+        try {
+            CPTR_HIP(hipSetDevice(c->device));
+            StreamScope scope(B2.stream);
+            if (!B2.flag.p) {
+                B2.flag.alloc(4);
+                fill_int(B2.flag.p, 0, 1, B2.stream);
+            }
+            CPTR_HIP(hipStreamWaitEvent(B2.stream, c->ev_side[2], 0));
+            build_hierarchy(&B2, hl, vals, c->mlp.p);
+            if (judge && hl.L.size() > 1) rl = conv_factor(c, hl, RHO_CYCLES, RHO_SEED, B2.stream);
+        } catch (...) {
+            err = std::current_exception();
+        }
+    });
+    std::exception_ptr err1;
+    double rc = -1.0;
+    try {
+        build_hierarchy(&B, c->H[k], vals);
+        if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
+    } catch (...) {
+        err1 = std::current_exception();
+    }
+    t2.join();
+    if (err1) std::rethrow_exception(err1);
+    if (err) std::rethrow_exception(err);
+    if (c->H[k].L.size() < 2) return;           // a single level: no interpolation to learn
+    if (!judge || rl < rc) {
         c->H[k] = std::move(hl);
         c->used_learned = 1;
     }
+    c->rho_cls = rc;
+    c->rho_lrn = rl;
 }
 
 static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
@@ -962,7 +1000,7 @@ cptr_status cptr_create(cptr_ctx **out, int32_t dev, void *stream, const cptr_op
     CPTR_HIP(hipEventCreate(&c->ev1));
     for (auto &e : c->tev) CPTR_HIP(hipEventCreate(&e));
     CPTR_HIP(hipEventCreateWithFlags(&c->ev_dec, hipEventDisableTiming));
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         CPTR_HIP(hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));   // default priority
         CPTR_HIP(hipEventCreateWithFlags(&c->ev_side[k], hipEventDisableTiming));
     }
