@@ -51,12 +51,18 @@ struct cptr_ctx {
     DBuf<int> rp, ci, tpos;
     DBuf<double> abar, wp, wt, beta, slabT, slabP;
     DBuf<float> abar32, slabT32, slabP32;
+    // the coupling entry of every block that the second scalar stage's input
+    // needs: Abar[P,T] (T stage first) or Abar[T,P] (P stage first)
+    DBuf<double> cpl;
+    DBuf<float> cpl32;
     // last stage
     bool use_tiles = false;
     TileSched ts;
     DBuf<int> cell_list;
     DBuf<double> dinv;
     DBuf<float> dinv32;
+    DBuf<double> tb;        // in-tile neighbour blocks of the BILU(0) level chains
+    DBuf<float> tb32;
     // scalar stages: 0 = temperature (C_TT), 1 = pressure (B_PP)
     Hierarchy H[2];
     DBuf<double> ctt, bpp;          // level-0 values of the two scalar operators
@@ -460,30 +466,30 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     const T *v = Prec<T>::v(L.A);
     const T *dinv = Prec<T>::dinv(L);
     if (o.pre_sweeps >= 1) {
-        vc_presmooth_residual<T>(n, L.A.rp, L.A.ci, v, dinv, omega, b, 1, 0, x, r, s);
+        vc_presmooth_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, r, s);
         if (o.pre_sweeps > 1) {
             for (int k = 1; k < o.pre_sweeps; ++k) {
-                vc_smooth<T>(n, L.A.rp, L.A.ci, v, dinv, omega, b, 1, 0, x, tmp, s);
+                vc_smooth<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, tmp, s);
                 CPTR_HIP(hipMemcpyAsync(x, tmp, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
             }
-            vc_residual<T>(n, L.A.rp, L.A.ci, v, b, x, r, s);
+            vc_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, b, x, r, s);
         }
     } else {
         CPTR_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, s));
         CPTR_HIP(hipMemcpyAsync(r, b, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
     }
     Level &Ln = h.L[lvl + 1];
-    vc_spmv<T>(L.R.n, L.R.rp, L.R.ci, Prec<T>::v(L.R), r, Prec<T>::b(Ln), s);
+    vc_spmv<T>(L.R.n, L.R.nnz, L.R.rp, L.R.ci, Prec<T>::v(L.R), r, Prec<T>::b(Ln), s);
     T *xc = vcycle<T>(c, h, lvl + 1, s);
     if (o.post_sweeps == 0) {
-        vc_prolong_add<T>(n, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, s);
+        vc_prolong_add<T>(n, L.P.nnz, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, s);
     } else {
         // prolong into the spare buffer so that an odd number of Jacobi sweeps
         // ends in x without a copy
-        vc_prolong_to<T>(n, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, tmp, s);
+        vc_prolong_to<T>(n, L.P.nnz, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, tmp, s);
         std::swap(x, tmp);
         for (int k = 0; k < o.post_sweeps; ++k) {
-            vc_smooth<T>(n, L.A.rp, L.A.ci, v, dinv, omega, b, 1, 0, x, tmp, s);
+            vc_smooth<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, tmp, s);
             std::swap(x, tmp);
         }
     }
@@ -521,7 +527,8 @@ static void precond_apply(cptr_ctx *c, const double *r, double *y) {
         const T *x1 = vcycle<T>(c, h1, 0, s);
         c->mark(1);
         // M2 on z = r - Abar x (only its comp2 entries are needed)
-        ms_stage_input<T>(n, b, c->rp.p, c->ci.p, t_first ? slabT : slabP, comp2, r, x1, Prec<T>::b(h2.L[0]), s);
+        const T *cpl = f32 ? (const T *)c->cpl32.p : (const T *)c->cpl.p;
+        ms_stage_input<T>(n, b, c->rp.p, c->ci.p, cpl, comp2, r, x1, Prec<T>::b(h2.L[0]), s);
         const T *x2 = vcycle<T>(c, h2, 0, s);
         c->mark(2);
         xT = t_first ? x1 : x2;
@@ -539,7 +546,11 @@ static void precond_apply(cptr_ctx *c, const double *r, double *y) {
     }
     // last stage on u = r - Abar (x + v), combined output y = x + v + ilu^{-1} u
     if (c->use_tiles)
-        bilu_apply_tiles<T>(c->ts, b, c->rp.p, c->ci.p, abar, dinv, slabT, slabP, c->ip, c->it, r, xT, vP, tw, y, s);
+    {
+        const T *tb = f32 ? (const T *)c->tb32.p : (const T *)c->tb.p;
+        bilu_apply_tiles<T>(c->ts, b, c->rp.p, c->ci.p, abar, tb, dinv, slabT, slabP, c->ip, c->it, r, xT, vP, tw, y,
+                            s);
+    }
     else
         bj_apply_cells<T>(n, b, c->rp.p, c->ci.p, dinv, slabT, slabP, c->ip, c->it, r, xT, vP, y, s);
 }
@@ -566,7 +577,7 @@ static double conv_factor(cptr_ctx *c, Hierarchy &h, int cycles, uint64_t seed, 
     kr_norm2_partial(n, e.p, part.p, nblk, s);
     kr_reduce(part.p, nblk, 1, nrm.p, s);
     for (int k = 0; k < cycles; ++k) {
-        vc_spmv<double>(n, L0.A.rp, L0.A.ci, L0.A.v.p, e.p, L0.b.p, s);
+        vc_spmv<double>(n, L0.A.nnz, L0.A.rp, L0.A.ci, L0.A.v.p, e.p, L0.b.p, s);
         const double *x = vcycle<double>(c, h, 0, s);
         vc_sub(n, x, e.p, s);
     }
@@ -701,6 +712,13 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     int bad = read_scalar(c->s_i4.p, s);
     if (bad != 0x7fffffff)
         throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block (D_ss or Ahat_PP) in cell " + std::to_string(bad));
+    if (c->opt.variant == CPTR_VARIANT_CPTR3) {
+        const bool t_first = (c->opt.stage_order == CPTR_T_THEN_P);
+        c->cpl.alloc(nnzb);
+        if (fp32) c->cpl32.alloc(nnzb);
+        ms_gather_comp(nnzb, b, t_first ? c->slabT.p : c->slabP.p, t_first ? c->ip : c->it, c->cpl.p,
+                       fp32 ? c->cpl32.p : nullptr, s);
+    }
     // scalar stages: the two hierarchies are built concurrently, each on its
     // own stream and host thread, while this stream factors the last stage
     const bool need[2] = {c->opt.variant == CPTR_VARIANT_CPTR3,
@@ -787,6 +805,15 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         if (need[k]) CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[k], 0));
     if (bad != 0x7fffffff)
         throw Error(CPTR_E_SINGULAR_BLOCK, "singular ILU pivot block in cell " + std::to_string(bad));
+    if (c->use_tiles && bilu_wave_ok(c->ts, b)) {
+        if (fp32) {
+            c->tb32.alloc((size_t)n * 4 * b * b);
+            bilu_tile_blocks<float>(c->ts, n, b, c->rp.p, c->ci.p, c->abar.p, c->tb32.p, s);
+        } else {
+            c->tb.alloc((size_t)n * 4 * b * b);
+            bilu_tile_blocks<double>(c->ts, n, b, c->rp.p, c->ci.p, c->abar.p, c->tb.p, s);
+        }
+    }
     if (fp32) {
         c->dinv32.alloc((size_t)n * b * b);
         to_float(c->dinv.p, c->dinv32.p, (size_t)n * b * b, s);

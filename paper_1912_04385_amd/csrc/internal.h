@@ -177,26 +177,28 @@ void amg_dense_inverse(int n, const int *rp, const int *ci, const double *v, dou
 
 // k_vcycle.hip (double and float instantiations)
 template <class T>
-void vc_presmooth_residual(int n, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b,
-                           int bstride, int boff, T *x, T *r, hipStream_t st);
+void vc_presmooth_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, T omega,
+                           const T *b, T *x, T *r, hipStream_t st);
 template <class T>
-void vc_spmv(int n, const int *rp, const int *ci, const T *v, const T *x, T *y, hipStream_t st);
+void vc_spmv(int n, int nnz, const int *rp, const int *ci, const T *v, const T *x, T *y, hipStream_t st);
 template <class T>
-void vc_prolong_add(int n, const int *rp, const int *ci, const T *v, const T *xc, T *x, hipStream_t st);
+void vc_prolong_add(int n, int nnz, const int *rp, const int *ci, const T *v, const T *xc, T *x, hipStream_t st);
 template <class T>
-void vc_prolong_to(int n, const int *rp, const int *ci, const T *v, const T *xc, const T *xin, T *xout,
+void vc_prolong_to(int n, int nnz, const int *rp, const int *ci, const T *v, const T *xc, const T *xin, T *xout,
                    hipStream_t st);
 template <class T>
-void vc_smooth(int n, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b, int bstride,
-               int boff, const T *xin, T *xout, hipStream_t st);
+void vc_smooth(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b,
+               const T *xin, T *xout, hipStream_t st);
 template <class T>
-void vc_residual(int n, const int *rp, const int *ci, const T *v, const T *b, const T *x, T *r, hipStream_t st);
+void vc_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *b, const T *x, T *r,
+                 hipStream_t st);
 template <class T>
 void vc_dense_apply(int n, const T *Minv, const T *b, T *x, hipStream_t st);
 void vc_dense_apply_mixed(int n, const double *Minv, const float *b, float *x, hipStream_t st);
 template <class T>
-void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *slab, int comp, const double *r,
+void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *cpl, int comp, const double *r,
                     const T *xs, T *out, hipStream_t st);
+void ms_gather_comp(int nnzb, int b, const double *slab, int comp, double *out, float *out32, hipStream_t st);
 
 void vc_hash_uniform(int n, uint64_t seed, double *e, hipStream_t st);
 void vc_sub(int n, const double *x, double *e, hipStream_t st);
@@ -243,10 +245,16 @@ void bj_factor_cells(int n, int b, const int *rp, const int *ci, const double *a
 // last stage apply, fused with Algorithm 2's residual updates:
 //   u = r - Abar[:,T] xT - Abar[:,P] vP  (terms dropped when xT / vP are null)
 //   w = ilu(Abar)^{-1} u,  y = w + xT e_T + vP e_P
+// tb: the in-tile neighbour blocks gathered by bilu_tile_blocks (NULL: the
+// multi-wavefront kernel that reads Abar directly)
 template <class T>
-void bilu_apply_tiles(const TileSched &ts, int b, const int *rp, const int *ci, const T *abar, const T *dinv,
-                      const T *slabT, const T *slabP, int ip, int it, const double *r, const T *xT, const T *vP,
-                      T *tw, double *y, hipStream_t st);
+void bilu_apply_tiles(const TileSched &ts, int b, const int *rp, const int *ci, const T *abar, const T *tb,
+                      const T *dinv, const T *slabT, const T *slabP, int ip, int it, const double *r, const T *xT,
+                      const T *vP, T *tw, double *y, hipStream_t st);
+bool bilu_wave_ok(const TileSched &ts, int b);
+template <class T>
+void bilu_tile_blocks(const TileSched &ts, int n, int b, const int *rp, const int *ci, const double *abar, T *tb,
+                      hipStream_t st);
 template <class T>
 void bj_apply_cells(int n, int b, const int *rp, const int *ci, const T *dinv, const T *slabT, const T *slabP,
                     int ip, int it, const double *r, const T *xT, const T *vP, double *y, hipStream_t st);

@@ -315,18 +315,66 @@ __global__ void k_cross_tile(int n, int b, int mode, const int *__restrict__ col
     u[t] = acc;
 }
 
-// Level chain of one tile per wavefront.  s0 (forward right-hand side, with
-// the couplings to lower-colour tiles already folded in) and q0 (backward:
-// couplings to higher-colour tiles) come from u; in-tile neighbour values come
-// from LDS; the next level's matrix rows, D^{-1} row and s0/q0/t are loaded
-// into registers while the current level computes.
+// In-tile neighbour blocks of every cell, gathered once per setup so that the
+// level chains below address them arithmetically (no index loads):
+// tb[(i*4 + k)*B*B + r*B + c] = Abar_ij[r][c] for j the S (k = 0), W (1),
+// E (2), N (3) neighbour of cell i when j lies in i's tile, else 0.
+template <class T>
+__global__ void k_tile_blocks(int n, int b, int nx, int tx, int ty, const int *__restrict__ rp,
+                              const int *__restrict__ ci, const double *__restrict__ abar, T *__restrict__ tb) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int bb = b * b;
+    if (t >= (long)n * 4 * bb) return;
+    const int el = (int)(t % bb);
+    const int k = (int)((t / bb) % 4);
+    const int i = (int)(t / (4L * bb));
+    const int x = i % nx, y = i / nx;
+    const int dx = (k == 1) ? -1 : (k == 2) ? 1 : 0, dy = (k == 0) ? -1 : (k == 3) ? 1 : 0;
+    const int xj = x + dx, yj = y + dy;
+    T v = 0;
+    if (xj >= 0 && xj < nx && yj >= 0 && xj / tx == x / tx && yj / ty == y / ty) {
+        const int j = xj + nx * yj;
+        for (int e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] == j) { v = (T)abar[(size_t)e * bb + el]; break; }
+    }
+    tb[t] = v;
+}
+
+template <class T>
+void bilu_tile_blocks(const TileSched &ts, int n, int b, const int *rp, const int *ci, const double *abar, T *tb,
+                      hipStream_t st) {
+    const long tot = (long)n * 4 * b * b;
+    hipLaunchKernelGGL(k_tile_blocks<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, b, ts.nx, ts.tx,
+                       ts.ty, rp, ci, abar, tb);
+    CPTR_CHECK_LAUNCH();
+}
+template void bilu_tile_blocks<double>(const TileSched &, int, int, const int *, const int *, const double *,
+                                       double *, hipStream_t);
+template void bilu_tile_blocks<float>(const TileSched &, int, int, const int *, const int *, const double *,
+                                      float *, hipStream_t);
+
+// Level chain of one tile per wavefront.  Every anti-diagonal of a tile has at
+// most min(tx, ty) <= 64/B cells, so level `lev` is one step: lane group g owns
+// cell lx = lo + g of it.  s0 (forward right-hand side, with the couplings to
+// lower-colour tiles already folded in) and q0 (backward: couplings to
+// higher-colour tiles) come from u; in-tile neighbour values come from LDS.
+// The matrix rows, D^{-1} row and s0/q0/t of the next PF levels are kept in
+// flight in a register ring, so the chain waits on memory only when PF levels
+// of compute are shorter than one memory latency.
 //   mode 0: forward only (t to LDS and global)
 //   mode 1: forward then backward (the last colour); w to global, y written
 //   mode 2: backward only (t read from global); y written
+constexpr int PF = 4;
+
+template <class T, int B>
+struct LevelRegs {
+    T a0[B], a1[B], d[B];
+    T s, tv;
+};
+
 template <class T, int B>
 __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const int *__restrict__ tiles,
-                                                  const int *__restrict__ rp, const int *__restrict__ ci,
-                                                  const T *__restrict__ abar, const T *__restrict__ dinv,
+                                                  const T *__restrict__ tb, const T *__restrict__ dinv,
                                                   const T *__restrict__ u, T *__restrict__ tw,
                                                   double *__restrict__ y, int ip, int it, const T *__restrict__ xT,
                                                   const T *__restrict__ vP) {
@@ -341,135 +389,126 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
     int x0, y0, tw_, th;
     tile_dims(g, tile, x0, y0, tw_, th);
     const int nlev = tw_ + th - 1;
-    auto in_tile = [&](int j, int &loc) {
-        const int xj = j % g.nx - x0, yj = j / g.nx - y0;
-        loc = xj + tw_ * yj;
-        return xj >= 0 && xj < tw_ && yj >= 0 && yj < th;
-    };
-    // prefetch registers
-    T na0[B], na1[B], nd[B];
-    T ns = 0, ntv = 0;
-    int nl0 = -1, nl1 = -1, nloc = -1, ni = 0;
-    auto load = [&](int lev, int slot, bool fwd) {
-        nloc = -1; nl0 = -1; nl1 = -1;
-        if (!glane || lev < 0 || lev >= nlev) return;
+    // this lane group's cell of level lev (false if none)
+    auto cell_of = [&](int lev, int &lx, int &ly, int &i) {
+        if (!glane || lev < 0 || lev >= nlev) return false;
         const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
-        const int lx = lo + slot + grp;      // this lane group's cell of the level
-        if (lx > hi) return;
-        const int ly = lev - lx;
-        nloc = lx + tw_ * ly;
-        ni = (x0 + lx) + g.nx * (y0 + ly);
-        for (int e = rp[ni]; e < rp[ni + 1]; ++e) {
-            const int j = ci[e];
-            int lj;
-            if (j == ni || !in_tile(j, lj) || (fwd ? (j > ni) : (j < ni))) continue;
-            const T *Aij = abar + (size_t)e * B * B + r * B;
-            if (nl0 < 0) {
-                nl0 = lj;
-#pragma unroll
-                for (int m = 0; m < B; ++m) na0[m] = Aij[m];
-            } else {
-                nl1 = lj;
-#pragma unroll
-                for (int m = 0; m < B; ++m) na1[m] = Aij[m];
-            }
-        }
-        const T *Di = dinv + (size_t)ni * B * B + r * B;
-#pragma unroll
-        for (int c = 0; c < B; ++c) nd[c] = Di[c];
-        ns = u[(size_t)ni * B + r];
-        if (!fwd && mode == 2) ntv = tw[(size_t)ni * B + r];
+        lx = lo + grp;
+        if (lx > hi) return false;
+        ly = lev - lx;
+        i = (x0 + lx) + g.nx * (y0 + ly);
+        return true;
     };
+    // loads of level lev into q, issued unconditionally (levels and lane groups
+    // without a cell read a clamped, valid cell that is never used) so that the
+    // memory counters stay exact across the unrolled ring
+    auto load = [&](LevelRegs<T, B> &q, int lev, bool fwd) {
+        const int lc = min(max(lev, 0), nlev - 1);
+        const int lo = max(0, lc - th + 1), hi = min(lc, tw_ - 1);
+        const int lx = min(lo + grp, hi), ly = lc - lx;
+        const int i = (x0 + lx) + g.nx * (y0 + ly);
+        const T *blk = tb + ((size_t)i * 4 + (fwd ? 0 : 2)) * B * B + r * B;
+#pragma unroll
+        for (int m = 0; m < B; ++m) q.a0[m] = blk[m];
+#pragma unroll
+        for (int m = 0; m < B; ++m) q.a1[m] = blk[B * B + m];
+        const T *Di = dinv + (size_t)i * B * B + r * B;
+#pragma unroll
+        for (int c = 0; c < B; ++c) q.d[c] = Di[c];
+        q.s = u[(size_t)i * B + r];
+        q.tv = tw[(size_t)i * B + r];   // used by the backward-only mode
+    };
+    LevelRegs<T, B> ring[PF];
 
     if (mode == 0 || mode == 1) {
-        int lev = 0, slot = 0;
-        load(0, 0, true);
-        while (lev < nlev) {
-            T a0[B], a1[B], d[B];
 #pragma unroll
-            for (int m = 0; m < B; ++m) { a0[m] = na0[m]; a1[m] = na1[m]; d[m] = nd[m]; }
-            const int l0 = nl0, l1 = nl1, loc = nloc, i = ni;
-            T s = ns;
-            const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
-            int nlev_ = lev, nslot = slot + GPW;
-            if (lo + nslot > hi) { nlev_ = lev + 1; nslot = 0; }
-            load(nlev_, nslot, true);
-            if (loc >= 0) {
-                if (l0 >= 0) {
+        for (int k = 0; k < PF; ++k) load(ring[k], k, true);
+        for (int base = 0; base < nlev; base += PF) {
 #pragma unroll
-                    for (int m = 0; m < B; ++m) s -= a0[m] * W[l0 * B + m];
+            for (int k = 0; k < PF; ++k) {
+                const int lev = base + k;
+                if (lev >= nlev) break;
+                int lx = 0, ly = 0, i = 0;
+                const bool own = cell_of(lev, lx, ly, i);
+                const int loc = lx + tw_ * ly;
+                T s = ring[k].s;
+                if (own) {
+                    // lower in-tile neighbours in ascending order: S, then W
+                    if (ly > 0) {
+#pragma unroll
+                        for (int m = 0; m < B; ++m) s -= ring[k].a0[m] * W[(loc - tw_) * B + m];
+                    }
+                    if (lx > 0) {
+#pragma unroll
+                        for (int m = 0; m < B; ++m) s -= ring[k].a1[m] * W[(loc - 1) * B + m];
+                    }
+                } else {
+                    s = 0;
                 }
-                if (l1 >= 0) {
+                T tv = 0;
 #pragma unroll
-                    for (int m = 0; m < B; ++m) s -= a1[m] * W[l1 * B + m];
+                for (int c = 0; c < B; ++c) tv += ring[k].d[c] * shfl(s, gbase + c);
+                load(ring[k], lev + PF, true);
+                if (own) {
+                    W[loc * B + r] = tv;
+                    if (mode == 0) tw[(size_t)i * B + r] = tv;
                 }
-            } else {
-                s = 0;
+                __syncthreads();
             }
-            T tv = 0;
-#pragma unroll
-            for (int c = 0; c < B; ++c) tv += d[c] * shfl(s, gbase + c);
-            if (loc >= 0) {
-                W[loc * B + r] = tv;
-                if (mode == 0) tw[(size_t)i * B + r] = tv;
-            }
-            __syncthreads();
-            lev = nlev_;
-            slot = nslot;
         }
     }
     if (mode == 1 || mode == 2) {
-        int lev = nlev - 1, slot = 0;
-        load(lev, 0, false);
-        while (lev >= 0) {
-            T a0[B], a1[B], d[B];
 #pragma unroll
-            for (int m = 0; m < B; ++m) { a0[m] = na0[m]; a1[m] = na1[m]; d[m] = nd[m]; }
-            const int l0 = nl0, l1 = nl1, loc = nloc, i = ni;
-            T q = (mode == 2) ? ns : (T)0;
-            const T tglob = ntv;
-            const int lo = max(0, lev - th + 1), hi = min(lev, tw_ - 1);
-            int nlev_ = lev, nslot = slot + GPW;
-            if (lo + nslot > hi) { nlev_ = lev - 1; nslot = 0; }
-            load(nlev_, nslot, false);
-            T tval = 0;
-            if (loc >= 0) {
-                tval = (mode == 2) ? tglob : W[loc * B + r];
-                if (l0 >= 0) {
+        for (int k = 0; k < PF; ++k) load(ring[k], nlev - 1 - k, false);
+        for (int base = 0; base < nlev; base += PF) {
 #pragma unroll
-                    for (int m = 0; m < B; ++m) q += a0[m] * W[l0 * B + m];
+            for (int k = 0; k < PF; ++k) {
+                const int step = base + k;
+                if (step >= nlev) break;
+                const int lev = nlev - 1 - step;
+                int lx = 0, ly = 0, i = 0;
+                const bool own = cell_of(lev, lx, ly, i);
+                const int loc = lx + tw_ * ly;
+                T q = (mode == 2) ? ring[k].s : (T)0;
+                T tval = 0;
+                if (own) {
+                    tval = (mode == 2) ? ring[k].tv : W[loc * B + r];
+                    // upper in-tile neighbours in ascending order: E, then N
+                    if (lx < tw_ - 1) {
+#pragma unroll
+                        for (int m = 0; m < B; ++m) q += ring[k].a0[m] * W[(loc + 1) * B + m];
+                    }
+                    if (ly < th - 1) {
+#pragma unroll
+                        for (int m = 0; m < B; ++m) q += ring[k].a1[m] * W[(loc + tw_) * B + m];
+                    }
+                } else {
+                    q = 0;
                 }
-                if (l1 >= 0) {
+                T corr = 0;
 #pragma unroll
-                    for (int m = 0; m < B; ++m) q += a1[m] * W[l1 * B + m];
+                for (int c = 0; c < B; ++c) corr += ring[k].d[c] * shfl(q, gbase + c);
+                load(ring[k], lev - PF, false);
+                __syncthreads();   // every lane has read its W entries before they are overwritten
+                if (own) {
+                    const T w = tval - corr;
+                    W[loc * B + r] = w;
+                    if (mode == 1) tw[(size_t)i * B + r] = w;
+                    double yv = (double)w;
+                    if (r == it && xT) yv += (double)xT[i];
+                    if (r == ip && vP) yv += (double)vP[i];
+                    y[(size_t)i * B + r] = yv;
                 }
-            } else {
-                q = 0;
+                __syncthreads();
             }
-            T corr = 0;
-#pragma unroll
-            for (int c = 0; c < B; ++c) corr += d[c] * shfl(q, gbase + c);
-            __syncthreads();   // every lane has read its W entries before they are overwritten
-            if (loc >= 0) {
-                const T w = tval - corr;
-                W[loc * B + r] = w;
-                if (mode == 1) tw[(size_t)i * B + r] = w;
-                double yv = (double)w;
-                if (r == it && xT) yv += (double)xT[i];
-                if (r == ip && vP) yv += (double)vP[i];
-                y[(size_t)i * B + r] = yv;
-            }
-            __syncthreads();
-            lev = nlev_;
-            slot = nslot;
         }
     }
 }
 
 template <class T>
 static void bilu_apply_wave(const TileSched &ts, int n, int b, const int *rp, const int *ci, const T *abar,
-                            const T *dinv, const T *slabT, const T *slabP, int ip, int it, const double *r,
-                            const T *xT, const T *vP, T *u, T *tw, double *y, hipStream_t st) {
+                            const T *tb, const T *dinv, const T *slabT, const T *slabP, int ip, int it,
+                            const double *r, const T *xT, const T *vP, T *u, T *tw, double *y, hipStream_t st) {
     const long nr = (long)n * b;
     const int gr = (int)((nr + 255) / 256);
     hipLaunchKernelGGL(k_stage_residual<T>, dim3(gr), dim3(256), 0, st, n, b, rp, ci, slabT, slabP, r, xT, vP, u);
@@ -478,7 +517,7 @@ static void bilu_apply_wave(const TileSched &ts, int n, int b, const int *rp, co
     auto launch = [&](int color, int mode) {
         const int nt = ts.ntiles[color];
         if (nt == 0) return;
-#define CASE(BB) case BB: hipLaunchKernelGGL((k_bilu_wave<T, BB>), dim3(nt), dim3(64), lds, st, g, mode, ts.tiles[color].p, rp, ci, abar, dinv, u, tw, y, ip, it, xT, vP); break;
+#define CASE(BB) case BB: hipLaunchKernelGGL((k_bilu_wave<T, BB>), dim3(nt), dim3(64), lds, st, g, mode, ts.tiles[color].p, tb, dinv, u, tw, y, ip, it, xT, vP); break;
         switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
 #undef CASE
         CPTR_CHECK_LAUNCH();
@@ -500,13 +539,13 @@ bool bilu_wave_ok(const TileSched &ts, int b) {
 }
 
 template <class T>
-void bilu_apply_tiles(const TileSched &ts, int b, const int *rp, const int *ci, const T *abar, const T *dinv,
-                      const T *slabT, const T *slabP, int ip, int it, const double *r, const T *xT, const T *vP,
-                      T *tw, double *y, hipStream_t st) {
-    if (bilu_wave_ok(ts, b)) {
+void bilu_apply_tiles(const TileSched &ts, int b, const int *rp, const int *ci, const T *abar, const T *tb,
+                      const T *dinv, const T *slabT, const T *slabP, int ip, int it, const double *r, const T *xT,
+                      const T *vP, T *tw, double *y, hipStream_t st) {
+    if (bilu_wave_ok(ts, b) && tb) {
         // tw holds 2 n b values: the stage residual u, then t / w
         const int n = ts.nx * ts.ny;
-        bilu_apply_wave<T>(ts, n, b, rp, ci, abar, dinv, slabT, slabP, ip, it, r, xT, vP, tw + (size_t)n * b, tw,
+        bilu_apply_wave<T>(ts, n, b, rp, ci, abar, tb, dinv, slabT, slabP, ip, it, r, xT, vP, tw + (size_t)n * b, tw,
                            y, st);
         return;
     }
@@ -528,11 +567,12 @@ void bilu_apply_tiles(const TileSched &ts, int b, const int *rp, const int *ci, 
     }
 }
 template void bilu_apply_tiles<double>(const TileSched &, int, const int *, const int *, const double *,
-                                       const double *, const double *, const double *, int, int, const double *,
-                                       const double *, const double *, double *, double *, hipStream_t);
+                                       const double *, const double *, const double *, const double *, int, int,
+                                       const double *, const double *, const double *, double *, double *,
+                                       hipStream_t);
 template void bilu_apply_tiles<float>(const TileSched &, int, const int *, const int *, const float *,
-                                      const float *, const float *, const float *, int, int, const double *,
-                                      const float *, const float *, float *, double *, hipStream_t);
+                                      const float *, const float *, const float *, const float *, int, int,
+                                      const double *, const float *, const float *, float *, double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // block Jacobi: y_i = D_i^{-1} u_i + xT e_T + vP e_P   (D_i^{-1} = inv(Abar_ii))

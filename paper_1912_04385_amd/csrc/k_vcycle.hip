@@ -9,116 +9,124 @@ namespace cptr {
 
 static inline int nblocks(long n, int t) { long b = (n + t - 1) / t; return (int)(b < 1 ? 1 : b); }
 
+// The level kernels share one row loop: G lanes per row (G = 1 for the short
+// rows of the fine level, up to 64 for the long rows of Galerkin coarse
+// levels), each lane summing every G-th entry, then an xor-shuffle reduction
+// inside the lane group.  OP selects what is done with the row sum
+// acc_i = sum_j a_ij x_j:
+enum CsrOp {
+    OP_SPMV,          // y_i = acc_i                                    (x = xin)
+    OP_RESIDUAL,      // r_i = b_i - acc_i                              (x = xin)
+    OP_SMOOTH,        // x_i = xin_i + omega dinv_i (b_i - acc_i)       (x = xin)
+    OP_PRESMOOTH,     // x_i = omega dinv_i b_i, r_i = b_i - acc_i      (x_j = omega dinv_j b_j)
+    OP_PROLONG        // x_i = xin_i + acc_i                            (x = coarse vector)
+};
+
+template <class T, int G, int OP>
+__global__ void __launch_bounds__(256) k_csr_op(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                const T *__restrict__ v, const T *__restrict__ xs,
+                                                const T *__restrict__ dinv, T omega, const T *__restrict__ b,
+                                                const T *xin, T *xout, T *__restrict__ rout) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), sub = (int)(t % G);
+    const bool act = i < n;
+    T acc = 0;
+    if (act) {
+        const int e1 = rp[i + 1];
+        for (int e = rp[i] + sub; e < e1; e += G) {
+            const int j = ci[e];
+            if constexpr (OP == OP_PRESMOOTH)
+                acc += v[e] * (omega * dinv[j] * b[j]);
+            else
+                acc += v[e] * xs[j];
+        }
+    }
+    if constexpr (G > 1) {
+#pragma unroll
+        for (int d = G / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, G);
+    }
+    if (!act || sub != 0) return;
+    if constexpr (OP == OP_SPMV) {
+        xout[i] = acc;
+    } else if constexpr (OP == OP_RESIDUAL) {
+        rout[i] = b[i] - acc;
+    } else if constexpr (OP == OP_SMOOTH) {
+        xout[i] = xin[i] + omega * dinv[i] * (b[i] - acc);
+    } else if constexpr (OP == OP_PRESMOOTH) {
+        const T bi = b[i];
+        xout[i] = omega * dinv[i] * bi;
+        rout[i] = bi - acc;
+    } else {
+        xout[i] = xin[i] + acc;
+    }
+}
+
+// lanes per row from the average row length
+static inline int lanes_for(int n, int nnz) {
+    const int avg = n > 0 ? nnz / n : 0;
+    if (avg <= 6) return 1;
+    if (avg <= 12) return 4;
+    if (avg <= 24) return 8;
+    if (avg <= 48) return 16;
+    if (avg <= 96) return 32;
+    return 64;
+}
+
+template <class T, int OP>
+static void csr_op(int n, int nnz, const int *rp, const int *ci, const T *v, const T *xs, const T *dinv, T omega,
+                   const T *b, const T *xin, T *xout, T *rout, hipStream_t st) {
+    if (n == 0) return;
+    const int G = lanes_for(n, nnz);
+    const int blocks = nblocks((long)n * G, 256);
+#define CASE(GG)                                                                                               \
+    case GG:                                                                                                   \
+        hipLaunchKernelGGL((k_csr_op<T, GG, OP>), dim3(blocks), dim3(256), 0, st, n, rp, ci, v, xs, dinv, omega, \
+                           b, xin, xout, rout);                                                                \
+        break;
+    switch (G) { CASE(1) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64) }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
 // first Jacobi sweep from a zero guess fused with the residual:
 //   x_i = omega dinv_i b_i,   r_i = b_i - sum_j a_ij (omega dinv_j b_j)
 template <class T>
-__global__ void k_presmooth_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                     const T *__restrict__ v, const T *__restrict__ dinv, T omega,
-                                     const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T acc = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        int j = ci[e];
-        acc += v[e] * (omega * dinv[j] * b[j]);
-    }
-    const T bi = b[i];
-    x[i] = omega * dinv[i] * bi;
-    r[i] = bi - acc;
-}
-
-template <class T>
-void vc_presmooth_residual(int n, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b,
-                           int bstride, int boff, T *x, T *r, hipStream_t st) {
-    (void)bstride; (void)boff;
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_presmooth_residual<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, dinv, omega,
-                       b, x, r);
-    CPTR_CHECK_LAUNCH();
+void vc_presmooth_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, T omega,
+                           const T *b, T *x, T *r, hipStream_t st) {
+    csr_op<T, OP_PRESMOOTH>(n, nnz, rp, ci, v, nullptr, dinv, omega, b, nullptr, x, r, st);
 }
 
 // y = A x
 template <class T>
-__global__ void k_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci, const T *__restrict__ v,
-                       const T *__restrict__ x, T *__restrict__ y) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T acc = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) acc += v[e] * x[ci[e]];
-    y[i] = acc;
+void vc_spmv(int n, int nnz, const int *rp, const int *ci, const T *v, const T *x, T *y, hipStream_t st) {
+    csr_op<T, OP_SPMV>(n, nnz, rp, ci, v, x, nullptr, (T)0, nullptr, nullptr, y, nullptr, st);
 }
 
+// x = x + P xc
 template <class T>
-void vc_spmv(int n, const int *rp, const int *ci, const T *v, const T *x, T *y, hipStream_t st) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_spmv<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, x, y);
-    CPTR_CHECK_LAUNCH();
+void vc_prolong_add(int n, int nnz, const int *rp, const int *ci, const T *v, const T *xc, T *x, hipStream_t st) {
+    csr_op<T, OP_PROLONG>(n, nnz, rp, ci, v, xc, nullptr, (T)0, nullptr, x, x, nullptr, st);
 }
 
-// xout = xin + P xc (xout may alias xin)
+// xout = xin + P xc
 template <class T>
-__global__ void k_prolong_add(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                              const T *__restrict__ v, const T *__restrict__ xc, const T *xin, T *xout) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T acc = xin[i];
-    for (int e = rp[i]; e < rp[i + 1]; ++e) acc += v[e] * xc[ci[e]];
-    xout[i] = acc;
-}
-
-template <class T>
-void vc_prolong_add(int n, const int *rp, const int *ci, const T *v, const T *xc, T *x, hipStream_t st) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, xc, x, x);
-    CPTR_CHECK_LAUNCH();
-}
-
-template <class T>
-void vc_prolong_to(int n, const int *rp, const int *ci, const T *v, const T *xc, const T *xin, T *xout,
+void vc_prolong_to(int n, int nnz, const int *rp, const int *ci, const T *v, const T *xc, const T *xin, T *xout,
                    hipStream_t st) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, xc, xin, xout);
-    CPTR_CHECK_LAUNCH();
+    csr_op<T, OP_PROLONG>(n, nnz, rp, ci, v, xc, nullptr, (T)0, nullptr, xin, xout, nullptr, st);
 }
 
 // one damped Jacobi sweep: xout = xin + omega dinv (b - A xin)
 template <class T>
-__global__ void k_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci, const T *__restrict__ v,
-                         const T *__restrict__ dinv, T omega, const T *__restrict__ b, const T *__restrict__ xin,
-                         T *__restrict__ xout) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T acc = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) acc += v[e] * xin[ci[e]];
-    xout[i] = xin[i] + omega * dinv[i] * (b[i] - acc);
-}
-
-template <class T>
-void vc_smooth(int n, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b, int bstride,
-               int boff, const T *xin, T *xout, hipStream_t st) {
-    (void)bstride; (void)boff;
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_smooth<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, dinv, omega, b, xin,
-                       xout);
-    CPTR_CHECK_LAUNCH();
+void vc_smooth(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, T omega, const T *b,
+               const T *xin, T *xout, hipStream_t st) {
+    csr_op<T, OP_SMOOTH>(n, nnz, rp, ci, v, xin, dinv, omega, b, xin, xout, nullptr, st);
 }
 
 // r = b - A x
 template <class T>
-__global__ void k_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci, const T *__restrict__ v,
-                           const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ r) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T acc = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) acc += v[e] * x[ci[e]];
-    r[i] = b[i] - acc;
-}
-
-template <class T>
-void vc_residual(int n, const int *rp, const int *ci, const T *v, const T *b, const T *x, T *r, hipStream_t st) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_residual<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, b, x, r);
-    CPTR_CHECK_LAUNCH();
+void vc_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *b, const T *x, T *r,
+                 hipStream_t st) {
+    csr_op<T, OP_RESIDUAL>(n, nnz, rp, ci, v, x, nullptr, (T)0, b, nullptr, nullptr, r, st);
 }
 
 // coarsest level: x = Ainv b (dense, one wavefront per row); accumulation in
@@ -160,26 +168,43 @@ void vc_dense_apply_mixed(int n, const double *Minv, const float *b, float *x, h
     CPTR_CHECK_LAUNCH();
 }
 
-// Algorithm 2 glue: out_i = r[i*b + comp] - sum_e slab[e*b + comp] * xs[ci[e]]
-// (z_P = r_P - Abar[P,T] x_T when the T stage runs first)
+// Algorithm 2 glue: out_i = r[i*b + comp] - sum_e cpl[e] * xs[ci[e]]
+// (z_P = r_P - Abar[P,T] x_T when the T stage runs first; cpl holds the one
+// coupling entry of every block that the update needs, contiguous)
 template <class T>
 __global__ void k_stage_input(int n, int b, const int *__restrict__ rp, const int *__restrict__ ci,
-                              const T *__restrict__ slab, int comp, const double *__restrict__ r,
+                              const T *__restrict__ cpl, int comp, const double *__restrict__ r,
                               const T *__restrict__ xs, T *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     T acc = (T)r[(size_t)i * b + comp];
     if (xs)
-        for (int e = rp[i]; e < rp[i + 1]; ++e) acc -= slab[(size_t)e * b + comp] * xs[ci[e]];
+        for (int e = rp[i]; e < rp[i + 1]; ++e) acc -= cpl[e] * xs[ci[e]];
     out[i] = acc;
 }
 
 template <class T>
-void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *slab, int comp, const double *r,
+void ms_stage_input(int n, int b, const int *rp, const int *ci, const T *cpl, int comp, const double *r,
                     const T *xs, T *out, hipStream_t st) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_stage_input<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, b, rp, ci, slab, comp, r, xs,
+    hipLaunchKernelGGL(k_stage_input<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, b, rp, ci, cpl, comp, r, xs,
                        out);
+    CPTR_CHECK_LAUNCH();
+}
+
+// cpl[e] = slab[e*b + comp] (and its FP32 copy)
+__global__ void k_gather_comp(int nnzb, int b, const double *__restrict__ slab, int comp, double *__restrict__ out,
+                              float *__restrict__ out32) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnzb) return;
+    const double v = slab[(size_t)e * b + comp];
+    out[e] = v;
+    if (out32) out32[e] = (float)v;
+}
+
+void ms_gather_comp(int nnzb, int b, const double *slab, int comp, double *out, float *out32, hipStream_t st) {
+    if (nnzb == 0) return;
+    hipLaunchKernelGGL(k_gather_comp, dim3(nblocks(nnzb, 256)), dim3(256), 0, st, nnzb, b, slab, comp, out, out32);
     CPTR_CHECK_LAUNCH();
 }
 
@@ -218,15 +243,15 @@ void vc_sub(int n, const double *x, double *e, hipStream_t st) {
 }
 
 #define INST(T)                                                                                                   \
-    template void vc_presmooth_residual<T>(int, const int *, const int *, const T *, const T *, T, const T *, int, \
-                                           int, T *, T *, hipStream_t);                                          \
-    template void vc_spmv<T>(int, const int *, const int *, const T *, const T *, T *, hipStream_t);             \
-    template void vc_prolong_add<T>(int, const int *, const int *, const T *, const T *, T *, hipStream_t);      \
-    template void vc_prolong_to<T>(int, const int *, const int *, const T *, const T *, const T *, T *,          \
+    template void vc_presmooth_residual<T>(int, int, const int *, const int *, const T *, const T *, T, const T *, \
+                                           T *, T *, hipStream_t);                                               \
+    template void vc_spmv<T>(int, int, const int *, const int *, const T *, const T *, T *, hipStream_t);        \
+    template void vc_prolong_add<T>(int, int, const int *, const int *, const T *, const T *, T *, hipStream_t); \
+    template void vc_prolong_to<T>(int, int, const int *, const int *, const T *, const T *, const T *, T *,     \
                                    hipStream_t);                                                                 \
-    template void vc_smooth<T>(int, const int *, const int *, const T *, const T *, T, const T *, int, int,        \
-                               const T *, T *, hipStream_t);                                                     \
-    template void vc_residual<T>(int, const int *, const int *, const T *, const T *, const T *, T *,            \
+    template void vc_smooth<T>(int, int, const int *, const int *, const T *, const T *, T, const T *, const T *, \
+                               T *, hipStream_t);                                                                \
+    template void vc_residual<T>(int, int, const int *, const int *, const T *, const T *, const T *, T *,       \
                                  hipStream_t);                                                                   \
     template void vc_dense_apply<T>(int, const T *, const T *, T *, hipStream_t);                                \
     template void ms_stage_input<T>(int, int, const int *, const int *, const T *, int, const double *,          \
