@@ -27,6 +27,7 @@ static thread_local std::string g_last_error;
 static void set_error(const std::string &m) { g_last_error = m; }
 
 constexpr int MAX_COARSE_DENSE = 8192;
+constexpr int PMIS_BATCH = 3;
 
 // per-hierarchy setup state: each AMG hierarchy is built on its own stream
 // (and host thread) with its own scratch and flag word
@@ -188,7 +189,6 @@ static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
     amg_compact(m, c->s_i2.p, hk.p, hv.p, C.rp_own.p, C.ci_own.p, C.v.p, s);
     C.rp = C.rp_own.p;
     C.ci = C.ci_own.p;
-    CPTR_HIP(hipStreamSynchronize(s));
 }
 
 static void csr_transpose(Builder *c, const CsrD &P, CsrD &R) {
@@ -228,13 +228,15 @@ static void coarse_inverse(Builder *c, Hierarchy &h) {
     h.ncoarse = nc;
     h.cinv.alloc((size_t)nc * nc);
     if (fp32) h.cinv32.alloc((size_t)nc * nc);
-    DBuf<double> aug;
+    DBuf<double> aug, F, U;
     DBuf<int> used, piv;
     aug.alloc((size_t)nc * 2 * nc);
     used.alloc(nc);
     piv.alloc(nc);
+    F.alloc((size_t)nc * 16);
+    U.alloc((size_t)16 * 2 * nc);
     amg_dense_inverse(nc, Lc.A.rp, Lc.A.ci, Lc.A.v.p, aug.p, used.p, piv.p, c->flag.p, h.cinv.p,
-                      fp32 ? h.cinv32.p : nullptr, s);
+                      fp32 ? h.cinv32.p : nullptr, F.p, U.p, s);
     int f = read_flag_and_clear(c);
     if (f & 64) throw Error(CPTR_E_SINGULAR_BLOCK, "singular coarsest AMG operator");
     if (f & 32) throw Error(CPTR_E_SINGULAR_BLOCK, "zero diagonal in an AMG level");
@@ -332,7 +334,10 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         // strength and PMIS
         c->s_i1.alloc((size_t)L.A.nnz + 1);    // transpose positions
         transpose_index(m, L.A.rp, L.A.ci, c->s_i1.p, c->flag.p, s);
-        if (read_flag_and_clear(c) & 8) throw Error(CPTR_E_ARG, "AMG level pattern is not structurally symmetric");
+        // Galerkin products P^T A P of a structurally symmetric A are symmetric:
+        // only the fine level's pattern needs the check
+        if (h.L.size() == 1 && (read_flag_and_clear(c) & 8))
+            throw Error(CPTR_E_ARG, "AMG level pattern is not structurally symmetric");
         L.strong.alloc((size_t)L.A.nnz + 1);
         amg_strength(m, L.A.rp, L.A.ci, L.A.v.p, o.amg_theta, L.strong.p, s);
         c->s_i2.alloc((size_t)m + 1);          // |S^T|
@@ -343,14 +348,18 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         fill_int(c->s_i3.p, 0, 1, s);
         amg_pmis_init(m, L.A.rp, L.A.ci, L.strong.p, c->s_i1.p, o.pmis_seed, c->s_i2.p, c->s_u1.p, L.cf.p,
                       c->s_i3.p, s);
-        int und = read_scalar(c->s_i3.p, s);
-        int rounds = 0;
+        // rounds run in batches between reads of the undecided count (a round
+        // on a fully decided level changes nothing)
+        int und = 1, rounds = 0;
         while (und > 0) {
-            fill_int(c->s_i3.p, 0, 1, s);
-            amg_pmis_round(m, L.A.rp, L.A.ci, L.strong.p, c->s_i1.p, c->s_i2.p, c->s_u1.p, L.cf.p, c->s_c1.p,
-                           c->s_i3.p, s);
+            for (int q = 0; q < PMIS_BATCH; ++q) {
+                fill_int(c->s_i3.p, 0, 1, s);
+                amg_pmis_round(m, L.A.rp, L.A.ci, L.strong.p, c->s_i1.p, c->s_i2.p, c->s_u1.p, L.cf.p, c->s_c1.p,
+                               c->s_i3.p, s);
+            }
             und = read_scalar(c->s_i3.p, s);
-            if (++rounds > 10000) throw Error(CPTR_E_STATE, "PMIS did not terminate");
+            rounds += PMIS_BATCH;
+            if (rounds > 10000) throw Error(CPTR_E_STATE, "PMIS did not terminate");
         }
         // coarse numbering
         DBuf<int> cidx;

@@ -172,8 +172,9 @@ void amg_spgemm_compute_wave(int m, const int *arp, const int *aci, const double
                              const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
 void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
                    int *flag, hipStream_t st);
+// F: n * 16 doubles, U: 16 * 2n doubles (panel multipliers and pivot rows)
 void amg_dense_inverse(int n, const int *rp, const int *ci, const double *v, double *aug, int *used, int *pivrow,
-                       int *flag, double *inv, float *inv32, hipStream_t st);
+                       int *flag, double *inv, float *inv32, double *F, double *U, hipStream_t st);
 
 // k_vcycle.hip (double and float instantiations)
 template <class T>

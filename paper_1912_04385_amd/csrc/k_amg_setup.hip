@@ -853,60 +853,101 @@ __global__ void k_dense_aug(int n, const int *__restrict__ rp, const int *__rest
 }
 
 // Gauss-Jordan elimination with partial pivoting, without row normalisation,
-// one launch per column k.  Every block first finds the pivot of column k
-// redundantly (the first unused row with the largest |aug[r][k]|; rows used by
-// earlier steps are excluded through used[] (steps < k-1, written by earlier
-// launches) and pivrow[k-1]), so all blocks agree without a grid barrier; block
-// (0,0) records pivrow[k] and marks the previous pivot used.  Then every row
-// r != p of the block's row range gets aug[r][c] -= (aug[r][k]/aug[p][k]) aug[p][c]
-// for the block's columns c > k.
+// in panels of GJ_NB columns.  Column k: the pivot p_k is the first unused row
+// with the largest |aug[r][k]|; every row r != p_k gets
+// aug[r][c] -= f_rk aug[p_k][c] for c > k with f_rk = aug[r][k] / aug[p_k][k].
+// The panel kernel (one workgroup) runs these steps on the panel's own
+// columns and records the multipliers F[r][k - k0] (0 for r = p_k).  The
+// columns right of the panel then take all steps at once: with
+// u_k(c) = aug[p_k][c] - sum_{j<k} F[p_k][j] u_j(c) (the pivot rows' values
+// as the sequential steps see them), aug[r][c] -= sum_k F[r][k] u_k(c).
+constexpr int GJ_NB = 16;
 constexpr int GJ_ROWS = 16;
+constexpr int GJ_PANEL_THREADS = 1024;
 
-__global__ void __launch_bounds__(256) k_gj_step(int n, int k, double *aug, int *used, int *pivrow, int *flag) {
-    __shared__ double bv[256];
-    __shared__ int bi[256];
+__global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, int nb, double *aug, int *used,
+                                                                int *pivrow, double *F, int *flag) {
+    __shared__ double bv[GJ_PANEL_THREADS];
+    __shared__ int bi[GJ_PANEL_THREADS];
     const size_t ld = 2 * (size_t)n;
-    const int pprev = (k > 0) ? pivrow[k - 1] : -1;
-    double best = -1.0;
-    int arg = -1;
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        if (r == pprev || used[r]) continue;
-        double a = fabs(aug[(size_t)r * ld + k]);
-        if (a > best) { best = a; arg = r; }
-    }
-    bv[threadIdx.x] = best;
-    bi[threadIdx.x] = arg;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            double ov = bv[threadIdx.x + s];
-            int oi = bi[threadIdx.x + s];
-            if (oi >= 0 && (bi[threadIdx.x] < 0 || ov > bv[threadIdx.x] ||
-                            (ov == bv[threadIdx.x] && oi < bi[threadIdx.x]))) {
-                bv[threadIdx.x] = ov;
-                bi[threadIdx.x] = oi;
+    const int tid = threadIdx.x;
+    for (int kk = 0; kk < nb; ++kk) {
+        const int k = k0 + kk;
+        double best = -1.0;
+        int arg = -1;
+        for (int r = tid; r < n; r += blockDim.x) {
+            if (used[r]) continue;
+            const double a = fabs(aug[(size_t)r * ld + k]);
+            if (a > best) { best = a; arg = r; }
+        }
+        bv[tid] = best;
+        bi[tid] = arg;
+        __syncthreads();
+        for (int sft = blockDim.x / 2; sft > 0; sft >>= 1) {
+            if (tid < sft) {
+                const double ov = bv[tid + sft];
+                const int oi = bi[tid + sft];
+                if (oi >= 0 && (bi[tid] < 0 || ov > bv[tid] || (ov == bv[tid] && oi < bi[tid]))) {
+                    bv[tid] = ov;
+                    bi[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int p = bi[0];
+        const bool bad = (p < 0) || (bv[0] == 0.0);
+        __syncthreads();
+        if (bad) {
+            if (tid == 0) atomicOr(flag, 64);
+            return;
+        }
+        const double piv = aug[(size_t)p * ld + k];
+        for (int r = tid; r < n; r += blockDim.x) F[(size_t)r * nb + kk] = (r == p) ? 0.0 : aug[(size_t)r * ld + k] / piv;
+        if (tid == 0) {
+            pivrow[k] = p;
+            used[p] = 1;
+        }
+        __syncthreads();
+        const int w = k0 + nb - k - 1;   // panel columns right of k
+        if (w > 0) {
+            for (long idx = tid; idx < (long)n * w; idx += blockDim.x) {
+                const int r = (int)(idx / w), c = k + 1 + (int)(idx % w);
+                if (r == p) continue;
+                aug[(size_t)r * ld + c] -= F[(size_t)r * nb + kk] * aug[(size_t)p * ld + c];
             }
         }
         __syncthreads();
     }
-    int p = bi[0];
-    const bool bad = (p < 0) || (bv[0] == 0.0);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-        pivrow[k] = (p < 0) ? 0 : p;
-        if (pprev >= 0) used[pprev] = 1;
-        if (bad) atomicOr(flag, 64);
-    }
-    if (bad) return;
-    const double piv = aug[(size_t)p * ld + k];
-    const int c = k + 1 + blockIdx.x * blockDim.x + threadIdx.x;
+}
+
+// U[kk][c] = u_k(c) for the columns right of the panel
+__global__ void k_gj_pivot_rows(int n, int k0, int nb, const double *__restrict__ aug, const int *__restrict__ pivrow,
+                                const double *__restrict__ F, double *__restrict__ U) {
+    const size_t ld = 2 * (size_t)n;
+    const int c = k0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= 2 * n) return;
-    const double pc = aug[(size_t)p * ld + c];
-    const int r0 = blockIdx.y * GJ_ROWS;
-    const int r1 = min(n, r0 + GJ_ROWS);
+    double u[GJ_NB];
+    for (int kk = 0; kk < nb; ++kk) {
+        const int p = pivrow[k0 + kk];
+        double v = aug[(size_t)p * ld + c];
+        for (int j = 0; j < kk; ++j) v -= F[(size_t)p * nb + j] * u[j];
+        u[kk] = v;
+        U[(size_t)kk * ld + c] = v;
+    }
+}
+
+__global__ void k_gj_trailing(int n, int k0, int nb, double *__restrict__ aug, const double *__restrict__ F,
+                              const double *__restrict__ U) {
+    const size_t ld = 2 * (size_t)n;
+    const int c = k0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= 2 * n) return;
+    double u[GJ_NB];
+    for (int kk = 0; kk < nb; ++kk) u[kk] = U[(size_t)kk * ld + c];
+    const int r0 = blockIdx.y * GJ_ROWS, r1 = min(n, r0 + GJ_ROWS);
     for (int r = r0; r < r1; ++r) {
-        if (r == p) continue;
-        const double f = aug[(size_t)r * ld + k] / piv;
-        aug[(size_t)r * ld + c] -= f * pc;
+        double a = aug[(size_t)r * ld + c];
+        for (int kk = 0; kk < nb; ++kk) a -= F[(size_t)r * nb + kk] * u[kk];
+        aug[(size_t)r * ld + c] = a;
     }
 }
 
@@ -925,16 +966,18 @@ __global__ void k_gj_extract(int n, const double *aug, const int *pivrow, double
 }
 
 void amg_dense_inverse(int n, const int *rp, const int *ci, const double *v, double *aug, int *used, int *pivrow,
-                       int *flag, double *inv, float *inv32, hipStream_t st) {
+                       int *flag, double *inv, float *inv32, double *F, double *U, hipStream_t st) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_dense_aug, dim3(n), dim3(256), 0, st, n, rp, ci, v, aug);
     fill_int(used, 0, n, st);
     const int nby = (n + GJ_ROWS - 1) / GJ_ROWS;
-    for (int k = 0; k < n; ++k) {
-        int width = 2 * n - (k + 1);
-        int nbx = (width + 255) / 256;
-        if (nbx < 1) nbx = 1;
-        hipLaunchKernelGGL(k_gj_step, dim3(nbx, nby), dim3(256), 0, st, n, k, aug, used, pivrow, flag);
+    for (int k0 = 0; k0 < n; k0 += GJ_NB) {
+        const int nb = std::min(GJ_NB, n - k0);
+        hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(GJ_PANEL_THREADS), 0, st, n, k0, nb, aug, used, pivrow, F, flag);
+        const int width = 2 * n - (k0 + nb);
+        const int nbx = (width + 255) / 256;
+        hipLaunchKernelGGL(k_gj_pivot_rows, dim3(nbx), dim3(256), 0, st, n, k0, nb, aug, pivrow, F, U);
+        hipLaunchKernelGGL(k_gj_trailing, dim3(nbx, nby), dim3(256), 0, st, n, k0, nb, aug, F, U);
     }
     hipLaunchKernelGGL(k_gj_extract, dim3(n), dim3(256), 0, st, n, aug, pivrow, inv, inv32);
     CPTR_CHECK_LAUNCH();
