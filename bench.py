@@ -335,6 +335,8 @@ def main() -> int:
         dt = time.perf_counter() - t0
         for k, r in enumerate(results):
             print(f"# {label} step {k}: its={r['iterations']} setup={r['setup_ms']:.1f} ms "
+                  f"(scale {r['t_setup_scale_ms']:.1f}, AMG T {r['t_setup_amgT_ms']:.1f}, "
+                  f"AMG P {r['t_setup_amgP_ms']:.1f}, values {r['t_setup_values_ms']:.1f}) "
                   f"solve={r['solve_ms']:.1f} ms rel_res={r['rel_res_scaled']:.2e} "
                   f"unscaled={r['rel_res_unscaled']:.2e}", file=sys.stderr, flush=True)
         return dt * 1000.0 / args.steps, results

@@ -121,6 +121,10 @@ typedef struct {
     /* learned interpolation judge of the last full temperature build        */
     /* (-1: not measured)                                                    */
     double  rho_T_classical, rho_T_learned;
+    /* host wall clock of the last setup / update_values: scaling and          */
+    /* extraction; temperature and pressure hierarchies (built concurrently,  */
+    /* each from its start); the whole value-dependent setup                  */
+    double  t_setup_scale_ms, t_setup_amgT_ms, t_setup_amgP_ms, t_setup_values_ms;
 } cptr_result;
 
 /* Fill *opt with the defaults noted above (CPTR3, T then P, BILU(0) in 32x8

@@ -57,6 +57,8 @@ class Result(ctypes.Structure):
         ("t_stage1_ms", ctypes.c_double), ("t_stage2_ms", ctypes.c_double), ("t_last_ms", ctypes.c_double),
         ("t_spmv_ms", ctypes.c_double), ("t_arnoldi_ms", ctypes.c_double),
         ("rho_T_classical", ctypes.c_double), ("rho_T_learned", ctypes.c_double),
+        ("t_setup_scale_ms", ctypes.c_double), ("t_setup_amgT_ms", ctypes.c_double),
+        ("t_setup_amgP_ms", ctypes.c_double), ("t_setup_values_ms", ctypes.c_double),
     ]
 
     def to_dict(self) -> dict:

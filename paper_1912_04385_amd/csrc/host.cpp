@@ -102,6 +102,9 @@ struct cptr_ctx {
     Builder bld[3];
     double tacc[5] = {};
     int tsteps = 0;
+    // host wall-clock phases of the last setup: scaling + extraction,
+    // temperature and pressure hierarchies (concurrent), last-stage factor
+    double tph[4] = {};
 
     void mark(int k) {
         if (opt.timing) CPTR_HIP(hipEventRecord(tev[k], stream));
@@ -686,8 +689,13 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals) {
     c->rho_lrn = rl;
 }
 
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     hipStream_t s = c->stream;
+    const auto t_start = std::chrono::steady_clock::now();
     const int n = c->n, b = c->b, nnzb = c->nnzb;
     const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
     c->abar.alloc((size_t)nnzb * b * b);
@@ -730,6 +738,8 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     }
     // scalar stages: the two hierarchies are built concurrently, each on its
     // own stream and host thread, while this stream factors the last stage
+    c->tph[0] = ms_since(t_start);
+    const auto t_hier = std::chrono::steady_clock::now();
     const bool need[2] = {c->opt.variant == CPTR_VARIANT_CPTR3,
                           c->opt.variant == CPTR_VARIANT_CPTR3 || c->opt.variant == CPTR_VARIANT_CPR};
     const double *svals[2] = {ctt.p, bpp.p};
@@ -759,7 +769,8 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         B.nnzb = nnzb;
         B.rp.p = c->rp.p;
         B.ci.p = c->ci.p;
-        th[k] = std::thread([c, k, &B, &svals, &err, &refresh, &kept]() {
+        c->tph[1 + k] = 0.0;
+        th[k] = std::thread([c, k, &B, &svals, &err, &refresh, &kept, t_hier]() {
             try {
                 CPTR_HIP(hipSetDevice(c->device));
                 StreamScope scope(B.stream);
@@ -786,6 +797,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                     full_build(c, B, k, svals[k]);
                 }
                 CPTR_HIP(hipEventRecord(c->ev_side[k], B.stream));
+                c->tph[1 + k] = ms_since(t_hier);
             } catch (...) {
                 err[k] = std::current_exception();
             }
@@ -831,6 +843,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         c->tw.alloc(2 * (size_t)n * b);
     }
     CPTR_HIP(hipStreamSynchronize(s));
+    c->tph[3] = ms_since(t_start);
 }
 
 static void alloc_krylov(cptr_ctx *c) {
@@ -1175,6 +1188,10 @@ cptr_status cptr_solve(cptr_ctx *c, const double *d_rhs, double *d_x, cptr_resul
     res.used_learned = c->used_learned;
     res.rho_T_classical = c->rho_cls;
     res.rho_T_learned = c->rho_lrn;
+    res.t_setup_scale_ms = c->tph[0];
+    res.t_setup_amgT_ms = c->tph[1];
+    res.t_setup_amgP_ms = c->tph[2];
+    res.t_setup_values_ms = c->tph[3];
     if (out) *out = res;
     return st;
     CPTR_API_END
