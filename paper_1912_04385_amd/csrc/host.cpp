@@ -28,6 +28,7 @@ static void set_error(const std::string &m) { g_last_error = m; }
 
 constexpr int MAX_COARSE_DENSE = 8192;
 constexpr int PMIS_BATCH = 3;
+constexpr int SPGEMM_THREAD_CAP = 48;   // LDS hash capacity of the thread-per-row SpGEMM
 
 // per-hierarchy setup state: each AMG hierarchy is built on its own stream
 // (and host thread) with its own scratch and flag word
@@ -166,22 +167,27 @@ static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
     hipStream_t s = c->stream;
     const int m = A.n;
     c->s_i1.alloc((size_t)m + 1);
-    c->s_i2.alloc((size_t)m + 1);
+    c->s_i2.alloc((size_t)m + 2);
     c->s_i3.alloc((size_t)m + 1);
-    amg_spgemm_bound(m, A.rp, A.ci, B.rp, c->s_i1.p, s);
-    const int cap = scan_total(c->s_i1.p, c->s_i2.p, m, s);   // hash offsets
+    // capacities, their offsets, and (in s_i2[m + 1]) the longest row's product count
+    amg_spgemm_bound(m, A.rp, A.ci, B.rp, c->s_i1.p, c->s_i2.p + m + 1, s);
+    scan_exclusive(c->s_i1.p, c->s_i2.p, m, nullptr, s);
+    int tm[2];
+    CPTR_HIP(hipMemcpyAsync(tm, c->s_i2.p + m, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CPTR_HIP(hipStreamSynchronize(s));
+    const int cap = tm[0], maxprod = tm[1];
     DBuf<int> hk;
     DBuf<double> hv;
     hk.alloc((size_t)cap);
     hv.alloc((size_t)cap);
-    // short rows: one thread per row; long rows (coarse levels): one wavefront per row
-    // many rows: one thread per row keeps the machine busy; few (long) rows:
-    // one wavefront per row avoids a sequential tail
+    // rows short enough for an LDS hash table: one thread per row; longer
+    // rows: lane groups that sort the row's products (all kernels give the
+    // same sums, bit for bit)
     const int sk = c->opt.setup_kernels;
-    if (sk == 2 || (sk == 0 && m > 50000))
+    if (sk == 2 || (sk == 0 && 2 * maxprod + 1 <= SPGEMM_THREAD_CAP))
         amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
     else
-        amg_spgemm_compute_wave(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
+        amg_spgemm_compute_sort(m, maxprod, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
     C.n = m;
     C.ncols = B.ncols;
     C.rp_own.alloc((size_t)m + 1);

@@ -165,11 +165,13 @@ void amg_compact(int n, const int *off, const int *tcol, const double *tw, const
                  hipStream_t st);
 void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v, int *rpT, int *ciT, double *vT,
                    int *work, hipStream_t st);
-void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, hipStream_t st);
+// maxprod (device, may be NULL) receives the largest product count of a row
+void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, int *maxprod, hipStream_t st);
+void amg_spgemm_compute_sort(int m, int maxprod, const int *arp, const int *aci, const double *av, const int *brp,
+                             const int *bci, const double *bv, const int *off, int *tcol, double *tval, int *cnt,
+                             hipStream_t st);
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
                         const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
-void amg_spgemm_compute_wave(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
-                             const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
 void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
                    int *flag, hipStream_t st);
 // F: n * 16 doubles, U: 16 * 2n doubles (panel multipliers and pivot rows)

@@ -627,7 +627,7 @@ void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v
 // in ascending k starting from the first term)
 // --------------------------------------------------------------------------
 __global__ void k_spgemm_bound(int m, const int *__restrict__ arp, const int *__restrict__ aci,
-                               const int *__restrict__ brp, int *__restrict__ ub) {
+                               const int *__restrict__ brp, int *__restrict__ ub, int *maxprod) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     int c = 0;
@@ -636,11 +636,13 @@ __global__ void k_spgemm_bound(int m, const int *__restrict__ arp, const int *__
         c += brp[k + 1] - brp[k];
     }
     ub[i] = 2 * c + 1;      // hash capacity
+    if (maxprod) atomicMax(maxprod, c);
 }
 
-void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, hipStream_t st) {
+void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, int *maxprod, hipStream_t st) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_spgemm_bound, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, arp, aci, brp, ub);
+    if (maxprod) fill_int(maxprod, 0, 1, st);
+    hipLaunchKernelGGL(k_spgemm_bound, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, arp, aci, brp, ub, maxprod);
     CPTR_CHECK_LAUNCH();
 }
 
@@ -718,89 +720,105 @@ __global__ void __launch_bounds__(SPG_T) k_spgemm_compute(int m, const int *__re
         spgemm_row(i, arp, aci, av, brp, bci, bv, ok, ov, 1, cap, ok, ov, cnt);
 }
 
-// One wavefront per output row, for products with long rows (coarse levels).
-// The row's products are expanded into LDS in A's row order (position p),
-// stably ranked by column (rank = #smaller columns + #equal columns at smaller
-// p), and each distinct column is summed sequentially over its terms in p
-// order starting from the first term -- the same sum, bit for bit, as the
-// sequential accumulation.  Rows with more than SPW_CAP products are handled
-// by lane 0 with the global-memory hash.
-constexpr int SPW_CAP = 1024;
-
-__global__ void __launch_bounds__(64) k_spgemm_wave(int m, const int *__restrict__ arp, const int *__restrict__ aci,
+// G lanes per output row, for rows of up to CAP products: the products are
+// expanded into LDS in A's row order (position p), sorted by the key
+// (column, p) with a bitonic network, and each distinct column is summed over
+// its terms in p order starting from the first term -- the same sum, bit for
+// bit, as the sequential accumulation.  Longer rows: lane 0 of the group with
+// the global-memory hash.  One wavefront per block; the sort length is the
+// wavefront's largest row rounded up to a power of two.
+template <int G, int CAP>
+__global__ void __launch_bounds__(64) k_spgemm_sort(int m, const int *__restrict__ arp, const int *__restrict__ aci,
                                                     const double *__restrict__ av, const int *__restrict__ brp,
                                                     const int *__restrict__ bci, const double *__restrict__ bv,
                                                     const int *__restrict__ off, int *__restrict__ tcol,
                                                     double *__restrict__ tval, int *__restrict__ cnt) {
-    __shared__ int key[SPW_CAP];
-    __shared__ double val[SPW_CAP];
-    __shared__ int skey[SPW_CAP];
-    __shared__ double sval[SPW_CAP];
-    __shared__ int head_pos[SPW_CAP];
-    const int i = blockIdx.x;
-    const int lane = threadIdx.x;
-    if (i >= m) return;
-    const int cap = off[i + 1] - off[i];
-    const int nprod = (cap - 1) / 2;           // the bound kernel stored 2 * products + 1
+    constexpr int NG = 64 / G;
+    __shared__ unsigned long long skey[NG][CAP];
+    __shared__ double sval[NG][CAP];
+    const int lane = threadIdx.x, g = lane / G, gl = lane % G;
+    const int i = blockIdx.x * NG + g;
+    const bool act = i < m;
+    int cap = 0, nprod = 0;
+    if (act) {
+        cap = off[i + 1] - off[i];
+        nprod = (cap - 1) / 2;                // the bound kernel stored 2 * products + 1
+    }
+    const bool big = nprod > CAP;
+    const int myP = (act && !big) ? nprod : 0;
+    int maxP = myP;
+    for (int d = 32; d >= 1; d >>= 1) maxP = max(maxP, __shfl_xor(maxP, d, 64));
+    int S = 1;
+    while (S < maxP) S <<= 1;
+    if (act && !big) {
+        int base = 0;
+        for (int e = arp[i]; e < arp[i + 1]; ++e) {
+            const int k = aci[e];
+            const double a = av[e];
+            const int f0 = brp[k], len = brp[k + 1] - f0;
+            for (int t = gl; t < len; t += G) {
+                const int p = base + t;
+                skey[g][p] = ((unsigned long long)(unsigned)bci[f0 + t] << 32) | (unsigned)p;
+                sval[g][p] = a * bv[f0 + t];
+            }
+            base += len;
+        }
+    }
+    for (int p = myP + gl; p < S; p += G) skey[g][p] = ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= S; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = gl; t < S; t += G) {
+                const int q = t ^ j;
+                if (q > t) {
+                    const unsigned long long x = skey[g][t], y = skey[g][q];
+                    if ((x > y) == ((t & k) == 0)) {
+                        skey[g][t] = y;
+                        skey[g][q] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (!act) return;
     int *ok = tcol + off[i];
     double *ov = tval + off[i];
-    if (nprod > SPW_CAP) {
-        if (lane == 0) spgemm_row(i, arp, aci, av, brp, bci, bv, ok, ov, 1, cap, ok, ov, cnt);
+    if (big) {
+        if (gl == 0) spgemm_row(i, arp, aci, av, brp, bci, bv, ok, ov, 1, cap, ok, ov, cnt);
         return;
     }
-    // expansion in A's row order
-    int base = 0;
-    for (int e = arp[i]; e < arp[i + 1]; ++e) {
-        const int k = aci[e];
-        const double a = av[e];
-        const int f0 = brp[k], len = brp[k + 1] - f0;
-        for (int t = lane; t < len; t += 64) {
-            key[base + t] = bci[f0 + t];
-            val[base + t] = a * bv[f0 + t];
-        }
-        base += len;
-    }
-    __syncthreads();
-    const int P = base;
-    // stable rank by column: smaller columns anywhere, equal columns earlier
-    for (int p = lane; p < P; p += 64) {
-        const int kp = key[p];
-        int rank = 0;
-        for (int q = 0; q < P; ++q) {
-            const int kq = key[q];
-            rank += (kq < kp) || (kq == kp && q < p);
-        }
-        skey[rank] = kp;
-        sval[rank] = val[p];
-    }
-    __syncthreads();
-    // segment heads and their output slots
-    int nheads_before = 0;
-    for (int c0 = 0; c0 < P; c0 += 64) {
-        const int pos = c0 + lane;
-        const bool head = pos < P && (pos == 0 || skey[pos] != skey[pos - 1]);
-        const unsigned long long mask = __ballot(head);
+    const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
+    int nh = 0;
+    for (int c0 = 0; c0 < myP; c0 += G) {
+        const int pos = c0 + gl;
+        const bool head = pos < myP && (pos == 0 || (skey[g][pos] >> 32) != (skey[g][pos - 1] >> 32));
+        const unsigned long long mask = __ballot(head) & gmask;
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
-        if (head) head_pos[nheads_before + before] = pos;
-        nheads_before += __popcll(mask);
+        if (head) {
+            const unsigned long long kh = skey[g][pos];
+            const unsigned j = (unsigned)(kh >> 32);
+            double acc = sval[g][(unsigned)kh];
+            for (int t = pos + 1; t < myP && (unsigned)(skey[g][t] >> 32) == j; ++t)
+                acc = acc + sval[g][(unsigned)skey[g][t]];
+            ok[nh + before] = (int)j;
+            ov[nh + before] = acc;
+        }
+        nh += __popcll(mask);
     }
-    __syncthreads();
-    const int u = nheads_before;
-    for (int h = lane; h < u; h += 64) {
-        const int pos = head_pos[h];
-        const int j = skey[pos];
-        double acc = sval[pos];
-        for (int t = pos + 1; t < P && skey[t] == j; ++t) acc = acc + sval[t];
-        ok[h] = j;
-        ov[h] = acc;
-    }
-    if (lane == 0) cnt[i] = u;
+    if (gl == 0) cnt[i] = nh;
 }
 
-void amg_spgemm_compute_wave(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
-                             const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st) {
+void amg_spgemm_compute_sort(int m, int maxprod, const int *arp, const int *aci, const double *av, const int *brp,
+                             const int *bci, const double *bv, const int *off, int *tcol, double *tval, int *cnt,
+                             hipStream_t st) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_spgemm_wave, dim3(m), dim3(64), 0, st, m, arp, aci, av, brp, bci, bv, off, tcol, tval, cnt);
+    if (maxprod <= 256)
+        hipLaunchKernelGGL((k_spgemm_sort<16, 256>), dim3((m + 3) / 4), dim3(64), 0, st, m, arp, aci, av, brp, bci,
+                           bv, off, tcol, tval, cnt);
+    else
+        hipLaunchKernelGGL((k_spgemm_sort<64, 1024>), dim3(m), dim3(64), 0, st, m, arp, aci, av, brp, bci, bv, off,
+                           tcol, tval, cnt);
     CPTR_CHECK_LAUNCH();
 }
 
