@@ -29,6 +29,7 @@ static void set_error(const std::string &m) { g_last_error = m; }
 constexpr int MAX_COARSE_DENSE = 8192;
 constexpr int PMIS_BATCH = 3;
 constexpr int SPGEMM_THREAD_CAP = 48;   // LDS hash capacity of the thread-per-row SpGEMM
+constexpr int EXTI_THREAD_ROWS = 100000;  // ext+i: one thread per row above this many rows
 
 // per-hierarchy setup state: each AMG hierarchy is built on its own stream
 // (and host thread) with its own scratch and flag word
@@ -381,13 +382,14 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         ub.alloc(m + 1);
         off.alloc(m + 1);
         cnt.alloc(m + 1);
-        amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, s);
+        const bool exti_thread = (o.setup_kernels == 2 || (o.setup_kernels == 0 && m > EXTI_THREAD_ROWS));
+        amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, !exti_thread, s);
         const int cap = scan_total(ub.p, off.p, m, s);
         tcol.alloc(cap);
         twt.alloc(cap);
         td.alloc((size_t)L.A.nnz + 1);
         // short rows: one thread per row; long rows (coarse levels): one wavefront per row
-        if (o.setup_kernels == 2 || (o.setup_kernels == 0 && m > 100000))
+        if (exti_thread)
             amg_exti_compute2(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
                               tcol.p, twt.p, td.p, cnt.p, s);
         else

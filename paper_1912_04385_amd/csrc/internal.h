@@ -153,7 +153,7 @@ void amg_pmis_init(int n, const int *rp, const int *ci, const unsigned char *s, 
                    int *cntT, uint64_t *h, int *state, int *und, hipStream_t st);
 void amg_pmis_round(int n, const int *rp, const int *ci, const unsigned char *s, const int *tpos, const int *cntT,
                     const uint64_t *h, int *state, unsigned char *newc, int *und, hipStream_t st);
-void amg_exti_bound(int n, const int *rp, const int *ci, const unsigned char *s, const int *cf, int *ub,
+void amg_exti_bound(int n, const int *rp, const int *ci, const unsigned char *s, const int *cf, int *ub, bool wave,
                     hipStream_t st);
 void amg_exti_compute2(int n, const int *rp, const int *ci, const double *v, const unsigned char *s, const int *cf,
                        const int *cidx, const double *dg, int pmax, const int *off, int *tcol, double *tw,

@@ -157,9 +157,36 @@ __global__ void k_exti_bound(int n, const int *__restrict__ rp, const int *__res
     ub[i] = c > 0 ? c : 1;
 }
 
-void amg_exti_bound(int n, const int *rp, const int *ci, const unsigned char *s, const int *cf, int *ub,
+// the same count, one wavefront per row (coarse levels with long rows): the
+// lanes scan each strong F neighbour's row
+__global__ void __launch_bounds__(64) k_exti_bound_wave(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                        const unsigned char *__restrict__ s,
+                                                        const int *__restrict__ cf, int *__restrict__ ub) {
+    const int i = blockIdx.x, lane = threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == ST_C) {
+        if (lane == 0) ub[i] = 1;
+        return;
+    }
+    int c = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        if (!s[e]) continue;
+        const int j = ci[e];
+        if (cf[j] == ST_C) { c += (lane == 0); continue; }
+        for (int f = rp[j] + lane; f < rp[j + 1]; f += 64)
+            if (s[f] && cf[ci[f]] == ST_C) c++;
+    }
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (lane == 0) ub[i] = c > 0 ? c : 1;
+}
+
+void amg_exti_bound(int n, const int *rp, const int *ci, const unsigned char *s, const int *cf, int *ub, bool wave,
                     hipStream_t st) {
-    hipLaunchKernelGGL(k_exti_bound, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, rp, ci, s, cf, ub);
+    if (n == 0) return;
+    if (wave)
+        hipLaunchKernelGGL(k_exti_bound_wave, dim3(n), dim3(64), 0, st, n, rp, ci, s, cf, ub);
+    else
+        hipLaunchKernelGGL(k_exti_bound, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, rp, ci, s, cf, ub);
     CPTR_CHECK_LAUNCH();
 }
 
@@ -398,25 +425,30 @@ __global__ void __launch_bounds__(64) k_exti_wave(int n, const int *__restrict__
         if (lane == 0) cnt[i] = 0;
         return;
     }
-    // 2. sort + unique: flag first occurrences, then rank them among each other
-    for (int p = lane; p < nc; p += 64) {
-        const int kp = cand[p];
-        bool first = true;
-        for (int r = 0; r < p && first; ++r) first = (cand[r] != kp);
-        kept[p] = first ? 1 : 0;      // kept[] doubles as the first-occurrence flag here
-    }
+    // 2. sort (bitonic network, padded to a power of two) + unique
+    int S = 1;
+    while (S < nc) S <<= 1;
+    for (int p = nc + lane; p < S; p += 64) cand[p] = 0x7fffffff;
     __syncthreads();
+    for (int k = 2; k <= S; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < S; t += 64) {
+                const int q = t ^ j;
+                if (q > t) {
+                    const int x = cand[t], y = cand[q];
+                    if ((x > y) == ((t & k) == 0)) { cand[t] = y; cand[q] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
     int nh = 0;
     for (int c0 = 0; c0 < nc; c0 += 64) {
         const int p = c0 + lane;
-        nh += __popcll(__ballot(p < nc && kept[p]));
-    }
-    for (int p = lane; p < nc; p += 64) {
-        if (!kept[p]) continue;
-        const int kp = cand[p];
-        int rank = 0;
-        for (int q = 0; q < nc; ++q) rank += (kept[q] && cand[q] < kp);
-        hat[rank] = kp;
+        const bool head = p < nc && (p == 0 || cand[p] != cand[p - 1]);
+        const unsigned long long mask = __ballot(head);
+        if (head) hat[nh + __popcll(mask & ((1ull << lane) - 1ull))] = cand[p];
+        nh += __popcll(mask);
     }
     __syncthreads();
     auto inhat = [&](int key) {
@@ -596,17 +628,73 @@ __global__ void k_tr_scatter(int nr, const int *__restrict__ rp, const int *__re
     }
 }
 
+// rows of up to SR_SHORT entries: one thread per row, insertion sort in
+// registers; longer rows: one wavefront per row, bitonic sort in LDS (rows
+// beyond SR_LONG: lane 0 in place)
+constexpr int SR_SHORT = 32;
+constexpr int SR_LONG = 1024;
+
 __global__ void k_sort_rows(int n, const int *__restrict__ rp, int *__restrict__ ci, double *__restrict__ v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int a = rp[i], b = rp[i + 1];
-    for (int p = a + 1; p < b; ++p) {
-        int c = ci[p];
-        double x = v[p];
+    const int a = rp[i], len = rp[i + 1] - a;
+    if (len > SR_SHORT || len < 2) return;
+    int c[SR_SHORT];
+    double x[SR_SHORT];
+    for (int p = 0; p < len; ++p) { c[p] = ci[a + p]; x[p] = v[a + p]; }
+    for (int p = 1; p < len; ++p) {
+        const int cc = c[p];
+        const double xx = x[p];
         int q = p - 1;
-        while (q >= a && ci[q] > c) { ci[q + 1] = ci[q]; v[q + 1] = v[q]; --q; }
-        ci[q + 1] = c;
-        v[q + 1] = x;
+        while (q >= 0 && c[q] > cc) { c[q + 1] = c[q]; x[q + 1] = x[q]; --q; }
+        c[q + 1] = cc;
+        x[q + 1] = xx;
+    }
+    for (int p = 0; p < len; ++p) { ci[a + p] = c[p]; v[a + p] = x[p]; }
+}
+
+__global__ void __launch_bounds__(64) k_sort_rows_long(int n, const int *__restrict__ rp, int *__restrict__ ci,
+                                                       double *__restrict__ v) {
+    __shared__ unsigned long long key[SR_LONG];
+    __shared__ double val[SR_LONG];
+    const int i = blockIdx.x, lane = threadIdx.x;
+    if (i >= n) return;
+    const int a = rp[i], len = rp[i + 1] - a;
+    if (len <= SR_SHORT) return;
+    if (len > SR_LONG) {
+        if (lane == 0)
+            for (int p = a + 1; p < a + len; ++p) {
+                const int cc = ci[p];
+                const double xx = v[p];
+                int q = p - 1;
+                while (q >= a && ci[q] > cc) { ci[q + 1] = ci[q]; v[q + 1] = v[q]; --q; }
+                ci[q + 1] = cc;
+                v[q + 1] = xx;
+            }
+        return;
+    }
+    int S = 1;
+    while (S < len) S <<= 1;
+    for (int p = lane; p < S; p += 64) {
+        key[p] = p < len ? (((unsigned long long)(unsigned)ci[a + p] << 32) | (unsigned)p) : ~0ull;
+        if (p < len) val[p] = v[a + p];
+    }
+    __syncthreads();
+    for (int k = 2; k <= S; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < S; t += 64) {
+                const int q = t ^ j;
+                if (q > t) {
+                    const unsigned long long x = key[t], y = key[q];
+                    if ((x > y) == ((t & k) == 0)) { key[t] = y; key[q] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int p = lane; p < len; p += 64) {
+        ci[a + p] = (int)(key[p] >> 32);
+        v[a + p] = val[(unsigned)key[p]];
     }
 }
 
@@ -618,6 +706,7 @@ void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v
     CPTR_HIP(hipMemcpyAsync(work, rpT, sizeof(int) * nc, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_tr_scatter, dim3(blocks_for(nr, 256)), dim3(256), 0, st, nr, rp, ci, v, work, ciT, vT);
     hipLaunchKernelGGL(k_sort_rows, dim3(blocks_for(nc, 128)), dim3(128), 0, st, nc, rpT, ciT, vT);
+    hipLaunchKernelGGL(k_sort_rows_long, dim3(nc), dim3(64), 0, st, nc, rpT, ciT, vT);
     CPTR_CHECK_LAUNCH();
 }
 
@@ -880,17 +969,23 @@ __global__ void k_dense_aug(int n, const int *__restrict__ rp, const int *__rest
 // u_k(c) = aug[p_k][c] - sum_{j<k} F[p_k][j] u_j(c) (the pivot rows' values
 // as the sequential steps see them), aug[r][c] -= sum_k F[r][k] u_k(c).
 constexpr int GJ_NB = 16;
-constexpr int GJ_ROWS = 16;
+constexpr int GJ_ROWS = 4;
 constexpr int GJ_PANEL_THREADS = 1024;
 
+// Panel kernel, one workgroup: the steps of the panel's columns, the
+// multipliers into F.  Thread (row group, panel column): every thread of a
+// row computes that row's multiplier, the first one stores it.
 __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, int nb, double *aug, int *used,
                                                                 int *pivrow, double *F, int *flag) {
-    __shared__ double bv[GJ_PANEL_THREADS];
-    __shared__ int bi[GJ_PANEL_THREADS];
+    __shared__ double wv[GJ_PANEL_THREADS / 64];
+    __shared__ int wi[GJ_PANEL_THREADS / 64];
+    __shared__ int sp;
     const size_t ld = 2 * (size_t)n;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cc = tid % GJ_NB, r0 = tid / GJ_NB, rstep = blockDim.x / GJ_NB;
     for (int kk = 0; kk < nb; ++kk) {
         const int k = k0 + kk;
+        // pivot: the first unused row with the largest |value| in column k
         double best = -1.0;
         int arg = -1;
         for (int r = tid; r < n; r += blockDim.x) {
@@ -898,41 +993,33 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, in
             const double a = fabs(aug[(size_t)r * ld + k]);
             if (a > best) { best = a; arg = r; }
         }
-        bv[tid] = best;
-        bi[tid] = arg;
-        __syncthreads();
-        for (int sft = blockDim.x / 2; sft > 0; sft >>= 1) {
-            if (tid < sft) {
-                const double ov = bv[tid + sft];
-                const int oi = bi[tid + sft];
-                if (oi >= 0 && (bi[tid] < 0 || ov > bv[tid] || (ov == bv[tid] && oi < bi[tid]))) {
-                    bv[tid] = ov;
-                    bi[tid] = oi;
-                }
-            }
-            __syncthreads();
+        for (int d = 32; d >= 1; d >>= 1) {
+            const double ov = __shfl_xor(best, d, 64);
+            const int oi = __shfl_xor(arg, d, 64);
+            if (oi >= 0 && (arg < 0 || ov > best || (ov == best && oi < arg))) { best = ov; arg = oi; }
         }
-        const int p = bi[0];
-        const bool bad = (p < 0) || (bv[0] == 0.0);
+        if (lane == 0) { wv[wave] = best; wi[wave] = arg; }
         __syncthreads();
-        if (bad) {
-            if (tid == 0) atomicOr(flag, 64);
-            return;
-        }
-        const double piv = aug[(size_t)p * ld + k];
-        for (int r = tid; r < n; r += blockDim.x) F[(size_t)r * nb + kk] = (r == p) ? 0.0 : aug[(size_t)r * ld + k] / piv;
         if (tid == 0) {
-            pivrow[k] = p;
-            used[p] = 1;
+            double b0 = wv[0];
+            int a0 = wi[0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+                if (wi[w] >= 0 && (a0 < 0 || wv[w] > b0 || (wv[w] == b0 && wi[w] < a0))) { b0 = wv[w]; a0 = wi[w]; }
+            sp = (a0 >= 0 && b0 != 0.0) ? a0 : -1;
+            if (sp < 0) atomicOr(flag, 64);
+            else { pivrow[k] = a0; used[a0] = 1; }
         }
         __syncthreads();
-        const int w = k0 + nb - k - 1;   // panel columns right of k
-        if (w > 0) {
-            for (long idx = tid; idx < (long)n * w; idx += blockDim.x) {
-                const int r = (int)(idx / w), c = k + 1 + (int)(idx % w);
-                if (r == p) continue;
-                aug[(size_t)r * ld + c] -= F[(size_t)r * nb + kk] * aug[(size_t)p * ld + c];
-            }
+        const int p = sp;
+        if (p < 0) return;
+        const double piv = aug[(size_t)p * ld + k];
+        const int c = k + 1 + cc;
+        const bool upd = (c < k0 + nb);
+        const double pc = upd ? aug[(size_t)p * ld + c] : 0.0;
+        for (int r = r0; r < n; r += rstep) {
+            const double f = (r == p) ? 0.0 : aug[(size_t)r * ld + k] / piv;
+            if (cc == 0) F[(size_t)r * nb + kk] = f;
+            if (upd && r != p) aug[(size_t)r * ld + c] -= f * pc;
         }
         __syncthreads();
     }
