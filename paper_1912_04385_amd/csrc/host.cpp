@@ -729,21 +729,13 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         launch_extract(n, b, nnzb, c->abar.p, c->ip, c->it, ctt.p, bpp.p, c->slabT.p, c->slabP.p,
                        fp32 ? c->abar32.p : nullptr, fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
     } else {
-        launch_decouple_extract(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->abar.p, c->wp.p,
-                                c->wt.p, c->beta.p, c->s_i4.p, ctt.p, bpp.p, c->slabT.p, c->slabP.p,
-                                fp32 ? c->abar32.p : nullptr, fp32 ? c->slabT32.p : nullptr,
-                                fp32 ? c->slabP32.p : nullptr, s);
+        // phase 1: the weights and the two scalar operators (all the AMG setups need)
+        launch_decouple_weights(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
+                                c->beta.p, c->s_i4.p, ctt.p, bpp.p, s);
     }
     int bad = read_scalar(c->s_i4.p, s);
     if (bad != 0x7fffffff)
         throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block (D_ss or Ahat_PP) in cell " + std::to_string(bad));
-    if (c->opt.variant == CPTR_VARIANT_CPTR3) {
-        const bool t_first = (c->opt.stage_order == CPTR_T_THEN_P);
-        c->cpl.alloc(nnzb);
-        if (fp32) c->cpl32.alloc(nnzb);
-        ms_gather_comp(nnzb, b, t_first ? c->slabT.p : c->slabP.p, t_first ? c->ip : c->it, c->cpl.p,
-                       fp32 ? c->cpl32.p : nullptr, s);
-    }
     // scalar stages: the two hierarchies are built concurrently, each on its
     // own stream and host thread, while this stream factors the last stage
     c->tph[0] = ms_since(t_start);
@@ -815,7 +807,19 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         std::thread *t;
         ~Joiner() { for (int k = 0; k < 2; ++k) if (t[k].joinable()) t[k].join(); }
     } joiner{th};
-    // last stage
+    // phase 2 of the scaling, concurrently with the hierarchy builds: the
+    // scaled matrix, its column slabs and FP32 copies, then the last stage
+    if (c->opt.variant != CPTR_VARIANT_LAST_ONLY)
+        launch_decouple_apply(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
+                              c->beta.p, c->abar.p, c->slabT.p, c->slabP.p, fp32 ? c->abar32.p : nullptr,
+                              fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
+    if (c->opt.variant == CPTR_VARIANT_CPTR3) {
+        const bool t_first = (c->opt.stage_order == CPTR_T_THEN_P);
+        c->cpl.alloc(nnzb);
+        if (fp32) c->cpl32.alloc(nnzb);
+        ms_gather_comp(nnzb, b, t_first ? c->slabT.p : c->slabP.p, t_first ? c->ip : c->it, c->cpl.p,
+                       fp32 ? c->cpl32.p : nullptr, s);
+    }
     c->dinv.alloc((size_t)n * b * b);
     fill_int(c->s_i4.p, 0x7fffffff, 1, s);
     if (c->use_tiles) {

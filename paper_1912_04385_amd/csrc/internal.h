@@ -135,10 +135,14 @@ void to_float(const double *x, float *y, size_t n, hipStream_t s);
 // k_decouple.hip
 void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                      double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s);
-void launch_decouple_extract(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
-                             int it, double *abar, double *wp, double *wt, double *beta, int *err, double *ctt,
-                             double *bpp, double *slabT, double *slabP, float *abar32, float *slabT32,
-                             float *slabP32, hipStream_t s);
+// phase 1 (one thread per cell): weights w_P, w_T, beta and the B_PP / C_TT
+// entries; phase 2 (one wavefront per cell): the scaled matrix, slabs, FP32 copies
+void launch_decouple_weights(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
+                             int it, double *wp, double *wt, double *beta, int *err, double *ctt, double *bpp,
+                             hipStream_t s);
+void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
+                           const double *wp, const double *wt, const double *beta, double *abar, double *slabT,
+                           double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s);
 void launch_scale_rhs(int variant, int n, int b, const double *rhs, int ip, int it, const double *wp,
                       const double *wt, const double *beta, double *out, hipStream_t s);
 void launch_unscale(int variant, int n, int b, const double *v, int ip, int it, const double *wp,

@@ -18,38 +18,34 @@ __device__ inline int group_index(int k, int ip, int it, bool with_t) {
     return g;
 }
 
-// One wavefront per cell.  Every lane redundantly solves the small system
+// Phase 1, one thread per cell: solve the small system
 // D_gg^T [w_P w_T] = [D_Pg^T D_Tg^T] (g = the eliminated group: s for CPTR3,
 // s u {T} for CPR) by Gaussian elimination with partial pivoting -- first
-// largest |pivot|, kij order, back substitution in descending rows -- in
-// registers, then handles block entry (r, c) = (lane / b, lane % b) of every
-// block of the row:
-//   Ahat[P][c] = A[P][c] - sum_{k ascending} w_P[k] A[g_k][c]
-//   Ahat[T][c] = A[T][c] - sum_{k ascending} w_T[k] A[g_k][c]
-//   CPTR3: beta = Ahat_ii[T][P] / Ahat_ii[P][P];  Abar[T][c] = Ahat[T][c] - beta Ahat[P][c]
-// The same lanes extract C_TT = Abar[T,T], B_PP = Abar[P,P], the T and P
-// column slabs and the FP32 copies.
+// largest |pivot|, kij order, back substitution in descending rows -- and
+//   CPTR3: beta = Ahat_ii[T][P] / Ahat_ii[P][P],
+// with Ahat[P][c] = A[P][c] - sum_{k ascending} w_P[k] A[g_k][c] and
+// Ahat[T][c] likewise with w_T.  w_P, w_T are stored by unknown (0 outside
+// the group).  The same thread extracts B_PP = Abar[P,P] and
+// C_TT = Abar[T,T] (Abar[T][c] = Ahat[T][c] - beta Ahat[P][c] for CPTR3), the
+// only parts of the scaled matrix that the AMG setups need, so that they can
+// start while phase 2 scales the whole matrix.
 template <int B, int VAR>
-__global__ void __launch_bounds__(64) k_decouple(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                 const double *__restrict__ A, int ip, int it,
-                                                 double *__restrict__ abar, double *__restrict__ wp,
-                                                 double *__restrict__ wt, double *__restrict__ beta, int *err,
-                                                 double *__restrict__ ctt, double *__restrict__ bpp,
-                                                 double *__restrict__ slabT, double *__restrict__ slabP,
-                                                 float *__restrict__ abar32, float *__restrict__ slabT32,
-                                                 float *__restrict__ slabP32) {
+__global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__restrict__ rp,
+                                                          const int *__restrict__ ci, const double *__restrict__ A,
+                                                          int ip, int it, double *__restrict__ wp,
+                                                          double *__restrict__ wt, double *__restrict__ beta, int *err,
+                                                          double *__restrict__ ctt, double *__restrict__ bpp) {
     constexpr bool CPR = (VAR == CPTR_VARIANT_CPR);
     constexpr int NG = CPR ? B - 1 : B - 2;
     constexpr int NR = CPR ? 1 : 2;
     constexpr int NGX = NG > 0 ? NG : 1;
-    const int i = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int d = -1;
     for (int e = rp[i]; e < rp[i + 1]; ++e)
         if (ci[e] == i) d = e;
     if (d < 0) {
-        if (lane == 0) atomicMin(err, i);
+        atomicMin(err, i);
         return;
     }
     const double *D = A + (size_t)d * B * B;
@@ -93,7 +89,7 @@ __global__ void __launch_bounds__(64) k_decouple(int n, const int *__restrict__ 
         }
     }
     if (singular) {
-        if (lane == 0) atomicMin(err, i);
+        atomicMin(err, i);
         return;
     }
 #pragma unroll
@@ -114,21 +110,71 @@ __global__ void __launch_bounds__(64) k_decouple(int n, const int *__restrict__ 
 #pragma unroll
         for (int k = 0; k < NG; ++k) ht = ht - F[k][NR - 1] * D[group_index(k, ip, it, CPR) * B + ip];
         if (hp == 0.0) {
-            if (lane == 0) atomicMin(err, i);
+            atomicMin(err, i);
             return;
         }
         bt = ht / hp;
     }
-    if (lane < B) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
         double vp = 0.0, vt = 0.0;
 #pragma unroll
         for (int k = 0; k < NG; ++k)
-            if (group_index(k, ip, it, CPR) == lane) { vp = F[k][0]; vt = (NR == 2) ? F[k][NR - 1] : 0.0; }
-        wp[(size_t)i * B + lane] = vp;
-        wt[(size_t)i * B + lane] = vt;
+            if (group_index(k, ip, it, CPR) == u) { vp = F[k][0]; vt = (NR == 2) ? F[k][NR - 1] : 0.0; }
+        wp[(size_t)i * B + u] = vp;
+        wt[(size_t)i * B + u] = vt;
     }
-    if (lane == 0) beta[i] = bt;
-    if (lane >= B * B) return;
+    beta[i] = bt;
+    if (!ctt && !bpp) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const double *Bk = A + (size_t)e * B * B;
+        // Abar[P][P]: the P row at column P
+        double hpP = Bk[ip * B + ip];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) hpP = hpP - F[k][0] * Bk[group_index(k, ip, it, CPR) * B + ip];
+        if (bpp) bpp[e] = hpP;
+        if (ctt) {
+            if (CPR) {
+                ctt[e] = Bk[it * B + it];       // T is in the eliminated group: its row is unchanged
+            } else {
+                double hpT = Bk[ip * B + it], htT = Bk[it * B + it];
+#pragma unroll
+                for (int k = 0; k < NG; ++k) hpT = hpT - F[k][0] * Bk[group_index(k, ip, it, CPR) * B + it];
+#pragma unroll
+                for (int k = 0; k < NG; ++k) htT = htT - F[k][NR - 1] * Bk[group_index(k, ip, it, CPR) * B + it];
+                ctt[e] = (VAR == CPTR_VARIANT_CPTR3) ? htT - bt * hpT : htT;
+            }
+        }
+    }
+}
+
+// Phase 2, one wavefront per cell, lane = block entry (r, c) = (lane / b,
+// lane % b) of every block of the row, with the stored weights:
+//   Abar[P][c] = Ahat[P][c],  Abar[T][c] = Ahat[T][c] - beta Ahat[P][c] (CPTR3),
+// other rows copied; also the T and P column slabs and the FP32 copies.
+template <int B, int VAR>
+__global__ void __launch_bounds__(64) k_decouple_apply(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                       const double *__restrict__ A, int ip, int it,
+                                                       const double *__restrict__ wp, const double *__restrict__ wt,
+                                                       const double *__restrict__ beta, double *__restrict__ abar,
+                                                       double *__restrict__ slabT, double *__restrict__ slabP,
+                                                       float *__restrict__ abar32, float *__restrict__ slabT32,
+                                                       float *__restrict__ slabP32) {
+    constexpr bool CPR = (VAR == CPTR_VARIANT_CPR);
+    constexpr int NG = CPR ? B - 1 : B - 2;
+    constexpr int NR = CPR ? 1 : 2;
+    constexpr int NGX = NG > 0 ? NG : 1;
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (i >= n || lane >= B * B) return;
+    double F[NGX][NR];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        const int g = group_index(k, ip, it, CPR);
+        F[k][0] = wp[(size_t)i * B + g];
+        if (NR == 2) F[k][NR - 1] = wt[(size_t)i * B + g];
+    }
+    const double bt = beta[i];
     const int r = lane / B, c = lane % B;
     const bool rowP = (r == ip), rowT = (!CPR && r == it);
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
@@ -154,29 +200,48 @@ __global__ void __launch_bounds__(64) k_decouple(int n, const int *__restrict__ 
         if (c == it) {
             if (slabT) slabT[(size_t)e * B + r] = out;
             if (slabT32) slabT32[(size_t)e * B + r] = (float)out;
-            if (r == it && ctt) ctt[e] = out;
         }
         if (c == ip) {
             if (slabP) slabP[(size_t)e * B + r] = out;
             if (slabP32) slabP32[(size_t)e * B + r] = (float)out;
-            if (r == ip && bpp) bpp[e] = out;
         }
     }
 }
 
-void launch_decouple_extract(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
-                             int it, double *abar, double *wp, double *wt, double *beta, int *err, double *ctt,
-                             double *bpp, double *slabT, double *slabP, float *abar32, float *slabT32,
-                             float *slabP32, hipStream_t s) {
+void launch_decouple_weights(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
+                             int it, double *wp, double *wt, double *beta, int *err, double *ctt, double *bpp,
+                             hipStream_t s) {
+    if (n == 0) return;
+    const dim3 g((n + 127) / 128), t(128);
+#define CASE(BB)                                                                                                  \
+    case BB:                                                                                                      \
+        if (variant == CPTR_VARIANT_CPR)                                                                          \
+            hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPR>), g, t, 0, s, n, rp, ci, A, ip, it, wp,  \
+                               wt, beta, err, ctt, bpp);                                                          \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPTR3>), g, t, 0, s, n, rp, ci, A, ip, it, wp, \
+                               wt, beta, err, ctt, bpp);                                                          \
+        break;
+    switch (b) {
+        CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        default: throw Error(CPTR_E_ARG, "block size must be 2..8");
+    }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
+                           const double *wp, const double *wt, const double *beta, double *abar, double *slabT,
+                           double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s) {
     if (n == 0) return;
 #define CASE(BB)                                                                                                  \
     case BB:                                                                                                      \
         if (variant == CPTR_VARIANT_CPR)                                                                          \
-            hipLaunchKernelGGL((k_decouple<BB, CPTR_VARIANT_CPR>), dim3(n), dim3(64), 0, s, n, rp, ci, A, ip, it,  \
-                               abar, wp, wt, beta, err, ctt, bpp, slabT, slabP, abar32, slabT32, slabP32);       \
+            hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPR>), dim3(n), dim3(64), 0, s, n, rp, ci, A,    \
+                               ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);              \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_decouple<BB, CPTR_VARIANT_CPTR3>), dim3(n), dim3(64), 0, s, n, rp, ci, A, ip,    \
-                               it, abar, wp, wt, beta, err, ctt, bpp, slabT, slabP, abar32, slabT32, slabP32);   \
+            hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPTR3>), dim3(n), dim3(64), 0, s, n, rp, ci, A,  \
+                               ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);              \
         break;
     switch (b) {
         CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -188,8 +253,9 @@ void launch_decouple_extract(int variant, int n, int b, const int *rp, const int
 
 void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                      double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s) {
-    launch_decouple_extract(variant, n, b, rp, ci, A, ip, it, abar, wp, wt, beta, err, nullptr, nullptr, nullptr,
-                            nullptr, nullptr, nullptr, nullptr, s);
+    launch_decouple_weights(variant, n, b, rp, ci, A, ip, it, wp, wt, beta, err, nullptr, nullptr, s);
+    launch_decouple_apply(variant, n, b, rp, ci, A, ip, it, wp, wt, beta, abar, nullptr, nullptr, nullptr, nullptr,
+                          nullptr, s);
 }
 
 // bbar = N^{-1} b for one right-hand side, same order as the rows:
