@@ -1,6 +1,7 @@
 """GPU parity at the benchmark's full size: the 1000 x 500-cell, b = 8 system
 (4M unknowns) that bench.py times, in the same launch configuration
-(CPTR3, BILU(0) in 32 x 8 tiles, restart 50).
+(CPTR3, BILU(0) in 64 x 8 tiles, two Jacobi sweeps before and after,
+restart 50).
 
 The oracle handles this size in seconds for the setup arithmetic (C
 routines) and in about ten seconds for a whole FP64 solve, so the checks are
@@ -22,6 +23,8 @@ if not torch.cuda.is_available():
 from paper_1912_04385_amd import cptr  # noqa: E402
 
 NX, NY = 1000, 500
+TILE = (64, 8)
+SWEEPS = 2
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +37,7 @@ def c3():
 
 
 def _solver(s, **kw):
-    sv = cptr.Solver(restart=50, **kw)
+    sv = cptr.Solver(restart=50, ilu_tile_x=TILE[0], ilu_tile_y=TILE[1], pre_sweeps=SWEEPS, post_sweeps=SWEEPS, **kw)
     sv.setup(torch.from_numpy(s.row_ptr), torch.from_numpy(s.col_idx), torch.from_numpy(s.vals.reshape(-1)), 0, 1,
              NX, NY)
     return sv
@@ -66,7 +69,8 @@ def test_scaled_matrix_and_hierarchies_bitwise(c3):
 def test_plain_fp64_solve_matches_the_oracle(c3):
     s, A, dec = c3
     print("case full-size plain FP64 solve (oracle solve ~10 s)", flush=True)
-    ref = O.solve(s, O.Options(color=O.tile_colors(NX, NY), restart=50))
+    ref = O.solve(s, O.Options(color=O.tile_colors(NX, NY, *TILE), restart=50,
+                               amg=O.AMGOptions(pre=SWEEPS, post=SWEEPS)))
     sv = _solver(s)
     try:
         x, res = sv.solve(torch.from_numpy(s.rhs).cuda())
