@@ -218,11 +218,11 @@ static void csr_transpose(Builder *c, const CsrD &P, CsrD &R) {
 static void level_vectors(Level &L, int n, bool fp32) {
     L.x.alloc(n);
     L.b.alloc(n);
-    L.r.alloc(2 * (size_t)n);   // r and the ping-pong buffer of the smoother
+    L.r.alloc(3 * (size_t)n);   // r and the ping-pong buffers of the smoother
     if (fp32) {
         L.x32.alloc(n);
         L.b32.alloc(n);
-        L.r32.alloc(2 * (size_t)n);
+        L.r32.alloc(3 * (size_t)n);
     }
 }
 
@@ -481,43 +481,40 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     }
     const cptr_options &o = c->opt;
     const T omega = (T)((o.smoother == CPTR_SMOOTH_JACOBI) ? o.jacobi_omega : 1.0);
-    T *r = Prec<T>::r(L);
-    T *tmp = r + n;
     const T *v = Prec<T>::v(L.A);
     const T *dinv = Prec<T>::dinv(L);
+    // buffers: x (the level's result) and three spares of the same length
+    T *const X = x;
+    T *spare[3] = {Prec<T>::r(L), Prec<T>::r(L) + n, Prec<T>::r(L) + 2 * (size_t)n};
+    // pre-smoothing from zero; every further sweep fused with the next residual
+    T *xa = X, *ra = spare[0];
+    const T *rres = b;   // what is restricted
     if (o.pre_sweeps >= 1) {
-        vc_presmooth_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, r, s);
-        if (o.pre_sweeps > 1) {
-            for (int k = 1; k < o.pre_sweeps; ++k) {
-                vc_smooth<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, tmp, s);
-                CPTR_HIP(hipMemcpyAsync(x, tmp, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
-            }
-            vc_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, b, x, r, s);
+        vc_presmooth_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, xa, ra, s);
+        T *xb = spare[1], *rb = spare[2];
+        for (int k = 1; k < o.pre_sweeps; ++k) {
+            vc_sweep_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, xa, ra, xb, rb, s);
+            std::swap(xa, xb);
+            std::swap(ra, rb);
         }
+        rres = ra;
     } else {
-        CPTR_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, s));
-        CPTR_HIP(hipMemcpyAsync(r, b, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+        CPTR_HIP(hipMemsetAsync(xa, 0, sizeof(T) * n, s));
     }
     Level &Ln = h.L[lvl + 1];
-    vc_spmv<T>(L.R.n, L.R.nnz, L.R.rp, L.R.ci, Prec<T>::v(L.R), r, Prec<T>::b(Ln), s);
-    T *xc = vcycle<T>(c, h, lvl + 1, s);
-    if (o.post_sweeps == 0) {
-        vc_prolong_add<T>(n, L.P.nnz, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, s);
-    } else {
-        // prolong into the spare buffer so that an odd number of Jacobi sweeps
-        // ends in x without a copy
-        vc_prolong_to<T>(n, L.P.nnz, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, x, tmp, s);
-        std::swap(x, tmp);
-        for (int k = 0; k < o.post_sweeps; ++k) {
-            vc_smooth<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, tmp, s);
-            std::swap(x, tmp);
-        }
+    vc_spmv<T>(L.R.n, L.R.nnz, L.R.rp, L.R.ci, Prec<T>::v(L.R), rres, Prec<T>::b(Ln), s);
+    const T *xc = vcycle<T>(c, h, lvl + 1, s);
+    // prolongation, then post-smoothing ping-ponging so that the last write
+    // lands in X: the prolonged value goes to X for an even number of sweeps
+    T *Y = (xa == X) ? spare[0] : ((spare[0] != xa) ? spare[0] : spare[1]);
+    T *cur = (o.post_sweeps % 2 == 0) ? X : Y;
+    T *oth = (cur == X) ? Y : X;
+    vc_prolong_to<T>(n, L.P.nnz, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, xa, cur, s);
+    for (int k = 0; k < o.post_sweeps; ++k) {
+        vc_smooth<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, cur, oth, s);
+        std::swap(cur, oth);
     }
-    if (x != Prec<T>::x(L)) {
-        CPTR_HIP(hipMemcpyAsync(Prec<T>::x(L), x, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
-        x = Prec<T>::x(L);
-    }
-    return x;
+    return X;
 }
 
 // ---------------------------------------------------------------------------

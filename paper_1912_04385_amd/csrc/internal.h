@@ -189,6 +189,9 @@ void vc_presmooth_residual(int n, int nnz, const int *rp, const int *ci, const T
 template <class T>
 void vc_spmv(int n, int nnz, const int *rp, const int *ci, const T *v, const T *x, T *y, hipStream_t st);
 template <class T>
+void vc_sweep_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, T omega,
+                       const T *b, const T *x, const T *r, T *xout, T *rout, hipStream_t st);
+template <class T>
 void vc_prolong_add(int n, int nnz, const int *rp, const int *ci, const T *v, const T *xc, T *x, hipStream_t st);
 template <class T>
 void vc_prolong_to(int n, int nnz, const int *rp, const int *ci, const T *v, const T *xc, const T *xin, T *xout,

@@ -19,7 +19,10 @@ enum CsrOp {
     OP_RESIDUAL,      // r_i = b_i - acc_i                              (x = xin)
     OP_SMOOTH,        // x_i = xin_i + omega dinv_i (b_i - acc_i)       (x = xin)
     OP_PRESMOOTH,     // x_i = omega dinv_i b_i, r_i = b_i - acc_i      (x_j = omega dinv_j b_j)
-    OP_PROLONG        // x_i = xin_i + acc_i                            (x = coarse vector)
+    OP_PROLONG,       // x_i = xin_i + acc_i                            (x = coarse vector)
+    OP_SWEEP_RESID    // x_i = xin_i + omega dinv_i rin_i, r_i = b_i - acc_i
+                      //   (x_j = xin_j + omega dinv_j rin_j: the next Jacobi
+                      //   sweep from the previous one's residual rin = xs)
 };
 
 template <class T, int G, int OP>
@@ -37,6 +40,8 @@ __global__ void __launch_bounds__(256) k_csr_op(int n, const int *__restrict__ r
             const int j = ci[e];
             if constexpr (OP == OP_PRESMOOTH)
                 acc += v[e] * (omega * dinv[j] * b[j]);
+            else if constexpr (OP == OP_SWEEP_RESID)
+                acc += v[e] * (xin[j] + omega * dinv[j] * xs[j]);
             else
                 acc += v[e] * xs[j];
         }
@@ -56,6 +61,9 @@ __global__ void __launch_bounds__(256) k_csr_op(int n, const int *__restrict__ r
         const T bi = b[i];
         xout[i] = omega * dinv[i] * bi;
         rout[i] = bi - acc;
+    } else if constexpr (OP == OP_SWEEP_RESID) {
+        xout[i] = xin[i] + omega * dinv[i] * xs[i];
+        rout[i] = b[i] - acc;
     } else {
         xout[i] = xin[i] + acc;
     }
@@ -94,6 +102,15 @@ template <class T>
 void vc_presmooth_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, T omega,
                            const T *b, T *x, T *r, hipStream_t st) {
     csr_op<T, OP_PRESMOOTH>(n, nnz, rp, ci, v, nullptr, dinv, omega, b, nullptr, x, r, st);
+}
+
+// a further Jacobi sweep from x (with its residual r) fused with the new
+// residual: xout = x + omega dinv r, rout = b - A xout (xout, rout distinct
+// from x, r)
+template <class T>
+void vc_sweep_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, T omega,
+                       const T *b, const T *x, const T *r, T *xout, T *rout, hipStream_t st) {
+    csr_op<T, OP_SWEEP_RESID>(n, nnz, rp, ci, v, r, dinv, omega, b, x, xout, rout, st);
 }
 
 // y = A x
@@ -246,6 +263,8 @@ void vc_sub(int n, const double *x, double *e, hipStream_t st) {
     template void vc_presmooth_residual<T>(int, int, const int *, const int *, const T *, const T *, T, const T *, \
                                            T *, T *, hipStream_t);                                               \
     template void vc_spmv<T>(int, int, const int *, const int *, const T *, const T *, T *, hipStream_t);        \
+    template void vc_sweep_residual<T>(int, int, const int *, const int *, const T *, const T *, T, const T *,   \
+                                       const T *, const T *, T *, T *, hipStream_t);                            \
     template void vc_prolong_add<T>(int, int, const int *, const int *, const T *, const T *, T *, hipStream_t); \
     template void vc_prolong_to<T>(int, int, const int *, const int *, const T *, const T *, const T *, T *,     \
                                    hipStream_t);                                                                 \
