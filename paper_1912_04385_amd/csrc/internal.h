@@ -245,6 +245,8 @@ struct TileSched {
     int ntiles[2] = {0, 0};
     DBuf<int> tiles[2];     // tile ids per colour
     DBuf<int> color;        // per cell
+    int nrim[2] = {0, 0};
+    DBuf<int> rim[2];       // cells on the perimeter of a tile, per colour
 };
 void tiles_build(TileSched &ts, int n, int nx, int ny, int tx, int ty, const int *rp, const int *ci, int *flag,
                  hipStream_t st);

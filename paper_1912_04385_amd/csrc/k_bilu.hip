@@ -290,19 +290,21 @@ __global__ void k_stage_residual(int n, int b, const int *__restrict__ rp, const
 }
 
 // Couplings between tiles of different colours, fully parallel (one thread
-// per scalar row), in place on u:
+// per scalar row of the cells on the perimeter of a tile of the target
+// colour -- only they have neighbours in other tiles), in place on u:
 //   mode 0 (before the black sweep): black rows  u_i -= sum_{red j} Abar_ij t_j
 //   mode 1 (before the red backward sweep): red rows  u_i = sum_{black j} Abar_ij w_j
+// (the backward sweep takes 0 for the red cells inside a tile)
 template <class T>
-__global__ void k_cross_tile(int n, int b, int mode, const int *__restrict__ color, const int *__restrict__ rp,
-                             const int *__restrict__ ci, const T *__restrict__ abar, const T *__restrict__ tw,
-                             T *__restrict__ u) {
+__global__ void k_cross_tile(int nlist, int b, int mode, const int *__restrict__ cells,
+                             const int *__restrict__ color, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const T *__restrict__ abar, const T *__restrict__ tw, T *__restrict__ u) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)n * b) return;
-    const int i = (int)(t / b), r = (int)(t % b);
+    if (t >= (long)nlist * b) return;
+    const int i = cells[t / b], r = (int)(t % b);
     const int ci_ = color[i];
-    if ((mode == 0 && ci_ == 0) || (mode == 1 && ci_ != 0)) return;
-    T acc = (mode == 0) ? u[t] : (T)0;
+    const size_t ti = (size_t)i * b + r;
+    T acc = (mode == 0) ? u[ti] : (T)0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const int j = ci[e];
         if (j == i || color[j] == ci_) continue;
@@ -312,7 +314,7 @@ __global__ void k_cross_tile(int n, int b, int mode, const int *__restrict__ col
         for (int m = 0; m < b; ++m) d += Aij[m] * vj[m];
         if (mode == 0) acc -= d; else acc += d;
     }
-    u[t] = acc;
+    u[ti] = acc;
 }
 
 // In-tile neighbour blocks of every cell, gathered once per setup so that the
@@ -469,7 +471,8 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
                 int lx = 0, ly = 0, i = 0;
                 const bool own = cell_of(lev, lx, ly, i);
                 const int loc = lx + tw_ * ly;
-                T q = (mode == 2) ? ring[k].s : (T)0;
+                const bool rim = (lx == 0 || ly == 0 || lx == tw_ - 1 || ly == th - 1);
+                T q = (mode == 2 && rim) ? ring[k].s : (T)0;
                 T tval = 0;
                 if (own) {
                     tval = (mode == 2) ? ring[k].tv : W[loc * B + r];
@@ -525,10 +528,17 @@ static void bilu_apply_wave(const TileSched &ts, int n, int b, const int *rp, co
     if (ts.ntiles[1] == 0) {
         launch(0, 1);
     } else {
+        auto cross = [&](int mode) {
+            const int color = (mode == 0) ? 1 : 0;
+            const long nr_ = (long)ts.nrim[color] * b;
+            if (nr_ == 0) return;
+            hipLaunchKernelGGL(k_cross_tile<T>, dim3((unsigned)((nr_ + 255) / 256)), dim3(256), 0, st,
+                               ts.nrim[color], b, mode, ts.rim[color].p, ts.color.p, rp, ci, abar, tw, u);
+        };
         launch(0, 0);
-        hipLaunchKernelGGL(k_cross_tile<T>, dim3(gr), dim3(256), 0, st, n, b, 0, ts.color.p, rp, ci, abar, tw, u);
+        cross(0);
         launch(1, 1);
-        hipLaunchKernelGGL(k_cross_tile<T>, dim3(gr), dim3(256), 0, st, n, b, 1, ts.color.p, rp, ci, abar, tw, u);
+        cross(1);
         launch(0, 2);
     }
     CPTR_CHECK_LAUNCH();
@@ -665,12 +675,27 @@ void tiles_build(TileSched &ts, int n, int nx, int ny, int tx, int ty, const int
     ts.nty = (ny + ty - 1) / ty;
     std::vector<int> lists[2];
     for (int t = 0; t < ts.ntx * ts.nty; ++t) lists[((t % ts.ntx) + (t / ts.ntx)) & 1].push_back(t);
+    // cells on the perimeter of their tile, per colour
+    std::vector<int> rims[2];
+    for (int c = 0; c < 2; ++c)
+        for (int t : lists[c]) {
+            const int x0 = (t % ts.ntx) * tx, y0 = (t / ts.ntx) * ty;
+            const int w = std::min(tx, nx - x0), h = std::min(ty, ny - y0);
+            for (int ly = 0; ly < h; ++ly)
+                for (int lx = 0; lx < w; ++lx)
+                    if (lx == 0 || ly == 0 || lx == w - 1 || ly == h - 1) rims[c].push_back(x0 + lx + nx * (y0 + ly));
+        }
     for (int c = 0; c < 2; ++c) {
         ts.ntiles[c] = (int)lists[c].size();
         ts.tiles[c].alloc(lists[c].size() + 1);
         if (!lists[c].empty())
             CPTR_HIP(hipMemcpyAsync(ts.tiles[c].p, lists[c].data(), sizeof(int) * lists[c].size(),
                                     hipMemcpyHostToDevice, st));
+        ts.nrim[c] = (int)rims[c].size();
+        ts.rim[c].alloc(rims[c].size() + 1);
+        if (!rims[c].empty())
+            CPTR_HIP(hipMemcpyAsync(ts.rim[c].p, rims[c].data(), sizeof(int) * rims[c].size(), hipMemcpyHostToDevice,
+                                    st));
     }
     ts.color.alloc(n);
     hipLaunchKernelGGL(k_tile_colors, dim3((n + 255) / 256), dim3(256), 0, st, nx, ny, tx, ty, ts.color.p);
