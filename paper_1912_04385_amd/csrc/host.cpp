@@ -10,8 +10,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <exception>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <string>
 #include <type_traits>
@@ -136,11 +138,46 @@ struct cptr_ctx {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// Reads of device scalars go through small pinned host buffers: a copy into
+// pinned memory is one direct transfer, where pageable memory takes a staged
+// copy.  The buffers are kept for reuse until the process ends.
+static std::mutex g_pin_mu;
+static std::vector<void *> g_pin_free;
+constexpr size_t PIN_BYTES = 64;
+
+static void *pin_acquire() {
+    {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        if (!g_pin_free.empty()) {
+            void *p = g_pin_free.back();
+            g_pin_free.pop_back();
+            return p;
+        }
+    }
+    void *p = nullptr;
+    CPTR_HIP(hipHostMalloc(&p, PIN_BYTES, hipHostMallocDefault));
+    return p;
+}
+
+static void pin_release(void *p) {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.push_back(p);
+}
+
+// copy `bytes` (<= PIN_BYTES) from device memory to host after the stream's work
+static void read_bytes(void *dst, const void *d, size_t bytes, hipStream_t s) {
+    void *h = pin_acquire();
+    hipError_t e = hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) std::memcpy(dst, h, bytes);
+    pin_release(h);
+    CPTR_HIP(e);
+}
+
 template <class T>
 static T read_scalar(const T *d, hipStream_t s) {
     T v;
-    CPTR_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, s));
-    CPTR_HIP(hipStreamSynchronize(s));
+    read_bytes(&v, d, sizeof(T), s);
     return v;
 }
 
@@ -174,8 +211,7 @@ static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
     amg_spgemm_bound(m, A.rp, A.ci, B.rp, c->s_i1.p, c->s_i2.p + m + 1, s);
     scan_exclusive(c->s_i1.p, c->s_i2.p, m, nullptr, s);
     int tm[2];
-    CPTR_HIP(hipMemcpyAsync(tm, c->s_i2.p + m, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    CPTR_HIP(hipStreamSynchronize(s));
+    read_bytes(tm, c->s_i2.p + m, 2 * sizeof(int), s);
     const int cap = tm[0], maxprod = tm[1];
     DBuf<int> hk;
     DBuf<double> hv;
