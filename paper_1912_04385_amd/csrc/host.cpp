@@ -353,7 +353,10 @@ static void apply_learned(hipStream_t s, Level &L, const float *mlp) {
     CPTR_HIP(hipStreamSynchronize(s));
 }
 
-static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const float *mlp = nullptr) {
+// `own` (optional): the buffer holding vals, taken over as the fine level's
+// values instead of copying them
+static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const float *mlp = nullptr,
+                            DBuf<double> *own = nullptr) {
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     const bool fp32 = (o.precond_precision == CPTR_FP32);
@@ -366,8 +369,12 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         L0.A.nnz = c->nnzb;
         L0.A.rp = c->rp.p;
         L0.A.ci = c->ci.p;
-        L0.A.v.alloc(c->nnzb);
-        CPTR_HIP(hipMemcpyAsync(L0.A.v.p, vals, sizeof(double) * c->nnzb, hipMemcpyDeviceToDevice, s));
+        if (own && own->p == vals && own->n >= (size_t)c->nnzb) {
+            L0.A.v = std::move(*own);
+        } else {
+            L0.A.v.alloc(c->nnzb);
+            CPTR_HIP(hipMemcpyAsync(L0.A.v.p, vals, sizeof(double) * c->nnzb, hipMemcpyDeviceToDevice, s));
+        }
     }
     while (true) {
         Level &L = h.L.back();
@@ -461,12 +468,15 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
 // every level are kept; the Galerkin products A_{l+1} = R_l A_l P_l, the
 // smoother diagonals and the coarsest inverse are recomputed from the new
 // values with the same kernels as a full setup.
-static void refresh_hierarchy(Builder *c, Hierarchy &h, const double *vals) {
+static void refresh_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<double> *own) {
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     if (!h.built || h.L.empty()) throw Error(CPTR_E_STATE, "no hierarchy to reuse");
     Level &L0 = h.L[0];
-    CPTR_HIP(hipMemcpyAsync(L0.A.v.p, vals, sizeof(double) * c->nnzb, hipMemcpyDeviceToDevice, s));
+    if (own && own->p == vals && own->n >= (size_t)c->nnzb)
+        L0.A.v = std::move(*own);
+    else
+        CPTR_HIP(hipMemcpyAsync(L0.A.v.p, vals, sizeof(double) * c->nnzb, hipMemcpyDeviceToDevice, s));
     for (size_t l = 0; l < h.L.size(); ++l) {
         Level &L = h.L[l];
         const int m = L.A.n;
@@ -671,14 +681,14 @@ static void validate_options(const cptr_options &o) {
 // interpolation requested, the classical and the learned hierarchies are both
 // built and the learned one is kept only if its measured V-cycle convergence
 // factor is lower (CPTR_INTERP_LEARNED_FORCED keeps it without the judge).
-static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals) {
+static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<double> *own) {
     const bool learned = (k == 0) && c->have_mlp && c->opt.t_interp != CPTR_INTERP_CLASSICAL;
     if (k == 0) {
         c->used_learned = 0;
         c->rho_cls = c->rho_lrn = -1.0;
     }
     if (!learned) {
-        build_hierarchy(&B, c->H[k], vals);
+        build_hierarchy(&B, c->H[k], vals, nullptr, own);
         return;
     }
     // the learned hierarchy (and its convergence factor) on its own stream
@@ -713,6 +723,8 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals) {
     std::exception_ptr err1;
     double rc = -1.0;
     try {
+        // the values are copied here: the losing hierarchy is released while
+        // the other stream may still read them
         build_hierarchy(&B, c->H[k], vals);
         if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
     } catch (...) {
@@ -812,11 +824,13 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                     fill_int(B.flag.p, 0, 1, B.stream);
                 }
                 CPTR_HIP(hipStreamWaitEvent(B.stream, c->ev_dec, 0));
+                // the fine level takes over the buffer of its values
+                DBuf<double> *own = k == 0 ? &c->ctt : &c->bpp;
                 if (refresh[k]) {
                     // reuse decision: keep the refreshed hierarchy while its
                     // measured V-cycle convergence factor stays below the
                     // threshold, else build it anew
-                    refresh_hierarchy(&B, c->H[k], svals[k]);
+                    refresh_hierarchy(&B, c->H[k], svals[k], own);
                     c->rho[k] = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
                     if (c->rho[k] < c->opt.reuse_rho_max) {
                         kept.fetch_or(1 << k);
@@ -824,10 +838,12 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                     } else {
                         c->skip_left[k] = c->backoff[k];
                         c->backoff[k] = std::min(2 * c->backoff[k], MAX_REUSE_BACKOFF);
-                        full_build(c, B, k, svals[k]);
+                        // hand the values back before the old hierarchy goes
+                        *own = std::move(c->H[k].L[0].A.v);
+                        full_build(c, B, k, svals[k], own);
                     }
                 } else {
-                    full_build(c, B, k, svals[k]);
+                    full_build(c, B, k, svals[k], own);
                 }
                 CPTR_HIP(hipEventRecord(c->ev_side[k], B.stream));
                 c->tph[1 + k] = ms_since(t_hier);
