@@ -877,16 +877,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     } else {
         bj_factor_cells(n, b, c->rp.p, c->ci.p, c->abar.p, c->dinv.p, c->s_i4.p, nullptr, s);
     }
-    bad = read_scalar(c->s_i4.p, s);
-    for (int k = 0; k < 2; ++k)
-        if (th[k].joinable()) th[k].join();
-    for (int k = 0; k < 2; ++k)
-        if (err[k]) std::rethrow_exception(err[k]);
-    c->reused = kept.load();
-    for (int k = 0; k < 2; ++k)
-        if (need[k]) CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[k], 0));
-    if (bad != 0x7fffffff)
-        throw Error(CPTR_E_SINGULAR_BLOCK, "singular ILU pivot block in cell " + std::to_string(bad));
+    // the sweeps' side arrays, also while the hierarchies are still being built
     if (c->use_tiles && bilu_wave_ok(c->ts, b)) {
         if (fp32) {
             c->tb32.alloc((size_t)n * 4 * b * b);
@@ -903,6 +894,16 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     } else {
         c->tw.alloc(2 * (size_t)n * b);
     }
+    bad = read_scalar(c->s_i4.p, s);
+    for (int k = 0; k < 2; ++k)
+        if (th[k].joinable()) th[k].join();
+    for (int k = 0; k < 2; ++k)
+        if (err[k]) std::rethrow_exception(err[k]);
+    c->reused = kept.load();
+    for (int k = 0; k < 2; ++k)
+        if (need[k]) CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[k], 0));
+    if (bad != 0x7fffffff)
+        throw Error(CPTR_E_SINGULAR_BLOCK, "singular ILU pivot block in cell " + std::to_string(bad));
     CPTR_HIP(hipStreamSynchronize(s));
     c->tph[3] = ms_since(t_start);
 }

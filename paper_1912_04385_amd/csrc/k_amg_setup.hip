@@ -206,15 +206,20 @@ __device__ inline double csr_value(const int *rp, const int *ci, const double *v
     return 0.0;
 }
 
-__device__ inline bool in_sorted(const int *a, int stride, int len, int key) {
+// position of key in a sorted strided array, -1 if absent
+__device__ inline int find_sorted(const int *a, int stride, int len, int key) {
     int lo = 0, hi = len - 1;
     while (lo <= hi) {
         int mid = (lo + hi) >> 1;
         int c = a[mid * stride];
-        if (c == key) return true;
+        if (c == key) return mid;
         if (c < key) lo = mid + 1; else hi = mid - 1;
     }
-    return false;
+    return -1;
+}
+
+__device__ inline bool in_sorted(const int *a, int stride, int len, int key) {
+    return find_sorted(a, stride, len, key) >= 0;
 }
 
 // One thread per row.  Writes the row of P (coarse columns, weights) into the
@@ -289,20 +294,29 @@ __device__ inline void exti_row(int i, const int *__restrict__ rp, const int *__
         }
     }
     if (at == 0.0) { cnt[i] = 0; return; }
-    for (int p = 0; p < nh; ++p) {
-        const int j = hat[p * hs];
-        double num = csr_value(rp, ci, v, i, j);
-        for (int e = a; e < b; ++e) {
-            int k = ci[e];
-            if (k == i || !s[e] || cf[k] == ST_C) continue;
-            double d = td[e];
-            if (d == 0.0) continue;
-            double ab = abar_of(dg[k], csr_value(rp, ci, v, k, j));
-            if (ab == 0.0) continue;
-            num = num + (v[e] * ab) / d;
-        }
-        w[p] = -num / at;
+    // numerators, accumulated in w: a_ij first, then the strong F neighbours'
+    // terms in row order (each row k scattered to the positions of its
+    // interpolatory columns, so every num_j sees its terms in that order)
+    for (int p = 0; p < nh; ++p) w[p] = 0.0;
+    for (int e = a; e < b; ++e) {
+        const int pos = find_sorted(hat, hs, nh, ci[e]);
+        if (pos >= 0) w[pos] = v[e];
     }
+    for (int e = a; e < b; ++e) {
+        const int k = ci[e];
+        if (k == i || !s[e] || cf[k] == ST_C) continue;
+        const double d = td[e];
+        if (d == 0.0) continue;
+        const double akk = dg[k], aik = v[e];
+        for (int f = rp[k]; f < rp[k + 1]; ++f) {
+            const int pos = find_sorted(hat, hs, nh, ci[f]);
+            if (pos < 0) continue;
+            const double ab = abar_of(akk, v[f]);
+            if (ab == 0.0) continue;
+            w[pos] = w[pos] + (aik * ab) / d;
+        }
+    }
+    for (int p = 0; p < nh; ++p) w[p] = -w[p] / at;
     int keep = nh;
     if (pmax > 0 && nh > pmax) {
         // mark kept entries by encoding the column as -1 - col
@@ -515,22 +529,35 @@ __global__ void __launch_bounds__(64) k_exti_wave(int n, const int *__restrict__
         if (lane == 0) cnt[i] = 0;
         return;
     }
-    // 5. weights: one lane per interpolatory point
+    // 5. weights.  The numerators accumulate in w: a_ij first, then the
+    // strong F neighbours in row order, the lanes splitting each row k (its
+    // columns are distinct, so no two lanes meet on one numerator)
     for (int p = lane; p < nh; p += 64) {
-        const int j = hat[p];
-        double num = csr_value(rp, ci, v, i, j);
-        for (int e = a; e < b; ++e) {
-            const int k = ci[e];
-            if (k == i || !s[e] || cf[k] == ST_C) continue;
-            const double d = dk[e - a];
-            if (d == 0.0) continue;
-            const double ab = abar_of(dg[k], csr_value(rp, ci, v, k, j));
-            if (ab == 0.0) continue;
-            num = num + (v[e] * ab) / d;
-        }
-        w[p] = -num / at;
+        w[p] = 0.0;
         kept[p] = 0;
     }
+    __syncthreads();
+    for (int e = a + lane; e < b; e += 64) {
+        const int pos = find_sorted(hat, 1, nh, ci[e]);
+        if (pos >= 0) w[pos] = v[e];
+    }
+    __syncthreads();
+    for (int e = a; e < b; ++e) {
+        const int k = ci[e];
+        if (k == i || !s[e] || cf[k] == ST_C) continue;
+        const double d = dk[e - a];
+        if (d == 0.0) continue;
+        const double akk = dg[k], aik = v[e];
+        for (int f = rp[k] + lane; f < rp[k + 1]; f += 64) {
+            const int pos = find_sorted(hat, 1, nh, ci[f]);
+            if (pos < 0) continue;
+            const double ab = abar_of(akk, v[f]);
+            if (ab == 0.0) continue;
+            w[pos] = w[pos] + (aik * ab) / d;
+        }
+        __syncthreads();
+    }
+    for (int p = lane; p < nh; p += 64) w[p] = -w[p] / at;
     __syncthreads();
     int keep = nh;
     if (pmax > 0 && nh > pmax) {

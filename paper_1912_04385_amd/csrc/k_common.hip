@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_blocksum(const int *in, i
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_offsets(int *bsum, int nb, int *out_total) {
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_offsets(int *bsum, int nb, int *out_total, int *out_total2) {
     __shared__ int lds[33];
     int carry = 0;
     for (int base = 0; base < nb; base += SCAN_THREADS) {
@@ -139,7 +139,39 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_offsets(int *bsum, int nb
         if (i < nb) bsum[i] = e + carry;
         carry += tot;
     }
-    if (threadIdx.x == 0) *out_total = carry;
+    if (threadIdx.x == 0) {
+        *out_total = carry;
+        if (out_total2) *out_total2 = carry;
+    }
+}
+
+// the whole scan in one block, tile after tile (short inputs)
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_single(const int *in, int n, int *out, int *out_total,
+                                                              int *out_total2) {
+    __shared__ int lds[33];
+    int carry = 0;
+    for (long t0 = 0; t0 < n; t0 += SCAN_TILE) {
+        const long base = t0 + threadIdx.x * SCAN_ITEMS;
+        int v[SCAN_ITEMS];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            v[k] = (base + k < n) ? in[base + k] : 0;
+            sum += v[k];
+        }
+        int tot;
+        int e = block_scan_excl(sum, lds, &tot) + carry;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            if (base + k < n) out[base + k] = e;
+            e += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        *out_total = carry;
+        if (out_total2) *out_total2 = carry;
+    }
 }
 
 __global__ void __launch_bounds__(SCAN_THREADS) k_scan_final(const int *in, int n, const int *boff, int *out) {
@@ -161,18 +193,25 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_final(const int *in, int 
 }
 
 // the block sums live in a pooled buffer of the calling stream
+// up to this many tiles the scan runs as a single block
+constexpr int SCAN_SINGLE_TILES = 16;
+
 void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t s) {
     int nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb < 1) nb = 1;
+    int *tot = total_dev ? total_dev : out + n;
+    int *tot2 = (total_dev && total_dev != out + n) ? out + n : nullptr;
+    if (nb <= SCAN_SINGLE_TILES) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, out, tot, tot2);
+        CPTR_CHECK_LAUNCH();
+        return;
+    }
     DBuf<int> scratch;
     scratch.alloc((size_t)nb + 1);
     int *bsum = scratch.p;
     hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, bsum);
-    int *tot = total_dev ? total_dev : out + n;
-    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(SCAN_THREADS), 0, s, bsum, nb, tot);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(SCAN_THREADS), 0, s, bsum, nb, tot, tot2);
     hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, bsum, out);
-    if (total_dev && total_dev != out + n)
-        CPTR_HIP(hipMemcpyAsync(out + n, total_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
     CPTR_CHECK_LAUNCH();
 }
 
