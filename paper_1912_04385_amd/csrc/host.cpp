@@ -246,7 +246,7 @@ static void csr_transpose(Builder *c, const CsrD &P, CsrD &R) {
     R.ci_own.alloc((size_t)R.nnz);
     R.v.alloc((size_t)R.nnz);
     c->s_i4.alloc((size_t)R.n + 1);
-    amg_transpose(P.n, P.ncols, P.rp, P.ci, P.v.p, R.rp_own.p, R.ci_own.p, R.v.p, c->s_i4.p, s);
+    amg_transpose(P.n, P.ncols, P.nnz, P.rp, P.ci, P.v.p, R.rp_own.p, R.ci_own.p, R.v.p, c->s_i4.p, s);
     R.rp = R.rp_own.p;
     R.ci = R.ci_own.p;
 }

@@ -167,8 +167,8 @@ void amg_exti_compute_wave(int n, const int *rp, const int *ci, const double *v,
                            double *tw, double *td, int *cnt, hipStream_t st);
 void amg_compact(int n, const int *off, const int *tcol, const double *tw, const int *prp, int *pci, double *pv,
                  hipStream_t st);
-void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v, int *rpT, int *ciT, double *vT,
-                   int *work, hipStream_t st);
+void amg_transpose(int nr, int nc, int nnz, const int *rp, const int *ci, const double *v, int *rpT, int *ciT,
+                   double *vT, int *work, hipStream_t st);
 // maxprod (device, may be NULL) receives the largest product count of a row
 void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, int *maxprod, hipStream_t st);
 void amg_spgemm_compute_sort(int m, int maxprod, const int *arp, const int *aci, const double *av, const int *brp,

@@ -635,7 +635,9 @@ void amg_compact(int n, const int *off, const int *tcol, const double *tw, const
 }
 
 // --------------------------------------------------------------------------
-// transpose (R = P^T): count, scan, scatter, then sort each row by column
+// transpose (R = P^T): count, scan, scatter (in arbitrary order, with the
+// target row of every entry), then every entry moves to its rank in its row
+// (the columns of a row are distinct, so the ranks are a permutation)
 // --------------------------------------------------------------------------
 __global__ void k_tr_count(int nr, const int *__restrict__ rp, const int *__restrict__ ci, int *__restrict__ cnt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -644,96 +646,74 @@ __global__ void k_tr_count(int nr, const int *__restrict__ rp, const int *__rest
 }
 
 __global__ void k_tr_scatter(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
-                             const double *__restrict__ v, int *__restrict__ cursor, int *__restrict__ ciT,
-                             double *__restrict__ vT) {
+                             const double *__restrict__ v, int *__restrict__ cursor, int *__restrict__ tci,
+                             double *__restrict__ tv, int *__restrict__ trow) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nr) return;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        int p = atomicAdd(&cursor[ci[e]], 1);
-        ciT[p] = i;
-        vT[p] = v[e];
+        const int c = ci[e];
+        const int p = atomicAdd(&cursor[c], 1);
+        tci[p] = i;
+        tv[p] = v[e];
+        trow[p] = c;
     }
 }
 
-// rows of up to SR_SHORT entries: one thread per row, insertion sort in
-// registers; longer rows: one wavefront per row, bitonic sort in LDS (rows
-// beyond SR_LONG: lane 0 in place)
-constexpr int SR_SHORT = 32;
-constexpr int SR_LONG = 1024;
+// rows longer than this are copied as they are and sorted by k_sort_rows_huge
+constexpr int TR_RANK_MAX = 1024;
 
-__global__ void k_sort_rows(int n, const int *__restrict__ rp, int *__restrict__ ci, double *__restrict__ v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a = rp[i], len = rp[i + 1] - a;
-    if (len > SR_SHORT || len < 2) return;
-    int c[SR_SHORT];
-    double x[SR_SHORT];
-    for (int p = 0; p < len; ++p) { c[p] = ci[a + p]; x[p] = v[a + p]; }
-    for (int p = 1; p < len; ++p) {
-        const int cc = c[p];
-        const double xx = x[p];
-        int q = p - 1;
-        while (q >= 0 && c[q] > cc) { c[q + 1] = c[q]; x[q + 1] = x[q]; --q; }
-        c[q + 1] = cc;
-        x[q + 1] = xx;
-    }
-    for (int p = 0; p < len; ++p) { ci[a + p] = c[p]; v[a + p] = x[p]; }
-}
-
-__global__ void __launch_bounds__(64) k_sort_rows_long(int n, const int *__restrict__ rp, int *__restrict__ ci,
-                                                       double *__restrict__ v) {
-    __shared__ unsigned long long key[SR_LONG];
-    __shared__ double val[SR_LONG];
-    const int i = blockIdx.x, lane = threadIdx.x;
-    if (i >= n) return;
-    const int a = rp[i], len = rp[i + 1] - a;
-    if (len <= SR_SHORT) return;
-    if (len > SR_LONG) {
-        if (lane == 0)
-            for (int p = a + 1; p < a + len; ++p) {
-                const int cc = ci[p];
-                const double xx = v[p];
-                int q = p - 1;
-                while (q >= a && ci[q] > cc) { ci[q + 1] = ci[q]; v[q + 1] = v[q]; --q; }
-                ci[q + 1] = cc;
-                v[q + 1] = xx;
-            }
+__global__ void k_tr_rank(int nnz, const int *__restrict__ rpT, const int *__restrict__ trow,
+                          const int *__restrict__ tci, const double *__restrict__ tv, int *__restrict__ ciT,
+                          double *__restrict__ vT) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnz) return;
+    const int c = trow[t];
+    const int a = rpT[c], len = rpT[c + 1] - a;
+    const int key = tci[t];
+    if (len > TR_RANK_MAX) {
+        ciT[t] = key;
+        vT[t] = tv[t];
         return;
     }
-    int S = 1;
-    while (S < len) S <<= 1;
-    for (int p = lane; p < S; p += 64) {
-        key[p] = p < len ? (((unsigned long long)(unsigned)ci[a + p] << 32) | (unsigned)p) : ~0ull;
-        if (p < len) val[p] = v[a + p];
-    }
-    __syncthreads();
-    for (int k = 2; k <= S; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = lane; t < S; t += 64) {
-                const int q = t ^ j;
-                if (q > t) {
-                    const unsigned long long x = key[t], y = key[q];
-                    if ((x > y) == ((t & k) == 0)) { key[t] = y; key[q] = x; }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int p = lane; p < len; p += 64) {
-        ci[a + p] = (int)(key[p] >> 32);
-        v[a + p] = val[(unsigned)key[p]];
+    int rank = 0;
+    for (int q = a; q < a + len; ++q) rank += (tci[q] < key) ? 1 : 0;
+    ciT[a + rank] = key;
+    vT[a + rank] = tv[t];
+}
+
+// one thread per row: insertion sort in place of the rows beyond TR_RANK_MAX
+__global__ void k_sort_rows_huge(int n, const int *__restrict__ rp, int *__restrict__ ci, double *__restrict__ v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = rp[i], len = rp[i + 1] - a;
+    if (len <= TR_RANK_MAX) return;
+    for (int p = a + 1; p < a + len; ++p) {
+        const int cc = ci[p];
+        const double xx = v[p];
+        int q = p - 1;
+        while (q >= a && ci[q] > cc) { ci[q + 1] = ci[q]; v[q + 1] = v[q]; --q; }
+        ci[q + 1] = cc;
+        v[q + 1] = xx;
     }
 }
 
-void amg_transpose(int nr, int nc, const int *rp, const int *ci, const double *v, int *rpT, int *ciT, double *vT,
-                   int *work, hipStream_t st) {
+void amg_transpose(int nr, int nc, int nnz, const int *rp, const int *ci, const double *v, int *rpT, int *ciT,
+                   double *vT, int *work, hipStream_t st) {
     fill_int(work, 0, (size_t)nc + 1, st);
     hipLaunchKernelGGL(k_tr_count, dim3(blocks_for(nr, 256)), dim3(256), 0, st, nr, rp, ci, work);
     scan_exclusive(work, rpT, nc, nullptr, st);
+    if (nnz == 0) return;
     CPTR_HIP(hipMemcpyAsync(work, rpT, sizeof(int) * nc, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_tr_scatter, dim3(blocks_for(nr, 256)), dim3(256), 0, st, nr, rp, ci, v, work, ciT, vT);
-    hipLaunchKernelGGL(k_sort_rows, dim3(blocks_for(nc, 128)), dim3(128), 0, st, nc, rpT, ciT, vT);
-    hipLaunchKernelGGL(k_sort_rows_long, dim3(nc), dim3(64), 0, st, nc, rpT, ciT, vT);
+    DBuf<int> tci, trow;
+    DBuf<double> tv;
+    tci.alloc(nnz);
+    trow.alloc(nnz);
+    tv.alloc(nnz);
+    hipLaunchKernelGGL(k_tr_scatter, dim3(blocks_for(nr, 256)), dim3(256), 0, st, nr, rp, ci, v, work, tci.p, tv.p,
+                       trow.p);
+    hipLaunchKernelGGL(k_tr_rank, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, nnz, rpT, trow.p, tci.p, tv.p, ciT,
+                       vT);
+    hipLaunchKernelGGL(k_sort_rows_huge, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, rpT, ciT, vT);
     CPTR_CHECK_LAUNCH();
 }
 
@@ -987,8 +967,10 @@ __global__ void k_dense_aug(int n, const int *__restrict__ rp, const int *__rest
 }
 
 // Gauss-Jordan elimination with partial pivoting, without row normalisation,
-// in panels of GJ_NB columns.  Column k: the pivot p_k is the first unused row
-// with the largest |aug[r][k]|; every row r != p_k gets
+// in panels of GJ_NB columns.  Column k: the pivot p_k is an unused row with
+// the largest |aug[r][k]| (the first such row in k_gj_panel; up to 2^-11
+// relative in k_gj_panel_lds, which serves coarse levels of at most 1024
+// rows); every row r != p_k gets
 // aug[r][c] -= f_rk aug[p_k][c] for c > k with f_rk = aug[r][k] / aug[p_k][k].
 // The panel kernel (one workgroup) runs these steps on the panel's own
 // columns and records the multipliers F[r][k - k0] (0 for r = p_k).  The
@@ -1052,6 +1034,86 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, in
     }
 }
 
+// The same panel steps with the panel's columns (and the used flags) held in
+// LDS for the whole panel (n <= GJ_LDS_ROWS), padded to an odd row stride.
+// The pivot of column k is chosen by a 32-bit key: the top 22 bits of |value|
+// (its exponent and 11 mantissa bits) above 10 bits of (1023 - row), so the
+// pivot is an unused row whose |value| is within 2^-11 of the column's
+// largest (the lower row among equal keys); the keys meet in an LDS atomicMax,
+// filled for column k + 1 by the lanes that update it in step k, so each step
+// takes one barrier.  Multipliers use the pivot's reciprocal.
+constexpr int GJ_LDS_ROWS = 1024;
+constexpr int GJ_LDS_LD = GJ_NB + 1;
+
+__device__ inline unsigned gj_key(double a, int r) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(a));
+    return ((unsigned)(bits >> 41) << 10) | (unsigned)(1023 - r);
+}
+
+__global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel_lds(int n, int k0, int nb, double *aug, int *used,
+                                                                    int *pivrow, double *F, int *flag) {
+    __shared__ double pan[GJ_LDS_ROWS * GJ_LDS_LD];
+    __shared__ unsigned char uf[GJ_LDS_ROWS];
+    __shared__ unsigned K[3];
+    const size_t ld = 2 * (size_t)n;
+    const int tid = threadIdx.x;
+    const int cc = tid % GJ_NB, r0 = tid / GJ_NB, rstep = GJ_PANEL_THREADS / GJ_NB;
+    for (int t = tid; t < n * GJ_NB; t += GJ_PANEL_THREADS) {
+        const int r = t / GJ_NB, q = t % GJ_NB;
+        if (q < nb) pan[r * GJ_LDS_LD + q] = aug[(size_t)r * ld + k0 + q];
+    }
+    for (int r = tid; r < n; r += GJ_PANEL_THREADS) uf[r] = used[r] ? 1 : 0;
+    if (tid < 3) K[tid] = 0u;
+    __syncthreads();
+    {
+        unsigned loc = 0u;
+        for (int r = tid; r < n; r += GJ_PANEL_THREADS)
+            if (!uf[r]) loc = max(loc, gj_key(pan[r * GJ_LDS_LD], r));
+        if (loc) atomicMax(&K[0], loc);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < nb; ++kk) {
+        // K[kk % 3] is complete; K[(kk + 1) % 3] collects the next column's
+        // keys; K[(kk + 2) % 3] was read one step ago and is cleared for reuse
+        const unsigned key = K[kk % 3];
+        const int p = 1023 - (int)(key & 1023u);
+        if ((key >> 10) == 0u) {
+            if (tid == 0) atomicOr(flag, 64);
+            break;
+        }
+        if (tid == 0) {
+            pivrow[k0 + kk] = p;
+            K[(kk + 2) % 3] = 0u;
+        }
+        const double rinv = 1.0 / pan[p * GJ_LDS_LD + kk];
+        const int c = kk + 1 + cc;
+        const bool upd = (c < nb);
+        const double pc = upd ? pan[p * GJ_LDS_LD + c] : 0.0;
+        unsigned loc = 0u;
+        for (int r = r0; r < n; r += rstep) {
+            const double f = (r == p) ? 0.0 : pan[r * GJ_LDS_LD + kk] * rinv;
+            if (cc == 0) {
+                F[(size_t)r * nb + kk] = f;
+                if (r == p) uf[r] = 1;
+            }
+            if (upd && r != p) {
+                const double nv = pan[r * GJ_LDS_LD + c] - f * pc;
+                pan[r * GJ_LDS_LD + c] = nv;
+                if (cc == 0 && !uf[r]) loc = max(loc, gj_key(nv, r));
+            }
+        }
+        if (loc) atomicMax(&K[(kk + 1) % 3], loc);
+        __syncthreads();
+    }
+    __syncthreads();
+    // the panel's columns and the flags back to global memory
+    for (int t = tid; t < n * GJ_NB; t += GJ_PANEL_THREADS) {
+        const int r = t / GJ_NB, q = t % GJ_NB;
+        if (q < nb) aug[(size_t)r * ld + k0 + q] = pan[r * GJ_LDS_LD + q];
+    }
+    for (int r = tid; r < n; r += GJ_PANEL_THREADS) used[r] = uf[r];
+}
+
 // U[kk][c] = u_k(c) for the columns right of the panel
 __global__ void k_gj_pivot_rows(int n, int k0, int nb, const double *__restrict__ aug, const int *__restrict__ pivrow,
                                 const double *__restrict__ F, double *__restrict__ U) {
@@ -1105,9 +1167,14 @@ void amg_dense_inverse(int n, const int *rp, const int *ci, const double *v, dou
     const int nby = (n + GJ_ROWS - 1) / GJ_ROWS;
     for (int k0 = 0; k0 < n; k0 += GJ_NB) {
         const int nb = std::min(GJ_NB, n - k0);
-        hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(GJ_PANEL_THREADS), 0, st, n, k0, nb, aug, used, pivrow, F, flag);
         const int width = 2 * n - (k0 + nb);
         const int nbx = (width + 255) / 256;
+        if (n <= GJ_LDS_ROWS)
+            hipLaunchKernelGGL(k_gj_panel_lds, dim3(1), dim3(GJ_PANEL_THREADS), 0, st, n, k0, nb, aug, used, pivrow,
+                               F, flag);
+        else
+            hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(GJ_PANEL_THREADS), 0, st, n, k0, nb, aug, used, pivrow, F,
+                               flag);
         hipLaunchKernelGGL(k_gj_pivot_rows, dim3(nbx), dim3(256), 0, st, n, k0, nb, aug, pivrow, F, U);
         hipLaunchKernelGGL(k_gj_trailing, dim3(nbx, nby), dim3(256), 0, st, n, k0, nb, aug, F, U);
     }
