@@ -617,20 +617,28 @@ void amg_exti_compute2(int n, const int *rp, const int *ci, const double *v, con
     CPTR_CHECK_LAUNCH();
 }
 
-// copy segments [off[i], off[i] + (prp[i+1]-prp[i])) to the compact CSR
+// copy segments [off[i], off[i] + (prp[i+1]-prp[i])) to the compact CSR,
+// CP_G lanes per row
+constexpr int CP_G = 8;
+
 __global__ void k_compact(int n, const int *__restrict__ off, const int *__restrict__ tcol,
                           const double *__restrict__ tw, const int *__restrict__ prp, int *__restrict__ pci,
                           double *__restrict__ pv) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / CP_G), l = (int)(t % CP_G);
     if (i >= n) return;
-    int o = off[i], d = prp[i], c = prp[i + 1] - prp[i];
-    for (int p = 0; p < c; ++p) { pci[d + p] = tcol[o + p]; pv[d + p] = tw[o + p]; }
+    const int o = off[i], d = prp[i], c = prp[i + 1] - prp[i];
+    for (int p = l; p < c; p += CP_G) {
+        pci[d + p] = tcol[o + p];
+        pv[d + p] = tw[o + p];
+    }
 }
 
 void amg_compact(int n, const int *off, const int *tcol, const double *tw, const int *prp, int *pci, double *pv,
                  hipStream_t st) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, off, tcol, tw, prp, pci, pv);
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for((size_t)n * CP_G, 256)), dim3(256), 0, st, n, off, tcol, tw, prp,
+                       pci, pv);
     CPTR_CHECK_LAUNCH();
 }
 

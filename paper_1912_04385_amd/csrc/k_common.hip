@@ -82,8 +82,9 @@ void pool_trim(hipStream_t s) {
     for (auto &kv : victims) (void)hipFree(kv.second);
 }
 
-constexpr int SCAN_THREADS = 1024;
-constexpr int SCAN_ITEMS = 4;
+// 256-thread blocks: they find room on the GPU beside concurrent kernels
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
 // exclusive scan of one value per thread across a 1024-thread block
@@ -194,7 +195,7 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_final(const int *in, int 
 
 // the block sums live in a pooled buffer of the calling stream
 // up to this many tiles the scan runs as a single block
-constexpr int SCAN_SINGLE_TILES = 16;
+constexpr int SCAN_SINGLE_TILES = 32;
 
 void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t s) {
     int nb = (n + SCAN_TILE - 1) / SCAN_TILE;

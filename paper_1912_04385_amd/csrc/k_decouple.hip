@@ -6,6 +6,8 @@
 // definition's evaluation order (stated at each formula).
 #include "internal.h"
 
+#include <algorithm>
+
 namespace cptr {
 
 // index of the k-th unknown of the eliminated group: the unknowns other than
@@ -164,9 +166,9 @@ __global__ void __launch_bounds__(64) k_decouple_apply(int n, const int *__restr
     constexpr int NG = CPR ? B - 1 : B - 2;
     constexpr int NR = CPR ? 1 : 2;
     constexpr int NGX = NG > 0 ? NG : 1;
-    const int i = blockIdx.x;
     const int lane = threadIdx.x;
-    if (i >= n || lane >= B * B) return;
+    if (lane >= B * B) return;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
     double F[NGX][NR];
 #pragma unroll
     for (int k = 0; k < NG; ++k) {
@@ -206,6 +208,7 @@ __global__ void __launch_bounds__(64) k_decouple_apply(int n, const int *__restr
             if (slabP32) slabP32[(size_t)e * B + r] = (float)out;
         }
     }
+    }
 }
 
 void launch_decouple_weights(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
@@ -230,18 +233,24 @@ void launch_decouple_weights(int variant, int n, int b, const int *rp, const int
     CPTR_CHECK_LAUNCH();
 }
 
+// The apply phase runs beside the AMG setups: its grid is capped so that it
+// holds a quarter of the GPU's wavefront slots and leaves room for their
+// kernels (each wavefront loops over cells).
+constexpr int DA_MAX_WAVES = 2048;
+
 void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                            const double *wp, const double *wt, const double *beta, double *abar, double *slabT,
                            double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s) {
     if (n == 0) return;
+    const int grid = std::min(n, DA_MAX_WAVES);
 #define CASE(BB)                                                                                                  \
     case BB:                                                                                                      \
         if (variant == CPTR_VARIANT_CPR)                                                                          \
-            hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPR>), dim3(n), dim3(64), 0, s, n, rp, ci, A,    \
+            hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPR>), dim3(grid), dim3(64), 0, s, n, rp, ci, A, \
                                ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);              \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPTR3>), dim3(n), dim3(64), 0, s, n, rp, ci, A,  \
-                               ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);              \
+            hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPTR3>), dim3(grid), dim3(64), 0, s, n, rp, ci,  \
+                               A, ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);           \
         break;
     switch (b) {
         CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
