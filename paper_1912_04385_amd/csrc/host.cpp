@@ -224,7 +224,8 @@ static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
     if (sk == 2 || (sk == 0 && 2 * maxprod + 1 <= SPGEMM_THREAD_CAP))
         amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
     else
-        amg_spgemm_compute_sort(m, maxprod, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
+        amg_spgemm_compute_sort(m, B.ncols, maxprod, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p,
+                                c->s_i3.p, s);
     C.n = m;
     C.ncols = B.ncols;
     C.rp_own.alloc((size_t)m + 1);

@@ -171,9 +171,9 @@ void amg_transpose(int nr, int nc, int nnz, const int *rp, const int *ci, const 
                    double *vT, int *work, hipStream_t st);
 // maxprod (device, may be NULL) receives the largest product count of a row
 void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, int *maxprod, hipStream_t st);
-void amg_spgemm_compute_sort(int m, int maxprod, const int *arp, const int *aci, const double *av, const int *brp,
-                             const int *bci, const double *bv, const int *off, int *tcol, double *tval, int *cnt,
-                             hipStream_t st);
+void amg_spgemm_compute_sort(int m, int ncols, int maxprod, const int *arp, const int *aci, const double *av,
+                             const int *brp, const int *bci, const double *bv, const int *off, int *tcol,
+                             double *tval, int *cnt, hipStream_t st);
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
                         const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
 void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,

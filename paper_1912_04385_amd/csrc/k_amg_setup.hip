@@ -831,15 +831,25 @@ __global__ void __launch_bounds__(SPG_T) k_spgemm_compute(int m, const int *__re
 // bit, as the sequential accumulation.  Longer rows: lane 0 of the group with
 // the global-memory hash.  One wavefront per block; the sort length is the
 // wavefront's largest row rounded up to a power of two.
-template <int G, int CAP>
+template <int G, int CAP, int SA_CHUNK, typename KEY>
 __global__ void __launch_bounds__(64) k_spgemm_sort(int m, const int *__restrict__ arp, const int *__restrict__ aci,
                                                     const double *__restrict__ av, const int *__restrict__ brp,
                                                     const int *__restrict__ bci, const double *__restrict__ bv,
                                                     const int *__restrict__ off, int *__restrict__ tcol,
                                                     double *__restrict__ tval, int *__restrict__ cnt) {
     constexpr int NG = 64 / G;
-    __shared__ unsigned long long skey[NG][CAP];
+    constexpr int SA_PER = SA_CHUNK / G;
+    static_assert(SA_PER >= 1 && SA_PER <= 2 && SA_PER * G == SA_CHUNK, "chunk of A entries per group");
+    // key = column above the position: 32 bits when the columns fit above
+    // log2(CAP) position bits, else 64
+    constexpr int PB = (sizeof(KEY) == 4) ? (CAP == 256 ? 8 : 10) : 32;
+    static_assert(sizeof(KEY) == 8 || (1 << PB) == CAP, "position bits");
+    constexpr KEY PMASK = (KEY)(((KEY)1 << PB) - 1);
+    __shared__ KEY skey[NG][CAP];
     __shared__ double sval[NG][CAP];
+    __shared__ double sa_val[NG][SA_CHUNK];
+    __shared__ int sa_beg[NG][SA_CHUNK];
+    __shared__ int sa_off[NG][SA_CHUNK + 1];
     const int lane = threadIdx.x, g = lane / G, gl = lane % G;
     const int i = blockIdx.x * NG + g;
     const bool act = i < m;
@@ -854,32 +864,73 @@ __global__ void __launch_bounds__(64) k_spgemm_sort(int m, const int *__restrict
     for (int d = 32; d >= 1; d >>= 1) maxP = max(maxP, __shfl_xor(maxP, d, 64));
     int S = 1;
     while (S < maxP) S <<= 1;
-    if (act && !big) {
-        int base = 0;
-        for (int e = arp[i]; e < arp[i + 1]; ++e) {
-            const int k = aci[e];
-            const double a = av[e];
-            const int f0 = brp[k], len = brp[k + 1] - f0;
-            for (int t = gl; t < len; t += G) {
-                const int p = base + t;
-                skey[g][p] = ((unsigned long long)(unsigned)bci[f0 + t] << 32) | (unsigned)p;
-                sval[g][p] = a * bv[f0 + t];
+    // expansion, SA_CHUNK entries of A's row at a time: the group loads their
+    // columns, values and B-row extents at once, scans the extents, and then
+    // every lane fetches its products (product t of the chunk belongs to the
+    // entry whose extent holds t), so the loads do not form one serial chain
+    const int e0 = (act && !big) ? arp[i] : 0;
+    const int ne_row = (act && !big) ? arp[i + 1] - e0 : 0;
+    int nchunk = (ne_row + SA_CHUNK - 1) / SA_CHUNK;
+    for (int d = 32; d >= 1; d >>= 1) nchunk = max(nchunk, __shfl_xor(nchunk, d, 64));
+    int base = 0;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int c0 = ch * SA_CHUNK;
+        const int ne = max(0, min(SA_CHUNK, ne_row - c0));
+        // entries 2 gl and 2 gl + 1 of the chunk (G = 16 lanes cover 32)
+        int len0 = 0, len1 = 0;
+        for (int q = gl * SA_PER; q < gl * SA_PER + SA_PER; ++q) {
+            int len = 0;
+            if (q < ne) {
+                const int k = aci[e0 + c0 + q];
+                const int f0 = brp[k];
+                len = brp[k + 1] - f0;
+                sa_val[g][q] = av[e0 + c0 + q];
+                sa_beg[g][q] = f0;
             }
-            base += len;
+            if (q == gl * SA_PER) len0 = len; else len1 += len;
         }
+        // exclusive scan of the per-lane sums across the group
+        const int mine = len0 + len1;
+        int incl = mine;
+        for (int d = 1; d < G; d <<= 1) {
+            const int y = __shfl_up(incl, d, G);
+            if (gl >= d) incl += y;
+        }
+        const int excl = incl - mine;
+        const int total = __shfl(incl, G - 1, G);
+        if (gl * SA_PER < SA_CHUNK) {
+            sa_off[g][gl * SA_PER] = excl;
+            if (SA_PER > 1) sa_off[g][gl * SA_PER + 1] = excl + len0;
+        }
+        if (gl == 0) sa_off[g][SA_CHUNK] = total;
+        __syncthreads();
+        for (int t = gl; t < total; t += G) {
+            // the last entry q with sa_off[q] <= t (empty extents are skipped)
+            int lo = 0, hi = ne - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sa_off[g][mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const int f = sa_beg[g][lo] + (t - sa_off[g][lo]);
+            const int p = base + t;
+            skey[g][p] = ((KEY)(unsigned)bci[f] << PB) | (KEY)p;
+            sval[g][p] = sa_val[g][lo] * bv[f];
+        }
+        base += total;
+        __syncthreads();
     }
-    for (int p = myP + gl; p < S; p += G) skey[g][p] = ~0ull;
+    for (int p = myP + gl; p < S; p += G) skey[g][p] = ~(KEY)0;
     __syncthreads();
+    // bitonic network; each lane takes compare-exchange pairs (t, t + j)
     for (int k = 2; k <= S; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = gl; t < S; t += G) {
-                const int q = t ^ j;
-                if (q > t) {
-                    const unsigned long long x = skey[g][t], y = skey[g][q];
-                    if ((x > y) == ((t & k) == 0)) {
-                        skey[g][t] = y;
-                        skey[g][q] = x;
-                    }
+            for (int u = gl; u < (S >> 1); u += G) {
+                const int t = ((u & ~(j - 1)) << 1) | (u & (j - 1));
+                const int q = t + j;
+                const KEY x = skey[g][t], y = skey[g][q];
+                if ((x > y) == ((t & k) == 0)) {
+                    skey[g][t] = y;
+                    skey[g][q] = x;
                 }
             }
             __syncthreads();
@@ -896,15 +947,15 @@ __global__ void __launch_bounds__(64) k_spgemm_sort(int m, const int *__restrict
     int nh = 0;
     for (int c0 = 0; c0 < myP; c0 += G) {
         const int pos = c0 + gl;
-        const bool head = pos < myP && (pos == 0 || (skey[g][pos] >> 32) != (skey[g][pos - 1] >> 32));
+        const bool head = pos < myP && (pos == 0 || (skey[g][pos] >> PB) != (skey[g][pos - 1] >> PB));
         const unsigned long long mask = __ballot(head) & gmask;
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
         if (head) {
-            const unsigned long long kh = skey[g][pos];
-            const unsigned j = (unsigned)(kh >> 32);
-            double acc = sval[g][(unsigned)kh];
-            for (int t = pos + 1; t < myP && (unsigned)(skey[g][t] >> 32) == j; ++t)
-                acc = acc + sval[g][(unsigned)skey[g][t]];
+            const KEY kh = skey[g][pos];
+            const unsigned j = (unsigned)(kh >> PB);
+            double acc = sval[g][(unsigned)(kh & PMASK)];
+            for (int t = pos + 1; t < myP && (unsigned)(skey[g][t] >> PB) == j; ++t)
+                acc = acc + sval[g][(unsigned)(skey[g][t] & PMASK)];
             ok[nh + before] = (int)j;
             ov[nh + before] = acc;
         }
@@ -913,16 +964,26 @@ __global__ void __launch_bounds__(64) k_spgemm_sort(int m, const int *__restrict
     if (gl == 0) cnt[i] = nh;
 }
 
-void amg_spgemm_compute_sort(int m, int maxprod, const int *arp, const int *aci, const double *av, const int *brp,
-                             const int *bci, const double *bv, const int *off, int *tcol, double *tval, int *cnt,
-                             hipStream_t st) {
+void amg_spgemm_compute_sort(int m, int ncols, int maxprod, const int *arp, const int *aci, const double *av,
+                             const int *brp, const int *bci, const double *bv, const int *off, int *tcol,
+                             double *tval, int *cnt, hipStream_t st) {
     if (m == 0) return;
-    if (maxprod <= 256)
-        hipLaunchKernelGGL((k_spgemm_sort<16, 256>), dim3((m + 3) / 4), dim3(64), 0, st, m, arp, aci, av, brp, bci,
-                           bv, off, tcol, tval, cnt);
-    else
-        hipLaunchKernelGGL((k_spgemm_sort<64, 1024>), dim3(m), dim3(64), 0, st, m, arp, aci, av, brp, bci, bv, off,
-                           tcol, tval, cnt);
+    const dim3 g4((m + 3) / 4), g1(m), w(64);
+    if (maxprod <= 256) {
+        if (ncols < (1 << 24))
+            hipLaunchKernelGGL((k_spgemm_sort<16, 256, 32, unsigned>), g4, w, 0, st, m, arp, aci, av, brp, bci, bv,
+                               off, tcol, tval, cnt);
+        else
+            hipLaunchKernelGGL((k_spgemm_sort<16, 256, 32, unsigned long long>), g4, w, 0, st, m, arp, aci, av, brp,
+                               bci, bv, off, tcol, tval, cnt);
+    } else {
+        if (ncols < (1 << 22))
+            hipLaunchKernelGGL((k_spgemm_sort<64, 1024, 64, unsigned>), g1, w, 0, st, m, arp, aci, av, brp, bci, bv,
+                               off, tcol, tval, cnt);
+        else
+            hipLaunchKernelGGL((k_spgemm_sort<64, 1024, 64, unsigned long long>), g1, w, 0, st, m, arp, aci, av, brp,
+                               bci, bv, off, tcol, tval, cnt);
+    }
     CPTR_CHECK_LAUNCH();
 }
 
