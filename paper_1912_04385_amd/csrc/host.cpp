@@ -31,7 +31,7 @@ static void set_error(const std::string &m) { g_last_error = m; }
 constexpr int MAX_COARSE_DENSE = 8192;
 constexpr int PMIS_BATCH = 3;
 constexpr int SPGEMM_THREAD_CAP = 48;   // LDS hash capacity of the thread-per-row SpGEMM
-constexpr int EXTI_THREAD_ROWS = 100000;  // ext+i: one thread per row above this many rows
+constexpr double EXTI_SHORT_ROW = 8.0;     // ext+i: one thread per row up to this average row length
 
 // per-hierarchy setup state: each AMG hierarchy is built on its own stream
 // (and host thread) with its own scratch and flag word
@@ -426,19 +426,27 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         ub.alloc(m + 1);
         off.alloc(m + 1);
         cnt.alloc(m + 1);
-        const bool exti_thread = (o.setup_kernels == 2 || (o.setup_kernels == 0 && m > EXTI_THREAD_ROWS));
-        amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, !exti_thread, s);
+        // row kernels: by row length (default: one thread per row on short
+        // rows, a wavefront with the rows fetched into LDS on long ones), one
+        // wavefront per row (1) or one thread per row (2); all give the same
+        // interpolation bit for bit
+        const double avg_row = (double)L.A.nnz / (double)m;
+        const int ek = o.setup_kernels;
+        const bool thread_rows = (ek == 2) || (ek == 0 && avg_row <= EXTI_SHORT_ROW);
+        amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, !thread_rows, s);
         const int cap = scan_total(ub.p, off.p, m, s);
         tcol.alloc(cap);
         twt.alloc(cap);
         td.alloc((size_t)L.A.nnz + 1);
-        // short rows: one thread per row; long rows (coarse levels): one wavefront per row
-        if (exti_thread)
+        if (thread_rows)
             amg_exti_compute2(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
                               tcol.p, twt.p, td.p, cnt.p, s);
-        else
+        else if (ek == 1)
             amg_exti_compute_wave(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax,
                                   off.p, tcol.p, twt.p, td.p, cnt.p, s);
+        else
+            amg_exti_compute_group(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax,
+                                   off.p, tcol.p, twt.p, td.p, cnt.p, s);
         CsrD &P = L.P;
         P.n = m;
         P.ncols = nc;

@@ -600,6 +600,340 @@ __global__ void __launch_bounds__(64) k_exti_wave(int n, const int *__restrict__
     if (lane == 0) cnt[i] = keep;
 }
 
+// One group of G lanes per row (64 / G rows per wavefront; G = 64 serves the
+// Galerkin levels, whose rows are long).  The row's entries
+// and the rows of its strong F neighbours (flattened into one list, entry t of
+// the list belonging to the neighbour whose extent holds t) are fetched into
+// LDS by all lanes at once; every quantity of exti_row is then formed from
+// LDS with exti_row's definition and summation order:
+//   Chat_i  - the distinct candidates (rank of each first occurrence);
+//   d_k     - one lane per strong F neighbour, over its extent in order;
+//   atilde  - one lane over the row's terms in order;
+//   num_j   - a_ij, then the neighbours' terms in list order (= row order of
+//             the neighbours, then of their rows), one lane per j;
+//   truncation as in exti_row.
+// Rows beyond the caps (RCAP entries, WCAP listed entries, HCAP candidates)
+// run exti_row on the group's first lane.
+template <int G, int RCAP, int WCAP, int HCAP>
+__global__ void __launch_bounds__(64) k_exti_group(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                   const double *__restrict__ v, const unsigned char *__restrict__ s,
+                                                   const int *__restrict__ cf, const int *__restrict__ cidx,
+                                                   const double *__restrict__ dg, int pmax,
+                                                   const int *__restrict__ off, int *__restrict__ tcol,
+                                                   double *__restrict__ tw, double *__restrict__ td,
+                                                   int *__restrict__ cnt) {
+    constexpr int NG = 64 / G;
+    constexpr int RPL = (RCAP + G - 1) / G;
+    // row entry flags
+    constexpr unsigned char RS = 1, RC = 2, RF = 4, RX = 8, RU = 16;
+    __shared__ int r_col[NG][RCAP];
+    __shared__ double r_val[NG][RCAP];
+    __shared__ unsigned char r_fl[NG][RCAP];
+    __shared__ int r_beg[NG][RCAP];
+    __shared__ int r_off[NG][RCAP + 1];
+    __shared__ double r_dg[NG][RCAP];
+    __shared__ double r_d[NG][RCAP];
+    __shared__ double r_term[NG][RCAP];
+    __shared__ int f_col[NG][WCAP];
+    __shared__ double f_val[NG][WCAP];
+    __shared__ unsigned char f_fl[NG][WCAP];
+    __shared__ int f_pos[NG][WCAP];
+    __shared__ double f_con[NG][WCAP];
+    __shared__ int h_cand[NG][HCAP];
+    __shared__ unsigned char h_first[NG][HCAP];
+    __shared__ int h_hat[NG][HCAP];
+    __shared__ double h_w[NG][HCAP];
+    __shared__ unsigned char h_kept[NG][HCAP];
+    __shared__ double g_at[NG];
+    const int lane = threadIdx.x, g = lane / G, gl = lane % G;
+    const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
+    const int i = blockIdx.x * NG + g;
+    const bool act = i < n;
+    const bool isC = act && cf[i] == ST_C;
+    const int a = act ? rp[i] : 0;
+    const int L = act ? rp[i + 1] - a : 0;
+    const int ub = act ? off[i + 1] - off[i] : 0;
+    bool work = act && !isC && L <= RCAP && ub <= HCAP;
+    bool fb = act && !isC && !work;
+    // A. the row's entries and its neighbours' extents
+    int W = 0;
+    {
+        int lens[RPL];
+        int mine = 0;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+            const int q = gl * RPL + u;
+            int len = 0;
+            if (work && q < L) {
+                const int e = a + q;
+                const int col = ci[e];
+                const bool sv = s[e] != 0;
+                const int c = cf[col];
+                unsigned char fl = (sv ? RS : 0) | (c == ST_C ? RC : 0) | (c == ST_F ? RF : 0);
+                if (sv && c != ST_C) {
+                    fl |= RX;
+                    const int b0 = rp[col];
+                    len = rp[col + 1] - b0;
+                    r_beg[g][q] = b0;
+                    r_dg[g][q] = dg[col];
+                }
+                r_col[g][q] = col;
+                r_val[g][q] = v[e];
+                r_fl[g][q] = fl;
+            }
+            lens[u] = len;
+            mine += len;
+        }
+        int incl = mine;
+        for (int d = 1; d < G; d <<= 1) {
+            const int y = __shfl_up(incl, d, G);
+            if (gl >= d) incl += y;
+        }
+        int run = incl - mine;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+            const int q = gl * RPL + u;
+            if (q < RCAP) r_off[g][q] = run;
+            run += lens[u];
+        }
+        W = __shfl(incl, G - 1, G);
+        if (gl == 0) r_off[g][RCAP] = W;
+        if (work && W > WCAP) {
+            work = false;
+            fb = true;
+        }
+    }
+    __syncthreads();
+    // B. the flattened rows of the strong F neighbours
+    if (work) {
+        for (int t = gl; t < W; t += G) {
+            int lo = 0, hi = L - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (r_off[g][mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const int f = r_beg[g][lo] + (t - r_off[g][lo]);
+            const int l = ci[f];
+            f_col[g][t] = l;
+            f_val[g][t] = v[f];
+            f_fl[g][t] = (s[f] ? RS : 0) | (cf[l] == ST_C ? RC : 0);
+        }
+    }
+    __syncthreads();
+    // C. candidates with repeats: strong C entries of the row, then strong C
+    // entries of the listed rows
+    int nc = 0;
+    if (work) {
+        for (int q0 = 0; q0 < L; q0 += G) {
+            const int q = q0 + gl;
+            const bool take = q < L && (r_fl[g][q] & (RS | RC)) == (RS | RC);
+            const unsigned long long m = __ballot(take) & gmask;
+            if (take) h_cand[g][nc + __popcll(m & ((1ull << lane) - 1ull))] = r_col[g][q];
+            nc += __popcll(m);
+        }
+        for (int t0 = 0; t0 < W; t0 += G) {
+            const int t = t0 + gl;
+            const bool take = t < W && (f_fl[g][t] & (RS | RC)) == (RS | RC);
+            const unsigned long long m = __ballot(take) & gmask;
+            if (take) h_cand[g][nc + __popcll(m & ((1ull << lane) - 1ull))] = f_col[g][t];
+            nc += __popcll(m);
+        }
+    }
+    __syncthreads();
+    // D. first occurrences
+    if (work) {
+        for (int t = gl; t < nc; t += G) {
+            const int x = h_cand[g][t];
+            bool first = true;
+            for (int u = 0; u < t; ++u)
+                if (h_cand[g][u] == x) { first = false; break; }
+            h_first[g][t] = first ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    // E. each distinct candidate at its rank: Chat_i in ascending order
+    int nh = 0;
+    if (work) {
+        int cntf = 0;
+        for (int t = gl; t < nc; t += G) {
+            if (!h_first[g][t]) continue;
+            ++cntf;
+            const int x = h_cand[g][t];
+            int rank = 0;
+            for (int u = 0; u < nc; ++u) rank += (h_first[g][u] && h_cand[g][u] < x) ? 1 : 0;
+            h_hat[g][rank] = x;
+        }
+        for (int d = G >> 1; d >= 1; d >>= 1) cntf += __shfl_xor(cntf, d, G);
+        nh = cntf;
+    }
+    __syncthreads();
+    auto hat_pos = [&](int key) {
+        int lo = 0, hi = nh - 1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const int c = h_hat[g][mid];
+            if (c == key) return mid;
+            if (c < key) lo = mid + 1; else hi = mid - 1;
+        }
+        return -1;
+    };
+    // F. d_k of every strong F neighbour and the terms of atilde
+    if (work && nh > 0) {
+        for (int q = gl; q < L; q += G) {
+            const unsigned char fl = r_fl[g][q];
+            const int col = r_col[g][q];
+            double d = 0.0, aki = 0.0;
+            if (fl & RX) {
+                const double akk = r_dg[g][q];
+                for (int t = r_off[g][q]; t < r_off[g][q + 1]; ++t) {
+                    const int l = f_col[g][t];
+                    if (l == i) aki = f_val[g][t];
+                    if (l == i || (l != col && (f_fl[g][t] & RC) && hat_pos(l) >= 0)) {
+                        const double ab = abar_of(akk, f_val[g][t]);
+                        if (ab != 0.0) d = d + ab;
+                    }
+                }
+            }
+            r_d[g][q] = d;
+            bool use = false;
+            double term = 0.0;
+            if (col != i) {
+                if ((fl & RS) && (fl & RF)) {
+                    if (d != 0.0) {
+                        const double ab = abar_of(r_dg[g][q], aki);
+                        if (ab != 0.0) { term = (r_val[g][q] * ab) / d; use = true; }
+                    } else {
+                        term = r_val[g][q];
+                        use = true;
+                    }
+                } else if (!(fl & RS) && !((fl & RC) && hat_pos(col) >= 0)) {
+                    term = r_val[g][q];
+                    use = true;
+                }
+            }
+            r_term[g][q] = term;
+            if (use) r_fl[g][q] = fl | RU;
+        }
+        for (int p = gl; p < nh; p += G) {
+            h_w[g][p] = 0.0;
+            h_kept[g][p] = 0;
+        }
+    }
+    __syncthreads();
+    // G. atilde (one lane, row order); a_ij into the numerators; the listed
+    // entries' numerator terms
+    if (work && nh > 0) {
+        if (gl == 0) {
+            double at = dg[i];
+            for (int q = 0; q < L; ++q)
+                if (r_fl[g][q] & RU) at = at + r_term[g][q];
+            g_at[g] = at;
+        }
+        for (int q = gl; q < L; q += G) {
+            const int pos = hat_pos(r_col[g][q]);
+            if (pos >= 0) h_w[g][pos] = r_val[g][q];
+        }
+        for (int t = gl; t < W; t += G) {
+            int lo = 0, hi = L - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (r_off[g][mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const int k = r_col[g][lo];
+            const double d = r_d[g][lo];
+            int pos = -1;
+            double con = 0.0;
+            if (k != i && d != 0.0) {
+                pos = hat_pos(f_col[g][t]);
+                if (pos >= 0) {
+                    const double ab = abar_of(r_dg[g][lo], f_val[g][t]);
+                    if (ab != 0.0) con = (r_val[g][lo] * ab) / d;
+                    else pos = -1;
+                }
+            }
+            f_pos[g][t] = pos;
+            f_con[g][t] = con;
+        }
+    }
+    __syncthreads();
+    // H. numerators summed in list order, weights
+    double at = 0.0;
+    if (work && nh > 0) {
+        at = g_at[g];
+        if (at != 0.0) {
+            for (int p = gl; p < nh; p += G) {
+                double num = h_w[g][p];
+                for (int t = 0; t < W; ++t)
+                    if (f_pos[g][t] == p) num = num + f_con[g][t];
+                h_w[g][p] = -num / at;
+            }
+        }
+    }
+    __syncthreads();
+    // I. truncation to the pmax largest |w| (ties: lower position)
+    const bool trunc = work && nh > 0 && at != 0.0 && pmax > 0 && nh > pmax;
+    for (int round = 0; round < pmax; ++round) {
+        if (trunc) {
+            double bv = -1.0;
+            int bp = 0x7fffffff;
+            for (int p = gl; p < nh; p += G) {
+                if (h_kept[g][p]) continue;
+                const double av = fabs(h_w[g][p]);
+                if (av > bv || (av == bv && p < bp)) { bv = av; bp = p; }
+            }
+            for (int d = G >> 1; d >= 1; d >>= 1) {
+                const double ov = __shfl_xor(bv, d, G);
+                const int op = __shfl_xor(bp, d, G);
+                if (ov > bv || (ov == bv && op < bp)) { bv = ov; bp = op; }
+            }
+            if (gl == 0) h_kept[g][bp] = 1;
+        }
+        __syncthreads();
+    }
+    // J. output
+    if (act) {
+        int *ocol = tcol + off[i];
+        double *ow = tw + off[i];
+        if (isC) {
+            if (gl == 0) { ocol[0] = cidx[i]; ow[0] = 1.0; cnt[i] = 1; }
+        } else if (fb) {
+            if (gl == 0) exti_row(i, rp, ci, v, s, cf, cidx, dg, pmax, ocol, 1, ow, td, ocol, cnt);
+        } else if (nh == 0 || at == 0.0) {
+            if (gl == 0) cnt[i] = 0;
+        } else if (trunc) {
+            if (gl == 0) {
+                double sall = 0.0, skept = 0.0;
+                for (int p = 0; p < nh; ++p) sall = sall + h_w[g][p];
+                for (int p = 0; p < nh; ++p) if (h_kept[g][p]) skept = skept + h_w[g][p];
+                const double scale = (skept != 0.0) ? sall / skept : 1.0;
+                int q = 0;
+                for (int p = 0; p < nh; ++p) {
+                    if (!h_kept[g][p]) continue;
+                    ocol[q] = cidx[h_hat[g][p]];
+                    ow[q] = (skept != 0.0) ? h_w[g][p] * scale : h_w[g][p];
+                    q++;
+                }
+                cnt[i] = pmax;
+            }
+        } else {
+            for (int p = gl; p < nh; p += G) {
+                ocol[p] = cidx[h_hat[g][p]];
+                ow[p] = h_w[g][p];
+            }
+            if (gl == 0) cnt[i] = nh;
+        }
+    }
+}
+
+void amg_exti_compute_group(int n, const int *rp, const int *ci, const double *v, const unsigned char *s,
+                            const int *cf, const int *cidx, const double *dg, int pmax, const int *off, int *tcol,
+                            double *tw, double *td, int *cnt, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_exti_group<64, 64, 512, 128>), dim3(n), dim3(64), 0, st, n, rp, ci, v, s, cf, cidx, dg,
+                       pmax, off, tcol, tw, td, cnt);
+    CPTR_CHECK_LAUNCH();
+}
+
 void amg_exti_compute_wave(int n, const int *rp, const int *ci, const double *v, const unsigned char *s,
                            const int *cf, const int *cidx, const double *dg, int pmax, const int *off, int *tcol,
                            double *tw, double *td, int *cnt, hipStream_t st) {
