@@ -31,7 +31,8 @@ static void set_error(const std::string &m) { g_last_error = m; }
 constexpr int MAX_COARSE_DENSE = 8192;
 constexpr int PMIS_BATCH = 3;
 constexpr int SPGEMM_THREAD_CAP = 48;   // LDS hash capacity of the thread-per-row SpGEMM
-constexpr double EXTI_SHORT_ROW = 8.0;     // ext+i: one thread per row up to this average row length
+constexpr double EXTI_SHORT_ROW = 8.0;     // ext+i: one thread per row up to this average row length,
+constexpr double EXTI_HALF_WAVE_ROW = 16.0; // then 32 lanes per row up to this one, then 64
 
 // per-hierarchy setup state: each AMG hierarchy is built on its own stream
 // (and host thread) with its own scratch and flag word
@@ -445,8 +446,8 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
             amg_exti_compute_wave(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax,
                                   off.p, tcol.p, twt.p, td.p, cnt.p, s);
         else
-            amg_exti_compute_group(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax,
-                                   off.p, tcol.p, twt.p, td.p, cnt.p, s);
+            amg_exti_compute_group(m, avg_row <= EXTI_HALF_WAVE_ROW, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p,
+                                   cidx.p, c->s_d1.p, o.amg_pmax, off.p, tcol.p, twt.p, td.p, cnt.p, s);
         CsrD &P = L.P;
         P.n = m;
         P.ncols = nc;

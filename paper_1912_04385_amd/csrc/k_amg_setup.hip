@@ -600,8 +600,8 @@ __global__ void __launch_bounds__(64) k_exti_wave(int n, const int *__restrict__
     if (lane == 0) cnt[i] = keep;
 }
 
-// One group of G lanes per row (64 / G rows per wavefront; G = 64 serves the
-// Galerkin levels, whose rows are long).  The row's entries
+// One group of G lanes per row (64 / G rows per wavefront; 32 or 64 lanes on
+// the Galerkin levels, whose rows are long).  The row's entries
 // and the rows of its strong F neighbours (flattened into one list, entry t of
 // the list belonging to the neighbour whose extent holds t) are fetched into
 // LDS by all lanes at once; every quantity of exti_row is then formed from
@@ -634,11 +634,11 @@ __global__ void __launch_bounds__(64) k_exti_group(int n, const int *__restrict_
     __shared__ double r_dg[NG][RCAP];
     __shared__ double r_d[NG][RCAP];
     __shared__ double r_term[NG][RCAP];
+    // listed entries: column and value, overwritten in place (same lane) by
+    // the numerator position and term
     __shared__ int f_col[NG][WCAP];
     __shared__ double f_val[NG][WCAP];
     __shared__ unsigned char f_fl[NG][WCAP];
-    __shared__ int f_pos[NG][WCAP];
-    __shared__ double f_con[NG][WCAP];
     __shared__ int h_cand[NG][HCAP];
     __shared__ unsigned char h_first[NG][HCAP];
     __shared__ int h_hat[NG][HCAP];
@@ -851,8 +851,8 @@ __global__ void __launch_bounds__(64) k_exti_group(int n, const int *__restrict_
                     else pos = -1;
                 }
             }
-            f_pos[g][t] = pos;
-            f_con[g][t] = con;
+            f_col[g][t] = pos;
+            f_val[g][t] = con;
         }
     }
     __syncthreads();
@@ -864,7 +864,7 @@ __global__ void __launch_bounds__(64) k_exti_group(int n, const int *__restrict_
             for (int p = gl; p < nh; p += G) {
                 double num = h_w[g][p];
                 for (int t = 0; t < W; ++t)
-                    if (f_pos[g][t] == p) num = num + f_con[g][t];
+                    if (f_col[g][t] == p) num = num + f_val[g][t];
                 h_w[g][p] = -num / at;
             }
         }
@@ -925,12 +925,16 @@ __global__ void __launch_bounds__(64) k_exti_group(int n, const int *__restrict_
     }
 }
 
-void amg_exti_compute_group(int n, const int *rp, const int *ci, const double *v, const unsigned char *s,
-                            const int *cf, const int *cidx, const double *dg, int pmax, const int *off, int *tcol,
-                            double *tw, double *td, int *cnt, hipStream_t st) {
+void amg_exti_compute_group(int n, bool half_wave, const int *rp, const int *ci, const double *v,
+                            const unsigned char *s, const int *cf, const int *cidx, const double *dg, int pmax,
+                            const int *off, int *tcol, double *tw, double *td, int *cnt, hipStream_t st) {
     if (n == 0) return;
-    hipLaunchKernelGGL((k_exti_group<64, 64, 512, 128>), dim3(n), dim3(64), 0, st, n, rp, ci, v, s, cf, cidx, dg,
-                       pmax, off, tcol, tw, td, cnt);
+    if (half_wave)
+        hipLaunchKernelGGL((k_exti_group<32, 32, 256, 64>), dim3((n + 1) / 2), dim3(64), 0, st, n, rp, ci, v, s, cf,
+                           cidx, dg, pmax, off, tcol, tw, td, cnt);
+    else
+        hipLaunchKernelGGL((k_exti_group<64, 64, 512, 128>), dim3(n), dim3(64), 0, st, n, rp, ci, v, s, cf, cidx,
+                           dg, pmax, off, tcol, tw, td, cnt);
     CPTR_CHECK_LAUNCH();
 }
 
