@@ -31,7 +31,7 @@ static void set_error(const std::string &m) { g_last_error = m; }
 constexpr int MAX_COARSE_DENSE = 8192;
 constexpr int PMIS_BATCH = 3;
 constexpr int SPGEMM_THREAD_CAP = 48;   // LDS hash capacity of the thread-per-row SpGEMM
-constexpr double EXTI_SHORT_ROW = 8.0;     // ext+i: one thread per row up to this average row length,
+constexpr double EXTI_SHORT_ROW = 8.0;     // ext+i: 8 lanes per row up to this average row length,
 constexpr double EXTI_HALF_WAVE_ROW = 16.0; // then 32 lanes per row up to this one, then 64
 
 // per-hierarchy setup state: each AMG hierarchy is built on its own stream
@@ -427,14 +427,14 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         ub.alloc(m + 1);
         off.alloc(m + 1);
         cnt.alloc(m + 1);
-        // row kernels: by row length (default: one thread per row on short
-        // rows, a wavefront with the rows fetched into LDS on long ones), one
-        // wavefront per row (1) or one thread per row (2); all give the same
-        // interpolation bit for bit
+        // row kernels: lane groups sized by the row length, with the rows
+        // fetched into LDS (default), one wavefront per row (1) or one thread
+        // per row (2); all give the same interpolation bit for bit
         const double avg_row = (double)L.A.nnz / (double)m;
         const int ek = o.setup_kernels;
-        const bool thread_rows = (ek == 2) || (ek == 0 && avg_row <= EXTI_SHORT_ROW);
-        amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, !thread_rows, s);
+        const bool thread_rows = (ek == 2);
+        amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, ek == 1 || (ek == 0 && avg_row > EXTI_SHORT_ROW),
+                       s);
         const int cap = scan_total(ub.p, off.p, m, s);
         tcol.alloc(cap);
         twt.alloc(cap);
@@ -446,8 +446,9 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
             amg_exti_compute_wave(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax,
                                   off.p, tcol.p, twt.p, td.p, cnt.p, s);
         else
-            amg_exti_compute_group(m, avg_row <= EXTI_HALF_WAVE_ROW, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p,
-                                   cidx.p, c->s_d1.p, o.amg_pmax, off.p, tcol.p, twt.p, td.p, cnt.p, s);
+            amg_exti_compute_group(m, avg_row <= EXTI_SHORT_ROW ? 8 : avg_row <= EXTI_HALF_WAVE_ROW ? 32 : 64, L.A.rp,
+                                   L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p, tcol.p,
+                                   twt.p, td.p, cnt.p, s);
         CsrD &P = L.P;
         P.n = m;
         P.ncols = nc;

@@ -162,7 +162,7 @@ void amg_exti_bound(int n, const int *rp, const int *ci, const unsigned char *s,
 void amg_exti_compute2(int n, const int *rp, const int *ci, const double *v, const unsigned char *s, const int *cf,
                        const int *cidx, const double *dg, int pmax, const int *off, int *tcol, double *tw,
                        double *td, int *cnt, hipStream_t st);
-void amg_exti_compute_group(int n, bool half_wave, const int *rp, const int *ci, const double *v,
+void amg_exti_compute_group(int n, int lanes, const int *rp, const int *ci, const double *v,
                             const unsigned char *s, const int *cf, const int *cidx, const double *dg, int pmax,
                             const int *off, int *tcol, double *tw, double *td, int *cnt, hipStream_t st);
 void amg_exti_compute_wave(int n, const int *rp, const int *ci, const double *v, const unsigned char *s,

@@ -600,8 +600,8 @@ __global__ void __launch_bounds__(64) k_exti_wave(int n, const int *__restrict__
     if (lane == 0) cnt[i] = keep;
 }
 
-// One group of G lanes per row (64 / G rows per wavefront; 32 or 64 lanes on
-// the Galerkin levels, whose rows are long).  The row's entries
+// One group of G lanes per row (64 / G rows per wavefront: 8 lanes on the
+// 5-point fine level, 32 or 64 on the Galerkin levels).  The row's entries
 // and the rows of its strong F neighbours (flattened into one list, entry t of
 // the list belonging to the neighbour whose extent holds t) are fetched into
 // LDS by all lanes at once; every quantity of exti_row is then formed from
@@ -925,11 +925,14 @@ __global__ void __launch_bounds__(64) k_exti_group(int n, const int *__restrict_
     }
 }
 
-void amg_exti_compute_group(int n, bool half_wave, const int *rp, const int *ci, const double *v,
+void amg_exti_compute_group(int n, int lanes, const int *rp, const int *ci, const double *v,
                             const unsigned char *s, const int *cf, const int *cidx, const double *dg, int pmax,
                             const int *off, int *tcol, double *tw, double *td, int *cnt, hipStream_t st) {
     if (n == 0) return;
-    if (half_wave)
+    if (lanes == 8)
+        hipLaunchKernelGGL((k_exti_group<8, 8, 32, 16>), dim3((n + 7) / 8), dim3(64), 0, st, n, rp, ci, v, s, cf,
+                           cidx, dg, pmax, off, tcol, tw, td, cnt);
+    else if (lanes == 32)
         hipLaunchKernelGGL((k_exti_group<32, 32, 256, 64>), dim3((n + 1) / 2), dim3(64), 0, st, n, rp, ci, v, s, cf,
                            cidx, dg, pmax, off, tcol, tw, td, cnt);
     else
