@@ -1452,7 +1452,7 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, in
 // largest (the lower row among equal keys); the keys meet in an LDS atomicMax,
 // filled for column k + 1 by the lanes that update it in step k, so each step
 // takes one barrier.  Multipliers use the pivot's reciprocal.
-constexpr int GJ_LDS_ROWS = 1024;
+constexpr int GJ_LDS_ROWS = GJ_PANEL_THREADS;
 constexpr int GJ_LDS_LD = GJ_NB + 1;
 
 __device__ inline unsigned gj_key(double a, int r) {
@@ -1462,66 +1462,100 @@ __device__ inline unsigned gj_key(double a, int r) {
 
 __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel_lds(int n, int k0, int nb, double *aug, int *used,
                                                                     int *pivrow, double *F, int *flag) {
+    // one thread per row: the row's panel values and multipliers in
+    // registers, every row's current values in LDS for the pivot row's
+    // broadcast; the multipliers and pivots reach global memory at the end
+    // (a barrier also waits for pending global stores)
     __shared__ double pan[GJ_LDS_ROWS * GJ_LDS_LD];
-    __shared__ unsigned char uf[GJ_LDS_ROWS];
     __shared__ unsigned K[3];
+    __shared__ int piv[GJ_NB];
     const size_t ld = 2 * (size_t)n;
-    const int tid = threadIdx.x;
-    const int cc = tid % GJ_NB, r0 = tid / GJ_NB, rstep = GJ_PANEL_THREADS / GJ_NB;
-    for (int t = tid; t < n * GJ_NB; t += GJ_PANEL_THREADS) {
-        const int r = t / GJ_NB, q = t % GJ_NB;
-        if (q < nb) pan[r * GJ_LDS_LD + q] = aug[(size_t)r * ld + k0 + q];
+    const int r = threadIdx.x, lane = r & 63;
+    const bool own = r < n;
+    double row[GJ_NB], fr[GJ_NB];
+    bool usedr = true;
+#pragma unroll
+    for (int q = 0; q < GJ_NB; ++q) {
+        row[q] = 0.0;
+        fr[q] = 0.0;
     }
-    for (int r = tid; r < n; r += GJ_PANEL_THREADS) uf[r] = used[r] ? 1 : 0;
-    if (tid < 3) K[tid] = 0u;
-    __syncthreads();
-    {
-        unsigned loc = 0u;
-        for (int r = tid; r < n; r += GJ_PANEL_THREADS)
-            if (!uf[r]) loc = max(loc, gj_key(pan[r * GJ_LDS_LD], r));
-        if (loc) atomicMax(&K[0], loc);
+    if (own) {
+        usedr = used[r] != 0;
+#pragma unroll
+        for (int q = 0; q < GJ_NB; ++q)
+            if (q < nb) {
+                row[q] = aug[(size_t)r * ld + k0 + q];
+                pan[r * GJ_LDS_LD + q] = row[q];
+            }
     }
+    if (r < 3) K[r] = 0u;
     __syncthreads();
+    unsigned key = (own && !usedr) ? gj_key(row[0], r) : 0u;
+    for (int d = 32; d >= 1; d >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, d, 64));
+    if (lane == 0 && key) atomicMax(&K[0], key);
+    __syncthreads();
+    int done = nb;
     for (int kk = 0; kk < nb; ++kk) {
         // K[kk % 3] is complete; K[(kk + 1) % 3] collects the next column's
         // keys; K[(kk + 2) % 3] was read one step ago and is cleared for reuse
-        const unsigned key = K[kk % 3];
-        const int p = 1023 - (int)(key & 1023u);
-        if ((key >> 10) == 0u) {
-            if (tid == 0) atomicOr(flag, 64);
+        const unsigned kv = K[kk % 3];
+        const int p = 1023 - (int)(kv & 1023u);
+        if ((kv >> 10) == 0u) {
+            done = kk;
             break;
         }
-        if (tid == 0) {
-            pivrow[k0 + kk] = p;
+        if (r == 0) {
+            piv[kk] = p;
             K[(kk + 2) % 3] = 0u;
         }
         const double rinv = 1.0 / pan[p * GJ_LDS_LD + kk];
-        const int c = kk + 1 + cc;
-        const bool upd = (c < nb);
-        const double pc = upd ? pan[p * GJ_LDS_LD + c] : 0.0;
-        unsigned loc = 0u;
-        for (int r = r0; r < n; r += rstep) {
-            const double f = (r == p) ? 0.0 : pan[r * GJ_LDS_LD + kk] * rinv;
-            if (cc == 0) {
-                F[(size_t)r * nb + kk] = f;
-                if (r == p) uf[r] = 1;
-            }
-            if (upd && r != p) {
-                const double nv = pan[r * GJ_LDS_LD + c] - f * pc;
-                pan[r * GJ_LDS_LD + c] = nv;
-                if (cc == 0 && !uf[r]) loc = max(loc, gj_key(nv, r));
+        if (own) {
+            double ak = 0.0;
+#pragma unroll
+            for (int q = 0; q < GJ_NB; ++q)
+                if (q == kk) ak = row[q];
+            const double f = (r == p) ? 0.0 : ak * rinv;
+#pragma unroll
+            for (int q = 0; q < GJ_NB; ++q)
+                if (q == kk) fr[q] = f;
+            if (r == p) {
+                usedr = true;
+            } else {
+#pragma unroll
+                for (int q = 0; q < GJ_NB; ++q)
+                    if (q > kk && q < nb) row[q] -= f * pan[p * GJ_LDS_LD + q];
             }
         }
-        if (loc) atomicMax(&K[(kk + 1) % 3], loc);
+        __syncthreads();   // every thread has read the pivot row
+        unsigned nkey = 0u;
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < GJ_NB; ++q)
+                if (q > kk && q < nb) pan[r * GJ_LDS_LD + q] = row[q];
+            if (!usedr && kk + 1 < nb) {
+                double an = 0.0;
+#pragma unroll
+                for (int q = 0; q < GJ_NB; ++q)
+                    if (q == kk + 1) an = row[q];
+                nkey = gj_key(an, r);
+            }
+        }
+        for (int d = 32; d >= 1; d >>= 1) nkey = max(nkey, (unsigned)__shfl_xor((int)nkey, d, 64));
+        if (lane == 0 && nkey) atomicMax(&K[(kk + 1) % 3], nkey);
         __syncthreads();
     }
     __syncthreads();
-    // the panel's columns and the flags back to global memory
-    for (int t = tid; t < n * GJ_NB; t += GJ_PANEL_THREADS) {
-        const int r = t / GJ_NB, q = t % GJ_NB;
-        if (q < nb) aug[(size_t)r * ld + k0 + q] = pan[r * GJ_LDS_LD + q];
+    if (done < nb && r == 0) atomicOr(flag, 64);
+    if (r < done) pivrow[k0 + r] = piv[r];
+    if (own) {
+#pragma unroll
+        for (int q = 0; q < GJ_NB; ++q)
+            if (q < nb) {
+                aug[(size_t)r * ld + k0 + q] = row[q];
+                F[(size_t)r * nb + q] = fr[q];
+            }
+        used[r] = usedr ? 1 : 0;
     }
-    for (int r = tid; r < n; r += GJ_PANEL_THREADS) used[r] = uf[r];
 }
 
 // U[kk][c] = u_k(c) for the columns right of the panel
