@@ -29,7 +29,9 @@ static thread_local std::string g_last_error;
 static void set_error(const std::string &m) { g_last_error = m; }
 
 constexpr int MAX_COARSE_DENSE = 8192;
-constexpr int PMIS_BATCH = 3;
+constexpr int PMIS_BATCH = 3;            // PMIS rounds between reads of the undecided count
+constexpr int PMIS_BATCH_SMALL = 6;      // ... on levels below PMIS_SMALL_LEVEL rows
+constexpr int PMIS_SMALL_LEVEL = 100000;
 constexpr int SPGEMM_THREAD_CAP = 48;   // LDS hash capacity of the thread-per-row SpGEMM
 constexpr double EXTI_SHORT_ROW = 8.0;     // ext+i: 8 lanes per row up to this average row length,
 constexpr double EXTI_HALF_WAVE_ROW = 16.0; // then 32 lanes per row up to this one, then 64
@@ -42,10 +44,13 @@ struct Builder {
     int n = 0, nnzb = 0;
     struct { const int *p = nullptr; } rp, ci;
     DBuf<int> s_i1, s_i2, s_i3, s_i4, flag;
+    DBuf<int> stage;             // device ints gathered for one host read
     DBuf<double> s_d1;
     DBuf<uint64_t> s_u1;
     DBuf<unsigned char> s_c1;
 };
+
+
 
 struct cptr_ctx {
     int device = 0;
@@ -199,44 +204,78 @@ static int scan_total(const int *in, int *out, int n, hipStream_t s) {
     return read_scalar(out + n, s);
 }
 
+// three device ints with one host round trip
+static void read_ints3(Builder *c, const int *a, const int *b, const int *d, int out[3]) {
+    c->stage.alloc(4);
+    gather_ints(a, b, d, c->stage.p, c->stream);
+    read_bytes(out, c->stage.p, 3 * sizeof(int), c->stream);
+}
+
 // ---------------------------------------------------------------------------
 // AMG hierarchy (setup)
 // ---------------------------------------------------------------------------
-static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
-    hipStream_t s = c->stream;
-    const int m = A.n;
-    c->s_i1.alloc((size_t)m + 1);
-    c->s_i2.alloc((size_t)m + 2);
-    c->s_i3.alloc((size_t)m + 1);
-    // capacities, their offsets, and (in s_i2[m + 1]) the longest row's product count
-    amg_spgemm_bound(m, A.rp, A.ci, B.rp, c->s_i1.p, c->s_i2.p + m + 1, s);
-    scan_exclusive(c->s_i1.p, c->s_i2.p, m, nullptr, s);
-    int tm[2];
-    read_bytes(tm, c->s_i2.p + m, 2 * sizeof(int), s);
-    const int cap = tm[0], maxprod = tm[1];
+// SpGEMM C = A B in three phases, so that a caller can batch its host reads:
+//   plan:    capacities and their offsets; off[m] = capacity, off[m + 1] =
+//            the longest row's product count (device)
+//   compute: the products into the scratch, row counts, and their scan into
+//            C.rp; C.rp[m] = nnz (device)
+//   finish:  compaction into C once nnz is known
+struct SpgPlan {
+    int m = 0;
+    DBuf<int> ub, off, cnt;
     DBuf<int> hk;
     DBuf<double> hv;
-    hk.alloc((size_t)cap);
-    hv.alloc((size_t)cap);
+};
+
+static void spgemm_plan(Builder *c, const CsrD &A, const CsrD &B, SpgPlan &P) {
+    hipStream_t s = c->stream;
+    const int m = A.n;
+    P.m = m;
+    P.ub.alloc((size_t)m + 1);
+    P.off.alloc((size_t)m + 2);
+    P.cnt.alloc((size_t)m + 1);
+    amg_spgemm_bound(m, A.rp, A.ci, B.rp, P.ub.p, P.off.p + m + 1, s);
+    scan_exclusive(P.ub.p, P.off.p, m, nullptr, s);
+}
+
+static void spgemm_compute(Builder *c, const CsrD &A, const CsrD &B, SpgPlan &P, int cap, int maxprod, CsrD &C) {
+    hipStream_t s = c->stream;
+    const int m = P.m;
+    P.hk.alloc((size_t)cap);
+    P.hv.alloc((size_t)cap);
     // rows short enough for an LDS hash table: one thread per row; longer
     // rows: lane groups that sort the row's products (all kernels give the
     // same sums, bit for bit)
     const int sk = c->opt.setup_kernels;
     if (sk == 2 || (sk == 0 && 2 * maxprod + 1 <= SPGEMM_THREAD_CAP))
-        amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p, c->s_i3.p, s);
+        amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, P.off.p, P.hk.p, P.hv.p, P.cnt.p, s);
     else
-        amg_spgemm_compute_sort(m, B.ncols, maxprod, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, c->s_i2.p, hk.p, hv.p,
-                                c->s_i3.p, s);
+        amg_spgemm_compute_sort(m, B.ncols, maxprod, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, P.off.p, P.hk.p, P.hv.p,
+                                P.cnt.p, s);
     C.n = m;
     C.ncols = B.ncols;
     C.rp_own.alloc((size_t)m + 1);
-    const int nnz = scan_total(c->s_i3.p, C.rp_own.p, m, s);
+    scan_exclusive(P.cnt.p, C.rp_own.p, m, nullptr, s);
+    C.rp = C.rp_own.p;
+}
+
+static void spgemm_finish(Builder *c, SpgPlan &P, int nnz, CsrD &C) {
     C.nnz = nnz;
     C.ci_own.alloc((size_t)nnz);
     C.v.alloc((size_t)nnz);
-    amg_compact(m, c->s_i2.p, hk.p, hv.p, C.rp_own.p, C.ci_own.p, C.v.p, s);
-    C.rp = C.rp_own.p;
+    amg_compact(P.m, P.off.p, P.hk.p, P.hv.p, C.rp_own.p, C.ci_own.p, C.v.p, c->stream);
     C.ci = C.ci_own.p;
+    P.hk.release();
+    P.hv.release();
+}
+
+static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
+    SpgPlan P;
+    spgemm_plan(c, A, B, P);
+    int tm[3];
+    read_ints3(c, P.off.p + A.n, P.off.p + A.n + 1, nullptr, tm);
+    spgemm_compute(c, A, B, P, tm[0], tm[1], C);
+    spgemm_finish(c, P, read_scalar(C.rp_own.p + A.n, c->stream), C);
 }
 
 static void csr_transpose(Builder *c, const CsrD &P, CsrD &R) {
@@ -405,41 +444,46 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
                       c->s_i3.p, s);
         // rounds run in batches between reads of the undecided count (a round
         // on a fully decided level changes nothing)
+        // (small levels take longer batches: their rounds are cheap, and
+        // their coarsening needs more of them)
+        const int batch = (m >= PMIS_SMALL_LEVEL) ? PMIS_BATCH : PMIS_BATCH_SMALL;
         int und = 1, rounds = 0;
         while (und > 0) {
-            for (int q = 0; q < PMIS_BATCH; ++q) {
+            for (int q = 0; q < batch; ++q) {
                 fill_int(c->s_i3.p, 0, 1, s);
                 amg_pmis_round(m, L.A.rp, L.A.ci, L.strong.p, c->s_i1.p, c->s_i2.p, c->s_u1.p, L.cf.p, c->s_c1.p,
                                c->s_i3.p, s);
             }
             und = read_scalar(c->s_i3.p, s);
-            rounds += PMIS_BATCH;
+            rounds += batch;
             if (rounds > 10000) throw Error(CPTR_E_STATE, "PMIS did not terminate");
         }
-        // coarse numbering
+        // coarse numbering and the ext+i capacity bound, read together.  Row
+        // kernels: lane groups sized by the row length, with the rows fetched
+        // into LDS (default), one wavefront per row (1) or one thread per row
+        // (2); all give the same interpolation bit for bit.
         DBuf<int> cidx;
         cidx.alloc((size_t)m + 1);
-        const int nc = scan_total(L.cf.p, cidx.p, m, s);
-        if (nc == 0 || nc == m) break;
-        // extended+i interpolation
+        scan_exclusive(L.cf.p, cidx.p, m, nullptr, s);
         DBuf<int> ub, off, cnt, tcol;
         DBuf<double> twt, td;
         ub.alloc(m + 1);
         off.alloc(m + 1);
         cnt.alloc(m + 1);
-        // row kernels: lane groups sized by the row length, with the rows
-        // fetched into LDS (default), one wavefront per row (1) or one thread
-        // per row (2); all give the same interpolation bit for bit
         const double avg_row = (double)L.A.nnz / (double)m;
         const int ek = o.setup_kernels;
-        const bool thread_rows = (ek == 2);
         amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, ek == 1 || (ek == 0 && avg_row > EXTI_SHORT_ROW),
                        s);
-        const int cap = scan_total(ub.p, off.p, m, s);
+        scan_exclusive(ub.p, off.p, m, nullptr, s);
+        int rd[3];
+        read_ints3(c, cidx.p + m, off.p + m, nullptr, rd);
+        const int nc = rd[0], cap = rd[1];
+        if (nc == 0 || nc == m) break;
+        // extended+i interpolation
         tcol.alloc(cap);
         twt.alloc(cap);
         td.alloc((size_t)L.A.nnz + 1);
-        if (thread_rows)
+        if (ek == 2)
             amg_exti_compute2(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
                               tcol.p, twt.p, td.p, cnt.p, s);
         else if (ek == 1)
@@ -453,19 +497,32 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         P.n = m;
         P.ncols = nc;
         P.rp_own.alloc((size_t)m + 1);
-        P.nnz = scan_total(cnt.p, P.rp_own.p, m, s);
+        scan_exclusive(cnt.p, P.rp_own.p, m, nullptr, s);
+        P.rp = P.rp_own.p;
+        // A P needs only P's row pointers for its plan: P's size and the
+        // product's capacity in one read
+        SpgPlan pAP;
+        spgemm_plan(c, L.A, P, pAP);
+        read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
+        P.nnz = rd[0];
+        const int capAP = rd[1], maxAP = rd[2];
         P.ci_own.alloc((size_t)P.nnz + 1);
         P.v.alloc((size_t)P.nnz + 1);
         amg_compact(m, off.p, tcol.p, twt.p, P.rp_own.p, P.ci_own.p, P.v.p, s);
-        P.rp = P.rp_own.p;
         P.ci = P.ci_own.p;
         L.nc = nc;
         if (mlp && h.L.size() == 1) apply_learned(s, L, mlp);
         csr_transpose(c, P, L.R);
         CsrD AP;
-        csr_spgemm(c, L.A, P, AP);
+        spgemm_compute(c, L.A, P, pAP, capAP, maxAP, AP);
+        // R (A P) needs only A P's row pointers for its plan
+        SpgPlan pRAP;
+        spgemm_plan(c, L.R, AP, pRAP);
+        read_ints3(c, AP.rp_own.p + m, pRAP.off.p + nc, pRAP.off.p + nc + 1, rd);
+        spgemm_finish(c, pAP, rd[0], AP);
         Level nxt;
-        csr_spgemm(c, L.R, AP, nxt.A);
+        spgemm_compute(c, L.R, AP, pRAP, rd[1], rd[2], nxt.A);
+        spgemm_finish(c, pRAP, read_scalar(nxt.A.rp_own.p + nc, s), nxt.A);
         h.L.push_back(std::move(nxt));
     }
     coarse_inverse(c, h);

@@ -125,6 +125,7 @@ struct Hierarchy {
 // ---------------------------------------------------------------------------
 // k_common.hip
 void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t s);   // out[n] = total
+void gather_ints(const int *a, const int *b, const int *c, int *out, hipStream_t s);   // out[0..2]; null -> 0
 void fill_int(int *p, int v, size_t n, hipStream_t s);
 void fill_double(double *p, double v, size_t n, hipStream_t s);
 void check_pattern(int n, const int *rp, const int *ci, int *flag_dev, hipStream_t s);

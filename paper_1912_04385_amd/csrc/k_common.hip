@@ -216,6 +216,20 @@ void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t 
     CPTR_CHECK_LAUNCH();
 }
 
+// up to three device ints side by side, for one host read
+__global__ void k_gather_ints(const int *a, const int *b, const int *c, int *out) {
+    if (threadIdx.x == 0) {
+        out[0] = a ? *a : 0;
+        out[1] = b ? *b : 0;
+        out[2] = c ? *c : 0;
+    }
+}
+
+void gather_ints(const int *a, const int *b, const int *c, int *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_ints, dim3(1), dim3(64), 0, s, a, b, c, out);
+    CPTR_CHECK_LAUNCH();
+}
+
 template <class T>
 __global__ void k_fill(T *p, T v, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
