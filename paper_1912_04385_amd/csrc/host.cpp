@@ -332,19 +332,20 @@ static void coarse_inverse(Builder *c, Hierarchy &h) {
 // FP32 copies of every level's operator, smoother diagonal and transfer operators
 static void hierarchy_fp32(Builder *c, Hierarchy &h) {
     if (c->opt.precond_precision != CPTR_FP32) return;
-    hipStream_t s = c->stream;
+    std::vector<ToFloatJob> jobs;
     for (auto &L : h.L) {
         L.A.v32.alloc((size_t)L.A.nnz + 1);
-        to_float(L.A.v.p, L.A.v32.p, L.A.nnz, s);
+        jobs.push_back({L.A.v.p, L.A.v32.p, (size_t)L.A.nnz});
         L.dinv32.alloc(L.A.n);
-        to_float(L.dinv.p, L.dinv32.p, L.A.n, s);
+        jobs.push_back({L.dinv.p, L.dinv32.p, (size_t)L.A.n});
         if (L.P.nnz) {
             L.P.v32.alloc(L.P.nnz);
-            to_float(L.P.v.p, L.P.v32.p, L.P.nnz, s);
+            jobs.push_back({L.P.v.p, L.P.v32.p, (size_t)L.P.nnz});
             L.R.v32.alloc(L.R.nnz);
-            to_float(L.R.v.p, L.R.v32.p, L.R.nnz, s);
+            jobs.push_back({L.R.v.p, L.R.v32.p, (size_t)L.R.nnz});
         }
     }
+    to_float_multi(jobs.data(), (int)jobs.size(), c->stream);
 }
 
 // Build the hierarchy of a scalar operator whose level-0 pattern is the BSR

@@ -132,6 +132,13 @@ void check_pattern(int n, const int *rp, const int *ci, int *flag_dev, hipStream
 void transpose_index(int n, const int *rp, const int *ci, int *tpos, int *flag_dev, hipStream_t s);
 void count_nonfinite(const double *x, size_t n, int *flag_dev, hipStream_t s);
 void to_float(const double *x, float *y, size_t n, hipStream_t s);
+struct ToFloatJob {
+    const double *src;
+    float *dst;
+    size_t n;
+};
+constexpr int TF_MAX_JOBS = 32;   // jobs per launch of to_float_multi
+void to_float_multi(const ToFloatJob *jobs, int count, hipStream_t s);
 
 // k_decouple.hip
 void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,

@@ -1,6 +1,7 @@
 // Shared device utilities: prefix scan, fills, pattern checks, conversions.
 #include "internal.h"
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -323,6 +324,33 @@ __global__ void k_to_float(const double *x, float *y, size_t n) {
 void to_float(const double *x, float *y, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_to_float, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
     CPTR_CHECK_LAUNCH();
+}
+
+// several conversions in one launch: blockIdx.y selects the job (the jobs
+// travel in the kernel arguments)
+struct ToFloatBatch {
+    ToFloatJob j[TF_MAX_JOBS];
+};
+
+__global__ void k_to_float_multi(ToFloatBatch b) {
+    const ToFloatJob jb = b.j[blockIdx.y];
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t st = (size_t)gridDim.x * blockDim.x;
+    for (; i < jb.n; i += st) jb.dst[i] = (float)jb.src[i];
+}
+
+void to_float_multi(const ToFloatJob *jobs, int count, hipStream_t s) {
+    for (int base = 0; base < count; base += TF_MAX_JOBS) {
+        const int k = std::min(TF_MAX_JOBS, count - base);
+        ToFloatBatch b{};
+        size_t longest = 1;
+        for (int q = 0; q < k; ++q) {
+            b.j[q] = jobs[base + q];
+            longest = std::max(longest, b.j[q].n);
+        }
+        hipLaunchKernelGGL(k_to_float_multi, dim3(grid_for(longest, 256, 4096), k), dim3(256), 0, s, b);
+        CPTR_CHECK_LAUNCH();
+    }
 }
 
 }  // namespace cptr
