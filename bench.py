@@ -35,8 +35,14 @@ def spmv_algorithmic_bytes(n: int, nnzb: int, b: int, s: int = 8) -> int:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the BSR SpMV section of the Krylov kernel source (from its
+    launch constant to the start of the reductions): the counter summary
+    holds only while that code is unchanged."""
     p = os.path.join(ROOT, "paper_1912_04385_amd", "csrc", "k_krylov.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    src = open(p, "rb").read()
+    a = src.index(b"constexpr int SPMV_UNROLL")
+    b = src.index(b"constexpr int KR_THREADS")
+    return hashlib.sha256(src[a:b]).hexdigest()[:16]
 
 
 def load_traffic(nbytes_alg: int):
@@ -116,6 +122,51 @@ def traffic_probe(args, dev) -> int:
     print(json.dumps({"spmv_algorithmic_bytes": nbytes, "copy_bytes_read": copy_bytes,
                       "copy_bytes_written": copy_bytes, "spmv_checksum": float(y.sum()),
                       "kernel_source_hash": kernel_source_hash()}))
+    return 0
+
+
+def solve_probe(args, dev) -> int:
+    """Two FP32-preconditioned setup+solve calls on the config-3 system (Pe
+    0.1) in the benchmark's configuration, then five device-to-device copies
+    of 1 GiB: the run that per-kernel HBM byte counters are read on (the
+    copies calibrate the counters).  Prints the hierarchy sizes that the
+    kernels' algorithmic bytes follow from."""
+    import torch
+    from paper_1912_04385_amd import cptr
+    from synthetic import config3
+
+    s = config3(0, args.nx, args.ny)
+    rp = torch.from_numpy(s.row_ptr).to(dev)
+    ci = torch.from_numpy(s.col_idx).to(dev)
+    vals = torch.from_numpy(s.vals.reshape(-1)).to(dev)
+    rhs = torch.from_numpy(s.rhs).to(dev)
+    meta = dict(n=s.n, nnzb=s.nnzb, b=s.b)
+    del s
+    sol = cptr.Solver(krylov=cptr.FGMRES, restart=50, precond_precision=cptr.FP32, pre_sweeps=args.sweeps,
+                      post_sweeps=args.sweeps, ilu_tile_x=args.tile[0], ilu_tile_y=args.tile[1])
+    its = []
+    for _ in range(2):
+        sol.setup(rp, ci, vals, 0, 1, args.nx, args.ny)
+        x, r = sol.solve(rhs)
+        its.append(r["iterations"])
+    torch.cuda.synchronize()
+    levels = {}
+    for which, name in ((0, "T"), (1, "P")):
+        lv = []
+        for lvl in range(sol.amg_levels(which)):
+            g = sol.amg_level(which, lvl)
+            lv.append(dict(n=int(len(g["rp"]) - 1), nnz=int(g["rp"][-1]),
+                           p_nnz=int(len(g["pci"])) if "pci" in g and g["pci"] is not None else 0))
+        levels[name] = lv
+    sol.close()
+    copy_bytes = 1 << 30
+    src = torch.ones(copy_bytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(meta, iterations=its, levels=levels, copy_bytes_read=copy_bytes,
+                          copy_bytes_written=copy_bytes)))
     return 0
 
 
@@ -295,6 +346,9 @@ def main() -> int:
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the outer SpMV and a plain device copy of known size, 5 times each "
                          "(the run that the HBM byte counters are read on)")
+    ap.add_argument("--solve-probe", action="store_true",
+                    help="two setup+solve calls on the config-3 system, then the calibration copies "
+                         "(the run that per-kernel HBM byte counters are read on)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -311,6 +365,8 @@ def main() -> int:
     dev = torch.device("cuda:0")
     if args.traffic_probe:
         return traffic_probe(args, dev)
+    if args.solve_probe:
+        return solve_probe(args, dev)
     if args.workload == "c5":
         return sequence_bench(args, dev)
     if args.workload == "c4":

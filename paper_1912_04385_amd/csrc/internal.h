@@ -258,6 +258,7 @@ struct TileSched {
     DBuf<int> color;        // per cell
     int nrim[2] = {0, 0};
     DBuf<int> rim[2];       // cells on the perimeter of a tile, per colour
+    DBuf<int> rim_cross[2]; // per rim cell: its entries to the other colour (4 slots, -1 pads)
 };
 void tiles_build(TileSched &ts, int n, int nx, int ny, int tx, int ty, const int *rp, const int *ci, int *flag,
                  hipStream_t st);

@@ -271,20 +271,22 @@ __global__ void __launch_bounds__(BL_THREADS) k_bilu_apply(TileGeom g, int mode,
 // ---------------------------------------------------------------------------
 constexpr int WT_MAX_CELLS = 512;   // 64 KB of LDS at b = 8 in FP64
 
-// u = r - Abar[:,T] xT - Abar[:,P] vP, one thread per scalar row
-template <class T>
-__global__ void k_stage_residual(int n, int b, const int *__restrict__ rp, const int *__restrict__ ci,
+// u = r - Abar[:,T] xT - Abar[:,P] vP, one thread per scalar row (rows of
+// the 5-point pattern: at most 5 entries, loaded before the sum)
+template <class T, int B>
+__global__ void k_stage_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                  const T *__restrict__ slabT, const T *__restrict__ slabP,
                                  const double *__restrict__ rv, const T *__restrict__ xT, const T *__restrict__ vP,
                                  T *__restrict__ u) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)n * b) return;
-    const int i = (int)(t / b), r = (int)(t % b);
+    if (t >= (long)n * B) return;
+    const int i = (int)(t / B), r = (int)(t % B);
     T acc = (T)rv[t];
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int e0 = rp[i], e1 = rp[i + 1];
+    for (int e = e0; e < e1; ++e) {
         const int j = ci[e];
-        if (xT) acc -= slabT[(size_t)e * b + r] * xT[j];
-        if (vP) acc -= slabP[(size_t)e * b + r] * vP[j];
+        if (xT) acc -= slabT[(size_t)e * B + r] * xT[j];
+        if (vP) acc -= slabP[(size_t)e * B + r] * vP[j];
     }
     u[t] = acc;
 }
@@ -295,26 +297,48 @@ __global__ void k_stage_residual(int n, int b, const int *__restrict__ rp, const
 //   mode 0 (before the black sweep): black rows  u_i -= sum_{red j} Abar_ij t_j
 //   mode 1 (before the red backward sweep): red rows  u_i = sum_{black j} Abar_ij w_j
 // (the backward sweep takes 0 for the red cells inside a tile)
-template <class T>
-__global__ void k_cross_tile(int nlist, int b, int mode, const int *__restrict__ cells,
-                             const int *__restrict__ color, const int *__restrict__ rp, const int *__restrict__ ci,
-                             const T *__restrict__ abar, const T *__restrict__ tw, T *__restrict__ u) {
+template <class T, int B>
+__global__ void k_cross_tile(int nlist, int mode, const int *__restrict__ cells, const int4 *__restrict__ cross,
+                             const int *__restrict__ ci, const T *__restrict__ abar, const T *__restrict__ tw,
+                             T *__restrict__ u) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)nlist * b) return;
-    const int i = cells[t / b], r = (int)(t % b);
-    const int ci_ = color[i];
-    const size_t ti = (size_t)i * b + r;
+    if (t >= (long)nlist * B) return;
+    const int k = (int)(t / B), r = (int)(t % B);
+    const int i = cells[k];
+    const int4 ent = cross[k];
+    const int es[4] = {ent.x, ent.y, ent.z, ent.w};
+    const size_t ti = (size_t)i * B + r;
     T acc = (mode == 0) ? u[ti] : (T)0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = es[q];
+        if (e < 0) break;
         const int j = ci[e];
-        if (j == i || color[j] == ci_) continue;
-        const T *Aij = abar + (size_t)e * b * b + (size_t)r * b;
-        const T *vj = tw + (size_t)j * b;
+        const T *Aij = abar + (size_t)e * B * B + (size_t)r * B;
+        const T *vj = tw + (size_t)j * B;
         T d = 0;
-        for (int m = 0; m < b; ++m) d += Aij[m] * vj[m];
+#pragma unroll
+        for (int m = 0; m < B; ++m) d += Aij[m] * vj[m];
         if (mode == 0) acc -= d; else acc += d;
     }
     u[ti] = acc;
+}
+
+// the entries of every listed cell's row that couple it to a tile of the
+// other colour, ascending (at most 4 on the 5-point pattern; -1 pads)
+__global__ void k_cross_entries(int nlist, const int *__restrict__ cells, const int *__restrict__ color,
+                                const int *__restrict__ rp, const int *__restrict__ ci, int4 *__restrict__ cross) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nlist) return;
+    const int i = cells[k];
+    const int ci_ = color[i];
+    int es[4] = {-1, -1, -1, -1};
+    int q = 0;
+    for (int e = rp[i]; e < rp[i + 1] && q < 4; ++e) {
+        const int j = ci[e];
+        if (j != i && color[j] != ci_) es[q++] = e;
+    }
+    cross[k] = make_int4(es[0], es[1], es[2], es[3]);
 }
 
 // In-tile neighbour blocks of every cell, gathered once per setup so that the
@@ -514,7 +538,9 @@ static void bilu_apply_wave(const TileSched &ts, int n, int b, const int *rp, co
                             const double *r, const T *xT, const T *vP, T *u, T *tw, double *y, hipStream_t st) {
     const long nr = (long)n * b;
     const int gr = (int)((nr + 255) / 256);
-    hipLaunchKernelGGL(k_stage_residual<T>, dim3(gr), dim3(256), 0, st, n, b, rp, ci, slabT, slabP, r, xT, vP, u);
+#define CASE(BB) case BB: hipLaunchKernelGGL((k_stage_residual<T, BB>), dim3(gr), dim3(256), 0, st, n, rp, ci, slabT, slabP, r, xT, vP, u); break;
+    switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
     TileGeom g{ts.nx, ts.ny, ts.tx, ts.ty, ts.ntx};
     const size_t lds = (size_t)ts.tx * ts.ty * b * sizeof(T);
     auto launch = [&](int color, int mode) {
@@ -532,8 +558,11 @@ static void bilu_apply_wave(const TileSched &ts, int n, int b, const int *rp, co
             const int color = (mode == 0) ? 1 : 0;
             const long nr_ = (long)ts.nrim[color] * b;
             if (nr_ == 0) return;
-            hipLaunchKernelGGL(k_cross_tile<T>, dim3((unsigned)((nr_ + 255) / 256)), dim3(256), 0, st,
-                               ts.nrim[color], b, mode, ts.rim[color].p, ts.color.p, rp, ci, abar, tw, u);
+            const dim3 grid((unsigned)((nr_ + 255) / 256));
+            const int4 *cross = reinterpret_cast<const int4 *>(ts.rim_cross[color].p);
+#define CASE(BB) case BB: hipLaunchKernelGGL((k_cross_tile<T, BB>), grid, dim3(256), 0, st, ts.nrim[color], mode, ts.rim[color].p, cross, ci, abar, tw, u); break;
+            switch (b) { CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "block size"); }
+#undef CASE
         };
         launch(0, 0);
         cross(0);
@@ -700,6 +729,12 @@ void tiles_build(TileSched &ts, int n, int nx, int ny, int tx, int ty, const int
     ts.color.alloc(n);
     hipLaunchKernelGGL(k_tile_colors, dim3((n + 255) / 256), dim3(256), 0, st, nx, ny, tx, ty, ts.color.p);
     hipLaunchKernelGGL(k_check_5pt, dim3((n + 255) / 256), dim3(256), 0, st, n, nx, rp, ci, flag);
+    for (int c = 0; c < 2; ++c) {
+        ts.rim_cross[c].alloc(4 * ((size_t)ts.nrim[c] + 1));
+        if (ts.nrim[c] > 0)
+            hipLaunchKernelGGL(k_cross_entries, dim3((ts.nrim[c] + 255) / 256), dim3(256), 0, st, ts.nrim[c],
+                               ts.rim[c].p, ts.color.p, rp, ci, reinterpret_cast<int4 *>(ts.rim_cross[c].p));
+    }
     CPTR_HIP(hipStreamSynchronize(st));   // host lists must outlive the copies
     CPTR_CHECK_LAUNCH();
 }

@@ -129,7 +129,7 @@ __device__ inline double block_sum(double v, double *lds) {
 // partial[blk*(k+1) + k] = w . w
 __global__ void __launch_bounds__(KR_THREADS) k_mdot(int N, int k, const double *__restrict__ V, size_t ldv,
                                                      const double *__restrict__ w, double *__restrict__ partial) {
-    __shared__ double lds[KR_THREADS / 64];
+    __shared__ double red[KR_GROUP][KR_THREADS / 64];
     const long chunk = ((long)N + gridDim.x - 1) / gridDim.x;
     const long r0 = (long)blockIdx.x * chunk;
     const long r1 = min((long)N, r0 + chunk);
@@ -146,13 +146,24 @@ __global__ void __launch_bounds__(KR_THREADS) k_mdot(int N, int k, const double 
                 else if (j == k) acc[q] += wr * wr;
             }
         }
+        // the group's block sums together (same order as block_sum: a
+        // shuffle tree per wavefront, then the wavefronts in order)
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-        for (int q = 0; q < KR_GROUP; ++q) {
-            const int j = j0 + q;
-            if (j > k) break;
-            double s = block_sum(acc[q], lds);
-            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (k + 1) + j] = s;
+        for (int q = 0; q < KR_GROUP; ++q)
+            for (int d = 32; d >= 1; d >>= 1) acc[q] += __shfl_xor(acc[q], d, 64);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < KR_GROUP; ++q) red[q][wave] = acc[q];
         }
+        __syncthreads();
+        if ((int)threadIdx.x < KR_GROUP && j0 + (int)threadIdx.x <= k) {
+            const int q = threadIdx.x;
+            double sum = 0.0;
+            for (int w = 0; w < KR_THREADS / 64; ++w) sum += red[q][w];
+            partial[(size_t)blockIdx.x * (k + 1) + j0 + q] = sum;
+        }
+        __syncthreads();   // red is reused by the next group
     }
 }
 
