@@ -283,10 +283,33 @@ __global__ void k_stage_residual(int n, const int *__restrict__ rp, const int *_
     const int i = (int)(t / B), r = (int)(t % B);
     T acc = (T)rv[t];
     const int e0 = rp[i], e1 = rp[i + 1];
-    for (int e = e0; e < e1; ++e) {
-        const int j = ci[e];
-        if (xT) acc -= slabT[(size_t)e * B + r] * xT[j];
-        if (vP) acc -= slabP[(size_t)e * B + r] * vP[j];
+    constexpr int ME = 5;
+    if (e1 - e0 <= ME) {
+        // every operand loaded before the sum, which keeps the row order
+        int js[ME];
+        T a[ME], x[ME], c[ME], y[ME];
+#pragma unroll
+        for (int q = 0; q < ME; ++q) js[q] = (e0 + q < e1) ? ci[e0 + q] : 0;
+#pragma unroll
+        for (int q = 0; q < ME; ++q) {
+            const bool on = e0 + q < e1;
+            a[q] = (on && xT) ? slabT[(size_t)(e0 + q) * B + r] : (T)0;
+            x[q] = (on && xT) ? xT[js[q]] : (T)0;
+            c[q] = (on && vP) ? slabP[(size_t)(e0 + q) * B + r] : (T)0;
+            y[q] = (on && vP) ? vP[js[q]] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < ME; ++q) {
+            if (e0 + q >= e1) break;
+            if (xT) acc -= a[q] * x[q];
+            if (vP) acc -= c[q] * y[q];
+        }
+    } else {
+        for (int e = e0; e < e1; ++e) {
+            const int j = ci[e];
+            if (xT) acc -= slabT[(size_t)e * B + r] * xT[j];
+            if (vP) acc -= slabP[(size_t)e * B + r] * vP[j];
+        }
     }
     u[t] = acc;
 }

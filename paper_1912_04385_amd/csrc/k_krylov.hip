@@ -137,7 +137,27 @@ __global__ void __launch_bounds__(KR_THREADS) k_mdot(int N, int k, const double 
         double acc[KR_GROUP];
 #pragma unroll
         for (int q = 0; q < KR_GROUP; ++q) acc[q] = 0.0;
-        for (long r = r0 + threadIdx.x; r < r1; r += KR_THREADS) {
+        // four rows per pass: their loads are all issued before the sums
+        // (each accumulator still takes the thread's rows in ascending order)
+        long r = r0 + threadIdx.x;
+        for (; r + 3 * KR_THREADS < r1; r += 4 * KR_THREADS) {
+            double wr[4], vr[KR_GROUP][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wr[u] = w[r + u * KR_THREADS];
+#pragma unroll
+            for (int q = 0; q < KR_GROUP; ++q) {
+                const int j = j0 + q;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) vr[q][u] = (j < k) ? V[(size_t)j * ldv + r + u * KR_THREADS] : wr[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int q = 0; q < KR_GROUP; ++q)
+                    if (j0 + q <= k) acc[q] += vr[q][u] * wr[u];
+            }
+        }
+        for (; r < r1; r += KR_THREADS) {
             const double wr = w[r];
 #pragma unroll
             for (int q = 0; q < KR_GROUP; ++q) {
