@@ -227,7 +227,28 @@ __global__ void __launch_bounds__(KR_THREADS) k_update(int N, int k, const doubl
     const long r0 = (long)blockIdx.x * chunk;
     const long r1 = min((long)N, r0 + chunk);
     double nrm = 0.0;
-    for (long r = r0 + threadIdx.x; r < r1; r += KR_THREADS) {
+    // four rows per pass (their loads of each V_j issued together); every
+    // row and the norm keep their order
+    long r = r0 + threadIdx.x;
+    for (; r + 3 * KR_THREADS < r1; r += 4 * KR_THREADS) {
+        double acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = w[r + u * KR_THREADS];
+        for (int j = 0; j < k; ++j) {
+            const double hj = hs[j];
+            double vv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) vv[u] = V[(size_t)j * ldv + r + u * KR_THREADS];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] -= hj * vv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            w[r + u * KR_THREADS] = acc[u];
+            nrm += acc[u] * acc[u];
+        }
+    }
+    for (; r < r1; r += KR_THREADS) {
         double acc = w[r];
         for (int j = 0; j < k; ++j) acc -= hs[j] * V[(size_t)j * ldv + r];
         w[r] = acc;

@@ -34,7 +34,49 @@ __global__ void __launch_bounds__(256) k_csr_op(int n, const int *__restrict__ r
     const int i = (int)(t / G), sub = (int)(t % G);
     const bool act = i < n;
     T acc = 0;
-    if (act) {
+    // single-lane rows of at most ME entries (the fine level): every operand
+    // is loaded before the sum, which then runs in row order as below
+    constexpr int ME = 8;
+    bool done = false;
+    if constexpr (G == 1) {
+        if (act) {
+            const int e0 = rp[i], e1 = rp[i + 1];
+            if (e1 - e0 <= ME) {
+                int js[ME];
+                T vv[ME], o1[ME], o2[ME], o3[ME];
+#pragma unroll
+                for (int q = 0; q < ME; ++q) js[q] = (e0 + q < e1) ? ci[e0 + q] : 0;
+#pragma unroll
+                for (int q = 0; q < ME; ++q) {
+                    const bool on = e0 + q < e1;
+                    const int j = js[q];
+                    vv[q] = on ? v[e0 + q] : (T)0;
+                    if constexpr (OP == OP_PRESMOOTH) {
+                        o1[q] = on ? dinv[j] : (T)0;
+                        o2[q] = on ? b[j] : (T)0;
+                    } else if constexpr (OP == OP_SWEEP_RESID) {
+                        o1[q] = on ? xin[j] : (T)0;
+                        o2[q] = on ? dinv[j] : (T)0;
+                        o3[q] = on ? xs[j] : (T)0;
+                    } else {
+                        o1[q] = on ? xs[j] : (T)0;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < ME; ++q) {
+                    if (e0 + q >= e1) break;
+                    if constexpr (OP == OP_PRESMOOTH)
+                        acc += vv[q] * (omega * o1[q] * o2[q]);
+                    else if constexpr (OP == OP_SWEEP_RESID)
+                        acc += vv[q] * (o1[q] + omega * o2[q] * o3[q]);
+                    else
+                        acc += vv[q] * o1[q];
+                }
+                done = true;
+            }
+        }
+    }
+    if (act && !done) {
         const int e1 = rp[i + 1];
         for (int e = rp[i] + sub; e < e1; e += G) {
             const int j = ci[e];
