@@ -93,8 +93,10 @@ typedef struct {
     int32_t timing;             /* 1: time every stage of every Arnoldi step with */
                                 /*    HIP events on the solve stream              */
     int32_t setup_kernels;      /* AMG setup row kernels: 0 by row length, 1 one  */
-                                /* wavefront per row, 2 one thread per row (the   */
-                                /* hierarchy is bit-identical either way)         */
+                                /* wavefront per row, 2 one thread per row, 3     */
+                                /* 8-lane groups on every level (long rows take   */
+                                /* the sequential path; for tests).  The          */
+                                /* hierarchy is bit-identical either way.         */
 } cptr_options;
 
 typedef struct {

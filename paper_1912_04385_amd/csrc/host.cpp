@@ -461,8 +461,10 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         }
         // coarse numbering and the ext+i capacity bound, read together.  Row
         // kernels: lane groups sized by the row length, with the rows fetched
-        // into LDS (default), one wavefront per row (1) or one thread per row
-        // (2); all give the same interpolation bit for bit.
+        // into LDS (default), one wavefront per row (1), one thread per row
+        // (2), or 8-lane groups on every level (3: rows beyond the groups'
+        // LDS caps take the per-row sequential path); all give the same
+        // interpolation bit for bit.
         DBuf<int> cidx;
         cidx.alloc((size_t)m + 1);
         scan_exclusive(L.cf.p, cidx.p, m, nullptr, s);
@@ -491,9 +493,10 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
             amg_exti_compute_wave(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax,
                                   off.p, tcol.p, twt.p, td.p, cnt.p, s);
         else
-            amg_exti_compute_group(m, avg_row <= EXTI_SHORT_ROW ? 8 : avg_row <= EXTI_HALF_WAVE_ROW ? 32 : 64, L.A.rp,
-                                   L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p, tcol.p,
-                                   twt.p, td.p, cnt.p, s);
+            amg_exti_compute_group(m,
+                                   (ek == 3 || avg_row <= EXTI_SHORT_ROW) ? 8 : avg_row <= EXTI_HALF_WAVE_ROW ? 32 : 64,
+                                   L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
+                                   tcol.p, twt.p, td.p, cnt.p, s);
         CsrD &P = L.P;
         P.n = m;
         P.ncols = nc;
@@ -740,6 +743,7 @@ static void validate_options(const cptr_options &o) {
     if (o.amg_max_coarse < 1 || o.amg_max_levels < 1) throw Error(CPTR_E_ARG, "AMG size limits must be positive");
     if (o.ilu_tile_x < 1 || o.ilu_tile_y < 1) throw Error(CPTR_E_ARG, "ILU tile must be at least 1 x 1");
     if (o.pre_sweeps < 0 || o.post_sweeps < 0) throw Error(CPTR_E_ARG, "negative smoothing sweeps");
+    if (o.setup_kernels < 0 || o.setup_kernels > 3) throw Error(CPTR_E_ARG, "setup_kernels must be 0, 1, 2 or 3");
     if (o.t_interp < CPTR_INTERP_CLASSICAL || o.t_interp > CPTR_INTERP_LEARNED_FORCED)
         throw Error(CPTR_E_ARG, "unknown t_interp");
     if (o.t_interp != CPTR_INTERP_CLASSICAL && (o.amg_pmax < 1 || o.amg_pmax > 16))

@@ -81,7 +81,7 @@ def _compare_hierarchy(solver, h, which):
             assert np.array_equal(g["pv"], L.P.v), f"level {lvl} interpolation weights differ"
 
 
-@pytest.mark.parametrize("kernels", [0, 1, 2])
+@pytest.mark.parametrize("kernels", [0, 1, 2, 3])
 @pytest.mark.parametrize("name,max_coarse,pmax", [("c1", 40, 4), ("tiny48x40b6", 30, 4), ("tiny48x40b6", 30, 0),
                                                   ("tiny64x20b8", 50, 2), ("c2-0", 100, 4)])
 def test_amg_hierarchy_bitwise(name, max_coarse, pmax, kernels):
