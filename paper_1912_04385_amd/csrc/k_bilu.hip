@@ -419,6 +419,7 @@ template <class T, int B>
 struct LevelRegs {
     T a0[B], a1[B], d[B];
     T s, tv;
+    T add;   // backward: the stage-1/2 correction this lane's row of y takes
 };
 
 template <class T, int B>
@@ -466,6 +467,13 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
         for (int c = 0; c < B; ++c) q.d[c] = Di[c];
         q.s = u[(size_t)i * B + r];
         q.tv = tw[(size_t)i * B + r];   // used by the backward-only mode
+        // y = w + x_T (T row) + v_P (P row): prefetched with the level, so
+        // the chain does not wait for these loads
+        q.add = (T)0;
+        if (!fwd) {
+            if (r == it && xT) q.add = xT[i];
+            if (r == ip && vP) q.add = vP[i];
+        }
     };
     LevelRegs<T, B> ring[PF];
 
@@ -538,6 +546,7 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
                 T corr = 0;
 #pragma unroll
                 for (int c = 0; c < B; ++c) corr += ring[k].d[c] * shfl(q, gbase + c);
+                const T add = ring[k].add;
                 load(ring[k], lev - PF, false);
                 __syncthreads();   // every lane has read its W entries before they are overwritten
                 if (own) {
@@ -545,8 +554,7 @@ __global__ void __launch_bounds__(64) k_bilu_wave(TileGeom g, int mode, const in
                     W[loc * B + r] = w;
                     if (mode == 1) tw[(size_t)i * B + r] = w;
                     double yv = (double)w;
-                    if (r == it && xT) yv += (double)xT[i];
-                    if (r == ip && vP) yv += (double)vP[i];
+                    if ((r == it && xT) || (r == ip && vP)) yv += (double)add;
                     y[(size_t)i * B + r] = yv;
                 }
                 __syncthreads();
