@@ -72,18 +72,25 @@ __device__ inline bool beats(int i, int j, const int *cntT, const uint64_t *h) {
 
 constexpr int ST_UND = -1, ST_F = 0, ST_C = 1;
 
+// one atomic per wavefront for a count over its lanes
+__device__ inline void wave_count_add(bool pred, int *counter) {
+    const unsigned long long m = __ballot(pred);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(counter, (int)__popcll(m));
+}
+
 __global__ void k_pmis_init(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                             const unsigned char *__restrict__ s, const int *__restrict__ tpos, uint64_t seed,
                             int *__restrict__ cntT, uint64_t *__restrict__ h, int *__restrict__ state, int *und) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int c = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e)
-        if (ci[e] != i && tpos[e] >= 0 && s[tpos[e]]) c++;   // entry (j, i) strong: i in S_j
-    cntT[i] = c;
-    h[i] = splitmix64(seed, (uint64_t)i);
-    state[i] = (c == 0) ? ST_F : ST_UND;
-    if (c != 0) atomicAdd(und, 1);
+    if (i < n) {
+        for (int e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] != i && tpos[e] >= 0 && s[tpos[e]]) c++;   // entry (j, i) strong: i in S_j
+        cntT[i] = c;
+        h[i] = splitmix64(seed, (uint64_t)i);
+        state[i] = (c == 0) ? ST_F : ST_UND;
+    }
+    wave_count_add(i < n && c != 0, und);
 }
 
 void amg_pmis_init(int n, const int *rp, const int *ci, const unsigned char *s, const int *tpos, uint64_t seed,
@@ -119,13 +126,20 @@ __global__ void k_pmis_select(int n, const int *__restrict__ rp, const int *__re
 __global__ void k_pmis_apply(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                              const unsigned char *__restrict__ s, const unsigned char *__restrict__ newc,
                              int *__restrict__ state, int *und) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (state[i] != ST_UND) return;
-    if (newc[i]) { state[i] = ST_C; return; }
-    for (int e = rp[i]; e < rp[i + 1]; ++e)
-        if (s[e] && newc[ci[e]]) { state[i] = ST_F; return; }
-    atomicAdd(und, 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool still = false;
+    if (i < n && state[i] == ST_UND) {
+        if (newc[i]) {
+            state[i] = ST_C;
+        } else {
+            bool f = false;
+            for (int e = rp[i]; e < rp[i + 1]; ++e)
+                if (s[e] && newc[ci[e]]) { f = true; break; }
+            if (f) state[i] = ST_F;
+            else still = true;
+        }
+    }
+    wave_count_add(still, und);
 }
 
 void amg_pmis_round(int n, const int *rp, const int *ci, const unsigned char *s, const int *tpos, const int *cntT,
@@ -1073,15 +1087,21 @@ void amg_transpose(int nr, int nc, int nnz, const int *rp, const int *ci, const 
 // --------------------------------------------------------------------------
 __global__ void k_spgemm_bound(int m, const int *__restrict__ arp, const int *__restrict__ aci,
                                const int *__restrict__ brp, int *__restrict__ ub, int *maxprod) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int c = 0;
-    for (int e = arp[i]; e < arp[i + 1]; ++e) {
-        int k = aci[e];
-        c += brp[k + 1] - brp[k];
+    if (i < m) {
+        for (int e = arp[i]; e < arp[i + 1]; ++e) {
+            const int k = aci[e];
+            c += brp[k + 1] - brp[k];
+        }
+        ub[i] = 2 * c + 1;      // hash capacity
     }
-    ub[i] = 2 * c + 1;      // hash capacity
-    if (maxprod) atomicMax(maxprod, c);
+    if (maxprod) {
+        // one atomic per wavefront
+        int w = c;
+        for (int d = 32; d >= 1; d >>= 1) w = max(w, __shfl_xor(w, d, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(maxprod, w);
+    }
 }
 
 void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, int *maxprod, hipStream_t st) {
