@@ -190,6 +190,35 @@ cptr_status cptr_decouple(int32_t variant, int32_t n_cells, int32_t b, const int
 cptr_status cptr_bsr_spmv(int32_t n_cells, int32_t b, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                           const double *d_vals, const double *d_x, double *d_y, void *hip_stream);
 
+/* Static condensation of the full Newton system (Sec. "Static-Condensation
+ * Strategy", Eqs. global and reduced): the secondary unknowns couple only
+ * within their cell (J22 block diagonal, J21 cell-local), and
+ *   Q_j = J22_jj^{-1} J21_jj,  q_j = J22_jj^{-1} r2_j           per cell,
+ *   A_ij = J11_ij - J12_ij Q_j,  b_i = -r1_i + sum_j J12_ij q_j  per block,
+ * so A keeps the pattern (d_row_ptr, d_col_idx) of J11.  The per-cell
+ * solves are Gauss-Jordan with partial pivoting.
+ *   n1 primary (1..8) and n2 secondary (0..8) unknowns per cell;
+ *   d_J11: nnzb x n1 x n1 and d_J12: nnzb x n1 x n2, row-major blocks;
+ *   d_J21: n_cells x n2 x n1, d_J22: n_cells x n2 x n2, row-major per cell;
+ *   d_r1: n_cells*n1, d_r2: n_cells*n2 (cell-interleaved).
+ * Writes d_A (nnzb x n1 x n1), d_b (n_cells*n1) and the cell factors d_Q
+ * (n_cells x n2 x n1) and d_q (n_cells*n2) that cptr_recover_secondary
+ * takes; all caller-owned device memory.  Returns after the work is done on
+ * the stream.  CPTR_E_SINGULAR_BLOCK if some J22_jj is singular
+ * (cptr_last_error names the lowest such cell); nothing is written to d_A,
+ * d_b then. */
+cptr_status cptr_condense(int32_t n_cells, int32_t n1, int32_t n2, int32_t nnzb, const int32_t *d_row_ptr,
+                          const int32_t *d_col_idx, const double *d_J11, const double *d_J12,
+                          const double *d_J21, const double *d_J22, const double *d_r1, const double *d_r2,
+                          double *d_A, double *d_b, double *d_Q, double *d_q, void *hip_stream);
+
+/* The secondary Newton update from the primary one (second block row of Eq.
+ * global): d2_j = -q_j - Q_j d1_j, with Q, q from cptr_condense.  d_delta1:
+ * n_cells*n1, d_delta2: n_cells*n2, cell-interleaved.  Asynchronous on the
+ * stream. */
+cptr_status cptr_recover_secondary(int32_t n_cells, int32_t n1, int32_t n2, const double *d_Q, const double *d_q,
+                                   const double *d_delta1, double *d_delta2, void *hip_stream);
+
 /* Number of AMG levels of hierarchy `which` (0 = temperature C_TT, 1 = pressure B_PP). */
 cptr_status cptr_amg_levels(const cptr_ctx *ctx, int32_t which, int32_t *levels);
 

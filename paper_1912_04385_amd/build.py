@@ -24,6 +24,7 @@ SOURCES = {
     "k_vcycle.hip": [],
     "k_bilu.hip": [],
     "k_krylov.hip": [],
+    "k_condense.hip": [],
     "k_learned.hip": ["-ffp-contract=off"],
     "host.cpp": [],
 }

@@ -99,6 +99,8 @@ def lib() -> ctypes.CDLL:
             "cptr_mlp_train_step": [P, P, I32, ctypes.c_uint64, D, ctypes.POINTER(D)],
             "cptr_mlp_edges": [P, P, P, P, I32, ctypes.POINTER(I32)],
             "cptr_mlp_destroy": [P],
+            "cptr_condense": [I32, I32, I32, I32, P, P, P, P, P, P, P, P, P, P, P, P, P],
+            "cptr_recover_secondary": [I32, I32, I32, P, P, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -304,6 +306,34 @@ def bsr_spmv(row_ptr, col_idx, vals, x, b: int):
     y = torch.empty_like(xx)
     _check(lib().cptr_bsr_spmv(rp.numel() - 1, b, _ptr(rp), _ptr(ci), _ptr(v), _ptr(xx), _ptr(y), _stream()))
     return y
+
+
+def condense(row_ptr, col_idx, J11, J12, J21, J22, r1, r2, n1: int, n2: int):
+    """Static condensation of the full Newton system (cptr_condense): returns
+    the reduced blocks A (nnzb*n1*n1), b (n*n1) and the cell factors Q, q."""
+    import torch
+    rp, ci = _dev(row_ptr, torch.int32), _dev(col_idx, torch.int32)
+    n, nnzb = rp.numel() - 1, ci.numel()
+    t = [_dev(x, torch.float64) for x in (J11, J12, J21, J22, r1, r2)]
+    dev = t[0].device
+    A = torch.empty(nnzb * n1 * n1, dtype=torch.float64, device=dev)
+    b = torch.empty(n * n1, dtype=torch.float64, device=dev)
+    Q = torch.empty(max(n * n2 * n1, 1), dtype=torch.float64, device=dev)
+    q = torch.empty(max(n * n2, 1), dtype=torch.float64, device=dev)
+    _check(lib().cptr_condense(n, n1, n2, nnzb, _ptr(rp), _ptr(ci), *[_ptr(x) for x in t], _ptr(A), _ptr(b),
+                               _ptr(Q), _ptr(q), _stream()))
+    return A, b, Q[: n * n2 * n1], q[: n * n2]
+
+
+def recover_secondary(Q, q, delta1, n1: int, n2: int):
+    """d2_j = -q_j - Q_j d1_j (cptr_recover_secondary)."""
+    import torch
+    d1 = _dev(delta1, torch.float64)
+    n = d1.numel() // n1
+    d2 = torch.empty(max(n * n2, 1), dtype=torch.float64, device=d1.device)
+    Qd, qd = _dev(Q, torch.float64), _dev(q, torch.float64)
+    _check(lib().cptr_recover_secondary(n, n1, n2, _ptr(Qd), _ptr(qd), _ptr(d1), _ptr(d2), _stream()))
+    return d2[: n * n2]
 
 
 def solver_for(system, **opts) -> Solver:

@@ -1375,6 +1375,42 @@ cptr_status cptr_bsr_spmv(int32_t n, int32_t b, const int32_t *d_rp, const int32
     CPTR_API_END
 }
 
+cptr_status cptr_condense(int32_t n, int32_t n1, int32_t n2, int32_t nnzb, const int32_t *d_rp, const int32_t *d_ci,
+                          const double *d_J11, const double *d_J12, const double *d_J21, const double *d_J22,
+                          const double *d_r1, const double *d_r2, double *d_A, double *d_b, double *d_Q,
+                          double *d_q, void *stream) {
+    CPTR_API_BEGIN
+    if (n < 0 || nnzb < n || n1 < 1 || n1 > 8 || n2 < 0 || n2 > 8)
+        throw Error(CPTR_E_ARG, "sizes: n1 must be 1..8, n2 0..8, nnzb >= n_cells");
+    if (n == 0) return CPTR_OK;
+    if (!d_rp || !d_ci || !d_J11 || !d_r1 || !d_A || !d_b) throw Error(CPTR_E_ARG, "null pointer");
+    if (n2 > 0 && (!d_J12 || !d_J21 || !d_J22 || !d_r2 || !d_Q || !d_q)) throw Error(CPTR_E_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope scope(s);
+    DBuf<int> flag;
+    flag.alloc(1);
+    fill_int(flag.p, 0x7fffffff, 1, s);
+    launch_condense_cells(n, n1, n2, d_J21, d_J22, d_r2, d_Q, d_q, flag.p, s);
+    const int bad = read_scalar(flag.p, s);
+    if (bad != 0x7fffffff)
+        throw Error(CPTR_E_SINGULAR_BLOCK, "singular secondary block J22 in cell " + std::to_string(bad));
+    launch_condense_blocks(n, n1, n2, d_rp, d_ci, d_J11, d_J12, d_Q, d_q, d_r1, d_A, d_b, s);
+    CPTR_HIP(hipStreamSynchronize(s));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_recover_secondary(int32_t n, int32_t n1, int32_t n2, const double *d_Q, const double *d_q,
+                                   const double *d_d1, double *d_d2, void *stream) {
+    CPTR_API_BEGIN
+    if (n < 0 || n1 < 1 || n1 > 8 || n2 < 0 || n2 > 8) throw Error(CPTR_E_ARG, "sizes: n1 must be 1..8, n2 0..8");
+    if (n == 0 || n2 == 0) return CPTR_OK;
+    if (!d_Q || !d_q || !d_d1 || !d_d2) throw Error(CPTR_E_ARG, "null pointer");
+    launch_condense_recover(n, n1, n2, d_Q, d_q, d_d1, d_d2, (hipStream_t)stream);
+    return CPTR_OK;
+    CPTR_API_END
+}
+
 static Hierarchy &pick(const cptr_ctx *c, int which) {
     if (!c || !c->ready) throw Error(CPTR_E_STATE, "context not set up");
     if (which < 0 || which > 1) throw Error(CPTR_E_ARG, "which must be 0 (T) or 1 (P)");

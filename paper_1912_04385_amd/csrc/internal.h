@@ -250,6 +250,15 @@ void ln_grad_reduce(int nw, const float *part, float *grad, hipStream_t s);
 void ln_adam(float *p, float *m, float *v, const float *g, double lr, double b1, double b2, double eps, int t,
              hipStream_t s);
 
+// k_condense.hip: static condensation of the full Newton system
+void launch_condense_cells(int n, int n1, int n2, const double *J21, const double *J22, const double *r2, double *Q,
+                           double *q, int *flag, hipStream_t st);
+void launch_condense_blocks(int n, int n1, int n2, const int *rp, const int *ci, const double *J11, const double *J12,
+                            const double *Q, const double *q, const double *r1, double *A, double *b,
+                            hipStream_t st);
+void launch_condense_recover(int n, int n1, int n2, const double *Q, const double *q, const double *d1, double *d2,
+                             hipStream_t st);
+
 // k_bilu.hip: BILU(0) in tile order / block Jacobi
 struct TileSched {
     int nx = 0, ny = 0, tx = 0, ty = 0, ntx = 0, nty = 0;

@@ -1,0 +1,157 @@
+// Static condensation of the full Newton system (Sec. "Static-Condensation
+// Strategy", Eqs. global and reduced): the secondary unknowns couple only
+// within their cell, so J22 is block diagonal and J21 cell-local, and
+//   Q_j = J22_jj^{-1} J21_jj,   q_j = J22_jj^{-1} r2_j              (per cell)
+//   A_ij = J11_ij - J12_ij Q_j,   b_i = -r1_i + sum_j J12_ij q_j     (per block)
+//   d2_j = -q_j - Q_j d1_j                                          (recovery)
+// The reduced system keeps the pattern of J11.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace cptr {
+
+// Per cell, one group of 8 lanes: lane r < n2 holds row r of the augmented
+// block [J22_jj | J21_jj (8 columns, zero beyond n1) | r2_j] in registers.  Gauss-Jordan with partial
+// pivoting without row exchanges (a row that served as pivot is marked), the
+// pivot row broadcast by shuffles; the row that pivoted column k then holds
+// row k of the solution, scaled by its pivot.  flag: lowest singular cell.
+constexpr int CD_G = 8;
+
+template <int N2>
+__global__ void __launch_bounds__(256) k_condense_cells(int n, int n1, const double *__restrict__ J21,
+                                                        const double *__restrict__ J22,
+                                                        const double *__restrict__ r2, double *__restrict__ Q,
+                                                        double *__restrict__ q, int *flag) {
+    constexpr int NC = N2 + 9;   // J22 columns, 8 for J21, r2 last
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = (int)(t / CD_G), r = (int)(t % CD_G);
+    const int gbase = (threadIdx.x & 63) - r;
+    const bool act = j < n;
+    const bool own = act && r < N2;
+    double row[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) row[c] = 0.0;
+    if (own) {
+#pragma unroll
+        for (int c = 0; c < N2; ++c) row[c] = J22[((size_t)j * N2 + r) * N2 + c];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < n1) row[N2 + c] = J21[((size_t)j * N2 + r) * n1 + c];
+        row[NC - 1] = r2[(size_t)j * N2 + r];
+    }
+    bool used = !own;
+    int myk = -1;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+        // pivot: the first unused row with the largest |row[k]|
+        const double mine = used ? -1.0 : fabs(row[k]);
+        double best = -2.0;
+        int who = 0;
+#pragma unroll
+        for (int s = 0; s < N2; ++s) {
+            const double o = __shfl(mine, gbase + s, 64);
+            if (o > best) { best = o; who = s; }
+        }
+        if (best <= 0.0) bad = true;
+        double prow[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) prow[c] = __shfl(row[c], gbase + who, 64);
+        if (own && !bad) {
+            if (r == who) {
+                used = true;
+                myk = k;
+            } else {
+                const double f = row[k] / prow[k];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    if (c > k) row[c] -= f * prow[c];
+                row[k] = 0.0;
+            }
+        }
+    }
+    if (!act) return;
+    if (bad) {
+        if (r == 0) atomicMin(flag, j);
+        return;
+    }
+    if (own) {
+        const double d = row[myk];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < n1) Q[((size_t)j * N2 + myk) * n1 + c] = row[N2 + c] / d;
+        q[(size_t)j * N2 + myk] = row[NC - 1] / d;
+    }
+}
+
+// Per block row, one wavefront: lane (r, c) of the n1 x n1 block forms
+// A_ij[r][c] = J11_ij[r][c] - sum_k J12_ij[r][k] Q_j[k][c] for every block of
+// the row; lanes with c = 0 also sum b_i[r] over the row's blocks in order.
+__global__ void __launch_bounds__(64) k_condense_blocks(int n, int n1, int n2, const int *__restrict__ rp,
+                                                        const int *__restrict__ ci, const double *__restrict__ J11,
+                                                        const double *__restrict__ J12,
+                                                        const double *__restrict__ Q, const double *__restrict__ q,
+                                                        const double *__restrict__ r1, double *__restrict__ A,
+                                                        double *__restrict__ b) {
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (i >= n || lane >= n1 * n1) return;
+    const int r = lane / n1, c = lane % n1;
+    double acc = -r1[(size_t)i * n1 + r];
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        const double *J12r = J12 + ((size_t)e * n1 + r) * n2;
+        const double *Qj = Q + (size_t)j * n2 * n1;
+        double a = J11[((size_t)e * n1 + r) * n1 + c];
+        double t = 0.0;
+        for (int k = 0; k < n2; ++k) {
+            a -= J12r[k] * Qj[k * n1 + c];
+            if (c == 0) t += J12r[k] * q[(size_t)j * n2 + k];
+        }
+        A[((size_t)e * n1 + r) * n1 + c] = a;
+        acc += t;
+    }
+    if (c == 0) b[(size_t)i * n1 + r] = acc;
+}
+
+// d2_j[k] = -q_j[k] - sum_c Q_j[k][c] d1_j[c], one thread per secondary unknown
+__global__ void k_condense_recover(int n, int n1, int n2, const double *__restrict__ Q,
+                                   const double *__restrict__ q, const double *__restrict__ d1,
+                                   double *__restrict__ d2) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n * n2) return;
+    const int j = (int)(t / n2), k = (int)(t % n2);
+    const double *Qk = Q + ((size_t)j * n2 + k) * n1;
+    double s = -q[t];
+    for (int c = 0; c < n1; ++c) s -= Qk[c] * d1[(size_t)j * n1 + c];
+    d2[t] = s;
+}
+
+void launch_condense_cells(int n, int n1, int n2, const double *J21, const double *J22, const double *r2, double *Q,
+                           double *q, int *flag, hipStream_t st) {
+    if (n == 0 || n2 == 0) return;
+    const dim3 grid((unsigned)(((long)n * CD_G + 255) / 256));
+#define CASE(NN) case NN: hipLaunchKernelGGL(k_condense_cells<NN>, grid, dim3(256), 0, st, n, n1, J21, J22, r2, Q, q, flag); break;
+    switch (n2) { CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "n2 must be 0..8"); }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+void launch_condense_blocks(int n, int n1, int n2, const int *rp, const int *ci, const double *J11, const double *J12,
+                            const double *Q, const double *q, const double *r1, double *A, double *b,
+                            hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_condense_blocks, dim3(n), dim3(64), 0, st, n, n1, n2, rp, ci, J11, J12, Q, q, r1, A, b);
+    CPTR_CHECK_LAUNCH();
+}
+
+void launch_condense_recover(int n, int n1, int n2, const double *Q, const double *q, const double *d1, double *d2,
+                             hipStream_t st) {
+    if (n == 0 || n2 == 0) return;
+    hipLaunchKernelGGL(k_condense_recover, dim3((unsigned)(((long)n * n2 + 255) / 256)), dim3(256), 0, st, n, n1, n2,
+                       Q, q, d1, d2);
+    CPTR_CHECK_LAUNCH();
+}
+
+}  // namespace cptr
