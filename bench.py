@@ -125,6 +125,49 @@ def traffic_probe(args, dev) -> int:
     return 0
 
 
+def front_end_bench(args, dev, n2: int = 4, reps: int = 5) -> dict:
+    """The static-condensation front end on the config-3 grid with n2
+    secondary unknowns per cell (not part of the headline value): the
+    Schur complement and right-hand side, then the secondary recovery, timed
+    with HIP events on the current stream (inputs resident in HBM)."""
+    import numpy as np
+    import torch
+    from paper_1912_04385_amd import cptr
+    from synthetic import config3, full_system
+
+    fs = full_system(config3(0, args.nx, args.ny), n2, seed=0)
+    n, n1, nnzb = fs.n, fs.n1, fs.nnzb
+    t = {k: torch.from_numpy(np.ascontiguousarray(v).reshape(-1)).to(dev)
+         for k, v in dict(rp=fs.row_ptr, ci=fs.col_idx, J11=fs.J11, J12=fs.J12, J21=fs.J21, J22=fs.J22,
+                          r1=fs.r1, r2=fs.r2).items()}
+    del fs
+    d1 = torch.rand(n * n1, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ms_c, ms_r = [], []
+    for k in range(reps + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        A, b, Q, q = cptr.condense(t["rp"], t["ci"], t["J11"], t["J12"], t["J21"], t["J22"], t["r1"], t["r2"], n1, n2)
+        e1.record()
+        cptr.recover_secondary(Q, q, d1, n1, n2)
+        e2.record()
+        torch.cuda.synchronize()
+        if k > 0:
+            ms_c.append(e0.elapsed_time(e1))
+            ms_r.append(e1.elapsed_time(e2))
+    s = 8
+    read = (nnzb * n1 * n1 + nnzb * n1 * n2 + n * n2 * n1 + n * n2 * n2 + n * n1 + n * n2) * s \
+        + (n * n2 * n1 + n * n2) * s + (nnzb + n + 1) * 4
+    write = (nnzb * n1 * n1 + n * n1 + n * n2 * n1 + n * n2) * s
+    mc = float(np.median(ms_c))
+    return {"workload": f"config-3 grid, full Newton system with n1 = {n1} primary and n2 = {n2} secondary "
+                        f"unknowns per cell (synthetic)",
+            "condense_ms": round(mc, 3), "recover_ms": round(float(np.median(ms_r)), 3),
+            "condense_algorithmic_bytes": int(read + write),
+            "condense_GBps": round((read + write) / (mc * 1e-3) / 1e9, 1),
+            "condense_frac_of_hbm_peak": round((read + write) / (mc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def solve_probe(args, dev) -> int:
     """Two FP32-preconditioned setup+solve calls on the config-3 system (Pe
     0.1) in the benchmark's configuration, then five device-to-device copies
@@ -346,6 +389,8 @@ def main() -> int:
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the outer SpMV and a plain device copy of known size, 5 times each "
                          "(the run that the HBM byte counters are read on)")
+    ap.add_argument("--no-front-end", action="store_true",
+                    help="skip timing the static-condensation front end")
     ap.add_argument("--solve-probe", action="store_true",
                     help="two setup+solve calls on the config-3 system, then the calibration copies "
                          "(the run that per-kernel HBM byte counters are read on)")
@@ -466,6 +511,8 @@ def main() -> int:
                              "setup_ms": [round(r["setup_ms"], 2) for r in res64],
                              "solve_ms": [round(r["solve_ms"], 2) for r in res64]}
         out["speedup_vs_fp64"] = round(ms64 / ms32, 4)
+    if not args.no_front_end:
+        out["front_end"] = front_end_bench(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, tuple(args.tile), args.sweeps)
     else:
