@@ -86,31 +86,53 @@ __global__ void __launch_bounds__(256) k_condense_cells(int n, int n1, const dou
 }
 
 // Per block row, one wavefront: lane (r, c) of the n1 x n1 block forms
-// A_ij[r][c] = J11_ij[r][c] - sum_k J12_ij[r][k] Q_j[k][c] for every block of
-// the row; lanes with c = 0 also sum b_i[r] over the row's blocks in order.
-__global__ void __launch_bounds__(64) k_condense_blocks(int n, int n1, int n2, const int *__restrict__ rp,
+// A_ij[r][c] = J11_ij[r][c] - sum_k J12_ij[r][k] Q_j[k][c] (k ascending) for
+// every block of the row; lanes with c = 0 also sum b_i[r] over the row's
+// blocks in order.  The blocks are taken CH at a time with all their
+// operands loaded before the sums.
+template <int N2>
+__global__ void __launch_bounds__(64) k_condense_blocks(int n, int n1, const int *__restrict__ rp,
                                                         const int *__restrict__ ci, const double *__restrict__ J11,
                                                         const double *__restrict__ J12,
                                                         const double *__restrict__ Q, const double *__restrict__ q,
                                                         const double *__restrict__ r1, double *__restrict__ A,
                                                         double *__restrict__ b) {
+    constexpr int CH = (N2 <= 2) ? 6 : (N2 <= 4 ? 4 : 2);
     const int i = blockIdx.x;
     const int lane = threadIdx.x;
     if (i >= n || lane >= n1 * n1) return;
     const int r = lane / n1, c = lane % n1;
     double acc = -r1[(size_t)i * n1 + r];
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        const int j = ci[e];
-        const double *J12r = J12 + ((size_t)e * n1 + r) * n2;
-        const double *Qj = Q + (size_t)j * n2 * n1;
-        double a = J11[((size_t)e * n1 + r) * n1 + c];
-        double t = 0.0;
-        for (int k = 0; k < n2; ++k) {
-            a -= J12r[k] * Qj[k * n1 + c];
-            if (c == 0) t += J12r[k] * q[(size_t)j * n2 + k];
+    const int e0 = rp[i], e1 = rp[i + 1];
+    for (int base = e0; base < e1; base += CH) {
+        int js[CH];
+        double a[CH], x[CH][N2 > 0 ? N2 : 1], y[CH][N2 > 0 ? N2 : 1], z[CH][N2 > 0 ? N2 : 1];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) js[u] = (base + u < e1) ? ci[base + u] : 0;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const bool on = base + u < e1;
+            const size_t e = (size_t)(base + u);
+            a[u] = on ? J11[(e * n1 + r) * n1 + c] : 0.0;
+#pragma unroll
+            for (int k = 0; k < N2; ++k) {
+                x[u][k] = on ? J12[(e * n1 + r) * N2 + k] : 0.0;
+                y[u][k] = on ? Q[((size_t)js[u] * N2 + k) * n1 + c] : 0.0;
+                z[u][k] = (on && c == 0) ? q[(size_t)js[u] * N2 + k] : 0.0;
+            }
         }
-        A[((size_t)e * n1 + r) * n1 + c] = a;
-        acc += t;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (base + u >= e1) break;
+            double v = a[u], t = 0.0;
+#pragma unroll
+            for (int k = 0; k < N2; ++k) {
+                v -= x[u][k] * y[u][k];
+                t += x[u][k] * z[u][k];
+            }
+            A[((size_t)(base + u) * n1 + r) * n1 + c] = v;
+            acc += t;
+        }
     }
     if (c == 0) b[(size_t)i * n1 + r] = acc;
 }
@@ -142,7 +164,9 @@ void launch_condense_blocks(int n, int n1, int n2, const int *rp, const int *ci,
                             const double *Q, const double *q, const double *r1, double *A, double *b,
                             hipStream_t st) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_condense_blocks, dim3(n), dim3(64), 0, st, n, n1, n2, rp, ci, J11, J12, Q, q, r1, A, b);
+#define CASE(NN) case NN: hipLaunchKernelGGL(k_condense_blocks<NN>, dim3(n), dim3(64), 0, st, n, n1, rp, ci, J11, J12, Q, q, r1, A, b); break;
+    switch (n2) { CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "n2 must be 0..8"); }
+#undef CASE
     CPTR_CHECK_LAUNCH();
 }
 
