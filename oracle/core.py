@@ -346,6 +346,121 @@ def amg_setup(A: CSR, opts: AMGOptions | None = None, interp_fn=None) -> Hierarc
     return _finish_hierarchy(levels, opts)
 
 
+# ---------------------------------------------------------------------------
+# unknown-based system AMG for the 2x2 elliptic block B_ee of the two-stage
+# CPTR scheme (Sec. "Two-stage Constrained Pressure-Temperature Residual";
+# the system-AMG direction of the conclusions)
+# ---------------------------------------------------------------------------
+
+def elliptic_system(Abar: BSR, ip: int = 0, it: int = 1) -> CSR:
+    """B_ee = [[B_PP, B_PT], [B_TP, B_TT]] of the scaled matrix as one scalar
+    CSR of 2n rows, unknowns ordered [P of every cell; T of every cell]; a
+    row holds its P-block columns, then its T-block columns (shifted by n)."""
+    n = Abar.n
+    rp, ci = Abar.rp.astype(np.int64), Abar.ci.astype(np.int64)
+    cnt = np.diff(rp)
+    srp = np.concatenate([[0], np.cumsum(np.concatenate([2 * cnt, 2 * cnt]))])
+    nnzb = ci.size
+    rows = np.repeat(np.arange(n), cnt)
+    t = np.arange(nnzb) - rp[rows]
+    sci = np.empty(4 * nnzb, np.int64)
+    sv = np.empty(4 * nnzb)
+    for u, ru in enumerate((ip, it)):
+        base = srp[u * n + rows]
+        sci[base + t] = ci
+        sv[base + t] = Abar.vals[:, ru, ip]
+        sci[base + cnt[rows] + t] = ci + n
+        sv[base + cnt[rows] + t] = Abar.vals[:, ru, it]
+    return CSR(2 * n, 2 * n, _i32(srp), _i32(sci), sv)
+
+
+def submatrix(A: CSR, o: int, m: int) -> CSR:
+    """Rows and columns [o, o + m) of A, columns shifted by -o (order kept)."""
+    a, b_ = int(A.rp[o]), int(A.rp[o + m])
+    rows = np.repeat(np.arange(m), np.diff(A.rp[o:o + m + 1]))
+    c = A.ci[a:b_]
+    keep = (c >= o) & (c < o + m)
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=m))])
+    return CSR(m, m, _i32(rp), _i32(c[keep] - o), _f64(A.v[a:b_][keep]))
+
+
+def block_diagonal(Ps: list) -> CSR:
+    """blockdiag(P_0, P_1, ...): rows and columns of each block after the previous ones."""
+    rp = [np.zeros(1, np.int64)]
+    ci, v = [], []
+    r0 = c0 = nz = 0
+    for P in Ps:
+        rp.append(P.rp[1:].astype(np.int64) + nz)
+        ci.append(P.ci.astype(np.int64) + c0)
+        v.append(P.v)
+        nz += P.nnz
+        r0 += P.nrows
+        c0 += P.ncols
+    return CSR(r0, c0, _i32(np.concatenate(rp)), _i32(np.concatenate(ci)), _f64(np.concatenate(v)))
+
+
+def amg_setup_system(A: CSR, parts: list, opts: AMGOptions | None = None) -> Hierarchy:
+    """Unknown-based AMG: A holds len(parts) unknowns in consecutive row
+    ranges.  On every level each unknown's diagonal block is coarsened on its
+    own (strength, PMIS and extended+i with truncation as in amg_setup, the
+    PMIS measure indexed within the block), P = blockdiag(P_u), R = P^T and
+    A_c = R A P keeps every coupling between the unknowns.  Coarsening stops
+    when the level has at most ``max_coarse`` rows, at ``max_levels``, or when
+    some unknown's block stalls (no C point, or no F point); the coarsest
+    level is factored densely."""
+    opts = opts or AMGOptions()
+    levels = []
+    cur = A
+    parts = list(parts)
+    while True:
+        L = Level(cur, cur.diagonal())
+        levels.append(L)
+        if cur.nrows <= opts.max_coarse or len(levels) >= opts.max_levels:
+            break
+        Ps, cfs, ss, ncs = [], [], [], []
+        o = 0
+        stalled = False
+        for m in parts:
+            Au = submatrix(cur, o, m)
+            s = strength(Au, opts.theta)
+            cf, _ = pmis(Au, s, opts.seed)
+            nc = int(cf.sum())
+            if nc == 0 or nc == m:
+                stalled = True
+                break
+            Ps.append(interp_exti(Au, s, cf, opts.pmax))
+            cfs.append(cf)
+            ss.append(s)
+            ncs.append(nc)
+            o += m
+        if stalled:
+            break
+        P = block_diagonal(Ps)
+        R = P.transpose()
+        L.P, L.R, L.cf = P, R, np.concatenate(cfs)
+        L.strong = ss
+        cur = galerkin(cur, P, R)
+        parts = ncs
+    return _finish_hierarchy(levels, opts)
+
+
+class SystemStage:
+    """M_ee^{-1} of the two-stage CPTR scheme (Eq. CPTRM1 with the elliptic
+    block): gather the P and T components of every cell into [r_P; r_T],
+    apply ``solve`` to B_ee, scatter back with zeros elsewhere."""
+
+    def __init__(self, n: int, b: int, ip: int, it: int, solve):
+        self.n, self.b, self.ip, self.it, self.solve = n, b, ip, it, solve
+
+    def __call__(self, r: np.ndarray) -> np.ndarray:
+        n, b = self.n, self.b
+        x = self.solve(np.concatenate([r[self.ip::b], r[self.it::b]]))
+        y = np.zeros(n * b)
+        y[self.ip::b] = x[:n]
+        y[self.it::b] = x[n:]
+        return y
+
+
 def _finish_hierarchy(levels: list, opts: AMGOptions) -> Hierarchy:
     """Smoother data of every level but the last; dense LU of the last."""
     for L in levels[:-1]:
@@ -730,7 +845,8 @@ def build_preconditioner(dec: Decoupled, opts: Options, previous: dict | None = 
     """The stages of the chosen variant on Abar, in the paper's order:
     CPTR3: M1 = amg(C_TT), M2 = amg(B_PP), M3 = ilu(Abar) (Eqs. CPTR3M1,
     CPTRM2, CPTR3M3); CPR: M1 = amg(B_PP), M2 = ilu(Abar) (Eqs. CPRM1 ff.);
-    BJ_ONLY: the last stage alone.  Returns (apply, stages, hierarchies).
+    CPTR: M1 = unknown-based system amg(B_ee), M2 = ilu(Abar) (two-stage
+    CPTR, Algorithm 1); BJ_ONLY: the last stage alone.  Returns (apply, stages, hierarchies).
 
     ``previous`` (name -> Hierarchy of the previous system of a sequence)
     switches on reuse: each scalar stage first refreshes the previous
@@ -810,8 +926,18 @@ def build_preconditioner(dec: Decoupled, opts: Options, previous: dict | None = 
         sT = ScalarStage(n, b, it, scalar_solver("T", it))
         sP = ScalarStage(n, b, ip, scalar_solver("P", ip))
         stages = [sT, sP] if opts.stage_order == T_THEN_P else [sP, sT]
-    elif opts.variant in (CPR, CPTR):
+    elif opts.variant == CPR:
         stages = [ScalarStage(n, b, ip, scalar_solver("P", ip))]
+    elif opts.variant == CPTR:
+        # two stages: system AMG on B_ee, then the last stage
+        B = elliptic_system(Abar, ip, it)
+        if opts.exact_subsolves:
+            ee = _Direct(B)
+        else:
+            h = amg_setup_system(B, [n, n], opts.amg)
+            hier["ee"] = h
+            ee = lambda rr, h=h: vcycle(h, rr)  # noqa: E731
+        stages = [SystemStage(n, b, ip, it, ee)]
     stages.append(last)
     return (lambda r: multistage_apply(Abar, stages, r)), stages, hier
 
