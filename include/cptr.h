@@ -54,8 +54,19 @@ typedef enum {
     CPTR_E_STATE = -6            /* call out of order (e.g. solve before setup) */
 } cptr_status;
 
-/* preconditioner variants (Sec. "Multi-Stage Preconditioning") */
-enum { CPTR_VARIANT_CPTR3 = 0, CPTR_VARIANT_CPR = 1, CPTR_VARIANT_LAST_ONLY = 3 };
+/* preconditioner variants (Sec. "Multi-Stage Preconditioning"):
+ *   CPTR3: three stages, AMG on C_TT, AMG on B_PP, last stage (Algorithm 2);
+ *   CPR: AMG on B_PP, last stage (Algorithm 1);
+ *   CPTR: two-stage CPTR (Sec. "Two-stage Constrained Pressure-Temperature
+ *     Residual", Algorithm 1): the first scaling of the decoupling alone
+ *     (beta = 0), one unknown-based system AMG V-cycle on the 2x2 elliptic
+ *     block B_ee = [[B_PP, B_PT], [B_TP, B_TT]] -- each unknown's diagonal
+ *     block coarsened on its own, P = blockdiag(P_P, P_T), R = P^T, full
+ *     Galerkin products -- then the last stage.  Its system hierarchy is
+ *     hierarchy index 0 of the cptr_amg_* inspection calls, with rows ordered
+ *     [P of every cell; T of every cell]; levels_T reports its depth;
+ *   LAST_ONLY: the last stage alone. */
+enum { CPTR_VARIANT_CPTR3 = 0, CPTR_VARIANT_CPR = 1, CPTR_VARIANT_CPTR = 2, CPTR_VARIANT_LAST_ONLY = 3 };
 /* order of the two scalar AMG stages of CPTR3: temperature first as in
  * Eqs. CPTR3M1 / CPTRM2, or pressure first */
 enum { CPTR_T_THEN_P = 0, CPTR_P_THEN_T = 1 };
@@ -179,8 +190,9 @@ cptr_status cptr_destroy(cptr_ctx *ctx);
 /* All pointers are device memory unless stated otherwise.                  */
 /* ---------------------------------------------------------------------- */
 
-/* The left scaling of Eqs. CPTR31/CPTR32 (variant CPTR3) or Eq. CPR (variant
- * CPR) on a BSR matrix and rhs: writes d_abar (nnzb*b*b) and d_rhsbar. */
+/* The left scaling of Eqs. CPTR31/CPTR32 (variant CPTR3), Eq. CPR (variant
+ * CPR) or the first scaling alone (variant CPTR) on a BSR matrix and rhs:
+ * writes d_abar (nnzb*b*b) and d_rhsbar. */
 cptr_status cptr_decouple(int32_t variant, int32_t n_cells, int32_t b, const int32_t *d_row_ptr,
                           const int32_t *d_col_idx, const double *d_vals, const double *d_rhs,
                           int32_t p_index, int32_t T_index, double *d_abar, double *d_rhsbar,
@@ -219,7 +231,8 @@ cptr_status cptr_condense(int32_t n_cells, int32_t n1, int32_t n2, int32_t nnzb,
 cptr_status cptr_recover_secondary(int32_t n_cells, int32_t n1, int32_t n2, const double *d_Q, const double *d_q,
                                    const double *d_delta1, double *d_delta2, void *hip_stream);
 
-/* Number of AMG levels of hierarchy `which` (0 = temperature C_TT, 1 = pressure B_PP). */
+/* Number of AMG levels of hierarchy `which` (0 = temperature C_TT, 1 = pressure
+ * B_PP; with variant CPTR, 0 = the system hierarchy of B_ee). */
 cptr_status cptr_amg_levels(const cptr_ctx *ctx, int32_t which, int32_t *levels);
 
 /* Sizes of level `level`: rows and nnz of the operator, nnz of P (0 on the coarsest). */

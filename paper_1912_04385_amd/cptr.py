@@ -15,7 +15,7 @@ import weakref
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcptr.so")
 
-VARIANT_CPTR3, VARIANT_CPR, VARIANT_LAST_ONLY = 0, 1, 3
+VARIANT_CPTR3, VARIANT_CPR, VARIANT_CPTR, VARIANT_LAST_ONLY = 0, 1, 2, 3
 T_THEN_P, P_THEN_T = 0, 1
 LAST_BILU0, LAST_BJACOBI = 0, 1
 GMRES, FGMRES = 0, 1

@@ -48,6 +48,9 @@ struct Builder {
     DBuf<double> s_d1;
     DBuf<uint64_t> s_u1;
     DBuf<unsigned char> s_c1;
+    // unknown-based system AMG: the row counts of the unknowns, in row order
+    // (empty for a scalar operator)
+    std::vector<int> parts;
 };
 
 
@@ -77,6 +80,10 @@ struct cptr_ctx {
     // scalar stages: 0 = temperature (C_TT), 1 = pressure (B_PP)
     Hierarchy H[2];
     DBuf<double> ctt, bpp;          // level-0 values of the two scalar operators
+    // two-stage CPTR: the elliptic block B_ee (2n rows [P; T]); its system
+    // hierarchy takes slot 0 of H
+    DBuf<int> ee_rp, ee_ci;
+    DBuf<double> ee_v;
     double rho[2] = {-1.0, -1.0};   // V-cycle convergence factors measured by update_values
     int reused = 0;                 // bit k: hierarchy k was kept by the last update_values
     // reuse trials after a rejection: the next skip[k] updates rebuild
@@ -395,8 +402,158 @@ static void apply_learned(hipStream_t s, Level &L, const float *mlp) {
     CPTR_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------------------
+// unknown-based system AMG (two-stage CPTR on B_ee)
+// ---------------------------------------------------------------------------
+// The scalar coarsening of one unknown's diagonal block Au, diagonal dg:
+// strength, PMIS (random measure indexed within the block) and extended+i
+// with truncation, with the kernels and row-kernel choices of the scalar
+// levels.  Writes the C/F split to cf (Au.n entries) and builds P; returns the
+// number of C points (P is left empty when that is 0 or Au.n).
+static int coarsen_block(Builder *c, const CsrD &Au, const double *dg, int *cf, CsrD &P, bool check_sym) {
+    hipStream_t s = c->stream;
+    const cptr_options &o = c->opt;
+    const int m = Au.n;
+    c->s_i1.alloc((size_t)Au.nnz + 1);
+    transpose_index(m, Au.rp, Au.ci, c->s_i1.p, c->flag.p, s);
+    if (check_sym && (read_flag_and_clear(c) & 8))
+        throw Error(CPTR_E_ARG, "AMG level pattern is not structurally symmetric");
+    DBuf<unsigned char> strong;
+    strong.alloc((size_t)Au.nnz + 1);
+    amg_strength(m, Au.rp, Au.ci, Au.v.p, o.amg_theta, strong.p, s);
+    c->s_i2.alloc((size_t)m + 1);
+    c->s_u1.alloc((size_t)m);
+    c->s_c1.alloc((size_t)m);
+    c->s_i3.alloc(4);
+    fill_int(c->s_i3.p, 0, 1, s);
+    amg_pmis_init(m, Au.rp, Au.ci, strong.p, c->s_i1.p, o.pmis_seed, c->s_i2.p, c->s_u1.p, cf, c->s_i3.p, s);
+    const int batch = (m >= PMIS_SMALL_LEVEL) ? PMIS_BATCH : PMIS_BATCH_SMALL;
+    int und = 1, rounds = 0;
+    while (und > 0) {
+        for (int q = 0; q < batch; ++q) {
+            fill_int(c->s_i3.p, 0, 1, s);
+            amg_pmis_round(m, Au.rp, Au.ci, strong.p, c->s_i1.p, c->s_i2.p, c->s_u1.p, cf, c->s_c1.p, c->s_i3.p, s);
+        }
+        und = read_scalar(c->s_i3.p, s);
+        rounds += batch;
+        if (rounds > 10000) throw Error(CPTR_E_STATE, "PMIS did not terminate");
+    }
+    DBuf<int> cidx, ub, off, cnt, tcol;
+    DBuf<double> twt, td;
+    cidx.alloc((size_t)m + 1);
+    scan_exclusive(cf, cidx.p, m, nullptr, s);
+    ub.alloc(m + 1);
+    off.alloc(m + 1);
+    cnt.alloc(m + 1);
+    const double avg_row = (double)Au.nnz / (double)m;
+    const int ek = o.setup_kernels;
+    amg_exti_bound(m, Au.rp, Au.ci, strong.p, cf, ub.p, ek == 1 || (ek == 0 && avg_row > EXTI_SHORT_ROW), s);
+    scan_exclusive(ub.p, off.p, m, nullptr, s);
+    int rd[3];
+    read_ints3(c, cidx.p + m, off.p + m, nullptr, rd);
+    const int nc = rd[0], cap = rd[1];
+    if (nc == 0 || nc == m) return nc;
+    tcol.alloc(cap);
+    twt.alloc(cap);
+    td.alloc((size_t)Au.nnz + 1);
+    if (ek == 2)
+        amg_exti_compute2(m, Au.rp, Au.ci, Au.v.p, strong.p, cf, cidx.p, dg, o.amg_pmax, off.p, tcol.p, twt.p, td.p,
+                          cnt.p, s);
+    else if (ek == 1)
+        amg_exti_compute_wave(m, Au.rp, Au.ci, Au.v.p, strong.p, cf, cidx.p, dg, o.amg_pmax, off.p, tcol.p, twt.p,
+                              td.p, cnt.p, s);
+    else
+        amg_exti_compute_group(m, (ek == 3 || avg_row <= EXTI_SHORT_ROW) ? 8 : avg_row <= EXTI_HALF_WAVE_ROW ? 32 : 64,
+                               Au.rp, Au.ci, Au.v.p, strong.p, cf, cidx.p, dg, o.amg_pmax, off.p, tcol.p, twt.p, td.p,
+                               cnt.p, s);
+    P.n = m;
+    P.ncols = nc;
+    P.rp_own.alloc((size_t)m + 1);
+    scan_exclusive(cnt.p, P.rp_own.p, m, nullptr, s);
+    P.rp = P.rp_own.p;
+    P.nnz = read_scalar(P.rp_own.p + m, s);
+    P.ci_own.alloc((size_t)P.nnz + 1);
+    P.v.alloc((size_t)P.nnz + 1);
+    amg_compact(m, off.p, tcol.p, twt.p, P.rp_own.p, P.ci_own.p, P.v.p, s);
+    P.ci = P.ci_own.p;
+    return nc;
+}
+
+// One level of unknown-based coarsening: the unknowns hold consecutive row
+// ranges (parts) of L.  Each unknown's diagonal block is extracted and
+// coarsened on its own; P = blockdiag(P_u) (its C points ordered unknown by
+// unknown), R = P^T, and the next operator R A P keeps every coupling between
+// the unknowns.  Returns false, leaving L the coarsest level, when some
+// unknown's block has no C point or no F point; else fills nxt and replaces
+// parts by the unknowns' coarse sizes.
+static bool coarsen_system(Builder *c, Level &L, std::vector<int> &parts, bool check_sym, Level &nxt) {
+    hipStream_t s = c->stream;
+    const int m = L.A.n;
+    const int nu = (int)parts.size();
+    std::vector<CsrD> Ps(nu);
+    std::vector<int> ncs(nu);
+    DBuf<int> cf;
+    cf.alloc((size_t)m + 1);
+    int o = 0;
+    for (int u = 0; u < nu; ++u) {
+        const int mu = parts[u];
+        CsrD Au;
+        Au.n = Au.ncols = mu;
+        Au.rp_own.alloc((size_t)mu + 1);
+        DBuf<int> cnt;
+        cnt.alloc((size_t)mu + 1);
+        amg_submatrix_count(mu, o, L.A.rp, L.A.ci, cnt.p, s);
+        scan_exclusive(cnt.p, Au.rp_own.p, mu, nullptr, s);
+        Au.rp = Au.rp_own.p;
+        Au.nnz = read_scalar(Au.rp_own.p + mu, s);
+        Au.ci_own.alloc((size_t)Au.nnz + 1);
+        Au.v.alloc((size_t)Au.nnz + 1);
+        amg_submatrix_fill(mu, o, L.A.rp, L.A.ci, L.A.v.p, Au.rp, Au.ci_own.p, Au.v.p, s);
+        Au.ci = Au.ci_own.p;
+        ncs[u] = coarsen_block(c, Au, c->s_d1.p + o, cf.p + o, Ps[u], check_sym && u == 0);
+        if (ncs[u] == 0 || ncs[u] == mu) return false;
+        o += mu;
+    }
+    CsrD &P = L.P;
+    int nz = 0, nc = 0;
+    for (int u = 0; u < nu; ++u) {
+        nz += Ps[u].nnz;
+        nc += ncs[u];
+    }
+    P.n = m;
+    P.ncols = nc;
+    P.nnz = nz;
+    P.rp_own.alloc((size_t)m + 1);
+    P.ci_own.alloc((size_t)nz + 1);
+    P.v.alloc((size_t)nz + 1);
+    int ro = 0, co = 0, zo = 0;
+    for (int u = 0; u < nu; ++u) {
+        // rows u: pointers shifted by the entries before, columns by the
+        // coarse points before (the shared boundary pointer is written twice
+        // with the same value)
+        amg_offset_copy(parts[u] + 1, Ps[u].rp, zo, P.rp_own.p + ro, s);
+        amg_offset_copy(Ps[u].nnz, Ps[u].ci, co, P.ci_own.p + zo, s);
+        if (Ps[u].nnz)
+            CPTR_HIP(hipMemcpyAsync(P.v.p + zo, Ps[u].v.p, sizeof(double) * Ps[u].nnz, hipMemcpyDeviceToDevice, s));
+        ro += parts[u];
+        co += ncs[u];
+        zo += Ps[u].nnz;
+    }
+    P.rp = P.rp_own.p;
+    P.ci = P.ci_own.p;
+    L.cf = std::move(cf);
+    L.nc = nc;
+    csr_transpose(c, P, L.R);
+    CsrD AP;
+    csr_spgemm(c, L.A, P, AP);
+    csr_spgemm(c, L.R, AP, nxt.A);
+    parts = ncs;
+    return true;
+}
+
 // `own` (optional): the buffer holding vals, taken over as the fine level's
-// values instead of copying them
+// values instead of copying them.  With c->parts set, the operator holds
+// several unknowns and is coarsened unknown by unknown.
 static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const float *mlp = nullptr,
                             DBuf<double> *own = nullptr) {
     hipStream_t s = c->stream;
@@ -404,6 +561,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
     const bool fp32 = (o.precond_precision == CPTR_FP32);
     h.L.clear();
     h.L.emplace_back();
+    std::vector<int> parts = c->parts;
     {
         Level &L0 = h.L.back();
         L0.A.n = c->n;
@@ -426,6 +584,12 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
         level_vectors(L, m, fp32);
         if (m <= o.amg_max_coarse || (int)h.L.size() >= o.amg_max_levels) break;
+        if (parts.size() > 1) {
+            Level nxt;
+            if (!coarsen_system(c, L, parts, h.L.size() == 1, nxt)) break;
+            h.L.push_back(std::move(nxt));
+            continue;
+        }
         // strength and PMIS
         c->s_i1.alloc((size_t)L.A.nnz + 1);    // transpose positions
         transpose_index(m, L.A.rp, L.A.ci, c->s_i1.p, c->flag.p, s);
@@ -637,7 +801,8 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // multi-stage preconditioner: y = M^{-1} r (Eq. multistageprec; Algorithm 2
-// for CPTR3, Algorithm 1 for CPR), r and y double, internals in T
+// for CPTR3, Algorithm 1 for CPR and for the two-stage CPTR scheme with the
+// system AMG on B_ee), r and y double, internals in T
 // ---------------------------------------------------------------------------
 template <class T>
 static void precond_apply(cptr_ctx *c, const double *r, double *y) {
@@ -675,6 +840,18 @@ static void precond_apply(cptr_ctx *c, const double *r, double *y) {
         vP = vcycle<T>(c, hp, 0, s);
         c->mark(1);
         c->mark(2);
+    } else if (variant == CPTR_VARIANT_CPTR) {
+        // two-stage CPTR: one system V-cycle on [r_P; r_T]; the last stage
+        // takes its P half as the P correction and its T half as the T one
+        Hierarchy &h = c->H[0];
+        T *bs = Prec<T>::b(h.L[0]);
+        ms_stage_input<T>(n, b, c->rp.p, c->ci.p, (const T *)nullptr, c->ip, r, (const T *)nullptr, bs, s);
+        ms_stage_input<T>(n, b, c->rp.p, c->ci.p, (const T *)nullptr, c->it, r, (const T *)nullptr, bs + n, s);
+        const T *xs = vcycle<T>(c, h, 0, s);
+        c->mark(1);
+        c->mark(2);
+        vP = xs;
+        xT = xs + n;
     } else {
         c->mark(1);
         c->mark(2);
@@ -733,7 +910,8 @@ constexpr uint64_t RHO_SEED = 0;
 // setup
 // ---------------------------------------------------------------------------
 static void validate_options(const cptr_options &o) {
-    if (o.variant != CPTR_VARIANT_CPTR3 && o.variant != CPTR_VARIANT_CPR && o.variant != CPTR_VARIANT_LAST_ONLY)
+    if (o.variant != CPTR_VARIANT_CPTR3 && o.variant != CPTR_VARIANT_CPR && o.variant != CPTR_VARIANT_CPTR &&
+        o.variant != CPTR_VARIANT_LAST_ONLY)
         throw Error(CPTR_E_ARG, "unknown variant");
     if (o.restart < 1 || o.restart > 200) throw Error(CPTR_E_ARG, "restart must be 1..200");
     if (o.max_iters < 1) throw Error(CPTR_E_ARG, "max_iters must be positive");
@@ -755,7 +933,8 @@ static void validate_options(const cptr_options &o) {
 // built and the learned one is kept only if its measured V-cycle convergence
 // factor is lower (CPTR_INTERP_LEARNED_FORCED keeps it without the judge).
 static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<double> *own) {
-    const bool learned = (k == 0) && c->have_mlp && c->opt.t_interp != CPTR_INTERP_CLASSICAL;
+    const bool learned = (k == 0) && c->opt.variant == CPTR_VARIANT_CPTR3 && c->have_mlp &&
+                         c->opt.t_interp != CPTR_INTERP_CLASSICAL;
     if (k == 0) {
         c->used_learned = 0;
         c->rho_cls = c->rho_lrn = -1.0;
@@ -824,6 +1003,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     const auto t_start = std::chrono::steady_clock::now();
     const int n = c->n, b = c->b, nnzb = c->nnzb;
     const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
+    const bool sys = (c->opt.variant == CPTR_VARIANT_CPTR);
     c->abar.alloc((size_t)nnzb * b * b);
     c->wp.alloc((size_t)n * b);
     c->wt.alloc((size_t)n * b);
@@ -846,6 +1026,19 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         CPTR_HIP(hipMemcpyAsync(c->abar.p, vals, sizeof(double) * nnzb * b * b, hipMemcpyDeviceToDevice, s));
         launch_extract(n, b, nnzb, c->abar.p, c->ip, c->it, ctt.p, bpp.p, c->slabT.p, c->slabP.p,
                        fp32 ? c->abar32.p : nullptr, fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
+    } else if (sys) {
+        // the elliptic block needs all four of its couplings: both phases of
+        // the scaling run before the system hierarchy's build
+        launch_decouple_weights(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
+                                c->beta.p, c->s_i4.p, nullptr, nullptr, s);
+        launch_decouple_apply(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
+                              c->beta.p, c->abar.p, c->slabT.p, c->slabP.p, fp32 ? c->abar32.p : nullptr,
+                              fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
+        c->ee_rp.alloc(2 * (size_t)n + 1);
+        c->ee_ci.alloc(4 * (size_t)nnzb);
+        c->ee_v.alloc(4 * (size_t)nnzb);
+        launch_elliptic_system(n, b, nnzb, c->rp.p, c->ci.p, c->abar.p, c->ip, c->it, c->ee_rp.p, c->ee_ci.p,
+                               c->ee_v.p, s);
     } else {
         // phase 1: the weights and the two scalar operators (all the AMG setups need)
         launch_decouple_weights(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
@@ -858,12 +1051,14 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     // own stream and host thread, while this stream factors the last stage
     c->tph[0] = ms_since(t_start);
     const auto t_hier = std::chrono::steady_clock::now();
-    const bool need[2] = {c->opt.variant == CPTR_VARIANT_CPTR3,
+    // (slot 0 holds the system hierarchy of B_ee for the two-stage scheme,
+    // which is always built anew)
+    const bool need[2] = {c->opt.variant == CPTR_VARIANT_CPTR3 || sys,
                           c->opt.variant == CPTR_VARIANT_CPTR3 || c->opt.variant == CPTR_VARIANT_CPR};
-    const double *svals[2] = {ctt.p, bpp.p};
+    const double *svals[2] = {sys ? c->ee_v.p : ctt.p, bpp.p};
     bool refresh[2] = {false, false};
     for (int k = 0; k < 2; ++k) {
-        refresh[k] = need[k] && reuse && c->H[k].built;
+        refresh[k] = need[k] && reuse && c->H[k].built && !sys;
         if (!reuse) {
             c->skip_left[k] = 0;
             c->backoff[k] = 1;
@@ -883,12 +1078,15 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         Builder &B = c->bld[k];
         B.stream = c->side[k];
         B.opt = c->opt;
-        B.n = n;
-        B.nnzb = nnzb;
-        B.rp.p = c->rp.p;
-        B.ci.p = c->ci.p;
+        const bool ee = sys && k == 0;
+        B.n = ee ? 2 * n : n;
+        B.nnzb = ee ? 4 * nnzb : nnzb;
+        B.rp.p = ee ? c->ee_rp.p : c->rp.p;
+        B.ci.p = ee ? c->ee_ci.p : c->ci.p;
+        B.parts.clear();
+        if (ee) B.parts = {n, n};
         c->tph[1 + k] = 0.0;
-        th[k] = std::thread([c, k, &B, &svals, &err, &refresh, &kept, t_hier]() {
+        th[k] = std::thread([c, k, sys, &B, &svals, &err, &refresh, &kept, t_hier]() {
             try {
                 CPTR_HIP(hipSetDevice(c->device));
                 StreamScope scope(B.stream);
@@ -898,7 +1096,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                 }
                 CPTR_HIP(hipStreamWaitEvent(B.stream, c->ev_dec, 0));
                 // the fine level takes over the buffer of its values
-                DBuf<double> *own = k == 0 ? &c->ctt : &c->bpp;
+                DBuf<double> *own = k == 0 ? (sys ? &c->ee_v : &c->ctt) : &c->bpp;
                 if (refresh[k]) {
                     // reuse decision: keep the refreshed hierarchy while its
                     // measured V-cycle convergence factor stays below the
@@ -931,7 +1129,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     } joiner{th};
     // phase 2 of the scaling, concurrently with the hierarchy builds: the
     // scaled matrix, its column slabs and FP32 copies, then the last stage
-    if (c->opt.variant != CPTR_VARIANT_LAST_ONLY)
+    if (c->opt.variant != CPTR_VARIANT_LAST_ONLY && !sys)
         launch_decouple_apply(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
                               c->beta.p, c->abar.p, c->slabT.p, c->slabP.p, fp32 ? c->abar32.p : nullptr,
                               fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
@@ -1348,7 +1546,8 @@ cptr_status cptr_decouple(int32_t variant, int32_t n, int32_t b, const int32_t *
                           double *d_rhsbar, void *stream) {
     CPTR_API_BEGIN
     StreamScope scope((hipStream_t)stream);
-    if (variant != CPTR_VARIANT_CPTR3 && variant != CPTR_VARIANT_CPR) throw Error(CPTR_E_ARG, "variant");
+    if (variant != CPTR_VARIANT_CPTR3 && variant != CPTR_VARIANT_CPR && variant != CPTR_VARIANT_CPTR)
+        throw Error(CPTR_E_ARG, "variant");
     if (n <= 0 || b < 2 || b > 8) throw Error(CPTR_E_ARG, "sizes");
     hipStream_t s = (hipStream_t)stream;
     DBuf<double> wp, wt, beta;

@@ -157,6 +157,9 @@ void launch_unscale(int variant, int n, int b, const double *v, int ip, int it, 
                     const double *wt, const double *beta, double *out, hipStream_t s);
 void launch_extract(int n, int b, int nnzb, const double *abar, int ip, int it, double *ctt, double *bpp,
                     double *slabT, double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s);
+// B_ee of the two-stage scheme: 2n rows [P; T], 4 nnzb entries, srp[2n] = 4 nnzb
+void launch_elliptic_system(int n, int b, int nnzb, const int *rp, const int *ci, const double *abar, int ip, int it,
+                            int *srp, int *sci, double *sv, hipStream_t s);
 
 // k_amg_setup.hip
 void amg_strength(int n, const int *rp, const int *ci, const double *v, double theta, unsigned char *s,
@@ -187,6 +190,13 @@ void amg_spgemm_compute_sort(int m, int ncols, int maxprod, const int *arp, cons
                              double *tval, int *cnt, hipStream_t st);
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
                         const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
+// rows and columns [o, o + m) of a CSR matrix with sorted rows: entry counts,
+// then the entries in their order with columns shifted by -o
+void amg_submatrix_count(int m, int o, const int *rp, const int *ci, int *cnt, hipStream_t st);
+void amg_submatrix_fill(int m, int o, const int *rp, const int *ci, const double *v, const int *srp, int *sci,
+                        double *sv, hipStream_t st);
+// out[i] = in[i] + add, i < n
+void amg_offset_copy(int n, const int *in, int add, int *out, hipStream_t st);
 void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
                    int *flag, hipStream_t st);
 // F: n * 16 doubles, U: 16 * 2n doubles (panel multipliers and pivot rows)

@@ -1378,6 +1378,58 @@ __global__ void k_diag_inv(int n, const int *__restrict__ rp, const int *__restr
     dinv[i] = 1.0 / d;
 }
 
+// Diagonal block of one unknown in a system level (unknown-based AMG): row
+// o + i keeps the entries whose column lies in [o, o + m), in their order,
+// with the column shifted by -o.  One thread per row.
+__global__ void k_sub_count(int m, int o, const int *__restrict__ rp, const int *__restrict__ ci,
+                            int *__restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int k = 0;
+    for (int e = rp[o + i]; e < rp[o + i + 1]; ++e) k += (ci[e] >= o && ci[e] < o + m);
+    cnt[i] = k;
+}
+
+__global__ void k_sub_fill(int m, int o, const int *__restrict__ rp, const int *__restrict__ ci,
+                           const double *__restrict__ v, const int *__restrict__ srp, int *__restrict__ sci,
+                           double *__restrict__ sv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int k = srp[i];
+    for (int e = rp[o + i]; e < rp[o + i + 1]; ++e) {
+        const int c = ci[e];
+        if (c >= o && c < o + m) {
+            sci[k] = c - o;
+            sv[k] = v[e];
+            ++k;
+        }
+    }
+}
+
+__global__ void k_offset_copy(int n, const int *__restrict__ in, int add, int *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i] + add;
+}
+
+void amg_submatrix_count(int m, int o, const int *rp, const int *ci, int *cnt, hipStream_t st) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_sub_count, dim3((m + 255) / 256), dim3(256), 0, st, m, o, rp, ci, cnt);
+    CPTR_CHECK_LAUNCH();
+}
+
+void amg_submatrix_fill(int m, int o, const int *rp, const int *ci, const double *v, const int *srp, int *sci,
+                        double *sv, hipStream_t st) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_sub_fill, dim3((m + 255) / 256), dim3(256), 0, st, m, o, rp, ci, v, srp, sci, sv);
+    CPTR_CHECK_LAUNCH();
+}
+
+void amg_offset_copy(int n, const int *in, int add, int *out, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_offset_copy, dim3((n + 255) / 256), dim3(256), 0, st, n, in, add, out);
+    CPTR_CHECK_LAUNCH();
+}
+
 void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
                    int *flag, hipStream_t st) {
     if (n == 0) return;

@@ -24,7 +24,8 @@ __device__ inline int group_index(int k, int ip, int it, bool with_t) {
 // D_gg^T [w_P w_T] = [D_Pg^T D_Tg^T] (g = the eliminated group: s for CPTR3,
 // s u {T} for CPR) by Gaussian elimination with partial pivoting -- first
 // largest |pivot|, kij order, back substitution in descending rows -- and
-//   CPTR3: beta = Ahat_ii[T][P] / Ahat_ii[P][P],
+//   CPTR3: beta = Ahat_ii[T][P] / Ahat_ii[P][P] (the two-stage CPTR scheme
+//   keeps the first scaling alone: beta = 0, Abar[T] = Ahat[T]),
 // with Ahat[P][c] = A[P][c] - sum_{k ascending} w_P[k] A[g_k][c] and
 // Ahat[T][c] likewise with w_T.  w_P, w_T are stored by unknown (0 outside
 // the group).  The same thread extracts B_PP = Abar[P,P] and
@@ -105,7 +106,7 @@ __global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__re
         }
     }
     double bt = 0.0;
-    if (!CPR) {
+    if (VAR == CPTR_VARIANT_CPTR3) {
         double hp = D[ip * B + ip], ht = D[it * B + ip];
 #pragma unroll
         for (int k = 0; k < NG; ++k) hp = hp - F[k][0] * D[group_index(k, ip, it, CPR) * B + ip];
@@ -221,6 +222,9 @@ void launch_decouple_weights(int variant, int n, int b, const int *rp, const int
         if (variant == CPTR_VARIANT_CPR)                                                                          \
             hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPR>), g, t, 0, s, n, rp, ci, A, ip, it, wp,  \
                                wt, beta, err, ctt, bpp);                                                          \
+        else if (variant == CPTR_VARIANT_CPTR)                                                                    \
+            hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPTR>), g, t, 0, s, n, rp, ci, A, ip, it, wp,  \
+                               wt, beta, err, ctt, bpp);                                                          \
         else                                                                                                      \
             hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPTR3>), g, t, 0, s, n, rp, ci, A, ip, it, wp, \
                                wt, beta, err, ctt, bpp);                                                          \
@@ -248,6 +252,9 @@ void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *
         if (variant == CPTR_VARIANT_CPR)                                                                          \
             hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPR>), dim3(grid), dim3(64), 0, s, n, rp, ci, A, \
                                ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);              \
+        else if (variant == CPTR_VARIANT_CPTR)                                                                    \
+            hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPTR>), dim3(grid), dim3(64), 0, s, n, rp, ci,   \
+                               A, ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);           \
         else                                                                                                      \
             hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPTR3>), dim3(grid), dim3(64), 0, s, n, rp, ci,  \
                                A, ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);           \
@@ -370,6 +377,45 @@ void launch_extract(int n, int b, int nnzb, const double *abar, int ip, int it, 
     if (nnzb == 0) return;
     hipLaunchKernelGGL(k_extract, dim3((nnzb + 255) / 256), dim3(256), 0, s, nnzb, b, abar, ip, it, ctt, bpp, slabT,
                        slabP, abar32, slabT32, slabP32);
+    CPTR_CHECK_LAUNCH();
+}
+
+// The elliptic block B_ee = [[B_PP, B_PT], [B_TP, B_TT]] of the scaled matrix
+// (two-stage CPTR, Sec. "Two-stage Constrained Pressure-Temperature
+// Residual") as one scalar CSR of 2n rows: unknowns ordered [P of every cell;
+// T of every cell]; row u*n + i holds the P-block columns of cell row i, then
+// its T-block columns shifted by n, so it starts at 2 (u nnzb + rp[i]).  One
+// thread per (unknown, cell) row.
+__global__ void k_elliptic_system(int n, int b, int nnzb, const int *__restrict__ rp, const int *__restrict__ ci,
+                                  const double *__restrict__ abar, int ip, int it, int *__restrict__ srp,
+                                  int *__restrict__ sci, double *__restrict__ sv) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row > 2 * n) return;
+    if (row == 2 * n) {
+        srp[row] = 4 * nnzb;
+        return;
+    }
+    const int u = row / n, i = row - u * n;
+    const int ru = u == 0 ? ip : it;
+    const int e0 = rp[i], cnt = rp[i + 1] - e0;
+    const size_t base = 2 * ((size_t)u * nnzb + e0);
+    srp[row] = (int)base;
+    for (int t = 0; t < cnt; ++t) {
+        const int e = e0 + t;
+        const double *Bk = abar + (size_t)e * b * b + (size_t)ru * b;
+        sci[base + t] = ci[e];
+        sv[base + t] = Bk[ip];
+        sci[base + cnt + t] = ci[e] + n;
+        sv[base + cnt + t] = Bk[it];
+    }
+}
+
+void launch_elliptic_system(int n, int b, int nnzb, const int *rp, const int *ci, const double *abar, int ip, int it,
+                            int *srp, int *sci, double *sv, hipStream_t s) {
+    if (n == 0) return;
+    if ((size_t)4 * nnzb > 0x7fffffffULL) throw Error(CPTR_E_ARG, "elliptic block exceeds 32-bit indexing");
+    hipLaunchKernelGGL(k_elliptic_system, dim3((2 * n + 1 + 255) / 256), dim3(256), 0, s, n, b, nnzb, rp, ci, abar, ip,
+                       it, srp, sci, sv);
     CPTR_CHECK_LAUNCH();
 }
 

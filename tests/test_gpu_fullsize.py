@@ -98,3 +98,34 @@ def test_fp32_preconditioner_reaches_the_fp64_tolerance(c3):
     print(f"  its={res['iterations']} gpu rel_res={res['rel_res_scaled']:.3e} oracle-recomputed {rel:.3e}", flush=True)
     assert res["converged"] == 1
     assert rel <= 1e-8 * (1 + 1e-6)
+
+
+def test_two_stage_cptr_system_amg(c3):
+    """The two-stage CPTR scheme at full size: the unknown-based system
+    hierarchy of the 1M-row elliptic block bit for bit, and the plain FP64
+    solve to 1e-10 with iterations within one."""
+    s, A, dec = c3
+    print("case full-size two-stage CPTR (oracle solve ~20 s)", flush=True)
+    ref = O.solve(s, O.Options(color=O.tile_colors(NX, NY, *TILE), restart=50, variant=O.CPTR,
+                               amg=O.AMGOptions(pre=SWEEPS, post=SWEEPS)))
+    h = ref.hierarchies["ee"]
+    sv = _solver(s, variant=cptr.VARIANT_CPTR)
+    try:
+        assert sv.amg_levels(0) == len(h.levels), h.sizes
+        for lvl, L in enumerate(h.levels):
+            g = sv.amg_level(0, lvl)
+            assert np.array_equal(g["rp"], L.A.rp) and np.array_equal(g["ci"], L.A.ci)
+            assert np.array_equal(g["v"], L.A.v), f"system level {lvl} operator"
+            if lvl + 1 < len(h.levels):
+                assert np.array_equal(g["cf"], L.cf)
+                assert np.array_equal(g["pci"], L.P.ci) and np.array_equal(g["pv"], L.P.v)
+        print(f"  system hierarchy: sizes {h.sizes} identical", flush=True)
+        x, res = sv.solve(torch.from_numpy(s.rhs).cuda())
+    finally:
+        sv.close()
+    x = x.cpu().numpy()
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    print(f"  gpu its={res['iterations']} oracle its={ref.iterations} err={err:.2e}", flush=True)
+    assert res["converged"] == 1 and res["rel_res_scaled"] <= 1e-8
+    assert abs(res["iterations"] - ref.iterations) <= 1
+    assert err <= 1e-10
