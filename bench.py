@@ -213,6 +213,49 @@ def solve_probe(args, dev) -> int:
     return 0
 
 
+EXACT_STUDY_PECLET = ((0.01, "diffusion dominated"), (1.0, "neutral"), (100.0, "advection dominated"))
+
+
+def exact_study(args, dev, n: int = 64) -> int:
+    """The Schur-complement quality study: GMRES(30) iterations of CPR, CPTR3
+    and the two-stage CPTR scheme when every AMG stage applies its operator
+    exactly (dense inverse; B_ee has 2 n^2 = 8192 rows at n = 64), beside the
+    same solvers with AMG, on homogeneous n x n, b = 6 systems at a diffusion
+    dominated, a neutral and an advection dominated Peclet number.  Plain FP64
+    on the GPU; one setup + solve per entry."""
+    import numpy as np
+    import torch
+    from paper_1912_04385_amd import cptr
+    from synthetic import assemble
+
+    variants = (("CPR", cptr.VARIANT_CPR), ("CPTR3", cptr.VARIANT_CPTR3), ("CPTR two-stage", cptr.VARIANT_CPTR))
+    rows = []
+    for k, (pe, regime) in enumerate(EXACT_STUDY_PECLET):
+        sy = assemble(n, n, 6, np.ones((n, n)), peclet=pe, seed=k, field_seed=k)
+        rp, ci = torch.from_numpy(sy.row_ptr).to(dev), torch.from_numpy(sy.col_idx).to(dev)
+        vals, rhs = torch.from_numpy(sy.vals.reshape(-1)).to(dev), torch.from_numpy(sy.rhs).to(dev)
+        for vname, v in variants:
+            for sub in (1, 0):
+                sol = cptr.Solver(variant=v, exact_subsolves=sub, restart=30, max_iters=500, ilu_tile_x=32,
+                                  ilu_tile_y=8)
+                try:
+                    sol.setup(rp, ci, vals, 0, 1, n, n)
+                    _, res = sol.solve(rhs)
+                finally:
+                    sol.close()
+                row = {"peclet": pe, "regime": regime, "variant": vname,
+                       "subsolves": "exact" if sub else "AMG", "iterations": res["iterations"],
+                       "converged": res["converged"], "rel_res": res["rel_res_scaled"],
+                       "setup_ms": round(res["setup_ms"], 2), "solve_ms": round(res["solve_ms"], 2)}
+                rows.append(row)
+                print(f"# Pe {pe:g} {vname:15s} {row['subsolves']:5s}: its={row['iterations']} "
+                      f"setup={row['setup_ms']} ms solve={row['solve_ms']} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "exact sub-solves vs AMG (Schur-complement quality)",
+                      "grid": f"{n}x{n}, b=6, homogeneous k=1", "krylov": "GMRES(30), FP64, tol 1e-8",
+                      "last_stage": "BILU(0) in 32x8 tiles", "rows": rows}))
+    return 0
+
+
 def learned_bench(args, dev) -> int:
     """Learned against classical temperature interpolation on the 1000 x 500,
     b = 8 systems (Pe 0.1 and 100): FP32-preconditioned FGMRES(50) with the
@@ -376,9 +419,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--weights", default=None, help="learned-interpolation parameters (.npy) for c4")
-    ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
-                    help="c3: 1000x500 single systems (default); c5: the 2000x1000 Newton sequence with "
-                         "hierarchy reuse")
+    ap.add_argument("--workload", choices=["c3", "c4", "c5", "exact"], default="c3",
+                    help="c3: 1000x500 single systems (default); c4: learned against classical "
+                         "interpolation; c5: the 2000x1000 Newton sequence with hierarchy reuse; exact: "
+                         "the exact sub-solver study")
     ap.add_argument("--systems", type=int, default=20, help="length of the c5 sequence")
     ap.add_argument("--sweeps", type=int, default=2,
                     help="Jacobi pre- and post-smoothing sweeps of the V-cycles (2 for every workload: two damped "
@@ -389,6 +433,8 @@ def main() -> int:
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the outer SpMV and a plain device copy of known size, 5 times each "
                          "(the run that the HBM byte counters are read on)")
+    ap.add_argument("--no-two-stage", action="store_true",
+                    help="skip timing the two-stage CPTR variant beside the headline")
     ap.add_argument("--no-front-end", action="store_true",
                     help="skip timing the static-condensation front end")
     ap.add_argument("--solve-probe", action="store_true",
@@ -416,6 +462,8 @@ def main() -> int:
         return sequence_bench(args, dev)
     if args.workload == "c4":
         return learned_bench(args, dev)
+    if args.workload == "exact":
+        return exact_study(args, dev)
     t_gen = time.perf_counter()
     systems = []
     for idx in (0, 1):
@@ -511,6 +559,22 @@ def main() -> int:
                              "setup_ms": [round(r["setup_ms"], 2) for r in res64],
                              "solve_ms": [round(r["solve_ms"], 2) for r in res64]}
         out["speedup_vs_fp64"] = round(ms64 / ms32, 4)
+    if not args.no_two_stage:
+        # the two-stage CPTR scheme (system AMG on B_ee, then the last stage)
+        # on the same systems, FP32 preconditioner inside FP64 FGMRES(50)
+        two = cptr.Solver(krylov=cptr.FGMRES, precond_precision=cptr.FP32, variant=cptr.VARIANT_CPTR, **common)
+        ms2, res2 = timed(two, "two-stage-fp32")
+        two.close()
+        l2 = sum(r["timed_steps"] for r in res2)
+        out["two_stage"] = {"preconditioner": "two-stage CPTR: system AMG V-cycle on B_ee (2n rows), then BILU(0)",
+                            "ms_per_step": round(ms2, 2), "solves_per_s": round(1000.0 / ms2, 4),
+                            "iterations": [r["iterations"] for r in res2],
+                            "levels": [r["levels_T"] for r in res2],
+                            "setup_ms": [round(r["setup_ms"], 2) for r in res2],
+                            "solve_ms": [round(r["solve_ms"], 2) for r in res2],
+                            "stage_ms_per_step": {k: round(sum(r[k] for r in res2) / max(1, l2), 4)
+                                                  for k in ("t_stage1_ms", "t_last_ms", "t_spmv_ms",
+                                                            "t_arnoldi_ms")}}
     if not args.no_front_end:
         out["front_end"] = front_end_bench(args, dev)
     if not args.no_cpu_baseline:

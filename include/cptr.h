@@ -108,6 +108,13 @@ typedef struct {
                                 /* 8-lane groups on every level (long rows take   */
                                 /* the sequential path; for tests).  The          */
                                 /* hierarchy is bit-identical either way.         */
+    int32_t exact_subsolves;    /* 1: every AMG stage applies its operator's      */
+                                /* exact inverse instead of a V-cycle (the Schur- */
+                                /* complement quality study of Sec. "Numerical    */
+                                /* Results": M_PP = B_PP, M_TT = C_TT, M_ee =     */
+                                /* B_ee), by a dense inverse on the GPU; setup    */
+                                /* fails with CPTR_E_ARG when an operator has     */
+                                /* more than 8192 rows (0)                        */
 } cptr_options;
 
 typedef struct {

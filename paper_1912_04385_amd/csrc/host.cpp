@@ -316,6 +316,9 @@ static void coarse_inverse(Builder *c, Hierarchy &h) {
     const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
     Level &Lc = h.L.back();
     const int nc = Lc.A.n;
+    if (nc > MAX_COARSE_DENSE && c->opt.exact_subsolves)
+        throw Error(CPTR_E_ARG, "exact sub-solve of an operator with " + std::to_string(nc) + " rows (the dense limit is " +
+                                    std::to_string(MAX_COARSE_DENSE) + ")");
     if (nc > MAX_COARSE_DENSE)
         throw Error(CPTR_E_ARG, "coarsest AMG level has " + std::to_string(nc) +
                                     " rows (more than the dense limit); raise amg_max_levels or lower amg_max_coarse");
@@ -583,7 +586,9 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         c->s_d1.alloc(m);   // diagonal of this level
         amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
         level_vectors(L, m, fp32);
-        if (m <= o.amg_max_coarse || (int)h.L.size() >= o.amg_max_levels) break;
+        // (exact sub-solves: the fine level is the coarsest, applied by its
+        // dense inverse)
+        if (o.exact_subsolves || m <= o.amg_max_coarse || (int)h.L.size() >= o.amg_max_levels) break;
         if (parts.size() > 1) {
             Level nxt;
             if (!coarsen_system(c, L, parts, h.L.size() == 1, nxt)) break;
@@ -922,6 +927,7 @@ static void validate_options(const cptr_options &o) {
     if (o.ilu_tile_x < 1 || o.ilu_tile_y < 1) throw Error(CPTR_E_ARG, "ILU tile must be at least 1 x 1");
     if (o.pre_sweeps < 0 || o.post_sweeps < 0) throw Error(CPTR_E_ARG, "negative smoothing sweeps");
     if (o.setup_kernels < 0 || o.setup_kernels > 3) throw Error(CPTR_E_ARG, "setup_kernels must be 0, 1, 2 or 3");
+    if (o.exact_subsolves != 0 && o.exact_subsolves != 1) throw Error(CPTR_E_ARG, "exact_subsolves must be 0 or 1");
     if (o.t_interp < CPTR_INTERP_CLASSICAL || o.t_interp > CPTR_INTERP_LEARNED_FORCED)
         throw Error(CPTR_E_ARG, "unknown t_interp");
     if (o.t_interp != CPTR_INTERP_CLASSICAL && (o.amg_pmax < 1 || o.amg_pmax > 16))
@@ -1358,6 +1364,7 @@ cptr_status cptr_default_options(cptr_options *o) {
     o->reuse_rho_max = 0.3;
     o->timing = 0;
     o->setup_kernels = 0;
+    o->exact_subsolves = 0;
     return CPTR_OK;
 }
 

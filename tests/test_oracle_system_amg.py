@@ -86,3 +86,25 @@ def test_cptr_amg_converges_config2():
     res = O.solve(s, O.Options(variant=O.CPTR, color=O.tile_colors(s.nx, s.ny), restart=30))
     assert res.converged and res.iterations < 60
     print("config2-1 CPTR-AMG iterations", res.iterations, "levels", res.hierarchies["ee"].sizes)
+
+
+def test_two_stage_exact_subsolve_uncoupled_upwind():
+    """Exact B_ee solve (the paper's M_ee = B_ee) + zero cross coupling + flow
+    only toward +x/+y: the stage-1 residual vanishes on (P, T), the
+    composition rows are lower triangular in the natural order so ILU(0) is
+    exact on them, and M^{-1} = Abar^{-1}: GMRES converges in one step."""
+    s = tiny(6, 5, 5, seed=4, zero_coupling=True)
+    r = O.solve(s, O.Options(color=np.arange(30), variant=O.CPTR, exact_subsolves=True))
+    assert r.iterations == 1 and r.rel_res_scaled <= 1e-12
+
+
+def test_two_stage_single_level_amg_is_the_exact_subsolve():
+    """A system hierarchy with a single level applies B_ee^{-1} (dense LU of
+    the coarsest level), so it reproduces the exact sub-solve variant."""
+    s = tiny(12, 9, 4, peclet=3.0, seed=8)
+    base = dict(color=O.tile_colors(12, 9, 4, 3), variant=O.CPTR, restart=40)
+    a = O.solve(s, O.Options(exact_subsolves=True, **base))
+    b = O.solve(s, O.Options(amg=O.AMGOptions(max_coarse=10000), **base))
+    assert len(b.hierarchies["ee"].levels) == 1
+    assert a.iterations == b.iterations
+    assert np.linalg.norm(a.x - b.x) <= 1e-12 * np.linalg.norm(a.x)
