@@ -1033,22 +1033,18 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         launch_extract(n, b, nnzb, c->abar.p, c->ip, c->it, ctt.p, bpp.p, c->slabT.p, c->slabP.p,
                        fp32 ? c->abar32.p : nullptr, fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
     } else if (sys) {
-        // the elliptic block needs all four of its couplings: both phases of
-        // the scaling run before the system hierarchy's build
-        launch_decouple_weights(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
-                                c->beta.p, c->s_i4.p, nullptr, nullptr, s);
-        launch_decouple_apply(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
-                              c->beta.p, c->abar.p, c->slabT.p, c->slabP.p, fp32 ? c->abar32.p : nullptr,
-                              fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
+        // phase 1: the weights and the elliptic block B_ee (all the system
+        // AMG setup needs)
+        if ((size_t)4 * nnzb > 0x7fffffffULL) throw Error(CPTR_E_ARG, "elliptic block exceeds 32-bit indexing");
         c->ee_rp.alloc(2 * (size_t)n + 1);
         c->ee_ci.alloc(4 * (size_t)nnzb);
         c->ee_v.alloc(4 * (size_t)nnzb);
-        launch_elliptic_system(n, b, nnzb, c->rp.p, c->ci.p, c->abar.p, c->ip, c->it, c->ee_rp.p, c->ee_ci.p,
-                               c->ee_v.p, s);
+        launch_decouple_weights(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
+                                c->beta.p, c->s_i4.p, nullptr, nullptr, c->ee_rp.p, c->ee_ci.p, c->ee_v.p, s);
     } else {
         // phase 1: the weights and the two scalar operators (all the AMG setups need)
         launch_decouple_weights(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
-                                c->beta.p, c->s_i4.p, ctt.p, bpp.p, s);
+                                c->beta.p, c->s_i4.p, ctt.p, bpp.p, nullptr, nullptr, nullptr, s);
     }
     int bad = read_scalar(c->s_i4.p, s);
     if (bad != 0x7fffffff)
@@ -1135,7 +1131,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     } joiner{th};
     // phase 2 of the scaling, concurrently with the hierarchy builds: the
     // scaled matrix, its column slabs and FP32 copies, then the last stage
-    if (c->opt.variant != CPTR_VARIANT_LAST_ONLY && !sys)
+    if (c->opt.variant != CPTR_VARIANT_LAST_ONLY)
         launch_decouple_apply(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
                               c->beta.p, c->abar.p, c->slabT.p, c->slabP.p, fp32 ? c->abar32.p : nullptr,
                               fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);

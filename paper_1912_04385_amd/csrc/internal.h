@@ -144,10 +144,12 @@ void to_float_multi(const ToFloatJob *jobs, int count, hipStream_t s);
 void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                      double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s);
 // phase 1 (one thread per cell): weights w_P, w_T, beta and the B_PP / C_TT
-// entries; phase 2 (one wavefront per cell): the scaled matrix, slabs, FP32 copies
+// entries (two-stage variant: the elliptic block B_ee, 2n rows [P; T], 4 nnzb
+// entries, with ee_v non-null); phase 2 (one wavefront per cell): the scaled
+// matrix, slabs, FP32 copies
 void launch_decouple_weights(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
                              int it, double *wp, double *wt, double *beta, int *err, double *ctt, double *bpp,
-                             hipStream_t s);
+                             int *ee_rp, int *ee_ci, double *ee_v, hipStream_t s);
 void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                            const double *wp, const double *wt, const double *beta, double *abar, double *slabT,
                            double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s);
@@ -157,9 +159,6 @@ void launch_unscale(int variant, int n, int b, const double *v, int ip, int it, 
                     const double *wt, const double *beta, double *out, hipStream_t s);
 void launch_extract(int n, int b, int nnzb, const double *abar, int ip, int it, double *ctt, double *bpp,
                     double *slabT, double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s);
-// B_ee of the two-stage scheme: 2n rows [P; T], 4 nnzb entries, srp[2n] = 4 nnzb
-void launch_elliptic_system(int n, int b, int nnzb, const int *rp, const int *ci, const double *abar, int ip, int it,
-                            int *srp, int *sci, double *sv, hipStream_t s);
 
 // k_amg_setup.hip
 void amg_strength(int n, const int *rp, const int *ci, const double *v, double theta, unsigned char *s,

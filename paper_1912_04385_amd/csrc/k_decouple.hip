@@ -37,7 +37,9 @@ __global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__re
                                                           const int *__restrict__ ci, const double *__restrict__ A,
                                                           int ip, int it, double *__restrict__ wp,
                                                           double *__restrict__ wt, double *__restrict__ beta, int *err,
-                                                          double *__restrict__ ctt, double *__restrict__ bpp) {
+                                                          double *__restrict__ ctt, double *__restrict__ bpp,
+                                                          int *__restrict__ ee_rp, int *__restrict__ ee_ci,
+                                                          double *__restrict__ ee_v) {
     constexpr bool CPR = (VAR == CPTR_VARIANT_CPR);
     constexpr int NG = CPR ? B - 1 : B - 2;
     constexpr int NR = CPR ? 1 : 2;
@@ -128,6 +130,38 @@ __global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__re
         wt[(size_t)i * B + u] = vt;
     }
     beta[i] = bt;
+    if (VAR == CPTR_VARIANT_CPTR && ee_v) {
+        // the elliptic block B_ee straight from the weights (row u n + i at
+        // 2 (u nnzb + rp[i]): P-block columns, then T-block columns + n),
+        // each entry evaluated in the order of the apply phase
+        const int nnzb = rp[n], e0 = rp[i], cnt = rp[i + 1] - e0;
+        const size_t bp = 2 * (size_t)e0, bt2 = 2 * ((size_t)nnzb + e0);
+        ee_rp[i] = (int)bp;
+        ee_rp[n + i] = (int)bt2;
+        if (i == n - 1) ee_rp[2 * n] = 4 * nnzb;
+        for (int t = 0; t < cnt; ++t) {
+            const int e = e0 + t;
+            const double *Bk = A + (size_t)e * B * B;
+            double pP = Bk[ip * B + ip], pT = Bk[ip * B + it], tP = Bk[it * B + ip], tT = Bk[it * B + it];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                const int g = group_index(k, ip, it, CPR);
+                pP = pP - F[k][0] * Bk[g * B + ip];
+                pT = pT - F[k][0] * Bk[g * B + it];
+                tP = tP - F[k][NR - 1] * Bk[g * B + ip];
+                tT = tT - F[k][NR - 1] * Bk[g * B + it];
+            }
+            const int c = ci[e];
+            ee_ci[bp + t] = c;
+            ee_v[bp + t] = pP;
+            ee_ci[bp + cnt + t] = c + n;
+            ee_v[bp + cnt + t] = pT;
+            ee_ci[bt2 + t] = c;
+            ee_v[bt2 + t] = tP;
+            ee_ci[bt2 + cnt + t] = c + n;
+            ee_v[bt2 + cnt + t] = tT;
+        }
+    }
     if (!ctt && !bpp) return;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const double *Bk = A + (size_t)e * B * B;
@@ -214,20 +248,21 @@ __global__ void __launch_bounds__(64) k_decouple_apply(int n, const int *__restr
 
 void launch_decouple_weights(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
                              int it, double *wp, double *wt, double *beta, int *err, double *ctt, double *bpp,
-                             hipStream_t s) {
+                             int *ee_rp, int *ee_ci, double *ee_v, hipStream_t s) {
+    if (ee_v && variant != CPTR_VARIANT_CPTR) throw Error(CPTR_E_ARG, "the elliptic block belongs to the two-stage variant");
     if (n == 0) return;
     const dim3 g((n + 127) / 128), t(128);
 #define CASE(BB)                                                                                                  \
     case BB:                                                                                                      \
         if (variant == CPTR_VARIANT_CPR)                                                                          \
             hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPR>), g, t, 0, s, n, rp, ci, A, ip, it, wp,  \
-                               wt, beta, err, ctt, bpp);                                                          \
+                               wt, beta, err, ctt, bpp, ee_rp, ee_ci, ee_v);                                      \
         else if (variant == CPTR_VARIANT_CPTR)                                                                    \
             hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPTR>), g, t, 0, s, n, rp, ci, A, ip, it, wp,  \
-                               wt, beta, err, ctt, bpp);                                                          \
+                               wt, beta, err, ctt, bpp, ee_rp, ee_ci, ee_v);                                      \
         else                                                                                                      \
             hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPTR3>), g, t, 0, s, n, rp, ci, A, ip, it, wp, \
-                               wt, beta, err, ctt, bpp);                                                          \
+                               wt, beta, err, ctt, bpp, ee_rp, ee_ci, ee_v);                                      \
         break;
     switch (b) {
         CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -269,7 +304,8 @@ void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *
 
 void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                      double *abar, double *wp, double *wt, double *beta, int *err, hipStream_t s) {
-    launch_decouple_weights(variant, n, b, rp, ci, A, ip, it, wp, wt, beta, err, nullptr, nullptr, s);
+    launch_decouple_weights(variant, n, b, rp, ci, A, ip, it, wp, wt, beta, err, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, s);
     launch_decouple_apply(variant, n, b, rp, ci, A, ip, it, wp, wt, beta, abar, nullptr, nullptr, nullptr, nullptr,
                           nullptr, s);
 }
@@ -377,45 +413,6 @@ void launch_extract(int n, int b, int nnzb, const double *abar, int ip, int it, 
     if (nnzb == 0) return;
     hipLaunchKernelGGL(k_extract, dim3((nnzb + 255) / 256), dim3(256), 0, s, nnzb, b, abar, ip, it, ctt, bpp, slabT,
                        slabP, abar32, slabT32, slabP32);
-    CPTR_CHECK_LAUNCH();
-}
-
-// The elliptic block B_ee = [[B_PP, B_PT], [B_TP, B_TT]] of the scaled matrix
-// (two-stage CPTR, Sec. "Two-stage Constrained Pressure-Temperature
-// Residual") as one scalar CSR of 2n rows: unknowns ordered [P of every cell;
-// T of every cell]; row u*n + i holds the P-block columns of cell row i, then
-// its T-block columns shifted by n, so it starts at 2 (u nnzb + rp[i]).  One
-// thread per (unknown, cell) row.
-__global__ void k_elliptic_system(int n, int b, int nnzb, const int *__restrict__ rp, const int *__restrict__ ci,
-                                  const double *__restrict__ abar, int ip, int it, int *__restrict__ srp,
-                                  int *__restrict__ sci, double *__restrict__ sv) {
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row > 2 * n) return;
-    if (row == 2 * n) {
-        srp[row] = 4 * nnzb;
-        return;
-    }
-    const int u = row / n, i = row - u * n;
-    const int ru = u == 0 ? ip : it;
-    const int e0 = rp[i], cnt = rp[i + 1] - e0;
-    const size_t base = 2 * ((size_t)u * nnzb + e0);
-    srp[row] = (int)base;
-    for (int t = 0; t < cnt; ++t) {
-        const int e = e0 + t;
-        const double *Bk = abar + (size_t)e * b * b + (size_t)ru * b;
-        sci[base + t] = ci[e];
-        sv[base + t] = Bk[ip];
-        sci[base + cnt + t] = ci[e] + n;
-        sv[base + cnt + t] = Bk[it];
-    }
-}
-
-void launch_elliptic_system(int n, int b, int nnzb, const int *rp, const int *ci, const double *abar, int ip, int it,
-                            int *srp, int *sci, double *sv, hipStream_t s) {
-    if (n == 0) return;
-    if ((size_t)4 * nnzb > 0x7fffffffULL) throw Error(CPTR_E_ARG, "elliptic block exceeds 32-bit indexing");
-    hipLaunchKernelGGL(k_elliptic_system, dim3((2 * n + 1 + 255) / 256), dim3(256), 0, s, n, b, nnzb, rp, ci, abar, ip,
-                       it, srp, sci, sv);
     CPTR_CHECK_LAUNCH();
 }
 
