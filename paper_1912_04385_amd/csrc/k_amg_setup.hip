@@ -1462,6 +1462,7 @@ __global__ void k_dense_aug(int n, const int *__restrict__ rp, const int *__rest
 constexpr int GJ_NB = 16;
 constexpr int GJ_ROWS = 4;
 constexpr int GJ_PANEL_THREADS = 1024;
+constexpr int GJ_RB = 8;     // rows per thread with loads in flight together (k_gj_panel)
 
 // Panel kernel, one workgroup: the steps of the panel's columns, the
 // multipliers into F.  Thread (row group, panel column): every thread of a
@@ -1477,12 +1478,22 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, in
     for (int kk = 0; kk < nb; ++kk) {
         const int k = k0 + kk;
         // pivot: the first unused row with the largest |value| in column k
+        // (a thread's rows are taken GJ_RB at a time, their loads issued
+        // together: the rows lie 2n doubles apart, one cache line each)
         double best = -1.0;
         int arg = -1;
-        for (int r = tid; r < n; r += blockDim.x) {
-            if (used[r]) continue;
-            const double a = fabs(aug[(size_t)r * ld + k]);
-            if (a > best) { best = a; arg = r; }
+        for (int rb = tid; rb < n; rb += GJ_RB * blockDim.x) {
+            double a[GJ_RB];
+            int u[GJ_RB];
+#pragma unroll
+            for (int q = 0; q < GJ_RB; ++q) {
+                const int r = rb + q * blockDim.x;
+                u[q] = (r < n) ? used[r] : 1;
+                a[q] = (r < n) ? fabs(aug[(size_t)r * ld + k]) : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < GJ_RB; ++q)
+                if (!u[q] && a[q] > best) { best = a[q]; arg = rb + q * blockDim.x; }
         }
         for (int d = 32; d >= 1; d >>= 1) {
             const double ov = __shfl_xor(best, d, 64);
@@ -1507,10 +1518,22 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, in
         const int c = k + 1 + cc;
         const bool upd = (c < k0 + nb);
         const double pc = upd ? aug[(size_t)p * ld + c] : 0.0;
-        for (int r = r0; r < n; r += rstep) {
-            const double f = (r == p) ? 0.0 : aug[(size_t)r * ld + k] / piv;
-            if (cc == 0) F[(size_t)r * nb + kk] = f;
-            if (upd && r != p) aug[(size_t)r * ld + c] -= f * pc;
+        for (int rb = r0; rb < n; rb += GJ_RB * rstep) {
+            double a[GJ_RB], x[GJ_RB];
+#pragma unroll
+            for (int q = 0; q < GJ_RB; ++q) {
+                const int r = rb + q * rstep;
+                a[q] = (r < n) ? aug[(size_t)r * ld + k] : 0.0;
+                x[q] = (upd && r < n) ? aug[(size_t)r * ld + c] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < GJ_RB; ++q) {
+                const int r = rb + q * rstep;
+                if (r >= n) break;
+                const double f = (r == p) ? 0.0 : a[q] / piv;
+                if (cc == 0) F[(size_t)r * nb + kk] = f;
+                if (upd && r != p) aug[(size_t)r * ld + c] = x[q] - f * pc;
+            }
         }
         __syncthreads();
     }
