@@ -49,8 +49,19 @@ struct Builder {
     DBuf<uint64_t> s_u1;
     DBuf<unsigned char> s_c1;
     // unknown-based system AMG: the row counts of the unknowns, in row order
-    // (empty for a scalar operator)
+    // (empty for a scalar operator), and a second builder (own stream and
+    // scratch) that coarsens the second unknown of a level concurrently
     std::vector<int> parts;
+    Builder *aux = nullptr;
+    int device = 0;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    Builder() = default;
+    Builder(const Builder &) = delete;
+    Builder &operator=(const Builder &) = delete;
+    ~Builder() {
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+    }
 };
 
 
@@ -482,6 +493,27 @@ static int coarsen_block(Builder *c, const CsrD &Au, const double *dg, int *cf, 
     return nc;
 }
 
+// One unknown's diagonal block (rows and columns [o, o + mu) of L.A)
+// extracted and coarsened; returns its number of C points.
+static int coarsen_unknown(Builder *c, const Level &L, int o, int mu, int *cf, const double *dg, CsrD &P,
+                           bool check_sym) {
+    hipStream_t s = c->stream;
+    CsrD Au;
+    Au.n = Au.ncols = mu;
+    Au.rp_own.alloc((size_t)mu + 1);
+    DBuf<int> cnt;
+    cnt.alloc((size_t)mu + 1);
+    amg_submatrix_count(mu, o, L.A.rp, L.A.ci, cnt.p, s);
+    scan_exclusive(cnt.p, Au.rp_own.p, mu, nullptr, s);
+    Au.rp = Au.rp_own.p;
+    Au.nnz = read_scalar(Au.rp_own.p + mu, s);
+    Au.ci_own.alloc((size_t)Au.nnz + 1);
+    Au.v.alloc((size_t)Au.nnz + 1);
+    amg_submatrix_fill(mu, o, L.A.rp, L.A.ci, L.A.v.p, Au.rp, Au.ci_own.p, Au.v.p, s);
+    Au.ci = Au.ci_own.p;
+    return coarsen_block(c, Au, dg, cf, P, check_sym);
+}
+
 // One level of unknown-based coarsening: the unknowns hold consecutive row
 // ranges (parts) of L.  Each unknown's diagonal block is extracted and
 // coarsened on its own; P = blockdiag(P_u) (its C points ordered unknown by
@@ -494,29 +526,54 @@ static bool coarsen_system(Builder *c, Level &L, std::vector<int> &parts, bool c
     const int m = L.A.n;
     const int nu = (int)parts.size();
     std::vector<CsrD> Ps(nu);
-    std::vector<int> ncs(nu);
+    std::vector<int> ncs(nu), offs(nu, 0);
+    for (int u = 1; u < nu; ++u) offs[u] = offs[u - 1] + parts[u - 1];
     DBuf<int> cf;
     cf.alloc((size_t)m + 1);
-    int o = 0;
-    for (int u = 0; u < nu; ++u) {
-        const int mu = parts[u];
-        CsrD Au;
-        Au.n = Au.ncols = mu;
-        Au.rp_own.alloc((size_t)mu + 1);
-        DBuf<int> cnt;
-        cnt.alloc((size_t)mu + 1);
-        amg_submatrix_count(mu, o, L.A.rp, L.A.ci, cnt.p, s);
-        scan_exclusive(cnt.p, Au.rp_own.p, mu, nullptr, s);
-        Au.rp = Au.rp_own.p;
-        Au.nnz = read_scalar(Au.rp_own.p + mu, s);
-        Au.ci_own.alloc((size_t)Au.nnz + 1);
-        Au.v.alloc((size_t)Au.nnz + 1);
-        amg_submatrix_fill(mu, o, L.A.rp, L.A.ci, L.A.v.p, Au.rp, Au.ci_own.p, Au.v.p, s);
-        Au.ci = Au.ci_own.p;
-        ncs[u] = coarsen_block(c, Au, c->s_d1.p + o, cf.p + o, Ps[u], check_sym && u == 0);
-        if (ncs[u] == 0 || ncs[u] == mu) return false;
-        o += mu;
+    Builder *aux = (nu == 2) ? c->aux : nullptr;
+    if (aux) {
+        // the second unknown on the second builder's stream and host thread:
+        // its stream starts after this level's operator and diagonal are
+        // ready, and this stream resumes once both blocks are coarsened (its
+        // buffers return to its own stream's pool, whose next use is again
+        // ordered after this stream)
+        if (!c->ev_in) CPTR_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+        if (!c->ev_out) CPTR_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+        CPTR_HIP(hipEventRecord(c->ev_in, s));
+        std::exception_ptr err;
+        std::thread t([&]() {
+            try {
+                CPTR_HIP(hipSetDevice(aux->device));
+                StreamScope scope(aux->stream);
+                CPTR_HIP(hipStreamWaitEvent(aux->stream, c->ev_in, 0));
+                if (!aux->flag.p) {
+                    aux->flag.alloc(4);
+                    fill_int(aux->flag.p, 0, 1, aux->stream);
+                }
+                ncs[1] = coarsen_unknown(aux, L, offs[1], parts[1], cf.p + offs[1], c->s_d1.p + offs[1], Ps[1], false);
+                CPTR_HIP(hipEventRecord(c->ev_out, aux->stream));
+            } catch (...) {
+                err = std::current_exception();
+            }
+        });
+        try {
+            ncs[0] = coarsen_unknown(c, L, 0, parts[0], cf.p, c->s_d1.p, Ps[0], check_sym);
+        } catch (...) {
+            t.join();
+            throw;
+        }
+        t.join();
+        if (err) std::rethrow_exception(err);
+        CPTR_HIP(hipStreamWaitEvent(s, c->ev_out, 0));
+    } else {
+        for (int u = 0; u < nu; ++u) {
+            ncs[u] = coarsen_unknown(c, L, offs[u], parts[u], cf.p + offs[u], c->s_d1.p + offs[u], Ps[u],
+                                     check_sym && u == 0);
+            if (ncs[u] == 0 || ncs[u] == parts[u]) return false;
+        }
     }
+    for (int u = 0; u < nu; ++u)
+        if (ncs[u] == 0 || ncs[u] == parts[u]) return false;
     CsrD &P = L.P;
     int nz = 0, nc = 0;
     for (int u = 0; u < nu; ++u) {
@@ -1086,7 +1143,20 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         B.rp.p = ee ? c->ee_rp.p : c->rp.p;
         B.ci.p = ee ? c->ee_ci.p : c->ci.p;
         B.parts.clear();
-        if (ee) B.parts = {n, n};
+        B.aux = nullptr;
+        B.device = c->device;
+        if (ee) {
+            B.parts = {n, n};
+            // the pressure builder is idle in the two-stage scheme: it
+            // coarsens the temperature block of every level concurrently
+            Builder &A2 = c->bld[1];
+            A2.stream = c->side[1];
+            A2.opt = c->opt;
+            A2.device = c->device;
+            A2.parts.clear();
+            A2.aux = nullptr;
+            B.aux = &A2;
+        }
         c->tph[1 + k] = 0.0;
         th[k] = std::thread([c, k, sys, &B, &svals, &err, &refresh, &kept, t_hier]() {
             try {
