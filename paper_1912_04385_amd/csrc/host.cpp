@@ -417,79 +417,116 @@ static void apply_learned(hipStream_t s, Level &L, const float *mlp) {
 }
 
 // ---------------------------------------------------------------------------
-// unknown-based system AMG (two-stage CPTR on B_ee)
+// classical coarsening and interpolation of one scalar operator
 // ---------------------------------------------------------------------------
-// The scalar coarsening of one unknown's diagonal block Au, diagonal dg:
-// strength, PMIS (random measure indexed within the block) and extended+i
-// with truncation, with the kernels and row-kernel choices of the scalar
-// levels.  Writes the C/F split to cf (Au.n entries) and builds P; returns the
-// number of C points (P is left empty when that is 0 or Au.n).
-static int coarsen_block(Builder *c, const CsrD &Au, const double *dg, int *cf, CsrD &P, bool check_sym) {
+// the interpolation's entries before compaction
+struct InterpScratch {
+    DBuf<int> off, tcol;
+    DBuf<double> twt;
+};
+
+// Strength, PMIS (random measure indexed by row) and extended+i with
+// truncation on the scalar operator A with diagonal dg: the C/F split into cf
+// (A.n entries), the strength flags into strong (A.nnz + 1 bytes), the
+// interpolation's entries into the scratch and P's row pointers into
+// P.rp_own (P.rp_own[A.n] = P's nnz, on the device).  Returns the number of C
+// points; P is not formed when that is 0 or A.n.  Row kernels of ext+i: lane
+// groups sized by the row length with the rows fetched into LDS (default),
+// one wavefront per row (1), one thread per row (2), or 8-lane groups on
+// every level (3: rows beyond the groups' LDS caps take the per-row
+// sequential path); all give the same interpolation bit for bit.
+static int interp_rows(Builder *c, const CsrD &A, const double *dg, int *cf, unsigned char *strong, bool check_sym,
+                       InterpScratch &is, CsrD &P) {
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
-    const int m = Au.n;
-    c->s_i1.alloc((size_t)Au.nnz + 1);
-    transpose_index(m, Au.rp, Au.ci, c->s_i1.p, c->flag.p, s);
+    const int m = A.n;
+    c->s_i1.alloc((size_t)A.nnz + 1);      // transpose positions
+    transpose_index(m, A.rp, A.ci, c->s_i1.p, c->flag.p, s);
+    // Galerkin products P^T A P of a structurally symmetric A are symmetric:
+    // only the fine level's pattern needs the check
     if (check_sym && (read_flag_and_clear(c) & 8))
         throw Error(CPTR_E_ARG, "AMG level pattern is not structurally symmetric");
-    DBuf<unsigned char> strong;
-    strong.alloc((size_t)Au.nnz + 1);
-    amg_strength(m, Au.rp, Au.ci, Au.v.p, o.amg_theta, strong.p, s);
-    c->s_i2.alloc((size_t)m + 1);
-    c->s_u1.alloc((size_t)m);
-    c->s_c1.alloc((size_t)m);
-    c->s_i3.alloc(4);
+    amg_strength(m, A.rp, A.ci, A.v.p, o.amg_theta, strong, s);
+    c->s_i2.alloc((size_t)m + 1);          // |S^T|
+    c->s_u1.alloc((size_t)m);              // random measure
+    c->s_c1.alloc((size_t)m);              // new C flags
+    c->s_i3.alloc(4);                      // undecided counter
     fill_int(c->s_i3.p, 0, 1, s);
-    amg_pmis_init(m, Au.rp, Au.ci, strong.p, c->s_i1.p, o.pmis_seed, c->s_i2.p, c->s_u1.p, cf, c->s_i3.p, s);
+    amg_pmis_init(m, A.rp, A.ci, strong, c->s_i1.p, o.pmis_seed, c->s_i2.p, c->s_u1.p, cf, c->s_i3.p, s);
+    // rounds run in batches between reads of the undecided count (a round on
+    // a fully decided level changes nothing); small levels take longer
+    // batches: their rounds are cheap, and their coarsening needs more of them
     const int batch = (m >= PMIS_SMALL_LEVEL) ? PMIS_BATCH : PMIS_BATCH_SMALL;
     int und = 1, rounds = 0;
     while (und > 0) {
         for (int q = 0; q < batch; ++q) {
             fill_int(c->s_i3.p, 0, 1, s);
-            amg_pmis_round(m, Au.rp, Au.ci, strong.p, c->s_i1.p, c->s_i2.p, c->s_u1.p, cf, c->s_c1.p, c->s_i3.p, s);
+            amg_pmis_round(m, A.rp, A.ci, strong, c->s_i1.p, c->s_i2.p, c->s_u1.p, cf, c->s_c1.p, c->s_i3.p, s);
         }
         und = read_scalar(c->s_i3.p, s);
         rounds += batch;
         if (rounds > 10000) throw Error(CPTR_E_STATE, "PMIS did not terminate");
     }
-    DBuf<int> cidx, ub, off, cnt, tcol;
-    DBuf<double> twt, td;
+    // coarse numbering and the ext+i capacity bound, read together
+    DBuf<int> cidx, ub, cnt;
+    DBuf<double> td;
     cidx.alloc((size_t)m + 1);
     scan_exclusive(cf, cidx.p, m, nullptr, s);
     ub.alloc(m + 1);
-    off.alloc(m + 1);
+    is.off.alloc(m + 1);
     cnt.alloc(m + 1);
-    const double avg_row = (double)Au.nnz / (double)m;
+    const double avg_row = (double)A.nnz / (double)m;
     const int ek = o.setup_kernels;
-    amg_exti_bound(m, Au.rp, Au.ci, strong.p, cf, ub.p, ek == 1 || (ek == 0 && avg_row > EXTI_SHORT_ROW), s);
-    scan_exclusive(ub.p, off.p, m, nullptr, s);
+    amg_exti_bound(m, A.rp, A.ci, strong, cf, ub.p, ek == 1 || (ek == 0 && avg_row > EXTI_SHORT_ROW), s);
+    scan_exclusive(ub.p, is.off.p, m, nullptr, s);
     int rd[3];
-    read_ints3(c, cidx.p + m, off.p + m, nullptr, rd);
+    read_ints3(c, cidx.p + m, is.off.p + m, nullptr, rd);
     const int nc = rd[0], cap = rd[1];
     if (nc == 0 || nc == m) return nc;
-    tcol.alloc(cap);
-    twt.alloc(cap);
-    td.alloc((size_t)Au.nnz + 1);
+    is.tcol.alloc(cap);
+    is.twt.alloc(cap);
+    td.alloc((size_t)A.nnz + 1);
     if (ek == 2)
-        amg_exti_compute2(m, Au.rp, Au.ci, Au.v.p, strong.p, cf, cidx.p, dg, o.amg_pmax, off.p, tcol.p, twt.p, td.p,
-                          cnt.p, s);
+        amg_exti_compute2(m, A.rp, A.ci, A.v.p, strong, cf, cidx.p, dg, o.amg_pmax, is.off.p, is.tcol.p, is.twt.p,
+                          td.p, cnt.p, s);
     else if (ek == 1)
-        amg_exti_compute_wave(m, Au.rp, Au.ci, Au.v.p, strong.p, cf, cidx.p, dg, o.amg_pmax, off.p, tcol.p, twt.p,
-                              td.p, cnt.p, s);
+        amg_exti_compute_wave(m, A.rp, A.ci, A.v.p, strong, cf, cidx.p, dg, o.amg_pmax, is.off.p, is.tcol.p,
+                              is.twt.p, td.p, cnt.p, s);
     else
         amg_exti_compute_group(m, (ek == 3 || avg_row <= EXTI_SHORT_ROW) ? 8 : avg_row <= EXTI_HALF_WAVE_ROW ? 32 : 64,
-                               Au.rp, Au.ci, Au.v.p, strong.p, cf, cidx.p, dg, o.amg_pmax, off.p, tcol.p, twt.p, td.p,
-                               cnt.p, s);
+                               A.rp, A.ci, A.v.p, strong, cf, cidx.p, dg, o.amg_pmax, is.off.p, is.tcol.p, is.twt.p,
+                               td.p, cnt.p, s);
     P.n = m;
     P.ncols = nc;
     P.rp_own.alloc((size_t)m + 1);
     scan_exclusive(cnt.p, P.rp_own.p, m, nullptr, s);
     P.rp = P.rp_own.p;
-    P.nnz = read_scalar(P.rp_own.p + m, s);
+    return nc;
+}
+
+// P's columns and weights once its nnz (P.nnz) is known
+static void compact_interp(Builder *c, InterpScratch &is, CsrD &P) {
     P.ci_own.alloc((size_t)P.nnz + 1);
     P.v.alloc((size_t)P.nnz + 1);
-    amg_compact(m, off.p, tcol.p, twt.p, P.rp_own.p, P.ci_own.p, P.v.p, s);
+    amg_compact(P.n, is.off.p, is.tcol.p, is.twt.p, P.rp_own.p, P.ci_own.p, P.v.p, c->stream);
     P.ci = P.ci_own.p;
+}
+
+// ---------------------------------------------------------------------------
+// unknown-based system AMG (two-stage CPTR on B_ee)
+// ---------------------------------------------------------------------------
+// The scalar coarsening of one unknown's diagonal block Au, diagonal dg
+// (interp_rows, then P's size read and P compacted): the C/F split into cf
+// (Au.n entries) and P; returns the number of C points (P is left empty when
+// that is 0 or Au.n).
+static int coarsen_block(Builder *c, const CsrD &Au, const double *dg, int *cf, CsrD &P, bool check_sym) {
+    DBuf<unsigned char> strong;
+    strong.alloc((size_t)Au.nnz + 1);
+    InterpScratch is;
+    const int nc = interp_rows(c, Au, dg, cf, strong.p, check_sym, is, P);
+    if (nc == 0 || nc == Au.n) return nc;
+    P.nnz = read_scalar(P.rp_own.p + Au.n, c->stream);
+    compact_interp(c, is, P);
     return nc;
 }
 
@@ -652,94 +689,21 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
             h.L.push_back(std::move(nxt));
             continue;
         }
-        // strength and PMIS
-        c->s_i1.alloc((size_t)L.A.nnz + 1);    // transpose positions
-        transpose_index(m, L.A.rp, L.A.ci, c->s_i1.p, c->flag.p, s);
-        // Galerkin products P^T A P of a structurally symmetric A are symmetric:
-        // only the fine level's pattern needs the check
-        if (h.L.size() == 1 && (read_flag_and_clear(c) & 8))
-            throw Error(CPTR_E_ARG, "AMG level pattern is not structurally symmetric");
         L.strong.alloc((size_t)L.A.nnz + 1);
-        amg_strength(m, L.A.rp, L.A.ci, L.A.v.p, o.amg_theta, L.strong.p, s);
-        c->s_i2.alloc((size_t)m + 1);          // |S^T|
-        c->s_u1.alloc((size_t)m);              // random measure
         L.cf.alloc((size_t)m + 1);             // state -> C/F
-        c->s_c1.alloc((size_t)m);              // new C flags
-        c->s_i3.alloc(4);                      // undecided counter
-        fill_int(c->s_i3.p, 0, 1, s);
-        amg_pmis_init(m, L.A.rp, L.A.ci, L.strong.p, c->s_i1.p, o.pmis_seed, c->s_i2.p, c->s_u1.p, L.cf.p,
-                      c->s_i3.p, s);
-        // rounds run in batches between reads of the undecided count (a round
-        // on a fully decided level changes nothing)
-        // (small levels take longer batches: their rounds are cheap, and
-        // their coarsening needs more of them)
-        const int batch = (m >= PMIS_SMALL_LEVEL) ? PMIS_BATCH : PMIS_BATCH_SMALL;
-        int und = 1, rounds = 0;
-        while (und > 0) {
-            for (int q = 0; q < batch; ++q) {
-                fill_int(c->s_i3.p, 0, 1, s);
-                amg_pmis_round(m, L.A.rp, L.A.ci, L.strong.p, c->s_i1.p, c->s_i2.p, c->s_u1.p, L.cf.p, c->s_c1.p,
-                               c->s_i3.p, s);
-            }
-            und = read_scalar(c->s_i3.p, s);
-            rounds += batch;
-            if (rounds > 10000) throw Error(CPTR_E_STATE, "PMIS did not terminate");
-        }
-        // coarse numbering and the ext+i capacity bound, read together.  Row
-        // kernels: lane groups sized by the row length, with the rows fetched
-        // into LDS (default), one wavefront per row (1), one thread per row
-        // (2), or 8-lane groups on every level (3: rows beyond the groups'
-        // LDS caps take the per-row sequential path); all give the same
-        // interpolation bit for bit.
-        DBuf<int> cidx;
-        cidx.alloc((size_t)m + 1);
-        scan_exclusive(L.cf.p, cidx.p, m, nullptr, s);
-        DBuf<int> ub, off, cnt, tcol;
-        DBuf<double> twt, td;
-        ub.alloc(m + 1);
-        off.alloc(m + 1);
-        cnt.alloc(m + 1);
-        const double avg_row = (double)L.A.nnz / (double)m;
-        const int ek = o.setup_kernels;
-        amg_exti_bound(m, L.A.rp, L.A.ci, L.strong.p, L.cf.p, ub.p, ek == 1 || (ek == 0 && avg_row > EXTI_SHORT_ROW),
-                       s);
-        scan_exclusive(ub.p, off.p, m, nullptr, s);
-        int rd[3];
-        read_ints3(c, cidx.p + m, off.p + m, nullptr, rd);
-        const int nc = rd[0], cap = rd[1];
+        InterpScratch is;
+        const int nc = interp_rows(c, L.A, c->s_d1.p, L.cf.p, L.strong.p, h.L.size() == 1, is, L.P);
         if (nc == 0 || nc == m) break;
-        // extended+i interpolation
-        tcol.alloc(cap);
-        twt.alloc(cap);
-        td.alloc((size_t)L.A.nnz + 1);
-        if (ek == 2)
-            amg_exti_compute2(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
-                              tcol.p, twt.p, td.p, cnt.p, s);
-        else if (ek == 1)
-            amg_exti_compute_wave(m, L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax,
-                                  off.p, tcol.p, twt.p, td.p, cnt.p, s);
-        else
-            amg_exti_compute_group(m,
-                                   (ek == 3 || avg_row <= EXTI_SHORT_ROW) ? 8 : avg_row <= EXTI_HALF_WAVE_ROW ? 32 : 64,
-                                   L.A.rp, L.A.ci, L.A.v.p, L.strong.p, L.cf.p, cidx.p, c->s_d1.p, o.amg_pmax, off.p,
-                                   tcol.p, twt.p, td.p, cnt.p, s);
-        CsrD &P = L.P;
-        P.n = m;
-        P.ncols = nc;
-        P.rp_own.alloc((size_t)m + 1);
-        scan_exclusive(cnt.p, P.rp_own.p, m, nullptr, s);
-        P.rp = P.rp_own.p;
         // A P needs only P's row pointers for its plan: P's size and the
         // product's capacity in one read
+        CsrD &P = L.P;
         SpgPlan pAP;
         spgemm_plan(c, L.A, P, pAP);
+        int rd[3];
         read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
         P.nnz = rd[0];
         const int capAP = rd[1], maxAP = rd[2];
-        P.ci_own.alloc((size_t)P.nnz + 1);
-        P.v.alloc((size_t)P.nnz + 1);
-        amg_compact(m, off.p, tcol.p, twt.p, P.rp_own.p, P.ci_own.p, P.v.p, s);
-        P.ci = P.ci_own.p;
+        compact_interp(c, is, P);
         L.nc = nc;
         if (mlp && h.L.size() == 1) apply_learned(s, L, mlp);
         csr_transpose(c, P, L.R);
