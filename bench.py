@@ -214,44 +214,54 @@ def solve_probe(args, dev) -> int:
 
 
 EXACT_STUDY_PECLET = ((0.01, "diffusion dominated"), (1.0, "neutral"), (100.0, "advection dominated"))
+EXACT_STUDY_GRIDS = (16, 32, 64, 128, 256)
+EXACT_STUDY_DENSE_MAX = 64       # B_ee of an n x n grid has 2 n^2 rows: at most 8192 for the dense inverse
 
 
-def exact_study(args, dev, n: int = 64) -> int:
-    """The Schur-complement quality study: GMRES(30) iterations of CPR, CPTR3
-    and the two-stage CPTR scheme when every AMG stage applies its operator
-    exactly (dense inverse; B_ee has 2 n^2 = 8192 rows at n = 64), beside the
-    same solvers with AMG, on homogeneous n x n, b = 6 systems at a diffusion
-    dominated, a neutral and an advection dominated Peclet number.  Plain FP64
-    on the GPU; one setup + solve per entry."""
+def exact_study(args, dev) -> int:
+    """The paper's comparison of the preconditioners by GMRES iterations:
+    ILU(0) alone, CPR, CPTR3 and the two-stage CPTR scheme, with AMG
+    sub-solves and -- where the operators fit the dense inverse (B_ee of an
+    n x n grid has 2 n^2 rows) -- with exact ones (the Schur-complement
+    quality study), on homogeneous n x n, b = 6 systems at a diffusion
+    dominated, a neutral and an advection dominated Peclet number, n from 16
+    to 256.  GMRES(30), plain FP64 on the GPU, BILU(0) in 32 x 8 tiles; one
+    setup + solve per entry."""
     import numpy as np
     import torch
     from paper_1912_04385_amd import cptr
     from synthetic import assemble
 
-    variants = (("CPR", cptr.VARIANT_CPR), ("CPTR3", cptr.VARIANT_CPTR3), ("CPTR two-stage", cptr.VARIANT_CPTR))
+    variants = (("ILU0", cptr.VARIANT_LAST_ONLY), ("CPR", cptr.VARIANT_CPR), ("CPTR3", cptr.VARIANT_CPTR3),
+                ("CPTR two-stage", cptr.VARIANT_CPTR))
     rows = []
     for k, (pe, regime) in enumerate(EXACT_STUDY_PECLET):
-        sy = assemble(n, n, 6, np.ones((n, n)), peclet=pe, seed=k, field_seed=k)
-        rp, ci = torch.from_numpy(sy.row_ptr).to(dev), torch.from_numpy(sy.col_idx).to(dev)
-        vals, rhs = torch.from_numpy(sy.vals.reshape(-1)).to(dev), torch.from_numpy(sy.rhs).to(dev)
-        for vname, v in variants:
-            for sub in (1, 0):
-                sol = cptr.Solver(variant=v, exact_subsolves=sub, restart=30, max_iters=500, ilu_tile_x=32,
-                                  ilu_tile_y=8)
-                try:
-                    sol.setup(rp, ci, vals, 0, 1, n, n)
-                    _, res = sol.solve(rhs)
-                finally:
-                    sol.close()
-                row = {"peclet": pe, "regime": regime, "variant": vname,
-                       "subsolves": "exact" if sub else "AMG", "iterations": res["iterations"],
-                       "converged": res["converged"], "rel_res": res["rel_res_scaled"],
-                       "setup_ms": round(res["setup_ms"], 2), "solve_ms": round(res["solve_ms"], 2)}
-                rows.append(row)
-                print(f"# Pe {pe:g} {vname:15s} {row['subsolves']:5s}: its={row['iterations']} "
-                      f"setup={row['setup_ms']} ms solve={row['solve_ms']} ms", file=sys.stderr, flush=True)
-    print(json.dumps({"study": "exact sub-solves vs AMG (Schur-complement quality)",
-                      "grid": f"{n}x{n}, b=6, homogeneous k=1", "krylov": "GMRES(30), FP64, tol 1e-8",
+        for n in EXACT_STUDY_GRIDS:
+            sy = assemble(n, n, 6, np.ones((n, n)), peclet=pe, seed=k, field_seed=k)
+            rp, ci = torch.from_numpy(sy.row_ptr).to(dev), torch.from_numpy(sy.col_idx).to(dev)
+            vals, rhs = torch.from_numpy(sy.vals.reshape(-1)).to(dev), torch.from_numpy(sy.rhs).to(dev)
+            for vname, v in variants:
+                subs = (0,) if v == cptr.VARIANT_LAST_ONLY else ((1, 0) if n <= EXACT_STUDY_DENSE_MAX else (0,))
+                for sub in subs:
+                    sol = cptr.Solver(variant=v, exact_subsolves=sub, restart=30, max_iters=600, ilu_tile_x=32,
+                                      ilu_tile_y=8)
+                    try:
+                        sol.setup(rp, ci, vals, 0, 1, n, n)
+                        _, res = sol.solve(rhs)
+                    finally:
+                        sol.close()
+                    label = "none" if v == cptr.VARIANT_LAST_ONLY else ("exact" if sub else "AMG")
+                    row = {"peclet": pe, "regime": regime, "grid": n, "variant": vname, "subsolves": label,
+                           "iterations": res["iterations"], "converged": res["converged"],
+                           "rel_res": res["rel_res_scaled"], "setup_ms": round(res["setup_ms"], 2),
+                           "solve_ms": round(res["solve_ms"], 2)}
+                    rows.append(row)
+                    print(f"# Pe {pe:g} {n:4d}^2 {vname:15s} {label:5s}: its={row['iterations']} "
+                          f"conv={row['converged']} setup={row['setup_ms']} ms solve={row['solve_ms']} ms",
+                          file=sys.stderr, flush=True)
+    print(json.dumps({"study": "preconditioners by GMRES iterations: exact sub-solves vs AMG, grid sweep",
+                      "grids": list(EXACT_STUDY_GRIDS), "block": 6, "permeability": "homogeneous k=1",
+                      "krylov": "GMRES(30), FP64, tol 1e-8, at most 600 iterations",
                       "last_stage": "BILU(0) in 32x8 tiles", "rows": rows}))
     return 0
 
