@@ -16,7 +16,8 @@ if not torch.cuda.is_available():
 
 from paper_1912_04385_amd import cptr  # noqa: E402
 
-VARIANTS = {O.CPTR3: cptr.VARIANT_CPTR3, O.CPR: cptr.VARIANT_CPR, O.CPTR: cptr.VARIANT_CPTR}
+VARIANTS = {O.CPTR3: cptr.VARIANT_CPTR3, O.CPR: cptr.VARIANT_CPR, O.CPTR: cptr.VARIANT_CPTR,
+            O.BJ_ONLY: cptr.VARIANT_LAST_ONLY}
 
 
 def test_empty_system_is_rejected():
@@ -31,7 +32,7 @@ def test_empty_system_is_rejected():
         sv.close()
 
 
-@pytest.mark.parametrize("variant", [O.CPTR3, O.CPR, O.CPTR])
+@pytest.mark.parametrize("variant", [O.CPTR3, O.CPR, O.CPTR, O.BJ_ONLY])
 @pytest.mark.parametrize("nx,ny,b", [(1, 1, 3), (2, 1, 2), (40, 1, 4), (1, 37, 6)])
 def test_degenerate_grid_solve(nx, ny, b, variant):
     print(f"case degenerate grid {nx}x{ny} b={b} variant={variant}", flush=True)

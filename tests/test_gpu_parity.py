@@ -181,7 +181,7 @@ def test_solve_config2(index):
 
 
 @pytest.mark.parametrize("case", ["b2", "ragged_tiles", "big_tiles", "single_level", "bjacobi", "cpr", "p_then_t", "restart5",
-                                  "l1jacobi", "sweeps2"])
+                                  "l1jacobi", "sweeps2", "ilu0_only"])
 def test_solve_variants(case):
     print(f"case solve variant {case}", flush=True)
     kw, tile = {}, (32, 8)
@@ -207,6 +207,9 @@ def test_solve_variants(case):
     elif case == "sweeps2":
         kw["amg_pre"] = 2
         kw["amg_post"] = 2
+    elif case == "ilu0_only":
+        kw["variant"] = O.BJ_ONLY
+        kw["max_iters"] = 400
     okw = dict(kw)
     gkw = {k: v for k, v in kw.items() if not k.startswith("amg_")}
     if "amg_max_coarse" in kw:
@@ -217,7 +220,7 @@ def test_solve_variants(case):
         gkw["pre_sweeps"], gkw["post_sweeps"] = kw["amg_pre"], kw["amg_post"]
     ref = O.solve(s, _oracle_opts(s, tile=tile, **okw))
     if "variant" in gkw:
-        gkw["variant"] = {O.CPTR3: 0, O.CPR: 1}[gkw["variant"]]
+        gkw["variant"] = {O.CPTR3: 0, O.CPR: 1, O.BJ_ONLY: 3}[gkw["variant"]]
     solver = cptr.solver_for(s, ilu_tile_x=tile[0], ilu_tile_y=tile[1], **gkw)
     x, res = solver.solve(_t(s.rhs))
     solver.close()
