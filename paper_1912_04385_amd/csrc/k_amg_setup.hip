@@ -1539,16 +1539,17 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, in
     }
 }
 
-// The same panel steps with the panel's columns (and the used flags) held in
-// LDS for the whole panel (n <= GJ_LDS_ROWS), padded to an odd row stride.
+// The same panel steps for at most GJ_LDS_ROWS rows, one thread per row with
+// the row's panel values and multipliers in registers.  Each step's pivot row
+// is the one value set another thread needs: its owner publishes it in LDS.
 // The pivot of column k is chosen by a 32-bit key: the top 22 bits of |value|
 // (its exponent and 11 mantissa bits) above 10 bits of (1023 - row), so the
 // pivot is an unused row whose |value| is within 2^-11 of the column's
 // largest (the lower row among equal keys); the keys meet in an LDS atomicMax,
-// filled for column k + 1 by the lanes that update it in step k, so each step
-// takes one barrier.  Multipliers use the pivot's reciprocal.
+// filled for column k + 1 by the lanes that update it in step k.  Two barriers
+// per step: after the pivot row is published, and after the next keys.
+// Multipliers use the pivot's reciprocal.
 constexpr int GJ_LDS_ROWS = GJ_PANEL_THREADS;
-constexpr int GJ_LDS_LD = GJ_NB + 1;
 
 __device__ inline unsigned gj_key(double a, int r) {
     const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(a));
@@ -1557,11 +1558,9 @@ __device__ inline unsigned gj_key(double a, int r) {
 
 __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel_lds(int n, int k0, int nb, double *aug, int *used,
                                                                     int *pivrow, double *F, int *flag) {
-    // one thread per row: the row's panel values and multipliers in
-    // registers, every row's current values in LDS for the pivot row's
-    // broadcast; the multipliers and pivots reach global memory at the end
-    // (a barrier also waits for pending global stores)
-    __shared__ double pan[GJ_LDS_ROWS * GJ_LDS_LD];
+    // the multipliers and pivots reach global memory at the end (a barrier
+    // also waits for pending global stores)
+    __shared__ double prow[GJ_NB];
     __shared__ unsigned K[3];
     __shared__ int piv[GJ_NB];
     const size_t ld = 2 * (size_t)n;
@@ -1578,10 +1577,7 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel_lds(int n, int k0
         usedr = used[r] != 0;
 #pragma unroll
         for (int q = 0; q < GJ_NB; ++q)
-            if (q < nb) {
-                row[q] = aug[(size_t)r * ld + k0 + q];
-                pan[r * GJ_LDS_LD + q] = row[q];
-            }
+            if (q < nb) row[q] = aug[(size_t)r * ld + k0 + q];
     }
     if (r < 3) K[r] = 0u;
     __syncthreads();
@@ -1590,54 +1586,51 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel_lds(int n, int k0
     if (lane == 0 && key) atomicMax(&K[0], key);
     __syncthreads();
     int done = nb;
-    for (int kk = 0; kk < nb; ++kk) {
-        // K[kk % 3] is complete; K[(kk + 1) % 3] collects the next column's
-        // keys; K[(kk + 2) % 3] was read one step ago and is cleared for reuse
-        const unsigned kv = K[kk % 3];
-        const int p = 1023 - (int)(kv & 1023u);
-        if ((kv >> 10) == 0u) {
-            done = kk;
-            break;
-        }
-        if (r == 0) {
-            piv[kk] = p;
-            K[(kk + 2) % 3] = 0u;
-        }
-        const double rinv = 1.0 / pan[p * GJ_LDS_LD + kk];
-        if (own) {
-            double ak = 0.0;
+    // the steps unrolled: the register arrays are then indexed by constants
+    // (go and the step test are uniform over the workgroup, so every thread
+    // meets the same barriers)
+    bool go = true;
 #pragma unroll
-            for (int q = 0; q < GJ_NB; ++q)
-                if (q == kk) ak = row[q];
-            const double f = (r == p) ? 0.0 : ak * rinv;
-#pragma unroll
-            for (int q = 0; q < GJ_NB; ++q)
-                if (q == kk) fr[q] = f;
-            if (r == p) {
-                usedr = true;
+    for (int kk = 0; kk < GJ_NB; ++kk) {
+        if (go && kk < nb) {
+            // K[kk % 3] is complete; K[(kk + 1) % 3] collects the next
+            // column's keys; K[(kk + 2) % 3] was read one step ago and is
+            // cleared for reuse
+            const unsigned kv = K[kk % 3];
+            const int p = 1023 - (int)(kv & 1023u);
+            if ((kv >> 10) == 0u) {
+                done = kk;
+                go = false;
             } else {
+                if (r == 0) {
+                    piv[kk] = p;
+                    K[(kk + 2) % 3] = 0u;
+                }
+                if (r == p) {
 #pragma unroll
-                for (int q = 0; q < GJ_NB; ++q)
-                    if (q > kk && q < nb) row[q] -= f * pan[p * GJ_LDS_LD + q];
+                    for (int q = kk; q < GJ_NB; ++q)
+                        if (q < nb) prow[q] = row[q];
+                }
+                __syncthreads();   // the pivot row is published
+                const double rinv = 1.0 / prow[kk];
+                unsigned nkey = 0u;
+                if (own) {
+                    const double f = (r == p) ? 0.0 : row[kk] * rinv;
+                    fr[kk] = f;
+                    if (r == p) {
+                        usedr = true;
+                    } else {
+#pragma unroll
+                        for (int q = kk + 1; q < GJ_NB; ++q)
+                            if (q < nb) row[q] -= f * prow[q];
+                    }
+                    if (!usedr && kk + 1 < nb) nkey = gj_key(row[kk + 1 < GJ_NB ? kk + 1 : kk], r);
+                }
+                for (int d = 32; d >= 1; d >>= 1) nkey = max(nkey, (unsigned)__shfl_xor((int)nkey, d, 64));
+                if (lane == 0 && nkey) atomicMax(&K[(kk + 1) % 3], nkey);
+                __syncthreads();   // every thread has read the pivot row; the next keys are in
             }
         }
-        __syncthreads();   // every thread has read the pivot row
-        unsigned nkey = 0u;
-        if (own) {
-#pragma unroll
-            for (int q = 0; q < GJ_NB; ++q)
-                if (q > kk && q < nb) pan[r * GJ_LDS_LD + q] = row[q];
-            if (!usedr && kk + 1 < nb) {
-                double an = 0.0;
-#pragma unroll
-                for (int q = 0; q < GJ_NB; ++q)
-                    if (q == kk + 1) an = row[q];
-                nkey = gj_key(an, r);
-            }
-        }
-        for (int d = 32; d >= 1; d >>= 1) nkey = max(nkey, (unsigned)__shfl_xor((int)nkey, d, 64));
-        if (lane == 0 && nkey) atomicMax(&K[(kk + 1) % 3], nkey);
-        __syncthreads();
     }
     __syncthreads();
     if (done < nb && r == 0) atomicOr(flag, 64);
