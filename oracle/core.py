@@ -7,6 +7,9 @@ reduced (primary) system, ``Abar = N^{-1} A`` the left-scaled matrix, ``B_PP``
 the pressure block after the first decoupling (Eq. CPTR31), ``C_TT`` the
 temperature block after the second (Eq. CPTR32), ``M_i`` the stages of the
 right preconditioner (Eq. multistageprec, Algorithms 1 and 2).
+
+TEST INFRASTRUCTURE, like the rest of ``oracle``: only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` use it.
 """
 from __future__ import annotations
 
