@@ -147,24 +147,28 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_offsets(int *bsum, int nb
     }
 }
 
-// the whole scan in one block, tile after tile (short inputs)
+// the whole scan in one block, tile after tile (short inputs); wider tiles
+// than the multi-block scan's, so that the chain of tiles stays short: each
+// thread takes SCAN1_ITEMS consecutive values, their loads issued together
+constexpr int SCAN1_ITEMS = 32;
+constexpr int SCAN1_TILE = SCAN_THREADS * SCAN1_ITEMS;
+
 __global__ void __launch_bounds__(SCAN_THREADS) k_scan_single(const int *in, int n, int *out, int *out_total,
                                                               int *out_total2) {
     __shared__ int lds[33];
     int carry = 0;
-    for (long t0 = 0; t0 < n; t0 += SCAN_TILE) {
-        const long base = t0 + threadIdx.x * SCAN_ITEMS;
-        int v[SCAN_ITEMS];
+    for (long t0 = 0; t0 < n; t0 += SCAN1_TILE) {
+        const long base = t0 + (long)threadIdx.x * SCAN1_ITEMS;
+        int v[SCAN1_ITEMS];
+#pragma unroll
+        for (int k = 0; k < SCAN1_ITEMS; ++k) v[k] = (base + k < n) ? in[base + k] : 0;
         int sum = 0;
 #pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; ++k) {
-            v[k] = (base + k < n) ? in[base + k] : 0;
-            sum += v[k];
-        }
+        for (int k = 0; k < SCAN1_ITEMS; ++k) sum += v[k];
         int tot;
         int e = block_scan_excl(sum, lds, &tot) + carry;
 #pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; ++k) {
+        for (int k = 0; k < SCAN1_ITEMS; ++k) {
             if (base + k < n) out[base + k] = e;
             e += v[k];
         }
