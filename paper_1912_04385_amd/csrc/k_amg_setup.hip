@@ -1508,8 +1508,15 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel(int n, int k0, in
             for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
                 if (wi[w] >= 0 && (a0 < 0 || wv[w] > b0 || (wv[w] == b0 && wi[w] < a0))) { b0 = wv[w]; a0 = wi[w]; }
             sp = (a0 >= 0 && b0 != 0.0) ? a0 : -1;
-            if (sp < 0) atomicOr(flag, 64);
-            else { pivrow[k] = a0; used[a0] = 1; }
+            if (sp < 0) {
+                // singular: the remaining pivots of the panel name row 0 (the
+                // kernels queued behind this one stay inside the matrix)
+                atomicOr(flag, 64);
+                for (int q = k; q < k0 + nb; ++q) pivrow[q] = 0;
+            } else {
+                pivrow[k] = a0;
+                used[a0] = 1;
+            }
         }
         __syncthreads();
         const int p = sp;
@@ -1634,7 +1641,10 @@ __global__ void __launch_bounds__(GJ_PANEL_THREADS) k_gj_panel_lds(int n, int k0
     }
     __syncthreads();
     if (done < nb && r == 0) atomicOr(flag, 64);
-    if (r < done) pivrow[k0 + r] = piv[r];
+    // (after a singular column the remaining pivots name row 0, so that the
+    // kernels still queued behind this one index inside the matrix; the call
+    // reports the singular operator)
+    if (r < nb) pivrow[k0 + r] = (r < done) ? piv[r] : 0;
     if (own) {
 #pragma unroll
         for (int q = 0; q < GJ_NB; ++q)

@@ -76,3 +76,22 @@ def test_one_context_many_shapes(variant):
             assert err <= 1e-10
     finally:
         solver.close()
+
+
+def test_singular_coarse_operator_is_reported():
+    """Two cells, b = 2, no pressure-temperature coupling, C_TT = [[1, 1], [1,
+    1]]: its dense inverse (a single-level hierarchy) meets an exactly zero
+    pivot, and setup reports the singular coarsest operator."""
+    print("case singular coarse operator", flush=True)
+    rp = np.array([0, 2, 4], np.int32)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    diag = [[2.0, 0.0], [0.0, 1.0]]
+    off = [[-1.0, 0.0], [0.0, 1.0]]
+    vals = np.array([diag, off, off, diag], np.float64).reshape(-1)
+    sv = cptr.Solver(ilu_tile_x=32, ilu_tile_y=8)
+    try:
+        with pytest.raises(cptr.CptrError, match="singular coarsest AMG operator") as ei:
+            sv.setup(torch.from_numpy(rp), torch.from_numpy(ci), torch.from_numpy(vals), 0, 1, 2, 1)
+        assert ei.value.status == -3
+    finally:
+        sv.close()
