@@ -176,7 +176,10 @@ cptr_status cptr_setup(cptr_ctx *ctx, int32_t n_cells, int32_t b, int32_t nnzb,
  * is kept if rho < options.reuse_rho_max and rebuilt from scratch otherwise.
  * reuse_rho_max <= 0 rebuilds always.  The next cptr_solve reports rho_T,
  * rho_P and the kept hierarchies in cptr_result.reused.  d_vals: device,
- * nnzb*b*b, same layout as in cptr_setup; copied. */
+ * nnzb*b*b, same layout as in cptr_setup; copied.  On an error (a non-finite
+ * entry, a singular block) the context is left without a valid setup:
+ * cptr_solve and cptr_update_values return CPTR_E_STATE until the next
+ * successful cptr_setup. */
 cptr_status cptr_update_values(cptr_ctx *ctx, const double *d_vals);
 
 /* Solve A x = b: d_rhs (device, n_cells*b) in, d_x (device) out.  Returns

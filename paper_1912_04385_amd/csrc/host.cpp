@@ -1035,10 +1035,16 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     c->wp.alloc((size_t)n * b);
     c->wt.alloc((size_t)n * b);
     c->beta.alloc(n);
-    count_nonfinite(vals, (size_t)nnzb * b * b, c->flag.p, s);
-    if (read_flag_and_clear(c) & 16) throw Error(CPTR_E_NONFINITE, "non-finite matrix entry");
+    // s_i4[0]: the lowest singular cell of the decoupling; s_i4[1]: the
+    // non-finite flag of the values, whose scan runs on a side stream beside
+    // phase 1 (both come back in one read)
     c->s_i4.alloc(2);
     fill_int(c->s_i4.p, 0x7fffffff, 1, s);
+    fill_int(c->s_i4.p + 1, 0, 1, s);
+    CPTR_HIP(hipEventRecord(c->ev_side[2], s));
+    CPTR_HIP(hipStreamWaitEvent(c->side[2], c->ev_side[2], 0));
+    count_nonfinite(vals, (size_t)nnzb * b * b, c->s_i4.p + 1, c->side[2]);
+    CPTR_HIP(hipEventRecord(c->ev_side[2], c->side[2]));
     c->slabT.alloc((size_t)nnzb * b);
     c->slabP.alloc((size_t)nnzb * b);
     DBuf<double> &ctt = c->ctt, &bpp = c->bpp;
@@ -1067,7 +1073,11 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         launch_decouple_weights(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
                                 c->beta.p, c->s_i4.p, ctt.p, bpp.p, nullptr, nullptr, nullptr, s);
     }
-    int bad = read_scalar(c->s_i4.p, s);
+    CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[2], 0));
+    int chk[2];
+    read_bytes(chk, c->s_i4.p, 2 * sizeof(int), s);
+    if (chk[1] & 16) throw Error(CPTR_E_NONFINITE, "non-finite matrix entry");
+    int bad = chk[0];
     if (bad != 0x7fffffff)
         throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block (D_ss or Ahat_PP) in cell " + std::to_string(bad));
     // scalar stages: the two hierarchies are built concurrently, each on its

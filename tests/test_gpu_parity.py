@@ -241,6 +241,39 @@ def test_nonfinite_rhs_is_rejected():
     solver.close()
 
 
+@pytest.mark.parametrize("variant", [0, 2, 3])
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_matrix_is_rejected(variant, bad):
+    """A non-finite matrix entry is reported (status -4) by setup and by
+    update_values, before a singular decoupling block elsewhere in the same
+    matrix; after the failed update the context needs a new setup, which
+    works."""
+    print(f"case non-finite matrix variant={variant} value={bad}", flush=True)
+    s = config1()
+    vals = s.vals.copy()
+    vals[7, 1, 2] = bad
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    d13 = np.nonzero((rows == 13) & (s.col_idx == 13))[0][0]
+    vals[d13, 2, :] = 0.0                     # D_ss of cell 13 singular as well
+    solver = cptr.Solver(variant=variant)
+    try:
+        with pytest.raises(cptr.CptrError) as e:
+            solver.setup(_t(s.row_ptr), _t(s.col_idx), _t(vals.reshape(-1)), 0, 1, s.nx, s.ny)
+        assert e.value.status == -4
+        solver.setup(_t(s.row_ptr), _t(s.col_idx), _t(s.vals.reshape(-1)), 0, 1, s.nx, s.ny)
+        with pytest.raises(cptr.CptrError) as e:
+            solver.update_values(_t(vals.reshape(-1)))
+        assert e.value.status == -4
+        with pytest.raises(cptr.CptrError) as e:
+            solver.solve(_t(s.rhs))
+        assert e.value.status == -6
+        solver.setup(_t(s.row_ptr), _t(s.col_idx), _t(s.vals.reshape(-1)), 0, 1, s.nx, s.ny)
+        x, res = solver.solve(_t(s.rhs))
+        assert res["converged"] == 1
+    finally:
+        solver.close()
+
+
 def test_singular_block_names_the_cell():
     s = tiny(6, 5, 4, seed=1)
     rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
