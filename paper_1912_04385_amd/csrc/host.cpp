@@ -593,14 +593,21 @@ static bool coarsen_system(Builder *c, Level &L, std::vector<int> &parts, bool c
                 err = std::current_exception();
             }
         });
+        // on an error, the second stream's queued work (which reads this
+        // level) ends before the exception leaves
         try {
             ncs[0] = coarsen_unknown(c, L, 0, parts[0], cf.p, c->s_d1.p, Ps[0], check_sym);
         } catch (...) {
             t.join();
+            (void)hipStreamSynchronize(aux->stream);
             throw;
         }
         t.join();
-        if (err) std::rethrow_exception(err);
+        if (err) {
+            (void)hipStreamSynchronize(aux->stream);
+            (void)hipStreamSynchronize(s);
+            std::rethrow_exception(err);
+        }
         CPTR_HIP(hipStreamWaitEvent(s, c->ev_out, 0));
     } else {
         for (int u = 0; u < nu; ++u) {
