@@ -1222,7 +1222,12 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     for (int k = 0; k < 2; ++k)
         if (th[k].joinable()) th[k].join();
     for (int k = 0; k < 2; ++k)
-        if (err[k]) std::rethrow_exception(err[k]);
+        if (err[k]) {
+            // a failed build may leave work queued on the side streams that
+            // reads the context's arrays: it ends before the error returns
+            for (int j = 0; j < 3; ++j) (void)hipStreamSynchronize(c->side[j]);
+            std::rethrow_exception(err[k]);
+        }
     c->reused = kept.load();
     for (int k = 0; k < 2; ++k)
         if (need[k]) CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[k], 0));
