@@ -337,6 +337,36 @@ def test_fp32_preconditioner_fgmres(index):
     assert np.linalg.norm(r) / np.linalg.norm(s.rhs) <= 2e-8
 
 
+@pytest.mark.parametrize("variant,last,order,tile", [(1, 0, 0, (32, 8)), (0, 1, 0, (32, 8)), (0, 0, 1, (16, 16)),
+                                                   (3, 0, 0, (32, 8)), (2, 1, 0, (7, 5))])
+def test_fp32_preconditioner_variants(variant, last, order, tile):
+    """The FP32 instantiations of the other stages (CPR, block Jacobi as the
+    last stage, pressure first, the last stage alone, the two-stage scheme
+    with block Jacobi in ragged tiles) inside FP64 FGMRES(50) reach the FP64
+    true residual 1e-8 recomputed by the oracle, within three iterations of
+    the plain FP64 oracle solve (ten per cent on long solves)."""
+    print(f"case fp32 variant={variant} last={last} order={order} tile={tile}", flush=True)
+    s = config2(1)
+    ov = {0: O.CPTR3, 1: O.CPR, 2: O.CPTR, 3: O.BJ_ONLY}[variant]
+    ref = O.solve(s, _oracle_opts(s, tile=tile, krylov=O.FGMRES, restart=50, variant=ov, stage_order=order,
+                                  last_stage=O.LAST_BJACOBI if last else O.LAST_BILU0, max_iters=600))
+    solver = cptr.solver_for(s, krylov=cptr.FGMRES, restart=50, precond_precision=cptr.FP32, variant=variant,
+                             last_stage=last, stage_order=order, ilu_tile_x=tile[0], ilu_tile_y=tile[1],
+                             max_iters=600)
+    try:
+        x, res = solver.solve(_t(s.rhs))
+    finally:
+        solver.close()
+    x = x.cpu().numpy()
+    dec = O.decouple(O.bsr_of(s), s.rhs, variant=ov)
+    r = dec.rhsbar - dec.Abar.matvec(x)
+    rel = np.linalg.norm(r) / np.linalg.norm(dec.rhsbar)
+    print(f"  fp32 its={res['iterations']} fp64 oracle its={ref.iterations} oracle-recomputed rel={rel:.2e}",
+          flush=True)
+    assert res["converged"] == 1 and rel <= 1e-8 * (1 + 1e-6)
+    assert res["iterations"] <= max(ref.iterations + 3, int(1.1 * ref.iterations))
+
+
 def test_fp32_needs_fgmres():
     with pytest.raises(cptr.CptrError):
         cptr.Solver(precond_precision=cptr.FP32, krylov=cptr.GMRES)
