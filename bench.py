@@ -536,8 +536,9 @@ def main() -> int:
 
     its32 = [r["iterations"] for r in res32]
     out = {
-        "metric": "solves/s to an FP64 true relative residual of 1e-8 (setup + solve), FP32-preconditioned "
-                  "CPTR3 FGMRES(50) vs plain FP64",
+        "metric": "time to 1e-8 FP64 residual + HBM GB/s: FP32/learned CPR-T vs plain FP64 -- reported as solves/s "
+                  "(setup + solve) of FP32-preconditioned CPTR3 FGMRES(50), plain FP64 in fp64_plain, HBM GB/s in "
+                  "roofline, the learned interpolation in --workload c4",
         "value": round(1000.0 / ms32, 4),
         "unit": "solves/s",
         "n_gpus": 1,
