@@ -77,7 +77,11 @@ enum { CPTR_FP64 = 0, CPTR_FP32 = 1 };
 enum { CPTR_SMOOTH_JACOBI = 0, CPTR_SMOOTH_L1JACOBI = 1 };
 /* fine-level interpolation of the temperature AMG stage: classical
  * extended+i, the learned correction judged against it by the V-cycle
- * convergence factor, or the learned correction without the judge */
+ * convergence factor, or the learned correction without the judge.  The
+ * judge runs at the first full build of the temperature hierarchy after
+ * cptr_setup (or cptr_load_mlp); later full builds through
+ * cptr_update_values with reuse on (reuse_rho_max > 0) follow its choice
+ * without judging again (rho_T_classical / rho_T_learned then read -1) */
 enum { CPTR_INTERP_CLASSICAL = 0, CPTR_INTERP_LEARNED = 1, CPTR_INTERP_LEARNED_FORCED = 2 };
 
 typedef struct {

@@ -155,3 +155,41 @@ def test_judge_keeps_classical_when_the_correction_is_zero():
     r = O.solve(s, opts)
     assert r.learned["rho_learned"] == r.learned["rho_classical"]
     assert r.learned["used"] is False
+
+
+def test_judge_once_per_sequence():
+    """Within a sequence with reuse on, the first full build of the
+    temperature hierarchy judges the learned interpolation; later full builds
+    follow that choice without judging (convergence factors reported as -1)
+    and build the same hierarchy as an explicit learned or classical setup.
+    Without reuse every system is judged."""
+    from synthetic import generator as G
+    perm = G.config5_field(48, 24)
+    systems = [G.config5(k, perm, nx=48, ny=24) for k in range(3)]
+    p = L.unpack(mlp_init(1).astype(np.float64))
+    p["W3"] *= 100.0
+    p["b1"][:] = 0.02
+    params = L.pack(p)
+
+    def opts(thr):
+        return O.Options(color=O.tile_colors(48, 24), amg=O.AMGOptions(max_coarse=30), mlp_params=params,
+                         reuse_rho_max=thr)
+
+    # a threshold no refreshed hierarchy meets: every system rebuilds both
+    r0 = O.solve(systems[0], opts(1e-9))
+    assert r0.learned["rho_classical"] > 0 and r0.reuse_state["T_learned"] == r0.learned["used"]
+    prev = r0
+    for s in systems[1:]:
+        r = O.solve(s, opts(1e-9), previous=prev)
+        assert r.learned["rho_classical"] == -1.0 and r.learned["rho_learned"] == -1.0
+        assert r.learned["used"] == r0.learned["used"]
+        A = r.dec.Abar.scalar_block(1, 1)
+        h = O.amg_setup(A, opts(1e-9).amg, L.learned_interp(params) if r0.learned["used"] else None)
+        got = r.hierarchies["T"]
+        assert len(got.levels) == len(h.levels)
+        for a, b in zip(got.levels[:-1], h.levels[:-1]):
+            assert np.array_equal(a.P.ci, b.P.ci) and np.array_equal(a.P.v, b.P.v)
+        prev = r
+    # reuse off: judged again
+    r1 = O.solve(systems[1], opts(0.0), previous=r0)
+    assert r1.learned["rho_classical"] > 0
