@@ -81,3 +81,45 @@ def test_exact_subsolve_beyond_the_dense_limit_is_rejected():
     s = tiny(100, 90, 3, seed=1)                       # 9000 rows > 8192
     with pytest.raises(cptr.CptrError, match="dense limit"):
         cptr.solver_for(s, exact_subsolves=1)
+
+
+@pytest.mark.parametrize("variant", [O.CPTR3, O.CPTR])
+def test_exact_subsolves_fp32_preconditioner(variant):
+    """Exact sub-solves inside the FP32 preconditioner (the dense inverses'
+    FP32 copies) reach the FP64 true residual 1e-8 recomputed by the oracle."""
+    print(f"case exact sub-solves fp32 variant={variant}", flush=True)
+    s = _case("t32x24b6")
+    solver = cptr.solver_for(s, variant=GPU_VARIANT[variant], exact_subsolves=1, krylov=cptr.FGMRES,
+                             precond_precision=cptr.FP32, ilu_tile_x=32, ilu_tile_y=8)
+    try:
+        x, res = solver.solve(_t(s.rhs))
+    finally:
+        solver.close()
+    dec = O.decouple(O.bsr_of(s), s.rhs, variant=variant)
+    r = dec.rhsbar - dec.Abar.matvec(x.cpu().numpy())
+    rel = np.linalg.norm(r) / np.linalg.norm(dec.rhsbar)
+    print(f"  its={res['iterations']} rel={rel:.2e}", flush=True)
+    assert res["converged"] == 1 and rel <= 1e-8 * (1 + 1e-6)
+
+
+def test_exact_subsolves_over_a_sequence():
+    """update_values with reuse on keeps the single-level hierarchies and
+    recomputes their dense inverses from the new values: each system solves
+    to the oracle's exact-sub-solve solution."""
+    print("case exact sub-solves over a sequence", flush=True)
+    systems = [tiny(32, 24, 6, peclet=5.0, seed=21 + k) for k in range(3)]
+    solver = cptr.solver_for(systems[0], variant=cptr.VARIANT_CPTR3, exact_subsolves=1, reuse_rho_max=0.3,
+                             ilu_tile_x=32, ilu_tile_y=8)
+    try:
+        for k, s in enumerate(systems):
+            if k > 0:
+                solver.update_values(torch.from_numpy(s.vals.reshape(-1)))
+            x, res = solver.solve(_t(s.rhs))
+            ref = O.solve(s, O.Options(color=O.tile_colors(s.nx, s.ny, 32, 8), variant=O.CPTR3,
+                                       exact_subsolves=True))
+            x = x.cpu().numpy()
+            err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+            print(f"  system {k}: gpu its={res['iterations']} oracle its={ref.iterations} err={err:.2e}", flush=True)
+            assert res["converged"] == 1 and abs(res["iterations"] - ref.iterations) <= 1 and err <= 1e-10
+    finally:
+        solver.close()
