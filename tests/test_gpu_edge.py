@@ -95,3 +95,31 @@ def test_singular_coarse_operator_is_reported():
         assert ei.value.status == -3
     finally:
         sv.close()
+
+
+def test_setup_without_grid_shape():
+    """Without the grid shape (nx = ny = 0) the block-Jacobi last stage works
+    on any BSR pattern and matches the oracle; BILU(0), whose order needs the
+    grid, is rejected."""
+    from synthetic import config1
+    print("case setup without grid shape", flush=True)
+    s = config1()
+    ref = O.solve(s, O.Options(color=O.tile_colors(s.nx, s.ny, 32, 8), last_stage=O.LAST_BJACOBI))
+    sv = cptr.Solver(last_stage=cptr.LAST_BJACOBI)
+    try:
+        sv.setup(torch.from_numpy(s.row_ptr), torch.from_numpy(s.col_idx), torch.from_numpy(s.vals.reshape(-1)),
+                 0, 1, 0, 0)
+        x, res = sv.solve(torch.from_numpy(s.rhs).cuda())
+    finally:
+        sv.close()
+    err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+    print(f"  gpu its={res['iterations']} oracle its={ref.iterations} err={err:.2e}", flush=True)
+    assert res["converged"] == 1 and abs(res["iterations"] - ref.iterations) <= 1 and err <= 1e-10
+    sv = cptr.Solver()
+    try:
+        with pytest.raises(cptr.CptrError, match="grid shape") as ei:
+            sv.setup(torch.from_numpy(s.row_ptr), torch.from_numpy(s.col_idx),
+                     torch.from_numpy(s.vals.reshape(-1)), 0, 1, 0, 0)
+        assert ei.value.status == -1
+    finally:
+        sv.close()
