@@ -74,7 +74,10 @@ enum { CPTR_T_THEN_P = 0, CPTR_P_THEN_T = 1 };
 enum { CPTR_LAST_BILU0 = 0, CPTR_LAST_BJACOBI = 1 };
 enum { CPTR_GMRES = 0, CPTR_FGMRES = 1 };
 enum { CPTR_FP64 = 0, CPTR_FP32 = 1 };
-enum { CPTR_SMOOTH_JACOBI = 0, CPTR_SMOOTH_L1JACOBI = 1 };
+/* AMG smoother: damped Jacobi, l1-Jacobi, or the Chebyshev iteration on
+ * D^{-1} A over [lambda/30, 1.1 lambda] with lambda the Gershgorin bound
+ * max_i sum_j |a_ij| / |a_ii| of each level (degree cheb_degree per sweep) */
+enum { CPTR_SMOOTH_JACOBI = 0, CPTR_SMOOTH_L1JACOBI = 1, CPTR_SMOOTH_CHEBYSHEV = 2 };
 /* fine-level interpolation of the temperature AMG stage: classical
  * extended+i, the learned correction judged against it by the V-cycle
  * convergence factor, or the learned correction without the judge.  The
@@ -119,6 +122,9 @@ typedef struct {
                                 /* B_ee), by a dense inverse on the GPU; setup    */
                                 /* fails with CPTR_E_ARG when an operator has     */
                                 /* more than 8192 rows (0)                        */
+    int32_t cheb_degree;        /* Chebyshev smoother: degree per sweep (2); the  */
+                                /* pre-smoothing is one Chebyshev iteration of    */
+                                /* degree cheb_degree * pre_sweeps, likewise post */
 } cptr_options;
 
 typedef struct {

@@ -20,7 +20,7 @@ T_THEN_P, P_THEN_T = 0, 1
 LAST_BILU0, LAST_BJACOBI = 0, 1
 GMRES, FGMRES = 0, 1
 FP64, FP32 = 0, 1
-SMOOTH_JACOBI, SMOOTH_L1JACOBI = 0, 1
+SMOOTH_JACOBI, SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1, 2
 INTERP_CLASSICAL, INTERP_LEARNED, INTERP_LEARNED_FORCED = 0, 1, 2
 MLP_NPARAMS = 5313
 
@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
         ("post_sweeps", ctypes.c_int32), ("jacobi_omega", ctypes.c_double), ("pmis_seed", ctypes.c_uint64),
         ("ilu_tile_x", ctypes.c_int32), ("ilu_tile_y", ctypes.c_int32), ("t_interp", ctypes.c_int32),
         ("reuse_rho_max", ctypes.c_double), ("timing", ctypes.c_int32), ("setup_kernels", ctypes.c_int32),
-        ("exact_subsolves", ctypes.c_int32),
+        ("exact_subsolves", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
     ]
 
 

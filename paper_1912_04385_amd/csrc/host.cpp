@@ -659,6 +659,25 @@ static bool coarsen_system(Builder *c, Level &L, std::vector<int> &parts, bool c
     return true;
 }
 
+// Chebyshev smoother: the Gershgorin bound of level l into the hierarchy's
+// device array, and all levels' bounds to the host in one read
+static void level_bound(Builder *c, Hierarchy &h, int l) {
+    if (c->opt.smoother != CPTR_SMOOTH_CHEBYSHEV) return;
+    const Level &L = h.L[l];
+    amg_gershgorin(L.A.n, L.A.rp, L.A.ci, L.A.v.p, h.lam_dev.p + l, c->stream);
+}
+
+static void read_bounds(Builder *c, Hierarchy &h) {
+    if (c->opt.smoother != CPTR_SMOOTH_CHEBYSHEV) return;
+    std::vector<unsigned long long> bits(h.L.size());
+    read_bytes(bits.data(), h.lam_dev.p, sizeof(unsigned long long) * bits.size(), c->stream);
+    for (size_t l = 0; l < h.L.size(); ++l) {
+        double q;
+        std::memcpy(&q, &bits[l], sizeof q);
+        h.L[l].lam_max = q;
+    }
+}
+
 // `own` (optional): the buffer holding vals, taken over as the fine level's
 // values instead of copying them.  With c->parts set, the operator holds
 // several unknowns and is coarsened unknown by unknown.
@@ -670,6 +689,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
     h.L.clear();
     h.L.emplace_back();
     std::vector<int> parts = c->parts;
+    if (o.smoother == CPTR_SMOOTH_CHEBYSHEV) h.lam_dev.alloc((size_t)o.amg_max_levels + 1);
     {
         Level &L0 = h.L.back();
         L0.A.n = c->n;
@@ -690,6 +710,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         L.dinv.alloc(m);
         c->s_d1.alloc(m);   // diagonal of this level
         amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
+        level_bound(c, h, (int)h.L.size() - 1);
         level_vectors(L, m, fp32);
         // (exact sub-solves: the fine level is the coarsest, applied by its
         // dense inverse)
@@ -730,6 +751,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         spgemm_finish(c, pRAP, read_scalar(nxt.A.rp_own.p + nc, s), nxt.A);
         h.L.push_back(std::move(nxt));
     }
+    read_bounds(c, h);
     coarse_inverse(c, h);
     hierarchy_fp32(c, h);
     CPTR_HIP(hipStreamSynchronize(s));
@@ -745,6 +767,7 @@ static void refresh_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     if (!h.built || h.L.empty()) throw Error(CPTR_E_STATE, "no hierarchy to reuse");
+    if (o.smoother == CPTR_SMOOTH_CHEBYSHEV) h.lam_dev.alloc((size_t)h.L.size() + 1);
     Level &L0 = h.L[0];
     if (own && own->p == vals && own->n >= (size_t)c->nnzb)
         L0.A.v = std::move(*own);
@@ -755,12 +778,14 @@ static void refresh_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf
         const int m = L.A.n;
         c->s_d1.alloc(m);
         amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
+        level_bound(c, h, (int)l);
         if (l + 1 == h.L.size()) break;
         CsrD AP, Ac;
         csr_spgemm(c, L.A, L.P, AP);
         csr_spgemm(c, L.R, AP, Ac);
         h.L[l + 1].A = std::move(Ac);
     }
+    read_bounds(c, h);
     coarse_inverse(c, h);
     hierarchy_fp32(c, h);
     CPTR_HIP(hipStreamSynchronize(s));
@@ -785,6 +810,32 @@ template <> struct Prec<float> {
     static const float *dinv(const Level &L) { return L.dinv32.p; }
 };
 
+// One Chebyshev iteration of the given degree on A x = b, in place on x (from
+// zero when `zero`), over [lam/30, 1.1 lam] of the spectrum of D^{-1} A with
+// lam the level's Gershgorin bound; r and d[0], d[1] are work vectors
+template <class T>
+static void cheb_smooth(const Level &L, const T *v, const T *dinv, const T *b, T *x, bool zero, int degree, T *r,
+                        T *const *d, hipStream_t s) {
+    const int n = L.A.n;
+    if (degree == 0) {
+        if (zero) CPTR_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, s));
+        return;
+    }
+    const double lmax = 1.1 * L.lam_max, lmin = L.lam_max / 30.0;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    vc_cheb_init<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, b, zero ? nullptr : x, x, r, d[0], (T)theta, s);
+    int cur = 0;
+    for (int k = 0; k < degree; ++k) {
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        const double c1 = rho_new * rho, c2 = 2.0 * rho_new / delta;
+        vc_cheb_step<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, d[cur], x, r, d[1 - cur], (T)c1, (T)c2, s);
+        cur = 1 - cur;
+        rho = rho_new;
+    }
+}
+
 template <class T>
 static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     Level &L = h.L[lvl];
@@ -805,6 +856,20 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     // buffers: x (the level's result) and three spares of the same length
     T *const X = x;
     T *spare[3] = {Prec<T>::r(L), Prec<T>::r(L) + n, Prec<T>::r(L) + 2 * (size_t)n};
+    if (o.smoother == CPTR_SMOOTH_CHEBYSHEV) {
+        // Chebyshev smoothing before and after the coarse correction, each one
+        // Chebyshev iteration of degree cheb_degree * sweeps, in place on X
+        Level &Lc = h.L[lvl + 1];
+        T *r = spare[0];
+        T *const d[2] = {spare[1], spare[2]};
+        cheb_smooth<T>(L, v, dinv, b, X, true, o.cheb_degree * o.pre_sweeps, r, d, s);
+        vc_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, b, X, r, s);
+        vc_spmv<T>(L.R.n, L.R.nnz, L.R.rp, L.R.ci, Prec<T>::v(L.R), r, Prec<T>::b(Lc), s);
+        const T *xc = vcycle<T>(c, h, lvl + 1, s);
+        vc_prolong_to<T>(n, L.P.nnz, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, X, X, s);
+        cheb_smooth<T>(L, v, dinv, b, X, false, o.cheb_degree * o.post_sweeps, r, d, s);
+        return X;
+    }
     // pre-smoothing from zero; every further sweep fused with the next residual
     T *xa = X, *ra = spare[0];
     const T *rres = b;   // what is restricted
@@ -960,6 +1025,9 @@ static void validate_options(const cptr_options &o) {
     if (o.pre_sweeps < 0 || o.post_sweeps < 0) throw Error(CPTR_E_ARG, "negative smoothing sweeps");
     if (o.setup_kernels < 0 || o.setup_kernels > 3) throw Error(CPTR_E_ARG, "setup_kernels must be 0, 1, 2 or 3");
     if (o.exact_subsolves != 0 && o.exact_subsolves != 1) throw Error(CPTR_E_ARG, "exact_subsolves must be 0 or 1");
+    if (o.smoother < CPTR_SMOOTH_JACOBI || o.smoother > CPTR_SMOOTH_CHEBYSHEV) throw Error(CPTR_E_ARG, "unknown smoother");
+    if (o.smoother == CPTR_SMOOTH_CHEBYSHEV && (o.cheb_degree < 1 || o.cheb_degree > 16))
+        throw Error(CPTR_E_ARG, "cheb_degree must be 1..16");
     if (o.t_interp < CPTR_INTERP_CLASSICAL || o.t_interp > CPTR_INTERP_LEARNED_FORCED)
         throw Error(CPTR_E_ARG, "unknown t_interp");
     if (o.t_interp != CPTR_INTERP_CLASSICAL && (o.amg_pmax < 1 || o.amg_pmax > 16))
@@ -1429,6 +1497,7 @@ cptr_status cptr_default_options(cptr_options *o) {
     o->timing = 0;
     o->setup_kernels = 0;
     o->exact_subsolves = 0;
+    o->cheb_degree = 2;
     return CPTR_OK;
 }
 

@@ -103,6 +103,7 @@ struct Level {
     DBuf<double> dinv;      // 1 / smoothing diagonal
     DBuf<float> dinv32;
     DBuf<int> cf;           // 1 = C, 0 = F (not on the coarsest level)
+    double lam_max = 0.0;   // Gershgorin bound of the spectrum of D^{-1} A (Chebyshev smoother)
     CsrD P, R;
     int nc = 0;
     // V-cycle work vectors
@@ -116,6 +117,7 @@ struct Hierarchy {
     std::vector<Level> L;
     int ncoarse = 0;
     DBuf<double> cinv;      // dense inverse of the coarsest operator, row-major
+    DBuf<unsigned long long> lam_dev;   // per-level Gershgorin bounds (Chebyshev smoother), as bits
     DBuf<float> cinv32;
     bool built = false;
 };
@@ -196,6 +198,9 @@ void amg_submatrix_fill(int m, int o, const int *rp, const int *ci, const double
                         double *sv, hipStream_t st);
 // out[i] = in[i] + add, i < n
 void amg_offset_copy(int n, const int *in, int add, int *out, hipStream_t st);
+// *out = the bit pattern of max_i sum_j |a_ij| / |a_ii| (a Gershgorin bound of
+// the spectrum of D^{-1} A), for the Chebyshev smoother
+void amg_gershgorin(int n, const int *rp, const int *ci, const double *v, unsigned long long *out, hipStream_t st);
 void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
                    int *flag, hipStream_t st);
 // F: n * 16 doubles, U: 16 * 2n doubles (panel multipliers and pivot rows)
@@ -222,6 +227,12 @@ void vc_smooth(int n, int nnz, const int *rp, const int *ci, const T *v, const T
 template <class T>
 void vc_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *b, const T *x, T *r,
                  hipStream_t st);
+template <class T>
+void vc_cheb_init(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, const T *b, const T *x,
+                  T *x0, T *r, T *d, T theta, hipStream_t st);
+template <class T>
+void vc_cheb_step(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, const T *din, T *x, T *r,
+                  T *dout, T c1, T c2, hipStream_t st);
 template <class T>
 void vc_dense_apply(int n, const T *Minv, const T *b, T *x, hipStream_t st);
 void vc_dense_apply_mixed(int n, const double *Minv, const float *b, float *x, hipStream_t st);

@@ -1430,6 +1430,32 @@ void amg_offset_copy(int n, const int *in, int add, int *out, hipStream_t st) {
     CPTR_CHECK_LAUNCH();
 }
 
+// Gershgorin bound of the spectrum of D^{-1} A: the largest row ratio
+// sum_j |a_ij| / |a_ii| (row sums in entry order), maximised through the bit
+// patterns of the non-negative doubles
+__global__ void k_gershgorin(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const double *__restrict__ v, unsigned long long *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0, d = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        s += fabs(v[e]);
+        if (ci[e] == i) d = v[e];
+    }
+    const double q = s / fabs(d);
+    atomicMax(out, (unsigned long long)__double_as_longlong(q));
+}
+
+__global__ void k_zero_u64(unsigned long long *p) {
+    if (threadIdx.x == 0) *p = 0ull;
+}
+
+void amg_gershgorin(int n, const int *rp, const int *ci, const double *v, unsigned long long *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, out);
+    if (n > 0) hipLaunchKernelGGL(k_gershgorin, dim3((n + 255) / 256), dim3(256), 0, st, n, rp, ci, v, out);
+    CPTR_CHECK_LAUNCH();
+}
+
 void amg_diag_inv2(int n, const int *rp, const int *ci, const double *v, int smoother, double *dinv, double *diag,
                    int *flag, hipStream_t st) {
     if (n == 0) return;

@@ -188,6 +188,75 @@ void vc_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const
     csr_op<T, OP_RESIDUAL>(n, nnz, rp, ci, v, x, nullptr, (T)0, b, nullptr, nullptr, r, st);
 }
 
+// Chebyshev smoothing: the Chebyshev iteration on D^{-1} A over an interval
+// [lmin, lmax] of its spectrum (three-term recurrence; theta and delta the
+// interval's centre and half-width):
+//   start  r = D^{-1} (b - A x),  d = r / theta   (x = 0: r = D^{-1} b, x set to 0)
+//   step   x += d,  r -= D^{-1} A d,  d' = c1 d + c2 r
+// with c1 = rho' rho, c2 = 2 rho' / delta and rho' = 1 / (2 theta / delta - rho)
+// from rho = delta / theta, computed by the caller.  G lanes per row as above.
+template <class T, int G, bool INIT>
+__global__ void __launch_bounds__(256) k_cheb(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                              const T *__restrict__ v, const T *__restrict__ dinv,
+                                              const T *__restrict__ b, const T *xs, T *x, T *r, T *dout, T theta,
+                                              T c1, T c2) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), sub = (int)(t % G);
+    const bool act = i < n;
+    T acc = 0;
+    if (act && xs) {
+        const int e1 = rp[i + 1];
+        for (int e = rp[i] + sub; e < e1; e += G) acc += v[e] * xs[ci[e]];
+    }
+    if constexpr (G > 1) {
+#pragma unroll
+        for (int d = G / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, G);
+    }
+    if (!act || sub != 0) return;
+    if constexpr (INIT) {
+        const T ri = (b[i] - acc) * dinv[i];
+        r[i] = ri;
+        dout[i] = ri / theta;
+        if (!xs) x[i] = (T)0;
+    } else {
+        const T di = xs[i];
+        x[i] = x[i] + di;
+        const T ri = r[i] - acc * dinv[i];
+        r[i] = ri;
+        dout[i] = c1 * di + c2 * ri;
+    }
+}
+
+template <class T, bool INIT>
+static void cheb_launch(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, const T *b,
+                        const T *xs, T *x, T *r, T *dout, T theta, T c1, T c2, hipStream_t st) {
+    if (n == 0) return;
+    const int G = lanes_for(n, nnz);
+    const int blocks = nblocks((long)n * G, 256);
+#define CASE(GG)                                                                                               \
+    case GG:                                                                                                   \
+        hipLaunchKernelGGL((k_cheb<T, GG, INIT>), dim3(blocks), dim3(256), 0, st, n, rp, ci, v, dinv, b, xs, x, r, \
+                           dout, theta, c1, c2);                                                               \
+        break;
+    switch (G) { CASE(1) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64) }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+// start of a Chebyshev smoothing from x (x == nullptr: from zero, written to x0)
+template <class T>
+void vc_cheb_init(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, const T *b, const T *x,
+                  T *x0, T *r, T *d, T theta, hipStream_t st) {
+    cheb_launch<T, true>(n, nnz, rp, ci, v, dinv, b, x, x0, r, d, theta, (T)0, (T)0, st);
+}
+
+// one Chebyshev step: x += din, r -= D^{-1} A din, dout = c1 din + c2 r
+template <class T>
+void vc_cheb_step(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, const T *din, T *x, T *r,
+                  T *dout, T c1, T c2, hipStream_t st) {
+    cheb_launch<T, false>(n, nnz, rp, ci, v, dinv, nullptr, din, x, r, dout, (T)1, c1, c2, st);
+}
+
 // coarsest level: x = Ainv b (dense, one wavefront per row); accumulation in
 // double in both precisions (the coarse solve stays FP64)
 template <class T>
@@ -308,6 +377,10 @@ void vc_sub(int n, const double *x, double *e, hipStream_t st) {
     template void vc_sweep_residual<T>(int, int, const int *, const int *, const T *, const T *, T, const T *,   \
                                        const T *, const T *, T *, T *, hipStream_t);                            \
     template void vc_prolong_add<T>(int, int, const int *, const int *, const T *, const T *, T *, hipStream_t); \
+    template void vc_cheb_init<T>(int, int, const int *, const int *, const T *, const T *, const T *, const T *,  \
+                                  T *, T *, T *, T, hipStream_t);                                                  \
+    template void vc_cheb_step<T>(int, int, const int *, const int *, const T *, const T *, const T *, T *, T *,   \
+                                  T *, T, T, hipStream_t);                                                         \
     template void vc_prolong_to<T>(int, int, const int *, const int *, const T *, const T *, const T *, T *,     \
                                    hipStream_t);                                                                 \
     template void vc_smooth<T>(int, int, const int *, const int *, const T *, const T *, T, const T *, const T *, \

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle.core as OC
 from synthetic import tiny
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -207,6 +208,50 @@ def test_other_smoothers_converge(smoother):
     M = poisson2d(16, 16, shift=0.01)
     h = O.amg_setup(csr_from_dense(M), O.AMGOptions(max_coarse=20, smoother=smoother))
     assert O.conv_factor(h, cycles=10) < 0.6
+
+
+def _cheb_level(M):
+    A = csr_from_dense(M)
+    L = O.Level(A, A.diagonal())
+    OC._smoother_setup(L, O.AMGOptions(smoother=O.SMOOTH_CHEBYSHEV))
+    return L
+
+
+def test_chebyshev_gershgorin_bound():
+    """lam_max is the Gershgorin bound max_i sum_j |a_ij| / |a_ii| (hand value
+    on a 3 x 3 matrix) and bounds the spectrum of D^{-1} A from above."""
+    M = np.array([[4.0, -1.0, 0.0], [-2.0, 5.0, -2.0], [0.0, -3.0, 2.0]])
+    assert _cheb_level(M).lam_max == 2.5                 # row 2: (3 + 2) / 2
+    M = poisson2d(7, 6, shift=0.2)
+    L = _cheb_level(M)
+    ev = np.linalg.eigvals(M / np.diag(M)[:, None])
+    assert np.max(np.abs(ev)) <= L.lam_max * (1 + 1e-14)
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 5])
+@pytest.mark.parametrize("zero_start", [True, False])
+def test_chebyshev_error_polynomial(degree, zero_start):
+    """The error after a degree-k Chebyshev iteration is p_k(D^{-1} A) e_0 with
+    p_k(t) = T_k((theta - t) / delta) / T_k(theta / delta) over the interval
+    [lam/30, 1.1 lam]; T_k here from the matrix form of the Chebyshev
+    polynomials' own recurrence T_{k+1} = 2 Z T_k - T_{k-1}."""
+    rng = np.random.default_rng(degree)
+    M = poisson2d(6, 5, shift=0.1) + np.diag(rng.uniform(0, 2, 30))
+    L = _cheb_level(M)
+    b = rng.standard_normal(30)
+    x0 = None if zero_start else rng.standard_normal(30)
+    xs = np.linalg.solve(M, b)
+    x = O.smooth(L, O.AMGOptions(smoother=O.SMOOTH_CHEBYSHEV, cheb_degree=degree), b, x0, 1)
+    lo, hi = L.lam_max / 30.0, 1.1 * L.lam_max
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    Z = (theta * np.eye(30) - M / np.diag(M)[:, None]) / delta
+    Tm, T = np.eye(30), Z.copy()
+    tm, t = 1.0, theta / delta
+    for _ in range(degree - 1):
+        Tm, T = T, 2 * Z @ T - Tm
+        tm, t = t, 2 * (theta / delta) * t - tm
+    e0 = xs - (np.zeros(30) if x0 is None else x0)
+    assert np.allclose(xs - x, (T / t) @ e0, rtol=0, atol=1e-12 * np.abs(e0).max())
 
 
 def test_hierarchy_on_generated_temperature_block():
