@@ -468,6 +468,9 @@ def main() -> int:
                     help="Jacobi pre- and post-smoothing sweeps of the V-cycles (2 for every workload: two damped "
                          "Jacobi sweeps each way stand in for the paper's symmetric Gauss-Seidel smoother, and on "
                          "c5 they keep fresh hierarchies at rho < 0.3, so that the 0.3 reuse threshold can be met)")
+    ap.add_argument("--smoother", choices=["jacobi", "l1jacobi", "chebyshev"], default="jacobi",
+                    help="AMG smoother of the c3 workload (the other workloads use damped Jacobi)")
+    ap.add_argument("--cheb-degree", type=int, default=2, help="Chebyshev degree per sweep (--smoother chebyshev)")
     ap.add_argument("--tile", type=int, nargs=2, default=(64, 8), metavar=("TX", "TY"),
                     help="BILU(0) tile shape")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -540,8 +543,12 @@ def main() -> int:
                   f"unscaled={r['rel_res_unscaled']:.2e}", file=sys.stderr, flush=True)
         return dt * 1000.0 / args.steps, results
 
+    smoother = {"jacobi": cptr.SMOOTH_JACOBI, "l1jacobi": cptr.SMOOTH_L1JACOBI,
+                "chebyshev": cptr.SMOOTH_CHEBYSHEV}[args.smoother]
     common = dict(restart=50, timing=1, pre_sweeps=args.sweeps, post_sweeps=args.sweeps, ilu_tile_x=args.tile[0],
-                  ilu_tile_y=args.tile[1])
+                  ilu_tile_y=args.tile[1], smoother=smoother, cheb_degree=args.cheb_degree)
+    smooth_label = {"jacobi": "Jacobi", "l1jacobi": "l1-Jacobi",
+                    "chebyshev": f"Chebyshev degree {args.cheb_degree} x"}[args.smoother]
     fp32 = cptr.Solver(krylov=cptr.FGMRES, precond_precision=cptr.FP32, **common)
     ms32, res32 = timed(fp32, "fp32-precond")
     fp32.close()
@@ -583,7 +590,7 @@ def main() -> int:
         "config": {"workload": f"config3: {args.nx}x{args.ny} cells, b=8 ({args.nx * args.ny * 8} unknowns), "
                                f"channelised ln-sigma 2, Pe 0.1 and 100 alternating",
                    "krylov": "FGMRES(50)",
-                   "preconditioner": f"CPTR3 (T-AMG, P-AMG with Jacobi {args.sweeps}+{args.sweeps} V-cycles, "
+                   "preconditioner": f"CPTR3 (T-AMG, P-AMG with {smooth_label} {args.sweeps}+{args.sweeps} V-cycles, "
                                      f"BILU(0) in {args.tile[0]}x{args.tile[1]} tiles), FP32",
                    "tol": 1e-8},
         "iterations": its32,
