@@ -663,6 +663,19 @@ static bool coarsen_system(Builder *c, Level &L, std::vector<int> &parts, bool c
 // device array, and all levels' bounds to the host in one read
 static void level_bound(Builder *c, Hierarchy &h, int l) {
     if (c->opt.smoother != CPTR_SMOOTH_CHEBYSHEV) return;
+    if (!h.lam_dev.p || (size_t)l >= h.lam_dev.n) {
+        // room for 32 levels at first, doubled when a hierarchy goes deeper;
+        // the bounds of the levels above are kept
+        DBuf<unsigned long long> grown;
+        grown.alloc(std::max<size_t>(32, 2 * (size_t)l));
+        if (l > 0 && h.lam_dev.p) {
+            CPTR_HIP(hipMemcpyAsync(grown.p, h.lam_dev.p, sizeof(unsigned long long) * l, hipMemcpyDeviceToDevice,
+                                    c->stream));
+            // the old block may belong to another stream's free list
+            CPTR_HIP(hipStreamSynchronize(c->stream));
+        }
+        h.lam_dev = std::move(grown);
+    }
     const Level &L = h.L[l];
     amg_gershgorin(L.A.n, L.A.rp, L.A.ci, L.A.v.p, h.lam_dev.p + l, c->stream);
 }
@@ -689,7 +702,6 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
     h.L.clear();
     h.L.emplace_back();
     std::vector<int> parts = c->parts;
-    if (o.smoother == CPTR_SMOOTH_CHEBYSHEV) h.lam_dev.alloc((size_t)o.amg_max_levels + 1);
     {
         Level &L0 = h.L.back();
         L0.A.n = c->n;
@@ -767,7 +779,6 @@ static void refresh_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     if (!h.built || h.L.empty()) throw Error(CPTR_E_STATE, "no hierarchy to reuse");
-    if (o.smoother == CPTR_SMOOTH_CHEBYSHEV) h.lam_dev.alloc((size_t)h.L.size() + 1);
     Level &L0 = h.L[0];
     if (own && own->p == vals && own->n >= (size_t)c->nnzb)
         L0.A.v = std::move(*own);

@@ -117,7 +117,7 @@ struct Hierarchy {
     std::vector<Level> L;
     int ncoarse = 0;
     DBuf<double> cinv;      // dense inverse of the coarsest operator, row-major
-    DBuf<unsigned long long> lam_dev;   // per-level Gershgorin bounds (Chebyshev smoother), as bits
+    DBuf<unsigned long long> lam_dev;   // per-level Gershgorin bounds (Chebyshev smoother), as bits; grown on demand
     DBuf<float> cinv32;
     bool built = false;
 };

@@ -141,3 +141,21 @@ def test_chebyshev_sequence_reuse():
             assert res["converged"] == 1 and abs(res["iterations"] - r.iterations) <= 1 and err <= 1e-10
     finally:
         solver.close()
+
+
+def test_chebyshev_with_unbounded_level_limit():
+    """amg_max_levels at its largest value: the per-level bounds take room for
+    the levels actually built (coarsening stops at the max coarse size), and
+    the solve matches the oracle's."""
+    print("case chebyshev with amg_max_levels = 2^31 - 1", flush=True)
+    s, mc = _case("t48x40b6")
+    ref = O.solve(s, O.Options(color=O.tile_colors(s.nx, s.ny, 32, 8), amg=_amg(mc)))
+    solver = cptr.solver_for(s, **_gpu(mc, amg_max_levels=2**31 - 1, ilu_tile_x=32, ilu_tile_y=8))
+    try:
+        x, res = solver.solve(_t(s.rhs))
+        assert solver.amg_levels(0) == len(ref.hierarchies["T"].levels)
+    finally:
+        solver.close()
+    err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+    print(f"  gpu its={res['iterations']} oracle its={ref.iterations} err={err:.2e}", flush=True)
+    assert res["converged"] == 1 and abs(res["iterations"] - ref.iterations) <= 1 and err <= 1e-10
