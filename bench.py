@@ -287,10 +287,14 @@ def learned_bench(args, dev) -> int:
         del s
     torch.cuda.synchronize()
     out = {}
-    for label, interp in (("classical", cptr.INTERP_CLASSICAL), ("learned", cptr.INTERP_LEARNED)):
-        sol = cptr.Solver(krylov=cptr.FGMRES, restart=50, precond_precision=cptr.FP32, t_interp=interp,
-                          pre_sweeps=args.sweeps, post_sweeps=args.sweeps, ilu_tile_x=args.tile[0],
-                          ilu_tile_y=args.tile[1])
+    legs = [("classical", dict(krylov=cptr.FGMRES, precond_precision=cptr.FP32, t_interp=cptr.INTERP_CLASSICAL)),
+            ("learned", dict(krylov=cptr.FGMRES, precond_precision=cptr.FP32, t_interp=cptr.INTERP_LEARNED))]
+    if not args.no_fp64:
+        legs.append(("fp64_plain", dict(krylov=cptr.GMRES, precond_precision=cptr.FP64,
+                                        t_interp=cptr.INTERP_CLASSICAL)))
+    for label, kw in legs:
+        sol = cptr.Solver(restart=50, pre_sweeps=args.sweeps, post_sweeps=args.sweeps, ilu_tile_x=args.tile[0],
+                          ilu_tile_y=args.tile[1], **kw)
         sol.load_mlp(w)
         rows = []
         for k in range(args.warmup + args.steps):
@@ -325,6 +329,9 @@ def learned_bench(args, dev) -> int:
                    "tol": 1e-8},
         "learned": out["learned"], "classical": out["classical"],
         "speedup_vs_classical": round(out["classical"]["ms_per_step"] / out["learned"]["ms_per_step"], 4),
+        "fp64_plain": out.get("fp64_plain"),
+        "speedup_vs_fp64_plain": (round(out["fp64_plain"]["ms_per_step"] / out["learned"]["ms_per_step"], 4)
+                                  if "fp64_plain" in out else None),
         "cpu_baseline": None,
     }
     print(json.dumps(res))
