@@ -1,0 +1,40 @@
+"""Host logic of the benchmark (no GPU): the refusal of more than one GPU,
+the algorithmic bytes of the outer SpMV counted by hand for the config-3
+matrix, and the HBM traffic figure, which is reported only while the SpMV
+source it was measured on is unchanged."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert p.returncode != 0
+    assert "one GPU" in (p.stdout + p.stderr)
+
+
+def test_spmv_bytes_hand_count():
+    # config 3: 1000 x 500 cells, 5-point pattern, b = 8
+    n = 1000 * 500
+    nnzb = n + 2 * (999 * 500) + 2 * (1000 * 499)
+    assert nnzb == 2497000
+    values = nnzb * 64 * 8            # FP64 8x8 blocks
+    cols = nnzb * 4                   # int32 column indices
+    rows = (n + 1) * 4                # int32 row pointers
+    vecs = 2 * n * 8 * 8              # x read once, y written once
+    assert bench.spmv_algorithmic_bytes(n, nnzb, 8) == values + cols + rows + vecs == 1354452004
+
+
+def test_traffic_follows_kernel_source(monkeypatch):
+    nbytes = bench.spmv_algorithmic_bytes(500000, 2497000, 8)
+    t = bench.load_traffic(nbytes)
+    assert t is not None and t > nbytes            # measured traffic, above the compulsory bytes
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.load_traffic(nbytes) is None
