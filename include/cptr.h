@@ -81,10 +81,11 @@ enum { CPTR_SMOOTH_JACOBI = 0, CPTR_SMOOTH_L1JACOBI = 1, CPTR_SMOOTH_CHEBYSHEV =
 /* fine-level interpolation of the temperature AMG stage: classical
  * extended+i, the learned correction judged against it by the V-cycle
  * convergence factor, or the learned correction without the judge.  The
- * judge runs at the first full build of the temperature hierarchy after
- * cptr_setup (or cptr_load_mlp); later full builds through
- * cptr_update_values with reuse on (reuse_rho_max > 0) follow its choice
- * without judging again (rho_T_classical / rho_T_learned then read -1) */
+ * judge runs at every full build of the temperature hierarchy (cptr_setup,
+ * and every rebuild by cptr_update_values): both hierarchies are built and
+ * the learned one is kept only when its convergence factor is lower.  A
+ * hierarchy kept by the reuse test of cptr_update_values keeps its
+ * interpolation and is not judged (rho_T_classical / rho_T_learned read -1) */
 enum { CPTR_INTERP_CLASSICAL = 0, CPTR_INTERP_LEARNED = 1, CPTR_INTERP_LEARNED_FORCED = 2 };
 
 typedef struct {
@@ -163,7 +164,11 @@ typedef struct {
 cptr_status cptr_default_options(cptr_options *opt);
 
 /* Create a context on HIP device `hip_device`; all work goes to `hip_stream`
- * (a hipStream_t, NULL = the default stream).  *opt is copied. */
+ * (a hipStream_t, NULL = the default stream).  *opt is copied.  The context
+ * holds one solver for the linear systems of a Newton iteration (Sec.
+ * "Numerical Results": right-preconditioned GMRES on the scaled system of
+ * Eq. splitPrec2, relative tolerance 1e-8); CPTR_E_ARG for invalid options,
+ * CPTR_E_HIP when the device cannot be used. */
 cptr_status cptr_create(cptr_ctx **ctx, int32_t hip_device, void *hip_stream, const cptr_options *opt);
 
 /* Set up the solver for a system (Eqs. splitPrec1, CPTR31, CPTR32 and the
@@ -192,12 +197,25 @@ cptr_status cptr_setup(cptr_ctx *ctx, int32_t n_cells, int32_t b, int32_t nnzb,
  * successful cptr_setup. */
 cptr_status cptr_update_values(cptr_ctx *ctx, const double *d_vals);
 
-/* Solve A x = b: d_rhs (device, n_cells*b) in, d_x (device) out.  Returns
- * after the work on the stream has finished; *out (host) may be NULL. */
+/* Solve A x = b through the scaled system Abar x = bbar of Eq. splitPrec2
+ * (the left scaling does not change x): right-preconditioned restarted GMRES,
+ * or flexible GMRES with the FP32 preconditioner, with x0 = 0 and the
+ * multi-stage preconditioner of Eq. multistageprec applied as in Algorithm 2
+ * (Algorithm 1 for the two-stage variants), until the recomputed FP64 residual
+ * satisfies |bbar - Abar x| <= rtol |bbar| (Sec. "Numerical Results").
+ * d_rhs (device, n_cells*b, cell-interleaved) in, d_x (device, same layout)
+ * out; both caller-owned.  Returns after the work on the stream has
+ * finished; *out (host) may be NULL.  CPTR_NOT_CONVERGED when max_iters is
+ * reached (d_x holds the last iterate), CPTR_E_STATE before a successful
+ * setup, CPTR_E_NONFINITE for a non-finite right-hand side or breakdown. */
 cptr_status cptr_solve(cptr_ctx *ctx, const double *d_rhs, double *d_x, cptr_result *out);
 
-/* Relative Givens residual estimates of the last solve, one per iteration
- * (host buffer of capacity cap; *len receives the count). */
+/* Relative Givens residual estimates |g_{j+1}| / |bbar| of the last solve,
+ * one per Arnoldi step over all restarts (the GMRES least-squares residual
+ * of Sec. "Numerical Results", non-increasing by the minimal-residual
+ * property): host buffer of capacity cap, of which the first min(cap, count)
+ * entries are written (host_buf may be NULL to query the count); *len
+ * receives the count.  CPTR_E_ARG for a null context or len. */
 cptr_status cptr_residual_history(const cptr_ctx *ctx, double *host_buf, int32_t cap, int32_t *len);
 
 /* Thread-local message describing the last error. */

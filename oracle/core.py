@@ -824,7 +824,7 @@ class SolveResult:
     dec: Decoupled
     rho: dict = dataclasses.field(default_factory=dict)      # measured for reused hierarchies
     reused: dict = dataclasses.field(default_factory=dict)   # name -> kept?
-    # name -> (skip, backoff); "T_learned" -> the judged choice of the learned interpolation
+    # name -> (skip, backoff)
     reuse_state: dict = dataclasses.field(default_factory=dict)
     learned: dict = dataclasses.field(default_factory=dict)  # judge of the learned interpolation
 
@@ -860,9 +860,9 @@ def build_preconditioner(dec: Decoupled, opts: Options, previous: dict | None = 
     After a rejected trial the next ``skip`` systems rebuild without a trial,
     ``skip`` doubling (up to MAX_REUSE_BACKOFF) with each rejection in a row
     and resetting to 1 on acceptance; ``info["state"]`` carries (skip,
-    backoff) per stage in and out, and the judged choice of the learned
-    temperature interpolation ("T_learned"), which later full builds of the
-    sequence follow without a second judge."""
+    backoff) per stage in and out.  Every full build of the temperature
+    hierarchy with learned parameters judges the learned interpolation
+    against the classical one (``info["learned"]``)."""
     Abar = dec.Abar
     n, b, ip, it = Abar.n, Abar.b, dec.ip, dec.it
     hier = {}
@@ -895,27 +895,16 @@ def build_preconditioner(dec: Decoupled, opts: Options, previous: dict | None = 
         if h is None:
             h = amg_setup(A, opts.amg)
             if name == "T" and opts.mlp_params is not None and len(h.levels) > 1:
-                # the learned fine-level interpolation, judged by the V-cycle
-                # convergence factor against the classical one.  Within a
-                # sequence with reuse on, the first judged decision stands for
-                # every later full build (no second judge)
+                # the learned fine-level interpolation, judged at every full
+                # build by the V-cycle convergence factor against the
+                # classical one: kept only when its factor is lower
                 from .learned import learned_interp
-                decided = None
-                if previous is not None and opts.reuse_rho_max > 0:
-                    decided = (info or {}).get("state", {}).get("T_learned")
-                if decided is None:
-                    hl = amg_setup(A, opts.amg, learned_interp(opts.mlp_params))
-                    rc = conv_factor(h, opts.rho_cycles, 0)
-                    rl = conv_factor(hl, opts.rho_cycles, 0)
-                    use = rl < rc
-                    if info is not None:
-                        info["learned"] = dict(used=use, rho_classical=rc, rho_learned=rl)
-                        info.setdefault("state", {})["T_learned"] = use
-                else:
-                    use = bool(decided)
-                    hl = amg_setup(A, opts.amg, learned_interp(opts.mlp_params)) if use else None
-                    if info is not None:
-                        info["learned"] = dict(used=use, rho_classical=-1.0, rho_learned=-1.0)
+                hl = amg_setup(A, opts.amg, learned_interp(opts.mlp_params))
+                rc = conv_factor(h, opts.rho_cycles, 0)
+                rl = conv_factor(hl, opts.rho_cycles, 0)
+                use = rl < rc
+                if info is not None:
+                    info["learned"] = dict(used=use, rho_classical=rc, rho_learned=rl)
                 if use:
                     h = hl
         hier[name] = h

@@ -105,10 +105,6 @@ struct cptr_ctx {
     bool have_mlp = false;
     int used_learned = 0;
     double rho_cls = -1.0, rho_lrn = -1.0;
-    // the judge's choice within a sequence (update_values with reuse on):
-    // -1 not judged yet, 0 classical, 1 learned; later full builds of the
-    // temperature hierarchy follow it without a second judge
-    int learned_decision = -1;
     DBuf<double> tw;
     DBuf<float> tw32;
     // Krylov workspace
@@ -1061,12 +1057,6 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
         return;
     }
     const bool judge = (c->opt.t_interp == CPTR_INTERP_LEARNED);
-    if (judge && c->learned_decision >= 0) {
-        // a judged choice of this sequence stands: only that hierarchy is built
-        build_hierarchy(&B, c->H[k], vals, c->learned_decision ? c->mlp.p : nullptr, own);
-        if (c->H[k].L.size() > 1) c->used_learned = c->learned_decision;
-        return;
-    }
     // the learned hierarchy (and its convergence factor) on its own stream
     // and host thread, concurrently with the classical one
     Hierarchy hl;
@@ -1115,7 +1105,6 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     }
     c->rho_cls = rc;
     c->rho_lrn = rl;
-    if (judge) c->learned_decision = c->used_learned;
 }
 
 static double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -1128,7 +1117,6 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     const int n = c->n, b = c->b, nnzb = c->nnzb;
     const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
     const bool sys = (c->opt.variant == CPTR_VARIANT_CPTR);
-    if (!reuse) c->learned_decision = -1;     // a new sequence judges again
     c->abar.alloc((size_t)nnzb * b * b);
     c->wp.alloc((size_t)n * b);
     c->wt.alloc((size_t)n * b);
@@ -1250,6 +1238,9 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                     if (c->rho[k] < c->opt.reuse_rho_max) {
                         kept.fetch_or(1 << k);
                         c->backoff[k] = 1;
+                        // a kept temperature hierarchy keeps its interpolation
+                        // (used_learned) and is not judged again
+                        if (k == 0) c->rho_cls = c->rho_lrn = -1.0;
                     } else {
                         c->skip_left[k] = c->backoff[k];
                         c->backoff[k] = std::min(2 * c->backoff[k], MAX_REUSE_BACKOFF);
@@ -1891,7 +1882,6 @@ cptr_status cptr_load_mlp(cptr_ctx *c, const float *host_params) {
     StreamScope scope(c ? c->stream : nullptr);
     if (!c) throw Error(CPTR_E_ARG, "null context");
     CPTR_HIP(hipSetDevice(c->device));
-    c->learned_decision = -1;            // new parameters are judged anew
     if (!host_params) {
         c->have_mlp = false;
         return CPTR_OK;

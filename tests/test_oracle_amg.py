@@ -103,19 +103,72 @@ def test_exti_linear_interpolation_1d_poisson():
             assert np.allclose(P[int(i)], expect, atol=1e-15), (case["cf"], i, P[int(i)])
 
 
-def test_exti_preserves_constants_on_zero_row_sums():
-    """Interior rows with zero row sum interpolate constants exactly: P 1 = 1."""
-    M = poisson2d(8, 8)
-    # pure Neumann-like interior rows: make every row sum zero
-    M = M - np.diag(M.sum(axis=1))
-    M += 1e-3 * np.eye(64)   # keep it nonsingular; row sums 1e-3 relative to 4
+def test_exti_hand_worked_branches():
+    """Every branch of the extended+i formula on one hand-worked matrix: a
+    weak neighbour lumped into the diagonal, a positive coupling removed by
+    the sign filter abar, a strong F neighbour with d_k = 0 lumped, a
+    distance-two C point reached through a strong F neighbour, a weak
+    neighbour inside Chat entering the numerator, empty interpolatory sets,
+    and the truncation's row-sum rescaling."""
+    from fractions import Fraction
+    g = json.load(open(os.path.join(GOLD, "exti_branches.json")))
+    M = np.array(g["matrix"])
     A = csr_from_dense(M)
+    s = O.strength(A, g["theta"])
+    for i in range(A.nrows):
+        got = [int(A.ci[e]) for e in range(A.rp[i], A.rp[i + 1]) if s[e] and A.ci[e] != i]
+        assert got == g["strong"][str(i)], (i, got)
+    cf = np.array(g["cf"], np.int32)
+    for pmax in (0, 1):
+        P = O.interp_exti(A, s, cf, pmax=pmax).to_dense()
+        rows = g["P"][f"pmax_{pmax}"]
+        fr = g["fractions"][f"pmax_{pmax}"]
+        for i, want in rows.items():
+            expect = np.zeros(P.shape[1])
+            for c, w in want.items():
+                expect[int(c)] = w
+            if i in fr:          # the decimal values equal the hand-worked fractions
+                vals = [float(Fraction(q)) for q in fr[i]]
+                assert np.allclose(sorted(vals), sorted(want.values()), rtol=0, atol=0)
+            assert np.allclose(P[int(i)], expect, rtol=2e-16, atol=1e-16), (pmax, i, P[int(i)], expect)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_exti_preserves_constants_on_zero_row_sums(seed):
+    """On rows whose entries sum to exactly zero, extended+i interpolates
+    constants exactly: sum_j w_ij = 1 follows from d_k's definition (the
+    sum over Chat_i of abar_kj is d_k - abar_ki) and atilde_ii's lumping,
+    whatever the signs, the strength pattern and the lumped terms.  Random
+    positive and negative couplings on a 2-D pattern, diagonals set to make
+    every row sum zero; the truncation with rescaling keeps it."""
+    rng = np.random.default_rng(seed)
+    nx, ny = 9, 8
+    n = nx * ny
+    M = np.zeros((n, n))
+    for y in range(ny):
+        for x in range(nx):
+            i = x + nx * y
+            for dx, dy in ((1, 0), (0, 1)):
+                if x + dx < nx and y + dy < ny:
+                    j = (x + dx) + nx * (y + dy)
+                    M[i, j] = -rng.uniform(0.1, 2.0)
+                    M[j, i] = -rng.uniform(0.1, 2.0)
+    for i in range(n):                  # one positive off-diagonal in some rows
+        nb = np.flatnonzero(M[i])
+        if len(nb) >= 3 and rng.random() < 0.4:
+            M[i, rng.choice(nb)] *= -0.05
+    np.fill_diagonal(M, 0.0)
+    np.fill_diagonal(M, -M.sum(axis=1))
+    assert np.all(np.diag(M) > 0)
+    A = csr_from_dense(M)
+    assert np.max(np.abs([A.v[A.rp[i]:A.rp[i + 1]].sum() for i in range(n)])) < 1e-14
     s = O.strength(A, 0.25)
-    cf, _ = O.pmis(A, s, 3)
-    P = O.interp_exti(A, s, cf, pmax=0).to_dense()
-    rs = P.sum(axis=1)
-    F = (cf == 0) & (P.sum(axis=1) != 0)
-    assert np.all(np.abs(rs[F] - 1.0) < 1e-2)
+    cf, _ = O.pmis(A, s, seed)
+    for pmax in (0, 4, 2):
+        P = O.interp_exti(A, s, cf, pmax=pmax).to_dense()
+        nonempty = np.count_nonzero(P, axis=1) > 0
+        assert nonempty.sum() > n // 2
+        assert np.max(np.abs(P.sum(axis=1)[nonempty] - 1.0)) < 1e-14, pmax
 
 
 def test_exti_truncation_keeps_pmax_and_row_sum():
