@@ -205,14 +205,17 @@ def assemble(nx: int, ny: int, b: int, perm: np.ndarray, *, peclet: float,
     nfc = has_w.astype(float) + has_e + has_s + has_n   # number of faces of the cell
     out_flux = f_e + f_n
 
-    # block-row structure: order S, W, I, E, N (ascending column index)
+    # block-row structure: order S, W, I, E, N (ascending column index).  The
+    # values are assembled on a dense (ny, nx, 5, b, b) array, one slot per
+    # possible neighbour, so every update is a strided slice; the slots of
+    # absent neighbours are dropped at the end.
     masks = [has_s, has_w, np.ones((ny, nx), bool), has_e, has_n]
     counts = sum(m.astype(np.int64) for m in masks).reshape(-1)
     row_ptr = np.zeros(n + 1, np.int64)
     np.cumsum(counts, out=row_ptr[1:])
     nnzb = int(row_ptr[-1])
     col_idx = np.empty(nnzb, np.int32)
-    vals = np.zeros((nnzb, b, b), np.float64)
+    dense = np.empty((ny, nx, 5, b, b), np.float64)
 
     cell = np.arange(n, dtype=np.int64).reshape(ny, nx)
     offsets = [cell - nx, cell - 1, cell, cell + 1, cell + nx]
@@ -233,25 +236,42 @@ def assemble(nx: int, ny: int, b: int, perm: np.ndarray, *, peclet: float,
         4: (-t_n, -kt * has_n + 0.0 * f_n, 0.0 * f_n),  # north is downwind
     }
     for k, m in enumerate(masks):
-        pos = slot[k][m]
-        col_idx[pos] = offsets[k][m].astype(np.int32)
-        if k == 2:
-            ep, et, ec = diag_p[m], diag_t[m], diag_c[m]
-        else:
-            ep, et, ec = (a[m] for a in offd[k])
-        vals[pos, P_INDEX, P_INDEX] = ep
-        vals[pos, T_INDEX, T_INDEX] = et
-        for r in range(2, b):
-            vals[pos, r, r] = ec
+        col_idx[slot[k][m]] = offsets[k][m].astype(np.int32)
+    principal = []
+    for k, m in enumerate(masks):
+        ep, et, ec = (diag_p, diag_t, diag_c) if k == 2 else offd[k]
+        principal.append([np.where(m, v, 0.0) for v in (ep, et, ec)])
+
+    def fill_rows(y0, y1):
+        dense[y0:y1] = 0.0
+        for k, (ep, et, ec) in enumerate(principal):
+            dense[y0:y1, :, k, P_INDEX, P_INDEX] = ep[y0:y1]
+            dense[y0:y1, :, k, T_INDEX, T_INDEX] = et[y0:y1]
+            for r in range(2, b):
+                dense[y0:y1, :, k, r, r] = ec[y0:y1]
+
+    with _pool() as pool:
+        for f in [pool.submit(fill_rows, y0, min(ny, y0 + 16)) for y0 in range(0, ny, 16)]:
+            f.result()
 
     # cross-unknown couplings ------------------------------------------------
     rng_c = np.random.default_rng([seed, 2])
-    if coupling_ref == "flux":
-        if not zero_coupling:
-            acc_col = np.full(b, acc)
-            acc_col[T_INDEX] = acc_t
-            _flux_couplings(vals, b, nx, ny, slot, tx, ty, fx, fy, acc_col, coupling, rng_c)
-    else:
+    if coupling_ref == "flux" and not zero_coupling:
+        acc_col = np.full(b, acc)
+        acc_col[T_INDEX] = acc_t
+        _flux_couplings(dense, b, tx, ty, fx, fy, acc_col, coupling, rng_c)
+    present = np.stack(masks, axis=-1)
+    vals = np.empty((nnzb, b, b), np.float64)
+
+    def compress_rows(y0, y1):
+        lo, hi = row_ptr[y0 * nx], row_ptr[y1 * nx]
+        vals[lo:hi] = dense[y0:y1].reshape(-1, b, b)[present[y0:y1].reshape(-1)]
+
+    with _pool() as pool:
+        for f in [pool.submit(compress_rows, y0, min(ny, y0 + 16)) for y0 in range(0, ny, 16)]:
+            f.result()
+    del dense
+    if coupling_ref != "flux":
         xi = rng_c.uniform(-coupling, coupling, size=(nnzb, b, b))
         if zero_coupling:
             xi[:] = 0.0
@@ -276,7 +296,7 @@ def assemble(nx: int, ny: int, b: int, perm: np.ndarray, *, peclet: float,
     return BSRSystem(nx, ny, b, row_ptr.astype(np.int32), col_idx, vals, rhs, meta)
 
 
-def _flux_couplings(vals, b, nx, ny, slot, tx, ty, fx, fy, acc_col, coupling, rng):
+def _flux_couplings(dense, b, tx, ty, fx, fy, acc_col, coupling, rng):
     """Conservative cross-unknown couplings (reading of "coupling entries
     uniform(-0.1, 0.1) times the diagonal").  For every interior face f from
     an upwind cell I to a downwind cell J and every pair r != c, the flux of
@@ -288,33 +308,76 @@ def _flux_couplings(vals, b, nx, ny, slot, tx, ty, fx, fy, acc_col, coupling, rn
     terms (conservation).  Each cell's accumulation of r also depends on its
     own unknown c with xi times c's accumulation coefficient.
     xi ~ U(-coupling, coupling), independent per face (or cell), r and c;
-    drawn in the order: x-faces, y-faces, cells."""
+    drawn in the order: x-faces, y-faces, cells.  ``dense`` is the
+    (ny, nx, 5, b, b) slot array (slots S, W, I, E, N)."""
     off = ~np.eye(b, dtype=bool)
-    s_dn, s_w, s_i, s_e, s_n = slot      # (ny, nx) block positions S, W, I, E, N
-    faces = (
-        # (T_f, F_f, block II, block IJ (I's entry for J), block JI, block JJ)
-        (tx, fx, s_i[:, :-1], s_e[:, :-1], s_w[:, 1:], s_i[:, 1:]),
-        (ty, fy, s_i[:-1, :], s_n[:-1, :], s_dn[1:, :], s_i[1:, :]),
-    )
-    for tf, ff, ii, ij, ji, jj in faces:
-        if tf.size == 0:
-            continue
-        xi = rng.uniform(-coupling, coupling, size=tf.shape + (b, b)) * off
+    S, W, I, E, N = range(5)
+    pcol = np.zeros(b, bool)
+    pcol[P_INDEX] = True
+    ny, nx = dense.shape[:2]
+
+    def face_terms(xi, tf, ff):
+        xi = xi * off
         scale = np.empty(tf.shape + (1, b))
         scale[..., :] = ff[..., None, None]
         scale[..., P_INDEX] = tf[..., None]
         coef = xi * scale                         # (.., r, c)
-        pcol = np.zeros(b, bool); pcol[P_INDEX] = True
         cp = np.where(pcol, coef, 0.0)            # pressure derivatives: central
         cu = np.where(pcol, 0.0, coef)            # other unknowns: upwind (cell I)
-        # each position occurs once per index array, so plain indexed adds
-        # equal unbuffered accumulation
-        vals[ii.reshape(-1)] += (cp + cu).reshape(-1, b, b)
-        vals[ij.reshape(-1)] += (-cp).reshape(-1, b, b)
-        vals[ji.reshape(-1)] += (-cp - cu).reshape(-1, b, b)
-        vals[jj.reshape(-1)] += cp.reshape(-1, b, b)
-    xi = rng.uniform(-coupling, coupling, size=(ny, nx, b, b)) * off
-    vals[s_i.reshape(-1)] += (xi * acc_col[None, None, None, :]).reshape(-1, b, b)
+        return cp, cu
+
+    # Rows are taken in chunks: the random draws are made in order on this
+    # thread, the arithmetic of the chunks runs on a thread pool.  Every entry
+    # receives its terms in the order x-faces (as upwind cell, then as
+    # downwind cell), y-faces (likewise), cell; chunks touch disjoint rows
+    # except for the downwind term of a chunk's last y-face row, which is
+    # added after the next chunk's upwind terms.
+    chunk = 16
+
+    def x_chunk(y0, y1, xi):
+        cp, cu = face_terms(xi, tx[y0:y1], fx[y0:y1])
+        dense[y0:y1, :-1, I] += cp + cu
+        dense[y0:y1, :-1, E] += -cp
+        dense[y0:y1, 1:, W] += -cp - cu
+        dense[y0:y1, 1:, I] += cp
+
+    def y_chunk(y0, y1, xi):
+        cp, cu = face_terms(xi, ty[y0:y1], fy[y0:y1])
+        dense[y0:y1, :, I] += cp + cu
+        dense[y0:y1, :, N] += -cp
+        dense[y0 + 1:y1 + 1, :, S] += -cp - cu
+        dense[y0 + 1:y1, :, I] += cp[:-1]
+        return cp[-1]
+
+    def cell_chunk(y0, y1, xi):
+        dense[y0:y1, :, I] += (xi * off) * acc_col[None, None, None, :]
+
+    with _pool() as pool:
+        if tx.size:
+            futs = [pool.submit(x_chunk, y0, min(ny, y0 + chunk),
+                                rng.uniform(-coupling, coupling, size=(min(ny, y0 + chunk) - y0, nx - 1, b, b)))
+                    for y0 in range(0, ny, chunk)]
+            for f in futs:
+                f.result()
+        if ty.size:
+            starts = list(range(0, ny - 1, chunk))
+            futs = [pool.submit(y_chunk, y0, min(ny - 1, y0 + chunk),
+                                rng.uniform(-coupling, coupling, size=(min(ny - 1, y0 + chunk) - y0, nx, b, b)))
+                    for y0 in starts]
+            last = [f.result() for f in futs]
+            for y0, cp_last in zip(starts, last):
+                dense[min(ny - 1, y0 + chunk), :, I] += cp_last
+        futs = [pool.submit(cell_chunk, y0, min(ny, y0 + chunk),
+                            rng.uniform(-coupling, coupling, size=(min(ny, y0 + chunk) - y0, nx, b, b)))
+                for y0 in range(0, ny, chunk)]
+        for f in futs:
+            f.result()
+
+
+def _pool():
+    import concurrent.futures
+    import os
+    return concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1)))
 
 
 # ---------------------------------------------------------------------------
