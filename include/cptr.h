@@ -126,6 +126,11 @@ typedef struct {
     int32_t cheb_degree;        /* Chebyshev smoother: degree per sweep (2); the  */
                                 /* pre-smoothing is one Chebyshev iteration of    */
                                 /* degree cheb_degree * pre_sweeps, likewise post */
+    int32_t stop_unscaled;      /* 1: the solve also requires the residual of the */
+                                /* unscaled system, |b - A x| <= rtol |b|; after  */
+                                /* a cycle that ends above it, later cycles stop  */
+                                /* their Givens estimate at min(target, |rbar|    */
+                                /* (rtol |b| / |b - A x|) / 2) (0)                */
 } cptr_options;
 
 typedef struct {

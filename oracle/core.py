@@ -710,7 +710,7 @@ class GmresResult:
 
 
 def gmres(matvec, b: np.ndarray, M, restart: int = 30, rtol: float = 1e-8, max_iters: int = 1000,
-          flexible: bool = False) -> GmresResult:
+          flexible: bool = False, unscaled=None) -> GmresResult:
     """Right-preconditioned GMRES(m) (Saad & Schultz; right preconditioning as in
     the paper's split form Eq. splitPrec2) with x0 = 0, modified Gram-Schmidt
     Arnoldi and Givens rotations.  Stops inside a cycle when the Givens
@@ -718,7 +718,15 @@ def gmres(matvec, b: np.ndarray, M, restart: int = 30, rtol: float = 1e-8, max_i
     residual |b - A x| <= rtol |b|; restarts otherwise.  ``flexible`` stores the
     preconditioned vectors Z and updates x += Z y (FGMRES, Saad 1993); the
     plain variant updates x += M^{-1}(V y).  Happy breakdown when
-    h_{j+1,j} <= 1e-14 |A z_j|.  Iterations count Arnoldi steps."""
+    h_{j+1,j} <= 1e-14 |A z_j|.  Iterations count Arnoldi steps.
+
+    ``unscaled`` (optional): a function of x returning the relative residual
+    of the unscaled system, |b0 - A0 x| / |b0|; the solve then also requires
+    it to be <= rtol.  When a cycle ends with that residual above rtol, the
+    cycles that follow stop their Givens estimate at
+    min(target, |r| (rtol / unscaled(x)) / 2) instead of rtol |b| (the scaled
+    residual needed for the unscaled one, if the two stay proportional, with
+    a factor 2 of margin)."""
     n = b.shape[0]
     x = np.zeros(n)
     bnorm = float(np.linalg.norm(b))
@@ -730,6 +738,7 @@ def gmres(matvec, b: np.ndarray, M, restart: int = 30, rtol: float = 1e-8, max_i
     r = b.copy()
     beta = bnorm
     breakdown = False
+    target = rtol * bnorm
     while True:
         m = restart
         V = np.zeros((m + 1, n))
@@ -768,7 +777,7 @@ def gmres(matvec, b: np.ndarray, M, restart: int = 30, rtol: float = 1e-8, max_i
             if hj1 <= 1e-14 * wnorm0:
                 breakdown = True
                 break
-            if abs(g[j + 1]) <= rtol * bnorm or its >= max_iters:
+            if abs(g[j + 1]) <= target or its >= max_iters:
                 break
             V[j + 1] = w / hj1
         y = np.zeros(k)
@@ -781,7 +790,13 @@ def gmres(matvec, b: np.ndarray, M, restart: int = 30, rtol: float = 1e-8, max_i
         r = b - matvec(x)
         beta = float(np.linalg.norm(r))
         true_rel = beta / bnorm
-        if true_rel <= rtol:
+        ok = true_rel <= rtol
+        if unscaled is not None:
+            ru = unscaled(x)
+            if ru > rtol:
+                ok = False
+                target = min(target, beta * (rtol / ru) * 0.5)
+        if ok:
             return GmresResult(x, its, restarts, True, history, true_rel, breakdown)
         if its >= max_iters or (breakdown and beta == 0.0):
             return GmresResult(x, its, restarts, False, history, true_rel, breakdown)
@@ -809,6 +824,7 @@ class Options:
     reuse_rho_max: float = 0.3           # keep a reused AMG hierarchy while rho < this
     rho_cycles: int = 10
     mlp_params: np.ndarray | None = None # learned T-interpolation weights (None = classical only)
+    stop_unscaled: bool = False          # also require |b - A x| <= rtol |b| (unscaled system)
 
 
 @dataclasses.dataclass
@@ -960,8 +976,12 @@ def solve(system, opts: Options | None = None, ip: int = 0, it: int = 1,
     dec = decouple(A, system.rhs, ip, it, opts.variant)
     info = {"state": dict(previous.reuse_state) if previous else {}}
     apply, _, hier = build_preconditioner(dec, opts, previous.hierarchies if previous else None, info)
+    bn0 = float(np.linalg.norm(system.rhs))
+    unscaled = None
+    if opts.stop_unscaled and bn0 > 0:
+        unscaled = lambda x: float(np.linalg.norm(system.rhs - A.matvec(x))) / bn0  # noqa: E731
     res = gmres(dec.Abar.matvec, dec.rhsbar, apply, opts.restart, opts.rtol, opts.max_iters,
-                flexible=(opts.krylov == FGMRES))
+                flexible=(opts.krylov == FGMRES), unscaled=unscaled)
     r = system.rhs - A.matvec(res.x)
     unscaled = float(np.linalg.norm(r) / np.linalg.norm(system.rhs))
     return SolveResult(res.x, res.iterations, res.restarts, res.converged, res.true_rel_res, unscaled,

@@ -1037,6 +1037,7 @@ static void validate_options(const cptr_options &o) {
         throw Error(CPTR_E_ARG, "cheb_degree must be 1..16");
     if (o.t_interp < CPTR_INTERP_CLASSICAL || o.t_interp > CPTR_INTERP_LEARNED_FORCED)
         throw Error(CPTR_E_ARG, "unknown t_interp");
+    if (o.stop_unscaled != 0 && o.stop_unscaled != 1) throw Error(CPTR_E_ARG, "stop_unscaled must be 0 or 1");
     if (o.t_interp != CPTR_INTERP_CLASSICAL && (o.amg_pmax < 1 || o.amg_pmax > 16))
         throw Error(CPTR_E_ARG, "learned interpolation needs amg_pmax in 1..16");
 }
@@ -1355,7 +1356,22 @@ static double device_norm(cptr_ctx *c, const double *v, int N) {
     return std::sqrt(read_scalar(c->hcol.p, c->stream));
 }
 
-static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
+// |b - A x| from the scaled residual rbar = bbar - Abar x: the unscaled
+// residual is N rbar with N the inverse of the per-cell left scaling.
+static double unscaled_norm(cptr_ctx *c, const double *rbar) {
+    const int N = c->n * c->b;
+    if (c->opt.variant == CPTR_VARIANT_LAST_ONLY)
+        return device_norm(c, rbar, N);
+    launch_unscale(c->opt.variant, c->n, c->b, rbar, c->ip, c->it, c->wp.p, c->wt.p, c->beta.p, c->tmpv.p,
+                   c->stream);
+    return device_norm(c, c->tmpv.p, N);
+}
+
+// Restarted (F)GMRES on the scaled system.  bnorm0 > 0 with the option
+// stop_unscaled: the solve also requires |b - A x| <= rtol |b| (bnorm0 =
+// |b|); after a cycle that ends above it, later cycles stop their Givens
+// estimate at min(target, |rbar| (rtol |b| / |b - A x|) / 2).
+static cptr_status run_gmres(cptr_ctx *c, cptr_result *res, double bnorm0) {
     hipStream_t s = c->stream;
     const int N = c->n * c->b;
     const int m = c->opt.restart;
@@ -1376,6 +1392,8 @@ static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
     int its = 0, restarts = 0;
     double true_rel = 1.0;
     bool converged = false;
+    double target = c->opt.rtol * bnorm;
+    const bool unscaled = c->opt.stop_unscaled && bnorm0 > 0.0;
     while (true) {
         kr_norm2_partial(N, c->r.p, c->part.p, nblk, s);
         kr_cycle_prep(c->part.p, nblk, m, c->g.p, c->scal.p, c->hinfo.p, s);
@@ -1423,7 +1441,7 @@ static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
             }
             c->history.push_back(gres / bnorm);
             if (hj1 <= 1e-14 * wn0) { breakdown = true; break; }
-            if (gres <= c->opt.rtol * bnorm || its >= c->opt.max_iters) break;
+            if (gres <= target || its >= c->opt.max_iters) break;
         }
         kr_solve_upper(k, m, c->Hm.p, c->g.p, c->y.p, s);
         kr_combine<double>(N, k, c->Z.p, ld, c->y.p, c->x.p, s);
@@ -1434,7 +1452,19 @@ static cptr_status run_gmres(cptr_ctx *c, cptr_result *res) {
             return CPTR_E_NONFINITE;
         }
         true_rel = rn / bnorm;
-        if (true_rel <= c->opt.rtol) { converged = true; break; }
+        bool ok = true_rel <= c->opt.rtol;
+        if (unscaled) {
+            const double ru = unscaled_norm(c, c->r.p) / bnorm0;
+            if (!std::isfinite(ru)) {
+                set_error("non-finite residual");
+                return CPTR_E_NONFINITE;
+            }
+            if (ru > c->opt.rtol) {
+                ok = false;
+                target = std::min(target, rn * (c->opt.rtol / ru) * 0.5);
+            }
+        }
+        if (ok) { converged = true; break; }
         if (its >= c->opt.max_iters) break;
         if (breakdown && rn == 0.0) break;
         ++restarts;
@@ -1500,6 +1530,7 @@ cptr_status cptr_default_options(cptr_options *o) {
     o->setup_kernels = 0;
     o->exact_subsolves = 0;
     o->cheb_degree = 2;
+    o->stop_unscaled = 0;
     return CPTR_OK;
 }
 
@@ -1638,16 +1669,11 @@ cptr_status cptr_solve(cptr_ctx *c, const double *d_rhs, double *d_x, cptr_resul
         CPTR_HIP(hipMemcpyAsync(c->rhsbar.p, d_rhs, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     else
         launch_scale_rhs(c->opt.variant, c->n, c->b, d_rhs, c->ip, c->it, c->wp.p, c->wt.p, c->beta.p, c->rhsbar.p, s);
-    cptr_status st = run_gmres(c, &res);
+    const double bn = device_norm(c, d_rhs, N);
+    cptr_status st = run_gmres(c, &res, bn);
     if (st < 0) return st;
     CPTR_HIP(hipMemcpyAsync(d_x, c->x.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    // unscaled residual |b - A x| = |N (bbar - Abar x)|
-    if (c->opt.variant == CPTR_VARIANT_LAST_ONLY)
-        CPTR_HIP(hipMemcpyAsync(c->tmpv.p, c->r.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    else
-        launch_unscale(c->opt.variant, c->n, c->b, c->r.p, c->ip, c->it, c->wp.p, c->wt.p, c->beta.p, c->tmpv.p, s);
-    const double rn = device_norm(c, c->tmpv.p, N);
-    const double bn = device_norm(c, d_rhs, N);
+    const double rn = unscaled_norm(c, c->r.p);
     res.rel_res_unscaled = (bn > 0) ? rn / bn : 0.0;
     CPTR_HIP(hipEventRecord(c->ev1, s));
     CPTR_HIP(hipEventSynchronize(c->ev1));

@@ -230,6 +230,33 @@ def test_solve_variants(case):
 # --------------------------------------------------------------------------
 # error paths (forced from the host with crafted inputs)
 # --------------------------------------------------------------------------
+def test_stop_on_the_unscaled_residual():
+    """The option stop_unscaled against the oracle: at a tolerance the scaled
+    residual meets while the unscaled one does not, both sides restart with
+    the tightened target and end with |b - A x| <= rtol |b|."""
+    print("case stop_unscaled", flush=True)
+    s = tiny(20, 12, 4, peclet=3.0, seed=7)
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    diag = np.nonzero(rows == s.col_idx)[0]
+    s.vals[diag, 0, 2] = 5.0 * s.vals[diag, 2, 2]
+    base = O.solve(s, _oracle_opts(s, amg_max_coarse=30))
+    for k in (4, 6):
+        rtol = base.history[k - 1] * 1.05
+        ref = O.solve(s, _oracle_opts(s, amg_max_coarse=30, rtol=rtol, stop_unscaled=True))
+        solver = cptr.solver_for(s, amg_max_coarse=30, rtol=rtol, stop_unscaled=1)
+        x, res = solver.solve(_t(s.rhs))
+        solver.close()
+        x = x.cpu().numpy()
+        print(f"  k={k} rtol={rtol:.3e} gpu its={res['iterations']} restarts={res['restarts']} "
+              f"unscaled={res['rel_res_unscaled']:.3e}; oracle its={ref.iterations} restarts={ref.restarts}",
+              flush=True)
+        assert res["converged"] == 1 and res["restarts"] >= 1
+        assert res["rel_res_unscaled"] <= rtol and res["rel_res_scaled"] <= rtol
+        assert abs(res["iterations"] - ref.iterations) <= 1
+        if res["iterations"] == ref.iterations:
+            assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
 def test_nonfinite_rhs_is_rejected():
     s = config1()
     solver = cptr.solver_for(s)

@@ -203,3 +203,36 @@ def test_stage_order_matters_but_both_converge():
     b = O.solve(s, O.Options(stage_order=O.P_THEN_T, **base))
     assert a.converged and b.converged
     assert not np.allclose(a.history[:3], b.history[:3])
+
+
+def _unscaled_case():
+    """A system whose pressure equations lean on a composition unknown inside
+    each cell (A_ii[P, c1] = 5 A_ii[c1, c1]): the decoupling's weights are
+    large and the unscaled residual runs about 2.4x the scaled one."""
+    s = tiny(20, 12, 4, peclet=3.0, seed=7)
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    diag = np.nonzero(rows == s.col_idx)[0]
+    s.vals[diag, 0, 2] = 5.0 * s.vals[diag, 2, 2]
+    return s
+
+
+def test_stop_on_the_unscaled_residual():
+    """With stop_unscaled the solve ends only when |b - A x| <= rtol |b| as
+    well: at a tolerance the scaled residual meets after k steps while the
+    unscaled one does not, the plain test stops at k with the unscaled
+    residual above rtol, the unscaled test restarts with a tighter target
+    and ends with both residuals below rtol (both checked from x here)."""
+    s = _unscaled_case()
+    color = O.tile_colors(s.nx, s.ny)
+    amg = O.AMGOptions(max_coarse=30)
+    base = O.solve(s, O.Options(color=color, restart=30, amg=amg))
+    A = O.bsr_of(s)
+    for k in (4, 6, 8):
+        rtol = base.history[k - 1] * 1.05
+        plain = O.solve(s, O.Options(color=color, restart=30, rtol=rtol, amg=amg))
+        both = O.solve(s, O.Options(color=color, restart=30, rtol=rtol, amg=amg, stop_unscaled=True))
+        ru = lambda x: np.linalg.norm(s.rhs - A.matvec(x)) / np.linalg.norm(s.rhs)  # noqa: E731
+        assert plain.iterations == k and ru(plain.x) > rtol
+        assert both.converged and both.iterations > k and both.restarts >= 1
+        assert ru(both.x) <= rtol and both.rel_res_scaled <= rtol
+        assert abs(both.rel_res_unscaled - ru(both.x)) <= 1e-12
