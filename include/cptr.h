@@ -241,6 +241,28 @@ cptr_status cptr_decouple(int32_t variant, int32_t n_cells, int32_t b, const int
                           int32_t p_index, int32_t T_index, double *d_abar, double *d_rhsbar,
                           void *hip_stream);
 
+/* cptr_decouple for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same results, bit for bit, with the per-cell
+ * weights w_P, w_T (n_cells*b doubles each), beta (n_cells doubles) and the
+ * singular-cell word held in a static device array of
+ * CPTR_NOALLOC_SCRATCH_BYTES per GPU (allocated with the library's code
+ * object, kept until the process ends) instead of memory allocated per call.
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine.  Limit: 256 + 2 align256(8 n_cells b) + align256(8 n_cells)
+ * bytes must fit the array (about 600k cells at b = 8); larger inputs
+ * return CPTR_E_ARG before any kernel runs.  All calls on one GPU share that
+ * GPU's array, so calls that overlap in time on one GPU (other streams or
+ * host threads) race; serialise them.  The caller passes inputs and outputs
+ * as for cptr_decouple (d_abar, and d_rhsbar when d_rhs is given, written);
+ * returns after the stream's work, CPTR_E_SINGULAR_BLOCK naming the lowest
+ * singular cell as cptr_decouple does. */
+#define CPTR_NOALLOC_SCRATCH_BYTES (80u * 1024u * 1024u)
+cptr_status cptr_decouple_noalloc(int32_t variant, int32_t n_cells, int32_t b, const int32_t *d_row_ptr,
+                                  const int32_t *d_col_idx, const double *d_vals, const double *d_rhs,
+                                  int32_t p_index, int32_t T_index, double *d_abar, double *d_rhsbar,
+                                  void *hip_stream);
+
 /* y = A x for a BSR matrix (the outer operator apply of every Arnoldi step). */
 cptr_status cptr_bsr_spmv(int32_t n_cells, int32_t b, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                           const double *d_vals, const double *d_x, double *d_y, void *hip_stream);

@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
             "cptr_residual_history": [P, P, I32, ctypes.POINTER(I32)],
             "cptr_destroy": [P],
             "cptr_decouple": [I32, I32, I32, P, P, P, P, I32, I32, P, P, P],
+            "cptr_decouple_noalloc": [I32, I32, I32, P, P, P, P, I32, I32, P, P, P],
             "cptr_bsr_spmv": [I32, I32, P, P, P, P, P, P],
             "cptr_amg_levels": [P, I32, ctypes.POINTER(I32)],
             "cptr_amg_level_info": [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)],
@@ -298,6 +299,18 @@ def decouple(variant, row_ptr, col_idx, vals, rhs, p_index=0, T_index=1):
                                _ptr(abar), _ptr(rb), _stream()))
     torch.cuda.synchronize()
     return abar, rb
+
+
+def decouple_noalloc(variant, row_ptr, col_idx, vals, rhs, abar, rhsbar, p_index=0, T_index=1):
+    """cptr_decouple_noalloc into caller-provided device tensors abar, rhsbar
+    (the library allocates nothing)."""
+    import torch
+    n = row_ptr.numel() - 1
+    b = rhs.numel() // n
+    _check(lib().cptr_decouple_noalloc(variant, n, b, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(rhs),
+                                       p_index, T_index, _ptr(abar), _ptr(rhsbar), _stream()))
+    torch.cuda.synchronize()
+    return abar, rhsbar
 
 
 def bsr_spmv(row_ptr, col_idx, vals, x, b: int):

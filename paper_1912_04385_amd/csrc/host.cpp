@@ -1733,6 +1733,65 @@ cptr_status cptr_decouple(int32_t variant, int32_t n, int32_t b, const int32_t *
     CPTR_API_END
 }
 
+// The decoupling without allocation (cptr_decouple_noalloc): the weights,
+// beta and the singular-cell word live in this file-scope device array, one
+// copy per GPU, whose address is looked up once per device.  Calls that
+// overlap on one GPU share it and race.
+static __device__ __align__(256) unsigned char scratch[CPTR_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+
+static unsigned char *scratch_on_current_device() {
+    int dev = 0;
+    CPTR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) throw Error(CPTR_E_ARG, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        CPTR_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Error(CPTR_E_HIP, "no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return (unsigned char *)g_scratch_ptr[dev];
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+cptr_status cptr_decouple_noalloc(int32_t variant, int32_t n, int32_t b, const int32_t *d_rp, const int32_t *d_ci,
+                                  const double *d_vals, const double *d_rhs, int32_t ip, int32_t it, double *d_abar,
+                                  double *d_rhsbar, void *stream) {
+    CPTR_API_BEGIN
+    if (variant != CPTR_VARIANT_CPTR3 && variant != CPTR_VARIANT_CPR && variant != CPTR_VARIANT_CPTR)
+        throw Error(CPTR_E_ARG, "variant");
+    if (n <= 0 || b < 2 || b > 8) throw Error(CPTR_E_ARG, "sizes");
+    if (!d_rp || !d_ci || !d_vals || !d_abar) throw Error(CPTR_E_ARG, "null pointer");
+    if (ip < 0 || ip >= b || it < 0 || it >= b || ip == it)
+        throw Error(CPTR_E_ARG, "invalid pressure / temperature index");
+    // layout: the singular-cell word, w_P and w_T (n*b each), beta (n)
+    const size_t o_wp = 256;
+    const size_t o_wt = o_wp + align256((size_t)n * b * sizeof(double));
+    const size_t o_beta = o_wt + align256((size_t)n * b * sizeof(double));
+    const size_t need = o_beta + align256((size_t)n * sizeof(double));
+    if (need > (size_t)CPTR_NOALLOC_SCRATCH_BYTES)
+        throw Error(CPTR_E_ARG, "decouple_noalloc: " + std::to_string(n) + " cells of block size " +
+                                    std::to_string(b) + " need " + std::to_string(need) +
+                                    " bytes of scratch, above the limit of " +
+                                    std::to_string((size_t)CPTR_NOALLOC_SCRATCH_BYTES));
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *base = scratch_on_current_device();
+    int *err = (int *)base;
+    double *wp = (double *)(base + o_wp), *wt = (double *)(base + o_wt), *beta = (double *)(base + o_beta);
+    fill_int(err, 0x7fffffff, 1, s);
+    launch_decouple(variant, n, b, d_rp, d_ci, d_vals, ip, it, d_abar, wp, wt, beta, err, s);
+    if (d_rhs && d_rhsbar) launch_scale_rhs(variant, n, b, d_rhs, ip, it, wp, wt, beta, d_rhsbar, s);
+    int bad = 0;
+    CPTR_HIP(hipMemcpyAsync(&bad, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    CPTR_HIP(hipStreamSynchronize(s));
+    if (bad != 0x7fffffff) throw Error(CPTR_E_SINGULAR_BLOCK, "singular decoupling block in cell " + std::to_string(bad));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
 cptr_status cptr_bsr_spmv(int32_t n, int32_t b, const int32_t *d_rp, const int32_t *d_ci, const double *d_vals,
                           const double *d_x, double *d_y, void *stream) {
     CPTR_API_BEGIN
