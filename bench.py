@@ -2,13 +2,20 @@
 """Benchmark of the multi-stage preconditioned GMRES path on one MI355X.
 
 A step is one complete pass of the hot path over one linear system: the left
-decoupling and extraction, both AMG setups, the BILU(0) factorisation, and the
-preconditioned Krylov solve to an FP64 true relative residual of 1e-8 on the
-scaled system.  The workload is the 1000 x 500-cell, block-8 (4M unknowns)
-channelised-permeability recipe at Pe 0.1 and Pe 100 (steps alternate between
-the two systems), solved with the FP32 preconditioner inside FP64 flexible
-GMRES(50); the plain FP64 path (GMRES(50), FP64 preconditioner) is timed the
-same way for comparison.  Inputs are resident in HBM before the timed region.
+decoupling and extraction, both AMG setups (or, within a Newton sequence,
+the refresh and convergence test of the kept hierarchies), the BILU(0)
+factorisation, and the preconditioned Krylov solve to an FP64 true relative
+residual of 1e-8 of the scaled and the unscaled system.
+
+The default workload is the 20-system Newton sequence on 2000 x 1000 cells
+(b = 8, 16M unknowns) with a combustion band moving 5 cells per system:
+FP32-preconditioned FGMRES(50) with the learned temperature interpolation
+and hierarchy reuse (the value), the same with classical interpolation, and
+plain FP64 GMRES(50) with a full setup per system.  Each system is generated
+and copied to HBM before its timed regions.  Beside it: the outer SpMV's
+roofline, the streaming-read ceiling of HBM measured with the library's own
+read kernel, the config-3 single systems, configs 1 and 2, and the CPU
+oracle's time on system 0 of the sequence (one core).
 
 Prints one JSON line (rank 0; one GPU only).
 """
@@ -45,14 +52,17 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(src[a:b]).hexdigest()[:16]
 
 
-def load_traffic(nbytes_alg: int):
-    """HBM bytes per SpMV launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source (else None)."""
-    p = os.path.join(ROOT, "profiles", "spmv_bsr8_c3_traffic.json")
+def load_traffic(nbytes_alg: int, name: str = "spmv_bsr8_c3_traffic.json"):
+    """HBM bytes per SpMV launch from a committed rocprofv3 counter summary,
+    if it was taken on the current kernel source and the same launch size
+    (else None)."""
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if d.get("algorithmic_bytes_per_launch", nbytes_alg) != nbytes_alg:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -96,14 +106,17 @@ def cpu_baseline(seconds_hint: float = 20.0, tile=(64, 8), sweeps: int = 2) -> d
 
 
 def traffic_probe(args, dev) -> int:
-    """Five launches of the b = 8 SpMV on the config-3 matrix, then five
-    device-to-device copies of 1 GiB: the copy's counter reading per byte
-    calibrates the SpMV's."""
+    """Five launches of the b = 8 SpMV on the config-3 (or, with --workload
+    c5, the config-5 system 0) matrix, then five device-to-device copies of
+    1 GiB: the copy's counter reading per byte calibrates the SpMV's."""
     import torch
     from paper_1912_04385_amd import cptr
-    from synthetic import config3
+    from synthetic import config3, config5
 
-    s = config3(0, args.nx, args.ny)
+    if args.workload == "c5":
+        s = config5(0, None, *args.c5_grid)
+    else:
+        s = config3(0, args.nx, args.ny)
     rp = torch.from_numpy(s.row_ptr).to(dev)
     ci = torch.from_numpy(s.col_idx).to(dev)
     vals = torch.from_numpy(s.vals.reshape(-1)).to(dev)
@@ -338,139 +351,342 @@ def learned_bench(args, dev) -> int:
     return 0
 
 
-def sequence_bench(args, dev) -> int:
-    """The Newton sequence on 2000 x 1000 cells (b = 8, 16M unknowns): a
-    combustion band moving 5 cells per system.  The FP32-preconditioned
-    FGMRES(50) solvers keep their AMG hierarchies across systems while their
-    measured V-cycle convergence factor stays below 0.3 (update_values): one
-    with the learned temperature interpolation (judged against the classical
-    one at every full build of the temperature hierarchy; the reported
-    value), one classical; the plain FP64 GMRES(50) solver sets up every
-    system from scratch.  Each system is generated and copied to HBM before
-    its timed region."""
+def host_cpu() -> dict:
+    """Core count and CPU model of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def read_ceiling(dev, nbytes: int = 4 << 30, reps: int = 10) -> dict:
+    """Streaming-read rate of HBM measured with the library's own read
+    kernel (cptr_stream_read) on a buffer of nbytes, timed with events on the
+    stream it runs on: the practical ceiling of the solve's HBM-bound kernels."""
+    import torch
+    from paper_1912_04385_amd import cptr
+
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    part = cptr.stream_read(x)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cptr.stream_read(x, part)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    best = min(ms)
+    med = sorted(ms)[len(ms) // 2]
+    del x
+    return {"kernel": "k_stream_read (non-temporal 8-byte loads, 512 B per wavefront load)", "bytes": nbytes,
+            "GBps_median": round(nbytes / (med * 1e-3) / 1e9, 1), "GBps_best": round(nbytes / (best * 1e-3) / 1e9, 1),
+            "frac_of_8TBps_median": round(nbytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def c5_headline(args, dev) -> int:
+    """The headline: the 20-system Newton sequence on 2000 x 1000 cells (b = 8,
+    16M unknowns) with a combustion band moving 5 cells per system.  Three
+    solvers run every system, each to an FP64 true residual of 1e-8 of both
+    the scaled and the unscaled system (stop_unscaled):
+      learned  -- FP32-preconditioned CPTR3 FGMRES(50), learned temperature
+                  interpolation judged against the classical one at every
+                  full temperature build, AMG hierarchies kept while their
+                  measured V-cycle convergence factor stays below 0.3
+                  (the reported value);
+      classical -- the same with classical interpolation only;
+      fp64_plain -- plain FP64 CPTR3 GMRES(50), full setup of every system.
+    Each system is generated and copied to HBM before its timed regions; each
+    leg's setup (or value update) + solve is bracketed by device
+    synchronisations.  The oracle's time on system 0 (one core) is the CPU
+    baseline, and its solution gives each leg's error on system 0."""
+    import numpy as np
     import torch
     from paper_1912_04385_amd import cptr
     from paper_1912_04385_amd.train_interp import DEFAULT_WEIGHTS, load_weights
     from synthetic import config5, config5_field
 
-    nx, ny = 2000, 1000
+    nx, ny = args.c5_grid
+    K, W = args.steps, args.warmup
     perm = config5_field(nx, ny)
-    sw = dict(pre_sweeps=args.sweeps, post_sweeps=args.sweeps, ilu_tile_x=args.tile[0], ilu_tile_y=args.tile[1])
-    lrn = cptr.Solver(krylov=cptr.FGMRES, restart=50, precond_precision=cptr.FP32, reuse_rho_max=0.3,
-                      t_interp=cptr.INTERP_LEARNED, **sw)
-    lrn.load_mlp(load_weights(args.weights or DEFAULT_WEIGHTS))
-    fp32 = cptr.Solver(krylov=cptr.FGMRES, restart=50, precond_precision=cptr.FP32, reuse_rho_max=0.3, **sw)
-    fp64 = None if args.no_fp64 else cptr.Solver(krylov=cptr.GMRES, restart=50, reuse_rho_max=0.0, **sw)
+    tg = time.perf_counter()
+    s0 = config5(0, perm, nx, ny)
+    print(f"# system 0 generated in {time.perf_counter() - tg:.1f} s", file=sys.stderr, flush=True)
+    n, nnzb, b = s0.n, s0.nnzb, s0.b
+    rp = torch.from_numpy(s0.row_ptr).to(dev)
+    ci = torch.from_numpy(s0.col_idx).to(dev)
+    sw = dict(restart=50, pre_sweeps=args.sweeps, post_sweeps=args.sweeps, ilu_tile_x=args.tile[0],
+              ilu_tile_y=args.tile[1], stop_unscaled=1)
+    legs = {
+        "learned": cptr.Solver(krylov=cptr.FGMRES, precond_precision=cptr.FP32, reuse_rho_max=0.3,
+                               t_interp=cptr.INTERP_LEARNED, timing=1, **sw),
+        "classical": cptr.Solver(krylov=cptr.FGMRES, precond_precision=cptr.FP32, reuse_rho_max=0.3, **sw),
+    }
+    legs["learned"].load_mlp(load_weights(args.weights or DEFAULT_WEIGHTS))
+    if not args.no_fp64:
+        legs["fp64_plain"] = cptr.Solver(krylov=cptr.GMRES, reuse_rho_max=0.0, **sw)
+
+    def step(name, sol, k, vals, rhs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if k == 0 or name == "fp64_plain":
+            sol.setup(rp, ci, vals, 0, 1, nx, ny)
+        else:
+            sol.update_values(vals)
+        x, r = sol.solve(rhs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if not r["converged"] or r["rel_res_scaled"] > 1e-8 or r["rel_res_unscaled"] > 1e-8:
+            raise RuntimeError(f"system {k} ({name}) did not reach 1e-8: {r}")
+        return dt, x, r
+
+    vals = torch.from_numpy(s0.vals.reshape(-1)).to(dev)
+    rhs = torch.from_numpy(s0.rhs).to(dev)
+    for w in range(W):
+        for name, sol in legs.items():
+            step(name, sol, 0, vals, rhs)
+    torch.cuda.synchronize()
+    tot = {name: 0.0 for name in legs}
+    x0 = {}
     rows = []
-    t32 = t64 = tl = 0.0
-    rp = ci = None
-    for k in range(args.systems):
-        tg = time.perf_counter()
-        s = config5(k, perm, nx, ny)
-        if rp is None:
-            rp = torch.from_numpy(s.row_ptr).to(dev)
-            ci = torch.from_numpy(s.col_idx).to(dev)
-        vals = torch.from_numpy(s.vals.reshape(-1)).to(dev)
-        rhs = torch.from_numpy(s.rhs).to(dev)
-        meta = (s.n, s.nnzb)
-        del s
-        torch.cuda.synchronize()
-        gen_s = time.perf_counter() - tg
-        t0 = time.perf_counter()
-        if k == 0:
-            lrn.setup(rp, ci, vals, 0, 1, nx, ny)
+    spmv_ms = 0.0
+    spmv_launches = 0
+    for k in range(K):
+        if k > 0:
+            tg = time.perf_counter()
+            sk = config5(k, perm, nx, ny)
+            vals = torch.from_numpy(sk.vals.reshape(-1)).to(dev)
+            rhs = torch.from_numpy(sk.rhs).to(dev)
+            del sk
+            gen_s = time.perf_counter() - tg
         else:
-            lrn.update_values(vals)
-        x, rl = lrn.solve(rhs)
-        torch.cuda.synchronize()
-        dl = time.perf_counter() - t0
-        if not rl["converged"] or rl["rel_res_scaled"] > 1e-8:
-            raise RuntimeError(f"system {k} (learned) did not reach 1e-8: {rl}")
-        tl += dl
-        t0 = time.perf_counter()
-        if k == 0:
-            fp32.setup(rp, ci, vals, 0, 1, nx, ny)
-        else:
-            fp32.update_values(vals)
-        x, r32 = fp32.solve(rhs)
-        torch.cuda.synchronize()
-        d32 = time.perf_counter() - t0
-        if not r32["converged"] or r32["rel_res_scaled"] > 1e-8:
-            raise RuntimeError(f"system {k} (fp32) did not reach 1e-8: {r32}")
-        t32 += d32
-        row = {"system": k, "fp32_ms": round(d32 * 1e3, 2), "its": r32["iterations"], "reused": r32["reused"],
-               "rho_T": round(r32["rho_T"], 4), "rho_P": round(r32["rho_P"], 4),
-               "setup_ms": round(r32["setup_ms"], 2), "solve_ms": round(r32["solve_ms"], 2),
-               "rel_res": r32["rel_res_scaled"],
-               "learned": {"ms": round(dl * 1e3, 2), "its": rl["iterations"], "reused": rl["reused"],
-                           "used_learned": rl["used_learned"], "rho_T": round(rl["rho_T"], 4),
-                           "rho_T_classical": round(rl["rho_T_classical"], 4),
-                           "rho_T_learned": round(rl["rho_T_learned"], 4), "setup_ms": round(rl["setup_ms"], 2),
-                           "solve_ms": round(rl["solve_ms"], 2), "rel_res": rl["rel_res_scaled"]}}
-        if fp64 is not None:
-            t0 = time.perf_counter()
-            fp64.setup(rp, ci, vals, 0, 1, nx, ny)
-            x, r64 = fp64.solve(rhs)
-            torch.cuda.synchronize()
-            d64 = time.perf_counter() - t0
-            if not r64["converged"] or r64["rel_res_scaled"] > 1e-8:
-                raise RuntimeError(f"system {k} (fp64) did not reach 1e-8: {r64}")
-            t64 += d64
-            row.update(fp64_ms=round(d64 * 1e3, 2), fp64_its=r64["iterations"])
+            gen_s = 0.0
+        row = {"system": k}
+        for name, sol in legs.items():
+            dt, x, r = step(name, sol, k, vals, rhs)
+            tot[name] += dt
+            if k == 0:
+                x0[name] = x.cpu().numpy()
+            if name == "learned":
+                spmv_ms += r["t_spmv_ms"]
+                spmv_launches += r["timed_steps"]
+            row[name] = {"ms": round(dt * 1e3, 2), "its": r["iterations"], "restarts": r["restarts"],
+                         "setup_ms": round(r["setup_ms"], 2), "solve_ms": round(r["solve_ms"], 2),
+                         "reused": r["reused"], "rho_T": round(r["rho_T"], 4), "rho_P": round(r["rho_P"], 4),
+                         "rel_res_scaled": r["rel_res_scaled"], "rel_res_unscaled": r["rel_res_unscaled"]}
+            if name == "learned":
+                row[name].update(used_learned=r["used_learned"], rho_T_classical=round(r["rho_T_classical"], 4),
+                                 rho_T_learned=round(r["rho_T_learned"], 4))
         rows.append(row)
         print(f"# system {k}: generated+copied in {gen_s:.1f} s; {row}", file=sys.stderr, flush=True)
-        del vals, rhs
-    lrn.close()
-    fp32.close()
-    if fp64 is not None:
-        fp64.close()
+    for sol in legs.values():
+        sol.close()
+    del vals, rhs
+
+    nbytes = spmv_algorithmic_bytes(n, nnzb, b)
+    avg_s = spmv_ms / max(1, spmv_launches) / 1000.0
+    achieved = nbytes / avg_s / 1e9
+    traffic = load_traffic(nbytes, "spmv_bsr8_c5_traffic.json")
+    ceiling = read_ceiling(dev)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_bsr8 (BSR SpMV, b=8, FP64, the outer operator apply)", "bytes_per_launch": nbytes,
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": spmv_launches,
+                "frac_of_read_ceiling": round(achieved / ceiling["GBps_median"], 4)}
+    ms = {name: tot[name] * 1e3 / K for name in legs}
     out = {
-        "metric": "solves/s to an FP64 true relative residual of 1e-8 (setup or reuse + solve), "
-                  "FP32-preconditioned CPTR3 FGMRES(50) with learned temperature interpolation and hierarchy "
-                  "reuse, vs the classical interpolation (classical) and plain FP64 (fp64_plain)",
-        "value": round(args.systems / tl, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.systems,
-        "warmup": 0, "ms_per_step": round(tl * 1e3 / args.systems, 2), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64 Krylov / f32 preconditioner / bf16 edge-MLP",
-        "data": "synthetic (seeded generator, config-5 recipe)",
-        "config": {"workload": f"config5: {nx}x{ny} cells, b=8 ({nx * ny * 8} unknowns), ln-sigma 1.5, Pe 10, "
-                               f"T-band x50 moving 5 cells per system, {args.systems} systems",
+        "metric": "time to 1e-8 FP64 residual + HBM GB/s: FP32/learned CPR-T vs plain FP64 -- solves/s "
+                  "(setup or reuse + solve, to an FP64 true relative residual of 1e-8 of the scaled and the "
+                  "unscaled system) of FP32-preconditioned CPTR3 FGMRES(50) with the judged learned temperature "
+                  "interpolation and hierarchy reuse; plain FP64 in fp64_plain, classical interpolation in "
+                  "classical, HBM GB/s in roofline",
+        "value": round(K / tot["learned"], 4), "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(ms["learned"], 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 Krylov / f32 preconditioner / bf16 edge-MLP",
+        "data": "synthetic (seeded generator, config-5 recipe; random-init-free: the edge-MLP weights are the "
+                "ones trained by train_interp on generated systems)",
+        "config": {"workload": f"config5: {nx}x{ny} cells, b=8 ({n * b} unknowns), ln-sigma 1.5, Pe 10, "
+                               f"T-band x50 moving 5 cells per system, {K} systems",
                    "krylov": "FGMRES(50)",
-                   "preconditioner": f"CPTR3, FP32, learned T-interpolation (judged), Jacobi "
+                   "preconditioner": f"CPTR3, FP32, learned T-interpolation judged at every full build, Jacobi "
                                      f"{args.sweeps}+{args.sweeps} V-cycles, BILU(0) in {args.tile[0]}x{args.tile[1]} "
                                      f"tiles, AMG reuse while rho < 0.3",
                    "tol": 1e-8},
+        "roofline": roofline,
+        "hbm_read_ceiling": ceiling,
+        "classical": {"interpolation": "classical ext+i only, same reuse", "ms_per_step": round(ms["classical"], 2),
+                      "solves_per_s": round(K / tot["classical"], 4)},
         "systems": rows,
-        "classical": {"interpolation": "classical ext+i only, same reuse",
-                      "ms_per_step": round(t32 * 1e3 / args.systems, 2),
-                      "solves_per_s": round(args.systems / t32, 4)},
-        "cpu_baseline": None,
     }
-    if fp64 is not None:
-        out["fp64_plain"] = {"setup": "full setup of every system, same V-cycles",
-                             "ms_per_step": round(t64 * 1e3 / args.systems, 2),
-                             "solves_per_s": round(args.systems / t64, 4)}
-        out["speedup_vs_fp64"] = round(t64 / tl, 4)
-        out["classical"]["speedup_vs_fp64"] = round(t64 / t32, 4)
+    if "fp64_plain" in legs:
+        out["fp64_plain"] = {"setup": "full setup of every system, FP64 preconditioner, GMRES(50)",
+                             "ms_per_step": round(ms["fp64_plain"], 2),
+                             "solves_per_s": round(K / tot["fp64_plain"], 4)}
+        out["speedup_vs_fp64"] = round(tot["fp64_plain"] / tot["learned"], 4)
+        out["classical"]["speedup_vs_fp64"] = round(tot["fp64_plain"] / tot["classical"], 4)
+    out["speedup_learned_vs_classical"] = round(tot["classical"] / tot["learned"], 4)
+    if args.extras:
+        out["c3"] = c3_extra(args, dev)
+        out["c1_c2"] = small_configs(dev)
+    if not args.no_cpu_baseline:
+        cb, xo = cpu_baseline_c5(s0)
+        cb["x_error_vs_oracle_system0"] = {name: float(np.linalg.norm(x0[name] - xo) / np.linalg.norm(xo))
+                                           for name in x0}
+        out["cpu_baseline"] = cb
+    else:
+        out["cpu_baseline"] = None
     print(json.dumps(out))
     return 0
+
+
+def cpu_baseline_c5(s0):
+    """The CPU FP64 oracle, as it stands, on system 0 of the config-5
+    sequence (the whole 2000 x 1000, b = 8 system, no scaling): plain FP64
+    CPTR3 GMRES(50) with the benchmark's tiles and V-cycles, on one core
+    (BLAS threads limited to 1).  Returns the line's entry and the oracle's
+    solution."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:   # pragma: no cover
+        threadpool_limits = None
+    import oracle as O
+
+    opts = O.Options(color=O.tile_colors(s0.nx, s0.ny, 64, 8), restart=50, amg=O.AMGOptions(pre=2, post=2),
+                     stop_unscaled=True)
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    t0 = time.perf_counter()
+    r = O.solve(s0, opts)
+    dt = time.perf_counter() - t0
+    if ctx is not None:
+        ctx.__exit__(None, None, None)
+    cb = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+          "sample": f"system 0 of the config-5 sequence ({s0.nx}x{s0.ny} cells, b=8, {s0.n * s0.b} unknowns), "
+                    f"plain FP64 CPTR3 GMRES(50), BILU(0) 64x8 tiles, Jacobi 2+2, one solve of {dt:.1f} s "
+                    f"({r.iterations} iterations, residual {r.rel_res_scaled:.2e} scaled / "
+                    f"{r.rel_res_unscaled:.2e} unscaled), not scaled",
+          "seconds": round(dt, 2), "iterations": r.iterations}
+    cb.update(host_cpu())
+    return cb, r.x
+
+
+def c3_extra(args, dev, steps: int = 6) -> dict:
+    """The config-3 single systems (1000 x 500, b = 8, Pe 0.1 and 100
+    alternating), FP32-preconditioned FGMRES(50) and plain FP64 GMRES(50),
+    each step a full setup + solve, with the outer SpMV's roofline there."""
+    import torch
+    from paper_1912_04385_amd import cptr
+    from synthetic import config3
+
+    systems = []
+    for idx in (0, 1):
+        s = config3(idx, 1000, 500)
+        systems.append(dict(rp=torch.from_numpy(s.row_ptr).to(dev), ci=torch.from_numpy(s.col_idx).to(dev),
+                            vals=torch.from_numpy(s.vals.reshape(-1)).to(dev), rhs=torch.from_numpy(s.rhs).to(dev),
+                            n=s.n, nnzb=s.nnzb, b=s.b))
+        del s
+    common = dict(restart=50, timing=1, pre_sweeps=args.sweeps, post_sweeps=args.sweeps, ilu_tile_x=args.tile[0],
+                  ilu_tile_y=args.tile[1], stop_unscaled=1)
+    out = {"workload": "config3: 1000x500 cells, b=8, channelised ln-sigma 2, Pe 0.1 and 100 alternating"}
+    for label, kw in (("fp32", dict(krylov=cptr.FGMRES, precond_precision=cptr.FP32)),
+                      ("fp64_plain", dict(krylov=cptr.GMRES))):
+        sol = cptr.Solver(**common, **kw)
+        res = []
+        torch.cuda.synchronize()
+        for k in range(steps + 1):
+            sy = systems[k % 2]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol.setup(sy["rp"], sy["ci"], sy["vals"], 0, 1, 1000, 500)
+            x, r = sol.solve(sy["rhs"])
+            torch.cuda.synchronize()
+            if not r["converged"] or r["rel_res_scaled"] > 1e-8 or r["rel_res_unscaled"] > 1e-8:
+                raise RuntimeError(f"config-3 {label} step {k} did not reach 1e-8: {r}")
+            if k > 0:
+                res.append((time.perf_counter() - t0, r))
+        sol.close()
+        ms = sum(t for t, _ in res) * 1e3 / steps
+        launches = sum(r["timed_steps"] for _, r in res)
+        entry = {"ms_per_step": round(ms, 2), "solves_per_s": round(1000.0 / ms, 4),
+                 "iterations": [r["iterations"] for _, r in res],
+                 "setup_ms": [round(r["setup_ms"], 2) for _, r in res],
+                 "solve_ms": [round(r["solve_ms"], 2) for _, r in res],
+                 "stage_ms_per_step": {q: round(sum(r[q] for _, r in res) / max(1, launches), 4)
+                                       for q in ("t_stage1_ms", "t_stage2_ms", "t_last_ms", "t_spmv_ms",
+                                                 "t_arnoldi_ms")}}
+        if label == "fp32":
+            nb = spmv_algorithmic_bytes(systems[0]["n"], systems[0]["nnzb"], 8)
+            avg = sum(r["t_spmv_ms"] for _, r in res) / max(1, launches) / 1000.0
+            entry["spmv_roofline"] = {"achieved_GBps": round(nb / avg / 1e9, 1),
+                                      "frac": round(nb / avg / 1e9 / HBM_PEAK_GBS, 4),
+                                      "avg_launch_us": round(avg * 1e6, 2), "bytes_per_launch": nb,
+                                      "traffic": load_traffic(nb)}
+        out[label] = entry
+    out["speedup_fp32_vs_fp64"] = round(out["fp64_plain"]["ms_per_step"] / out["fp32"]["ms_per_step"], 4)
+    return out
+
+
+def small_configs(dev, reps: int = 5) -> dict:
+    """Configs 1 and 2 with plain FP64: config 1 (20 x 20, b = 3, GMRES(30))
+    and the four config-2 systems (200 x 100, b = 6, one per Peclet number,
+    GMRES(30)); median setup + solve of reps runs each.  Both are launch-
+    latency bound: time only."""
+    import numpy as np
+    import torch
+    from paper_1912_04385_amd import cptr
+    from synthetic import config1, config2
+
+    def run(s):
+        t = dict(rp=torch.from_numpy(s.row_ptr).to(dev), ci=torch.from_numpy(s.col_idx).to(dev),
+                 vals=torch.from_numpy(s.vals.reshape(-1)).to(dev), rhs=torch.from_numpy(s.rhs).to(dev))
+        sol = cptr.Solver(restart=30)
+        ms, its = [], None
+        for k in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol.setup(t["rp"], t["ci"], t["vals"], 0, 1, s.nx, s.ny)
+            x, r = sol.solve(t["rhs"])
+            torch.cuda.synchronize()
+            if not r["converged"] or r["rel_res_scaled"] > 1e-8:
+                raise RuntimeError(f"small config did not reach 1e-8: {r}")
+            if k > 0:
+                ms.append((time.perf_counter() - t0) * 1e3)
+            its = r["iterations"]
+        sol.close()
+        return {"ms": round(float(np.median(ms)), 3), "iterations": its}
+
+    out = {"c1": dict(run(config1()), workload="20x20, b=3, Pe 1, plain FP64 GMRES(30)")}
+    for i, pe in enumerate((0.1, 1.0, 10.0, 100.0)):
+        out[f"c2_pe{pe:g}"] = dict(run(config2(i)), workload=f"200x100, b=6, Pe {pe:g}, plain FP64 GMRES(30)")
+    return out
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps: systems of the config-5 sequence (default workload), or setup+solve "
+                         "steps of the config-3/4 workloads")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nx", type=int, default=1000)
     ap.add_argument("--ny", type=int, default=500)
+    ap.add_argument("--c5-grid", type=int, nargs=2, default=(2000, 1000), metavar=("NX", "NY"),
+                    help="grid of the config-5 sequence")
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="c5: skip the config-3, config-1 and config-2 timings beside the headline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--weights", default=None, help="learned-interpolation parameters (.npy) for c4")
-    ap.add_argument("--workload", choices=["c3", "c4", "c5", "exact"], default="c3",
-                    help="c3: 1000x500 single systems (default); c4: learned against classical "
-                         "interpolation; c5: the 2000x1000 Newton sequence with hierarchy reuse; exact: "
-                         "the exact sub-solver study")
-    ap.add_argument("--systems", type=int, default=20, help="length of the c5 sequence")
+    ap.add_argument("--weights", default=None, help="learned-interpolation parameters (.npy) for c4 / c5")
+    ap.add_argument("--workload", choices=["c5", "c3", "c4", "exact"], default="c5",
+                    help="c5: the 2000x1000 Newton sequence with hierarchy reuse, learned against classical "
+                         "interpolation and plain FP64 (the headline, default); c3: 1000x500 single systems; "
+                         "c4: learned against classical interpolation; exact: the exact sub-solver study")
     ap.add_argument("--sweeps", type=int, default=2,
                     help="Jacobi pre- and post-smoothing sweeps of the V-cycles (2 for every workload: two damped "
                          "Jacobi sweeps each way stand in for the paper's symmetric Gauss-Seidel smoother, and on "
@@ -509,7 +725,7 @@ def main() -> int:
     if args.solve_probe:
         return solve_probe(args, dev)
     if args.workload == "c5":
-        return sequence_bench(args, dev)
+        return c5_headline(args, dev)
     if args.workload == "c4":
         return learned_bench(args, dev)
     if args.workload == "exact":

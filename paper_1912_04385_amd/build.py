@@ -26,6 +26,7 @@ SOURCES = {
     "k_krylov.hip": [],
     "k_condense.hip": [],
     "k_learned.hip": ["-ffp-contract=off"],
+    "k_probe.hip": [],
     "host.cpp": [],
 }
 

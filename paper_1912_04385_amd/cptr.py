@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
             "cptr_decouple": [I32, I32, I32, P, P, P, P, I32, I32, P, P, P],
             "cptr_decouple_noalloc": [I32, I32, I32, P, P, P, P, I32, I32, P, P, P],
             "cptr_bsr_spmv": [I32, I32, P, P, P, P, P, P],
+            "cptr_stream_read": [P, ctypes.c_uint64, P, ctypes.POINTER(I32), P],
             "cptr_amg_levels": [P, I32, ctypes.POINTER(I32)],
             "cptr_amg_level_info": [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)],
             "cptr_amg_level_copy": [P, I32, I32, P, P, P, P, P, P, P],
@@ -311,6 +312,19 @@ def decouple_noalloc(variant, row_ptr, col_idx, vals, rhs, abar, rhsbar, p_index
                                        p_index, T_index, _ptr(abar), _ptr(rhsbar), _stream()))
     torch.cuda.synchronize()
     return abar, rhsbar
+
+
+def stream_read(x, part=None):
+    """One streaming read of the float64 device tensor x (cptr_stream_read);
+    returns the per-workgroup partial sums (their total equals x.sum() up to
+    rounding)."""
+    import torch
+    blocks = ctypes.c_int32()
+    _check(lib().cptr_stream_read(None, x.numel(), None, ctypes.byref(blocks), None))
+    if part is None:
+        part = torch.empty(blocks.value, dtype=torch.float64, device=x.device)
+    _check(lib().cptr_stream_read(_ptr(x), x.numel(), _ptr(part), ctypes.byref(blocks), _stream()))
+    return part
 
 
 def bsr_spmv(row_ptr, col_idx, vals, x, b: int):

@@ -1792,6 +1792,18 @@ cptr_status cptr_decouple_noalloc(int32_t variant, int32_t n, int32_t b, const i
     CPTR_API_END
 }
 
+cptr_status cptr_stream_read(const double *d_x, uint64_t n, double *d_part, int32_t *blocks, void *stream) {
+    CPTR_API_BEGIN
+    if (!blocks) throw Error(CPTR_E_ARG, "null blocks");
+    *blocks = stream_read_blocks((size_t)n);
+    if (!d_x && !d_part) return CPTR_OK;       // size query
+    if (!d_x || !d_part) throw Error(CPTR_E_ARG, "null pointer");
+    if (n == 0) return CPTR_OK;
+    launch_stream_read((size_t)n, d_x, d_part, (hipStream_t)stream);
+    return CPTR_OK;
+    CPTR_API_END
+}
+
 cptr_status cptr_bsr_spmv(int32_t n, int32_t b, const int32_t *d_rp, const int32_t *d_ci, const double *d_vals,
                           const double *d_x, double *d_y, void *stream) {
     CPTR_API_BEGIN

@@ -313,6 +313,10 @@ void bj_apply_cells(int n, int b, const int *rp, const int *ci, const T *dinv, c
                     int ip, int it, const double *r, const T *xT, const T *vP, double *y, hipStream_t st);
 
 // k_krylov.hip: outer operator and Arnoldi
+// streaming read of n doubles, one partial sum per workgroup into part
+// (stream_read_blocks(n) entries)
+int stream_read_blocks(size_t n);
+void launch_stream_read(size_t n, const double *x, double *part, hipStream_t s);
 void launch_bsr_spmv(int n, int b, const int *rp, const int *ci, const double *A, const double *x, double *y,
                      hipStream_t s);
 void launch_bsr_residual(int n, int b, const int *rp, const int *ci, const double *A, const double *x,

@@ -38,3 +38,15 @@ def test_traffic_follows_kernel_source(monkeypatch):
     assert t is not None and t > nbytes            # measured traffic, above the compulsory bytes
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.load_traffic(nbytes) is None
+
+
+def test_traffic_follows_launch_size():
+    """The counter summary of one matrix is not reported for another."""
+    nbytes = bench.spmv_algorithmic_bytes(500000, 2497000, 8)
+    assert bench.load_traffic(nbytes + 8) is None
+    assert bench.load_traffic(nbytes, "no_such_summary.json") is None
+
+
+def test_host_cpu_reports_cores():
+    h = bench.host_cpu()
+    assert h["nproc"] == os.cpu_count() and h["nproc"] >= 1

@@ -64,6 +64,16 @@ def test_bsr_spmv(b, nx, ny):
     assert np.allclose(y, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n", [1, 1000, (1 << 22) + 12345])
+def test_stream_read_probe_sums_the_buffer(n):
+    """The streaming-read measurement kernel reads every element once: its
+    per-workgroup partial sums add up to the buffer's sum."""
+    print(f"case stream_read n={n}", flush=True)
+    x = torch.rand(n, dtype=torch.float64, device="cuda") - 0.25
+    part = cptr.stream_read(x)
+    assert abs(float(part.sum()) - float(x.sum())) <= 1e-9 * float(x.abs().sum())
+
+
 def _compare_hierarchy(solver, h, which):
     nl = solver.amg_levels(which)
     assert nl == len(h.levels), (nl, h.sizes)
