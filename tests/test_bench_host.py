@@ -50,3 +50,17 @@ def test_traffic_follows_launch_size():
 def test_host_cpu_reports_cores():
     h = bench.host_cpu()
     assert h["nproc"] == os.cpu_count() and h["nproc"] >= 1
+
+
+def test_cv_across_peclet_hand_worked():
+    """CV = population standard deviation / mean: iterations 55, 9, 9 have
+    mean 73/3 and deviations 92/3, -46/3, -46/3, so the standard deviation is
+    sqrt((92^2 + 2 * 46^2) / 27) = 21.6846 and the CV 0.8911; entries that
+    did not converge at every Peclet number are left out."""
+    rows = [dict(variant="CPR", subsolves="AMG", grid=64, peclet=pe, iterations=it, converged=1)
+            for pe, it in ((0.01, 55), (1.0, 9), (100.0, 9))]
+    rows += [dict(variant="X", subsolves="AMG", grid=64, peclet=pe, iterations=10, converged=int(pe != 1.0))
+             for pe in (0.01, 1.0, 100.0)]
+    cv = bench.cv_across_peclet(rows)
+    assert len(cv) == 1 and cv[0]["variant"] == "CPR"
+    assert cv[0]["cv"] == 0.8911 and cv[0]["mean"] == 24.333
