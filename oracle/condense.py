@@ -64,3 +64,69 @@ def full_dense(fs):
         J[N1 + i * n2:N1 + (i + 1) * n2, N1 + i * n2:N1 + (i + 1) * n2] = fs.J22[i]
     r = np.concatenate([fs.r1, fs.r2])
     return J, r
+
+
+# ---------------------------------------------------------------------------
+# well elimination (remark closing Sec. "Static-Condensation Strategy": the
+# well unknowns are eliminated exactly by a Schur complement; with one
+# perforation per well the reservoir pattern is kept)
+# ---------------------------------------------------------------------------
+#
+# Reading: a well w with nw unknowns perforates one cell c_w, and couples to
+# that cell's primary unknowns only: the primary rows of c_w carry a block
+# J1w_w (n1 x nw) against the well unknowns, the well's equations a block
+# Jw1_w (nw x n1) against c_w's primary unknowns and Jww_w (nw x nw) against
+# its own.  With the full system J [d1; d2; dw] = -[r1; r2; rw] and
+#   Qw_w = Jww_w^{-1} Jw1_w,   qw_w = Jww_w^{-1} rw_w,
+# eliminating dw changes only the diagonal block of c_w and its right-hand
+# side:  A_cc -= J1w_w Qw_w,  b_c += J1w_w qw_w  (wells taken in order), and
+# the well update follows from the well rows:  dw_w = -qw_w - Qw_w d1_c.
+
+
+def well_factors(W):
+    """Qw [nwells, nw, n1], qw [nwells, nw] (numpy's LU solve per well)."""
+    rhs = np.concatenate([W.Jw1, W.rw.reshape(W.count, W.nw, 1)], axis=2)
+    sol = np.linalg.solve(W.Jww, rhs)
+    n1 = W.Jw1.shape[2]
+    return sol[:, :, :n1], sol[:, :, n1]
+
+
+def eliminate_wells(A, b, row_ptr, col_idx, W):
+    """(A', b', Qw, qw): the reduced blocks A [nnzb, n1, n1] and right-hand
+    side b [n * n1] with the wells eliminated (copies)."""
+    A = np.array(A, dtype=np.float64, copy=True)
+    n1 = A.shape[1]
+    b = np.array(b, dtype=np.float64, copy=True).reshape(-1, n1)
+    Qw, qw = well_factors(W)
+    for w in range(W.count):
+        c = int(W.cell[w])
+        lo, hi = row_ptr[c], row_ptr[c + 1]
+        e = lo + int(np.nonzero(col_idx[lo:hi] == c)[0][0])
+        A[e] = A[e] - W.J1w[w] @ Qw[w]
+        b[c] = b[c] + W.J1w[w] @ qw[w]
+    return A, b.reshape(-1), Qw, qw
+
+
+def recover_wells(W, Qw, qw, d1):
+    """dw_w = -qw_w - Qw_w d1_{c_w} (the well rows of the full system)."""
+    n1 = Qw.shape[2]
+    d1 = d1.reshape(-1, n1)
+    return np.concatenate([-qw[w] - Qw[w] @ d1[int(W.cell[w])] for w in range(W.count)]) if W.count else np.zeros(0)
+
+
+def full_dense_with_wells(fs, W):
+    """The whole system with wells as one dense matrix and right-hand side,
+    unknowns ordered [d1; d2; dw] (for tests on tiny systems)."""
+    J, r = full_dense(fs)
+    N = J.shape[0]
+    nwt = W.count * W.nw
+    Jf = np.zeros((N + nwt, N + nwt))
+    Jf[:N, :N] = J
+    n1 = fs.n1
+    for w in range(W.count):
+        c = int(W.cell[w])
+        o = N + w * W.nw
+        Jf[c * n1:(c + 1) * n1, o:o + W.nw] = W.J1w[w]
+        Jf[o:o + W.nw, c * n1:(c + 1) * n1] = W.Jw1[w]
+        Jf[o:o + W.nw, o:o + W.nw] = W.Jww[w]
+    return Jf, np.concatenate([r, W.rw])

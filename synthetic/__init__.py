@@ -6,4 +6,4 @@ from .generator import (BSRSystem, P_INDEX, T_INDEX, assemble, tiny, config1, co
                         config3, config4_train, config5, config5_field, named,
                         CONFIG2_PECLET, CONFIG3_PECLET)
 from .mlp_init import mlp_init
-from .full_system import FullSystem, full_system
+from .full_system import FullSystem, Wells, full_system, wells

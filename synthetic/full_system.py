@@ -67,3 +67,43 @@ def full_system(base: BSRSystem, n2: int, seed: int = 0, j12_scale: float = 0.02
     r2 = gr.uniform(-1.0, 1.0, size=n * n2)
     return FullSystem(base.nx, base.ny, n1, n2, base.row_ptr.copy(), base.col_idx.copy(), base.vals.copy(),
                       J12, J21, J22, r1, r2)
+
+
+@dataclasses.dataclass
+class Wells:
+    """Wells with one perforation each: well w has nw unknowns and couples to
+    the primary unknowns of cell ``cell[w]`` (J1w [count, n1, nw]: that
+    cell's primary rows against the well unknowns; Jw1 [count, nw, n1]: the
+    well rows against the cell's primary unknowns; Jww [count, nw, nw];
+    rw [count * nw])."""
+    cell: np.ndarray
+    nw: int
+    J1w: np.ndarray
+    Jw1: np.ndarray
+    Jww: np.ndarray
+    rw: np.ndarray
+
+    @property
+    def count(self) -> int:
+        return int(self.cell.shape[0])
+
+
+def wells(nx: int, ny: int, n1: int, nw: int = 2, cells=None, seed: int = 0, scale: float = 0.5) -> Wells:
+    """Seeded wells (input recipe).  By default an injector and a producer at
+    opposite corners, cells 0 and nx*ny - 1 (the corner-to-corner pattern of
+    the paper's two-well cases); Jww_w: diagonal 1 + U(0, 1), off-diagonal
+    U(-0.1, 0.1); J1w, Jw1: U(-scale, scale); rw: U(-1, 1).  Streams
+    default_rng([seed, 21 .. 24])."""
+    cell = np.array([0, nx * ny - 1] if cells is None else cells, dtype=np.int32)
+    W = cell.shape[0]
+    gww = np.random.default_rng([seed, 21])
+    g1w = np.random.default_rng([seed, 22])
+    gw1 = np.random.default_rng([seed, 23])
+    gr = np.random.default_rng([seed, 24])
+    Jww = gww.uniform(-0.1, 0.1, size=(W, nw, nw))
+    idx = np.arange(nw)
+    Jww[:, idx, idx] = 1.0 + gww.uniform(0.0, 1.0, size=(W, nw))
+    J1w = g1w.uniform(-scale, scale, size=(W, n1, nw))
+    Jw1 = gw1.uniform(-scale, scale, size=(W, nw, n1))
+    rw = gr.uniform(-1.0, 1.0, size=W * nw)
+    return Wells(cell, nw, J1w, Jw1, Jww, rw)
