@@ -305,6 +305,39 @@ cptr_status cptr_condense(int32_t n_cells, int32_t n1, int32_t n2, int32_t nnzb,
 cptr_status cptr_recover_secondary(int32_t n_cells, int32_t n1, int32_t n2, const double *d_Q, const double *d_q,
                                    const double *d_delta1, double *d_delta2, void *hip_stream);
 
+/* Exact elimination of the well unknowns (the remark closing Sec.
+ * "Static-Condensation Strategy": wells eliminated by a Schur complement,
+ * one perforation per well, so the reservoir pattern is kept).  Reading:
+ * well w has nw unknowns, perforates cell c_w = d_well_cell[w] and couples to
+ * that cell's primary unknowns only: the cell's primary rows carry J1w_w
+ * (n1 x nw) against the well unknowns, the well rows carry Jw1_w (nw x n1)
+ * against the cell's primary unknowns and Jww_w (nw x nw) against their own;
+ * the well residual is rw_w.  With Qw_w = Jww_w^{-1} Jw1_w and
+ * qw_w = Jww_w^{-1} rw_w (Gauss-Jordan with partial pivoting per well):
+ *   A_{c_w c_w} -= J1w_w Qw_w,   b_{c_w} += J1w_w qw_w
+ * in place on the reduced system (d_A: nnzb x n1 x n1 blocks on the pattern
+ * d_row_ptr / d_col_idx, d_b: n_cells*n1, e.g. as written by cptr_condense),
+ * wells taken in index order (wells that share a cell add their terms in
+ * that order).  Inputs, device memory, row-major per well: d_well_cell
+ * int32[n_wells], d_J1w n_wells x n1 x nw, d_Jw1 n_wells x nw x n1, d_Jww
+ * n_wells x nw x nw, d_rw n_wells*nw.  Writes the factors d_Qw
+ * (n_wells x nw x n1) and d_qw (n_wells*nw) that cptr_recover_wells takes.
+ * Returns after the work is done.  CPTR_E_ARG for a well cell outside
+ * 0..n_cells-1 or without a stored diagonal block, CPTR_E_SINGULAR_BLOCK
+ * (cptr_last_error names the lowest such well) for a singular Jww; d_A and
+ * d_b are not changed then. */
+cptr_status cptr_condense_wells(int32_t n_cells, int32_t n1, int32_t nnzb, const int32_t *d_row_ptr,
+                                const int32_t *d_col_idx, int32_t n_wells, int32_t nw, const int32_t *d_well_cell,
+                                const double *d_J1w, const double *d_Jw1, const double *d_Jww, const double *d_rw,
+                                double *d_A, double *d_b, double *d_Qw, double *d_qw, void *hip_stream);
+
+/* The well update from the primary one (the well rows of the full system):
+ * dw_w = -qw_w - Qw_w d1_{c_w}, with Qw, qw from cptr_condense_wells.
+ * d_delta1: n_cells*n1, d_deltaw: n_wells*nw.  Asynchronous on the stream. */
+cptr_status cptr_recover_wells(int32_t n_wells, int32_t n1, int32_t nw, const int32_t *d_well_cell,
+                               const double *d_Qw, const double *d_qw, const double *d_delta1, double *d_deltaw,
+                               void *hip_stream);
+
 /* Number of AMG levels of hierarchy `which` (0 = temperature C_TT, 1 = pressure
  * B_PP; with variant CPTR, 0 = the system hierarchy of B_ee). */
 cptr_status cptr_amg_levels(const cptr_ctx *ctx, int32_t which, int32_t *levels);

@@ -845,16 +845,31 @@ class SolveResult:
     learned: dict = dataclasses.field(default_factory=dict)  # judge of the learned interpolation
 
 
+DIRECT_DENSE_MAX = 4096
+
+
 class _Direct:
-    """Direct solve of a scalar CSR system (dense LU with partial pivoting)."""
+    """Direct solve of a scalar CSR system (the paper's exact sub-solves):
+    dense LU with partial pivoting up to DIRECT_DENSE_MAX rows, above it the
+    sparse LU of SuperLU (scipy.sparse.linalg.splu, partial pivoting) as a
+    library step; both are exact solves up to rounding."""
 
     def __init__(self, A: CSR):
+        self.sparse = None
+        if A.nrows > DIRECT_DENSE_MAX:
+            import scipy.sparse as sp
+            from scipy.sparse.linalg import splu
+            M = sp.csr_matrix((A.v, A.ci, A.rp), shape=(A.nrows, A.ncols)).tocsc()
+            self.sparse = splu(M)
+            return
         self.lu = np.ascontiguousarray(A.to_dense())
         self.piv = np.zeros(A.nrows, np.int32)
         if lib().orc_dense_lu_factor(A.nrows, _p(self.lu), _p(self.piv)) != 0:
             raise OracleError("singular subsystem")
 
     def __call__(self, b):
+        if self.sparse is not None:
+            return self.sparse.solve(_f64(b).copy())
         f = _f64(b).copy()
         lib().orc_dense_lu_solve(self.lu.shape[0], _p(self.lu), _p(self.piv), _p(f))
         return f

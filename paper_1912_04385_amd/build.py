@@ -27,6 +27,7 @@ SOURCES = {
     "k_condense.hip": [],
     "k_learned.hip": ["-ffp-contract=off"],
     "k_probe.hip": [],
+    "k_blocktri.hip": [],
     "host.cpp": [],
 }
 

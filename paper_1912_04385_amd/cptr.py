@@ -104,6 +104,8 @@ def lib() -> ctypes.CDLL:
             "cptr_mlp_destroy": [P],
             "cptr_condense": [I32, I32, I32, I32, P, P, P, P, P, P, P, P, P, P, P, P, P],
             "cptr_recover_secondary": [I32, I32, I32, P, P, P, P, P],
+            "cptr_condense_wells": [I32, I32, I32, P, P, I32, I32, P, P, P, P, P, P, P, P, P, P],
+            "cptr_recover_wells": [I32, I32, I32, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -351,6 +353,32 @@ def condense(row_ptr, col_idx, J11, J12, J21, J22, r1, r2, n1: int, n2: int):
     _check(lib().cptr_condense(n, n1, n2, nnzb, _ptr(rp), _ptr(ci), *[_ptr(x) for x in t], _ptr(A), _ptr(b),
                                _ptr(Q), _ptr(q), _stream()))
     return A, b, Q[: n * n2 * n1], q[: n * n2]
+
+
+def condense_wells(row_ptr, col_idx, A, b, well_cell, J1w, Jw1, Jww, rw, n1: int, nw: int):
+    """Eliminate single-perforation wells in place on the reduced system (A,
+    b) (cptr_condense_wells); returns the well factors Qw, qw."""
+    import torch
+    rp, ci = _dev(row_ptr, torch.int32), _dev(col_idx, torch.int32)
+    wc = _dev(well_cell, torch.int32)
+    t = [_dev(x, torch.float64) for x in (J1w, Jw1, Jww, rw)]
+    W = wc.numel()
+    Qw = torch.empty(max(W * nw * n1, 1), dtype=torch.float64, device=A.device)
+    qw = torch.empty(max(W * nw, 1), dtype=torch.float64, device=A.device)
+    _check(lib().cptr_condense_wells(rp.numel() - 1, n1, ci.numel(), _ptr(rp), _ptr(ci), W, nw, _ptr(wc),
+                                     *[_ptr(x) for x in t], _ptr(A), _ptr(b), _ptr(Qw), _ptr(qw), _stream()))
+    return Qw[: W * nw * n1], qw[: W * nw]
+
+
+def recover_wells(well_cell, Qw, qw, delta1, n1: int, nw: int):
+    """dw_w = -qw_w - Qw_w d1_{c_w} (cptr_recover_wells)."""
+    import torch
+    wc = _dev(well_cell, torch.int32)
+    d1 = _dev(delta1, torch.float64)
+    W = wc.numel()
+    dw = torch.empty(max(W * nw, 1), dtype=torch.float64, device=d1.device)
+    _check(lib().cptr_recover_wells(W, n1, nw, _ptr(wc), _ptr(Qw), _ptr(qw), _ptr(d1), _ptr(dw), _stream()))
+    return dw[: W * nw]
 
 
 def recover_secondary(Q, q, delta1, n1: int, n2: int):

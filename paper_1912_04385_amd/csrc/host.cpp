@@ -53,6 +53,7 @@ struct Builder {
     // scratch) that coarsens the second unknown of a level concurrently
     std::vector<int> parts;
     Builder *aux = nullptr;
+    int gx = 0, gy = 0;          // grid shape of the cells (0: none), for the exact block-tridiagonal solves
     int device = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     Builder() = default;
@@ -321,12 +322,87 @@ static void level_vectors(Level &L, int n, bool fp32) {
     }
 }
 
+// Exact sub-solve of a grid operator by block-tridiagonal LU over grid rows
+// (no dense limit): groups of nx rows for a scalar operator, of 2 nx rows
+// (both unknowns of a grid row) for the elliptic block of the two-stage
+// scheme, whose rows come as [P of every cell; T of every cell].
+static void bt_build(Builder *c, Hierarchy &h) {
+    hipStream_t s = c->stream;
+    Level &L = h.L[0];
+    const int n = L.A.n;
+    const int gx = c->gx, gy = c->gy;
+    if (gx <= 0 || gy <= 0)
+        throw Error(CPTR_E_ARG, "exact sub-solves of an operator with " + std::to_string(n) +
+                                    " rows (above the dense limit of " + std::to_string(MAX_COARSE_DENSE) +
+                                    ") need the grid shape (nx, ny)");
+    const bool sys = c->parts.size() > 1;
+    const int g = sys ? 2 * gx : gx, ng = gy;
+    if ((long)g * ng != n) throw Error(CPTR_E_ARG, "operator rows do not match the grid shape");
+    if (g > BT_MAX_GROUP)
+        throw Error(CPTR_E_ARG, "exact block-tridiagonal sub-solve: a grid row holds " + std::to_string(g) +
+                                    " unknowns (at most " + std::to_string(BT_MAX_GROUP) + ")");
+    std::vector<int> perm(n), rowof(n);
+    for (int r = 0; r < n; ++r) {
+        const int u = sys ? r / (gx * gy) : 0, i = sys ? r % (gx * gy) : r;
+        const int q = (i / gx) * g + u * gx + i % gx;
+        perm[r] = q;
+        rowof[q] = r;
+    }
+    auto bt = std::make_unique<BlockTri>();
+    bt->ng = ng;
+    bt->g = g;
+    bt->perm.alloc(n);
+    bt->rowof.alloc(n);
+    CPTR_HIP(hipMemcpyAsync(bt->perm.p, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    CPTR_HIP(hipMemcpyAsync(bt->rowof.p, rowof.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    bt_check(n, L.A.rp, L.A.ci, bt->perm.p, g, c->flag.p, s);
+    if (read_flag_and_clear(c) & 1)
+        throw Error(CPTR_E_ARG, "exact block-tridiagonal sub-solve: the operator couples grid rows more than one apart");
+    CsrD AT;
+    csr_transpose(c, L.A, AT);
+    const size_t gg = (size_t)g * g;
+    bt->Sinv.alloc((size_t)ng * gg);
+    if (ng > 1) bt->G.alloc((size_t)(ng - 1) * gg);
+    bt->z.alloc(n);
+    bt->xw.alloc(n);
+    DBuf<int> drp, dci, used, piv;
+    DBuf<double> S, aug, F, U;
+    drp.alloc((size_t)g + 1);
+    dci.alloc(gg);
+    bt_dense_index(g, drp.p, dci.p, s);
+    S.alloc(gg);
+    aug.alloc(2 * gg);
+    used.alloc(g);
+    piv.alloc(g);
+    F.alloc((size_t)g * 16);
+    U.alloc((size_t)16 * 2 * g);
+    for (int y = 0; y < ng; ++y) {
+        bt_schur(y, g, L.A.rp, L.A.ci, L.A.v.p, bt->perm.p, bt->rowof.p, y > 0 ? bt->G.p + (y - 1) * gg : nullptr,
+                 S.p, s);
+        amg_dense_inverse(g, drp.p, dci.p, S.p, aug.p, used.p, piv.p, c->flag.p, bt->Sinv.p + y * gg, nullptr, F.p,
+                          U.p, s);
+        if (y + 1 < ng)
+            bt_g(y, g, AT.rp, AT.ci, AT.v.p, bt->perm.p, bt->rowof.p, bt->Sinv.p + y * gg, bt->G.p + y * gg, s);
+    }
+    const int f = read_flag_and_clear(c);
+    if (f & 64) throw Error(CPTR_E_SINGULAR_BLOCK, "singular block in the exact block-tridiagonal factorisation");
+    h.ncoarse = n;
+    h.bt = std::move(bt);
+}
+
 // coarsest level: dense inverse (FP64, plus an FP32 copy for the precision split)
 static void coarse_inverse(Builder *c, Hierarchy &h) {
     hipStream_t s = c->stream;
     const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
     Level &Lc = h.L.back();
     const int nc = Lc.A.n;
+    h.bt.reset();
+    // exact sub-solves: the dense inverse up to the dense limit, the
+    // block-tridiagonal factorisation above it (always with exact_subsolves 2)
+    if (c->opt.exact_subsolves == 2 || (c->opt.exact_subsolves == 1 && nc > MAX_COARSE_DENSE)) {
+        bt_build(c, h);
+        return;
+    }
     if (nc > MAX_COARSE_DENSE && c->opt.exact_subsolves)
         throw Error(CPTR_E_ARG, "exact sub-solve of an operator with " + std::to_string(nc) + " rows (the dense limit is " +
                                     std::to_string(MAX_COARSE_DENSE) + ")");
@@ -850,10 +926,15 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     T *x = Prec<T>::x(L);
     T *b = Prec<T>::b(L);
     if (lvl == (int)h.L.size() - 1) {
-        if constexpr (std::is_same<T, double>::value)
+        if (h.bt) {
+            const BlockTri &bt = *h.bt;
+            bt_solve<T>(bt.ng, bt.g, L.A.rp, L.A.ci, L.A.v.p, bt.perm.p, bt.rowof.p, bt.Sinv.p, bt.G.p, bt.z.p,
+                        bt.xw.p, b, x, s);
+        } else if constexpr (std::is_same<T, double>::value) {
             vc_dense_apply<double>(n, h.cinv.p, b, x, s);
-        else
+        } else {
             vc_dense_apply_mixed(n, h.cinv.p, b, x, s);
+        }
         return x;
     }
     const cptr_options &o = c->opt;
@@ -1031,7 +1112,7 @@ static void validate_options(const cptr_options &o) {
     if (o.ilu_tile_x < 1 || o.ilu_tile_y < 1) throw Error(CPTR_E_ARG, "ILU tile must be at least 1 x 1");
     if (o.pre_sweeps < 0 || o.post_sweeps < 0) throw Error(CPTR_E_ARG, "negative smoothing sweeps");
     if (o.setup_kernels < 0 || o.setup_kernels > 3) throw Error(CPTR_E_ARG, "setup_kernels must be 0, 1, 2 or 3");
-    if (o.exact_subsolves != 0 && o.exact_subsolves != 1) throw Error(CPTR_E_ARG, "exact_subsolves must be 0 or 1");
+    if (o.exact_subsolves < 0 || o.exact_subsolves > 2) throw Error(CPTR_E_ARG, "exact_subsolves must be 0, 1 or 2");
     if (o.smoother < CPTR_SMOOTH_JACOBI || o.smoother > CPTR_SMOOTH_CHEBYSHEV) throw Error(CPTR_E_ARG, "unknown smoother");
     if (o.smoother == CPTR_SMOOTH_CHEBYSHEV && (o.cheb_degree < 1 || o.cheb_degree > 16))
         throw Error(CPTR_E_ARG, "cheb_degree must be 1..16");
@@ -1067,6 +1148,8 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     B2.stream = c->side[2];
     B2.opt = B.opt;
     B2.n = B.n;
+    B2.gx = B.gx;
+    B2.gy = B.gy;
     B2.nnzb = B.nnzb;
     B2.rp.p = B.rp.p;
     B2.ci.p = B.ci.p;
@@ -1206,6 +1289,8 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         B.parts.clear();
         B.aux = nullptr;
         B.device = c->device;
+        B.gx = c->nx;
+        B.gy = c->ny;
         if (ee) {
             B.parts = {n, n};
             // the pressure builder is idle in the two-stage scheme: it
@@ -1834,6 +1919,53 @@ cptr_status cptr_condense(int32_t n, int32_t n1, int32_t n2, int32_t nnzb, const
         throw Error(CPTR_E_SINGULAR_BLOCK, "singular secondary block J22 in cell " + std::to_string(bad));
     launch_condense_blocks(n, n1, n2, d_rp, d_ci, d_J11, d_J12, d_Q, d_q, d_r1, d_A, d_b, s);
     CPTR_HIP(hipStreamSynchronize(s));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_condense_wells(int32_t n, int32_t n1, int32_t nnzb, const int32_t *d_rp, const int32_t *d_ci,
+                                int32_t n_wells, int32_t nw, const int32_t *d_well_cell, const double *d_J1w,
+                                const double *d_Jw1, const double *d_Jww, const double *d_rw, double *d_A, double *d_b,
+                                double *d_Qw, double *d_qw, void *stream) {
+    CPTR_API_BEGIN
+    if (n < 0 || nnzb < n || n1 < 1 || n1 > 8 || nw < 1 || nw > 8 || n_wells < 0)
+        throw Error(CPTR_E_ARG, "sizes: n1 must be 1..8, nw 1..8, n_wells >= 0, nnzb >= n_cells");
+    if (n_wells == 0) return CPTR_OK;
+    if (n == 0) throw Error(CPTR_E_ARG, "wells need cells");
+    if (!d_rp || !d_ci || !d_well_cell || !d_J1w || !d_Jw1 || !d_Jww || !d_rw || !d_A || !d_b || !d_Qw || !d_qw)
+        throw Error(CPTR_E_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope scope(s);
+    std::vector<int> cells((size_t)n_wells);
+    CPTR_HIP(hipMemcpyAsync(cells.data(), d_well_cell, sizeof(int) * n_wells, hipMemcpyDeviceToHost, s));
+    CPTR_HIP(hipStreamSynchronize(s));
+    for (int w = 0; w < n_wells; ++w)
+        if (cells[w] < 0 || cells[w] >= n)
+            throw Error(CPTR_E_ARG, "well " + std::to_string(w) + " perforates cell " + std::to_string(cells[w]) +
+                                        ", outside 0.." + std::to_string(n - 1));
+    DBuf<int> flag;
+    flag.alloc(2);
+    fill_int(flag.p, 0x7fffffff, 2, s);
+    launch_condense_wells(n_wells, n1, nw, d_rp, d_ci, d_well_cell, d_J1w, d_Jw1, d_Jww, d_rw, d_A, d_b, d_Qw, d_qw,
+                          flag.p, s);
+    int bad[2];
+    read_bytes(bad, flag.p, sizeof(bad), s);
+    if (bad[1] != 0x7fffffff)
+        throw Error(CPTR_E_ARG, "the cell of well " + std::to_string(bad[1]) + " has no diagonal block");
+    if (bad[0] != 0x7fffffff)
+        throw Error(CPTR_E_SINGULAR_BLOCK, "singular well block Jww in well " + std::to_string(bad[0]));
+    return CPTR_OK;
+    CPTR_API_END
+}
+
+cptr_status cptr_recover_wells(int32_t n_wells, int32_t n1, int32_t nw, const int32_t *d_well_cell,
+                               const double *d_Qw, const double *d_qw, const double *d_delta1, double *d_deltaw,
+                               void *stream) {
+    CPTR_API_BEGIN
+    if (n_wells < 0 || n1 < 1 || n1 > 8 || nw < 1 || nw > 8) throw Error(CPTR_E_ARG, "sizes: n1 and nw must be 1..8");
+    if (n_wells == 0) return CPTR_OK;
+    if (!d_well_cell || !d_Qw || !d_qw || !d_delta1 || !d_deltaw) throw Error(CPTR_E_ARG, "null pointer");
+    launch_recover_wells(n_wells, n1, nw, d_well_cell, d_Qw, d_qw, d_delta1, d_deltaw, (hipStream_t)stream);
     return CPTR_OK;
     CPTR_API_END
 }

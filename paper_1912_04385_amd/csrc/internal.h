@@ -9,6 +9,7 @@
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "cptr.h"
@@ -113,8 +114,20 @@ struct Level {
     DBuf<unsigned char> strong;
 };
 
+// exact block-tridiagonal factors of a grid operator (k_blocktri.hip):
+// ng groups of g rows, perm / rowof between operator rows and group-major
+// positions, S_y^{-1} (ng x g x g) and G_y = S_y^{-1} U_y ((ng - 1) x g x g)
+constexpr int BT_MAX_GROUP = 4096;
+struct BlockTri {
+    int ng = 0, g = 0;
+    DBuf<int> perm, rowof;
+    DBuf<double> Sinv, G;
+    DBuf<double> z, xw;     // solve work vectors, group-major
+};
+
 struct Hierarchy {
     std::vector<Level> L;
+    std::unique_ptr<BlockTri> bt;   // exact block-tridiagonal solve of the (single) level
     int ncoarse = 0;
     DBuf<double> cinv;      // dense inverse of the coarsest operator, row-major
     DBuf<unsigned long long> lam_dev;   // per-level Gershgorin bounds (Chebyshev smoother), as bits; grown on demand
@@ -270,12 +283,28 @@ void ln_grad_reduce(int nw, const float *part, float *grad, hipStream_t s);
 void ln_adam(float *p, float *m, float *v, const float *g, double lr, double b1, double b2, double eps, int t,
              hipStream_t s);
 
+// k_blocktri.hip: exact block-tridiagonal solves of grid operators
+void bt_check(int n, const int *rp, const int *ci, const int *perm, int g, int *flag, hipStream_t s);
+void bt_dense_index(int g, int *drp, int *dci, hipStream_t s);
+void bt_schur(int y, int g, const int *rp, const int *ci, const double *v, const int *perm, const int *rowof,
+              const double *Gprev, double *S, hipStream_t s);
+void bt_g(int y, int g, const int *atrp, const int *atci, const double *atv, const int *perm, const int *rowof,
+          const double *Sinv, double *G, hipStream_t s);
+template <class T>
+void bt_solve(int ng, int g, const int *rp, const int *ci, const double *v, const int *perm, const int *rowof,
+              const double *Sinv, const double *G, double *z, double *xw, const T *b, T *x, hipStream_t s);
+
 // k_condense.hip: static condensation of the full Newton system
 void launch_condense_cells(int n, int n1, int n2, const double *J21, const double *J22, const double *r2, double *Q,
                            double *q, int *flag, hipStream_t st);
 void launch_condense_blocks(int n, int n1, int n2, const int *rp, const int *ci, const double *J11, const double *J12,
                             const double *Q, const double *q, const double *r1, double *A, double *b,
                             hipStream_t st);
+void launch_condense_wells(int nwells, int n1, int nw, const int *rp, const int *ci, const int *wcell,
+                           const double *J1w, const double *Jw1, const double *Jww, const double *rw, double *A,
+                           double *b, double *Qw, double *qw, int *flag, hipStream_t st);
+void launch_recover_wells(int nwells, int n1, int nw, const int *wcell, const double *Qw, const double *qw,
+                          const double *d1, double *dw, hipStream_t st);
 void launch_condense_recover(int n, int n1, int n2, const double *Q, const double *q, const double *d1, double *d2,
                              hipStream_t st);
 

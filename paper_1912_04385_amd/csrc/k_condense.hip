@@ -150,6 +150,152 @@ __global__ void k_condense_recover(int n, int n1, int n2, const double *__restri
     d2[t] = s;
 }
 
+// Well elimination (remark closing Sec. "Static-Condensation Strategy"):
+// well w, with nw unknowns, perforates one cell c_w and couples to its
+// primary unknowns only, so
+//   Qw_w = Jww_w^{-1} Jw1_w,  qw_w = Jww_w^{-1} rw_w                  (per well)
+//   A_cc -= J1w_w Qw_w,  b_c += J1w_w qw_w   (diagonal block of c_w)
+//   dw_w = -qw_w - Qw_w d1_c                                       (recovery)
+// One workgroup: thread w factors well w (Gauss-Jordan with partial pivoting
+// on [Jww | Jw1 | rw], NW <= 8 rows held in registers); then the wells update
+// their cells' diagonal blocks one after the other in well order (wells that
+// share a cell add their terms in that order), lane (r, c) of the block.
+// flag[0]: lowest well with a singular Jww; flag[1]: lowest well whose cell
+// has no stored diagonal block.
+constexpr int WL_THREADS = 256;
+
+template <int NW>
+__global__ void __launch_bounds__(WL_THREADS) k_condense_wells(int nwells, int n1, const int *__restrict__ rp,
+                                                               const int *__restrict__ ci,
+                                                               const int *__restrict__ wcell,
+                                                               const double *__restrict__ J1w,
+                                                               const double *__restrict__ Jw1,
+                                                               const double *__restrict__ Jww,
+                                                               const double *__restrict__ rw, double *__restrict__ A,
+                                                               double *__restrict__ b, double *__restrict__ Qw,
+                                                               double *__restrict__ qw, int *flag) {
+    constexpr int NC = NW + 9;     // Jww columns, 8 for Jw1, rw last
+    __shared__ int s_bad[2];
+    if (threadIdx.x == 0) { s_bad[0] = 0x7fffffff; s_bad[1] = 0x7fffffff; }
+    __syncthreads();
+    for (int w = threadIdx.x; w < nwells; w += WL_THREADS) {
+        // the perforated cell's diagonal block must be stored
+        const int cell = wcell[w];
+        int e = rp[cell];
+        while (e < rp[cell + 1] && ci[e] != cell) ++e;
+        if (e == rp[cell + 1]) {
+            atomicMin(&s_bad[1], w);
+            atomicMin(flag + 1, w);
+            continue;
+        }
+        double m[NW][NC];
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+#pragma unroll
+            for (int c = 0; c < NW; ++c) m[r][c] = Jww[((size_t)w * NW + r) * NW + c];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) m[r][NW + c] = (c < n1) ? Jw1[((size_t)w * NW + r) * n1 + c] : 0.0;
+            m[r][NC - 1] = rw[(size_t)w * NW + r];
+        }
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            int p = k;
+            double best = fabs(m[k][k]);
+#pragma unroll
+            for (int r = k + 1; r < NW; ++r)
+                if (fabs(m[r][k]) > best) { best = fabs(m[r][k]); p = r; }
+            if (!(best > 0.0)) { bad = true; break; }
+            if (p != k) {
+#pragma unroll
+                for (int r = k + 1; r < NW; ++r)
+                    if (r == p) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) { const double t = m[k][c]; m[k][c] = m[r][c]; m[r][c] = t; }
+                    }
+            }
+            const double inv = 1.0 / m[k][k];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) m[k][c] *= inv;
+#pragma unroll
+            for (int r = 0; r < NW; ++r) {
+                if (r == k) continue;
+                const double f = m[r][k];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) m[r][c] -= f * m[k][c];
+            }
+        }
+        if (bad) {
+            atomicMin(&s_bad[0], w);
+            atomicMin(flag, w);
+            continue;
+        }
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < n1) Qw[((size_t)w * NW + r) * n1 + c] = m[r][NW + c];
+            qw[(size_t)w * NW + r] = m[r][NC - 1];
+        }
+    }
+    __syncthreads();
+    // a singular well block or a missing diagonal block: the host reports it
+    // and nothing is updated
+    if (s_bad[0] != 0x7fffffff || s_bad[1] != 0x7fffffff) return;
+    const int lane = threadIdx.x;
+    const bool on = lane < n1 * n1;
+    const int r = on ? lane / n1 : 0, c = on ? lane % n1 : 0;
+    for (int w = 0; w < nwells; ++w) {
+        const int cell = wcell[w];
+        int e = rp[cell];
+        while (ci[e] != cell) ++e;         // present: checked above
+        if (on) {
+            double v = A[((size_t)e * n1 + r) * n1 + c];
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                v -= J1w[((size_t)w * n1 + r) * NW + k] * Qw[((size_t)w * NW + k) * n1 + c];
+                if (c == 0) t += J1w[((size_t)w * n1 + r) * NW + k] * qw[(size_t)w * NW + k];
+            }
+            A[((size_t)e * n1 + r) * n1 + c] = v;
+            if (c == 0) b[(size_t)cell * n1 + r] += t;
+        }
+        __syncthreads();
+    }
+}
+
+// dw_w[k] = -qw_w[k] - sum_c Qw_w[k][c] d1_{c_w}[c], one thread per well unknown
+__global__ void k_recover_wells(int nwells, int n1, int nw, const int *__restrict__ wcell,
+                                const double *__restrict__ Qw, const double *__restrict__ qw,
+                                const double *__restrict__ d1, double *__restrict__ dw) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nwells * nw) return;
+    const int w = (int)(t / nw), k = (int)(t % nw);
+    const double *Qk = Qw + ((size_t)w * nw + k) * n1;
+    const double *x = d1 + (size_t)wcell[w] * n1;
+    double s = -qw[t];
+    for (int c = 0; c < n1; ++c) s -= Qk[c] * x[c];
+    dw[t] = s;
+}
+
+void launch_condense_wells(int nwells, int n1, int nw, const int *rp, const int *ci, const int *wcell,
+                           const double *J1w, const double *Jw1, const double *Jww, const double *rw, double *A,
+                           double *b, double *Qw, double *qw, int *flag, hipStream_t st) {
+    if (nwells == 0) return;
+#define CASE(NN) case NN: hipLaunchKernelGGL(k_condense_wells<NN>, dim3(1), dim3(WL_THREADS), 0, st, nwells, n1, rp, ci, wcell, J1w, Jw1, Jww, rw, A, b, Qw, qw, flag); break;
+    switch (nw) { CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) default: throw Error(CPTR_E_ARG, "nw must be 1..8"); }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+void launch_recover_wells(int nwells, int n1, int nw, const int *wcell, const double *Qw, const double *qw,
+                          const double *d1, double *dw, hipStream_t st) {
+    if (nwells == 0) return;
+    hipLaunchKernelGGL(k_recover_wells, dim3((unsigned)(((long)nwells * nw + 255) / 256)), dim3(256), 0, st, nwells,
+                       n1, nw, wcell, Qw, qw, d1, dw);
+    CPTR_CHECK_LAUNCH();
+}
+
 void launch_condense_cells(int n, int n1, int n2, const double *J21, const double *J22, const double *r2, double *Q,
                            double *q, int *flag, hipStream_t st) {
     if (n == 0 || n2 == 0) return;

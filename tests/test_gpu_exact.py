@@ -2,10 +2,12 @@
 Schur-complement approximations themselves (Sec. "Numerical Results"), where
 every AMG stage applies its operator exactly -- M_PP = B_PP (CPR, CPTR3),
 M_TT = C_TT (CPTR3), M_ee = B_ee (two-stage CPTR).  On the GPU the exact
-inverse is the dense Gauss-Jordan inverse of the operator; the oracle uses a
-dense LU with partial pivoting.  Bars: solution to 1e-10 relative and
-iterations within one; exactness shown by one-step convergence on the
-uncoupled upwind case."""
+solve is the dense Gauss-Jordan inverse of the operator up to 8192 rows and
+the block-tridiagonal LU over grid rows above (exact_subsolves = 2 takes the
+latter at any size); the oracle uses a dense LU with partial pivoting, and a
+sparse LU above 4096 rows.  Bars: solution to 1e-10 relative and iterations
+within one; exactness shown by one-step convergence on the uncoupled upwind
+case."""
 import numpy as np
 import pytest
 
@@ -76,20 +78,82 @@ def test_exact_subsolves_with_exact_ilu_converge_in_one_step(variant):
     assert res["iterations"] == 1 and res["rel_res_scaled"] <= 1e-12
 
 
-def test_exact_subsolve_beyond_the_dense_limit_is_rejected():
-    print("case exact sub-solve beyond the dense limit", flush=True)
+def test_exact_subsolve_beyond_the_dense_limit_needs_the_grid():
+    """Above the dense limit the exact solve is block tridiagonal over grid
+    rows: without the grid shape (an unstructured pattern, block Jacobi last
+    stage) it is rejected before any kernel runs."""
+    print("case exact sub-solve beyond the dense limit without the grid", flush=True)
     s = tiny(100, 90, 3, seed=1)                       # 9000 rows > 8192
-    with pytest.raises(cptr.CptrError, match="dense limit"):
-        cptr.solver_for(s, exact_subsolves=1)
+    solver = cptr.Solver(exact_subsolves=1, last_stage=cptr.LAST_BJACOBI)
+    try:
+        with pytest.raises(cptr.CptrError, match="grid shape"):
+            solver.setup(torch.from_numpy(s.row_ptr), torch.from_numpy(s.col_idx),
+                         torch.from_numpy(s.vals.reshape(-1)), 0, 1, 0, 0)
+    finally:
+        solver.close()
+
+
+@pytest.mark.parametrize("name,variant", [("c1", O.CPTR), ("t32x24b6", O.CPTR3), ("t32x24b6", O.CPR),
+                                          ("t32x24b6", O.CPTR), ("t30x20b2", O.CPTR)])
+def test_block_tridiagonal_exact_subsolves_parity(name, variant):
+    """exact_subsolves = 2: the block-tridiagonal LU over grid rows at every
+    size, against the oracle's dense LU."""
+    print(f"case block-tridiagonal exact sub-solves {name} variant={variant}", flush=True)
+    s = _case(name)
+    ref = O.solve(s, O.Options(color=O.tile_colors(s.nx, s.ny, 32, 8), variant=variant, exact_subsolves=True))
+    solver = cptr.solver_for(s, variant=GPU_VARIANT[variant], exact_subsolves=2, ilu_tile_x=32, ilu_tile_y=8)
+    try:
+        x, res = solver.solve(_t(s.rhs))
+    finally:
+        solver.close()
+    x = x.cpu().numpy()
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    print(f"  gpu its={res['iterations']} oracle its={ref.iterations} err={err:.2e}", flush=True)
+    assert res["converged"] == 1 and res["rel_res_scaled"] <= 1e-8
+    assert abs(res["iterations"] - ref.iterations) <= 1
+    assert err <= 1e-10
 
 
 @pytest.mark.parametrize("variant", [O.CPTR3, O.CPTR])
-def test_exact_subsolves_fp32_preconditioner(variant):
+def test_exact_subsolves_beyond_the_dense_limit(variant):
+    """100 x 90 cells, b = 3: B_PP and C_TT have 9000 rows and B_ee 18000,
+    beyond the dense inverse: the block-tridiagonal solves against the
+    oracle's sparse LU."""
+    print(f"case exact sub-solves beyond the dense limit variant={variant}", flush=True)
+    s = tiny(100, 90, 3, peclet=2.0, seed=1)
+    ref = O.solve(s, O.Options(color=O.tile_colors(s.nx, s.ny, 32, 8), variant=variant, exact_subsolves=True))
+    solver = cptr.solver_for(s, variant=GPU_VARIANT[variant], exact_subsolves=1, ilu_tile_x=32, ilu_tile_y=8)
+    try:
+        x, res = solver.solve(_t(s.rhs))
+    finally:
+        solver.close()
+    x = x.cpu().numpy()
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    print(f"  gpu its={res['iterations']} oracle its={ref.iterations} err={err:.2e}", flush=True)
+    assert res["converged"] == 1 and res["rel_res_scaled"] <= 1e-8
+    assert abs(res["iterations"] - ref.iterations) <= 1
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("variant", [O.CPTR3, O.CPTR])
+def test_block_tridiagonal_exact_with_exact_ilu_converge_in_one_step(variant):
+    print(f"case block-tridiagonal exact sub-solves uncoupled upwind variant={variant}", flush=True)
+    s = tiny(6, 5, 5, seed=4, zero_coupling=True)
+    solver = cptr.solver_for(s, variant=GPU_VARIANT[variant], exact_subsolves=2, ilu_tile_x=6, ilu_tile_y=5)
+    try:
+        _, res = solver.solve(_t(s.rhs))
+    finally:
+        solver.close()
+    assert res["iterations"] == 1 and res["rel_res_scaled"] <= 1e-12
+
+
+@pytest.mark.parametrize("variant,exact", [(O.CPTR3, 1), (O.CPTR, 1), (O.CPTR3, 2), (O.CPTR, 2)])
+def test_exact_subsolves_fp32_preconditioner(variant, exact):
     """Exact sub-solves inside the FP32 preconditioner (the dense inverses'
     FP32 copies) reach the FP64 true residual 1e-8 recomputed by the oracle."""
-    print(f"case exact sub-solves fp32 variant={variant}", flush=True)
+    print(f"case exact sub-solves fp32 variant={variant} exact={exact}", flush=True)
     s = _case("t32x24b6")
-    solver = cptr.solver_for(s, variant=GPU_VARIANT[variant], exact_subsolves=1, krylov=cptr.FGMRES,
+    solver = cptr.solver_for(s, variant=GPU_VARIANT[variant], exact_subsolves=exact, krylov=cptr.FGMRES,
                              precond_precision=cptr.FP32, ilu_tile_x=32, ilu_tile_y=8)
     try:
         x, res = solver.solve(_t(s.rhs))

@@ -236,3 +236,34 @@ def test_stop_on_the_unscaled_residual():
         assert both.converged and both.iterations > k and both.restarts >= 1
         assert ru(both.x) <= rtol and both.rel_res_scaled <= rtol
         assert abs(both.rel_res_unscaled - ru(both.x)) <= 1e-12
+
+
+def test_large_direct_subsolve_is_exact():
+    """Above the dense size the oracle's exact sub-solve is a sparse LU
+    (library step): on a 72 x 70 grid operator (5040 rows, non-symmetric
+    5-point stencil) its solution satisfies A x = b to rounding and equals
+    LAPACK's dense solve."""
+    from oracle.core import DIRECT_DENSE_MAX, _Direct
+    nx, ny = 72, 70
+    n = nx * ny
+    assert n > DIRECT_DENSE_MAX
+    rng = np.random.default_rng(3)
+    M = np.zeros((n, n))
+    for y in range(ny):
+        for x in range(nx):
+            i = x + nx * y
+            for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                if 0 <= x + dx < nx and 0 <= y + dy < ny:
+                    M[i, i + dx + nx * dy] = -rng.uniform(0.2, 1.0)
+            M[i, i] = -M[i].sum() + rng.uniform(0.01, 0.1)
+    rp, ci, v = [0], [], []
+    for i in range(n):
+        nz = np.nonzero(M[i])[0]
+        ci.extend(nz.tolist())
+        v.extend(M[i, nz].tolist())
+        rp.append(len(ci))
+    A = O.CSR(n, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v))
+    b = rng.uniform(-1, 1, n)
+    x = _Direct(A)(b)
+    assert np.linalg.norm(M @ x - b) <= 1e-12 * np.linalg.norm(b) * np.linalg.norm(M, 1)
+    assert np.allclose(x, np.linalg.solve(M, b), rtol=0, atol=1e-10 * np.abs(x).max())
