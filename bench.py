@@ -227,8 +227,8 @@ def solve_probe(args, dev) -> int:
 
 
 EXACT_STUDY_PECLET = ((0.01, "diffusion dominated"), (1.0, "neutral"), (100.0, "advection dominated"))
-EXACT_STUDY_GRIDS = (16, 32, 64, 128, 256)
-EXACT_STUDY_DENSE_MAX = 64       # B_ee of an n x n grid has 2 n^2 rows: at most 8192 for the dense inverse
+EXACT_STUDY_GRIDS = (10, 20, 40, 80, 125, 160, 256)   # the paper's grids of its homogeneous study, and 256
+EXACT_STUDY_BLOCK = 8
 
 
 def cv_across_peclet(rows) -> list:
@@ -255,12 +255,12 @@ def cv_across_peclet(rows) -> list:
 def exact_study(args, dev) -> int:
     """The paper's comparison of the preconditioners by GMRES iterations:
     ILU(0) alone, CPR, CPTR3 and the two-stage CPTR scheme, with AMG
-    sub-solves and -- where the operators fit the dense inverse (B_ee of an
-    n x n grid has 2 n^2 rows) -- with exact ones (the Schur-complement
-    quality study), on homogeneous n x n, b = 6 systems at a diffusion
-    dominated, a neutral and an advection dominated Peclet number, n from 16
-    to 256.  GMRES(30), plain FP64 on the GPU, BILU(0) in 32 x 8 tiles; one
-    setup + solve per entry."""
+    sub-solves and with exact ones (the Schur-complement quality study: the
+    dense inverse up to 8192 rows, the block-tridiagonal LU over grid rows
+    above), on homogeneous n x n, b = 8 systems at a diffusion dominated, a
+    neutral and an advection dominated Peclet number, n over the paper's
+    grids 10 to 160 and 256.  GMRES(30), plain FP64 on the GPU, BILU(0) in
+    32 x 8 tiles; one setup + solve per entry."""
     import numpy as np
     import torch
     from paper_1912_04385_amd import cptr
@@ -271,11 +271,11 @@ def exact_study(args, dev) -> int:
     rows = []
     for k, (pe, regime) in enumerate(EXACT_STUDY_PECLET):
         for n in EXACT_STUDY_GRIDS:
-            sy = assemble(n, n, 6, np.ones((n, n)), peclet=pe, seed=k, field_seed=k)
+            sy = assemble(n, n, EXACT_STUDY_BLOCK, np.ones((n, n)), peclet=pe, seed=k, field_seed=k)
             rp, ci = torch.from_numpy(sy.row_ptr).to(dev), torch.from_numpy(sy.col_idx).to(dev)
             vals, rhs = torch.from_numpy(sy.vals.reshape(-1)).to(dev), torch.from_numpy(sy.rhs).to(dev)
             for vname, v in variants:
-                subs = (0,) if v == cptr.VARIANT_LAST_ONLY else ((1, 0) if n <= EXACT_STUDY_DENSE_MAX else (0,))
+                subs = (0,) if v == cptr.VARIANT_LAST_ONLY else (1, 0)
                 for sub in subs:
                     sol = cptr.Solver(variant=v, exact_subsolves=sub, restart=30, max_iters=600, ilu_tile_x=32,
                                       ilu_tile_y=8)
@@ -294,7 +294,7 @@ def exact_study(args, dev) -> int:
                           f"conv={row['converged']} setup={row['setup_ms']} ms solve={row['solve_ms']} ms",
                           file=sys.stderr, flush=True)
     print(json.dumps({"study": "preconditioners by GMRES iterations: exact sub-solves vs AMG, grid sweep",
-                      "grids": list(EXACT_STUDY_GRIDS), "block": 6, "permeability": "homogeneous k=1",
+                      "grids": list(EXACT_STUDY_GRIDS), "block": EXACT_STUDY_BLOCK, "permeability": "homogeneous k=1",
                       "krylov": "GMRES(30), FP64, tol 1e-8, at most 600 iterations",
                       "last_stage": "BILU(0) in 32x8 tiles", "rows": rows,
                       "cv_across_peclet": cv_across_peclet(rows)}))
