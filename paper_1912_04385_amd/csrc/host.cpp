@@ -14,6 +14,7 @@
 #include <exception>
 #include <memory>
 #include <mutex>
+#include <future>
 #include <thread>
 #include <string>
 #include <type_traits>
@@ -763,18 +764,80 @@ static void read_bounds(Builder *c, Hierarchy &h) {
     }
 }
 
+// The fine level of a classical build handed to a second build (the learned
+// interpolation's judge): once the fine level's C/F split and classical
+// interpolation are formed, the classical builder publishes their device
+// buffers and an event on its stream; the second build copies them and goes
+// on from there (same level-0 arithmetic, so its hierarchy is the one a build
+// from scratch gives, bit for bit).  The promise resolves to false when the
+// classical build stops before forming an interpolation (a single level) or
+// fails.
+struct Level0Fork {
+    struct Shared {
+        int n = 0, nnz = 0, nc = 0, pnnz = 0;
+        const double *av = nullptr, *dinv = nullptr, *pv = nullptr;
+        const unsigned char *strong = nullptr;
+        const int *cf = nullptr, *prp = nullptr, *pci = nullptr;
+    } sh;
+    hipEvent_t ev = nullptr;
+    std::promise<bool> ready;
+    bool resolved = false;
+    void resolve(bool ok) {
+        if (!resolved) {
+            resolved = true;
+            ready.set_value(ok);
+        }
+    }
+};
+
+// the fine level of h from a published fork (allocated and copied on c's stream)
+static void level0_from_fork(Builder *c, Hierarchy &h, const Level0Fork::Shared &f) {
+    hipStream_t s = c->stream;
+    h.L.clear();
+    h.L.emplace_back();
+    Level &L = h.L.back();
+    L.A.n = L.A.ncols = f.n;
+    L.A.nnz = f.nnz;
+    L.A.rp = c->rp.p;
+    L.A.ci = c->ci.p;
+    L.A.v.alloc(f.nnz);
+    CPTR_HIP(hipMemcpyAsync(L.A.v.p, f.av, sizeof(double) * f.nnz, hipMemcpyDeviceToDevice, s));
+    L.dinv.alloc(f.n);
+    CPTR_HIP(hipMemcpyAsync(L.dinv.p, f.dinv, sizeof(double) * f.n, hipMemcpyDeviceToDevice, s));
+    L.strong.alloc((size_t)f.nnz + 1);
+    CPTR_HIP(hipMemcpyAsync(L.strong.p, f.strong, (size_t)f.nnz, hipMemcpyDeviceToDevice, s));
+    L.cf.alloc((size_t)f.n + 1);
+    CPTR_HIP(hipMemcpyAsync(L.cf.p, f.cf, sizeof(int) * f.n, hipMemcpyDeviceToDevice, s));
+    L.nc = f.nc;
+    CsrD &P = L.P;
+    P.n = f.n;
+    P.ncols = f.nc;
+    P.nnz = f.pnnz;
+    P.rp_own.alloc((size_t)f.n + 1);
+    CPTR_HIP(hipMemcpyAsync(P.rp_own.p, f.prp, sizeof(int) * (f.n + 1), hipMemcpyDeviceToDevice, s));
+    P.rp = P.rp_own.p;
+    P.ci_own.alloc((size_t)f.pnnz + 1);
+    P.v.alloc((size_t)f.pnnz + 1);
+    CPTR_HIP(hipMemcpyAsync(P.ci_own.p, f.pci, sizeof(int) * f.pnnz, hipMemcpyDeviceToDevice, s));
+    CPTR_HIP(hipMemcpyAsync(P.v.p, f.pv, sizeof(double) * f.pnnz, hipMemcpyDeviceToDevice, s));
+    P.ci = P.ci_own.p;
+}
+
 // `own` (optional): the buffer holding vals, taken over as the fine level's
 // values instead of copying them.  With c->parts set, the operator holds
-// several unknowns and is coarsened unknown by unknown.
+// several unknowns and is coarsened unknown by unknown.  `fork` (optional):
+// publish the fine level's classical interpolation for a second build.
+// resume: h already holds a fine level with its classical interpolation
+// (level0_from_fork); the build goes on from there.
 static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const float *mlp = nullptr,
-                            DBuf<double> *own = nullptr) {
+                            DBuf<double> *own = nullptr, Level0Fork *fork = nullptr, bool resume = false) {
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     const bool fp32 = (o.precond_precision == CPTR_FP32);
-    h.L.clear();
-    h.L.emplace_back();
     std::vector<int> parts = c->parts;
-    {
+    if (!resume) {
+        h.L.clear();
+        h.L.emplace_back();
         Level &L0 = h.L.back();
         L0.A.n = c->n;
         L0.A.ncols = c->n;
@@ -791,9 +854,12 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
     while (true) {
         Level &L = h.L.back();
         const int m = L.A.n;
-        L.dinv.alloc(m);
-        c->s_d1.alloc(m);   // diagonal of this level
-        amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
+        const bool resumed = resume && h.L.size() == 1;
+        if (!resumed) {
+            L.dinv.alloc(m);
+            c->s_d1.alloc(m);   // diagonal of this level
+            amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
+        }
         level_bound(c, h, (int)h.L.size() - 1);
         level_vectors(L, m, fp32);
         // (exact sub-solves: the fine level is the coarsest, applied by its
@@ -805,22 +871,38 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
             h.L.push_back(std::move(nxt));
             continue;
         }
-        L.strong.alloc((size_t)L.A.nnz + 1);
-        L.cf.alloc((size_t)m + 1);             // state -> C/F
-        InterpScratch is;
-        const int nc = interp_rows(c, L.A, c->s_d1.p, L.cf.p, L.strong.p, h.L.size() == 1, is, L.P);
-        if (nc == 0 || nc == m) break;
-        // A P needs only P's row pointers for its plan: P's size and the
-        // product's capacity in one read
         CsrD &P = L.P;
         SpgPlan pAP;
-        spgemm_plan(c, L.A, P, pAP);
         int rd[3];
-        read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
-        P.nnz = rd[0];
-        const int capAP = rd[1], maxAP = rd[2];
-        compact_interp(c, is, P);
-        L.nc = nc;
+        int nc, capAP, maxAP;
+        if (!resumed) {
+            L.strong.alloc((size_t)L.A.nnz + 1);
+            L.cf.alloc((size_t)m + 1);             // state -> C/F
+            InterpScratch is;
+            nc = interp_rows(c, L.A, c->s_d1.p, L.cf.p, L.strong.p, h.L.size() == 1, is, L.P);
+            if (nc == 0 || nc == m) break;
+            // A P needs only P's row pointers for its plan: P's size and the
+            // product's capacity in one read
+            spgemm_plan(c, L.A, P, pAP);
+            read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
+            P.nnz = rd[0];
+            capAP = rd[1];
+            maxAP = rd[2];
+            compact_interp(c, is, P);
+            L.nc = nc;
+            if (fork && h.L.size() == 1) {
+                fork->sh = {m, L.A.nnz, nc, P.nnz, L.A.v.p, L.dinv.p, P.v.p, L.strong.p, L.cf.p, P.rp_own.p,
+                            P.ci_own.p};
+                CPTR_HIP(hipEventRecord(fork->ev, s));
+                fork->resolve(true);
+            }
+        } else {
+            nc = L.nc;
+            spgemm_plan(c, L.A, P, pAP);
+            read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
+            capAP = rd[1];
+            maxAP = rd[2];
+        }
         if (mlp && h.L.size() == 1) apply_learned(s, L, mlp);
         csr_transpose(c, P, L.R);
         CsrD AP;
@@ -835,6 +917,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         spgemm_finish(c, pRAP, read_scalar(nxt.A.rp_own.p + nc, s), nxt.A);
         h.L.push_back(std::move(nxt));
     }
+    if (fork) fork->resolve(false);    // no fine-level interpolation formed
     read_bounds(c, h);
     coarse_inverse(c, h);
     hierarchy_fp32(c, h);
@@ -1140,7 +1223,10 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     }
     const bool judge = (c->opt.t_interp == CPTR_INTERP_LEARNED);
     // the learned hierarchy (and its convergence factor) on its own stream
-    // and host thread, concurrently with the classical one
+    // and host thread, concurrently with the classical one; it starts from
+    // the classical build's fine level once that level's C/F split and
+    // classical interpolation are formed (the learned correction changes
+    // only the fine level's weights)
     Hierarchy hl;
     double rl = -1.0;
     std::exception_ptr err;
@@ -1153,8 +1239,14 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     B2.nnzb = B.nnzb;
     B2.rp.p = B.rp.p;
     B2.ci.p = B.ci.p;
-    CPTR_HIP(hipEventRecord(c->ev_side[2], B.stream));   // vals are ready on B's stream
-    std::thread t2([c, &B2, &hl, &rl, &err, vals, judge]() {
+    Level0Fork fork;
+    CPTR_HIP(hipEventCreateWithFlags(&fork.ev, hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t e;
+        ~EvGuard() { if (e) (void)hipEventDestroy(e); }
+    } evg{fork.ev};
+    std::future<bool> published = fork.ready.get_future();
+    std::thread t2([c, &B2, &hl, &rl, &err, &fork, &published, judge]() {
         try {
             CPTR_HIP(hipSetDevice(c->device));
             StreamScope scope(B2.stream);
@@ -1162,8 +1254,10 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
                 B2.flag.alloc(4);
                 fill_int(B2.flag.p, 0, 1, B2.stream);
             }
-            CPTR_HIP(hipStreamWaitEvent(B2.stream, c->ev_side[2], 0));
-            build_hierarchy(&B2, hl, vals, c->mlp.p);
+            if (!published.get()) return;      // no fine-level interpolation: nothing to learn
+            CPTR_HIP(hipStreamWaitEvent(B2.stream, fork.ev, 0));
+            level0_from_fork(&B2, hl, fork.sh);
+            build_hierarchy(&B2, hl, nullptr, c->mlp.p, nullptr, nullptr, true);
             if (judge && hl.L.size() > 1) rl = conv_factor(c, hl, RHO_CYCLES, RHO_SEED, B2.stream);
         } catch (...) {
             err = std::current_exception();
@@ -1172,17 +1266,16 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     std::exception_ptr err1;
     double rc = -1.0;
     try {
-        // the values are copied here: the losing hierarchy is released while
-        // the other stream may still read them
-        build_hierarchy(&B, c->H[k], vals);
+        build_hierarchy(&B, c->H[k], vals, nullptr, own, &fork);
         if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
     } catch (...) {
         err1 = std::current_exception();
+        fork.resolve(false);
     }
     t2.join();
     if (err1) std::rethrow_exception(err1);
     if (err) std::rethrow_exception(err);
-    if (c->H[k].L.size() < 2) return;           // a single level: no interpolation to learn
+    if (c->H[k].L.size() < 2 || hl.L.size() < 2) return;   // a single level: no interpolation to learn
     if (!judge || rl < rc) {
         c->H[k] = std::move(hl);
         c->used_learned = 1;
