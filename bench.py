@@ -43,11 +43,11 @@ def spmv_algorithmic_bytes(n: int, nnzb: int, b: int, s: int = 8) -> int:
 
 def kernel_source_hash() -> str:
     """Hash of the BSR SpMV section of the Krylov kernel source (from its
-    launch constant to the start of the reductions): the counter summary
+    launch constants to the start of the reductions): the counter summary
     holds only while that code is unchanged."""
     p = os.path.join(ROOT, "paper_1912_04385_amd", "csrc", "k_krylov.hip")
     src = open(p, "rb").read()
-    a = src.index(b"constexpr int SPMV_UNROLL")
+    a = src.index(b"constexpr int SPMV_ROWS")
     b = src.index(b"constexpr int KR_THREADS")
     return hashlib.sha256(src[a:b]).hexdigest()[:16]
 

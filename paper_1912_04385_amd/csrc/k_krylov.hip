@@ -9,54 +9,78 @@ namespace cptr {
 // BSR SpMV
 // ---------------------------------------------------------------------------
 
-// b = 8: one wavefront per block row; lane l owns block entry (l/8, l%8), so
-// the row's value stream (contiguous, 512 B per block) is read fully
-// coalesced; the 8 partial products of a row are summed with xor shuffles.
-// The row index is made wave-uniform so that the row pointers and block
-// columns come through scalar loads, and all value and x loads of a row are
-// issued before the first product (up to SPMV_UNROLL blocks in flight per
-// wave).  The value stream is read once: non-temporal loads keep it from
-// evicting x from the caches.
-constexpr int SPMV_UNROLL = 5;
+// b = 8: one wavefront per SPMV_ROWS consecutive block rows, whose blocks
+// form one contiguous range of the value stream (512 B per block).  Every
+// load instruction covers two blocks: half h of the wavefront takes block
+// e0 + 2u + h, and lane p of a half holds the entry pair (p/4, 2(p%4)),
+// (p/4, 2(p%4)+1) of it in one 16-byte load, with the matching pair of x.
+// All SPMV_PAIRS pair loads of a batch are issued before the first product
+// (ten blocks: the two interior rows of the 5-point pattern in one batch);
+// each product is added to the partial sum of the row its block belongs to,
+// and the four lanes of a block row and the two halves are combined with
+// xor shuffles.  The value stream is read once: non-temporal loads keep it
+// from evicting x from the caches.
+constexpr int SPMV_ROWS = 2;
+constexpr int SPMV_PAIRS = 5;
+
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 template <bool RESID>
 __global__ void __launch_bounds__(256) k_bsr8(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                               const double *__restrict__ A, const double *__restrict__ x,
                                               const double *__restrict__ rhs, double *__restrict__ y) {
+    constexpr int R = SPMV_ROWS, PAIRS = SPMV_PAIRS;
     const int lane = threadIdx.x & 63;
-    const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    if (row >= n) return;
-    const int c = lane & 7;
-    const int a = rp[row], e1 = rp[row + 1];
-    double acc = 0.0;
-    const int last = e1 - 1;   // the diagonal block is always present: e1 > a
-    for (int e0 = a; e0 < e1; e0 += SPMV_UNROLL) {
-        // clamped entry indices: every load is in bounds and the batch has no
-        // branches; entries past the row end are loaded again and not summed
-        // (one vector load fetches the block columns; readlane makes them scalar)
-        int ek[SPMV_UNROLL], jk[SPMV_UNROLL];
-        const int jl = ci[min(e0 + (lane & 7), last)];
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const int row0 = w * R;
+    if (row0 >= n) return;
+    const int nr = min(R, n - row0);
+    const int h = lane >> 5, p = lane & 31;
+    const int r = p >> 2, c0 = (p & 3) * 2;
+    int rb[R + 1];
 #pragma unroll
-        for (int u = 0; u < SPMV_UNROLL; ++u) {
-            ek[u] = min(e0 + u, last);
-            jk[u] = __builtin_amdgcn_readlane(jl, u);
+    for (int k = 0; k <= R; ++k) rb[k] = rp[row0 + min(k, nr)];
+    const int ea = rb[0], eb = rb[R];
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    for (int e0 = ea; e0 < eb; e0 += 2 * PAIRS) {
+        // clamped entry indices: every load is in bounds; entries past the
+        // range are loaded again and not summed (every row holds its
+        // diagonal block, so eb > ea)
+        int ek[PAIRS], jk[PAIRS];
+#pragma unroll
+        for (int u = 0; u < PAIRS; ++u) {
+            ek[u] = min(e0 + 2 * u + h, eb - 1);
+            jk[u] = ci[ek[u]];
         }
-        double av[SPMV_UNROLL], xv[SPMV_UNROLL];
+        v2d av[PAIRS], xv[PAIRS];
 #pragma unroll
-        for (int u = 0; u < SPMV_UNROLL; ++u) {
-            av[u] = __builtin_nontemporal_load(A + (size_t)ek[u] * 64 + lane);
-            xv[u] = x[(size_t)jk[u] * 8 + c];
+        for (int u = 0; u < PAIRS; ++u) {
+            av[u] = __builtin_nontemporal_load((const v2d *)(A + (size_t)ek[u] * 64 + r * 8 + c0));
+            xv[u] = *(const v2d *)(x + (size_t)jk[u] * 8 + c0);
         }
 #pragma unroll
-        for (int u = 0; u < SPMV_UNROLL; ++u)
-            if (e0 + u < e1) acc += av[u] * xv[u];
+        for (int u = 0; u < PAIRS; ++u) {
+            const int e = e0 + 2 * u + h;
+            if (e < eb) {
+                const double pr = av[u].x * xv[u].x + av[u].y * xv[u].y;
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (e >= rb[k] && e < rb[k + 1]) acc[k] += pr;
+            }
+        }
     }
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    acc += __shfl_xor(acc, 4, 64);
-    if (c == 0) {
-        const size_t o = (size_t)row * 8 + (lane >> 3);
-        y[o] = RESID ? rhs[o] - acc : acc;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        double v = acc[k];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (k < nr && lane < 32 && (p & 3) == 0) {
+            const size_t o = (size_t)(row0 + k) * 8 + r;
+            y[o] = RESID ? rhs[o] - v : v;
+        }
     }
 }
 
@@ -81,7 +105,8 @@ void launch_bsr_spmv(int n, int b, const int *rp, const int *ci, const double *A
                      hipStream_t s) {
     if (n == 0) return;
     if (b == 8)
-        hipLaunchKernelGGL(k_bsr8<false>, dim3((n + 3) / 4), dim3(256), 0, s, n, rp, ci, A, x, nullptr, y);
+        hipLaunchKernelGGL(k_bsr8<false>, dim3((n + SPMV_ROWS * 4 - 1) / (SPMV_ROWS * 4)), dim3(256), 0, s, n, rp,
+                           ci, A, x, nullptr, y);
     else
         hipLaunchKernelGGL(k_bsr_gen<false>, dim3(((long)n * b + 255) / 256), dim3(256), 0, s, n, b, rp, ci, A, x,
                            nullptr, y);
@@ -92,7 +117,8 @@ void launch_bsr_residual(int n, int b, const int *rp, const int *ci, const doubl
                          const double *rhs, double *r, hipStream_t s) {
     if (n == 0) return;
     if (b == 8)
-        hipLaunchKernelGGL(k_bsr8<true>, dim3((n + 3) / 4), dim3(256), 0, s, n, rp, ci, A, x, rhs, r);
+        hipLaunchKernelGGL(k_bsr8<true>, dim3((n + SPMV_ROWS * 4 - 1) / (SPMV_ROWS * 4)), dim3(256), 0, s, n, rp,
+                           ci, A, x, rhs, r);
     else
         hipLaunchKernelGGL(k_bsr_gen<true>, dim3(((long)n * b + 255) / 256), dim3(256), 0, s, n, b, rp, ci, A, x,
                            rhs, r);
