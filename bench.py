@@ -407,7 +407,7 @@ def read_ceiling(dev, nbytes: int = 4 << 30, reps: int = 10) -> dict:
     best = min(ms)
     med = sorted(ms)[len(ms) // 2]
     del x
-    return {"kernel": "k_stream_read (non-temporal 8-byte loads, 512 B per wavefront load)", "bytes": nbytes,
+    return {"kernel": "k_stream_read (non-temporal 16-byte loads, 1 KB per wavefront load)", "bytes": nbytes,
             "GBps_median": round(nbytes / (med * 1e-3) / 1e9, 1), "GBps_best": round(nbytes / (best * 1e-3) / 1e9, 1),
             "frac_of_8TBps_median": round(nbytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 

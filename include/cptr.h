@@ -265,14 +265,17 @@ cptr_status cptr_decouple_noalloc(int32_t variant, int32_t n_cells, int32_t b, c
 
 /* Measurement of the HBM streaming-read rate that bounds the solve's
  * bandwidth-bound kernels (not part of the method): reads the n doubles of
- * d_x once, with the outer SpMV's access pattern (non-temporal 8-byte loads,
- * 512 contiguous bytes per wavefront load), and writes one partial sum per
+ * d_x once, with the outer SpMV's access pattern (non-temporal 16-byte loads,
+ * 1 KB of contiguous bytes per wavefront load), and writes one partial sum per
  * workgroup to d_part.  *blocks (host) receives the number of workgroups,
  * i.e. the doubles d_part must hold; with d_x = d_part = NULL the call only
- * reports it.  Asynchronous on the stream; the caller times it. */
+ * reports it.  d_x must be 16-byte aligned (CPTR_E_ARG otherwise).
+ * Asynchronous on the stream; the caller times it. */
 cptr_status cptr_stream_read(const double *d_x, uint64_t n, double *d_part, int32_t *blocks, void *hip_stream);
 
-/* y = A x for a BSR matrix (the outer operator apply of every Arnoldi step). */
+/* y = A x for a BSR matrix (the outer operator apply of every Arnoldi step).
+ * At b = 8 the values and x must be 16-byte aligned (any hipMalloc or torch
+ * allocation is); CPTR_E_ARG otherwise. */
 cptr_status cptr_bsr_spmv(int32_t n_cells, int32_t b, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                           const double *d_vals, const double *d_x, double *d_y, void *hip_stream);
 

@@ -1976,6 +1976,7 @@ cptr_status cptr_stream_read(const double *d_x, uint64_t n, double *d_part, int3
     *blocks = stream_read_blocks((size_t)n);
     if (!d_x && !d_part) return CPTR_OK;       // size query
     if (!d_x || !d_part) throw Error(CPTR_E_ARG, "null pointer");
+    if ((uintptr_t)d_x & 15) throw Error(CPTR_E_ARG, "d_x must be 16-byte aligned");
     if (n == 0) return CPTR_OK;
     launch_stream_read((size_t)n, d_x, d_part, (hipStream_t)stream);
     return CPTR_OK;
@@ -1986,6 +1987,8 @@ cptr_status cptr_bsr_spmv(int32_t n, int32_t b, const int32_t *d_rp, const int32
                           const double *d_x, double *d_y, void *stream) {
     CPTR_API_BEGIN
     if (n < 0 || b < 1 || b > 8) throw Error(CPTR_E_ARG, "sizes");
+    if (b == 8 && (((uintptr_t)d_vals | (uintptr_t)d_x) & 15))
+        throw Error(CPTR_E_ARG, "block size 8 needs 16-byte aligned values and x");
     launch_bsr_spmv(n, b, d_rp, d_ci, d_vals, d_x, d_y, (hipStream_t)stream);
     return CPTR_OK;
     CPTR_API_END
