@@ -413,7 +413,7 @@ template void bilu_tile_blocks<float>(const TileSched &, int, int, const int *, 
 //   mode 0: forward only (t to LDS and global)
 //   mode 1: forward then backward (the last colour); w to global, y written
 //   mode 2: backward only (t read from global); y written
-constexpr int PF = 4;
+constexpr int PF = 8;
 
 template <class T, int B>
 struct LevelRegs {
