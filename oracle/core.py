@@ -323,12 +323,11 @@ def galerkin(A: CSR, P: CSR, R: CSR) -> CSR:
     return spgemm(R, spgemm(A, P))
 
 
-def amg_setup(A: CSR, opts: AMGOptions | None = None, interp_fn=None) -> Hierarchy:
+def amg_setup(A: CSR, opts: AMGOptions | None = None) -> Hierarchy:
     """Classical AMG hierarchy: strength -> PMIS -> extended+i (+ truncation)
     -> R = P^T -> A_c = R A P, until the level has at most ``max_coarse`` rows,
     ``max_levels`` is reached or coarsening stalls; the coarsest level is
-    factored densely (LU with partial pivoting).  ``interp_fn(level_index, A,
-    s, cf)`` may replace the interpolation (the learned variant)."""
+    factored densely (LU with partial pivoting)."""
     opts = opts or AMGOptions()
     levels = []
     cur = A
@@ -342,7 +341,7 @@ def amg_setup(A: CSR, opts: AMGOptions | None = None, interp_fn=None) -> Hierarc
         nc = int(cf.sum())
         if nc == 0 or nc == cur.nrows:
             break
-        P = interp_fn(len(levels) - 1, cur, s, cf) if interp_fn else interp_exti(cur, s, cf, opts.pmax)
+        P = interp_exti(cur, s, cf, opts.pmax)
         R = P.transpose()
         L.P, L.R, L.strong, L.cf = P, R, s, cf
         cur = galerkin(cur, P, R)
@@ -476,20 +475,26 @@ def _finish_hierarchy(levels: list, opts: AMGOptions) -> Hierarchy:
     return Hierarchy(levels, lu, piv, opts)
 
 
-def amg_refresh(h: Hierarchy, A: CSR) -> Hierarchy:
+def amg_refresh(h: Hierarchy, A: CSR, P0: CSR | None = None) -> Hierarchy:
     """Reuse of hierarchy ``h`` for new level-0 values ``A`` on the same
     pattern (the next system of a Newton sequence): the C/F splits and the
     transfer operators P, R = P^T of every level are kept; the Galerkin
     products A_{l+1} = R A_l P, the smoother data and the coarsest LU are
-    recomputed from the new values."""
+    recomputed from the new values.  ``P0`` (optional) replaces the fine
+    level's interpolation by other weights on the same C/F split (the learned
+    interpolation), with R_0 = P0^T; the coarser levels keep h's splits and
+    transfer operators."""
     levels = []
     cur = A
-    for old in h.levels:
-        L = Level(cur, cur.diagonal(), old.P, old.R, old.strong, old.cf)
+    for l, old in enumerate(h.levels):
+        P, R = old.P, old.R
+        if l == 0 and P0 is not None and P is not None:
+            P, R = P0, P0.transpose()
+        L = Level(cur, cur.diagonal(), P, R, old.strong, old.cf)
         levels.append(L)
-        if old.P is None:
+        if P is None:
             break
-        cur = galerkin(cur, old.P, old.R)
+        cur = galerkin(cur, P, R)
     return _finish_hierarchy(levels, h.opts)
 
 
@@ -928,9 +933,13 @@ def build_preconditioner(dec: Decoupled, opts: Options, previous: dict | None = 
             if name == "T" and opts.mlp_params is not None and len(h.levels) > 1:
                 # the learned fine-level interpolation, judged at every full
                 # build by the V-cycle convergence factor against the
-                # classical one: kept only when its factor is lower
-                from .learned import learned_interp
-                hl = amg_setup(A, opts.amg, learned_interp(opts.mlp_params))
+                # classical one: kept only when its factor is lower.  The
+                # learned hierarchy differs from the classical one only in
+                # the fine level's weights (coarser levels: the classical
+                # C/F splits and transfer operators, Galerkin products
+                # formed from the learned fine level down)
+                from .learned import learned_hierarchy
+                hl = learned_hierarchy(opts.mlp_params, h)
                 rc = conv_factor(h, opts.rho_cycles, 0)
                 rl = conv_factor(hl, opts.rho_cycles, 0)
                 use = rl < rc

@@ -282,18 +282,22 @@ class Adam:
         return params - self.lr * mhat / (np.sqrt(vhat) + self.eps)
 
 
-def learned_interp(params: np.ndarray):
-    """``interp_fn`` for ``amg_setup``: the learned weights on the fine level,
-    classical extended+i on the coarser levels."""
-    from .core import interp_exti
+def learned_fine_interp(params: np.ndarray, A, s: np.ndarray, cf: np.ndarray, P):
+    """The learned weights of the classical fine-level interpolation P of
+    operator A (strength flags s, C/F split cf): P itself when it has no F-row
+    edge."""
+    e = edge_features(A, s, cf, P)
+    if len(e.row) == 0:
+        return P
+    o, _ = forward(params, e.X)
+    return learned_weights(P, e, delta_of(o))
 
-    def fn(level, A, s, cf):
-        P = interp_exti(A, s, cf, 4)
-        if level != 0:
-            return P
-        e = edge_features(A, s, cf, P)
-        if len(e.row) == 0:
-            return P
-        o, _ = forward(params, e.X)
-        return learned_weights(P, e, delta_of(o))
-    return fn
+
+def learned_hierarchy(params: np.ndarray, h):
+    """The learned counterpart of the classical hierarchy h: its fine level's
+    interpolation with the learned weights, and below it h's C/F splits and
+    transfer operators, the Galerkin products formed from the learned fine
+    level down (h's refresh with a new fine-level interpolation)."""
+    from .core import amg_refresh
+    L0 = h.levels[0]
+    return amg_refresh(h, L0.A, learned_fine_interp(params, L0.A, L0.strong, L0.cf, L0.P))

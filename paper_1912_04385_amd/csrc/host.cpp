@@ -13,6 +13,7 @@
 #include <cstring>
 #include <exception>
 #include <memory>
+#include <condition_variable>
 #include <mutex>
 #include <future>
 #include <thread>
@@ -764,102 +765,115 @@ static void read_bounds(Builder *c, Hierarchy &h) {
     }
 }
 
-// The fine level of a classical build handed to a second build (the learned
-// interpolation's judge): once the fine level's C/F split and classical
-// interpolation are formed, the classical builder publishes their device
-// buffers and an event on its stream; the second build copies them and goes
-// on from there (same level-0 arithmetic, so its hierarchy is the one a build
-// from scratch gives, bit for bit).  The promise resolves to false when the
-// classical build stops before forming an interpolation (a single level) or
-// fails.
-struct Level0Fork {
-    struct Shared {
-        int n = 0, nnz = 0, nc = 0, pnnz = 0;
-        const double *av = nullptr, *dinv = nullptr, *pv = nullptr;
+// The levels of a classical build handed to a second build that keeps its
+// C/F splits and transfer operators (the learned interpolation's judge).
+// The classical builder publishes level 0 once its C/F split and classical
+// interpolation are formed (with the fine operator, its smoother diagonal
+// and strength flags), and every coarser level once its interpolation and
+// restriction are formed, each with an event recorded on its stream; it
+// closes the feed when it stops forming interpolations (or fails).  The
+// published device buffers stay unchanged until the classical hierarchy is
+// destroyed, which the caller does only after the second build has ended.
+struct LevelFeed {
+    struct Csr {
+        int n = 0, ncols = 0, nnz = 0;
+        const int *rp = nullptr, *ci = nullptr;
+        const double *v = nullptr;
+    };
+    struct Item {
+        int n = 0, nc = 0;
+        const int *cf = nullptr;
+        Csr P, R;                                   // R: coarser levels only
+        int annz = 0;                               // level 0: the operator
+        const double *av = nullptr, *dinv = nullptr;
         const unsigned char *strong = nullptr;
-        const int *cf = nullptr, *prp = nullptr, *pci = nullptr;
-    } sh;
-    hipEvent_t ev = nullptr;
-    std::promise<bool> ready;
-    bool resolved = false;
-    void resolve(bool ok) {
-        if (!resolved) {
-            resolved = true;
-            ready.set_value(ok);
+        hipEvent_t ev = nullptr;
+    };
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<Item> items;
+    bool closed = false;
+    LevelFeed() = default;
+    LevelFeed(const LevelFeed &) = delete;
+    LevelFeed &operator=(const LevelFeed &) = delete;
+    ~LevelFeed() {
+        for (auto &it : items)
+            if (it.ev) (void)hipEventDestroy(it.ev);
+    }
+    static Csr view(const CsrD &a) { return {a.n, a.ncols, a.nnz, a.rp, a.ci, a.v.p}; }
+    void publish(Item it, hipStream_t s) {
+        CPTR_HIP(hipEventCreateWithFlags(&it.ev, hipEventDisableTiming));
+        const hipError_t e = hipEventRecord(it.ev, s);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            items.push_back(it);      // (the destructor releases the event)
         }
+        cv.notify_all();
+        if (e != hipSuccess) throw Error(CPTR_E_HIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+    }
+    void close() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            closed = true;
+        }
+        cv.notify_all();
+    }
+    // level l of the classical build, or false once the feed closed without it
+    bool wait(size_t l, Item &out) {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return items.size() > l || closed; });
+        if (items.size() <= l) return false;
+        out = items[l];
+        return true;
     }
 };
 
-// the fine level of h from a published fork (allocated and copied on c's stream)
-static void level0_from_fork(Builder *c, Hierarchy &h, const Level0Fork::Shared &f) {
-    hipStream_t s = c->stream;
-    h.L.clear();
-    h.L.emplace_back();
-    Level &L = h.L.back();
-    L.A.n = L.A.ncols = f.n;
-    L.A.nnz = f.nnz;
-    L.A.rp = c->rp.p;
-    L.A.ci = c->ci.p;
-    L.A.v.alloc(f.nnz);
-    CPTR_HIP(hipMemcpyAsync(L.A.v.p, f.av, sizeof(double) * f.nnz, hipMemcpyDeviceToDevice, s));
-    L.dinv.alloc(f.n);
-    CPTR_HIP(hipMemcpyAsync(L.dinv.p, f.dinv, sizeof(double) * f.n, hipMemcpyDeviceToDevice, s));
-    L.strong.alloc((size_t)f.nnz + 1);
-    CPTR_HIP(hipMemcpyAsync(L.strong.p, f.strong, (size_t)f.nnz, hipMemcpyDeviceToDevice, s));
-    L.cf.alloc((size_t)f.n + 1);
-    CPTR_HIP(hipMemcpyAsync(L.cf.p, f.cf, sizeof(int) * f.n, hipMemcpyDeviceToDevice, s));
-    L.nc = f.nc;
-    CsrD &P = L.P;
-    P.n = f.n;
-    P.ncols = f.nc;
-    P.nnz = f.pnnz;
-    P.rp_own.alloc((size_t)f.n + 1);
-    CPTR_HIP(hipMemcpyAsync(P.rp_own.p, f.prp, sizeof(int) * (f.n + 1), hipMemcpyDeviceToDevice, s));
-    P.rp = P.rp_own.p;
-    P.ci_own.alloc((size_t)f.pnnz + 1);
-    P.v.alloc((size_t)f.pnnz + 1);
-    CPTR_HIP(hipMemcpyAsync(P.ci_own.p, f.pci, sizeof(int) * f.pnnz, hipMemcpyDeviceToDevice, s));
-    CPTR_HIP(hipMemcpyAsync(P.v.p, f.pv, sizeof(double) * f.pnnz, hipMemcpyDeviceToDevice, s));
-    P.ci = P.ci_own.p;
+static void copy_csr(hipStream_t s, const LevelFeed::Csr &a, CsrD &d) {
+    d.n = a.n;
+    d.ncols = a.ncols;
+    d.nnz = a.nnz;
+    d.rp_own.alloc((size_t)a.n + 1);
+    d.ci_own.alloc((size_t)a.nnz + 1);
+    d.v.alloc((size_t)a.nnz + 1);
+    CPTR_HIP(hipMemcpyAsync(d.rp_own.p, a.rp, sizeof(int) * (a.n + 1), hipMemcpyDeviceToDevice, s));
+    if (a.nnz) {
+        CPTR_HIP(hipMemcpyAsync(d.ci_own.p, a.ci, sizeof(int) * a.nnz, hipMemcpyDeviceToDevice, s));
+        CPTR_HIP(hipMemcpyAsync(d.v.p, a.v, sizeof(double) * a.nnz, hipMemcpyDeviceToDevice, s));
+    }
+    d.rp = d.rp_own.p;
+    d.ci = d.ci_own.p;
 }
 
 // `own` (optional): the buffer holding vals, taken over as the fine level's
 // values instead of copying them.  With c->parts set, the operator holds
-// several unknowns and is coarsened unknown by unknown.  `fork` (optional):
-// publish the fine level's classical interpolation for a second build.
-// resume: h already holds a fine level with its classical interpolation
-// (level0_from_fork); the build goes on from there.
-static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const float *mlp = nullptr,
-                            DBuf<double> *own = nullptr, Level0Fork *fork = nullptr, bool resume = false) {
+// several unknowns and is coarsened unknown by unknown.  `feed` (optional):
+// publish every level's classical interpolation for a second build.
+static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<double> *own = nullptr,
+                            LevelFeed *feed = nullptr) {
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     const bool fp32 = (o.precond_precision == CPTR_FP32);
     std::vector<int> parts = c->parts;
-    if (!resume) {
-        h.L.clear();
-        h.L.emplace_back();
-        Level &L0 = h.L.back();
-        L0.A.n = c->n;
-        L0.A.ncols = c->n;
-        L0.A.nnz = c->nnzb;
-        L0.A.rp = c->rp.p;
-        L0.A.ci = c->ci.p;
-        if (own && own->p == vals && own->n >= (size_t)c->nnzb) {
-            L0.A.v = std::move(*own);
-        } else {
-            L0.A.v.alloc(c->nnzb);
-            CPTR_HIP(hipMemcpyAsync(L0.A.v.p, vals, sizeof(double) * c->nnzb, hipMemcpyDeviceToDevice, s));
-        }
+    h.L.clear();
+    h.L.emplace_back();
+    Level &L0 = h.L.back();
+    L0.A.n = c->n;
+    L0.A.ncols = c->n;
+    L0.A.nnz = c->nnzb;
+    L0.A.rp = c->rp.p;
+    L0.A.ci = c->ci.p;
+    if (own && own->p == vals && own->n >= (size_t)c->nnzb) {
+        L0.A.v = std::move(*own);
+    } else {
+        L0.A.v.alloc(c->nnzb);
+        CPTR_HIP(hipMemcpyAsync(L0.A.v.p, vals, sizeof(double) * c->nnzb, hipMemcpyDeviceToDevice, s));
     }
     while (true) {
         Level &L = h.L.back();
         const int m = L.A.n;
-        const bool resumed = resume && h.L.size() == 1;
-        if (!resumed) {
-            L.dinv.alloc(m);
-            c->s_d1.alloc(m);   // diagonal of this level
-            amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
-        }
+        L.dinv.alloc(m);
+        c->s_d1.alloc(m);   // diagonal of this level
+        amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
         level_bound(c, h, (int)h.L.size() - 1);
         level_vectors(L, m, fp32);
         // (exact sub-solves: the fine level is the coarsest, applied by its
@@ -874,37 +888,42 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         CsrD &P = L.P;
         SpgPlan pAP;
         int rd[3];
-        int nc, capAP, maxAP;
-        if (!resumed) {
-            L.strong.alloc((size_t)L.A.nnz + 1);
-            L.cf.alloc((size_t)m + 1);             // state -> C/F
-            InterpScratch is;
-            nc = interp_rows(c, L.A, c->s_d1.p, L.cf.p, L.strong.p, h.L.size() == 1, is, L.P);
-            if (nc == 0 || nc == m) break;
-            // A P needs only P's row pointers for its plan: P's size and the
-            // product's capacity in one read
-            spgemm_plan(c, L.A, P, pAP);
-            read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
-            P.nnz = rd[0];
-            capAP = rd[1];
-            maxAP = rd[2];
-            compact_interp(c, is, P);
-            L.nc = nc;
-            if (fork && h.L.size() == 1) {
-                fork->sh = {m, L.A.nnz, nc, P.nnz, L.A.v.p, L.dinv.p, P.v.p, L.strong.p, L.cf.p, P.rp_own.p,
-                            P.ci_own.p};
-                CPTR_HIP(hipEventRecord(fork->ev, s));
-                fork->resolve(true);
-            }
-        } else {
-            nc = L.nc;
-            spgemm_plan(c, L.A, P, pAP);
-            read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
-            capAP = rd[1];
-            maxAP = rd[2];
+        L.strong.alloc((size_t)L.A.nnz + 1);
+        L.cf.alloc((size_t)m + 1);             // state -> C/F
+        InterpScratch is;
+        const int nc = interp_rows(c, L.A, c->s_d1.p, L.cf.p, L.strong.p, h.L.size() == 1, is, L.P);
+        if (nc == 0 || nc == m) break;
+        // A P needs only P's row pointers for its plan: P's size and the
+        // product's capacity in one read
+        spgemm_plan(c, L.A, P, pAP);
+        read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
+        P.nnz = rd[0];
+        const int capAP = rd[1], maxAP = rd[2];
+        compact_interp(c, is, P);
+        L.nc = nc;
+        const bool fine = h.L.size() == 1;
+        if (feed && fine) {
+            LevelFeed::Item it;
+            it.n = m;
+            it.nc = nc;
+            it.cf = L.cf.p;
+            it.P = LevelFeed::view(P);
+            it.annz = L.A.nnz;
+            it.av = L.A.v.p;
+            it.dinv = L.dinv.p;
+            it.strong = L.strong.p;
+            feed->publish(it, s);
         }
-        if (mlp && h.L.size() == 1) apply_learned(s, L, mlp);
         csr_transpose(c, P, L.R);
+        if (feed && !fine) {
+            LevelFeed::Item it;
+            it.n = m;
+            it.nc = nc;
+            it.cf = L.cf.p;
+            it.P = LevelFeed::view(P);
+            it.R = LevelFeed::view(L.R);
+            feed->publish(it, s);
+        }
         CsrD AP;
         spgemm_compute(c, L.A, P, pAP, capAP, maxAP, AP);
         // R (A P) needs only A P's row pointers for its plan
@@ -917,7 +936,76 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, const 
         spgemm_finish(c, pRAP, read_scalar(nxt.A.rp_own.p + nc, s), nxt.A);
         h.L.push_back(std::move(nxt));
     }
-    if (fork) fork->resolve(false);    // no fine-level interpolation formed
+    if (feed) feed->close();
+    read_bounds(c, h);
+    coarse_inverse(c, h);
+    hierarchy_fp32(c, h);
+    CPTR_HIP(hipStreamSynchronize(s));
+    h.built = true;
+}
+
+// The learned counterpart of a classical build that publishes its levels on
+// `feed`: the fine level with the classical C/F split and interpolation
+// pattern, the learned weights and R_0 = P_0^T; below it the classical
+// build's C/F splits and transfer operators (copied as each level is
+// published), with every Galerkin product A_{l+1} = R_l A_l P_l formed from
+// this hierarchy's own finer level, then its smoother diagonals, bounds and
+// coarsest inverse.  It runs on c's stream, level by level behind the
+// classical build.  Empty when the classical build forms no interpolation.
+static void build_learned_hierarchy(Builder *c, Hierarchy &h, const float *mlp, LevelFeed &feed) {
+    hipStream_t s = c->stream;
+    const cptr_options &o = c->opt;
+    const bool fp32 = (o.precond_precision == CPTR_FP32);
+    h.L.clear();
+    LevelFeed::Item it;
+    if (!feed.wait(0, it)) return;
+    CPTR_HIP(hipStreamWaitEvent(s, it.ev, 0));
+    h.L.emplace_back();
+    {
+        Level &L0 = h.L.back();
+        L0.A.n = L0.A.ncols = it.n;
+        L0.A.nnz = it.annz;
+        L0.A.rp = c->rp.p;
+        L0.A.ci = c->ci.p;
+        L0.A.v.alloc(it.annz);
+        CPTR_HIP(hipMemcpyAsync(L0.A.v.p, it.av, sizeof(double) * it.annz, hipMemcpyDeviceToDevice, s));
+        L0.dinv.alloc(it.n);
+        CPTR_HIP(hipMemcpyAsync(L0.dinv.p, it.dinv, sizeof(double) * it.n, hipMemcpyDeviceToDevice, s));
+        L0.strong.alloc((size_t)it.annz + 1);
+        CPTR_HIP(hipMemcpyAsync(L0.strong.p, it.strong, (size_t)it.annz, hipMemcpyDeviceToDevice, s));
+    }
+    for (size_t l = 0;; ++l) {
+        Level &L = h.L[l];
+        const int m = L.A.n;
+        if (l > 0) {
+            L.dinv.alloc(m);
+            c->s_d1.alloc(m);
+            amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
+        }
+        level_bound(c, h, (int)l);
+        level_vectors(L, m, fp32);
+        if (l > 0) {
+            // the classical level l: its split and transfer operators, or none
+            // (then this level is the coarsest, as it is there)
+            if (!feed.wait(l, it)) break;
+            CPTR_HIP(hipStreamWaitEvent(s, it.ev, 0));
+        }
+        L.nc = it.nc;
+        L.cf.alloc((size_t)m + 1);
+        CPTR_HIP(hipMemcpyAsync(L.cf.p, it.cf, sizeof(int) * m, hipMemcpyDeviceToDevice, s));
+        copy_csr(s, it.P, L.P);
+        if (l == 0) {
+            apply_learned(s, L, mlp);
+            csr_transpose(c, L.P, L.R);
+        } else {
+            copy_csr(s, it.R, L.R);
+        }
+        Level nxt;
+        CsrD AP;
+        csr_spgemm(c, L.A, L.P, AP);
+        csr_spgemm(c, L.R, AP, nxt.A);
+        h.L.push_back(std::move(nxt));
+    }
     read_bounds(c, h);
     coarse_inverse(c, h);
     hierarchy_fp32(c, h);
@@ -1218,15 +1306,14 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
         c->rho_cls = c->rho_lrn = -1.0;
     }
     if (!learned) {
-        build_hierarchy(&B, c->H[k], vals, nullptr, own);
+        build_hierarchy(&B, c->H[k], vals, own);
         return;
     }
     const bool judge = (c->opt.t_interp == CPTR_INTERP_LEARNED);
     // the learned hierarchy (and its convergence factor) on its own stream
-    // and host thread, concurrently with the classical one; it starts from
-    // the classical build's fine level once that level's C/F split and
-    // classical interpolation are formed (the learned correction changes
-    // only the fine level's weights)
+    // and host thread, level by level behind the classical build, whose C/F
+    // splits and transfer operators it keeps below the fine level (the
+    // learned correction changes only the fine level's weights)
     Hierarchy hl;
     double rl = -1.0;
     std::exception_ptr err;
@@ -1239,14 +1326,8 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     B2.nnzb = B.nnzb;
     B2.rp.p = B.rp.p;
     B2.ci.p = B.ci.p;
-    Level0Fork fork;
-    CPTR_HIP(hipEventCreateWithFlags(&fork.ev, hipEventDisableTiming));
-    struct EvGuard {
-        hipEvent_t e;
-        ~EvGuard() { if (e) (void)hipEventDestroy(e); }
-    } evg{fork.ev};
-    std::future<bool> published = fork.ready.get_future();
-    std::thread t2([c, &B2, &hl, &rl, &err, &fork, &published, judge]() {
+    LevelFeed feed;
+    std::thread t2([c, &B2, &hl, &rl, &err, &feed, judge]() {
         try {
             CPTR_HIP(hipSetDevice(c->device));
             StreamScope scope(B2.stream);
@@ -1254,10 +1335,7 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
                 B2.flag.alloc(4);
                 fill_int(B2.flag.p, 0, 1, B2.stream);
             }
-            if (!published.get()) return;      // no fine-level interpolation: nothing to learn
-            CPTR_HIP(hipStreamWaitEvent(B2.stream, fork.ev, 0));
-            level0_from_fork(&B2, hl, fork.sh);
-            build_hierarchy(&B2, hl, nullptr, c->mlp.p, nullptr, nullptr, true);
+            build_learned_hierarchy(&B2, hl, c->mlp.p, feed);
             if (judge && hl.L.size() > 1) rl = conv_factor(c, hl, RHO_CYCLES, RHO_SEED, B2.stream);
         } catch (...) {
             err = std::current_exception();
@@ -1266,11 +1344,11 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     std::exception_ptr err1;
     double rc = -1.0;
     try {
-        build_hierarchy(&B, c->H[k], vals, nullptr, own, &fork);
+        build_hierarchy(&B, c->H[k], vals, own, &feed);
         if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
     } catch (...) {
         err1 = std::current_exception();
-        fork.resolve(false);
+        feed.close();
     }
     t2.join();
     if (err1) std::rethrow_exception(err1);

@@ -106,12 +106,6 @@ __device__ void forward_tile(int lane, const Weights &W, WaveBuf &B) {
     __syncthreads();
 }
 
-__device__ inline float output_of(int i, const Weights &W, const WaveBuf &B) {
-    float o = 0.f;
-    for (int j = 0; j < MLP_NH; ++j) o += B.h2[i * MLP_NH + j] * W.w3[j];
-    return o + W.b3;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -228,26 +222,101 @@ __global__ void k_edge_features(int nf, const int *__restrict__ frows, const int
 // ---------------------------------------------------------------------------
 // inference: o_e for every edge
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(THREADS) k_mlp_forward(int E, const float *__restrict__ X,
-                                                         const float *__restrict__ params, float *__restrict__ o) {
-    __shared__ Weights W;
-    __shared__ WaveBuf Bw[WAVES];
-    load_weights(params, W);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WaveBuf &B = Bw[wave];
-    const long ntiles = ((long)E + TILE - 1) / TILE;
-    const long groups = (ntiles + WAVES - 1) / WAVES;
+// The layers are computed transposed, H_l^T = W_l H_{l-1}^T: hidden units are
+// the MFMA rows, the tile's 32 edges the columns.  The accumulator of a
+// 32 x 32 block then holds, in lane l, edge l % 32 and the rows
+// 8 g + 4 (l / 32) + q (g, q = 0..3) -- exactly the B operand (k = 4 (l / 32)
+// + q of K-step g) that the next layer's product over those rows takes, so
+// the first hidden layer goes from one product to the next in registers.
+// W1 and W2 stay in registers as A operands for the whole launch (row
+// 32 m + l % 32, k = 8 s + 4 (l / 32) + q of K-step s); biases and W3 come
+// from LDS (every half-wavefront reads one address).  One wavefront per tile
+// at a time, tiles strided over the grid, the next tile's features loaded
+// while the current one computes.
+constexpr int FWD_WAVES = 4;
+constexpr int FWD_MAX_BLOCKS = 512;
+
+__global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_forward(int E, const float *__restrict__ X,
+                                                                const float *__restrict__ params,
+                                                                float *__restrict__ o) {
+    __shared__ float b1s[MLP_NH], b2s[MLP_NH], w3s[MLP_NH];
+    __shared__ float b3s;
+    for (int k = threadIdx.x; k < MLP_NH; k += blockDim.x) {
+        b1s[k] = params[OB1 + k];
+        b2s[k] = params[OB2 + k];
+        w3s[k] = bf2f(f2bf(params[OW3 + k]));
+    }
+    if (threadIdx.x == 0) b3s = params[OB3];
+    const int lane = threadIdx.x & 63, lr = lane & 31, lk = 4 * (lane >> 5);
+    bf16x4 a1[2][MLP_NF / 8], a2[2][MLP_NH / 8];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+#pragma unroll
+        for (int ks = 0; ks < MLP_NF / 8; ++ks)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                a1[m][ks][q] = (short)f2bf(params[OW1 + (m * 32 + lr) * MLP_NF + ks * 8 + lk + q]);
+#pragma unroll
+        for (int ks = 0; ks < MLP_NH / 8; ++ks)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                a2[m][ks][q] = (short)f2bf(params[OW2 + (m * 32 + lr) * MLP_NH + ks * 8 + lk + q]);
+    }
     __syncthreads();
-    for (long g = blockIdx.x; g < groups; g += gridDim.x) {     // uniform over the block
-        const long t = g * WAVES + wave;
-        load_tile(lane, t, E, X, B);
-        __syncthreads();
-        forward_tile(lane, W, B);
-        if (lane < TILE) {
-            const long e = t * TILE + lane;
-            if (e < E) o[e] = output_of(lane, W, B);
+    const long ntiles = ((long)E + TILE - 1) / TILE;
+    const long stride = (long)gridDim.x * FWD_WAVES;
+    long t = (long)blockIdx.x * FWD_WAVES + (threadIdx.x >> 6);
+    // this lane's features of edge t * 32 + lr: [lk, lk + 4) and [8 + lk, 12 + lk)
+    // (edges past the last one read as zeros)
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    long e = t * TILE + lr;
+    float4 u = (e < E) ? reinterpret_cast<const float4 *>(X + e * MLP_NF)[lk / 4] : zero4;
+    float4 v = (e < E) ? reinterpret_cast<const float4 *>(X + e * MLP_NF)[2 + lk / 4] : zero4;
+    for (; t < ntiles; t += stride) {
+        bf16x4 bx[2];
+        bx[0][0] = (short)f2bf(u.x); bx[0][1] = (short)f2bf(u.y); bx[0][2] = (short)f2bf(u.z); bx[0][3] = (short)f2bf(u.w);
+        bx[1][0] = (short)f2bf(v.x); bx[1][1] = (short)f2bf(v.y); bx[1][2] = (short)f2bf(v.z); bx[1][3] = (short)f2bf(v.w);
+        const long en = (t + stride) * TILE + lr;       // the next tile's edge
+        u = (en < E) ? reinterpret_cast<const float4 *>(X + en * MLP_NF)[lk / 4] : zero4;
+        v = (en < E) ? reinterpret_cast<const float4 *>(X + en * MLP_NF)[2 + lk / 4] : zero4;
+        // layer 1: H1^T (64 x 32) = W1 (64 x 16) X^T (16 x 32)
+        f32x16 z1[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            z1[m] = f32x16{};
+#pragma unroll
+            for (int ks = 0; ks < MLP_NF / 8; ++ks)
+                z1[m] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[m][ks], bx[ks], z1[m], 0, 0, 0);
         }
-        __syncthreads();
+        // h1 = BF16(ReLU(z1 + b1)) as the B operands of layer 2's K-steps
+        bf16x4 hb[MLP_NH / 8];
+#pragma unroll
+        for (int ks = 0; ks < MLP_NH / 8; ++ks)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = ks / 4, r = 4 * (ks % 4) + q;
+                const float z = z1[m][r] + b1s[m * 32 + 8 * (ks % 4) + lk + q];
+                hb[ks][q] = (short)f2bf(z > 0.f ? z : 0.f);
+            }
+        // layer 2: H2^T (64 x 32) = W2 (64 x 64) H1^T (64 x 32); output
+        // o = W3 h2 + b3 (this lane's 32 rows, then the other half's)
+        float part = 0.f;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            f32x16 z2 = {};
+#pragma unroll
+            for (int ks = 0; ks < MLP_NH / 8; ++ks)
+                z2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[m][ks], hb[ks], z2, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = m * 32 + 8 * (r >> 2) + lk + (r & 3);
+                const float z = z2[r] + b2s[j];
+                part += (z > 0.f ? z : 0.f) * w3s[j];
+            }
+        }
+        const float tot = part + __shfl_xor(part, 32, 64);
+        e = t * TILE + lr;
+        if (lk == 0 && e < E) o[e] = tot + b3s;
     }
 }
 
@@ -275,20 +344,34 @@ __device__ inline bool row_weights(int m, const double *w0, const double *delta,
     return false;
 }
 
+// per F row (one thread): the row's sums in a first pass over its edges, the
+// weights in a second (the same expressions, in the same order, as the
+// row_weights helper; pv_out may be pv)
 __global__ void k_learned_weights(int nf, const int *__restrict__ frows, const int *__restrict__ estart,
-                                  const int *__restrict__ prp, const double *__restrict__ pv,
-                                  const float *__restrict__ o, double *__restrict__ pv_out) {
+                                  const int *__restrict__ prp, const double *pv, const float *__restrict__ o,
+                                  double *pv_out) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nf) return;
-    const int i = frows[q], plo = prp[i];
-    const int m = estart[q + 1] - estart[q];
-    double w0[MAX_ROW_EDGES], d[MAX_ROW_EDGES], w[MAX_ROW_EDGES], S, D;
+    const int i = frows[q], plo = prp[i], e0 = estart[q];
+    const int m = estart[q + 1] - e0;
+    double S = 0.0, D = 0.0;
     for (int k = 0; k < m; ++k) {
-        w0[k] = pv[plo + k];
-        d[k] = 0.5 * tanh((double)o[estart[q] + k]);
+        const double w0 = pv[plo + k];
+        const double w = w0 * (1.0 + 0.5 * tanh((double)o[e0 + k]));
+        S += w0;
+        D += w;
     }
-    row_weights(m, w0, d, w, S, D);
-    for (int k = 0; k < m; ++k) pv_out[plo + k] = w[k];
+    bool scale = false;
+    if (D != 0.0) {
+        const double c = S / D;
+        scale = (c >= 0.25 && c <= 4.0);
+    }
+    for (int k = 0; k < m; ++k) {
+        const double w0 = pv[plo + k];
+        double w = w0 * (1.0 + 0.5 * tanh((double)o[e0 + k]));
+        if (scale) w = w * S / D;
+        pv_out[plo + k] = w;
+    }
 }
 
 // per F row: loss term and dL/do of its edges (E: K vectors of length n)
@@ -508,7 +591,9 @@ int ln_mlp_waves(int E) { return mlp_grid(E) * WAVES; }
 
 void ln_mlp_forward(int E, const float *X, const float *params, float *o, hipStream_t s) {
     if (E == 0) return;
-    hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_grid(E)), dim3(THREADS), 0, s, E, X, params, o);
+    const long tiles = ((long)E + TILE - 1) / TILE;
+    const int grid = (int)std::max(1L, std::min((tiles + FWD_WAVES - 1) / FWD_WAVES, (long)FWD_MAX_BLOCKS));
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(64 * FWD_WAVES), 0, s, E, X, params, o);
     CPTR_CHECK_LAUNCH();
 }
 

@@ -127,6 +127,40 @@ def test_learned_row_sums_equal_the_classical_ones():
         assert Pl.v[a:b].sum() == pytest.approx(P.v[a:b].sum(), rel=1e-12)
 
 
+def test_learned_hierarchy_keeps_the_classical_coarse_structure():
+    """The learned hierarchy differs from the classical one only in the fine
+    level's interpolation weights: same levels, the classical C/F split and
+    pattern of P_0 with other values and R_0 = P_0^T, the classical C/F splits
+    and transfer operators below, and every coarse operator the Galerkin
+    product of its own finer level (checked with dense products)."""
+    s = tiny(40, 28, 4, peclet=5.0, seed=3)
+    A = O.decouple(O.bsr_of(s), s.rhs).Abar.scalar_block(1, 1)
+    h = O.amg_setup(A, O.AMGOptions(max_coarse=30))
+    assert len(h.levels) >= 3
+    p = L.unpack(mlp_init(1).astype(np.float64))
+    p["W3"] *= 100.0
+    hl = L.learned_hierarchy(L.pack(p), h)
+    assert len(hl.levels) == len(h.levels)
+    a, b = hl.levels[0], h.levels[0]
+    assert a.A is b.A and np.array_equal(a.cf, b.cf)
+    assert np.array_equal(a.P.rp, b.P.rp) and np.array_equal(a.P.ci, b.P.ci)
+    assert np.max(np.abs(a.P.v - b.P.v)) > 1e-3          # the weights did change
+    assert np.array_equal(a.R.to_dense(), a.P.to_dense().T)
+    for a, b in zip(hl.levels[1:-1], h.levels[1:-1]):
+        assert a.P is b.P and a.R is b.R and np.array_equal(a.cf, b.cf)
+    for l in range(len(hl.levels) - 1):
+        Lf, Lc = hl.levels[l], hl.levels[l + 1]
+        ref = Lf.R.to_dense() @ Lf.A.to_dense() @ Lf.P.to_dense()
+        got = Lc.A.to_dense()
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # a zero correction gives the classical hierarchy, value for value
+    p["W3"][:] = 0.0
+    p["b3"][:] = 0.0
+    h0 = L.learned_hierarchy(L.pack(p), h)
+    for a, b in zip(h0.levels, h.levels):
+        assert np.array_equal(a.A.v, b.A.v) and np.array_equal(a.A.ci, b.A.ci)
+
+
 def test_gradient_against_finite_differences():
     A, st, cf, P, e = _setup(seed=4, nx=12, ny=10)
     E = L.smooth_vectors(A, K=4, seed=2)
@@ -189,7 +223,9 @@ def test_judge_on_every_full_build():
     classical one: rho_learned < rho_classical when the learned weights are
     used.  The chosen hierarchy equals an explicit learned or classical
     setup.  A refreshed hierarchy kept by the reuse test is not rebuilt and
-    not judged again."""
+    not judged again.  The learned hierarchy is the classical one with the
+    learned fine-level weights (its coarser levels keep the classical splits
+    and transfer operators)."""
     from synthetic import generator as G
     perm = G.config5_field(48, 24)
     systems = [G.config5(k, perm, nx=48, ny=24) for k in range(4)]
@@ -215,7 +251,9 @@ def test_judge_on_every_full_build():
                 assert rl < rc
             chosen.append(r.learned["used"])
             A = r.dec.Abar.scalar_block(1, 1)
-            h = O.amg_setup(A, opts(1e-9).amg, L.learned_interp(params) if r.learned["used"] else None)
+            h = O.amg_setup(A, opts(1e-9).amg)
+            if r.learned["used"]:
+                h = L.learned_hierarchy(params, h)
             got = r.hierarchies["T"]
             assert len(got.levels) == len(h.levels)
             for a, b in zip(got.levels[:-1], h.levels[:-1]):
