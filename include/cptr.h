@@ -83,9 +83,14 @@ enum { CPTR_SMOOTH_JACOBI = 0, CPTR_SMOOTH_L1JACOBI = 1, CPTR_SMOOTH_CHEBYSHEV =
  * convergence factor, or the learned correction without the judge.  The
  * judge runs at every full build of the temperature hierarchy (cptr_setup,
  * and every rebuild by cptr_update_values): both hierarchies are built and
- * the learned one is kept only when its convergence factor is lower.  A
- * hierarchy kept by the reuse test of cptr_update_values keeps its
- * interpolation and is not judged (rho_T_classical / rho_T_learned read -1) */
+ * the learned one is kept only when its convergence factor is lower.  The
+ * learned hierarchy differs from the classical one only in the fine level's
+ * interpolation weights (below it: the classical C/F splits and transfer
+ * operators, its own Galerkin products).  A hierarchy kept by the reuse test
+ * of cptr_update_values keeps its interpolation and is not judged
+ * (rho_T_classical / rho_T_learned read -1).  The judge and the reuse test
+ * measure the V-cycle in the preconditioner's precision (the FP32 V-cycle
+ * with precond_precision CPTR_FP32). */
 enum { CPTR_INTERP_CLASSICAL = 0, CPTR_INTERP_LEARNED = 1, CPTR_INTERP_LEARNED_FORCED = 2 };
 
 typedef struct {
@@ -364,7 +369,10 @@ cptr_status cptr_amg_vcycle(cptr_ctx *ctx, int32_t which, const double *d_b, dou
  * vector e_0[i] = u(seed, i) in [-1, 1), where u maps SplitMix64 of (seed, i)
  * to its top 53 bits scaled to [0, 1) then to 2 u - 1, iterate
  * e <- e - V(A e) `cycles` times (FP64) and return
- * rho = (|e_K|_2 / |e_0|_2)^(1/K) in *rho (host). */
+ * rho = (|e_K|_2 / |e_0|_2)^(1/K) in *rho (host).  (With the FP32
+ * preconditioner the reuse test and the judge apply the FP32 V-cycle: A e in
+ * FP64 rounded to FP32 as its input, its output subtracted in FP64; this call
+ * always measures the FP64 V-cycle.) */
 cptr_status cptr_amg_conv_factor(cptr_ctx *ctx, int32_t which, int32_t cycles, uint64_t seed, double *rho);
 
 /* One application of the multi-stage preconditioner: d_y = M^{-1} d_r. */

@@ -1237,8 +1237,12 @@ static void precond(cptr_ctx *c, const double *r, double *y) {
 
 // Asymptotic V-cycle convergence factor of a hierarchy on A e = 0:
 // e <- e - V(A e) from a SplitMix64-uniform start in [-1, 1), K cycles,
-// rho = (|e_K| / |e_0|)^(1/K).  FP64 V-cycles on stream s.
-static double conv_factor(cptr_ctx *c, Hierarchy &h, int cycles, uint64_t seed, hipStream_t s) {
+// rho = (|e_K| / |e_0|)^(1/K), on stream s.  V-cycles in FP64, or with fp32
+// the FP32 V-cycle the precision-split preconditioner applies (e and A e in
+// FP64, A e rounded to FP32 as the V-cycle's input, its output subtracted in
+// FP64).
+static double conv_factor(cptr_ctx *c, Hierarchy &h, int cycles, uint64_t seed, hipStream_t s,
+                          bool fp32 = false) {
     Level &L0 = h.L[0];
     const int n = L0.A.n;
     DBuf<double> e, part, nrm;
@@ -1250,9 +1254,15 @@ static double conv_factor(cptr_ctx *c, Hierarchy &h, int cycles, uint64_t seed, 
     kr_norm2_partial(n, e.p, part.p, nblk, s);
     kr_reduce(part.p, nblk, 1, nrm.p, s);
     for (int k = 0; k < cycles; ++k) {
-        vc_spmv<double>(n, L0.A.nnz, L0.A.rp, L0.A.ci, L0.A.v.p, e.p, L0.b.p, s);
-        const double *x = vcycle<double>(c, h, 0, s);
-        vc_sub(n, x, e.p, s);
+        if (fp32) {
+            vc_spmv_to_float(n, L0.A.rp, L0.A.ci, L0.A.v.p, e.p, L0.b32.p, s);
+            const float *x = vcycle<float>(c, h, 0, s);
+            vc_sub_float(n, x, e.p, s);
+        } else {
+            vc_spmv<double>(n, L0.A.nnz, L0.A.rp, L0.A.ci, L0.A.v.p, e.p, L0.b.p, s);
+            const double *x = vcycle<double>(c, h, 0, s);
+            vc_sub(n, x, e.p, s);
+        }
     }
     kr_norm2_partial(n, e.p, part.p, nblk, s);
     kr_reduce(part.p, nblk, 1, nrm.p + 1, s);
@@ -1327,7 +1337,8 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     B2.rp.p = B.rp.p;
     B2.ci.p = B.ci.p;
     LevelFeed feed;
-    std::thread t2([c, &B2, &hl, &rl, &err, &feed, judge]() {
+    const bool fp32 = (c->opt.precond_precision == CPTR_FP32);
+    std::thread t2([c, &B2, &hl, &rl, &err, &feed, judge, fp32]() {
         try {
             CPTR_HIP(hipSetDevice(c->device));
             StreamScope scope(B2.stream);
@@ -1336,7 +1347,7 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
                 fill_int(B2.flag.p, 0, 1, B2.stream);
             }
             build_learned_hierarchy(&B2, hl, c->mlp.p, feed);
-            if (judge && hl.L.size() > 1) rl = conv_factor(c, hl, RHO_CYCLES, RHO_SEED, B2.stream);
+            if (judge && hl.L.size() > 1) rl = conv_factor(c, hl, RHO_CYCLES, RHO_SEED, B2.stream, fp32);
         } catch (...) {
             err = std::current_exception();
         }
@@ -1345,7 +1356,7 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     double rc = -1.0;
     try {
         build_hierarchy(&B, c->H[k], vals, own, &feed);
-        if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
+        if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream, fp32);
     } catch (...) {
         err1 = std::current_exception();
         feed.close();
@@ -1475,7 +1486,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
             B.aux = &A2;
         }
         c->tph[1 + k] = 0.0;
-        th[k] = std::thread([c, k, sys, &B, &svals, &err, &refresh, &kept, t_hier]() {
+        th[k] = std::thread([c, k, sys, fp32, &B, &svals, &err, &refresh, &kept, t_hier]() {
             try {
                 CPTR_HIP(hipSetDevice(c->device));
                 StreamScope scope(B.stream);
@@ -1491,7 +1502,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                     // measured V-cycle convergence factor stays below the
                     // threshold, else build it anew
                     refresh_hierarchy(&B, c->H[k], svals[k], own);
-                    c->rho[k] = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream);
+                    c->rho[k] = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream, fp32);
                     if (c->rho[k] < c->opt.reuse_rho_max) {
                         kept.fetch_or(1 << k);
                         c->backoff[k] = 1;

@@ -256,6 +256,9 @@ void ms_gather_comp(int nnzb, int b, const double *slab, int comp, double *out, 
 
 void vc_hash_uniform(int n, uint64_t seed, double *e, hipStream_t st);
 void vc_sub(int n, const double *x, double *e, hipStream_t st);
+void vc_spmv_to_float(int n, const int *rp, const int *ci, const double *v, const double *x, float *y,
+                      hipStream_t st);
+void vc_sub_float(int n, const float *x, double *e, hipStream_t st);
 
 // k_learned.hip: edge-MLP correction of the fine-level temperature interpolation
 constexpr int MLP_NF = 16, MLP_NH = 64;

@@ -370,6 +370,35 @@ void vc_sub(int n, const double *x, double *e, hipStream_t st) {
     CPTR_CHECK_LAUNCH();
 }
 
+// the convergence-factor measurement of an FP32 V-cycle: y = A x in FP64,
+// rounded to FP32 (the V-cycle's input), and e -= x with x from the V-cycle
+__global__ void k_spmv_to_float(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                const double *__restrict__ v, const double *__restrict__ x, float *__restrict__ y) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) acc += v[e] * x[ci[e]];
+    y[i] = (float)acc;
+}
+
+__global__ void k_sub_float(int n, const float *__restrict__ x, double *__restrict__ e) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) e[i] -= (double)x[i];
+}
+
+void vc_spmv_to_float(int n, const int *rp, const int *ci, const double *v, const double *x, float *y,
+                      hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_spmv_to_float, dim3(nblocks(n, 256)), dim3(256), 0, st, n, rp, ci, v, x, y);
+    CPTR_CHECK_LAUNCH();
+}
+
+void vc_sub_float(int n, const float *x, double *e, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_sub_float, dim3(nblocks(n, 256)), dim3(256), 0, st, n, x, e);
+    CPTR_CHECK_LAUNCH();
+}
+
 #define INST(T)                                                                                                   \
     template void vc_presmooth_residual<T>(int, int, const int *, const int *, const T *, const T *, T, const T *, \
                                            T *, T *, hipStream_t);                                               \

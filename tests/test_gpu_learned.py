@@ -204,3 +204,55 @@ def test_sequence_judged_at_every_build():
         assert r1["used_learned"] == r0["used_learned"]
     finally:
         solver.close()
+
+
+def test_fp32_judge_and_reuse_measure_the_fp32_vcycle():
+    """With the FP32 preconditioner the judge and the reuse test measure the
+    FP32 V-cycle the solver applies.  The hierarchies are the oracle's (built
+    in FP64), only the V-cycle's rounding differs, so the convergence factors
+    agree with the oracle's FP64 ones to 1e-4 relative (classical hierarchy,
+    reuse trial) and 2e-2 (learned, whose weights come from the BF16
+    network), and the decisions follow them."""
+    print("case learned judge and reuse trial with the FP32 V-cycle", flush=True)
+    from synthetic import generator as G
+    perm = G.config5_field(48, 24)
+    systems = [G.config5(k, perm, nx=48, ny=24) for k in range(3)]
+    p = _params(seed=1, scale=100.0)
+    opts = O.Options(color=O.tile_colors(48, 24), amg=O.AMGOptions(max_coarse=30), mlp_params=p.astype(np.float64),
+                     reuse_rho_max=1e-9)
+    refs, prev = [], None
+    for s in systems:
+        prev = O.solve(s, opts, previous=prev)
+        refs.append(prev)
+    solver = cptr.Solver(amg_max_coarse=30, t_interp=cptr.INTERP_LEARNED, reuse_rho_max=1e-9, krylov=cptr.FGMRES,
+                         precond_precision=cptr.FP32)
+    try:
+        solver.load_mlp(p)
+        s0 = systems[0]
+        solver.setup(torch.from_numpy(s0.row_ptr), torch.from_numpy(s0.col_idx),
+                     torch.from_numpy(s0.vals.reshape(-1)), 0, 1, s0.nx, s0.ny)
+        trials = 0
+        for k, (s, ref) in enumerate(zip(systems, refs)):
+            if k > 0:
+                solver.update_values(torch.from_numpy(s.vals.reshape(-1)))
+            x, res = solver.solve(_t(s.rhs))
+            rc, rl = ref.learned["rho_classical"], ref.learned["rho_learned"]
+            print(f"  system {k}: gpu rho_T {res['rho_T']:.8f} judge {res['rho_T_classical']:.8f} "
+                  f"{res['rho_T_learned']:.8f} used={res['used_learned']}; oracle rho {ref.rho} judge {rc:.8f} "
+                  f"{rl:.8f} used={ref.learned['used']}", flush=True)
+            assert res["converged"] == 1 and res["rel_res_scaled"] <= 1e-8
+            assert abs(res["rho_T_classical"] - rc) <= 1e-4 * rc
+            assert abs(res["rho_T_learned"] - rl) <= 2e-2 * rl
+            if res["used_learned"]:
+                assert res["rho_T_learned"] < res["rho_T_classical"]
+            if abs(rl - rc) > 0.05 * rc:
+                assert res["used_learned"] == int(ref.learned["used"])
+            if "T" in ref.rho:
+                trials += 1
+                assert abs(res["rho_T"] - ref.rho["T"]) <= 1e-4 * ref.rho["T"]
+                assert not (res["reused"] & 1)
+            else:
+                assert res["rho_T"] == -1.0
+        assert trials >= 1
+    finally:
+        solver.close()
