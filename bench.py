@@ -182,27 +182,35 @@ def front_end_bench(args, dev, n2: int = 4, reps: int = 5) -> dict:
 
 
 def solve_probe(args, dev) -> int:
-    """Two FP32-preconditioned setup+solve calls on the config-3 system (Pe
-    0.1) in the benchmark's configuration, then five device-to-device copies
-    of 1 GiB: the run that per-kernel HBM byte counters are read on (the
-    copies calibrate the counters).  Prints the hierarchy sizes that the
-    kernels' algorithmic bytes follow from."""
+    """Two FP32-preconditioned setup+solve calls in the benchmark's
+    configuration -- on the config-3 system (Pe 0.1), or with --workload c5 on
+    system 0 of the config-5 sequence (2000 x 1000, the headline's solver with
+    classical interpolation) -- then five device-to-device copies of 1 GiB:
+    the run that per-kernel HBM byte counters are read on (the copies
+    calibrate the counters).  Prints the hierarchy sizes that the kernels'
+    algorithmic bytes follow from."""
     import torch
     from paper_1912_04385_amd import cptr
-    from synthetic import config3
+    from synthetic import config3, config5, config5_field
 
-    s = config3(0, args.nx, args.ny)
+    if args.workload == "c5":
+        nx, ny = args.c5_grid
+        s = config5(0, config5_field(nx, ny), nx, ny)
+    else:
+        nx, ny = args.nx, args.ny
+        s = config3(0, nx, ny)
     rp = torch.from_numpy(s.row_ptr).to(dev)
     ci = torch.from_numpy(s.col_idx).to(dev)
     vals = torch.from_numpy(s.vals.reshape(-1)).to(dev)
     rhs = torch.from_numpy(s.rhs).to(dev)
-    meta = dict(n=s.n, nnzb=s.nnzb, b=s.b)
+    meta = dict(workload=args.workload, n=s.n, nnzb=s.nnzb, b=s.b)
     del s
     sol = cptr.Solver(krylov=cptr.FGMRES, restart=50, precond_precision=cptr.FP32, pre_sweeps=args.sweeps,
-                      post_sweeps=args.sweeps, ilu_tile_x=args.tile[0], ilu_tile_y=args.tile[1])
+                      post_sweeps=args.sweeps, ilu_tile_x=args.tile[0], ilu_tile_y=args.tile[1],
+                      stop_unscaled=1 if args.workload == "c5" else 0)
     its = []
     for _ in range(2):
-        sol.setup(rp, ci, vals, 0, 1, args.nx, args.ny)
+        sol.setup(rp, ci, vals, 0, 1, nx, ny)
         x, r = sol.solve(rhs)
         its.append(r["iterations"])
     torch.cuda.synchronize()
