@@ -424,6 +424,7 @@ static void coarse_inverse(Builder *c, Hierarchy &h) {
     amg_dense_inverse(nc, Lc.A.rp, Lc.A.ci, Lc.A.v.p, aug.p, used.p, piv.p, c->flag.p, h.cinv.p,
                       fp32 ? h.cinv32.p : nullptr, F.p, U.p, s);
     int f = read_flag_and_clear(c);
+    if (f & 256) throw Error(CPTR_E_STATE, "Galerkin product outside its kept pattern");
     if (f & 64) throw Error(CPTR_E_SINGULAR_BLOCK, "singular coarsest AMG operator");
     if (f & 32) throw Error(CPTR_E_SINGULAR_BLOCK, "zero diagonal in an AMG level");
 }
@@ -767,13 +768,15 @@ static void read_bounds(Builder *c, Hierarchy &h) {
 
 // The levels of a classical build handed to a second build that keeps its
 // C/F splits and transfer operators (the learned interpolation's judge).
-// The classical builder publishes level 0 once its C/F split and classical
-// interpolation are formed (with the fine operator, its smoother diagonal
-// and strength flags), and every coarser level once its interpolation and
-// restriction are formed, each with an event recorded on its stream; it
-// closes the feed when it stops forming interpolations (or fails).  The
-// published device buffers stay unchanged until the classical hierarchy is
-// destroyed, which the caller does only after the second build has ended.
+// The classical builder publishes the fine level once its C/F split and
+// classical interpolation are formed (with the fine operator, its smoother
+// diagonal and strength flags), and every level once its Galerkin product is
+// formed (its interpolation and restriction, and the patterns of A P and of
+// the next level's operator, which the second build's products share), each
+// with an event recorded on its stream; it closes the feed when it stops
+// forming interpolations (or fails).  The published device buffers stay
+// unchanged until the classical hierarchy is destroyed, which the caller
+// does only after the second build has ended.
 struct LevelFeed {
     struct Csr {
         int n = 0, ncols = 0, nnz = 0;
@@ -783,30 +786,39 @@ struct LevelFeed {
     struct Item {
         int n = 0, nc = 0;
         const int *cf = nullptr;
-        Csr P, R;                                   // R: coarser levels only
-        int annz = 0;                               // level 0: the operator
+        Csr P, R;
+        Csr AP, Anext;                              // patterns (values unused)
+        int annz = 0;                               // fine level: the operator
         const double *av = nullptr, *dinv = nullptr;
         const unsigned char *strong = nullptr;
         hipEvent_t ev = nullptr;
     };
     std::mutex mu;
     std::condition_variable cv;
+    Item fine;
+    bool fine_ready = false;
     std::vector<Item> items;
     bool closed = false;
     LevelFeed() = default;
     LevelFeed(const LevelFeed &) = delete;
     LevelFeed &operator=(const LevelFeed &) = delete;
     ~LevelFeed() {
+        if (fine.ev) (void)hipEventDestroy(fine.ev);
         for (auto &it : items)
             if (it.ev) (void)hipEventDestroy(it.ev);
     }
     static Csr view(const CsrD &a) { return {a.n, a.ncols, a.nnz, a.rp, a.ci, a.v.p}; }
-    void publish(Item it, hipStream_t s) {
+    void publish(Item it, hipStream_t s, bool is_fine) {
         CPTR_HIP(hipEventCreateWithFlags(&it.ev, hipEventDisableTiming));
         const hipError_t e = hipEventRecord(it.ev, s);
         {
             std::lock_guard<std::mutex> lk(mu);
-            items.push_back(it);      // (the destructor releases the event)
+            if (is_fine) {
+                fine = it;
+                fine_ready = true;
+            } else {
+                items.push_back(it);      // (the destructor releases the events)
+            }
         }
         cv.notify_all();
         if (e != hipSuccess) throw Error(CPTR_E_HIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
@@ -818,7 +830,15 @@ struct LevelFeed {
         }
         cv.notify_all();
     }
-    // level l of the classical build, or false once the feed closed without it
+    // the fine level, or false once the feed closed without it
+    bool wait_fine(Item &out) {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return fine_ready || closed; });
+        if (!fine_ready) return false;
+        out = fine;
+        return true;
+    }
+    // level l's products, or false once the feed closed without them
     bool wait(size_t l, Item &out) {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait(lk, [&] { return items.size() > l || closed; });
@@ -828,7 +848,7 @@ struct LevelFeed {
     }
 };
 
-static void copy_csr(hipStream_t s, const LevelFeed::Csr &a, CsrD &d) {
+static void copy_csr(hipStream_t s, const LevelFeed::Csr &a, CsrD &d, bool values = true) {
     d.n = a.n;
     d.ncols = a.ncols;
     d.nnz = a.nnz;
@@ -838,10 +858,22 @@ static void copy_csr(hipStream_t s, const LevelFeed::Csr &a, CsrD &d) {
     CPTR_HIP(hipMemcpyAsync(d.rp_own.p, a.rp, sizeof(int) * (a.n + 1), hipMemcpyDeviceToDevice, s));
     if (a.nnz) {
         CPTR_HIP(hipMemcpyAsync(d.ci_own.p, a.ci, sizeof(int) * a.nnz, hipMemcpyDeviceToDevice, s));
-        CPTR_HIP(hipMemcpyAsync(d.v.p, a.v, sizeof(double) * a.nnz, hipMemcpyDeviceToDevice, s));
+        if (values) CPTR_HIP(hipMemcpyAsync(d.v.p, a.v, sizeof(double) * a.nnz, hipMemcpyDeviceToDevice, s));
     }
     d.rp = d.rp_own.p;
     d.ci = d.ci_own.p;
+}
+
+// the next level's operator A_{l+1} = R (A P) of level L on kept patterns:
+// A P (L.ap_*) into scratch, then R (A P) into N.A's values
+static void galerkin_numeric(Builder *c, Level &L, Level &N) {
+    hipStream_t s = c->stream;
+    DBuf<double> apv;
+    apv.alloc((size_t)L.ap_nnz + 1);
+    amg_spgemm_numeric(L.A.n, L.A.rp, L.A.ci, L.A.v.p, L.P.rp, L.P.ci, L.P.v.p, L.ap_rp.p, L.ap_ci.p, apv.p,
+                       c->flag.p, s);
+    amg_spgemm_numeric(L.R.n, L.R.rp, L.R.ci, L.R.v.p, L.ap_rp.p, L.ap_ci.p, apv.p, N.A.rp, N.A.ci, N.A.v.p,
+                       c->flag.p, s);
 }
 
 // `own` (optional): the buffer holding vals, taken over as the fine level's
@@ -901,8 +933,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
         const int capAP = rd[1], maxAP = rd[2];
         compact_interp(c, is, P);
         L.nc = nc;
-        const bool fine = h.L.size() == 1;
-        if (feed && fine) {
+        if (feed && h.L.size() == 1) {
             LevelFeed::Item it;
             it.n = m;
             it.nc = nc;
@@ -912,18 +943,9 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
             it.av = L.A.v.p;
             it.dinv = L.dinv.p;
             it.strong = L.strong.p;
-            feed->publish(it, s);
+            feed->publish(it, s, true);
         }
         csr_transpose(c, P, L.R);
-        if (feed && !fine) {
-            LevelFeed::Item it;
-            it.n = m;
-            it.nc = nc;
-            it.cf = L.cf.p;
-            it.P = LevelFeed::view(P);
-            it.R = LevelFeed::view(L.R);
-            feed->publish(it, s);
-        }
         CsrD AP;
         spgemm_compute(c, L.A, P, pAP, capAP, maxAP, AP);
         // R (A P) needs only A P's row pointers for its plan
@@ -934,6 +956,21 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
         Level nxt;
         spgemm_compute(c, L.R, AP, pRAP, rd[1], rd[2], nxt.A);
         spgemm_finish(c, pRAP, read_scalar(nxt.A.rp_own.p + nc, s), nxt.A);
+        // A P's pattern, for refreshing this product on new values
+        L.ap_rp = std::move(AP.rp_own);
+        L.ap_ci = std::move(AP.ci_own);
+        L.ap_nnz = AP.nnz;
+        if (feed) {
+            LevelFeed::Item it;
+            it.n = m;
+            it.nc = nc;
+            it.cf = L.cf.p;
+            it.P = LevelFeed::view(P);
+            it.R = LevelFeed::view(L.R);
+            it.AP = {m, nc, L.ap_nnz, L.ap_rp.p, L.ap_ci.p, nullptr};
+            it.Anext = {nxt.A.n, nxt.A.ncols, nxt.A.nnz, nxt.A.rp, nxt.A.ci, nullptr};
+            feed->publish(it, s, false);
+        }
         h.L.push_back(std::move(nxt));
     }
     if (feed) feed->close();
@@ -949,16 +986,18 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
 // pattern, the learned weights and R_0 = P_0^T; below it the classical
 // build's C/F splits and transfer operators (copied as each level is
 // published), with every Galerkin product A_{l+1} = R_l A_l P_l formed from
-// this hierarchy's own finer level, then its smoother diagonals, bounds and
-// coarsest inverse.  It runs on c's stream, level by level behind the
-// classical build.  Empty when the classical build forms no interpolation.
+// this hierarchy's own finer level on the classical product's pattern (the
+// patterns depend only on the operands' patterns, which are the classical
+// ones), then its smoother diagonals, bounds and coarsest inverse.  It runs
+// on c's stream, level by level behind the classical build.  Empty when the
+// classical build forms no interpolation.
 static void build_learned_hierarchy(Builder *c, Hierarchy &h, const float *mlp, LevelFeed &feed) {
     hipStream_t s = c->stream;
     const cptr_options &o = c->opt;
     const bool fp32 = (o.precond_precision == CPTR_FP32);
     h.L.clear();
     LevelFeed::Item it;
-    if (!feed.wait(0, it)) return;
+    if (!feed.wait_fine(it)) return;
     CPTR_HIP(hipStreamWaitEvent(s, it.ev, 0));
     h.L.emplace_back();
     {
@@ -973,38 +1012,45 @@ static void build_learned_hierarchy(Builder *c, Hierarchy &h, const float *mlp, 
         CPTR_HIP(hipMemcpyAsync(L0.dinv.p, it.dinv, sizeof(double) * it.n, hipMemcpyDeviceToDevice, s));
         L0.strong.alloc((size_t)it.annz + 1);
         CPTR_HIP(hipMemcpyAsync(L0.strong.p, it.strong, (size_t)it.annz, hipMemcpyDeviceToDevice, s));
+        L0.nc = it.nc;
+        L0.cf.alloc((size_t)it.n + 1);
+        CPTR_HIP(hipMemcpyAsync(L0.cf.p, it.cf, sizeof(int) * it.n, hipMemcpyDeviceToDevice, s));
+        copy_csr(s, it.P, L0.P);
+        level_bound(c, h, 0);
+        level_vectors(L0, it.n, fp32);
+        apply_learned(s, L0, mlp);
+        csr_transpose(c, L0.P, L0.R);
     }
     for (size_t l = 0;; ++l) {
+        // the classical level l's products, or none (then this level is the
+        // coarsest, as it is there)
+        if (!feed.wait(l, it)) break;
+        CPTR_HIP(hipStreamWaitEvent(s, it.ev, 0));
         Level &L = h.L[l];
-        const int m = L.A.n;
         if (l > 0) {
-            L.dinv.alloc(m);
-            c->s_d1.alloc(m);
-            amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
-        }
-        level_bound(c, h, (int)l);
-        level_vectors(L, m, fp32);
-        if (l > 0) {
-            // the classical level l: its split and transfer operators, or none
-            // (then this level is the coarsest, as it is there)
-            if (!feed.wait(l, it)) break;
-            CPTR_HIP(hipStreamWaitEvent(s, it.ev, 0));
-        }
-        L.nc = it.nc;
-        L.cf.alloc((size_t)m + 1);
-        CPTR_HIP(hipMemcpyAsync(L.cf.p, it.cf, sizeof(int) * m, hipMemcpyDeviceToDevice, s));
-        copy_csr(s, it.P, L.P);
-        if (l == 0) {
-            apply_learned(s, L, mlp);
-            csr_transpose(c, L.P, L.R);
-        } else {
+            L.nc = it.nc;
+            L.cf.alloc((size_t)L.A.n + 1);
+            CPTR_HIP(hipMemcpyAsync(L.cf.p, it.cf, sizeof(int) * L.A.n, hipMemcpyDeviceToDevice, s));
+            copy_csr(s, it.P, L.P);
             copy_csr(s, it.R, L.R);
         }
+        L.ap_nnz = it.AP.nnz;
+        L.ap_rp.alloc((size_t)it.AP.n + 1);
+        L.ap_ci.alloc((size_t)it.AP.nnz + 1);
+        CPTR_HIP(hipMemcpyAsync(L.ap_rp.p, it.AP.rp, sizeof(int) * (it.AP.n + 1), hipMemcpyDeviceToDevice, s));
+        if (it.AP.nnz)
+            CPTR_HIP(hipMemcpyAsync(L.ap_ci.p, it.AP.ci, sizeof(int) * it.AP.nnz, hipMemcpyDeviceToDevice, s));
         Level nxt;
-        CsrD AP;
-        csr_spgemm(c, L.A, L.P, AP);
-        csr_spgemm(c, L.R, AP, nxt.A);
+        copy_csr(s, it.Anext, nxt.A, false);
+        galerkin_numeric(c, L, nxt);
         h.L.push_back(std::move(nxt));
+        Level &N = h.L.back();
+        const int m = N.A.n;
+        N.dinv.alloc(m);
+        c->s_d1.alloc(m);
+        amg_diag_inv2(m, N.A.rp, N.A.ci, N.A.v.p, o.smoother, N.dinv.p, c->s_d1.p, c->flag.p, s);
+        level_bound(c, h, (int)l + 1);
+        level_vectors(N, m, fp32);
     }
     read_bounds(c, h);
     coarse_inverse(c, h);
@@ -1034,10 +1080,15 @@ static void refresh_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf
         amg_diag_inv2(m, L.A.rp, L.A.ci, L.A.v.p, o.smoother, L.dinv.p, c->s_d1.p, c->flag.p, s);
         level_bound(c, h, (int)l);
         if (l + 1 == h.L.size()) break;
-        CsrD AP, Ac;
-        csr_spgemm(c, L.A, L.P, AP);
-        csr_spgemm(c, L.R, AP, Ac);
-        h.L[l + 1].A = std::move(Ac);
+        if (L.ap_nnz >= 0) {
+            // the products on their kept patterns
+            galerkin_numeric(c, L, h.L[l + 1]);
+        } else {
+            CsrD AP, Ac;
+            csr_spgemm(c, L.A, L.P, AP);
+            csr_spgemm(c, L.R, AP, Ac);
+            h.L[l + 1].A = std::move(Ac);
+        }
     }
     read_bounds(c, h);
     coarse_inverse(c, h);

@@ -101,6 +101,10 @@ struct CsrD {
 
 struct Level {
     CsrD A;
+    // pattern of the product A P formed on the way to the next level's A
+    // (kept for refreshing the Galerkin product on new values)
+    DBuf<int> ap_rp, ap_ci;
+    int ap_nnz = -1;        // -1: not kept
     DBuf<double> dinv;      // 1 / smoothing diagonal
     DBuf<float> dinv32;
     DBuf<int> cf;           // 1 = C, 0 = F (not on the coarsest level)
@@ -202,6 +206,9 @@ void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int
 void amg_spgemm_compute_sort(int m, int ncols, int maxprod, const int *arp, const int *aci, const double *av,
                              const int *brp, const int *bci, const double *bv, const int *off, int *tcol,
                              double *tval, int *cnt, hipStream_t st);
+// C = A B on C's known pattern (crp, cci); flag bit 256: a product outside it
+void amg_spgemm_numeric(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
+                        const double *bv, const int *crp, const int *cci, double *cv, int *flag, hipStream_t st);
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
                         const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
 // rows and columns [o, o + m) of a CSR matrix with sorted rows: entry counts,

@@ -1357,6 +1357,74 @@ void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av,
 }
 
 // --------------------------------------------------------------------------
+// SpGEMM C = A B on a known pattern of C (a refreshed Galerkin product, or
+// the learned hierarchy's, whose patterns are the classical one's): one
+// thread per row of C takes the products of its row in A's row order --
+// entry e of A's row, then B's row aci[e] in order -- finds each product's
+// column in C's row by bisection and adds the product to that entry.  Every
+// entry therefore sums its terms in the order of the sequential
+// accumulation, starting from the first term (0 + t = t), bit for bit the
+// values of the symbolic kernels.  Rows of at most SPN_CAP entries keep
+// their columns and sums in LDS (interleaved across the block's threads);
+// longer rows work on C's own arrays.  A product whose column is not in C's
+// row sets flag bit 256 (a pattern that does not belong to these operands).
+// --------------------------------------------------------------------------
+constexpr int SPN_T = 64;
+constexpr int SPN_CAP = 64;
+
+__device__ inline int spn_find(const int *cols, int stride, int len, int j) {
+    int lo = 0, hi = len - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cols[mid * stride] < j) lo = mid + 1; else hi = mid;
+    }
+    return (len > 0 && cols[lo * stride] == j) ? lo : -1;
+}
+
+__global__ void __launch_bounds__(SPN_T) k_spgemm_numeric(int m, const int *__restrict__ arp,
+                                                          const int *__restrict__ aci, const double *__restrict__ av,
+                                                          const int *__restrict__ brp, const int *__restrict__ bci,
+                                                          const double *__restrict__ bv, const int *__restrict__ crp,
+                                                          const int *__restrict__ cci, double *__restrict__ cv,
+                                                          int *flag) {
+    __shared__ int scol[SPN_CAP * SPN_T];
+    __shared__ double sacc[SPN_CAP * SPN_T];
+    const int i = blockIdx.x * SPN_T + threadIdx.x;
+    if (i >= m) return;
+    const int c0 = crp[i], len = crp[i + 1] - c0;
+    const bool lds = len <= SPN_CAP;
+    const int *cols = lds ? scol + threadIdx.x : cci + c0;
+    double *acc = lds ? sacc + threadIdx.x : cv + c0;
+    const int stride = lds ? SPN_T : 1;
+    for (int q = 0; q < len; ++q) {
+        if (lds) scol[q * SPN_T + threadIdx.x] = cci[c0 + q];
+        acc[q * stride] = 0.0;
+    }
+    bool bad = false;
+    for (int e = arp[i]; e < arp[i + 1]; ++e) {
+        const int k = aci[e];
+        const double a = av[e];
+        for (int f = brp[k]; f < brp[k + 1]; ++f) {
+            const double t = a * bv[f];
+            const int q = spn_find(cols, stride, len, bci[f]);
+            if (q < 0) { bad = true; continue; }
+            acc[q * stride] = acc[q * stride] + t;
+        }
+    }
+    if (lds)
+        for (int q = 0; q < len; ++q) cv[c0 + q] = sacc[q * SPN_T + threadIdx.x];
+    if (bad) atomicOr(flag, 256);
+}
+
+void amg_spgemm_numeric(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
+                        const double *bv, const int *crp, const int *cci, double *cv, int *flag, hipStream_t st) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_spgemm_numeric, dim3(blocks_for(m, SPN_T)), dim3(SPN_T), 0, st, m, arp, aci, av, brp, bci,
+                       bv, crp, cci, cv, flag);
+    CPTR_CHECK_LAUNCH();
+}
+
+// --------------------------------------------------------------------------
 // smoother diagonal and the coarsest level
 // --------------------------------------------------------------------------
 // dinv = 1 / a_ii (Jacobi) or 1 / (a_ii + sign(a_ii) sum_{j!=i} |a_ij|) (l1-Jacobi);
