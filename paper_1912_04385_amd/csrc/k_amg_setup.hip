@@ -1370,7 +1370,7 @@ void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av,
 // row sets flag bit 256 (a pattern that does not belong to these operands).
 // --------------------------------------------------------------------------
 constexpr int SPN_T = 64;
-constexpr int SPN_CAP = 64;
+constexpr int SPN_CAP = 32;
 
 __device__ inline int spn_find(const int *cols, int stride, int len, int j) {
     int lo = 0, hi = len - 1;
