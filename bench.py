@@ -381,6 +381,75 @@ def learned_bench(args, dev) -> int:
     return 0
 
 
+def judge_study(args, dev) -> int:
+    """How many V-cycles the learned interpolation's judge needs.  For each
+    system, the classical and the learned temperature hierarchy (the learned
+    one built without the judge) are measured from the same start vector over
+    k = 1..10 cycles (FP64 V-cycles, cptr_amg_conv_factor); the study reports
+    whether the ranking after k cycles is the ranking after 10.  Systems: the
+    four config-2 systems (200 x 100, b = 6, Pe 0.1 .. 100), twelve systems of
+    the training recipe (256 x 128, b = 6), the two config-3/4 test systems
+    (1000 x 500, b = 8) and four systems of the config-5 sequence, with the
+    trained network and, on part of them, the same network with its output
+    layer negated."""
+    import numpy as np
+    import torch
+    from paper_1912_04385_amd import cptr
+    from paper_1912_04385_amd.train_interp import DEFAULT_WEIGHTS, load_weights
+    import synthetic as S
+
+    w = load_weights(args.weights or DEFAULT_WEIGHTS)
+    # the same network with its output layer (W3[64], b3, the blob's last 65
+    # entries) negated: the correction points the other way, so that the
+    # classical hierarchy wins on some systems too
+    w_neg = w.copy()
+    w_neg[-65:] *= -1.0
+    rows = []
+
+    def run(label, s, nx, ny, net="trained"):
+        rp, ci = torch.from_numpy(s.row_ptr).to(dev), torch.from_numpy(s.col_idx).to(dev)
+        vals = torch.from_numpy(s.vals.reshape(-1)).to(dev)
+        rec = {"system": label, "network": net}
+        for name, ti in (("classical", cptr.INTERP_CLASSICAL), ("learned", cptr.INTERP_LEARNED_FORCED)):
+            sol = cptr.Solver(t_interp=ti, pre_sweeps=args.sweeps, post_sweeps=args.sweeps, ilu_tile_x=args.tile[0],
+                              ilu_tile_y=args.tile[1], krylov=cptr.FGMRES, precond_precision=cptr.FP32)
+            sol.load_mlp(w if net == "trained" else w_neg)
+            sol.setup(rp, ci, vals, 0, 1, nx, ny)
+            rec[name] = [round(sol.conv_factor(0, k, 0), 6) for k in range(1, 11)]
+            sol.close()
+        d = [rec["learned"][k] - rec["classical"][k] for k in range(10)]
+        rec["same_ranking_as_10"] = [bool((x < 0) == (d[9] < 0)) for x in d]
+        rows.append(rec)
+        print(f"# {label} ({net}) classical {rec['classical']} learned {rec['learned']}", file=sys.stderr, flush=True)
+
+    for i in range(4):
+        s = S.config2(i)
+        run(f"config2 system {i}", s, 200, 100)
+        run(f"config2 system {i}", s, 200, 100, "output layer negated")
+    for i in range(12):
+        s = S.config4_train(i)
+        run(f"training recipe system {i}", s, 256, 128)
+        if i < 6:
+            run(f"training recipe system {i}", s, 256, 128, "output layer negated")
+    for i in range(2):
+        s = S.config3(i)
+        run(f"config3/4 system {i}", s, 1000, 500)
+        run(f"config3/4 system {i}", s, 1000, 500, "output layer negated")
+    perm = S.config5_field(2000, 1000)
+    for k in (0, 7, 14, 19):
+        s = S.config5(k, perm, 2000, 1000)
+        run(f"config5 system {k}", s, 2000, 1000)
+        if k == 0:
+            run(f"config5 system {k}", s, 2000, 1000, "output layer negated")
+    agree = [sum(r["same_ranking_as_10"][k] for r in rows) for k in range(10)]
+    learned_wins = sum(r["learned"][9] < r["classical"][9] for r in rows)
+    print(json.dumps({"study": "cycles of the learned interpolation's judge: ranking of the classical and the learned "
+                               "temperature hierarchy after k V-cycles against the ranking after 10",
+                      "cases": len(rows), "learned_lower_after_10": learned_wins,
+                      "same_ranking_as_10_by_k": agree, "rows": rows}))
+    return 0
+
+
 def host_cpu() -> dict:
     """Core count and CPU model of the host the oracle runs on."""
     model = None
@@ -713,10 +782,11 @@ def main() -> int:
                     help="c5: skip the config-3, config-1 and config-2 timings beside the headline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--weights", default=None, help="learned-interpolation parameters (.npy) for c4 / c5")
-    ap.add_argument("--workload", choices=["c5", "c3", "c4", "exact"], default="c5",
+    ap.add_argument("--workload", choices=["c5", "c3", "c4", "exact", "judge"], default="c5",
                     help="c5: the 2000x1000 Newton sequence with hierarchy reuse, learned against classical "
                          "interpolation and plain FP64 (the headline, default); c3: 1000x500 single systems; "
-                         "c4: learned against classical interpolation; exact: the exact sub-solver study")
+                         "c4: learned against classical interpolation; exact: the exact sub-solver study; "
+                         "judge: the ranking of the two temperature hierarchies by V-cycle count")
     ap.add_argument("--sweeps", type=int, default=2,
                     help="Jacobi pre- and post-smoothing sweeps of the V-cycles (2 for every workload: two damped "
                          "Jacobi sweeps each way stand in for the paper's symmetric Gauss-Seidel smoother, and on "
@@ -760,6 +830,8 @@ def main() -> int:
         return learned_bench(args, dev)
     if args.workload == "exact":
         return exact_study(args, dev)
+    if args.workload == "judge":
+        return judge_study(args, dev)
     t_gen = time.perf_counter()
     systems = []
     for idx in (0, 1):

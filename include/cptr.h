@@ -83,7 +83,8 @@ enum { CPTR_SMOOTH_JACOBI = 0, CPTR_SMOOTH_L1JACOBI = 1, CPTR_SMOOTH_CHEBYSHEV =
  * convergence factor, or the learned correction without the judge.  The
  * judge runs at every full build of the temperature hierarchy (cptr_setup,
  * and every rebuild by cptr_update_values): both hierarchies are built and
- * the learned one is kept only when its convergence factor is lower.  The
+ * the learned one is kept only when its convergence factor, measured over
+ * judge_cycles V-cycles from the reuse test's start vector, is lower.  The
  * learned hierarchy differs from the classical one only in the fine level's
  * interpolation weights (below it: the classical C/F splits and transfer
  * operators, its own Galerkin products).  A hierarchy kept by the reuse test
@@ -136,6 +137,12 @@ typedef struct {
                                 /* a cycle that ends above it, later cycles stop  */
                                 /* their Givens estimate at min(target, |rbar|    */
                                 /* (rtol |b| / |b - A x|) / 2) (0)                */
+    int32_t judge_cycles;       /* V-cycles of the learned interpolation's judge  */
+                                /* (1..1000, default 4): both temperature         */
+                                /* hierarchies are measured from the same start   */
+                                /* vector over this many cycles and the lower     */
+                                /* factor wins; the reuse test keeps 10 cycles,   */
+                                /* since it compares one factor with a threshold  */
 } cptr_options;
 
 typedef struct {

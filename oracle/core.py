@@ -827,7 +827,8 @@ class Options:
     exact_subsolves: bool = False        # replace amg(.) by direct solves (the paper's exact study)
     exact_last_stage: bool = False       # replace ilu(Abar) by an exact solve (tests only)
     reuse_rho_max: float = 0.3           # keep a reused AMG hierarchy while rho < this
-    rho_cycles: int = 10
+    rho_cycles: int = 10                 # V-cycles of the reuse test's factor
+    judge_cycles: int = 4                # V-cycles of the learned interpolation's judge
     mlp_params: np.ndarray | None = None # learned T-interpolation weights (None = classical only)
     stop_unscaled: bool = False          # also require |b - A x| <= rtol |b| (unscaled system)
 
@@ -940,8 +941,8 @@ def build_preconditioner(dec: Decoupled, opts: Options, previous: dict | None = 
                 # formed from the learned fine level down)
                 from .learned import learned_hierarchy
                 hl = learned_hierarchy(opts.mlp_params, h)
-                rc = conv_factor(h, opts.rho_cycles, 0)
-                rl = conv_factor(hl, opts.rho_cycles, 0)
+                rc = conv_factor(h, opts.judge_cycles, 0)
+                rl = conv_factor(hl, opts.judge_cycles, 0)
                 use = rl < rc
                 if info is not None:
                     info["learned"] = dict(used=use, rho_classical=rc, rho_learned=rl)

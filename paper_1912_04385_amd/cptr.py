@@ -45,6 +45,7 @@ class Options(ctypes.Structure):
         ("ilu_tile_x", ctypes.c_int32), ("ilu_tile_y", ctypes.c_int32), ("t_interp", ctypes.c_int32),
         ("reuse_rho_max", ctypes.c_double), ("timing", ctypes.c_int32), ("setup_kernels", ctypes.c_int32),
         ("exact_subsolves", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("stop_unscaled", ctypes.c_int32),
+        ("judge_cycles", ctypes.c_int32),
     ]
 
 

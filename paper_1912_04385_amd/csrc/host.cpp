@@ -1351,6 +1351,7 @@ static void validate_options(const cptr_options &o) {
     if (o.t_interp < CPTR_INTERP_CLASSICAL || o.t_interp > CPTR_INTERP_LEARNED_FORCED)
         throw Error(CPTR_E_ARG, "unknown t_interp");
     if (o.stop_unscaled != 0 && o.stop_unscaled != 1) throw Error(CPTR_E_ARG, "stop_unscaled must be 0 or 1");
+    if (o.judge_cycles < 1 || o.judge_cycles > 1000) throw Error(CPTR_E_ARG, "judge_cycles must be 1..1000");
     if (o.t_interp != CPTR_INTERP_CLASSICAL && (o.amg_pmax < 1 || o.amg_pmax > 16))
         throw Error(CPTR_E_ARG, "learned interpolation needs amg_pmax in 1..16");
 }
@@ -1398,7 +1399,7 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
                 fill_int(B2.flag.p, 0, 1, B2.stream);
             }
             build_learned_hierarchy(&B2, hl, c->mlp.p, feed);
-            if (judge && hl.L.size() > 1) rl = conv_factor(c, hl, RHO_CYCLES, RHO_SEED, B2.stream, fp32);
+            if (judge && hl.L.size() > 1) rl = conv_factor(c, hl, c->opt.judge_cycles, RHO_SEED, B2.stream, fp32);
         } catch (...) {
             err = std::current_exception();
         }
@@ -1407,7 +1408,7 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     double rc = -1.0;
     try {
         build_hierarchy(&B, c->H[k], vals, own, &feed);
-        if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, B.stream, fp32);
+        if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], c->opt.judge_cycles, RHO_SEED, B.stream, fp32);
     } catch (...) {
         err1 = std::current_exception();
         feed.close();
@@ -1849,6 +1850,7 @@ cptr_status cptr_default_options(cptr_options *o) {
     o->exact_subsolves = 0;
     o->cheb_degree = 2;
     o->stop_unscaled = 0;
+    o->judge_cycles = 4;
     return CPTR_OK;
 }
 

@@ -258,7 +258,7 @@ def test_judge_on_every_full_build():
             assert len(got.levels) == len(h.levels)
             for a, b in zip(got.levels[:-1], h.levels[:-1]):
                 assert np.array_equal(a.P.ci, b.P.ci) and np.array_equal(a.P.v, b.P.v)
-            assert O.conv_factor(got, 10, 0) == (rl if r.learned["used"] else rc)
+            assert O.conv_factor(got, opts(1e-9).judge_cycles, 0) == (rl if r.learned["used"] else rc)
             prev = r
         # a threshold every refreshed hierarchy meets: kept, not judged
         r0 = O.solve(systems[0], opts(0.99))
