@@ -232,12 +232,20 @@ static void read_ints3(Builder *c, const int *a, const int *b, const int *d, int
     read_bytes(out, c->stage.p, 3 * sizeof(int), c->stream);
 }
 
+// four device ints with one host round trip
+static void read_ints4(Builder *c, const int *a, const int *b, const int *d, const int *e, int out[4]) {
+    c->stage.alloc(4);
+    gather_ints(a, b, d, c->stage.p, c->stream, e);
+    read_bytes(out, c->stage.p, 4 * sizeof(int), c->stream);
+}
+
 // ---------------------------------------------------------------------------
 // AMG hierarchy (setup)
 // ---------------------------------------------------------------------------
 // SpGEMM C = A B in three phases, so that a caller can batch its host reads:
 //   plan:    capacities and their offsets; off[m] = capacity, off[m + 1] =
-//            the longest row's product count (device)
+//            the longest row's product count, off[m + 2] = the shape word
+//            (0: every row fits the register kernel) (device)
 //   compute: the products into the scratch, row counts, and their scan into
 //            C.rp; C.rp[m] = nnz (device)
 //   finish:  compaction into C once nnz is known
@@ -253,23 +261,27 @@ static void spgemm_plan(Builder *c, const CsrD &A, const CsrD &B, SpgPlan &P) {
     const int m = A.n;
     P.m = m;
     P.ub.alloc((size_t)m + 1);
-    P.off.alloc((size_t)m + 2);
+    P.off.alloc((size_t)m + 3);
     P.cnt.alloc((size_t)m + 1);
     amg_spgemm_bound(m, A.rp, A.ci, B.rp, P.ub.p, P.off.p + m + 1, s);
     scan_exclusive(P.ub.p, P.off.p, m, nullptr, s);
 }
 
-static void spgemm_compute(Builder *c, const CsrD &A, const CsrD &B, SpgPlan &P, int cap, int maxprod, CsrD &C) {
+static void spgemm_compute(Builder *c, const CsrD &A, const CsrD &B, SpgPlan &P, int cap, int maxprod, CsrD &C,
+                           int shape = 1) {
     hipStream_t s = c->stream;
     const int m = P.m;
     P.hk.alloc((size_t)cap);
     P.hv.alloc((size_t)cap);
-    // rows short enough for an LDS hash table: one thread per row; longer
-    // rows: lane groups that sort the row's products (all kernels give the
-    // same sums, bit for bit)
+    // rows of at most 5 entries of A times rows of B of at most 4 (shape 0):
+    // one thread per row with every product in registers; rows short
+    // enough for an LDS hash table: one thread per row; longer rows: lane
+    // groups that sort the row's products (all kernels give the same sums,
+    // bit for bit)
     const int sk = c->opt.setup_kernels;
     if (sk == 2 || (sk == 0 && 2 * maxprod + 1 <= SPGEMM_THREAD_CAP))
-        amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, P.off.p, P.hk.p, P.hv.p, P.cnt.p, s);
+        amg_spgemm_compute(m, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, P.off.p, P.hk.p, P.hv.p, P.cnt.p, s,
+                           sk == 0 && shape == 0);
     else
         amg_spgemm_compute_sort(m, B.ncols, maxprod, A.rp, A.ci, A.v.p, B.rp, B.ci, B.v.p, P.off.p, P.hk.p, P.hv.p,
                                 P.cnt.p, s);
@@ -294,8 +306,8 @@ static void csr_spgemm(Builder *c, const CsrD &A, const CsrD &B, CsrD &C) {
     SpgPlan P;
     spgemm_plan(c, A, B, P);
     int tm[3];
-    read_ints3(c, P.off.p + A.n, P.off.p + A.n + 1, nullptr, tm);
-    spgemm_compute(c, A, B, P, tm[0], tm[1], C);
+    read_ints3(c, P.off.p + A.n, P.off.p + A.n + 1, P.off.p + A.n + 2, tm);
+    spgemm_compute(c, A, B, P, tm[0], tm[1], C, tm[2]);
     spgemm_finish(c, P, read_scalar(C.rp_own.p + A.n, c->stream), C);
 }
 
@@ -788,6 +800,7 @@ struct LevelFeed {
         const int *cf = nullptr;
         Csr P, R;
         Csr AP, Anext;                              // patterns (values unused)
+        bool ap_narrow = false;                     // A P fits the register kernel
         int annz = 0;                               // fine level: the operator
         const double *av = nullptr, *dinv = nullptr;
         const unsigned char *strong = nullptr;
@@ -871,7 +884,7 @@ static void galerkin_numeric(Builder *c, Level &L, Level &N) {
     DBuf<double> apv;
     apv.alloc((size_t)L.ap_nnz + 1);
     amg_spgemm_numeric(L.A.n, L.A.rp, L.A.ci, L.A.v.p, L.P.rp, L.P.ci, L.P.v.p, L.ap_rp.p, L.ap_ci.p, apv.p,
-                       c->flag.p, s);
+                       c->flag.p, s, L.ap_narrow && c->opt.setup_kernels == 0);
     amg_spgemm_numeric(L.R.n, L.R.rp, L.R.ci, L.R.v.p, L.ap_rp.p, L.ap_ci.p, apv.p, N.A.rp, N.A.ci, N.A.v.p,
                        c->flag.p, s);
 }
@@ -919,7 +932,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
         }
         CsrD &P = L.P;
         SpgPlan pAP;
-        int rd[3];
+        int rd[4];
         L.strong.alloc((size_t)L.A.nnz + 1);
         L.cf.alloc((size_t)m + 1);             // state -> C/F
         InterpScratch is;
@@ -928,9 +941,9 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
         // A P needs only P's row pointers for its plan: P's size and the
         // product's capacity in one read
         spgemm_plan(c, L.A, P, pAP);
-        read_ints3(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, rd);
+        read_ints4(c, P.rp_own.p + m, pAP.off.p + m, pAP.off.p + m + 1, pAP.off.p + m + 2, rd);
         P.nnz = rd[0];
-        const int capAP = rd[1], maxAP = rd[2];
+        const int capAP = rd[1], maxAP = rd[2], shapeAP = rd[3];
         compact_interp(c, is, P);
         L.nc = nc;
         if (feed && h.L.size() == 1) {
@@ -947,7 +960,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
         }
         csr_transpose(c, P, L.R);
         CsrD AP;
-        spgemm_compute(c, L.A, P, pAP, capAP, maxAP, AP);
+        spgemm_compute(c, L.A, P, pAP, capAP, maxAP, AP, shapeAP);
         // R (A P) needs only A P's row pointers for its plan
         SpgPlan pRAP;
         spgemm_plan(c, L.R, AP, pRAP);
@@ -960,6 +973,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
         L.ap_rp = std::move(AP.rp_own);
         L.ap_ci = std::move(AP.ci_own);
         L.ap_nnz = AP.nnz;
+        L.ap_narrow = (shapeAP == 0);
         if (feed) {
             LevelFeed::Item it;
             it.n = m;
@@ -969,6 +983,7 @@ static void build_hierarchy(Builder *c, Hierarchy &h, const double *vals, DBuf<d
             it.R = LevelFeed::view(L.R);
             it.AP = {m, nc, L.ap_nnz, L.ap_rp.p, L.ap_ci.p, nullptr};
             it.Anext = {nxt.A.n, nxt.A.ncols, nxt.A.nnz, nxt.A.rp, nxt.A.ci, nullptr};
+            it.ap_narrow = L.ap_narrow;
             feed->publish(it, s, false);
         }
         h.L.push_back(std::move(nxt));
@@ -1035,6 +1050,7 @@ static void build_learned_hierarchy(Builder *c, Hierarchy &h, const float *mlp, 
             copy_csr(s, it.R, L.R);
         }
         L.ap_nnz = it.AP.nnz;
+        L.ap_narrow = it.ap_narrow;
         L.ap_rp.alloc((size_t)it.AP.n + 1);
         L.ap_ci.alloc((size_t)it.AP.nnz + 1);
         CPTR_HIP(hipMemcpyAsync(L.ap_rp.p, it.AP.rp, sizeof(int) * (it.AP.n + 1), hipMemcpyDeviceToDevice, s));
@@ -1440,15 +1456,19 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     c->wt.alloc((size_t)n * b);
     c->beta.alloc(n);
     // s_i4[0]: the lowest singular cell of the decoupling; s_i4[1]: the
-    // non-finite flag of the values, whose scan runs on a side stream beside
-    // phase 1 (both come back in one read)
+    // non-finite flag of the values (both come back in one read).  CPTR3 and
+    // CPR check the values inside phase 1, which reads every block row; the
+    // other variants scan them on a side stream beside it
     c->s_i4.alloc(2);
     fill_int(c->s_i4.p, 0x7fffffff, 1, s);
     fill_int(c->s_i4.p + 1, 0, 1, s);
-    CPTR_HIP(hipEventRecord(c->ev_side[2], s));
-    CPTR_HIP(hipStreamWaitEvent(c->side[2], c->ev_side[2], 0));
-    count_nonfinite(vals, (size_t)nnzb * b * b, c->s_i4.p + 1, c->side[2]);
-    CPTR_HIP(hipEventRecord(c->ev_side[2], c->side[2]));
+    const bool rows_kernel = !sys && c->opt.variant != CPTR_VARIANT_LAST_ONLY;
+    if (!rows_kernel) {
+        CPTR_HIP(hipEventRecord(c->ev_side[2], s));
+        CPTR_HIP(hipStreamWaitEvent(c->side[2], c->ev_side[2], 0));
+        count_nonfinite(vals, (size_t)nnzb * b * b, c->s_i4.p + 1, c->side[2]);
+        CPTR_HIP(hipEventRecord(c->ev_side[2], c->side[2]));
+    }
     c->slabT.alloc((size_t)nnzb * b);
     c->slabP.alloc((size_t)nnzb * b);
     DBuf<double> &ctt = c->ctt, &bpp = c->bpp;
@@ -1474,10 +1494,10 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                                 c->beta.p, c->s_i4.p, nullptr, nullptr, c->ee_rp.p, c->ee_ci.p, c->ee_v.p, s);
     } else {
         // phase 1: the weights and the two scalar operators (all the AMG setups need)
-        launch_decouple_weights(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
-                                c->beta.p, c->s_i4.p, ctt.p, bpp.p, nullptr, nullptr, nullptr, s);
+        launch_decouple_weights_rows(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
+                                     c->beta.p, c->s_i4.p, c->s_i4.p + 1, ctt.p, bpp.p, s);
     }
-    CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[2], 0));
+    if (!rows_kernel) CPTR_HIP(hipStreamWaitEvent(s, c->ev_side[2], 0));
     int chk[2];
     read_bytes(chk, c->s_i4.p, 2 * sizeof(int), s);
     if (chk[1] & 16) throw Error(CPTR_E_NONFINITE, "non-finite matrix entry");

@@ -105,6 +105,7 @@ struct Level {
     // (kept for refreshing the Galerkin product on new values)
     DBuf<int> ap_rp, ap_ci;
     int ap_nnz = -1;        // -1: not kept
+    bool ap_narrow = false; // A P's rows fit the register kernel (A rows <= 5, P rows <= 4)
     DBuf<double> dinv;      // 1 / smoothing diagonal
     DBuf<float> dinv32;
     DBuf<int> cf;           // 1 = C, 0 = F (not on the coarsest level)
@@ -144,7 +145,8 @@ struct Hierarchy {
 // ---------------------------------------------------------------------------
 // k_common.hip
 void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t s);   // out[n] = total
-void gather_ints(const int *a, const int *b, const int *c, int *out, hipStream_t s);   // out[0..2]; null -> 0
+void gather_ints(const int *a, const int *b, const int *c, int *out, hipStream_t s,
+                 const int *d = nullptr);   // out[0..3]; null -> 0
 void fill_int(int *p, int v, size_t n, hipStream_t s);
 void fill_double(double *p, double v, size_t n, hipStream_t s);
 void check_pattern(int n, const int *rp, const int *ci, int *flag_dev, hipStream_t s);
@@ -169,6 +171,11 @@ void launch_decouple(int variant, int n, int b, const int *rp, const int *ci, co
 void launch_decouple_weights(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
                              int it, double *wp, double *wt, double *beta, int *err, double *ctt, double *bpp,
                              int *ee_rp, int *ee_ci, double *ee_v, hipStream_t s);
+// Phase 1 for CPTR3 and CPR with the values' non-finite scan folded in
+// (nf: bit 16), the B_PP / C_TT entries as launch_decouple_weights gives them
+void launch_decouple_weights_rows(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
+                                  int it, double *wp, double *wt, double *beta, int *err, int *nf, double *ctt,
+                                  double *bpp, hipStream_t s);
 void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                            const double *wp, const double *wt, const double *beta, double *abar, double *slabT,
                            double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s);
@@ -201,16 +208,23 @@ void amg_compact(int n, const int *off, const int *tcol, const double *tw, const
                  hipStream_t st);
 void amg_transpose(int nr, int nc, int nnz, const int *rp, const int *ci, const double *v, int *rpT, int *ciT,
                    double *vT, int *work, hipStream_t st);
-// maxprod (device, may be NULL) receives the largest product count of a row
+// maxprod (device, may be NULL) receives the largest product count of a row,
+// maxprod[1] bit 0 when a row of A, or a row of B it reaches, is too long for
+// the register kernel (narrow = false)
 void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, int *maxprod, hipStream_t st);
 void amg_spgemm_compute_sort(int m, int ncols, int maxprod, const int *arp, const int *aci, const double *av,
                              const int *brp, const int *bci, const double *bv, const int *off, int *tcol,
                              double *tval, int *cnt, hipStream_t st);
 // C = A B on C's known pattern (crp, cci); flag bit 256: a product outside it
+// (narrow: the rows fit the register kernel, and C's pattern is exactly the
+// product's)
 void amg_spgemm_numeric(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
-                        const double *bv, const int *crp, const int *cci, double *cv, int *flag, hipStream_t st);
+                        const double *bv, const int *crp, const int *cci, double *cv, int *flag, hipStream_t st,
+                        bool narrow = false);
+// narrow: every row within the register kernel's limits (the shape word 0)
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
-                        const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st);
+                        const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st,
+                        bool narrow = false);
 // rows and columns [o, o + m) of a CSR matrix with sorted rows: entry counts,
 // then the entries in their order with columns shifted by -o
 void amg_submatrix_count(int m, int o, const int *rp, const int *ci, int *cnt, hipStream_t st);

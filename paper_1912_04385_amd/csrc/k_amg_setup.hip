@@ -1085,28 +1085,42 @@ void amg_transpose(int nr, int nc, int nnz, const int *rp, const int *ci, const 
 // accumulator processed in A's row order, so every output entry sums its terms
 // in ascending k starting from the first term)
 // --------------------------------------------------------------------------
+// maxprod[1], the shape word, gets bit 0 when some row of A has more than
+// SPR_EA entries or reaches a row of B with more than SPR_FB entries: the
+// register kernel below takes only products within both
+constexpr int SPR_EA = 5, SPR_FB = 4;
+
 __global__ void k_spgemm_bound(int m, const int *__restrict__ arp, const int *__restrict__ aci,
                                const int *__restrict__ brp, int *__restrict__ ub, int *maxprod) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int c = 0;
+    bool wide = false;
     if (i < m) {
-        for (int e = arp[i]; e < arp[i + 1]; ++e) {
+        const int e0 = arp[i], e1 = arp[i + 1];
+        wide = e1 - e0 > SPR_EA;
+        for (int e = e0; e < e1; ++e) {
             const int k = aci[e];
-            c += brp[k + 1] - brp[k];
+            const int nb = brp[k + 1] - brp[k];
+            c += nb;
+            wide = wide || nb > SPR_FB;
         }
         ub[i] = 2 * c + 1;      // hash capacity
     }
     if (maxprod) {
-        // one atomic per wavefront
+        // one atomic of each kind per wavefront
         int w = c;
         for (int d = 32; d >= 1; d >>= 1) w = max(w, __shfl_xor(w, d, 64));
-        if ((threadIdx.x & 63) == 0) atomicMax(maxprod, w);
+        const bool any_wide = __ballot(wide) != 0;
+        if ((threadIdx.x & 63) == 0) {
+            atomicMax(maxprod, w);
+            if (any_wide) atomicOr(maxprod + 1, 1);
+        }
     }
 }
 
 void amg_spgemm_bound(int m, const int *arp, const int *aci, const int *brp, int *ub, int *maxprod, hipStream_t st) {
     if (m == 0) return;
-    if (maxprod) fill_int(maxprod, 0, 1, st);
+    if (maxprod) fill_int(maxprod, 0, 2, st);
     hipLaunchKernelGGL(k_spgemm_bound, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, arp, aci, brp, ub, maxprod);
     CPTR_CHECK_LAUNCH();
 }
@@ -1183,6 +1197,127 @@ __global__ void __launch_bounds__(SPG_T) k_spgemm_compute(int m, const int *__re
         spgemm_row(i, arp, aci, av, brp, bci, bv, sk + threadIdx.x, sv + threadIdx.x, SPG_T, cap, ok, ov, cnt);
     else
         spgemm_row(i, arp, aci, av, brp, bci, bv, ok, ov, 1, cap, ok, ov, cnt);
+}
+
+// One thread per row for rows of at most EA entries of A whose rows of B
+// have at most FB entries (the fine level's A P: five-point rows times
+// truncated interpolation rows).  Every product stays in registers, product
+// p = (entry e of A's row, entry f of B's row) in A's row order, then B's:
+// the first product of a column starts its sum and the later ones are added
+// in product order -- the sequential accumulation, bit for bit -- and each
+// column's rank among the row's distinct columns places it in the sorted
+// output row.  No LDS, so the row's loads are all in flight together.
+template <int EA, int FB>
+__device__ inline unsigned spr_products(int i, const int *__restrict__ arp, const int *__restrict__ aci,
+                                        const double *__restrict__ av, const int *__restrict__ brp,
+                                        const int *__restrict__ bci, const double *__restrict__ bv,
+                                        int (&col)[EA * FB], double (&t)[EA * FB]) {
+    constexpr int NP = EA * FB;
+    static_assert(NP <= 32, "first-occurrence mask is 32 bits");
+    const int e0 = arp[i], na = arp[i + 1] - e0;
+    int kk[EA];
+    double a[EA];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+        const bool on = e < na;
+        kk[e] = on ? aci[e0 + e] : 0;
+        a[e] = on ? av[e0 + e] : 0.0;
+    }
+    int fb[EA], nb[EA];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+        const bool on = e < na;
+        fb[e] = on ? brp[kk[e]] : 0;
+        nb[e] = on ? brp[kk[e] + 1] - fb[e] : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            const int p = e * FB + f;
+            const bool on = f < nb[e];
+            col[p] = on ? bci[fb[e] + f] : -1 - p;     // an empty slot: a column of its own, below every real one
+            t[p] = on ? a[e] * bv[fb[e] + f] : 0.0;
+        }
+    }
+    // bit p: product p is its column's first
+    unsigned first = 0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        bool fst = col[p] >= 0;
+#pragma unroll
+        for (int q = 0; q < p; ++q) fst = fst && col[q] != col[p];
+        first |= fst ? (1u << p) : 0u;
+    }
+    return first;
+}
+
+// column p's sum over its products in order, and its rank in the row
+template <int NP>
+__device__ inline double spr_sum(int p, unsigned first, const int (&col)[NP], const double (&t)[NP], int &rank) {
+    double s = t[p];
+#pragma unroll
+    for (int q = p + 1; q < NP; ++q) s = (col[q] == col[p]) ? s + t[q] : s;
+    int r = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) r += (((first >> q) & 1u) && col[q] < col[p]) ? 1 : 0;
+    rank = r;
+    return s;
+}
+
+template <int EA, int FB>
+__global__ void __launch_bounds__(256) k_spgemm_reg(int m, const int *__restrict__ arp, const int *__restrict__ aci,
+                                                    const double *__restrict__ av, const int *__restrict__ brp,
+                                                    const int *__restrict__ bci, const double *__restrict__ bv,
+                                                    const int *__restrict__ off, int *__restrict__ tcol,
+                                                    double *__restrict__ tval, int *__restrict__ cnt) {
+    constexpr int NP = EA * FB;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int col[NP];
+    double t[NP];
+    const unsigned first = spr_products<EA, FB>(i, arp, aci, av, brp, bci, bv, col, t);
+    int *ok = tcol + off[i];
+    double *ov = tval + off[i];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if (!((first >> p) & 1u)) continue;
+        int r;
+        const double s = spr_sum<NP>(p, first, col, t, r);
+        ok[r] = col[p];
+        ov[r] = s;
+    }
+    cnt[i] = __popc(first);
+}
+
+// The same on C's known pattern (refreshed and learned Galerkin products):
+// the row's distinct columns must be exactly C's row, else flag bit 256.
+template <int EA, int FB>
+__global__ void __launch_bounds__(256) k_spgemm_reg_numeric(int m, const int *__restrict__ arp,
+                                                            const int *__restrict__ aci, const double *__restrict__ av,
+                                                            const int *__restrict__ brp, const int *__restrict__ bci,
+                                                            const double *__restrict__ bv, const int *__restrict__ crp,
+                                                            const int *__restrict__ cci, double *__restrict__ cv,
+                                                            int *flag) {
+    constexpr int NP = EA * FB;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int col[NP];
+    double t[NP];
+    const unsigned first = spr_products<EA, FB>(i, arp, aci, av, brp, bci, bv, col, t);
+    const int c0 = crp[i], len = crp[i + 1] - c0;
+    bool bad = __popc(first) != len;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if (!((first >> p) & 1u)) continue;
+        int r;
+        const double s = spr_sum<NP>(p, first, col, t, r);
+        if (r < len && cci[c0 + r] == col[p])
+            cv[c0 + r] = s;
+        else
+            bad = true;
+    }
+    if (bad) atomicOr(flag, 256);
 }
 
 // G lanes per output row, for rows of up to CAP products: the products are
@@ -1349,10 +1484,15 @@ void amg_spgemm_compute_sort(int m, int ncols, int maxprod, const int *arp, cons
 }
 
 void amg_spgemm_compute(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
-                        const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st) {
+                        const double *bv, const int *off, int *tcol, double *tval, int *cnt, hipStream_t st,
+                        bool narrow) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_spgemm_compute, dim3(blocks_for(m, SPG_T)), dim3(SPG_T), 0, st, m, arp, aci, av, brp, bci,
-                       bv, off, tcol, tval, cnt);
+    if (narrow)
+        hipLaunchKernelGGL((k_spgemm_reg<SPR_EA, SPR_FB>), dim3(blocks_for(m, 256)), dim3(256), 0, st, m, arp, aci,
+                           av, brp, bci, bv, off, tcol, tval, cnt);
+    else
+        hipLaunchKernelGGL(k_spgemm_compute, dim3(blocks_for(m, SPG_T)), dim3(SPG_T), 0, st, m, arp, aci, av, brp,
+                           bci, bv, off, tcol, tval, cnt);
     CPTR_CHECK_LAUNCH();
 }
 
@@ -1417,10 +1557,15 @@ __global__ void __launch_bounds__(SPN_T) k_spgemm_numeric(int m, const int *__re
 }
 
 void amg_spgemm_numeric(int m, const int *arp, const int *aci, const double *av, const int *brp, const int *bci,
-                        const double *bv, const int *crp, const int *cci, double *cv, int *flag, hipStream_t st) {
+                        const double *bv, const int *crp, const int *cci, double *cv, int *flag, hipStream_t st,
+                        bool narrow) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_spgemm_numeric, dim3(blocks_for(m, SPN_T)), dim3(SPN_T), 0, st, m, arp, aci, av, brp, bci,
-                       bv, crp, cci, cv, flag);
+    if (narrow)
+        hipLaunchKernelGGL((k_spgemm_reg_numeric<SPR_EA, SPR_FB>), dim3(blocks_for(m, 256)), dim3(256), 0, st, m, arp,
+                           aci, av, brp, bci, bv, crp, cci, cv, flag);
+    else
+        hipLaunchKernelGGL(k_spgemm_numeric, dim3(blocks_for(m, SPN_T)), dim3(SPN_T), 0, st, m, arp, aci, av, brp,
+                           bci, bv, crp, cci, cv, flag);
     CPTR_CHECK_LAUNCH();
 }
 

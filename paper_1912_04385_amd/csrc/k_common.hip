@@ -221,17 +221,18 @@ void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t 
     CPTR_CHECK_LAUNCH();
 }
 
-// up to three device ints side by side, for one host read
-__global__ void k_gather_ints(const int *a, const int *b, const int *c, int *out) {
+// up to four device ints side by side, for one host read
+__global__ void k_gather_ints(const int *a, const int *b, const int *c, const int *d, int *out) {
     if (threadIdx.x == 0) {
         out[0] = a ? *a : 0;
         out[1] = b ? *b : 0;
         out[2] = c ? *c : 0;
+        out[3] = d ? *d : 0;
     }
 }
 
-void gather_ints(const int *a, const int *b, const int *c, int *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_ints, dim3(1), dim3(64), 0, s, a, b, c, out);
+void gather_ints(const int *a, const int *b, const int *c, int *out, hipStream_t s, const int *d) {
+    hipLaunchKernelGGL(k_gather_ints, dim3(1), dim3(64), 0, s, a, b, c, d, out);
     CPTR_CHECK_LAUNCH();
 }
 

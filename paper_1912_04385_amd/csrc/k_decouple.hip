@@ -33,29 +33,22 @@ __device__ inline int group_index(int k, int ip, int it, bool with_t) {
 // only parts of the scaled matrix that the AMG setups need, so that they can
 // start while phase 2 scales the whole matrix.
 template <int B, int VAR>
-__global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__restrict__ rp,
-                                                          const int *__restrict__ ci, const double *__restrict__ A,
-                                                          int ip, int it, double *__restrict__ wp,
-                                                          double *__restrict__ wt, double *__restrict__ beta, int *err,
-                                                          double *__restrict__ ctt, double *__restrict__ bpp,
-                                                          int *__restrict__ ee_rp, int *__restrict__ ee_ci,
-                                                          double *__restrict__ ee_v) {
-    constexpr bool CPR = (VAR == CPTR_VARIANT_CPR);
-    constexpr int NG = CPR ? B - 1 : B - 2;
-    constexpr int NR = CPR ? 1 : 2;
-    constexpr int NGX = NG > 0 ? NG : 1;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int d = -1;
-    for (int e = rp[i]; e < rp[i + 1]; ++e)
-        if (ci[e] == i) d = e;
-    if (d < 0) {
-        atomicMin(err, i);
-        return;
-    }
-    const double *D = A + (size_t)d * B * B;
+struct DW {
+    static constexpr bool CPR = (VAR == CPTR_VARIANT_CPR);
+    static constexpr int NG = CPR ? B - 1 : B - 2;     // the eliminated group's size
+    static constexpr int NR = CPR ? 1 : 2;             // right-hand sides: w_P (and w_T)
+    static constexpr int NGX = NG > 0 ? NG : 1;
+};
+
+// The cell's solve from its diagonal block D (row-major B x B, any address
+// space): F[k][0] = w_P[g_k], F[k][NR - 1] = w_T[g_k], and beta (CPTR3).
+// False when a pivot is zero or Ahat_ii[P][P] is.
+template <int B, int VAR>
+__device__ inline bool dw_cell_solve(const double *D, int ip, int it, double (&F)[DW<B, VAR>::NGX][DW<B, VAR>::NR],
+                                     double &bt) {
+    constexpr bool CPR = DW<B, VAR>::CPR;
+    constexpr int NG = DW<B, VAR>::NG, NR = DW<B, VAR>::NR, NGX = DW<B, VAR>::NGX;
     double M[NGX][NGX];
-    double F[NGX][NR];
 #pragma unroll
     for (int r = 0; r < NG; ++r) {
         const int gr = group_index(r, ip, it, CPR);
@@ -93,10 +86,7 @@ __global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__re
             for (int j = 0; j < NR; ++j) F[r][j] = F[r][j] - l * F[k][j];
         }
     }
-    if (singular) {
-        atomicMin(err, i);
-        return;
-    }
+    if (singular) return false;
 #pragma unroll
     for (int k = NG - 1; k >= 0; --k) {
 #pragma unroll
@@ -107,19 +97,26 @@ __global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__re
             F[k][j] = t / M[k][k];
         }
     }
-    double bt = 0.0;
+    bt = 0.0;
     if (VAR == CPTR_VARIANT_CPTR3) {
         double hp = D[ip * B + ip], ht = D[it * B + ip];
 #pragma unroll
         for (int k = 0; k < NG; ++k) hp = hp - F[k][0] * D[group_index(k, ip, it, CPR) * B + ip];
 #pragma unroll
         for (int k = 0; k < NG; ++k) ht = ht - F[k][NR - 1] * D[group_index(k, ip, it, CPR) * B + ip];
-        if (hp == 0.0) {
-            atomicMin(err, i);
-            return;
-        }
+        if (hp == 0.0) return false;
         bt = ht / hp;
     }
+    return true;
+}
+
+// w_P, w_T stored by unknown (0 outside the group) and beta
+template <int B, int VAR>
+__device__ inline void dw_store_weights(int i, int ip, int it, const double (&F)[DW<B, VAR>::NGX][DW<B, VAR>::NR],
+                                        double bt, double *__restrict__ wp, double *__restrict__ wt,
+                                        double *__restrict__ beta) {
+    constexpr bool CPR = DW<B, VAR>::CPR;
+    constexpr int NG = DW<B, VAR>::NG, NR = DW<B, VAR>::NR;
 #pragma unroll
     for (int u = 0; u < B; ++u) {
         double vp = 0.0, vt = 0.0;
@@ -130,6 +127,59 @@ __global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__re
         wt[(size_t)i * B + u] = vt;
     }
     beta[i] = bt;
+}
+
+// B_PP and C_TT entries of one block of the cell's row from the block's P
+// and T columns: cP[r * stride] = A_ij[r][P], cT[r * stride] = A_ij[r][T]
+template <int B, int VAR>
+__device__ inline void dw_block_entries(const double *cP, const double *cT, int stride, int ip, int it,
+                                        const double (&F)[DW<B, VAR>::NGX][DW<B, VAR>::NR], double bt,
+                                        double &out_bpp, double &out_ctt) {
+    constexpr bool CPR = DW<B, VAR>::CPR;
+    constexpr int NG = DW<B, VAR>::NG, NR = DW<B, VAR>::NR;
+    // Abar[P][P]: the P row at column P
+    double hpP = cP[ip * stride];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) hpP = hpP - F[k][0] * cP[group_index(k, ip, it, CPR) * stride];
+    out_bpp = hpP;
+    if (CPR) {
+        out_ctt = cT[it * stride];       // T is in the eliminated group: its row is unchanged
+    } else {
+        double hpT = cT[ip * stride], htT = cT[it * stride];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) hpT = hpT - F[k][0] * cT[group_index(k, ip, it, CPR) * stride];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) htT = htT - F[k][NR - 1] * cT[group_index(k, ip, it, CPR) * stride];
+        out_ctt = (VAR == CPTR_VARIANT_CPTR3) ? htT - bt * hpT : htT;
+    }
+}
+
+template <int B, int VAR>
+__global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__restrict__ rp,
+                                                          const int *__restrict__ ci, const double *__restrict__ A,
+                                                          int ip, int it, double *__restrict__ wp,
+                                                          double *__restrict__ wt, double *__restrict__ beta, int *err,
+                                                          double *__restrict__ ctt, double *__restrict__ bpp,
+                                                          int *__restrict__ ee_rp, int *__restrict__ ee_ci,
+                                                          double *__restrict__ ee_v) {
+    constexpr bool CPR = DW<B, VAR>::CPR;
+    constexpr int NG = DW<B, VAR>::NG, NR = DW<B, VAR>::NR, NGX = DW<B, VAR>::NGX;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int d = -1;
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (ci[e] == i) d = e;
+    if (d < 0) {
+        atomicMin(err, i);
+        return;
+    }
+    double F[NGX][NR];
+    double bt;
+    if (!dw_cell_solve<B, VAR>(A + (size_t)d * B * B, ip, it, F, bt)) {
+        atomicMin(err, i);
+        return;
+    }
+    dw_store_weights<B, VAR>(i, ip, it, F, bt, wp, wt, beta);
     if (VAR == CPTR_VARIANT_CPTR && ee_v) {
         // the elliptic block B_ee straight from the weights (row u n + i at
         // 2 (u nnzb + rp[i]): P-block columns, then T-block columns + n),
@@ -165,23 +215,128 @@ __global__ void __launch_bounds__(128) k_decouple_weights(int n, const int *__re
     if (!ctt && !bpp) return;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const double *Bk = A + (size_t)e * B * B;
-        // Abar[P][P]: the P row at column P
-        double hpP = Bk[ip * B + ip];
+        double vb, vc;
+        dw_block_entries<B, VAR>(Bk + ip, Bk + it, B, ip, it, F, bt, vb, vc);
+        if (bpp) bpp[e] = vb;
+        if (ctt) ctt[e] = vc;
+    }
+}
+
+// Phase 1 for CPTR3 and CPR with the non-finite scan of the values folded
+// in: one group of 8 lanes per cell, lane r reading row r of every block of
+// the cell's row (so the block stream is read once, in contiguous rows, and
+// every value is checked: flag bit 16).  The diagonal block and the P and T
+// columns of up to DW_MAXB blocks go to LDS; one lane solves the cell as
+// above, then one lane per block forms its B_PP and C_TT entries -- the same
+// arithmetic as the one-thread-per-cell kernel, bit for bit.  Rows with more
+// blocks take that kernel's path on the group's first lane.
+constexpr int DW_CELLS = 32;     // cells per 256-thread workgroup
+constexpr int DW_MAXB = 6;
+
+template <int B, int VAR>
+__global__ void __launch_bounds__(256) k_decouple_weights_rows(int n, const int *__restrict__ rp,
+                                                               const int *__restrict__ ci,
+                                                               const double *__restrict__ A, int ip, int it,
+                                                               double *__restrict__ wp, double *__restrict__ wt,
+                                                               double *__restrict__ beta, int *err, int *nf,
+                                                               double *__restrict__ ctt, double *__restrict__ bpp) {
+    constexpr int NG = DW<B, VAR>::NG, NR = DW<B, VAR>::NR, NGX = DW<B, VAR>::NGX;
+    __shared__ double sD[DW_CELLS][B * B];
+    __shared__ double sP[DW_CELLS][DW_MAXB][B];
+    __shared__ double sT[DW_CELLS][DW_MAXB][B];
+    __shared__ double sF[DW_CELLS][NGX][NR];
+    __shared__ double sBt[DW_CELLS];
+    __shared__ int sOk[DW_CELLS];
+    const int g = threadIdx.x >> 3, r = threadIdx.x & 7;
+    const int i = blockIdx.x * DW_CELLS + g;
+    const bool act = i < n;
+    int e0 = 0, nb = 0;
+    if (act) {
+        e0 = rp[i];
+        nb = rp[i + 1] - e0;
+    }
+    // the diagonal block: the row's last entry in column i
+    int dq = -1;
+    for (int q = r; act && q < nb; q += 8)
+        if (ci[e0 + q] == i) dq = q;
 #pragma unroll
-        for (int k = 0; k < NG; ++k) hpP = hpP - F[k][0] * Bk[group_index(k, ip, it, CPR) * B + ip];
-        if (bpp) bpp[e] = hpP;
-        if (ctt) {
-            if (CPR) {
-                ctt[e] = Bk[it * B + it];       // T is in the eliminated group: its row is unchanged
-            } else {
-                double hpT = Bk[ip * B + it], htT = Bk[it * B + it];
+    for (int w = 4; w >= 1; w >>= 1) dq = max(dq, __shfl_xor(dq, w, 8));
+    const bool staged = act && dq >= 0 && nb <= DW_MAXB;
+    bool bad = false;
+    if (act && r < B) {
+        // the first DW_MAXB blocks with all their loads issued together
+        double v[DW_MAXB][B];
 #pragma unroll
-                for (int k = 0; k < NG; ++k) hpT = hpT - F[k][0] * Bk[group_index(k, ip, it, CPR) * B + it];
+        for (int q = 0; q < DW_MAXB; ++q) {
+            const double *row = A + ((size_t)(e0 + q) * B + r) * B;
 #pragma unroll
-                for (int k = 0; k < NG; ++k) htT = htT - F[k][NR - 1] * Bk[group_index(k, ip, it, CPR) * B + it];
-                ctt[e] = (VAR == CPTR_VARIANT_CPTR3) ? htT - bt * hpT : htT;
+            for (int c = 0; c < B; ++c) v[q][c] = (q < nb) ? row[c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < DW_MAXB; ++q) {
+#pragma unroll
+            for (int c = 0; c < B; ++c) bad = bad || !isfinite(v[q][c]);
+            if (staged && q < nb) {
+                if (q == dq) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) sD[g][r * B + c] = v[q][c];
+                }
+                const double *row = A + ((size_t)(e0 + q) * B + r) * B;
+                sP[g][q][r] = row[ip];
+                sT[g][q][r] = row[it];
             }
         }
+        for (int q = DW_MAXB; q < nb; ++q) {
+            const double *row = A + ((size_t)(e0 + q) * B + r) * B;
+#pragma unroll
+            for (int c = 0; c < B; ++c) bad = bad || !isfinite(row[c]);
+        }
+    }
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(nf, 16);
+    __syncthreads();
+    if (act && r == 0) {
+        int ok = 0;
+        if (dq < 0) {
+            atomicMin(err, i);
+        } else {
+            const double *D = staged ? &sD[g][0] : A + (size_t)(e0 + dq) * B * B;
+            double F[NGX][NR];
+            double bt;
+            if (!dw_cell_solve<B, VAR>(D, ip, it, F, bt)) {
+                atomicMin(err, i);
+            } else {
+                dw_store_weights<B, VAR>(i, ip, it, F, bt, wp, wt, beta);
+                if (staged) {
+                    ok = 1;
+#pragma unroll
+                    for (int k = 0; k < NGX; ++k)
+#pragma unroll
+                        for (int j = 0; j < NR; ++j) sF[g][k][j] = F[k][j];
+                    sBt[g] = bt;
+                } else {
+                    for (int e = e0; e < e0 + nb; ++e) {
+                        const double *Bk = A + (size_t)e * B * B;
+                        double vb, vc;
+                        dw_block_entries<B, VAR>(Bk + ip, Bk + it, B, ip, it, F, bt, vb, vc);
+                        bpp[e] = vb;
+                        ctt[e] = vc;
+                    }
+                }
+            }
+        }
+        sOk[g] = ok;
+    }
+    __syncthreads();
+    if (act && r < nb && sOk[g]) {
+        double F[NGX][NR];
+#pragma unroll
+        for (int k = 0; k < NGX; ++k)
+#pragma unroll
+            for (int j = 0; j < NR; ++j) F[k][j] = sF[g][k][j];
+        double vb, vc;
+        dw_block_entries<B, VAR>(&sP[g][r][0], &sT[g][r][0], 1, ip, it, F, sBt[g], vb, vc);
+        bpp[e0 + r] = vb;
+        ctt[e0 + r] = vc;
     }
 }
 
@@ -263,6 +418,30 @@ void launch_decouple_weights(int variant, int n, int b, const int *rp, const int
         else                                                                                                      \
             hipLaunchKernelGGL((k_decouple_weights<BB, CPTR_VARIANT_CPTR3>), g, t, 0, s, n, rp, ci, A, ip, it, wp, \
                                wt, beta, err, ctt, bpp, ee_rp, ee_ci, ee_v);                                      \
+        break;
+    switch (b) {
+        CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        default: throw Error(CPTR_E_ARG, "block size must be 2..8");
+    }
+#undef CASE
+    CPTR_CHECK_LAUNCH();
+}
+
+void launch_decouple_weights_rows(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip,
+                                  int it, double *wp, double *wt, double *beta, int *err, int *nf, double *ctt,
+                                  double *bpp, hipStream_t s) {
+    if (variant != CPTR_VARIANT_CPTR3 && variant != CPTR_VARIANT_CPR)
+        throw Error(CPTR_E_ARG, "the row kernel of the decoupling takes CPTR3 and CPR only");
+    if (n == 0) return;
+    const dim3 g((unsigned)((n + DW_CELLS - 1) / DW_CELLS)), t(256);
+#define CASE(BB)                                                                                                  \
+    case BB:                                                                                                      \
+        if (variant == CPTR_VARIANT_CPR)                                                                          \
+            hipLaunchKernelGGL((k_decouple_weights_rows<BB, CPTR_VARIANT_CPR>), g, t, 0, s, n, rp, ci, A, ip, it, \
+                               wp, wt, beta, err, nf, ctt, bpp);                                                  \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_decouple_weights_rows<BB, CPTR_VARIANT_CPTR3>), g, t, 0, s, n, rp, ci, A, ip,   \
+                               it, wp, wt, beta, err, nf, ctt, bpp);                                              \
         break;
     switch (b) {
         CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
