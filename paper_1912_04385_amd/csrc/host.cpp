@@ -1603,11 +1603,22 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         ~Joiner() { for (int k = 0; k < 2; ++k) if (t[k].joinable()) t[k].join(); }
     } joiner{th};
     // phase 2 of the scaling, concurrently with the hierarchy builds: the
-    // scaled matrix, its column slabs and FP32 copies, then the last stage
+    // scaled matrix, its column slabs and FP32 copies and the BILU(0)
+    // sweeps' in-tile neighbour blocks, then the last stage
+    const bool tile_blocks = c->use_tiles && bilu_wave_ok(c->ts, b);
+    if (tile_blocks) {
+        if (fp32)
+            c->tb32.alloc((size_t)n * 4 * b * b);
+        else
+            c->tb.alloc((size_t)n * 4 * b * b);
+    }
+    const bool tb_in_apply = tile_blocks && c->opt.variant != CPTR_VARIANT_LAST_ONLY;
     if (c->opt.variant != CPTR_VARIANT_LAST_ONLY)
         launch_decouple_apply(c->opt.variant, n, b, c->rp.p, c->ci.p, vals, c->ip, c->it, c->wp.p, c->wt.p,
                               c->beta.p, c->abar.p, c->slabT.p, c->slabP.p, fp32 ? c->abar32.p : nullptr,
-                              fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s);
+                              fp32 ? c->slabT32.p : nullptr, fp32 ? c->slabP32.p : nullptr, s, c->ts.nx, c->ts.tx,
+                              c->ts.ty, tb_in_apply && fp32 ? c->tb32.p : nullptr,
+                              tb_in_apply && !fp32 ? c->tb.p : nullptr);
     if (c->opt.variant == CPTR_VARIANT_CPTR3) {
         const bool t_first = (c->opt.stage_order == CPTR_T_THEN_P);
         c->cpl.alloc(nnzb);
@@ -1623,15 +1634,13 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
     } else {
         bj_factor_cells(n, b, c->rp.p, c->ci.p, c->abar.p, c->dinv.p, c->s_i4.p, nullptr, s);
     }
-    // the sweeps' side arrays, also while the hierarchies are still being built
-    if (c->use_tiles && bilu_wave_ok(c->ts, b)) {
-        if (fp32) {
-            c->tb32.alloc((size_t)n * 4 * b * b);
+    // the sweeps' side arrays (without the scaling's apply phase: gathered
+    // from the copied matrix), also while the hierarchies are still being built
+    if (tile_blocks && !tb_in_apply) {
+        if (fp32)
             bilu_tile_blocks<float>(c->ts, n, b, c->rp.p, c->ci.p, c->abar.p, c->tb32.p, s);
-        } else {
-            c->tb.alloc((size_t)n * 4 * b * b);
+        else
             bilu_tile_blocks<double>(c->ts, n, b, c->rp.p, c->ci.p, c->abar.p, c->tb.p, s);
-        }
     }
     if (fp32) {
         c->dinv32.alloc((size_t)n * b * b);

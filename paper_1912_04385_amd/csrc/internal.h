@@ -178,7 +178,10 @@ void launch_decouple_weights_rows(int variant, int n, int b, const int *rp, cons
                                   double *bpp, hipStream_t s);
 void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                            const double *wp, const double *wt, const double *beta, double *abar, double *slabT,
-                           double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s);
+                           double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s,
+                           int nx = 0, int tx = 0, int ty = 0, float *tb32 = nullptr, double *tb64 = nullptr);
+// (tb32 / tb64: also the BILU(0) sweeps' in-tile neighbour blocks of the
+// tx x ty tiles of an nx-wide grid, as bilu_tile_blocks gives them)
 void launch_scale_rhs(int variant, int n, int b, const double *rhs, int ip, int it, const double *wp,
                       const double *wt, const double *beta, double *out, hipStream_t s);
 void launch_unscale(int variant, int n, int b, const double *v, int ip, int it, const double *wp,

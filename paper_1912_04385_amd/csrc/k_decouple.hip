@@ -340,6 +340,18 @@ __global__ void __launch_bounds__(256) k_decouple_weights_rows(int n, const int 
     }
 }
 
+// In-tile neighbour slot of cell i's block in column j (0 S, 1 W, 2 E, 3 N;
+// -1 when j is not one of them or lies in another tx x ty tile)
+__device__ inline int tile_slot(int i, int j, int nx, int tx, int ty) {
+    const int x = i % nx, y = i / nx, xj = j % nx, yj = j / nx;
+    if (xj / tx != x / tx || yj / ty != y / ty) return -1;
+    if (yj == y - 1 && xj == x) return 0;
+    if (yj == y && xj == x - 1) return 1;
+    if (yj == y && xj == x + 1) return 2;
+    if (yj == y + 1 && xj == x) return 3;
+    return -1;
+}
+
 // Phase 2, one wavefront per cell, lane = block entry (r, c) = (lane / b,
 // lane % b) of every block of the row, with the stored weights:
 //   Abar[P][c] = Ahat[P][c],  Abar[T][c] = Ahat[T][c] - beta Ahat[P][c] (CPTR3),
@@ -351,14 +363,17 @@ __global__ void __launch_bounds__(64) k_decouple_apply(int n, const int *__restr
                                                        const double *__restrict__ beta, double *__restrict__ abar,
                                                        double *__restrict__ slabT, double *__restrict__ slabP,
                                                        float *__restrict__ abar32, float *__restrict__ slabT32,
-                                                       float *__restrict__ slabP32) {
+                                                       float *__restrict__ slabP32, int nx, int tx, int ty,
+                                                       float *__restrict__ tb32, double *__restrict__ tb64) {
     constexpr bool CPR = (VAR == CPTR_VARIANT_CPR);
     constexpr int NG = CPR ? B - 1 : B - 2;
     constexpr int NR = CPR ? 1 : 2;
     constexpr int NGX = NG > 0 ? NG : 1;
     const int lane = threadIdx.x;
     if (lane >= B * B) return;
+    const bool tiles = tb32 || tb64;
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    unsigned slots = 0;         // in-tile neighbour slots written for this cell
     double F[NGX][NR];
 #pragma unroll
     for (int k = 0; k < NG; ++k) {
@@ -396,6 +411,25 @@ __global__ void __launch_bounds__(64) k_decouple_apply(int n, const int *__restr
         if (c == ip) {
             if (slabP) slabP[(size_t)e * B + r] = out;
             if (slabP32) slabP32[(size_t)e * B + r] = (float)out;
+        }
+        if (tiles) {
+            // the BILU(0) sweeps' side array: the block of an in-tile
+            // neighbour (the row's first entry in that column)
+            const int k = tile_slot(i, ci[e], nx, tx, ty);
+            if (k >= 0 && !((slots >> k) & 1u)) {
+                slots |= 1u << k;
+                const size_t o = ((size_t)i * 4 + k) * B * B + lane;
+                if (tb32) tb32[o] = (float)out;
+                if (tb64) tb64[o] = out;
+            }
+        }
+    }
+    if (tiles) {
+        for (int k = 0; k < 4; ++k) {
+            if ((slots >> k) & 1u) continue;
+            const size_t o = ((size_t)i * 4 + k) * B * B + lane;
+            if (tb32) tb32[o] = 0.0f;
+            if (tb64) tb64[o] = 0.0;
         }
     }
     }
@@ -458,20 +492,21 @@ constexpr int DA_MAX_WAVES = 2048;
 
 void launch_decouple_apply(int variant, int n, int b, const int *rp, const int *ci, const double *A, int ip, int it,
                            const double *wp, const double *wt, const double *beta, double *abar, double *slabT,
-                           double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s) {
+                           double *slabP, float *abar32, float *slabT32, float *slabP32, hipStream_t s, int nx,
+                           int tx, int ty, float *tb32, double *tb64) {
     if (n == 0) return;
     const int grid = std::min(n, DA_MAX_WAVES);
 #define CASE(BB)                                                                                                  \
     case BB:                                                                                                      \
         if (variant == CPTR_VARIANT_CPR)                                                                          \
             hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPR>), dim3(grid), dim3(64), 0, s, n, rp, ci, A, \
-                               ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);              \
+                               ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32, nx, tx, ty, tb32, tb64);              \
         else if (variant == CPTR_VARIANT_CPTR)                                                                    \
             hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPTR>), dim3(grid), dim3(64), 0, s, n, rp, ci,   \
-                               A, ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);           \
+                               A, ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32, nx, tx, ty, tb32, tb64);           \
         else                                                                                                      \
             hipLaunchKernelGGL((k_decouple_apply<BB, CPTR_VARIANT_CPTR3>), dim3(grid), dim3(64), 0, s, n, rp, ci,  \
-                               A, ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32);           \
+                               A, ip, it, wp, wt, beta, abar, slabT, slabP, abar32, slabT32, slabP32, nx, tx, ty, tb32, tb64);           \
         break;
     switch (b) {
         CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
