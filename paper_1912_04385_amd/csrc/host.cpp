@@ -168,37 +168,75 @@ struct cptr_ctx {
 // Reads of device scalars go through small pinned host buffers: a copy into
 // pinned memory is one direct transfer, where pageable memory takes a staged
 // copy.  The buffers are kept for reuse until the process ends.
+// Host read slots: coherent pinned memory holding a sequence word and up
+// to PIN_DATA bytes, each with its device address (slots are reused, never
+// freed, across devices: coherent host memory is visible to every GPU)
+struct PinSlot {
+    unsigned char *h = nullptr;   // host address: [0, 8) sequence word, [8, 8 + PIN_DATA) data
+    unsigned char *d = nullptr;   // the same memory's device address
+};
 static std::mutex g_pin_mu;
-static std::vector<void *> g_pin_free;
-constexpr size_t PIN_BYTES = 64;
+static std::vector<PinSlot> g_pin_free;
+static std::atomic<unsigned long long> g_pin_seq{1};
+constexpr size_t PIN_DATA = 504;
+constexpr auto PIN_SPIN = std::chrono::milliseconds(20);   // then wait on the stream
 
-static void *pin_acquire() {
+static PinSlot pin_acquire() {
     {
         std::lock_guard<std::mutex> lk(g_pin_mu);
         if (!g_pin_free.empty()) {
-            void *p = g_pin_free.back();
+            PinSlot p = g_pin_free.back();
             g_pin_free.pop_back();
             return p;
         }
     }
-    void *p = nullptr;
-    CPTR_HIP(hipHostMalloc(&p, PIN_BYTES, hipHostMallocDefault));
+    PinSlot p;
+    void *h = nullptr, *d = nullptr;
+    CPTR_HIP(hipHostMalloc(&h, 8 + PIN_DATA, hipHostMallocCoherent));
+    const hipError_t e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(h);
+        CPTR_HIP(e);
+    }
+    p.h = (unsigned char *)h;
+    p.d = (unsigned char *)d;
+    __atomic_store_n((unsigned long long *)p.h, 0ULL, __ATOMIC_RELEASE);
     return p;
 }
 
-static void pin_release(void *p) {
+static void pin_release(PinSlot p) {
     std::lock_guard<std::mutex> lk(g_pin_mu);
     g_pin_free.push_back(p);
 }
 
-// copy `bytes` (<= PIN_BYTES) from device memory to host after the stream's work
+// copy `bytes` (<= PIN_DATA) from device memory to host after the stream's
+// work.  The device posts the bytes and a fresh sequence number into the
+// slot (post_to_host) and the host polls the number, which wakes it within
+// microseconds of the stream reaching the read; a read still pending after
+// PIN_SPIN waits on the stream instead (long queues, and the errors of
+// failed kernels, which the stream then reports).
 static void read_bytes(void *dst, const void *d, size_t bytes, hipStream_t s) {
-    void *h = pin_acquire();
-    hipError_t e = hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) std::memcpy(dst, h, bytes);
-    pin_release(h);
-    CPTR_HIP(e);
+    if (bytes > PIN_DATA) throw Error(CPTR_E_ARG, "host read larger than its slot");
+    PinSlot p = pin_acquire();
+    struct Release {
+        PinSlot p;
+        ~Release() { pin_release(p); }
+    } rel{p};
+    const unsigned long long seq = g_pin_seq.fetch_add(1);
+    unsigned long long *hseq = (unsigned long long *)p.h;
+    post_to_host(d, (int)bytes, p.d + 8, (unsigned long long *)p.d, seq, s);
+    const auto t0 = std::chrono::steady_clock::now();
+    unsigned it = 0;
+    while (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) != seq) {
+        if ((++it & 255u) == 0 && std::chrono::steady_clock::now() - t0 > PIN_SPIN) {
+            CPTR_HIP(hipStreamSynchronize(s));
+            if (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) != seq)
+                throw Error(CPTR_E_HIP, "device-to-host read not delivered");
+            break;
+        }
+        __builtin_ia32_pause();
+    }
+    std::memcpy(dst, p.h + 8, bytes);
 }
 
 template <class T>
@@ -1770,9 +1808,9 @@ static cptr_status run_gmres(cptr_ctx *c, cptr_result *res, double bnorm0) {
                                c->hinfo.p, s);
             kr_scale(N, c->w.p, c->scal.p, c->V.p + (size_t)(j + 1) * ld, s);
             c->mark(5);
-            CPTR_HIP(hipMemcpyAsync(c->hinfo_host, c->hinfo.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-            CPTR_HIP(hipStreamSynchronize(s));
+            read_bytes(c->hinfo_host, c->hinfo.p, 3 * sizeof(double), s);
             if (c->opt.timing) {
+                CPTR_HIP(hipEventSynchronize(c->tev[5]));
                 for (int q = 0; q < 5; ++q) {
                     float ms = 0.f;
                     CPTR_HIP(hipEventElapsedTime(&ms, c->tev[q], c->tev[q + 1]));

@@ -145,6 +145,10 @@ struct Hierarchy {
 // ---------------------------------------------------------------------------
 // k_common.hip
 void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t s);   // out[n] = total
+// d[0, bytes) to the host buffer hdata_dev (device address of coherent
+// pinned memory), then seq to *hseq_dev, after the stream's earlier work
+void post_to_host(const void *d, int bytes, void *hdata_dev, unsigned long long *hseq_dev, unsigned long long seq,
+                  hipStream_t s);
 void gather_ints(const int *a, const int *b, const int *c, int *out, hipStream_t s,
                  const int *d = nullptr);   // out[0..3]; null -> 0
 void fill_int(int *p, int v, size_t n, hipStream_t s);

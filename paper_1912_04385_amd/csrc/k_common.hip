@@ -221,6 +221,24 @@ void scan_exclusive(const int *in, int *out, int n, int *total_dev, hipStream_t 
     CPTR_CHECK_LAUNCH();
 }
 
+// Small device-to-host reads: one wavefront copies `bytes` into coherent
+// pinned host memory, then publishes `seq` beside them with a system-scope
+// release store (every lane's bytes are stored and acknowledged before it),
+// so the host can poll the sequence word instead of waiting on the stream.
+__global__ void __launch_bounds__(64) k_post_host(const unsigned char *d, int bytes, unsigned char *hdata,
+                                                  unsigned long long *hseq, unsigned long long seq) {
+    for (int k = threadIdx.x; k < bytes; k += 64) hdata[k] = d[k];
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(hseq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void post_to_host(const void *d, int bytes, void *hdata_dev, unsigned long long *hseq_dev, unsigned long long seq,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_post_host, dim3(1), dim3(64), 0, s, (const unsigned char *)d, bytes,
+                       (unsigned char *)hdata_dev, hseq_dev, seq);
+    CPTR_CHECK_LAUNCH();
+}
+
 // up to four device ints side by side, for one host read
 __global__ void k_gather_ints(const int *a, const int *b, const int *c, const int *d, int *out) {
     if (threadIdx.x == 0) {
