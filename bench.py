@@ -67,6 +67,29 @@ def load_traffic(nbytes_alg: int, name: str = "spmv_bsr8_c3_traffic.json"):
     return d.get("hbm_bytes_per_launch")
 
 
+def vcycle_bytes(sol, which: int, pre: int, post: int, t: int = 4) -> int:
+    """Algorithmic bytes of one V-cycle of hierarchy `which` (damped Jacobi,
+    the first pre-sweep fused with its residual, every further one with the
+    next residual, restriction by R = P^T, prolongation, post-sweeps; the
+    coarsest level's dense inverse applied in FP64): every operand counted
+    once per launch, t-byte values (4: FP32 preconditioner), 4-byte indices."""
+    nlev = sol.amg_levels(which)
+    sizes = [sol.amg_level_sizes(which, l) for l in range(nlev)]
+    tot = 0
+    for l, (n, nnz, pn) in enumerate(sizes):
+        if l == nlev - 1:
+            tot += n * n * 8 + 2 * n * t
+            break
+        nc = sizes[l + 1][0]
+        a_pass = (n + 1) * 4 + nnz * (4 + t)
+        tot += a_pass + 4 * n * t                                   # first sweep + residual
+        tot += max(0, pre - 1) * (a_pass + 6 * n * t)               # further sweeps + residual
+        tot += (nc + 1) * 4 + pn * (4 + t) + n * t + nc * t         # restriction
+        tot += (n + 1) * 4 + pn * (4 + t) + nc * t + 2 * n * t      # prolongation
+        tot += post * (a_pass + 4 * n * t)                          # post-sweeps
+    return tot
+
+
 def cpu_baseline(seconds_hint: float = 20.0, tile=(64, 8), sweeps: int = 2) -> dict:
     """The CPU FP64 oracle (as it stands) on a bounded sample of the same
     recipe: a 250 x 125-cell grid with the config-3 generator, plain FP64
@@ -556,6 +579,7 @@ def c5_headline(args, dev) -> int:
     rows = []
     spmv_ms = 0.0
     spmv_launches = 0
+    stage_ms = [0.0, 0.0]
     for k in range(K):
         if k > 0:
             tg = time.perf_counter()
@@ -575,6 +599,8 @@ def c5_headline(args, dev) -> int:
             if name == "learned":
                 spmv_ms += r["t_spmv_ms"]
                 spmv_launches += r["timed_steps"]
+                stage_ms[0] += r["t_stage1_ms"]
+                stage_ms[1] += r["t_stage2_ms"]
             row[name] = {"ms": round(dt * 1e3, 2), "its": r["iterations"], "restarts": r["restarts"],
                          "setup_ms": round(r["setup_ms"], 2), "solve_ms": round(r["solve_ms"], 2),
                          "reused": r["reused"], "rho_T": round(r["rho_T"], 4), "rho_P": round(r["rho_P"], 4),
@@ -584,6 +610,16 @@ def c5_headline(args, dev) -> int:
                                  rho_T_learned=round(r["rho_T_learned"], 4))
         rows.append(row)
         print(f"# system {k}: generated+copied in {gen_s:.1f} s; {row}", file=sys.stderr, flush=True)
+    # the V-cycles' bandwidth: algorithmic bytes of one V-cycle of each
+    # hierarchy (the learned leg's, on the last system) over the average time
+    # of its stage, which also holds the stage's input gather
+    vcyc = {}
+    for which, name in ((0, "temperature"), (1, "pressure")):
+        vb = vcycle_bytes(legs["learned"], which, args.sweeps, args.sweeps)
+        ms_app = stage_ms[which] / max(1, spmv_launches)
+        gbs = vb / (ms_app * 1e-3) / 1e9 if ms_app > 0 else 0.0
+        vcyc[name] = {"bytes_per_vcycle": vb, "stage_ms": round(ms_app, 4), "GBps": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4), "levels": legs["learned"].amg_levels(which)}
     for sol in legs.values():
         sol.close()
     del vals, rhs
@@ -618,6 +654,9 @@ def c5_headline(args, dev) -> int:
                                      f"tiles, AMG reuse while rho < 0.3",
                    "tol": 1e-8},
         "roofline": roofline,
+        "vcycle_roofline": dict(vcyc, note="FP32 V-cycles of the learned leg's stages (T first, then P): algorithmic "
+                                           "bytes of one V-cycle / the stage's average time (which also holds the "
+                                           "stage's input gather) / 8 TB/s"),
         "hbm_read_ceiling": ceiling,
         "classical": {"interpolation": "classical ext+i only, same reuse", "ms_per_step": round(ms["classical"], 2),
                       "solves_per_s": round(K / tot["classical"], 4)},

@@ -227,6 +227,13 @@ class Solver:
         _check(lib().cptr_amg_levels(self.ctx, which, ctypes.byref(n)))
         return n.value
 
+    def amg_level_sizes(self, which: int, level: int) -> tuple:
+        """(rows, operator nnz, P nnz) of one level (P nnz 0 on the coarsest)."""
+        nr, nnz, pn = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().cptr_amg_level_info(self.ctx, which, level, ctypes.byref(nr), ctypes.byref(nnz),
+                                         ctypes.byref(pn)))
+        return nr.value, nnz.value, pn.value
+
     def amg_level(self, which: int, level: int) -> dict:
         import numpy as np
         nr, nnz, pn = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -64,3 +64,21 @@ def test_cv_across_peclet_hand_worked():
     cv = bench.cv_across_peclet(rows)
     assert len(cv) == 1 and cv[0]["variant"] == "CPR"
     assert cv[0]["cv"] == 0.8911 and cv[0]["mean"] == 24.333
+
+
+def test_vcycle_bytes_hand_count():
+    """One V-cycle's algorithmic bytes on a two-level hierarchy counted by
+    hand: level 0 of 4 rows (10 entries, P with 5), 2 + 2 sweeps in FP32,
+    then the dense 2 x 2 inverse of the coarsest level in FP64."""
+    class Fake:
+        def amg_levels(self, which):
+            return 2
+
+        def amg_level_sizes(self, which, level):
+            return [(4, 10, 5), (2, 4, 0)][level]
+
+    a_pass = 5 * 4 + 10 * 8
+    level0 = ((a_pass + 4 * 4 * 4) + (a_pass + 6 * 4 * 4) + (3 * 4 + 5 * 8 + 4 * 4 + 2 * 4)
+              + (5 * 4 + 5 * 8 + 2 * 4 + 2 * 4 * 4) + 2 * (a_pass + 4 * 4 * 4))
+    assert level0 == 864
+    assert bench.vcycle_bytes(Fake(), 0, 2, 2) == 864 + 2 * 2 * 8 + 2 * 2 * 4
