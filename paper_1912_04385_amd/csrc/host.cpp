@@ -131,6 +131,10 @@ struct cptr_ctx {
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_dec = nullptr, ev_side[3] = {nullptr, nullptr, nullptr};
     Builder bld[3];
+    // the reuse trial of a hierarchy whose last trial failed runs on its own
+    // stream beside the speculative rebuild
+    hipStream_t side_trial = nullptr;
+    Builder bld_trial;
     double tacc[5] = {};
     int tsteps = 0;
     // host wall-clock phases of the last setup: scaling + extraction,
@@ -154,6 +158,13 @@ struct cptr_ctx {
                 (void)hipStreamDestroy(side[k]);
             }
             if (ev_side[k]) (void)hipEventDestroy(ev_side[k]);
+        }
+        if (side_trial) {
+            (void)hipStreamSynchronize(side_trial);
+            bld_trial.~Builder();
+            new (&bld_trial) Builder();
+            pool_trim(side_trial);
+            (void)hipStreamDestroy(side_trial);
         }
         if (ev_dec) (void)hipEventDestroy(ev_dec);
         if (hinfo_host) (void)hipHostFree(hinfo_host);
@@ -1372,8 +1383,7 @@ static double conv_factor(cptr_ctx *c, Hierarchy &h, int cycles, uint64_t seed, 
     kr_norm2_partial(n, e.p, part.p, nblk, s);
     kr_reduce(part.p, nblk, 1, nrm.p + 1, s);
     double v[2];
-    CPTR_HIP(hipMemcpyAsync(v, nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    CPTR_HIP(hipStreamSynchronize(s));
+    read_bytes(v, nrm.p, 2 * sizeof(double), s);
     if (!(v[0] > 0.0)) return 0.0;
     return std::pow(std::sqrt(v[1]) / std::sqrt(v[0]), 1.0 / cycles);
 }
@@ -1414,7 +1424,7 @@ static void validate_options(const cptr_options &o) {
 // interpolation requested, the classical and the learned hierarchies are both
 // built and the learned one is kept only if its measured V-cycle convergence
 // factor is lower (CPTR_INTERP_LEARNED_FORCED keeps it without the judge).
-static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<double> *own) {
+static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<double> *own, Hierarchy &dst) {
     const bool learned = (k == 0) && c->opt.variant == CPTR_VARIANT_CPTR3 && c->have_mlp &&
                          c->opt.t_interp != CPTR_INTERP_CLASSICAL;
     if (k == 0) {
@@ -1422,7 +1432,7 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
         c->rho_cls = c->rho_lrn = -1.0;
     }
     if (!learned) {
-        build_hierarchy(&B, c->H[k], vals, own);
+        build_hierarchy(&B, dst, vals, own);
         return;
     }
     const bool judge = (c->opt.t_interp == CPTR_INTERP_LEARNED);
@@ -1461,8 +1471,8 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     std::exception_ptr err1;
     double rc = -1.0;
     try {
-        build_hierarchy(&B, c->H[k], vals, own, &feed);
-        if (judge && c->H[k].L.size() > 1) rc = conv_factor(c, c->H[k], c->opt.judge_cycles, RHO_SEED, B.stream, fp32);
+        build_hierarchy(&B, dst, vals, own, &feed);
+        if (judge && dst.L.size() > 1) rc = conv_factor(c, dst, c->opt.judge_cycles, RHO_SEED, B.stream, fp32);
     } catch (...) {
         err1 = std::current_exception();
         feed.close();
@@ -1470,9 +1480,9 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     t2.join();
     if (err1) std::rethrow_exception(err1);
     if (err) std::rethrow_exception(err);
-    if (c->H[k].L.size() < 2 || hl.L.size() < 2) return;   // a single level: no interpolation to learn
+    if (dst.L.size() < 2 || hl.L.size() < 2) return;   // a single level: no interpolation to learn
     if (!judge || rl < rc) {
-        c->H[k] = std::move(hl);
+        dst = std::move(hl);
         c->used_learned = 1;
     }
     c->rho_cls = rc;
@@ -1607,7 +1617,64 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                 CPTR_HIP(hipStreamWaitEvent(B.stream, c->ev_dec, 0));
                 // the fine level takes over the buffer of its values
                 DBuf<double> *own = k == 0 ? (sys ? &c->ee_v : &c->ctt) : &c->bpp;
-                if (refresh[k]) {
+                if (refresh[k] && c->backoff[k] > 1) {
+                    // the hierarchy's last trial failed: its trial (refresh
+                    // and measurement, on the trial stream and a thread of
+                    // its own) runs beside a speculative rebuild, and the
+                    // decision then keeps one of the two -- the same choice,
+                    // and the same hierarchies, as trying first
+                    Builder &BT = c->bld_trial;
+                    BT.stream = c->side_trial;
+                    BT.opt = B.opt;
+                    BT.n = B.n;
+                    BT.nnzb = B.nnzb;
+                    BT.rp.p = B.rp.p;
+                    BT.ci.p = B.ci.p;
+                    BT.parts = B.parts;
+                    BT.aux = nullptr;
+                    BT.device = c->device;
+                    BT.gx = B.gx;
+                    BT.gy = B.gy;
+                    const int prev_used = c->used_learned;
+                    double rho_t = -1.0;
+                    std::exception_ptr terr;
+                    std::thread tt([c, k, fp32, &BT, &svals, &rho_t, &terr]() {
+                        try {
+                            CPTR_HIP(hipSetDevice(c->device));
+                            StreamScope scope2(BT.stream);
+                            if (!BT.flag.p) {
+                                BT.flag.alloc(4);
+                                fill_int(BT.flag.p, 0, 1, BT.stream);
+                            }
+                            CPTR_HIP(hipStreamWaitEvent(BT.stream, c->ev_dec, 0));
+                            refresh_hierarchy(&BT, c->H[k], svals[k], nullptr);
+                            rho_t = conv_factor(c, c->H[k], RHO_CYCLES, RHO_SEED, BT.stream, fp32);
+                        } catch (...) {
+                            terr = std::current_exception();
+                        }
+                    });
+                    struct Join {
+                        std::thread &t;
+                        ~Join() { if (t.joinable()) t.join(); }
+                    } join_tt{tt};
+                    Hierarchy hn;
+                    full_build(c, B, k, svals[k], own, hn);
+                    tt.join();
+                    if (terr) std::rethrow_exception(terr);
+                    c->rho[k] = rho_t;
+                    if (rho_t < c->opt.reuse_rho_max) {
+                        kept.fetch_or(1 << k);
+                        c->backoff[k] = 1;
+                        if (k == 0) {
+                            c->used_learned = prev_used;
+                            c->rho_cls = c->rho_lrn = -1.0;
+                        }
+                    } else {
+                        c->skip_left[k] = c->backoff[k];
+                        c->backoff[k] = std::min(2 * c->backoff[k], MAX_REUSE_BACKOFF);
+                        c->H[k] = std::move(hn);
+                    }
+                } else if (refresh[k]) {
                     // reuse decision: keep the refreshed hierarchy while its
                     // measured V-cycle convergence factor stays below the
                     // threshold, else build it anew
@@ -1624,10 +1691,10 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                         c->backoff[k] = std::min(2 * c->backoff[k], MAX_REUSE_BACKOFF);
                         // hand the values back before the old hierarchy goes
                         *own = std::move(c->H[k].L[0].A.v);
-                        full_build(c, B, k, svals[k], own);
+                        full_build(c, B, k, svals[k], own, c->H[k]);
                     }
                 } else {
-                    full_build(c, B, k, svals[k], own);
+                    full_build(c, B, k, svals[k], own, c->H[k]);
                 }
                 CPTR_HIP(hipEventRecord(c->ev_side[k], B.stream));
                 c->tph[1 + k] = ms_since(t_hier);
@@ -1946,6 +2013,7 @@ cptr_status cptr_create(cptr_ctx **out, int32_t dev, void *stream, const cptr_op
         CPTR_HIP(hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));   // default priority
         CPTR_HIP(hipEventCreateWithFlags(&c->ev_side[k], hipEventDisableTiming));
     }
+    CPTR_HIP(hipStreamCreateWithFlags(&c->side_trial, hipStreamNonBlocking));   // default priority
     CPTR_HIP(hipStreamSynchronize(c->stream));
     *out = c.release();
     return CPTR_OK;
