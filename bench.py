@@ -67,12 +67,15 @@ def load_traffic(nbytes_alg: int, name: str = "spmv_bsr8_c3_traffic.json"):
     return d.get("hbm_bytes_per_launch")
 
 
-def vcycle_bytes(sol, which: int, pre: int, post: int, t: int = 4) -> int:
+def vcycle_bytes(sol, which: int, pre: int, post: int, t: int = 4, fine_planes: bool = False) -> int:
     """Algorithmic bytes of one V-cycle of hierarchy `which` (damped Jacobi,
     the first pre-sweep fused with its residual, every further one with the
     next residual, restriction by R = P^T, prolongation, post-sweeps; the
     coarsest level's dense inverse applied in FP64): every operand counted
-    once per launch, t-byte values (4: FP32 preconditioner), 4-byte indices."""
+    once per launch, t-byte values (4: FP32 preconditioner), 4-byte indices.
+    fine_planes: the fine level's sweeps read the operator as five coefficient
+    planes (5 n values, no indices), as the FP32 sweeps of a scalar stage on
+    the 5-point grid pattern do."""
     nlev = sol.amg_levels(which)
     sizes = [sol.amg_level_sizes(which, l) for l in range(nlev)]
     tot = 0
@@ -81,7 +84,7 @@ def vcycle_bytes(sol, which: int, pre: int, post: int, t: int = 4) -> int:
             tot += n * n * 8 + 2 * n * t
             break
         nc = sizes[l + 1][0]
-        a_pass = (n + 1) * 4 + nnz * (4 + t)
+        a_pass = 5 * n * t if (fine_planes and l == 0) else (n + 1) * 4 + nnz * (4 + t)
         tot += a_pass + 4 * n * t                                   # first sweep + residual
         tot += max(0, pre - 1) * (a_pass + 6 * n * t)               # further sweeps + residual
         tot += (nc + 1) * 4 + pn * (4 + t) + n * t + nc * t         # restriction
@@ -612,10 +615,11 @@ def c5_headline(args, dev) -> int:
         print(f"# system {k}: generated+copied in {gen_s:.1f} s; {row}", file=sys.stderr, flush=True)
     # the V-cycles' bandwidth: algorithmic bytes of one V-cycle of each
     # hierarchy (the learned leg's, on the last system) over the average time
-    # of its stage, which also holds the stage's input gather
+    # of its stage, which also holds the stage's input gather; the fine
+    # levels (scalar operators on the 5-point grid, FP32) sweep five planes
     vcyc = {}
     for which, name in ((0, "temperature"), (1, "pressure")):
-        vb = vcycle_bytes(legs["learned"], which, args.sweeps, args.sweeps)
+        vb = vcycle_bytes(legs["learned"], which, args.sweeps, args.sweeps, fine_planes=True)
         ms_app = stage_ms[which] / max(1, spmv_launches)
         gbs = vb / (ms_app * 1e-3) / 1e9 if ms_app > 0 else 0.0
         vcyc[name] = {"bytes_per_vcycle": vb, "stage_ms": round(ms_app, 4), "GBps": round(gbs, 1),
@@ -655,8 +659,9 @@ def c5_headline(args, dev) -> int:
                    "tol": 1e-8},
         "roofline": roofline,
         "vcycle_roofline": dict(vcyc, note="FP32 V-cycles of the learned leg's stages (T first, then P): algorithmic "
-                                           "bytes of one V-cycle / the stage's average time (which also holds the "
-                                           "stage's input gather) / 8 TB/s"),
+                                           "bytes of one V-cycle (the fine level's sweeps on five coefficient "
+                                           "planes) / the stage's average time (which also holds the stage's input "
+                                           "gather) / 8 TB/s"),
         "hbm_read_ceiling": ceiling,
         "classical": {"interpolation": "classical ext+i only, same reuse", "ms_per_step": round(ms["classical"], 2),
                       "solves_per_s": round(K / tot["classical"], 4)},

@@ -56,6 +56,7 @@ struct Builder {
     std::vector<int> parts;
     Builder *aux = nullptr;
     int gx = 0, gy = 0;          // grid shape of the cells (0: none), for the exact block-tridiagonal solves
+    int ell_nx = 0;              // > 0: the fine level has the 5-point pattern of an ell_nx-wide grid
     int device = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     Builder() = default;
@@ -76,6 +77,7 @@ struct cptr_ctx {
     // problem
     int n = 0, b = 0, nnzb = 0, ip = 0, it = 1, nx = 0, ny = 0;
     bool ready = false;
+    bool ell5 = false;   // the block pattern is the 5-point stencil of the nx x ny grid
     DBuf<int> rp, ci, tpos;
     DBuf<double> abar, wp, wt, beta, slabT, slabP;
     DBuf<float> abar32, slabT32, slabP32;
@@ -507,6 +509,14 @@ static void hierarchy_fp32(Builder *c, Hierarchy &h) {
         }
     }
     to_float_multi(jobs.data(), (int)jobs.size(), c->stream);
+    // the fine level's five-plane copy for the FP32 sweeps (a scalar stage on
+    // the 5-point grid pattern: the level has one row per cell)
+    if (c->ell_nx > 0 && !h.L.empty() && h.L[0].A.n == c->n && c->n % c->ell_nx == 0) {
+        Level &L0 = h.L[0];
+        L0.ell32.alloc((size_t)5 * L0.A.n);
+        vc_ell5_fill(L0.A.n, c->ell_nx, L0.A.rp, L0.A.ci, L0.A.v32.p, L0.ell32.p, c->stream);
+        L0.ell_nx = c->ell_nx;
+    }
 }
 
 // Build the hierarchy of a scalar operator whose level-0 pattern is the BSR
@@ -1206,6 +1216,32 @@ static void cheb_smooth(const Level &L, const T *v, const T *dinv, const T *b, T
     }
 }
 
+// the level's Jacobi sweeps: on the five planes when the level has them
+// (FP32 fine level on the 5-point grid pattern), else on its CSR rows
+template <class T>
+static void lv_presmooth(const Level &L, const T *v, const T *dinv, T omega, const T *b, T *x, T *r, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (L.ell_nx > 0) return vc_ell5_presmooth_residual(L.A.n, L.ell_nx, L.ell32.p, dinv, omega, b, x, r, s);
+    }
+    vc_presmooth_residual<T>(L.A.n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, r, s);
+}
+template <class T>
+static void lv_sweep(const Level &L, const T *v, const T *dinv, T omega, const T *b, const T *x, const T *r, T *xout,
+                     T *rout, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (L.ell_nx > 0) return vc_ell5_sweep_residual(L.A.n, L.ell_nx, L.ell32.p, dinv, omega, b, x, r, xout, rout, s);
+    }
+    vc_sweep_residual<T>(L.A.n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, r, xout, rout, s);
+}
+template <class T>
+static void lv_smooth(const Level &L, const T *v, const T *dinv, T omega, const T *b, const T *xin, T *xout,
+                      hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (L.ell_nx > 0) return vc_ell5_smooth(L.A.n, L.ell_nx, L.ell32.p, dinv, omega, b, xin, xout, s);
+    }
+    vc_smooth<T>(L.A.n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, xin, xout, s);
+}
+
 template <class T>
 static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     Level &L = h.L[lvl];
@@ -1249,10 +1285,10 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     T *xa = X, *ra = spare[0];
     const T *rres = b;   // what is restricted
     if (o.pre_sweeps >= 1) {
-        vc_presmooth_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, xa, ra, s);
+        lv_presmooth<T>(L, v, dinv, omega, b, xa, ra, s);
         T *xb = spare[1], *rb = spare[2];
         for (int k = 1; k < o.pre_sweeps; ++k) {
-            vc_sweep_residual<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, xa, ra, xb, rb, s);
+            lv_sweep<T>(L, v, dinv, omega, b, xa, ra, xb, rb, s);
             std::swap(xa, xb);
             std::swap(ra, rb);
         }
@@ -1270,7 +1306,7 @@ static T *vcycle(cptr_ctx *c, Hierarchy &h, int lvl, hipStream_t s) {
     T *oth = (cur == X) ? Y : X;
     vc_prolong_to<T>(n, L.P.nnz, L.P.rp, L.P.ci, Prec<T>::v(L.P), xc, xa, cur, s);
     for (int k = 0; k < o.post_sweeps; ++k) {
-        vc_smooth<T>(n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, cur, oth, s);
+        lv_smooth<T>(L, v, dinv, omega, b, cur, oth, s);
         std::swap(cur, oth);
     }
     return X;
@@ -1449,6 +1485,7 @@ static void full_build(cptr_ctx *c, Builder &B, int k, const double *vals, DBuf<
     B2.n = B.n;
     B2.gx = B.gx;
     B2.gy = B.gy;
+    B2.ell_nx = B.ell_nx;
     B2.nnzb = B.nnzb;
     B2.rp.p = B.rp.p;
     B2.ci.p = B.ci.p;
@@ -1593,6 +1630,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
         B.device = c->device;
         B.gx = c->nx;
         B.gy = c->ny;
+        B.ell_nx = (!ee && c->ell5) ? c->nx : 0;
         if (ee) {
             B.parts = {n, n};
             // the pressure builder is idle in the two-stage scheme: it
@@ -1635,6 +1673,7 @@ static void do_setup_values(cptr_ctx *c, const double *vals, bool reuse) {
                     BT.device = c->device;
                     BT.gx = B.gx;
                     BT.gy = B.gy;
+                    BT.ell_nx = B.ell_nx;
                     const int prev_used = c->used_learned;
                     double rho_t = -1.0;
                     std::exception_ptr terr;
@@ -2061,7 +2100,9 @@ cptr_status cptr_setup(cptr_ctx *c, int32_t n, int32_t b, int32_t nnzb, const in
     check_pattern(n, c->rp.p, c->ci.p, c->flag.p, s);
     c->tpos.alloc(nnzb);
     transpose_index(n, c->rp.p, c->ci.p, c->tpos.p, c->flag.p, s);
+    if (grid && nx >= 2) check_grid5(n, nx, c->rp.p, c->ci.p, c->flag.p, s);
     int f = read_flag_and_clear(c);
+    c->ell5 = grid && nx >= 2 && !(f & 512);
     if (f & 1) throw Error(CPTR_E_ARG, "block column index out of range");
     if (f & 2) throw Error(CPTR_E_ARG, "block columns must ascend within each row");
     if (f & 4) throw Error(CPTR_E_ARG, "missing diagonal block");

@@ -301,6 +301,20 @@ void check_pattern(int n, const int *rp, const int *ci, int *flag_dev, hipStream
     CPTR_CHECK_LAUNCH();
 }
 
+__global__ void k_check_grid5(int n, int nx, const int *rp, const int *ci, int *flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int d = ci[e] - i;
+        if (d != -nx && d != -1 && d != 0 && d != 1 && d != nx) { atomicOr(flag, 512); return; }
+    }
+}
+
+void check_grid5(int n, int nx, const int *rp, const int *ci, int *flag_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_grid5, dim3((n + 255) / 256), dim3(256), 0, s, n, nx, rp, ci, flag_dev);
+    CPTR_CHECK_LAUNCH();
+}
+
 // tpos[e] = position of entry (j, i) for e = (i, j); flag bit 8 when missing
 __global__ void k_transpose_index(int n, const int *rp, const int *ci, int *tpos, int *flag) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -138,6 +138,107 @@ static void csr_op(int n, int nnz, const int *rp, const int *ci, const T *v, con
     CPTR_CHECK_LAUNCH();
 }
 
+// The fine level of a scalar stage whose pattern is the 5-point stencil of an
+// nx-wide grid, stored as five coefficient planes ell[k*n + i] for the
+// columns i - nx, i - 1, i, i + 1, i + nx (k = 0..4; zero where row i has no
+// such entry): the level's sweeps read them coalesced and need no row
+// pointers or column indices.  The row sum takes the five terms in column
+// order, as the CSR row loop takes a row's (ascending) entries, and a missing
+// entry adds an exact zero, so the results are those of k_csr_op.
+__global__ void k_ell5_fill(int n, int nx, const int *__restrict__ rp, const int *__restrict__ ci,
+                            const float *__restrict__ v, float *__restrict__ ell) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float c[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int d = ci[e] - i;   // one of -nx, -1, 0, 1, nx (checked at setup)
+        const int k = (d == -nx) ? 0 : (d == -1) ? 1 : (d == 0) ? 2 : (d == 1) ? 3 : 4;
+        c[k] = v[e];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) ell[(size_t)k * n + i] = c[k];
+}
+
+void vc_ell5_fill(int n, int nx, const int *rp, const int *ci, const float *v, float *ell, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_ell5_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, n, nx, rp, ci, v, ell);
+    CPTR_CHECK_LAUNCH();
+}
+
+// OP_PRESMOOTH, OP_SWEEP_RESID and OP_SMOOTH on the five planes (operands as
+// in k_csr_op; a missing entry's column is clamped into range and its zero
+// coefficient multiplies a finite value)
+template <int OP>
+__global__ void __launch_bounds__(256) k_ell5_op(int n, int nx, const float *__restrict__ ell,
+                                                 const float *__restrict__ xs, const float *__restrict__ dinv,
+                                                 float omega, const float *__restrict__ b, const float *xin,
+                                                 float *xout, float *__restrict__ rout) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int off[5] = {-nx, -1, 0, 1, nx};
+    float vv[5], o1[5], o2[5], o3[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int jr = i + off[q];
+        const int j = jr < 0 ? 0 : (jr >= n ? n - 1 : jr);
+        vv[q] = ell[(size_t)q * n + i];
+        if constexpr (OP == OP_PRESMOOTH) {
+            o1[q] = dinv[j];
+            o2[q] = b[j];
+        } else if constexpr (OP == OP_SWEEP_RESID) {
+            o1[q] = xin[j];
+            o2[q] = dinv[j];
+            o3[q] = xs[j];
+        } else {
+            o1[q] = xs[j];
+        }
+    }
+    float acc = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        if constexpr (OP == OP_PRESMOOTH)
+            acc += vv[q] * (omega * o1[q] * o2[q]);
+        else if constexpr (OP == OP_SWEEP_RESID)
+            acc += vv[q] * (o1[q] + omega * o2[q] * o3[q]);
+        else
+            acc += vv[q] * o1[q];
+    }
+    if constexpr (OP == OP_SMOOTH) {
+        xout[i] = xin[i] + omega * dinv[i] * (b[i] - acc);
+    } else if constexpr (OP == OP_PRESMOOTH) {
+        const float bi = b[i];
+        xout[i] = omega * dinv[i] * bi;
+        rout[i] = bi - acc;
+    } else {
+        xout[i] = xin[i] + omega * dinv[i] * xs[i];
+        rout[i] = b[i] - acc;
+    }
+}
+
+template <int OP>
+static void ell5_op(int n, int nx, const float *ell, const float *xs, const float *dinv, float omega, const float *b,
+                    const float *xin, float *xout, float *rout, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_ell5_op<OP>), dim3(nblocks(n, 256)), dim3(256), 0, st, n, nx, ell, xs, dinv, omega, b, xin,
+                       xout, rout);
+    CPTR_CHECK_LAUNCH();
+}
+
+void vc_ell5_presmooth_residual(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
+                                float *x, float *r, hipStream_t st) {
+    ell5_op<OP_PRESMOOTH>(n, nx, ell, nullptr, dinv, omega, b, nullptr, x, r, st);
+}
+
+void vc_ell5_sweep_residual(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
+                            const float *x, const float *r, float *xout, float *rout, hipStream_t st) {
+    ell5_op<OP_SWEEP_RESID>(n, nx, ell, r, dinv, omega, b, x, xout, rout, st);
+}
+
+void vc_ell5_smooth(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
+                    const float *xin, float *xout, hipStream_t st) {
+    ell5_op<OP_SMOOTH>(n, nx, ell, xin, dinv, omega, b, xin, xout, nullptr, st);
+}
+
 // first Jacobi sweep from a zero guess fused with the residual:
 //   x_i = omega dinv_i b_i,   r_i = b_i - sum_j a_ij (omega dinv_j b_j)
 template <class T>

@@ -82,3 +82,7 @@ def test_vcycle_bytes_hand_count():
               + (5 * 4 + 5 * 8 + 2 * 4 + 2 * 4 * 4) + 2 * (a_pass + 4 * 4 * 4))
     assert level0 == 864
     assert bench.vcycle_bytes(Fake(), 0, 2, 2) == 864 + 2 * 2 * 8 + 2 * 2 * 4
+    # the fine level's four sweeps on five planes: 5 x 4 rows x 4 bytes
+    # instead of 5 row pointers and 10 (index, value) pairs per pass
+    planes = 864 - 4 * a_pass + 4 * (5 * 4 * 4)
+    assert bench.vcycle_bytes(Fake(), 0, 2, 2, fine_planes=True) == planes + 2 * 2 * 8 + 2 * 2 * 4

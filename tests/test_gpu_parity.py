@@ -407,3 +407,33 @@ def test_fp32_preconditioner_variants(variant, last, order, tile):
 def test_fp32_needs_fgmres():
     with pytest.raises(cptr.CptrError):
         cptr.Solver(precond_precision=cptr.FP32, krylov=cptr.GMRES)
+
+
+def test_fp32_fine_level_planes_match_csr():
+    """The FP32 sweeps of a scalar stage's fine level on five coefficient
+    planes (a setup given the grid shape, whose pattern is the 5-point
+    stencil) give the CSR row kernels' results (the same system set up
+    without the grid shape) bit for bit, in preconditioner applications, in
+    the FP32 convergence factors and in a whole solve."""
+    print("case fine-level planes", flush=True)
+    s = tiny(64, 24, 8, peclet=5.0, seed=11)
+    kw = dict(krylov=cptr.FGMRES, precond_precision=cptr.FP32, last_stage=cptr.LAST_BJACOBI, amg_max_coarse=40)
+    rp, ci = torch.from_numpy(s.row_ptr), torch.from_numpy(s.col_idx)
+    vals = torch.from_numpy(s.vals.reshape(-1))
+    grid, flat = cptr.Solver(**kw), cptr.Solver(**kw)
+    try:
+        grid.setup(rp, ci, vals, 0, 1, s.nx, s.ny)
+        flat.setup(rp, ci, vals, 0, 1, 0, 0)
+        assert grid.amg_levels(0) > 1 and grid.amg_levels(1) > 1
+        rng = np.random.default_rng(12)
+        for _ in range(2):
+            r = _t(rng.standard_normal(s.n * s.b))
+            assert torch.equal(grid.precond_apply(r), flat.precond_apply(r))
+        for which in (0, 1):
+            assert grid.conv_factor(which, 6, 0) == flat.conv_factor(which, 6, 0)
+        xg, rg = grid.solve(_t(s.rhs))
+        xf, rf = flat.solve(_t(s.rhs))
+        assert rg["iterations"] == rf["iterations"] and torch.equal(xg, xf)
+    finally:
+        grid.close()
+        flat.close()
