@@ -493,8 +493,26 @@ static void coarse_inverse(Builder *c, Hierarchy &h) {
 }
 
 // FP32 copies of every level's operator, smoother diagonal and transfer operators
+// the fine level's five-plane copy for the sweeps in the preconditioner's
+// precision (a scalar stage on the 5-point grid pattern: one row per cell)
+static void fine_planes(Builder *c, Hierarchy &h) {
+    if (c->ell_nx <= 0 || h.L.empty() || h.L[0].A.n != c->n || c->n % c->ell_nx != 0) return;
+    Level &L0 = h.L[0];
+    if (c->opt.precond_precision == CPTR_FP32) {
+        L0.ell32.alloc((size_t)5 * L0.A.n);
+        vc_ell5_fill<float>(L0.A.n, c->ell_nx, L0.A.rp, L0.A.ci, L0.A.v32.p, L0.ell32.p, c->stream);
+    } else {
+        L0.ell64.alloc((size_t)5 * L0.A.n);
+        vc_ell5_fill<double>(L0.A.n, c->ell_nx, L0.A.rp, L0.A.ci, L0.A.v.p, L0.ell64.p, c->stream);
+    }
+    L0.ell_nx = c->ell_nx;
+}
+
 static void hierarchy_fp32(Builder *c, Hierarchy &h) {
-    if (c->opt.precond_precision != CPTR_FP32) return;
+    if (c->opt.precond_precision != CPTR_FP32) {
+        fine_planes(c, h);
+        return;
+    }
     std::vector<ToFloatJob> jobs;
     for (auto &L : h.L) {
         L.A.v32.alloc((size_t)L.A.nnz + 1);
@@ -509,14 +527,7 @@ static void hierarchy_fp32(Builder *c, Hierarchy &h) {
         }
     }
     to_float_multi(jobs.data(), (int)jobs.size(), c->stream);
-    // the fine level's five-plane copy for the FP32 sweeps (a scalar stage on
-    // the 5-point grid pattern: the level has one row per cell)
-    if (c->ell_nx > 0 && !h.L.empty() && h.L[0].A.n == c->n && c->n % c->ell_nx == 0) {
-        Level &L0 = h.L[0];
-        L0.ell32.alloc((size_t)5 * L0.A.n);
-        vc_ell5_fill(L0.A.n, c->ell_nx, L0.A.rp, L0.A.ci, L0.A.v32.p, L0.ell32.p, c->stream);
-        L0.ell_nx = c->ell_nx;
-    }
+    fine_planes(c, h);
 }
 
 // Build the hierarchy of a scalar operator whose level-0 pattern is the BSR
@@ -1216,29 +1227,31 @@ static void cheb_smooth(const Level &L, const T *v, const T *dinv, const T *b, T
     }
 }
 
-// the level's Jacobi sweeps: on the five planes when the level has them
-// (FP32 fine level on the 5-point grid pattern), else on its CSR rows
+// the level's five planes in precision T (null when the level has none:
+// the sweeps then run on its CSR rows)
+template <class T>
+static const T *planes(const Level &L) {
+    if (L.ell_nx <= 0) return nullptr;
+    if constexpr (std::is_same<T, float>::value) return L.ell32.p; else return L.ell64.p;
+}
+// the level's Jacobi sweeps: on the five planes when the level has them in
+// this precision (fine level on the 5-point grid pattern), else on its CSR rows
 template <class T>
 static void lv_presmooth(const Level &L, const T *v, const T *dinv, T omega, const T *b, T *x, T *r, hipStream_t s) {
-    if constexpr (std::is_same<T, float>::value) {
-        if (L.ell_nx > 0) return vc_ell5_presmooth_residual(L.A.n, L.ell_nx, L.ell32.p, dinv, omega, b, x, r, s);
-    }
+    if (const T *e = planes<T>(L)) return vc_ell5_presmooth_residual<T>(L.A.n, L.ell_nx, e, dinv, omega, b, x, r, s);
     vc_presmooth_residual<T>(L.A.n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, r, s);
 }
 template <class T>
 static void lv_sweep(const Level &L, const T *v, const T *dinv, T omega, const T *b, const T *x, const T *r, T *xout,
                      T *rout, hipStream_t s) {
-    if constexpr (std::is_same<T, float>::value) {
-        if (L.ell_nx > 0) return vc_ell5_sweep_residual(L.A.n, L.ell_nx, L.ell32.p, dinv, omega, b, x, r, xout, rout, s);
-    }
+    if (const T *e = planes<T>(L))
+        return vc_ell5_sweep_residual<T>(L.A.n, L.ell_nx, e, dinv, omega, b, x, r, xout, rout, s);
     vc_sweep_residual<T>(L.A.n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, x, r, xout, rout, s);
 }
 template <class T>
 static void lv_smooth(const Level &L, const T *v, const T *dinv, T omega, const T *b, const T *xin, T *xout,
                       hipStream_t s) {
-    if constexpr (std::is_same<T, float>::value) {
-        if (L.ell_nx > 0) return vc_ell5_smooth(L.A.n, L.ell_nx, L.ell32.p, dinv, omega, b, xin, xout, s);
-    }
+    if (const T *e = planes<T>(L)) return vc_ell5_smooth<T>(L.A.n, L.ell_nx, e, dinv, omega, b, xin, xout, s);
     vc_smooth<T>(L.A.n, L.A.nnz, L.A.rp, L.A.ci, v, dinv, omega, b, xin, xout, s);
 }
 

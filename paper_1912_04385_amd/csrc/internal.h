@@ -108,9 +108,11 @@ struct Level {
     bool ap_narrow = false; // A P's rows fit the register kernel (A rows <= 5, P rows <= 4)
     DBuf<double> dinv;      // 1 / smoothing diagonal
     DBuf<float> dinv32;
-    // FP32 five-plane copy of A (vc_ell5_fill) when this is the fine level of
-    // a scalar stage on the 5-point pattern of an ell_nx-wide grid (0: none)
+    // five-plane copy of A (vc_ell5_fill) in the preconditioner's precision
+    // when this is the fine level of a scalar stage on the 5-point pattern of
+    // an ell_nx-wide grid (0: none)
     DBuf<float> ell32;
+    DBuf<double> ell64;
     int ell_nx = 0;
     DBuf<int> cf;           // 1 = C, 0 = F (not on the coarsest level)
     double lam_max = 0.0;   // Gershgorin bound of the spectrum of D^{-1} A (Chebyshev smoother)
@@ -271,14 +273,18 @@ void vc_smooth(int n, int nnz, const int *rp, const int *ci, const T *v, const T
                const T *xin, T *xout, hipStream_t st);
 // the fine level of a scalar stage on the 5-point pattern of an nx-wide grid
 // as five coefficient planes (columns i - nx, i - 1, i, i + 1, i + nx), and
-// the FP32 sweeps on them (same results as the CSR kernels)
-void vc_ell5_fill(int n, int nx, const int *rp, const int *ci, const float *v, float *ell, hipStream_t st);
-void vc_ell5_presmooth_residual(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
-                                float *x, float *r, hipStream_t st);
-void vc_ell5_sweep_residual(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
-                            const float *x, const float *r, float *xout, float *rout, hipStream_t st);
-void vc_ell5_smooth(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
-                    const float *xin, float *xout, hipStream_t st);
+// the Jacobi sweeps on them (same results as the CSR kernels)
+template <class T>
+void vc_ell5_fill(int n, int nx, const int *rp, const int *ci, const T *v, T *ell, hipStream_t st);
+template <class T>
+void vc_ell5_presmooth_residual(int n, int nx, const T *ell, const T *dinv, T omega, const T *b, T *x, T *r,
+                                hipStream_t st);
+template <class T>
+void vc_ell5_sweep_residual(int n, int nx, const T *ell, const T *dinv, T omega, const T *b, const T *x, const T *r,
+                            T *xout, T *rout, hipStream_t st);
+template <class T>
+void vc_ell5_smooth(int n, int nx, const T *ell, const T *dinv, T omega, const T *b, const T *xin, T *xout,
+                    hipStream_t st);
 // flag bit 512 when some entry of the n-row pattern lies outside the 5-point
 // stencil of an nx-wide grid (columns i - nx, i - 1, i, i + 1, i + nx)
 void check_grid5(int n, int nx, const int *rp, const int *ci, int *flag_dev, hipStream_t s);

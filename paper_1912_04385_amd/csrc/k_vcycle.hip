@@ -145,11 +145,12 @@ static void csr_op(int n, int nnz, const int *rp, const int *ci, const T *v, con
 // pointers or column indices.  The row sum takes the five terms in column
 // order, as the CSR row loop takes a row's (ascending) entries, and a missing
 // entry adds an exact zero, so the results are those of k_csr_op.
+template <class T>
 __global__ void k_ell5_fill(int n, int nx, const int *__restrict__ rp, const int *__restrict__ ci,
-                            const float *__restrict__ v, float *__restrict__ ell) {
+                            const T *__restrict__ v, T *__restrict__ ell) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float c[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    T c[5] = {0, 0, 0, 0, 0};
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const int d = ci[e] - i;   // one of -nx, -1, 0, 1, nx (checked at setup)
         const int k = (d == -nx) ? 0 : (d == -1) ? 1 : (d == 0) ? 2 : (d == 1) ? 3 : 4;
@@ -159,24 +160,24 @@ __global__ void k_ell5_fill(int n, int nx, const int *__restrict__ rp, const int
     for (int k = 0; k < 5; ++k) ell[(size_t)k * n + i] = c[k];
 }
 
-void vc_ell5_fill(int n, int nx, const int *rp, const int *ci, const float *v, float *ell, hipStream_t st) {
+template <class T>
+void vc_ell5_fill(int n, int nx, const int *rp, const int *ci, const T *v, T *ell, hipStream_t st) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_ell5_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, n, nx, rp, ci, v, ell);
+    hipLaunchKernelGGL(k_ell5_fill<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, n, nx, rp, ci, v, ell);
     CPTR_CHECK_LAUNCH();
 }
 
-// OP_PRESMOOTH, OP_SWEEP_RESID and OP_SMOOTH on the five planes (operands as
+// OP_PRESMOOTH, OP_SWEEP_RESID and OP_SMOOTH on the five planes (FP32 or FP64) (operands as
 // in k_csr_op; a missing entry's column is clamped into range and its zero
 // coefficient multiplies a finite value)
-template <int OP>
-__global__ void __launch_bounds__(256) k_ell5_op(int n, int nx, const float *__restrict__ ell,
-                                                 const float *__restrict__ xs, const float *__restrict__ dinv,
-                                                 float omega, const float *__restrict__ b, const float *xin,
-                                                 float *xout, float *__restrict__ rout) {
+template <class T, int OP>
+__global__ void __launch_bounds__(256) k_ell5_op(int n, int nx, const T *__restrict__ ell, const T *__restrict__ xs,
+                                                 const T *__restrict__ dinv, T omega, const T *__restrict__ b,
+                                                 const T *xin, T *xout, T *__restrict__ rout) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int off[5] = {-nx, -1, 0, 1, nx};
-    float vv[5], o1[5], o2[5], o3[5];
+    T vv[5], o1[5], o2[5], o3[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const int jr = i + off[q];
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(256) k_ell5_op(int n, int nx, const float *__r
             o1[q] = xs[j];
         }
     }
-    float acc = 0;
+    T acc = 0;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         if constexpr (OP == OP_PRESMOOTH)
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(256) k_ell5_op(int n, int nx, const float *__r
     if constexpr (OP == OP_SMOOTH) {
         xout[i] = xin[i] + omega * dinv[i] * (b[i] - acc);
     } else if constexpr (OP == OP_PRESMOOTH) {
-        const float bi = b[i];
+        const T bi = b[i];
         xout[i] = omega * dinv[i] * bi;
         rout[i] = bi - acc;
     } else {
@@ -215,29 +216,42 @@ __global__ void __launch_bounds__(256) k_ell5_op(int n, int nx, const float *__r
     }
 }
 
-template <int OP>
-static void ell5_op(int n, int nx, const float *ell, const float *xs, const float *dinv, float omega, const float *b,
-                    const float *xin, float *xout, float *rout, hipStream_t st) {
+template <class T, int OP>
+static void ell5_op(int n, int nx, const T *ell, const T *xs, const T *dinv, T omega, const T *b, const T *xin,
+                    T *xout, T *rout, hipStream_t st) {
     if (n == 0) return;
-    hipLaunchKernelGGL((k_ell5_op<OP>), dim3(nblocks(n, 256)), dim3(256), 0, st, n, nx, ell, xs, dinv, omega, b, xin,
+    hipLaunchKernelGGL((k_ell5_op<T, OP>), dim3(nblocks(n, 256)), dim3(256), 0, st, n, nx, ell, xs, dinv, omega, b, xin,
                        xout, rout);
     CPTR_CHECK_LAUNCH();
 }
 
-void vc_ell5_presmooth_residual(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
-                                float *x, float *r, hipStream_t st) {
-    ell5_op<OP_PRESMOOTH>(n, nx, ell, nullptr, dinv, omega, b, nullptr, x, r, st);
+template <class T>
+void vc_ell5_presmooth_residual(int n, int nx, const T *ell, const T *dinv, T omega, const T *b, T *x, T *r,
+                                hipStream_t st) {
+    ell5_op<T, OP_PRESMOOTH>(n, nx, ell, nullptr, dinv, omega, b, nullptr, x, r, st);
 }
 
-void vc_ell5_sweep_residual(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
-                            const float *x, const float *r, float *xout, float *rout, hipStream_t st) {
-    ell5_op<OP_SWEEP_RESID>(n, nx, ell, r, dinv, omega, b, x, xout, rout, st);
+template <class T>
+void vc_ell5_sweep_residual(int n, int nx, const T *ell, const T *dinv, T omega, const T *b, const T *x, const T *r,
+                            T *xout, T *rout, hipStream_t st) {
+    ell5_op<T, OP_SWEEP_RESID>(n, nx, ell, r, dinv, omega, b, x, xout, rout, st);
 }
 
-void vc_ell5_smooth(int n, int nx, const float *ell, const float *dinv, float omega, const float *b,
-                    const float *xin, float *xout, hipStream_t st) {
-    ell5_op<OP_SMOOTH>(n, nx, ell, xin, dinv, omega, b, xin, xout, nullptr, st);
+template <class T>
+void vc_ell5_smooth(int n, int nx, const T *ell, const T *dinv, T omega, const T *b, const T *xin, T *xout,
+                    hipStream_t st) {
+    ell5_op<T, OP_SMOOTH>(n, nx, ell, xin, dinv, omega, b, xin, xout, nullptr, st);
 }
+
+#define INST_ELL5(T)                                                                                              \
+    template void vc_ell5_fill<T>(int, int, const int *, const int *, const T *, T *, hipStream_t);               \
+    template void vc_ell5_presmooth_residual<T>(int, int, const T *, const T *, T, const T *, T *, T *, hipStream_t); \
+    template void vc_ell5_sweep_residual<T>(int, int, const T *, const T *, T, const T *, const T *, const T *, T *, \
+                                            T *, hipStream_t);                                                    \
+    template void vc_ell5_smooth<T>(int, int, const T *, const T *, T, const T *, const T *, T *, hipStream_t);
+INST_ELL5(float)
+INST_ELL5(double)
+#undef INST_ELL5
 
 // first Jacobi sweep from a zero guess fused with the residual:
 //   x_i = omega dinv_i b_i,   r_i = b_i - sum_j a_ij (omega dinv_j b_j)

@@ -409,15 +409,18 @@ def test_fp32_needs_fgmres():
         cptr.Solver(precond_precision=cptr.FP32, krylov=cptr.GMRES)
 
 
-def test_fp32_fine_level_planes_match_csr():
-    """The FP32 sweeps of a scalar stage's fine level on five coefficient
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fine_level_planes_match_csr(precision):
+    """The Jacobi sweeps of a scalar stage's fine level on five coefficient
     planes (a setup given the grid shape, whose pattern is the 5-point
     stencil) give the CSR row kernels' results (the same system set up
     without the grid shape) bit for bit, in preconditioner applications, in
-    the FP32 convergence factors and in a whole solve."""
-    print("case fine-level planes", flush=True)
+    the convergence factors and in a whole solve, in both precisions."""
+    print(f"case fine-level planes {precision}", flush=True)
     s = tiny(64, 24, 8, peclet=5.0, seed=11)
-    kw = dict(krylov=cptr.FGMRES, precond_precision=cptr.FP32, last_stage=cptr.LAST_BJACOBI, amg_max_coarse=40)
+    kw = dict(last_stage=cptr.LAST_BJACOBI, amg_max_coarse=40)
+    if precision == "fp32":
+        kw.update(krylov=cptr.FGMRES, precond_precision=cptr.FP32)
     rp, ci = torch.from_numpy(s.row_ptr), torch.from_numpy(s.col_idx)
     vals = torch.from_numpy(s.vals.reshape(-1))
     grid, flat = cptr.Solver(**kw), cptr.Solver(**kw)
